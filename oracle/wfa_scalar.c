@@ -1,0 +1,186 @@
+/*
+ * Scalar CPU wavefront algorithm (WFA), gap-affine.  TEST INFRASTRUCTURE
+ * ONLY: it pins the Gotoh oracle (same optimum, same canonical CIGAR) and
+ * counts the wavefront work a pair needs.  It shares no code with the Gotoh
+ * oracle nor with the GPU library.
+ *
+ * Paper: System and Methods, "Wavefront Algorithm (WFA)": successive
+ * furthest-reaching wavefronts, one per score s, until the alignment reaches
+ * the end cell; O(n s) work.  The recurrences below are the affine-gap
+ * wavefront recurrences restated on offsets j (text position) along
+ * diagonals k = j - i:
+ *   I_s[k] = max(M_{s-o-e}[k+1], I_{s-e}[k+1])          (consumes P)
+ *   D_s[k] = max(M_{s-o-e}[k-1], D_{s-e}[k-1]) + 1      (consumes T)
+ *   M_s[k] = max(M_{s-x}[k] + 1, I_s[k], D_s[k])
+ * then every valid M_s[k] is extended along matching bases.  A candidate is
+ * invalid when it leaves the table (j > n or i = j - k > m).  M_0[0] =
+ * extend(0).  The first s with M_s[n-m] >= n is the optimum.  With
+ * max_score >= 0 the search stops (REJECTED) once s exceeds it.
+ *
+ * Backtrace (reproduces the Gotoh oracle's canonical CIGAR): from M at
+ * (s,k,f) let f0 = max of the three candidates; emit f - f0 '=' ops, then the
+ * op of the first candidate attaining f0 in the order X, I, D.  From I (or D)
+ * prefer the open source M_{s-o-e} over the extend source when both attain the
+ * value.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define NEG (INT32_MIN / 4)
+enum { OP_EQ = 0, OP_X = 1, OP_I = 2, OP_D = 3 };
+
+typedef struct {
+  int32_t lo, hi; /* diagonal range; empty wavefront when lo > hi */
+  int32_t *M, *I, *D; /* NULL when the component is null */
+} wavefront;
+
+static int32_t wf_get(const wavefront *w, const int32_t *a, int32_t k) {
+  if (!a || k < w->lo || k > w->hi) return NEG;
+  return a[k - w->lo];
+}
+
+static int32_t max2(int32_t a, int32_t b) { return a > b ? a : b; }
+
+/* Stats of the last call: cells computed (sum of wavefront widths over
+ * non-null scores) and bases compared during extension. */
+typedef struct { int64_t cells, compared, wavefronts; } wfa_stats;
+
+int oracle_wfa(const uint8_t *P, int32_t m, const uint8_t *T, int32_t n, int32_t x, int32_t o,
+               int32_t e, int32_t max_score, int32_t want_cigar, int32_t *score, int8_t *status,
+               uint32_t *runs, int32_t cap, int32_t *nruns, wfa_stats *st) {
+  int32_t oe = o + e;
+  int32_t cap_s = 64;
+  wavefront *W = (wavefront *)calloc((size_t)cap_s, sizeof(wavefront));
+  if (!W) return -1;
+  wfa_stats S = {0, 0, 0};
+  int32_t kend = n - m;
+  int32_t s = 0;
+  int rc = 0, done = 0;
+  *nruns = 0;
+  for (;; ++s) {
+    if (max_score >= 0 && s > max_score) break;
+    if (s >= cap_s) {
+      int32_t nc = cap_s * 2;
+      wavefront *nw = (wavefront *)realloc(W, sizeof(wavefront) * (size_t)nc);
+      if (!nw) { rc = -1; break; }
+      memset(nw + cap_s, 0, sizeof(wavefront) * (size_t)(nc - cap_s));
+      W = nw; cap_s = nc;
+    }
+    wavefront *w = &W[s];
+    w->lo = 1; w->hi = 0;
+    const wavefront *wx = s - x >= 0 ? &W[s - x] : NULL;
+    const wavefront *wo = s - oe >= 0 ? &W[s - oe] : NULL;
+    const wavefront *we = s - e >= 0 ? &W[s - e] : NULL;
+    if (s == 0) {
+      w->lo = w->hi = 0;
+      w->M = (int32_t *)malloc(sizeof(int32_t));
+      if (!w->M) { rc = -1; break; }
+      w->M[0] = 0;
+    } else {
+      int has_x = wx && wx->M, has_o = wo && wo->M, has_ie = we && we->I, has_de = we && we->D;
+      if (!has_x && !has_o && !has_ie && !has_de) continue;
+      int32_t lo = INT32_MAX, hi = INT32_MIN;
+      if (has_x) { lo = lo < wx->lo ? lo : wx->lo; hi = hi > wx->hi ? hi : wx->hi; }
+      if (has_o) { lo = lo < wo->lo ? lo : wo->lo; hi = hi > wo->hi ? hi : wo->hi; }
+      if (has_ie || has_de) { lo = lo < we->lo ? lo : we->lo; hi = hi > we->hi ? hi : we->hi; }
+      lo -= 1; hi += 1;
+      if (lo < -m) lo = -m;
+      if (hi > n) hi = n;
+      if (lo > hi) continue;
+      int32_t width = hi - lo + 1;
+      w->lo = lo; w->hi = hi;
+      w->M = (int32_t *)malloc(sizeof(int32_t) * (size_t)width);
+      w->I = (int32_t *)malloc(sizeof(int32_t) * (size_t)width);
+      w->D = (int32_t *)malloc(sizeof(int32_t) * (size_t)width);
+      if (!w->M || !w->I || !w->D) { rc = -1; break; }
+      for (int32_t k = lo; k <= hi; ++k) {
+        int32_t vi = max2(has_o ? wf_get(wo, wo->M, k + 1) : NEG, has_ie ? wf_get(we, we->I, k + 1) : NEG);
+        if (vi >= 0 && vi - k > m) vi = NEG;
+        int32_t vd = max2(has_o ? wf_get(wo, wo->M, k - 1) : NEG, has_de ? wf_get(we, we->D, k - 1) : NEG);
+        if (vd >= 0) { vd += 1; if (vd > n) vd = NEG; } else vd = NEG;
+        int32_t vx = has_x ? wf_get(wx, wx->M, k) : NEG;
+        if (vx >= 0) { vx += 1; if (vx > n || vx - k > m) vx = NEG; } else vx = NEG;
+        if (vi < 0) vi = NEG;
+        w->I[k - lo] = vi;
+        w->D[k - lo] = vd;
+        w->M[k - lo] = max2(vx, max2(vi, vd));
+      }
+      S.cells += width;
+    }
+    S.wavefronts += 1;
+    /* extend */
+    for (int32_t k = w->lo; k <= w->hi; ++k) {
+      int32_t f = w->M[k - w->lo];
+      if (f < 0) continue;
+      int32_t i = f - k, j = f;
+      while (i < m && j < n && P[i] == T[j]) { ++i; ++j; ++S.compared; }
+      if (i < m && j < n) ++S.compared;
+      w->M[k - w->lo] = j;
+    }
+    if (kend >= w->lo && kend <= w->hi && w->M[kend - w->lo] >= n) { done = 1; break; }
+  }
+  if (rc == 0 && !done) {
+    *score = -1; *status = 1;
+  } else if (rc == 0) {
+    *score = s; *status = 0;
+    if (want_cigar) {
+      uint8_t *rev = (uint8_t *)malloc((size_t)m + (size_t)n + 1);
+      if (!rev) rc = -1;
+      int32_t nops = 0, cs = s, k = kend, comp = 0; /* comp: 0 M, 1 I, 2 D */
+      int32_t f = n;
+      while (rc == 0) {
+        if (comp == 0) {
+          if (cs == 0) { /* start wavefront: only matches from (0,0) */
+            for (int32_t t = 0; t < f; ++t) rev[nops++] = OP_EQ;
+            break;
+          }
+          const wavefront *w = &W[cs];
+          const wavefront *wx = cs - x >= 0 ? &W[cs - x] : NULL;
+          int32_t vx = wx && wx->M ? wf_get(wx, wx->M, k) : NEG;
+          if (vx >= 0) { vx += 1; if (vx > n || vx - k > m) vx = NEG; } else vx = NEG;
+          int32_t vi = wf_get(w, w->I, k), vd = wf_get(w, w->D, k);
+          int32_t f0 = max2(vx, max2(vi, vd));
+          if (f0 < 0) { rc = -2; break; }
+          for (int32_t t = f0; t < f; ++t) rev[nops++] = OP_EQ;
+          if (vx == f0) { rev[nops++] = OP_X; cs -= x; f = f0 - 1; }
+          else if (vi == f0) { comp = 1; f = f0; }
+          else { comp = 2; f = f0; }
+        } else if (comp == 1) {
+          rev[nops++] = OP_I;
+          const wavefront *wo = cs - oe >= 0 ? &W[cs - oe] : NULL;
+          int32_t vo = wo && wo->M ? wf_get(wo, wo->M, k + 1) : NEG;
+          if (vo == f) { comp = 0; cs -= oe; }
+          else { cs -= e; }
+          k += 1;
+        } else {
+          rev[nops++] = OP_D;
+          const wavefront *wo = cs - oe >= 0 ? &W[cs - oe] : NULL;
+          int32_t vo = wo && wo->M ? wf_get(wo, wo->M, k - 1) : NEG;
+          if (vo >= 0 && vo + 1 == f) { comp = 0; cs -= oe; }
+          else { cs -= e; }
+          k -= 1; f -= 1;
+        }
+        if (cs < 0) { rc = -2; break; }
+      }
+      if (rc == 0) {
+        /* run-length encode the reversed op list */
+        int32_t nr = 0, t = nops - 1;
+        while (t >= 0) {
+          uint8_t op = rev[t];
+          int32_t len = 0;
+          while (t >= 0 && rev[t] == op) { ++len; --t; }
+          if (nr >= cap) { rc = -3; break; }
+          runs[nr++] = ((uint32_t)len << 4) | op;
+        }
+        if (rc == 0) *nruns = nr;
+      }
+      free(rev);
+    }
+  }
+  for (int32_t t = 0; t < cap_s; ++t) { free(W[t].M); free(W[t].I); free(W[t].D); }
+  free(W);
+  if (st) *st = S;
+  if (rc != 0) { *score = -1; *status = (int8_t)rc; }
+  return rc;
+}
