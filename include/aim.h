@@ -1,0 +1,189 @@
+/*
+ * aim.h -- C ABI of libaim.so: batched global pairwise alignment on AMD
+ * MI355X (gfx950).
+ *
+ * The operation follows the problem statement of the Alignment-in-Memory
+ * paper (System and Methods, "Overall Workflow" and "Supported Alignment
+ * Algorithms"): a batch of read pairs goes in, every pair is aligned on its
+ * own by the chosen algorithm with the chosen scoring parameters, and the
+ * alignment score plus the alignment operations (a CIGAR) come out per pair.
+ * An edit-distance threshold (abstract; GenASM's k) bounds the work: pairs
+ * whose optimum exceeds it are reported as rejected.
+ *
+ * Alignment model (all algorithms):
+ *   global (end to end) alignment of a pattern P (m bases) against a text T
+ *   (n bases); costs are minimised; match costs 0, a mismatch costs x, a run
+ *   of L gap bases costs gap_open + L * gap_extend (linear NW: gap_open 0).
+ *   Ops: '=' match, 'X' mismatch, 'I' a base of P only, 'D' a base of T only.
+ *   Among co-optimal alignments the library returns the canonical one: walking
+ *   back from the end it takes, at each cell, the first feasible op of
+ *   X, I, D, '=' and closes a gap run as early (towards the start) as the
+ *   optimum allows.  NW, SWG and WFA return identical CIGARs for identical
+ *   costs (SWG with gap_open 0 equals NW).
+ *
+ * Conventions:
+ *   - Every call returns aim_status: AIM_OK (0) or a negative error code;
+ *     aim_last_error() then describes it.  Nothing throws across the ABI.
+ *   - Device pointers are HIP device (or managed) memory of the context's
+ *     device.  The caller owns every buffer it passes; the library owns its
+ *     scratch, which lives in the context and grows on demand.
+ *   - Work is enqueued asynchronously on `stream` (a hipStream_t; NULL = the
+ *     null stream); outputs are valid once the stream is synchronised.  Calls
+ *     that share a context must not run concurrently from several host
+ *     threads.
+ *   - Per-pair outcomes are statuses, not errors (AIM_PAIR_*).
+ */
+#ifndef AIM_H
+#define AIM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t aim_status;
+#define AIM_OK 0
+#define AIM_ERR_INVALID_ARG (-1) /* bad pointer, size, penalty or option */
+#define AIM_ERR_UNSUPPORTED (-2) /* valid but not supported (e.g. match != 0) */
+#define AIM_ERR_OOM (-3)         /* device scratch allocation failed */
+#define AIM_ERR_HIP (-4)         /* a HIP runtime call failed */
+#define AIM_ERR_BUSY (-5)        /* serving: queue full / request still running */
+#define AIM_ERR_NOT_FOUND (-6)   /* serving: unknown request id */
+
+typedef enum { AIM_NW_LINEAR = 0, AIM_SWG_AFFINE = 1, AIM_WFA_AFFINE = 2 } aim_algorithm;
+
+/* Sequence encodings.  ASCII: bytes 'A','C','G','T' (upper case only).
+ * CODE: bytes 0..3 for A, C, G, T.  2BIT: 32 bases per uint64 word, base t of
+ * a sequence at bits 2*(t % 32) of word t / 32; each sequence starts on a
+ * word boundary.  Anything outside the alphabet makes that pair
+ * AIM_PAIR_INVALID. */
+typedef enum { AIM_ENC_ASCII = 0, AIM_ENC_CODE = 1, AIM_ENC_2BIT = 2 } aim_encoding;
+
+/* Per-pair status values written to aim_results.status. */
+#define AIM_PAIR_ALIGNED 0
+#define AIM_PAIR_REJECTED 1       /* optimum > max_score: score -1, empty CIGAR */
+#define AIM_PAIR_CIGAR_OVERFLOW 2 /* score valid, CIGAR did not fit cigar_cap */
+#define AIM_PAIR_INVALID 3        /* non-ACGT base or length beyond max_len */
+
+/* CIGAR run encoding: (run_length << 4) | op. */
+#define AIM_OP_MATCH 0
+#define AIM_OP_MISMATCH 1
+#define AIM_OP_INS 2 /* consumes the pattern only */
+#define AIM_OP_DEL 3 /* consumes the text only */
+
+/* Scoring parameters, as costs (paper: NW uses a match cost a, mismatch cost
+ * x and gap cost e; SWG and WFA add a gap-opening cost o).  Requirements:
+ * match == 0, mismatch > 0, gap_extend > 0, gap_open >= 0, each <= 65535;
+ * AIM_NW_LINEAR requires gap_open == 0 (one gap base costs gap_extend).
+ * Violations return AIM_ERR_UNSUPPORTED (match != 0) or AIM_ERR_INVALID_ARG. */
+typedef struct {
+  int32_t match, mismatch, gap_open, gap_extend;
+} aim_penalties;
+
+/* A batch of pairs in CSR form (all arrays are device pointers).
+ *   pat_seq / txt_seq: concatenated sequences in encoding `enc`
+ *     (uint8 for ASCII/CODE, uint64 words for 2BIT);
+ *   pat_off / txt_off: int64 [n_pairs] start of each sequence, in bytes for
+ *     ASCII/CODE and in uint64 words for 2BIT;
+ *   pat_len / txt_len: int32 [n_pairs] lengths in bases.
+ * max_len is a host-side upper bound on every length (it sizes scratch);
+ * a pair whose length exceeds it, or is negative, is AIM_PAIR_INVALID.
+ * 0 <= max_len <= 1048576. */
+typedef struct {
+  int64_t n_pairs;
+  int32_t enc;
+  int32_t max_len;
+  const void *pat_seq;
+  const int64_t *pat_off;
+  const int32_t *pat_len;
+  const void *txt_seq;
+  const int64_t *txt_off;
+  const int32_t *txt_len;
+} aim_batch;
+
+/* Outputs (device pointers, caller-owned).
+ *   score:     int32 [n_pairs], the optimal cost, -1 when rejected/invalid;
+ *   status:    int8  [n_pairs], AIM_PAIR_*;
+ *   cigar:     uint32 [cigar_cap] RLE runs of all pairs, CSR by cigar_off;
+ *   cigar_off: int64 [n_pairs + 1]; pair p owns cigar[cigar_off[p] ..
+ *              cigar_off[p+1]).  Pairs are laid out in order; the first pair
+ *              whose runs would pass cigar_cap and every later pair get
+ *              AIM_PAIR_CIGAR_OVERFLOW and an empty range.
+ *   want_cigar: 0 = score only (cigar may be NULL, cigar_off all zero). */
+typedef struct {
+  int32_t *score;
+  int8_t *status;
+  uint32_t *cigar;
+  int64_t *cigar_off;
+  int64_t cigar_cap;
+  int32_t want_cigar;
+} aim_results;
+
+/* Kernel family.
+ *   AIM_KERNEL_AUTO  -- the production path: NW/SWG run a banded DP with one
+ *     pair per GPU lane whose band is proven exact per pair (or widened), WFA
+ *     runs the wavefront kernel over length-bucketed work queues.
+ *   AIM_KERNEL_PLAIN -- the baseline: one pair per workgroup over the full
+ *     DP matrix (NW/SWG) or one pair per workgroup WFA without bucketing.
+ * Both return identical results. */
+typedef enum { AIM_KERNEL_AUTO = 0, AIM_KERNEL_PLAIN = 1 } aim_kernel;
+
+typedef struct {
+  int32_t kernel;        /* aim_kernel */
+  int32_t flags;         /* reserved, 0 */
+  int64_t scratch_limit; /* soft cap on library scratch in bytes (0: 8 GiB) */
+} aim_options;
+
+typedef struct aim_context aim_context;
+
+/* Create a context on HIP device `device`.  opt may be NULL (defaults).
+ * Returns AIM_ERR_INVALID_ARG for a bad device or options, AIM_ERR_HIP if the
+ * runtime refuses the device. */
+aim_status aim_create(aim_context **ctx, int32_t device, const aim_options *opt);
+
+/* Release the context and all its scratch.  Waits for its work to finish. */
+void aim_destroy(aim_context *ctx);
+
+/* Align every pair of `pairs` (paper: workflow steps 3-5 for all pairs,
+ * "Supported Alignment Algorithms" for `alg`), writing `out`.
+ *   alg: AIM_NW_LINEAR (NW subsection), AIM_SWG_AFFINE (SWG subsection, global
+ *        form), AIM_WFA_AFFINE (WFA subsection, exact gap-affine WFA);
+ *   pen: scoring parameters (see aim_penalties);
+ *   max_score: threshold in penalty units; a pair whose optimum exceeds it is
+ *        AIM_PAIR_REJECTED; < 0 means no threshold.  Results of accepted pairs
+ *        do not depend on it.
+ * Asynchronous on `stream`.  Errors: AIM_ERR_INVALID_ARG (NULL pointers,
+ * n_pairs < 0, max_len out of range, cigar_cap < 0 with want_cigar),
+ * AIM_ERR_UNSUPPORTED (penalties), AIM_ERR_OOM, AIM_ERR_HIP. */
+aim_status aim_align_batch(aim_context *ctx, const aim_batch *pairs, int32_t alg,
+                           aim_penalties pen, int32_t max_score, aim_results *out, void *stream);
+
+/* Encode sequences as 2-bit words (the "2BIT" layout above).
+ *   enc: AIM_ENC_ASCII or AIM_ENC_CODE; seq/off/len: device CSR (byte offsets);
+ *   out_off: device int64 [n_seqs + 1], written: word offset of each output
+ *            sequence (ceil(len/32) words each, in order), out_off[n] = total;
+ *   out_words: device uint64 [words_cap]; words_cap must be >= the total
+ *            (sum of ceil(len/32)), else AIM_ERR_INVALID_ARG is *not*
+ *            detectable without a sync, so the kernel writes only words below
+ *            words_cap and flags the rest;
+ *   seq_flags: device int8 [n_seqs] or NULL; set to 1 for a sequence holding
+ *            a byte outside the alphabet (or truncated by words_cap), else 0.
+ * Paper: the full pair sits in fast memory during alignment (Data
+ * Management); packing 4 bases per byte is how this library keeps it small. */
+aim_status aim_pack_2bit(aim_context *ctx, int64_t n_seqs, int32_t enc, const uint8_t *seq,
+                         const int64_t *off, const int32_t *len, uint64_t *out_words,
+                         int64_t words_cap, int64_t *out_off, int8_t *seq_flags, void *stream);
+
+/* Description of the last error on this host thread ("" if none).  Valid
+ * until the next library call on the same thread. */
+const char *aim_last_error(void);
+
+/* Library version string. */
+const char *aim_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AIM_H */

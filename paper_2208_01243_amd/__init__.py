@@ -1,0 +1,154 @@
+"""Python binding of libaim.so (batched pairwise alignment on MI355X).
+
+Argument marshalling only: every step of the alignment runs in the HIP
+kernels of ``libaim.so``; this module turns torch tensors (device memory) and
+torch streams into the plain pointers of the C ABI declared in
+``include/aim.h``, and C error codes into exceptions.  There is no fallback:
+if the library is not built, importing the entry points raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libaim.so")
+
+NW_LINEAR, SWG_AFFINE, WFA_AFFINE = 0, 1, 2
+ALGORITHMS = {"nw": NW_LINEAR, "swg": SWG_AFFINE, "wfa": WFA_AFFINE}
+ENC_ASCII, ENC_CODE, ENC_2BIT = 0, 1, 2
+KERNEL_AUTO, KERNEL_PLAIN = 0, 1
+PAIR_ALIGNED, PAIR_REJECTED, PAIR_CIGAR_OVERFLOW, PAIR_INVALID = 0, 1, 2, 3
+OP_MATCH, OP_MISMATCH, OP_INS, OP_DEL = 0, 1, 2, 3
+
+ERRORS = {-1: "AIM_ERR_INVALID_ARG", -2: "AIM_ERR_UNSUPPORTED", -3: "AIM_ERR_OOM",
+          -4: "AIM_ERR_HIP", -5: "AIM_ERR_BUSY", -6: "AIM_ERR_NOT_FOUND"}
+
+i32, i64, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+
+
+class Penalties(ctypes.Structure):
+    _fields_ = [("match", i32), ("mismatch", i32), ("gap_open", i32), ("gap_extend", i32)]
+
+
+class Batch(ctypes.Structure):
+    _fields_ = [("n_pairs", i64), ("enc", i32), ("max_len", i32),
+                ("pat_seq", vp), ("pat_off", vp), ("pat_len", vp),
+                ("txt_seq", vp), ("txt_off", vp), ("txt_len", vp)]
+
+
+class Results(ctypes.Structure):
+    _fields_ = [("score", vp), ("status", vp), ("cigar", vp), ("cigar_off", vp),
+                ("cigar_cap", i64), ("want_cigar", i32)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("kernel", i32), ("flags", i32), ("scratch_limit", i64)]
+
+
+class AimError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (ERRORS.get(code, "AIM_ERR"), code, msg))
+        self.code = code
+
+
+# Entry points: name -> (argtypes, restype).  The same names as the C ABI.
+SIGNATURES = {
+    "aim_create": ([ctypes.POINTER(vp), i32, ctypes.POINTER(Options)], i32),
+    "aim_destroy": ([vp], None),
+    "aim_align_batch": ([vp, ctypes.POINTER(Batch), i32, Penalties, i32, ctypes.POINTER(Results), vp], i32),
+    "aim_pack_2bit": ([vp, i64, i32, vp, vp, vp, vp, i64, vp, vp, vp], i32),
+    "aim_last_error": ([], ctypes.c_char_p),
+    "aim_version": ([], ctypes.c_char_p),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libaim.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libaim.so is not built; run __graft_entry__.build() "
+                              "(or python paper_2208_01243_amd/build.py)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(code):
+    if code != 0:
+        raise AimError(code, lib().aim_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else vp(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return vp(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return vp(stream)
+    return vp(stream.cuda_stream)
+
+
+class Context:
+    """An aim_context on one HIP device."""
+
+    def __init__(self, device: int = 0, kernel: str = "auto", scratch_limit: int = 0):
+        opt = Options(KERNEL_PLAIN if kernel == "plain" else KERNEL_AUTO, 0, scratch_limit)
+        h = vp()
+        _check(lib().aim_create(ctypes.byref(h), device, ctypes.byref(opt)))
+        self._h = h
+        self.device = device
+
+    def close(self):
+        if self._h:
+            lib().aim_destroy(self._h)
+            self._h = vp()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def align_batch(self, pat_seq, pat_off, pat_len, txt_seq, txt_off, txt_len, *, enc: int,
+                    max_len: int, alg, pen, max_score: int, score, status, cigar=None,
+                    cigar_off=None, want_cigar: bool = True, stream=None):
+        """aim_align_batch on device tensors; outputs are written in place."""
+        n = pat_len.numel()
+        b = Batch(n, enc, max_len, _ptr(pat_seq), _ptr(pat_off), _ptr(pat_len),
+                  _ptr(txt_seq), _ptr(txt_off), _ptr(txt_len))
+        r = Results(_ptr(score), _ptr(status), _ptr(cigar), _ptr(cigar_off),
+                    cigar.numel() if cigar is not None else 0, int(bool(want_cigar)))
+        a = ALGORITHMS[alg] if isinstance(alg, str) else int(alg)
+        _check(lib().aim_align_batch(self._h, ctypes.byref(b), a, Penalties(*pen), max_score,
+                                     ctypes.byref(r), _stream(stream)))
+
+    def pack_2bit(self, enc: int, seq, off, length, out_words, out_off, seq_flags=None, stream=None):
+        """aim_pack_2bit on device tensors."""
+        _check(lib().aim_pack_2bit(self._h, length.numel(), enc, _ptr(seq), _ptr(off), _ptr(length),
+                                   _ptr(out_words), out_words.numel(), _ptr(out_off), _ptr(seq_flags),
+                                   _stream(stream)))
+
+
+def version() -> str:
+    return lib().aim_version().decode()

@@ -1,0 +1,101 @@
+// Internal declarations shared by the HIP translation units of libaim.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace aim {
+
+// "Infinity" for int32 DP cells.  Every finite cost stays below 2^27 for the
+// supported lengths (<= 2^20) and penalties (<= 2^16 per op ... bounded by
+// the per-pair caps enforced on the host), and INF plus the largest per-row
+// growth stays below 2^31.
+constexpr int32_t DP_INF = 1 << 28;
+
+constexpr int OP_EQ = 0, OP_X = 1, OP_I = 2, OP_D = 3;
+constexpr int8_t ST_ALIGNED = 0, ST_REJECTED = 1, ST_OVERFLOW = 2, ST_INVALID = 3;
+
+// Pairs as 2-bit packed CSR (base t of a sequence at bits 2*(t%32) of word
+// t/32, sequences word aligned).
+struct Seqs {
+  const uint64_t *pat;
+  const int64_t *pat_off;
+  const int32_t *pat_len;
+  const uint64_t *txt;
+  const int64_t *txt_off;
+  const int32_t *txt_len;
+};
+
+// Per-pair results plus the run slots the align kernels write before the
+// CIGAR compaction (runs stored last-op-first, up to slot_cap per pair; the
+// true run count is always recorded in nruns).
+struct Outs {
+  int32_t *score;
+  int8_t *status;
+  int32_t *nruns;
+  uint32_t *slot;     // [n_pairs * slot_cap]
+  int32_t slot_cap;
+  const int8_t *flags; // per pair: nonzero = invalid input
+  // Direct mode (re-run of pairs whose runs exceeded slot_cap): runs are
+  // written last-op-first ending at cigar[cigar_off[p] + nruns[p] - 1].
+  uint32_t *cigar;
+  const int64_t *cigar_off;
+  int64_t cigar_cap;
+};
+
+struct Scoring {
+  int32_t x, o, e;     // linear NW: o == 0 and e == gap cost
+  int32_t max_score;   // < 0: none
+  int32_t want_cigar;
+};
+
+// A list of pair indices to work on, consumed in chunks through an atomic
+// counter; `count` (device) overrides `n` when non-null.
+struct Work {
+  const int32_t *idx;   // nullptr: identity
+  const int32_t *count; // nullptr: n
+  int64_t n;
+  int32_t *counter;     // chunk counter, zeroed before the launch
+  int32_t *next_idx;    // escalation list (may be nullptr)
+  int32_t *next_count;
+  int32_t direct;       // 1: write runs straight into Outs::cigar
+};
+
+// ---- host-side launchers (each enqueues on `stream`) ----------------------
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+hipError_t launch_pair_flags(int64_t n, int32_t max_len, const int32_t *pl, const int32_t *tl,
+                             const int8_t *pf, const int8_t *tf, int8_t *flags, hipStream_t s);
+hipError_t launch_pack(int64_t n, int32_t enc, const uint8_t *seq, const int64_t *off,
+                       const int32_t *len, int32_t max_len, uint64_t *words, int64_t words_cap,
+                       int64_t *out_off, int8_t *flags, int64_t *scan_tmp, hipStream_t s);
+size_t scan_tmp_elems(int64_t n);
+// exclusive scan of int32 counts into int64 out[n+1]
+hipError_t launch_scan_i32(const int32_t *in, int64_t n, int64_t *out, int64_t *tmp, hipStream_t s);
+
+// Banded DP (one pair per lane).  W in {32, 64}.
+hipError_t launch_band(int W, bool affine, const Seqs &S, const Outs &O, const Scoring &P,
+                       const Work &Wk, uint32_t *tb, int64_t tb_slot_words, int32_t rows_cap,
+                       int32_t nslots, hipStream_t s);
+int64_t band_tb_slot_words(int W, bool affine, int32_t rows_cap);
+
+// Full-matrix DP, one pair per workgroup.
+hipError_t launch_full(bool affine, const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk,
+                       uint32_t *scratch, int64_t slot_words, int32_t max_len, int32_t nslots,
+                       hipStream_t s);
+int64_t full_slot_words(int32_t max_len);
+
+// Wavefront algorithm, one pair per workgroup.
+hipError_t launch_wfa(const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk,
+                      int32_t *arena, int64_t slot_words, int32_t max_len, int32_t nslots,
+                      hipStream_t s);
+int64_t wfa_slot_words(int32_t max_len, const Scoring &P);
+
+// CIGAR compaction: cigar_off from nruns (with the cap cut), copy slot runs,
+// collect pairs whose runs exceeded the slot into spill list.
+hipError_t launch_compact(int64_t n, const Outs &O, int64_t *cigar_off, uint32_t *cigar,
+                          int64_t cigar_cap, int64_t *scan_tmp, int64_t *total_written,
+                          int32_t *spill_idx, int32_t *spill_count, int8_t *status,
+                          hipStream_t s);
+hipError_t launch_zero_offsets(int64_t n, int64_t *cigar_off, hipStream_t s);
+
+}  // namespace aim

@@ -1,0 +1,321 @@
+// C ABI of libaim.so: context, scratch management, validation and the
+// orchestration of the alignment kernels on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+#include "aim.h"
+#include "aim_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+aim_status fail(aim_status code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+aim_status fail(aim_status code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                 \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(AIM_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));        \
+  } while (0)
+
+struct Buf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct aim_context {
+  int32_t device = 0;
+  aim_options opt{};
+  int32_t cus = 256;
+  Buf flags, pflag, tflag, pat2, txt2, pat2off, txt2off, nruns, slot, tb32, tb64, full, list2,
+      list3, counters, scan_tmp, spill, wfa, total;
+};
+
+namespace {
+
+aim_status ensure(aim_context *c, Buf &b, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  if (b.bytes >= bytes) return AIM_OK;
+  if (b.p) {
+    // previously enqueued work may still use the old buffer
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipFree(b.p));
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  size_t want = bytes + bytes / 8;
+  hipError_t e = hipMalloc(&b.p, want);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      b.p = nullptr;
+      return fail(AIM_ERR_OOM, "cannot allocate %zu bytes of device scratch", bytes);
+    }
+    want = bytes;
+  }
+  b.bytes = want;
+  return AIM_OK;
+}
+
+template <class T>
+T *as(Buf &b) {
+  return (T *)b.p;
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+aim_status check_pen(int32_t alg, const aim_penalties &pen) {
+  if (alg < AIM_NW_LINEAR || alg > AIM_WFA_AFFINE) return fail(AIM_ERR_INVALID_ARG, "unknown algorithm %d", alg);
+  if (pen.match != 0) return fail(AIM_ERR_UNSUPPORTED, "match cost must be 0 (got %d)", pen.match);
+  if (pen.mismatch <= 0 || pen.gap_extend <= 0 || pen.gap_open < 0)
+    return fail(AIM_ERR_INVALID_ARG, "penalties need mismatch > 0, gap_extend > 0, gap_open >= 0");
+  if (pen.mismatch > 65535 || pen.gap_extend > 65535 || pen.gap_open > 65535)
+    return fail(AIM_ERR_INVALID_ARG, "penalties must not exceed 65535");
+  if (alg == AIM_NW_LINEAR && pen.gap_open != 0)
+    return fail(AIM_ERR_INVALID_ARG, "linear NW takes gap_open 0 (one gap base costs gap_extend)");
+  return AIM_OK;
+}
+
+constexpr int32_t MAX_LEN_LIMIT = 1 << 20;
+constexpr int32_t SLOT_CAP = 48;  // runs per pair held before compaction
+
+enum Counter { C_T1 = 0, C_T2, C_T3, C_L2, C_L3, C_SPILL, C_SPILL_W, C_WFA, C_N = 16 };
+
+}  // namespace
+
+extern "C" {
+
+const char *aim_last_error(void) { return g_err.c_str(); }
+
+const char *aim_version(void) { return "aim-mi355x 0.1 (gfx950)"; }
+
+aim_status aim_create(aim_context **ctx, int32_t device, const aim_options *opt) {
+  g_err.clear();
+  if (!ctx) return fail(AIM_ERR_INVALID_ARG, "ctx is NULL");
+  *ctx = nullptr;
+  int ndev = 0;
+  HIP_TRY(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(AIM_ERR_INVALID_ARG, "device %d out of range (have %d)", device, ndev);
+  aim_options o{};
+  if (opt) o = *opt;
+  if (o.kernel != AIM_KERNEL_AUTO && o.kernel != AIM_KERNEL_PLAIN)
+    return fail(AIM_ERR_INVALID_ARG, "unknown kernel option %d", o.kernel);
+  if (o.scratch_limit < 0) return fail(AIM_ERR_INVALID_ARG, "scratch_limit < 0");
+  if (o.scratch_limit == 0) o.scratch_limit = (int64_t)8 << 30;
+  auto *c = new aim_context();
+  c->device = device;
+  c->opt = o;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+    c->cus = prop.multiProcessorCount;
+  *ctx = c;
+  return AIM_OK;
+}
+
+void aim_destroy(aim_context *c) {
+  if (!c) return;
+  DeviceGuard g(c->device);
+  (void)hipDeviceSynchronize();
+  Buf *all[] = {&c->flags, &c->pflag, &c->tflag, &c->pat2, &c->txt2, &c->pat2off, &c->txt2off,
+                &c->nruns, &c->slot, &c->tb32, &c->tb64, &c->full, &c->list2, &c->list3,
+                &c->counters, &c->scan_tmp, &c->spill, &c->wfa, &c->total};
+  for (Buf *b : all)
+    if (b->p) (void)hipFree(b->p);
+  delete c;
+}
+
+aim_status aim_pack_2bit(aim_context *c, int64_t n, int32_t enc, const uint8_t *seq,
+                         const int64_t *off, const int32_t *len, uint64_t *out_words,
+                         int64_t words_cap, int64_t *out_off, int8_t *seq_flags, void *stream) {
+  g_err.clear();
+  if (!c) return fail(AIM_ERR_INVALID_ARG, "ctx is NULL");
+  if (n < 0) return fail(AIM_ERR_INVALID_ARG, "n_seqs < 0");
+  if (enc != AIM_ENC_ASCII && enc != AIM_ENC_CODE) return fail(AIM_ERR_INVALID_ARG, "enc must be ASCII or CODE");
+  if (!out_off || (n > 0 && (!seq || !off || !len || (!out_words && words_cap > 0))) || words_cap < 0)
+    return fail(AIM_ERR_INVALID_ARG, "NULL buffer or negative capacity");
+  DeviceGuard g(c->device);
+  hipStream_t s = (hipStream_t)stream;
+  const size_t tmp = aim::scan_tmp_elems(n) + (size_t)n + 2;
+  aim_status st = ensure(c, c->scan_tmp, tmp * sizeof(int64_t));
+  if (st) return st;
+  HIP_TRY(aim::launch_pack(n, enc, seq, off, len, INT32_MAX, out_words, words_cap, out_off, seq_flags,
+                           as<int64_t>(c->scan_tmp), s));
+  return AIM_OK;
+}
+
+aim_status aim_align_batch(aim_context *c, const aim_batch *B, int32_t alg, aim_penalties pen,
+                           int32_t max_score, aim_results *R, void *stream) {
+  g_err.clear();
+  // validation needs no device and happens before anything is enqueued
+  if (!B || !R) return fail(AIM_ERR_INVALID_ARG, "NULL batch or results");
+  aim_status st = check_pen(alg, pen);
+  if (st) return st;
+  const int64_t n = B->n_pairs;
+  if (n < 0 || n > (int64_t)INT32_MAX) return fail(AIM_ERR_INVALID_ARG, "n_pairs out of range");
+  if (B->max_len < 0 || B->max_len > MAX_LEN_LIMIT)
+    return fail(AIM_ERR_INVALID_ARG, "max_len must be in [0, %d]", MAX_LEN_LIMIT);
+  if (B->enc < AIM_ENC_ASCII || B->enc > AIM_ENC_2BIT) return fail(AIM_ERR_INVALID_ARG, "unknown encoding %d", B->enc);
+  if (n > 0 && (!B->pat_seq || !B->pat_off || !B->pat_len || !B->txt_seq || !B->txt_off || !B->txt_len))
+    return fail(AIM_ERR_INVALID_ARG, "NULL sequence array");
+  if (n > 0 && (!R->score || !R->status)) return fail(AIM_ERR_INVALID_ARG, "NULL score/status");
+  if (R->want_cigar && (!R->cigar_off || R->cigar_cap < 0 || (R->cigar_cap > 0 && !R->cigar)))
+    return fail(AIM_ERR_INVALID_ARG, "want_cigar needs cigar_off and a cigar buffer of cigar_cap >= 0");
+  if (!c) return fail(AIM_ERR_INVALID_ARG, "ctx is NULL");
+  DeviceGuard g(c->device);
+  hipStream_t s = (hipStream_t)stream;
+
+  if (n == 0) {
+    if (R->cigar_off) HIP_TRY(aim::launch_zero_offsets(0, R->cigar_off, s));
+    return AIM_OK;
+  }
+  const int32_t L = B->max_len;
+  const bool affine = alg != AIM_NW_LINEAR;
+  aim::Scoring P{pen.mismatch, alg == AIM_NW_LINEAR ? 0 : pen.gap_open, pen.gap_extend, max_score,
+                 R->want_cigar ? 1 : 0};
+
+  // ---- common scratch ----
+  const size_t tmp = aim::scan_tmp_elems(n) + (size_t)n + 2;
+  if ((st = ensure(c, c->scan_tmp, tmp * sizeof(int64_t)))) return st;
+  if ((st = ensure(c, c->counters, C_N * sizeof(int32_t) + 64))) return st;
+  if ((st = ensure(c, c->total, 64))) return st;
+  if ((st = ensure(c, c->flags, (size_t)n))) return st;
+  if ((st = ensure(c, c->nruns, (size_t)n * sizeof(int32_t)))) return st;
+  if ((st = ensure(c, c->spill, (size_t)n * sizeof(int32_t)))) return st;
+  if ((st = ensure(c, c->list2, (size_t)n * sizeof(int32_t)))) return st;
+  if ((st = ensure(c, c->list3, (size_t)n * sizeof(int32_t)))) return st;
+  const int32_t slot_cap = std::min<int32_t>(SLOT_CAP, 2 * L + 1);
+  if (R->want_cigar && (st = ensure(c, c->slot, (size_t)n * slot_cap * sizeof(uint32_t)))) return st;
+  int32_t *cnt = as<int32_t>(c->counters);
+  HIP_TRY(aim::launch_fill_i32(cnt, 0, C_N, s));
+
+  // ---- input encoding ----
+  aim::Seqs S;
+  const int8_t *pf = nullptr, *tf = nullptr;
+  if (B->enc == AIM_ENC_2BIT) {
+    S = {(const uint64_t *)B->pat_seq, B->pat_off, B->pat_len,
+         (const uint64_t *)B->txt_seq, B->txt_off, B->txt_len};
+  } else {
+    const size_t words = (size_t)n * ((L + 31) / 32) + 1;
+    if ((st = ensure(c, c->pat2, words * 8))) return st;
+    if ((st = ensure(c, c->txt2, words * 8))) return st;
+    if ((st = ensure(c, c->pat2off, (n + 1) * 8))) return st;
+    if ((st = ensure(c, c->txt2off, (n + 1) * 8))) return st;
+    if ((st = ensure(c, c->pflag, n))) return st;
+    if ((st = ensure(c, c->tflag, n))) return st;
+    // lengths above max_len are flagged invalid below; clamp the packing bound
+    HIP_TRY(aim::launch_pack(n, B->enc, (const uint8_t *)B->pat_seq, B->pat_off, B->pat_len, L,
+                             as<uint64_t>(c->pat2), (int64_t)words, as<int64_t>(c->pat2off),
+                             as<int8_t>(c->pflag), as<int64_t>(c->scan_tmp), s));
+    HIP_TRY(aim::launch_pack(n, B->enc, (const uint8_t *)B->txt_seq, B->txt_off, B->txt_len, L,
+                             as<uint64_t>(c->txt2), (int64_t)words, as<int64_t>(c->txt2off),
+                             as<int8_t>(c->tflag), as<int64_t>(c->scan_tmp), s));
+    S = {as<uint64_t>(c->pat2), as<int64_t>(c->pat2off), B->pat_len,
+         as<uint64_t>(c->txt2), as<int64_t>(c->txt2off), B->txt_len};
+    pf = as<int8_t>(c->pflag);
+    tf = as<int8_t>(c->tflag);
+  }
+  HIP_TRY(aim::launch_pair_flags(n, L, B->pat_len, B->txt_len, pf, tf, as<int8_t>(c->flags), s));
+
+  aim::Outs O{R->score, R->status, as<int32_t>(c->nruns), as<uint32_t>(c->slot), slot_cap,
+              as<int8_t>(c->flags), R->cigar, R->cigar_off, R->cigar_cap};
+  const int64_t budget = c->opt.scratch_limit / 4;
+  const bool plain = c->opt.kernel == AIM_KERNEL_PLAIN;
+
+  auto run_full = [&](const aim::Work &Wk, int64_t max_items) -> aim_status {
+    const int64_t sw = aim::full_slot_words(L);
+    int64_t slots = std::min<int64_t>(max_items, (int64_t)c->cus * 8);
+    slots = std::min<int64_t>(slots, std::max<int64_t>(1, budget / (sw * 4)));
+    slots = std::max<int64_t>(slots, 1);
+    aim_status e = ensure(c, c->full, (size_t)(slots * sw * 4));
+    if (e) return e;
+    HIP_TRY(aim::launch_full(affine, S, O, P, Wk, as<uint32_t>(c->full), sw, L, (int32_t)slots, s));
+    return AIM_OK;
+  };
+
+  if (alg == AIM_WFA_AFFINE) {
+    const int64_t sw = aim::wfa_slot_words(L, P);
+    int64_t slots = std::min<int64_t>(n, (int64_t)c->cus * 8);
+    slots = std::min<int64_t>(slots, std::max<int64_t>(1, budget / (sw * 4)));
+    slots = std::max<int64_t>(slots, 1);
+    if ((st = ensure(c, c->wfa, (size_t)(slots * sw * 4)))) return st;
+    aim::Work W1{nullptr, nullptr, n, cnt + C_WFA, nullptr, nullptr, 0};
+    HIP_TRY(aim::launch_wfa(S, O, P, W1, as<int32_t>(c->wfa), sw, L, (int32_t)slots, s));
+  } else if (plain) {
+    aim::Work W1{nullptr, nullptr, n, cnt + C_T1, nullptr, nullptr, 0};
+    if ((st = run_full(W1, n))) return st;
+  } else {
+    // tier 1: 32-diagonal band, one pair per lane
+    const int32_t rows_cap = L + 1;
+    const int64_t chunks = (n + 63) / 64;
+    const int64_t sw32 = aim::band_tb_slot_words(32, affine, rows_cap);
+    int64_t slots = std::min<int64_t>(chunks, (int64_t)c->cus * 16);
+    slots = std::max<int64_t>(1, std::min<int64_t>(slots, budget / (sw32 * 4)));
+    if ((st = ensure(c, c->tb32, (size_t)(slots * sw32 * 4)))) return st;
+    aim::Work W1{nullptr, nullptr, n, cnt + C_T1, as<int32_t>(c->list2), cnt + C_L2, 0};
+    HIP_TRY(aim::launch_band(32, affine, S, O, P, W1, as<uint32_t>(c->tb32), sw32, rows_cap,
+                             (int32_t)slots, s));
+    // tier 2: 64-diagonal band for the pairs tier 1 could not decide
+    const int64_t sw64 = aim::band_tb_slot_words(64, affine, rows_cap);
+    int64_t slots2 = std::min<int64_t>(chunks, (int64_t)c->cus * 4);
+    slots2 = std::max<int64_t>(1, std::min<int64_t>(slots2, budget / (sw64 * 4)));
+    if ((st = ensure(c, c->tb64, (size_t)(slots2 * sw64 * 4)))) return st;
+    aim::Work W2{as<int32_t>(c->list2), cnt + C_L2, n, cnt + C_T2, as<int32_t>(c->list3),
+                 cnt + C_L3, 0};
+    HIP_TRY(aim::launch_band(64, affine, S, O, P, W2, as<uint32_t>(c->tb64), sw64, rows_cap,
+                             (int32_t)slots2, s));
+    // tier 3: full matrix
+    aim::Work W3{as<int32_t>(c->list3), cnt + C_L3, n, cnt + C_T3, nullptr, nullptr, 0};
+    if ((st = run_full(W3, n))) return st;
+  }
+
+  if (!R->want_cigar) {
+    if (R->cigar_off) HIP_TRY(aim::launch_zero_offsets(n, R->cigar_off, s));
+    return AIM_OK;
+  }
+  HIP_TRY(aim::launch_compact(n, O, R->cigar_off, R->cigar, R->cigar_cap, as<int64_t>(c->scan_tmp),
+                              as<int64_t>(c->total), as<int32_t>(c->spill), cnt + C_SPILL,
+                              R->status, s));
+  // pairs whose runs exceeded the slot: recompute and write in place
+  aim::Work WS{as<int32_t>(c->spill), cnt + C_SPILL, n, cnt + C_SPILL_W, nullptr, nullptr, 1};
+  if (alg == AIM_WFA_AFFINE) {
+    const int64_t sw = aim::wfa_slot_words(L, P);
+    int64_t slots = std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(n, (int64_t)c->cus * 8),
+                                                           budget / (sw * 4)));
+    if ((st = ensure(c, c->wfa, (size_t)(slots * sw * 4)))) return st;
+    HIP_TRY(aim::launch_wfa(S, O, P, WS, as<int32_t>(c->wfa), sw, L, (int32_t)slots, s));
+  } else {
+    if ((st = run_full(WS, n))) return st;
+  }
+  return AIM_OK;
+}
+
+}  // extern "C"

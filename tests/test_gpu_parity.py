@@ -1,0 +1,183 @@
+"""Bit-exact parity of the GPU path (through the C ABI) against the CPU oracle.
+
+Every comparison is element by element: score, status, and the CIGAR runs of
+every pair, on seeded inputs.  Cases cover several tiles and ragged tails,
+the band tiers (32- and 64-diagonal bands, full-matrix fallback), the plain
+kernel, thresholds, empty and degenerate pairs, invalid input and CIGAR
+capacity overflow.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+import synth  # noqa: E402
+import paper_2208_01243_amd as aim  # noqa: E402
+from gpu_util import compare, describe, run  # noqa: E402
+
+NW, SWG = (0, 1, 0, 1), (0, 4, 6, 2)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available()
+    c = aim.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def ctx_plain():
+    c = aim.Context(0, kernel="plain")
+    yield c
+    c.close()
+
+
+def check(ctx, batch, alg, pen, max_score=-1, enc="2bit", **kw):
+    got = run(ctx, batch, alg, pen, max_score, enc=enc, **kw)
+    want = oracle.align_batch(batch, alg, pen, max_score)
+    bad = compare(got, want)
+    assert not bad, "%d mismatches, first: %s" % (len(bad), describe(batch, bad[0], got, want))
+    return got
+
+
+def _tiny_all(alphabet, maxlen):
+    seqs = [np.array(s, np.uint8) for L in range(maxlen + 1) for s in itertools.product(alphabet, repeat=L)]
+    pats, txts = zip(*[(p, t) for p in seqs for t in seqs])
+    return synth.from_lists(list(pats), list(txts))
+
+
+@pytest.mark.parametrize("alg,pen", [("nw", NW), ("swg", SWG), ("nw", (0, 3, 0, 4)), ("swg", (0, 3, 4, 1)),
+                                     ("swg", (0, 9, 1, 1)), ("nw", (0, 2, 0, 1))])
+def test_exhaustive_tiny(ctx, alg, pen):
+    check(ctx, _tiny_all(range(4), 3), alg, pen)
+
+
+def test_exhaustive_tiny_binary(ctx):
+    b = _tiny_all(range(2), 5)
+    for alg, pen in [("swg", SWG), ("swg", (0, 2, 1, 1)), ("nw", NW), ("nw", (0, 3, 0, 1))]:
+        check(ctx, b, alg, pen)
+
+
+def test_nw100_full_workload(ctx):
+    w = synth.WORKLOADS["nw100"]
+    b = synth.workload("nw100")
+    got = check(ctx, b, "nw", w["pen"], w["max_score"], enc="ascii")
+    assert 0.005 < (got[1] == aim.PAIR_REJECTED).mean() < 0.03
+
+
+def test_swg150_first_20k(ctx):
+    b = synth.workload("swg150", n=20_000)
+    check(ctx, b, "swg", SWG, -1)
+
+
+def test_plain_kernel_equals_oracle(ctx_plain):
+    b = synth.workload("swg150", n=3000)
+    check(ctx_plain, b, "swg", SWG, -1)
+    b = synth.workload("nw100", n=3000)
+    check(ctx_plain, b, "nw", NW, 5, enc="code")
+
+
+def _mixed_batch(seed, count, lmin, lmax, rates):
+    rng = np.random.default_rng(seed)
+    pats, txts = [], []
+    for _ in range(count):
+        L = int(rng.integers(lmin, lmax + 1))
+        T = rng.integers(0, 4, L).astype(np.uint8)
+        r = float(rng.choice(rates))
+        if r >= 1.0:
+            P = rng.integers(0, 4, int(rng.integers(lmin, lmax + 1))).astype(np.uint8)
+        else:
+            b = synth.from_lists([T], [T])
+            P, _ = synth.mutate(rng, b.txt, b.txt_off, [r])
+        pats.append(P)
+        txts.append(T)
+    return synth.from_lists(pats, txts)
+
+
+@pytest.mark.parametrize("alg,pen", [("swg", SWG), ("nw", NW)])
+def test_tiers_and_fallback(ctx, alg, pen):
+    # noisy and unrelated pairs of uneven length push pairs through the
+    # 64-diagonal band and the full-matrix fallback
+    b = _mixed_batch(21, 1500, 1, 400, [0.0, 0.02, 0.1, 0.3, 1.0])
+    check(ctx, b, alg, pen)
+
+
+@pytest.mark.parametrize("smax", [0, 1, 6, 20, 200])
+def test_thresholds(ctx, smax):
+    b = _mixed_batch(22, 800, 0, 160, [0.0, 0.01, 0.05, 0.2, 1.0])
+    check(ctx, b, "swg", SWG, smax)
+    check(ctx, b, "nw", NW, smax)
+
+
+def test_degenerate_pairs(ctx):
+    pats = ["", "", "A", "", "ACGT", "A" * 300, "", "ACGTACGT" * 40, "T" * 200, "G"]
+    txts = ["", "A", "", "ACGTACGTAC", "", "", "C" * 257, "ACGTACGT" * 40, "A" * 200, "G" * 500]
+    b = synth.from_lists(pats, txts)
+    for alg, pen in [("swg", SWG), ("nw", NW), ("swg", (0, 3, 4, 1))]:
+        check(ctx, b, alg, pen)
+        check(ctx, b, alg, pen, 10)
+
+
+def test_score_only_and_encodings(ctx):
+    b = synth.workload("nw100", n=2000)
+    full = run(ctx, b, "nw", NW, 5, enc="ascii")
+    for enc in ("code", "2bit"):
+        s, st, _, off = run(ctx, b, "nw", NW, 5, enc=enc)
+        assert np.array_equal(s, full[0]) and np.array_equal(st, full[1])
+    s, st, _, off = run(ctx, b, "nw", NW, 5, enc="ascii", want_cigar=False)
+    assert np.array_equal(s, full[0]) and np.array_equal(st, full[1]) and not off.any()
+
+
+def test_invalid_input_and_length_bound(ctx):
+    b = synth.from_lists(["ACGT", "ACGT", "ACGTA"], ["ACGT", "ACGT", "ACGT"])
+    dev_seq = synth.ascii_from_codes(b.pat).copy()
+    dev_seq[1] = ord("N")
+    import torch as T
+    ps = T.from_numpy(dev_seq).cuda()
+    po = T.from_numpy(b.pat_off[:-1].copy()).cuda()
+    pl = T.from_numpy(b.pat_len).cuda()
+    ts = T.from_numpy(synth.ascii_from_codes(b.txt).copy()).cuda()
+    to = T.from_numpy(b.txt_off[:-1].copy()).cuda()
+    tl = T.from_numpy(b.txt_len).cuda()
+    s, st, cg, off = run(ctx, b, "swg", SWG, dev=((ps, po, pl, ts, to, tl), aim.ENC_ASCII), max_len=4)
+    assert st.tolist() == [aim.PAIR_ALIGNED, aim.PAIR_INVALID, aim.PAIR_INVALID]
+    assert s.tolist()[1:] == [-1, -1] and s[0] == 0
+    assert off.tolist() == [0, 1, 1, 1]
+
+
+def test_cigar_capacity_cut(ctx):
+    b = synth.workload("swg150", n=500)
+    want = oracle.align_batch(b, "swg", SWG, -1)
+    runs = np.diff(want[3])
+    cap = int(runs[:200].sum())  # exactly the first 200 pairs fit
+    s, st, cg, off = run(ctx, b, "swg", SWG, cigar_cap=cap)
+    assert np.array_equal(s, want[0])
+    assert (st[:200] == 0).all() and (st[200:][runs[200:] > 0] == aim.PAIR_CIGAR_OVERFLOW).all()
+    assert off[200] == cap and (off[200:] == cap).all()
+    assert np.array_equal(cg[:cap], want[2][:cap])
+
+
+def test_long_runs_spill_path(ctx):
+    # alternating mismatches give many runs per pair: more than the per-pair
+    # slot holds, so the in-place re-run path writes those CIGARs
+    rng = np.random.default_rng(5)
+    pats, txts = [], []
+    for _ in range(64):
+        T = rng.integers(0, 4, 150).astype(np.uint8)
+        P = T.copy()
+        P[::3] = (P[::3] + 1) % 4
+        pats.append(P)
+        txts.append(T)
+    check(ctx, synth.from_lists(pats, txts), "swg", (0, 1, 6, 2))
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_long_reads(ctx, seed):
+    b = _mixed_batch(30 + seed, 60, 500, 1500, [0.01, 0.05])
+    check(ctx, b, "swg", SWG)
+    check(ctx, b, "nw", NW)
