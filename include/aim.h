@@ -129,9 +129,12 @@ typedef struct {
  * Both return identical results. */
 typedef enum { AIM_KERNEL_AUTO = 0, AIM_KERNEL_PLAIN = 1 } aim_kernel;
 
+/* aim_options.flags bits */
+#define AIM_FLAG_TIMING 1 /* time every kernel launch with HIP events (aim_timing) */
+
 typedef struct {
   int32_t kernel;        /* aim_kernel */
-  int32_t flags;         /* reserved, 0 */
+  int32_t flags;         /* AIM_FLAG_* */
   int64_t scratch_limit; /* soft cap on library scratch in bytes (0: 8 GiB) */
 } aim_options;
 
@@ -174,6 +177,16 @@ aim_status aim_align_batch(aim_context *ctx, const aim_batch *pairs, int32_t alg
 aim_status aim_pack_2bit(aim_context *ctx, int64_t n_seqs, int32_t enc, const uint8_t *seq,
                          const int64_t *off, const int32_t *len, uint64_t *out_words,
                          int64_t words_cap, int64_t *out_off, int8_t *seq_flags, void *stream);
+
+/* Per-phase GPU time of the launches made since the last aim_timing_reset,
+ * measured with HIP events recorded on the launch stream around each kernel
+ * (only with AIM_FLAG_TIMING).  Phase `idx` = 0, 1, ...: writes its name
+ * (static string, e.g. "band32", "full", "wfa", "compact"), the summed
+ * milliseconds and the number of launches.  Waits for the recorded events.
+ * Returns AIM_ERR_NOT_FOUND past the last phase. */
+aim_status aim_timing(aim_context *ctx, int32_t idx, const char **name, double *total_ms,
+                      int64_t *launches);
+aim_status aim_timing_reset(aim_context *ctx);
 
 /* Description of the last error on this host thread ("" if none).  Valid
  * until the next library call on the same thread. */

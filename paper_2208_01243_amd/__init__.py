@@ -18,6 +18,7 @@ NW_LINEAR, SWG_AFFINE, WFA_AFFINE = 0, 1, 2
 ALGORITHMS = {"nw": NW_LINEAR, "swg": SWG_AFFINE, "wfa": WFA_AFFINE}
 ENC_ASCII, ENC_CODE, ENC_2BIT = 0, 1, 2
 KERNEL_AUTO, KERNEL_PLAIN = 0, 1
+FLAG_TIMING = 1
 PAIR_ALIGNED, PAIR_REJECTED, PAIR_CIGAR_OVERFLOW, PAIR_INVALID = 0, 1, 2, 3
 OP_MATCH, OP_MISMATCH, OP_INS, OP_DEL = 0, 1, 2, 3
 
@@ -58,6 +59,9 @@ SIGNATURES = {
     "aim_destroy": ([vp], None),
     "aim_align_batch": ([vp, ctypes.POINTER(Batch), i32, Penalties, i32, ctypes.POINTER(Results), vp], i32),
     "aim_pack_2bit": ([vp, i64, i32, vp, vp, vp, vp, i64, vp, vp, vp], i32),
+    "aim_timing": ([vp, i32, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_double),
+                    ctypes.POINTER(i64)], i32),
+    "aim_timing_reset": ([vp], i32),
     "aim_last_error": ([], ctypes.c_char_p),
     "aim_version": ([], ctypes.c_char_p),
 }
@@ -102,8 +106,10 @@ def _stream(stream):
 class Context:
     """An aim_context on one HIP device."""
 
-    def __init__(self, device: int = 0, kernel: str = "auto", scratch_limit: int = 0):
-        opt = Options(KERNEL_PLAIN if kernel == "plain" else KERNEL_AUTO, 0, scratch_limit)
+    def __init__(self, device: int = 0, kernel: str = "auto", scratch_limit: int = 0,
+                 timing: bool = False):
+        opt = Options(KERNEL_PLAIN if kernel == "plain" else KERNEL_AUTO,
+                      FLAG_TIMING if timing else 0, scratch_limit)
         h = vp()
         _check(lib().aim_create(ctypes.byref(h), device, ctypes.byref(opt)))
         self._h = h
@@ -142,6 +148,22 @@ class Context:
         a = ALGORITHMS[alg] if isinstance(alg, str) else int(alg)
         _check(lib().aim_align_batch(self._h, ctypes.byref(b), a, Penalties(*pen), max_score,
                                      ctypes.byref(r), _stream(stream)))
+
+    def timing(self):
+        """{phase: (total_ms, launches)} since the last reset (AIM_FLAG_TIMING)."""
+        out = {}
+        k = 0
+        while True:
+            name, ms, cnt = ctypes.c_char_p(), ctypes.c_double(), i64()
+            rc = lib().aim_timing(self._h, k, ctypes.byref(name), ctypes.byref(ms), ctypes.byref(cnt))
+            if rc == -6:
+                return out
+            _check(rc)
+            out[name.value.decode()] = (ms.value, cnt.value)
+            k += 1
+
+    def timing_reset(self):
+        _check(lib().aim_timing_reset(self._h))
 
     def pack_2bit(self, enc: int, seq, off, length, out_words, out_off, seq_flags=None, stream=None):
         """aim_pack_2bit on device tensors."""

@@ -6,8 +6,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "aim.h"
 #include "aim_internal.h"
@@ -41,10 +43,51 @@ struct Buf {
 
 }  // namespace
 
+// Optional per-phase timing with events recorded on the launch stream.
+struct PhaseTimer {
+  struct Pending {
+    const char *name;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<const char *, std::pair<double, int64_t>>> totals;  // in first-seen order
+
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  void flush() {
+    for (auto &p : pending) {
+      float ms = 0.f;
+      if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+        bool found = false;
+        for (auto &t : totals)
+          if (!strcmp(t.first, p.name)) { t.second.first += ms; t.second.second += 1; found = true; }
+        if (!found) totals.push_back({p.name, {(double)ms, 1}});
+      }
+      pool.push_back(p.a);
+      pool.push_back(p.b);
+    }
+    pending.clear();
+  }
+  ~PhaseTimer() {
+    flush();
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
 struct aim_context {
   int32_t device = 0;
   aim_options opt{};
   int32_t cus = 256;
+  PhaseTimer timer;
   Buf flags, pflag, tflag, pat2, txt2, pat2off, txt2off, nruns, slot, tb32, tb64, full, list2,
       list3, counters, scan_tmp, spill, wfa, total;
 };
@@ -105,6 +148,28 @@ aim_status check_pen(int32_t alg, const aim_penalties &pen) {
   return AIM_OK;
 }
 
+// Brackets one launch with timing events when AIM_FLAG_TIMING is set.
+struct Phase {
+  aim_context *c;
+  hipStream_t s;
+  const char *name;
+  hipEvent_t a = nullptr;
+  Phase(aim_context *c_, hipStream_t s_, const char *n) : c(c_), s(s_), name(n) {
+    if (c->opt.flags & AIM_FLAG_TIMING) {
+      a = c->timer.get();
+      if (a) (void)hipEventRecord(a, s);
+    }
+  }
+  ~Phase() {
+    if (!a) return;
+    hipEvent_t b = c->timer.get();
+    if (!b) return;
+    (void)hipEventRecord(b, s);
+    c->timer.pending.push_back({name, a, b});
+    if (c->timer.pending.size() > 8192) c->timer.flush();
+  }
+};
+
 constexpr int32_t MAX_LEN_LIMIT = 1 << 20;
 constexpr int32_t SLOT_CAP = 48;  // runs per pair held before compaction
 
@@ -117,6 +182,29 @@ extern "C" {
 const char *aim_last_error(void) { return g_err.c_str(); }
 
 const char *aim_version(void) { return "aim-mi355x 0.1 (gfx950)"; }
+
+aim_status aim_timing(aim_context *c, int32_t idx, const char **name, double *total_ms,
+                      int64_t *launches) {
+  g_err.clear();
+  if (!c) return fail(AIM_ERR_INVALID_ARG, "ctx is NULL");
+  DeviceGuard g(c->device);
+  c->timer.flush();
+  if (idx < 0 || idx >= (int32_t)c->timer.totals.size()) return fail(AIM_ERR_NOT_FOUND, "no phase %d", idx);
+  const auto &t = c->timer.totals[(size_t)idx];
+  if (name) *name = t.first;
+  if (total_ms) *total_ms = t.second.first;
+  if (launches) *launches = t.second.second;
+  return AIM_OK;
+}
+
+aim_status aim_timing_reset(aim_context *c) {
+  g_err.clear();
+  if (!c) return fail(AIM_ERR_INVALID_ARG, "ctx is NULL");
+  DeviceGuard g(c->device);
+  c->timer.flush();
+  c->timer.totals.clear();
+  return AIM_OK;
+}
 
 aim_status aim_create(aim_context **ctx, int32_t device, const aim_options *opt) {
   g_err.clear();
@@ -220,6 +308,8 @@ aim_status aim_align_batch(aim_context *c, const aim_batch *B, int32_t alg, aim_
   // ---- input encoding ----
   aim::Seqs S;
   const int8_t *pf = nullptr, *tf = nullptr;
+  {
+  Phase ph_prep(c, s, "prep");
   if (B->enc == AIM_ENC_2BIT) {
     S = {(const uint64_t *)B->pat_seq, B->pat_off, B->pat_len,
          (const uint64_t *)B->txt_seq, B->txt_off, B->txt_len};
@@ -244,6 +334,7 @@ aim_status aim_align_batch(aim_context *c, const aim_batch *B, int32_t alg, aim_
     tf = as<int8_t>(c->tflag);
   }
   HIP_TRY(aim::launch_pair_flags(n, L, B->pat_len, B->txt_len, pf, tf, as<int8_t>(c->flags), s));
+  }
 
   aim::Outs O{R->score, R->status, as<int32_t>(c->nruns), as<uint32_t>(c->slot), slot_cap,
               as<int8_t>(c->flags), R->cigar, R->cigar_off, R->cigar_cap};
@@ -257,6 +348,7 @@ aim_status aim_align_batch(aim_context *c, const aim_batch *B, int32_t alg, aim_
     slots = std::max<int64_t>(slots, 1);
     aim_status e = ensure(c, c->full, (size_t)(slots * sw * 4));
     if (e) return e;
+    Phase ph(c, s, Wk.direct ? "full_rerun" : "full");
     HIP_TRY(aim::launch_full(affine, S, O, P, Wk, as<uint32_t>(c->full), sw, L, (int32_t)slots, s));
     return AIM_OK;
   };
@@ -268,6 +360,7 @@ aim_status aim_align_batch(aim_context *c, const aim_batch *B, int32_t alg, aim_
     slots = std::max<int64_t>(slots, 1);
     if ((st = ensure(c, c->wfa, (size_t)(slots * sw * 4)))) return st;
     aim::Work W1{nullptr, nullptr, n, cnt + C_WFA, nullptr, nullptr, 0};
+    Phase ph(c, s, "wfa");
     HIP_TRY(aim::launch_wfa(S, O, P, W1, as<int32_t>(c->wfa), sw, L, (int32_t)slots, s));
   } else if (plain) {
     aim::Work W1{nullptr, nullptr, n, cnt + C_T1, nullptr, nullptr, 0};
@@ -281,13 +374,17 @@ aim_status aim_align_batch(aim_context *c, const aim_batch *B, int32_t alg, aim_
     slots = std::max<int64_t>(1, std::min<int64_t>(slots, budget / (sw32 * 4)));
     if ((st = ensure(c, c->tb32, (size_t)(slots * sw32 * 4)))) return st;
     aim::Work W1{nullptr, nullptr, n, cnt + C_T1, as<int32_t>(c->list2), cnt + C_L2, 0};
+    {
+    Phase ph(c, s, "band32");
     HIP_TRY(aim::launch_band(32, affine, S, O, P, W1, as<uint32_t>(c->tb32), sw32, rows_cap,
                              (int32_t)slots, s));
+    }
     // tier 2: 64-diagonal band for the pairs tier 1 could not decide
     const int64_t sw64 = aim::band_tb_slot_words(64, affine, rows_cap);
     int64_t slots2 = std::min<int64_t>(chunks, (int64_t)c->cus * 4);
     slots2 = std::max<int64_t>(1, std::min<int64_t>(slots2, budget / (sw64 * 4)));
     if ((st = ensure(c, c->tb64, (size_t)(slots2 * sw64 * 4)))) return st;
+    Phase ph2(c, s, "band64");
     aim::Work W2{as<int32_t>(c->list2), cnt + C_L2, n, cnt + C_T2, as<int32_t>(c->list3),
                  cnt + C_L3, 0};
     HIP_TRY(aim::launch_band(64, affine, S, O, P, W2, as<uint32_t>(c->tb64), sw64, rows_cap,
@@ -301,9 +398,12 @@ aim_status aim_align_batch(aim_context *c, const aim_batch *B, int32_t alg, aim_
     if (R->cigar_off) HIP_TRY(aim::launch_zero_offsets(n, R->cigar_off, s));
     return AIM_OK;
   }
+  {
+  Phase ph(c, s, "compact");
   HIP_TRY(aim::launch_compact(n, O, R->cigar_off, R->cigar, R->cigar_cap, as<int64_t>(c->scan_tmp),
                               as<int64_t>(c->total), as<int32_t>(c->spill), cnt + C_SPILL,
                               R->status, s));
+  }
   // pairs whose runs exceeded the slot: recompute and write in place
   aim::Work WS{as<int32_t>(c->spill), cnt + C_SPILL, n, cnt + C_SPILL_W, nullptr, nullptr, 1};
   if (alg == AIM_WFA_AFFINE) {
@@ -311,6 +411,7 @@ aim_status aim_align_batch(aim_context *c, const aim_batch *B, int32_t alg, aim_
     int64_t slots = std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(n, (int64_t)c->cus * 8),
                                                            budget / (sw * 4)));
     if ((st = ensure(c, c->wfa, (size_t)(slots * sw * 4)))) return st;
+    Phase ph(c, s, "wfa_rerun");
     HIP_TRY(aim::launch_wfa(S, O, P, WS, as<int32_t>(c->wfa), sw, L, (int32_t)slots, s));
   } else {
     if ((st = run_full(WS, n))) return st;

@@ -136,7 +136,7 @@ def test_score_only_and_encodings(ctx):
 def test_invalid_input_and_length_bound(ctx):
     b = synth.from_lists(["ACGT", "ACGT", "ACGTA"], ["ACGT", "ACGT", "ACGT"])
     dev_seq = synth.ascii_from_codes(b.pat).copy()
-    dev_seq[1] = ord("N")
+    dev_seq[b.pat_off[1] + 1] = ord("N")  # a non-ACGT base in pair 1
     import torch as T
     ps = T.from_numpy(dev_seq).cuda()
     po = T.from_numpy(b.pat_off[:-1].copy()).cuda()
