@@ -6,10 +6,9 @@
 
 namespace aim {
 
-// "Infinity" for int32 DP cells.  Every finite cost stays below 2^27 for the
-// supported lengths (<= 2^20) and penalties (<= 2^16 per op ... bounded by
-// the per-pair caps enforced on the host), and INF plus the largest per-row
-// growth stays below 2^31.
+// "Infinity" for int32 DP cells.  Finite costs stay far below it for the
+// supported lengths (<= 2^20) and penalties (<= 65535), and it plus the
+// largest per-row growth stays below 2^31.
 constexpr int32_t DP_INF = 1 << 28;
 
 constexpr int OP_EQ = 0, OP_X = 1, OP_I = 2, OP_D = 3;
@@ -33,7 +32,7 @@ struct Outs {
   int32_t *score;
   int8_t *status;
   int32_t *nruns;
-  uint32_t *slot;     // [n_pairs * slot_cap]
+  uint32_t *slot;      // [n_pairs * slot_cap]
   int32_t slot_cap;
   const int8_t *flags; // per pair: nonzero = invalid input
   // Direct mode (re-run of pairs whose runs exceeded slot_cap): runs are
@@ -49,13 +48,13 @@ struct Scoring {
   int32_t want_cigar;
 };
 
-// A list of pair indices to work on, consumed in chunks through an atomic
-// counter; `count` (device) overrides `n` when non-null.
+// A list of pair indices to work on, consumed through an atomic counter;
+// `count` (device) overrides `n` when non-null.
 struct Work {
   const int32_t *idx;   // nullptr: identity
   const int32_t *count; // nullptr: n
   int64_t n;
-  int32_t *counter;     // chunk counter, zeroed before the launch
+  int32_t *counter;     // work counter, zeroed before the launch
   int32_t *next_idx;    // escalation list (may be nullptr)
   int32_t *next_count;
   int32_t direct;       // 1: write runs straight into Outs::cigar
@@ -84,11 +83,34 @@ hipError_t launch_full(bool affine, const Seqs &S, const Outs &O, const Scoring 
                        hipStream_t s);
 int64_t full_slot_words(int32_t max_len);
 
-// Wavefront algorithm, one pair per workgroup.
-hipError_t launch_wfa(const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk,
-                      int32_t *arena, int64_t slot_words, int32_t max_len, int32_t nslots,
-                      hipStream_t s);
-int64_t wfa_slot_words(int32_t max_len, const Scoring &P);
+// Wavefront algorithm, one pair per 64-lane wavefront, two passes.
+struct WfaLaunch {
+  int32_t R;            // ring slots (pass 1): max(x, o+e) + 1
+  int32_t wcap;         // ring width capacity of this launch (pass 1)
+  int32_t seq_words;    // words of LDS per staged sequence (0: read from HBM)
+  int32_t full_in_lds;  // pass 2: arena in LDS
+  int64_t slot_words;   // HBM slot per workgroup (pass 1 ring / pass 2 arena), or LDS arena words
+  int32_t *ring_list;   // pass 1: pairs whose width passed wcap
+  int32_t *ring_count;
+  int32_t *need_list[3];  // pass 1 -> pass 2: accepted pairs by full-store class
+  int32_t *need_count[3];
+  int64_t need_cap[3];    // class capacities in words
+  int64_t *need;          // per pair: words of the full store
+};
+
+struct WfaPlan {
+  int32_t R, wcap, wcap_lds, seq_words, lds_score_bytes, ring_slots, lds_arena_words;
+  int64_t ring_slot_words;
+  int64_t need_cap[3];
+  int32_t arena_slots[3];
+};
+
+WfaPlan wfa_plan(int32_t max_len, const Scoring &P, int64_t budget_bytes, int32_t cus, bool plain);
+hipError_t launch_wfa_score(const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk,
+                            const WfaLaunch &L, int32_t *hbm, bool ring_in_lds, int32_t nslots,
+                            hipStream_t s);
+hipError_t launch_wfa_trace(const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk,
+                            const WfaLaunch &L, int32_t *hbm, int32_t nslots, hipStream_t s);
 
 // CIGAR compaction: cigar_off from nruns (with the cap cut), copy slot runs,
 // collect pairs whose runs exceeded the slot into spill list.

@@ -89,7 +89,7 @@ struct aim_context {
   int32_t cus = 256;
   PhaseTimer timer;
   Buf flags, pflag, tflag, pat2, txt2, pat2off, txt2off, nruns, slot, tb32, tb64, full, list2,
-      list3, counters, scan_tmp, spill, wfa, total;
+      list3, counters, scan_tmp, spill, total, wring, warena1, warena2, wneed, wlists;
 };
 
 namespace {
@@ -136,6 +136,15 @@ struct DeviceGuard {
   }
 };
 
+enum Counter {
+  C_T1 = 0, C_T2, C_T3, C_L2, C_L3, C_SPILL, C_SPILL_W,
+  C_W1, C_W1G, C_RL, C_FAIL, C_N0, C_N1, C_N2, C_P0, C_P1, C_P2,
+  C_N = 32
+};
+
+// WFA requires a bounded ring of past wavefronts: max(x, o + e) <= this.
+constexpr int32_t WFA_MAX_STEP = 1024;
+
 aim_status check_pen(int32_t alg, const aim_penalties &pen) {
   if (alg < AIM_NW_LINEAR || alg > AIM_WFA_AFFINE) return fail(AIM_ERR_INVALID_ARG, "unknown algorithm %d", alg);
   if (pen.match != 0) return fail(AIM_ERR_UNSUPPORTED, "match cost must be 0 (got %d)", pen.match);
@@ -145,6 +154,8 @@ aim_status check_pen(int32_t alg, const aim_penalties &pen) {
     return fail(AIM_ERR_INVALID_ARG, "penalties must not exceed 65535");
   if (alg == AIM_NW_LINEAR && pen.gap_open != 0)
     return fail(AIM_ERR_INVALID_ARG, "linear NW takes gap_open 0 (one gap base costs gap_extend)");
+  if (alg == AIM_WFA_AFFINE && (pen.mismatch > WFA_MAX_STEP || pen.gap_open + pen.gap_extend > WFA_MAX_STEP))
+    return fail(AIM_ERR_UNSUPPORTED, "WFA needs mismatch and gap_open + gap_extend <= %d", WFA_MAX_STEP);
   return AIM_OK;
 }
 
@@ -173,7 +184,71 @@ struct Phase {
 constexpr int32_t MAX_LEN_LIMIT = 1 << 20;
 constexpr int32_t SLOT_CAP = 48;  // runs per pair held before compaction
 
-enum Counter { C_T1 = 0, C_T2, C_T3, C_L2, C_L3, C_SPILL, C_SPILL_W, C_WFA, C_N = 16 };
+
+
+// WFA: pass 1 (score) with the ring in LDS, then with the ring in HBM for
+// pairs too wide for LDS; pass 2 (full store + backtrace) by store-size class.
+aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const aim::Scoring &P,
+                   int64_t n, int32_t L, bool plain, int32_t *cnt, hipStream_t s) {
+  aim_status st;
+  const aim::WfaPlan pl = aim::wfa_plan(L, P, c->opt.scratch_limit / 4, c->cus, plain);
+  if ((st = ensure(c, c->wneed, (size_t)n * 8))) return st;
+  if ((st = ensure(c, c->wlists, (size_t)n * 4 * 5))) return st;
+  int32_t *lists = as<int32_t>(c->wlists);
+  aim::WfaLaunch WL{};
+  WL.R = pl.R;
+  WL.seq_words = pl.seq_words;
+  WL.ring_list = lists;
+  WL.ring_count = cnt + C_RL;
+  for (int k = 0; k < 3; ++k) {
+    WL.need_list[k] = lists + (int64_t)n * (k + 1);
+    WL.need_count[k] = cnt + C_N0 + k;
+    WL.need_cap[k] = pl.need_cap[k];
+  }
+  WL.need = as<int64_t>(c->wneed);
+  const int32_t slots = (int32_t)std::min<int64_t>(n, (int64_t)c->cus * 8);
+  if (!plain && pl.wcap_lds > 0) {
+    aim::WfaLaunch A = WL;
+    A.wcap = pl.wcap_lds;
+    aim::Work W{nullptr, nullptr, n, cnt + C_W1, nullptr, nullptr, 0};
+    Phase ph(c, s, "wfa_score");
+    HIP_TRY(aim::launch_wfa_score(S, O, P, W, A, nullptr, true, slots, s));
+  }
+  {
+    // pairs whose wavefronts outgrew the LDS ring (all pairs for the plain path)
+    if ((st = ensure(c, c->wring, (size_t)pl.ring_slot_words * 4 * pl.ring_slots))) return st;
+    aim::WfaLaunch B = WL;
+    B.wcap = pl.wcap;
+    B.slot_words = pl.ring_slot_words;
+    B.ring_list = lists + (int64_t)n * 4;  // never reached: wcap bounds every width
+    B.ring_count = cnt + C_FAIL;
+    const bool all = plain || pl.wcap_lds == 0;
+    aim::Work W{all ? nullptr : lists, all ? nullptr : cnt + C_RL, n, cnt + C_W1G, nullptr, nullptr, 0};
+    Phase ph(c, s, "wfa_score_hbm");
+    HIP_TRY(aim::launch_wfa_score(S, O, P, W, B, as<int32_t>(c->wring), false,
+                                  all ? std::min<int32_t>(slots, pl.ring_slots) : pl.ring_slots, s));
+  }
+  if (!P.want_cigar) return AIM_OK;
+  // pass 2 by class: 0 LDS arena, 1 medium HBM slots, 2 large HBM slot
+  for (int k = 0; k < 3; ++k) {
+    if (k == 0 && (plain || pl.lds_arena_words <= 0)) continue;
+    aim::WfaLaunch T = WL;
+    T.full_in_lds = k == 0;
+    T.slot_words = k == 0 ? pl.lds_arena_words : pl.need_cap[k];
+    int32_t *hbm = nullptr;
+    if (k == 1) {
+      if ((st = ensure(c, c->warena1, (size_t)pl.need_cap[1] * 4 * pl.arena_slots[1]))) return st;
+      hbm = as<int32_t>(c->warena1);
+    } else if (k == 2) {
+      if ((st = ensure(c, c->warena2, (size_t)pl.need_cap[2] * 4 * pl.arena_slots[2]))) return st;
+      hbm = as<int32_t>(c->warena2);
+    }
+    aim::Work W{WL.need_list[k], WL.need_count[k], n, cnt + C_P0 + k, nullptr, nullptr, 0};
+    Phase ph(c, s, k == 0 ? "wfa_trace_lds" : (k == 1 ? "wfa_trace_hbm" : "wfa_trace_large"));
+    HIP_TRY(aim::launch_wfa_trace(S, O, P, W, T, hbm, k == 0 ? slots : pl.arena_slots[k], s));
+  }
+  return AIM_OK;
+}
 
 }  // namespace
 
@@ -235,7 +310,8 @@ void aim_destroy(aim_context *c) {
   (void)hipDeviceSynchronize();
   Buf *all[] = {&c->flags, &c->pflag, &c->tflag, &c->pat2, &c->txt2, &c->pat2off, &c->txt2off,
                 &c->nruns, &c->slot, &c->tb32, &c->tb64, &c->full, &c->list2, &c->list3,
-                &c->counters, &c->scan_tmp, &c->spill, &c->wfa, &c->total};
+                &c->counters, &c->scan_tmp, &c->spill, &c->total, &c->wring, &c->warena1,
+                &c->warena2, &c->wneed, &c->wlists};
   for (Buf *b : all)
     if (b->p) (void)hipFree(b->p);
   delete c;
@@ -354,14 +430,7 @@ aim_status aim_align_batch(aim_context *c, const aim_batch *B, int32_t alg, aim_
   };
 
   if (alg == AIM_WFA_AFFINE) {
-    const int64_t sw = aim::wfa_slot_words(L, P);
-    int64_t slots = std::min<int64_t>(n, (int64_t)c->cus * 8);
-    slots = std::min<int64_t>(slots, std::max<int64_t>(1, budget / (sw * 4)));
-    slots = std::max<int64_t>(slots, 1);
-    if ((st = ensure(c, c->wfa, (size_t)(slots * sw * 4)))) return st;
-    aim::Work W1{nullptr, nullptr, n, cnt + C_WFA, nullptr, nullptr, 0};
-    Phase ph(c, s, "wfa");
-    HIP_TRY(aim::launch_wfa(S, O, P, W1, as<int32_t>(c->wfa), sw, L, (int32_t)slots, s));
+    if ((st = run_wfa(c, S, O, P, n, L, plain, cnt, s))) return st;
   } else if (plain) {
     aim::Work W1{nullptr, nullptr, n, cnt + C_T1, nullptr, nullptr, 0};
     if ((st = run_full(W1, n))) return st;
@@ -407,12 +476,16 @@ aim_status aim_align_batch(aim_context *c, const aim_batch *B, int32_t alg, aim_
   // pairs whose runs exceeded the slot: recompute and write in place
   aim::Work WS{as<int32_t>(c->spill), cnt + C_SPILL, n, cnt + C_SPILL_W, nullptr, nullptr, 1};
   if (alg == AIM_WFA_AFFINE) {
-    const int64_t sw = aim::wfa_slot_words(L, P);
-    int64_t slots = std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(n, (int64_t)c->cus * 8),
-                                                           budget / (sw * 4)));
-    if ((st = ensure(c, c->wfa, (size_t)(slots * sw * 4)))) return st;
+    aim::WfaPlan pl = aim::wfa_plan(L, P, c->opt.scratch_limit / 4, c->cus, plain);
+    aim::WfaLaunch WL{};
+    WL.R = pl.R;
+    WL.seq_words = pl.seq_words;
+    WL.full_in_lds = 0;
+    WL.slot_words = pl.need_cap[2];
+    WL.need = as<int64_t>(c->wneed);
+    if ((st = ensure(c, c->warena2, (size_t)pl.need_cap[2] * 4 * pl.arena_slots[2]))) return st;
     Phase ph(c, s, "wfa_rerun");
-    HIP_TRY(aim::launch_wfa(S, O, P, WS, as<int32_t>(c->wfa), sw, L, (int32_t)slots, s));
+    HIP_TRY(aim::launch_wfa_trace(S, O, P, WS, WL, as<int32_t>(c->warena2), pl.arena_slots[2], s));
   } else {
     if ((st = run_full(WS, n))) return st;
   }

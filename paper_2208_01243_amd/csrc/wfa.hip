@@ -1,14 +1,436 @@
-// Gap-affine wavefront alignment (placeholder until the kernel lands).
+// Gap-affine wavefront alignment (WFA), one pair per 64-lane wavefront with
+// the diagonals of each wavefront spread over the lanes.
+//
+// Paper: System and Methods, "Wavefront Algorithm (WFA)": successive
+// furthest-reaching wavefronts, one per score s, each computed from the
+// components of a few earlier wavefronts, until the end cell is reached; the
+// components are allocated dynamically as they grow (Data Management: the
+// per-thread bump allocator, here a per-pair arena with a bump pointer).  The
+// recurrences, restated on offsets j along diagonals k = j - i, are
+//   I_s[k] = max(M_{s-o-e}[k+1], I_{s-e}[k+1])         (consumes P)
+//   D_s[k] = max(M_{s-o-e}[k-1], D_{s-e}[k-1]) + 1     (consumes T)
+//   M_s[k] = max(M_{s-x}[k] + 1, I_s[k], D_s[k])
+// with every candidate that leaves the table (j > n or j - k > m) dropped,
+// then each M_s[k] extended along matching bases.  M_0[0] = extend(0); the
+// first s with M_s[n-m] >= n is the optimum; with a threshold the search stops
+// (rejected) once s exceeds it.
+//
+// Two passes:
+//   pass 1 (score): wavefronts in a ring of R = max(x, o+e) + 1 slots (the
+//     oldest source is s - max(x, o+e)), in LDS when it fits, else in an HBM
+//     slot.  Yields the score or the rejection, and the exact number of words
+//     the full store of pass 2 needs.
+//   pass 2 (accepted pairs, CIGAR wanted): recompute s = 0..score keeping every
+//     wavefront (arena in LDS when it fits, else an HBM slot sized by class),
+//     then one lane walks the canonical backtrace: from M at (s,k,f) emit
+//     f - f0 '=' ops, then the first of X, I, D whose candidate attains f0;
+//     from I (D) prefer the opening source M_{s-o-e} over extension.  This
+//     reproduces the DP oracle's canonical CIGAR (same tie order).
+#include <algorithm>
+
 #include "aim_internal.h"
 
 namespace aim {
+namespace {
 
-int64_t wfa_slot_words(int32_t max_len, const Scoring &P) { return 64; }
+constexpr int32_t NEG = INT32_MIN / 4;  // absent / invalid offset
+constexpr int WG = 64;
+constexpr int ENTRY = 4;                // table entry: lo, hi, base, present-bits
 
-hipError_t launch_wfa(const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk,
-                      int32_t *arena, int64_t slot_words, int32_t max_len, int32_t nslots,
-                      hipStream_t s) {
-  return hipErrorNotSupported;
+
+
+__device__ __forceinline__ uint64_t seq_window(const uint64_t *w, int64_t nw, int64_t t) {
+  // 32 bases starting at base t (t >= 0); words past the end read as zero
+  const int64_t q = t >> 5;
+  const uint32_t r = (uint32_t)(t & 31);
+  const uint64_t w0 = q < nw ? w[q] : 0ull;
+  const uint64_t w1 = q + 1 < nw ? w[q + 1] : 0ull;
+  return r ? ((w0 >> (2 * r)) | (w1 << (64 - 2 * r))) : w0;
+}
+
+// Extend offset f on diagonal k while P[i] == T[j] (i = f - k, j = f).
+__device__ __forceinline__ int32_t extend(const uint64_t *P, int64_t pnw, int32_t m,
+                                          const uint64_t *T, int64_t tnw, int32_t n, int32_t k,
+                                          int32_t f) {
+  int32_t i = f - k, j = f;
+  for (;;) {
+    const int32_t lim = min(m - i, n - j);
+    if (lim <= 0) break;
+    const uint64_t x = seq_window(P, pnw, i) ^ seq_window(T, tnw, j);
+    int32_t run = x ? (int32_t)(__builtin_ctzll(x) >> 1) : 32;
+    if (run > lim) run = lim;
+    i += run;
+    j += run;
+    if (run < 32) break;
+  }
+  return j;
+}
+
+__device__ __forceinline__ int32_t tab_get(const int32_t *tab, int32_t slot, int f) {
+  return tab[slot * ENTRY + f];
+}
+
+// One wavefront step: compute components of score s into `dst` (three
+// arrays of width hi-lo+1 at dst, dst+w, dst+2w).  Source tables/arrays are
+// located through `tab`/`store` with slot(s') giving the table slot.
+// Returns present bits of the new wavefront (0: null) and its lo/hi.
+template <class SlotOf>
+__device__ __forceinline__ int wf_step(int32_t s, int32_t x, int32_t oe, int32_t e, int32_t m,
+                                       int32_t n, const int32_t *tab, const int32_t *store,
+                                       SlotOf slot_of, int32_t *dst_base_store, int32_t dst_base,
+                                       int32_t wlimit, int32_t &lo_out, int32_t &hi_out,
+                                       const uint64_t *P, int64_t pnw, const uint64_t *T,
+                                       int64_t tnw, bool &overflow) {
+  const int lane = threadIdx.x;
+  int sx = -1, so = -1, se = -1;
+  int fx = 0, fo = 0, fe = 0;
+  int32_t lo = INT32_MAX, hi = INT32_MIN;
+  if (s - x >= 0) {
+    sx = slot_of(s - x);
+    fx = tab_get(tab, sx, 3) & 1;
+    if (fx) { lo = min(lo, tab_get(tab, sx, 0)); hi = max(hi, tab_get(tab, sx, 1)); }
+  }
+  if (s - oe >= 0) {
+    so = slot_of(s - oe);
+    fo = tab_get(tab, so, 3) & 1;
+    if (fo) { lo = min(lo, tab_get(tab, so, 0)); hi = max(hi, tab_get(tab, so, 1)); }
+  }
+  if (s - e >= 0) {
+    se = slot_of(s - e);
+    fe = tab_get(tab, se, 3) & 6;
+    if (fe) { lo = min(lo, tab_get(tab, se, 0)); hi = max(hi, tab_get(tab, se, 1)); }
+  }
+  if (!fx && !fo && !fe) return 0;
+  lo = max(lo - 1, -m);
+  hi = min(hi + 1, n);
+  if (lo > hi) return 0;
+  const int32_t w = hi - lo + 1;
+  if (w > wlimit) {
+    overflow = true;
+    return 0;
+  }
+  const int32_t xlo = fx ? tab_get(tab, sx, 0) : 0, xhi = fx ? tab_get(tab, sx, 1) : -1;
+  const int32_t xb = fx ? tab_get(tab, sx, 2) : 0;
+  const int32_t olo = fo ? tab_get(tab, so, 0) : 0, ohi = fo ? tab_get(tab, so, 1) : -1;
+  const int32_t ob = fo ? tab_get(tab, so, 2) : 0;
+  const int32_t elo = fe ? tab_get(tab, se, 0) : 0, ehi = fe ? tab_get(tab, se, 1) : -1;
+  const int32_t eb = fe ? tab_get(tab, se, 2) : 0, ew = ehi - elo + 1;
+  const bool eI = fe & 2, eD = fe & 4;
+  int32_t *dM = dst_base_store + dst_base;
+  int32_t *dI = dM + w;
+  int32_t *dD = dI + w;
+  for (int32_t k = lo + lane; k <= hi; k += WG) {
+    int32_t vi = NEG, vd = NEG, vx = NEG;
+    // I: from k + 1
+    if (fo && k + 1 >= olo && k + 1 <= ohi) vi = store[ob + (k + 1 - olo)];
+    if (eI && k + 1 >= elo && k + 1 <= ehi) vi = max(vi, store[eb + ew + (k + 1 - elo)]);
+    if (vi >= 0 && vi - k > m) vi = NEG;
+    // D: from k - 1
+    if (fo && k - 1 >= olo && k - 1 <= ohi) vd = store[ob + (k - 1 - olo)];
+    if (eD && k - 1 >= elo && k - 1 <= ehi) vd = max(vd, store[eb + 2 * ew + (k - 1 - elo)]);
+    if (vd >= 0) { vd += 1; if (vd > n) vd = NEG; } else vd = NEG;
+    // X: from k
+    if (fx && k >= xlo && k <= xhi) vx = store[xb + (k - xlo)];
+    if (vx >= 0) { vx += 1; if (vx > n || vx - k > m) vx = NEG; } else vx = NEG;
+    if (vi < 0) vi = NEG;
+    int32_t vm = max(vx, max(vi, vd));
+    if (vm >= 0) vm = extend(P, pnw, m, T, tnw, n, k, vm);
+    dM[k - lo] = vm;
+    dI[k - lo] = vi;
+    dD[k - lo] = vd;
+  }
+  lo_out = lo;
+  hi_out = hi;
+  return 1 | ((fo || eI) ? 2 : 0) | ((fo || eD) ? 4 : 0);
+}
+
+__device__ __forceinline__ void stage_seq(uint64_t *lds, const uint64_t *g, int64_t nw) {
+  for (int64_t q = threadIdx.x; q < nw; q += WG) lds[q] = g[q];
+}
+
+__device__ __forceinline__ void wave_append1(bool pred, int32_t v, int32_t *list, int32_t *cnt) {
+  if (pred && threadIdx.x == 0) {
+    const int32_t k = atomicAdd(cnt, 1);
+    list[k] = v;
+  }
+}
+
+// ---------------------------------------------------------------- pass 1
+// ring_in_lds: ring lives in dynamic LDS; else in the HBM slot of this WG.
+__global__ __launch_bounds__(WG) void k_wfa_score(Seqs S, Outs O, Scoring P, Work Wk, WfaLaunch L,
+                                                  int32_t *hbm, int32_t ring_in_lds) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int32_t sh_pair;
+  const int lane = threadIdx.x;
+  uint64_t *sP = (uint64_t *)smem;
+  uint64_t *sT = sP + L.seq_words;
+  int32_t *tab_ring = (int32_t *)(sT + L.seq_words);       // R entries
+  int32_t *lds_ring = tab_ring + L.R * ENTRY;
+  int32_t *ring = ring_in_lds ? lds_ring : (hbm + (int64_t)blockIdx.x * L.slot_words);
+  const int32_t x = P.x, oe = P.o + P.e, e = P.e, R = L.R;
+  const int64_t count = Wk.count ? (int64_t)(*(volatile const int32_t *)Wk.count) : Wk.n;
+  for (;;) {
+    __syncthreads();
+    if (lane == 0) sh_pair = atomicAdd(Wk.counter, 1);
+    __syncthreads();
+    const int64_t li = sh_pair;
+    if (li >= count) break;
+    const int64_t p = Wk.idx ? (int64_t)Wk.idx[li] : li;
+    if (O.flags && O.flags[p]) {
+      if (lane == 0) { O.score[p] = -1; O.status[p] = ST_INVALID; O.nruns[p] = 0; }
+      continue;
+    }
+    const int32_t m = S.pat_len[p], n = S.txt_len[p];
+    const int64_t pnw = (m + 31) >> 5, tnw = (n + 31) >> 5;
+    const uint64_t *gP = S.pat + S.pat_off[p], *gT = S.txt + S.txt_off[p];
+    const uint64_t *Pw = gP, *Tw = gT;
+    if (pnw <= L.seq_words && tnw <= L.seq_words) {
+      stage_seq(sP, gP, pnw);
+      stage_seq(sT, gT, tnw);
+      Pw = sP;
+      Tw = sT;
+    }
+    __syncthreads();
+    auto slot_of = [&](int32_t s) { return s % R; };
+    int32_t s = 0;
+    int64_t need = 0;
+    int result = 0;  // 1 aligned, 2 rejected, 3 ring overflow, 4 internal bound
+    const int32_t kend = n - m;
+    // the cost of one concrete alignment bounds the optimum: all diagonal ops
+    // plus one gap run for the length difference, or gap runs over both
+    const int64_t ad = m > n ? m - n : n - m;
+    const int64_t up1 = (int64_t)x * min(m, n) + (ad ? (int64_t)P.o + ad * e : 0);
+    const int64_t up2 = (m ? (int64_t)P.o + (int64_t)m * e : 0) + (n ? (int64_t)P.o + (int64_t)n * e : 0);
+    const int64_t s_upper = min(up1, up2);
+    for (;; ++s) {
+      if (P.max_score >= 0 && s > P.max_score) { result = 2; break; }
+      if (s > s_upper) { result = 4; break; }
+      const int sl = slot_of(s);
+      int32_t lo = 0, hi = -1;
+      int present;
+      bool overflow = false;
+      if (s == 0) {
+        if (lane == 0) ring[sl * 3 * L.wcap] = extend(Pw, pnw, m, Tw, tnw, n, 0, 0);
+        present = 1;
+        lo = hi = 0;
+      } else {
+        present = wf_step(s, x, oe, e, m, n, tab_ring, ring, slot_of, ring, sl * 3 * L.wcap, L.wcap,
+                          lo, hi, Pw, pnw, Tw, tnw, overflow);
+      }
+      if (overflow) { result = 3; break; }
+      __syncthreads();
+      if (lane == 0) {
+        tab_ring[sl * ENTRY + 0] = lo;
+        tab_ring[sl * ENTRY + 1] = hi;
+        tab_ring[sl * ENTRY + 2] = sl * 3 * L.wcap;
+        tab_ring[sl * ENTRY + 3] = present;
+      }
+      need += ENTRY + (present ? 3 * (int64_t)(hi - lo + 1) : 0);
+      __syncthreads();
+      if (present && kend >= lo && kend <= hi && ring[sl * 3 * L.wcap + (kend - lo)] >= n) {
+        result = 1;
+        break;
+      }
+    }
+    if (result == 3) {
+      wave_append1(true, (int32_t)p, L.ring_list, L.ring_count);
+      continue;
+    }
+    if (lane == 0) {
+      if (result == 2 || result == 4) {
+        O.score[p] = -1;
+        O.status[p] = result == 2 ? ST_REJECTED : ST_INVALID;
+        O.nruns[p] = 0;
+      } else {
+        O.score[p] = s;
+        O.status[p] = ST_ALIGNED;
+        O.nruns[p] = 0;
+        if (P.want_cigar) {
+          L.need[p] = need;
+          int c = need <= L.need_cap[0] ? 0 : (need <= L.need_cap[1] ? 1 : 2);
+          if (need > L.need_cap[2]) {
+            O.status[p] = ST_OVERFLOW;  // full store larger than any arena class
+          } else {
+            const int32_t k = atomicAdd(L.need_count[c], 1);
+            L.need_list[c][k] = (int32_t)p;
+          }
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- pass 2
+__global__ __launch_bounds__(WG) void k_wfa_trace(Seqs S, Outs O, Scoring P, Work Wk, WfaLaunch L,
+                                                  int32_t *hbm) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int32_t sh_pair, sh_top;
+  const int lane = threadIdx.x;
+  uint64_t *sP = (uint64_t *)smem;
+  uint64_t *sT = sP + L.seq_words;
+  int32_t *arena = L.full_in_lds ? (int32_t *)(sT + L.seq_words) : (hbm + (int64_t)blockIdx.x * L.slot_words);
+  const int32_t x = P.x, o = P.o, oe = P.o + P.e, e = P.e;
+  const int64_t count = Wk.count ? (int64_t)(*(volatile const int32_t *)Wk.count) : Wk.n;
+  for (;;) {
+    __syncthreads();
+    if (lane == 0) sh_pair = atomicAdd(Wk.counter, 1);
+    __syncthreads();
+    const int64_t li = sh_pair;
+    if (li >= count) break;
+    const int64_t p = Wk.idx ? (int64_t)Wk.idx[li] : li;
+    const int32_t m = S.pat_len[p], n = S.txt_len[p];
+    const int32_t sfin = O.score[p];
+    const int64_t pnw = (m + 31) >> 5, tnw = (n + 31) >> 5;
+    const uint64_t *gP = S.pat + S.pat_off[p], *gT = S.txt + S.txt_off[p];
+    const uint64_t *Pw = gP, *Tw = gT;
+    if (pnw <= L.seq_words && tnw <= L.seq_words) {
+      stage_seq(sP, gP, pnw);
+      stage_seq(sT, gT, tnw);
+      Pw = sP;
+      Tw = sT;
+    }
+    // table of sfin + 1 entries at the start of the arena, data after it
+    int32_t *tab = arena;
+    const int32_t data0 = (sfin + 1) * ENTRY;
+    if (lane == 0) sh_top = data0;
+    __syncthreads();
+    auto slot_of = [&](int32_t s2) { return s2; };
+    for (int32_t s = 0; s <= sfin; ++s) {
+      const int32_t base = sh_top;
+      int32_t lo = 0, hi = -1;
+      int present;
+      bool overflow = false;
+      if (s == 0) {
+        if (lane == 0) arena[base] = extend(Pw, pnw, m, Tw, tnw, n, 0, 0);
+        present = 1;
+        lo = hi = 0;
+      } else {
+        present = wf_step(s, x, oe, e, m, n, tab, arena, slot_of, arena, base, INT32_MAX, lo, hi,
+                          Pw, pnw, Tw, tnw, overflow);
+      }
+      __syncthreads();
+      if (lane == 0) {
+        tab[s * ENTRY + 0] = lo;
+        tab[s * ENTRY + 1] = hi;
+        tab[s * ENTRY + 2] = base;
+        tab[s * ENTRY + 3] = present;
+        if (present) sh_top = base + 3 * (hi - lo + 1);
+      }
+      __syncthreads();
+    }
+    // ---- backtrace (one lane) ----
+    if (lane == 0) {
+      const int32_t total = Wk.direct ? O.nruns[p] : 0;
+      uint32_t *dst = Wk.direct ? (O.cigar + O.cigar_off[p]) : (O.slot + p * O.slot_cap);
+      const int32_t cap = O.slot_cap;
+      uint32_t cur_op = 0xffu, cur_len = 0;
+      int32_t nr = 0;
+      auto put = [&](uint32_t op, uint32_t len) {
+        if (len == 0) return;
+        if (op == cur_op) {
+          cur_len += len;
+        } else {
+          if (cur_len) {
+            const uint32_t run = (cur_len << 4) | cur_op;
+            if (Wk.direct) { if (nr < total) dst[total - 1 - nr] = run; }
+            else if (nr < cap) dst[nr] = run;
+            ++nr;
+          }
+          cur_op = op;
+          cur_len = len;
+        }
+      };
+      auto val = [&](int32_t s2, int comp, int32_t k) -> int32_t {
+        // comp 0 M, 1 I, 2 D; NEG when absent
+        if (s2 < 0) return NEG;
+        const int32_t lo = tab[s2 * ENTRY], hi = tab[s2 * ENTRY + 1], pr = tab[s2 * ENTRY + 3];
+        if (!(pr & (1 << comp)) || k < lo || k > hi) return NEG;
+        return arena[tab[s2 * ENTRY + 2] + comp * (hi - lo + 1) + (k - lo)];
+      };
+      int32_t cs = sfin, k = n - m, f = n, comp = 0;
+      // each step emits one op or closes a run; the walk has at most m + n ops
+      int64_t guard = 2 * ((int64_t)m + n) + 8;
+      while (guard-- > 0) {
+        if (comp == 0) {
+          if (cs == 0) {
+            put(OP_EQ, (uint32_t)f);
+            break;
+          }
+          int32_t vx = val(cs - x, 0, k);
+          if (vx >= 0) { vx += 1; if (vx > n || vx - k > m) vx = NEG; } else vx = NEG;
+          const int32_t vi = val(cs, 1, k), vd = val(cs, 2, k);
+          const int32_t f0 = max(vx, max(vi, vd));
+          if (f0 < 0) break;  // cannot happen for a reached end cell
+          put(OP_EQ, (uint32_t)(f - f0));
+          if (vx == f0) { put(OP_X, 1); cs -= x; f = f0 - 1; }
+          else if (vi == f0) { comp = 1; f = f0; }
+          else { comp = 2; f = f0; }
+        } else if (comp == 1) {
+          put(OP_I, 1);
+          const int32_t vo = val(cs - oe, 0, k + 1);
+          if (vo == f) { comp = 0; cs -= oe; } else { cs -= e; }
+          k += 1;
+        } else {
+          put(OP_D, 1);
+          const int32_t vo = val(cs - oe, 0, k - 1);
+          if (vo >= 0 && vo + 1 == f) { comp = 0; cs -= oe; } else { cs -= e; }
+          k -= 1;
+          f -= 1;
+        }
+        if (cs < 0) break;
+      }
+      put(0xfu, 1);
+      if (!Wk.direct) O.nruns[p] = nr;
+    }
+    (void)o;
+  }
+}
+
+}  // namespace
+
+WfaPlan wfa_plan(int32_t max_len, const Scoring &P, int64_t budget_bytes, int32_t cus, bool plain) {
+  WfaPlan pl{};
+  const int32_t oe = P.o + P.e;
+  pl.R = std::max(P.x, oe) + 1;
+  const int32_t c = std::min(P.x, P.e);
+  int64_t w = 2 * (int64_t)max_len + 1;
+  if (P.max_score >= 0) w = std::min<int64_t>(w, 2 * (int64_t)(P.max_score / c) + 3);
+  pl.wcap = (int32_t)std::max<int64_t>(w, 1);
+  const int64_t seqw = ((int64_t)max_len + 31) / 32;
+  pl.seq_words = seqw <= 320 ? (int32_t)seqw : 0;
+  const int64_t lds_budget = 32 * 1024;
+  const int64_t fixed = 2 * (int64_t)pl.seq_words * 8 + (int64_t)pl.R * ENTRY * 4;
+  int64_t wl = (lds_budget - fixed) / ((int64_t)pl.R * 12);
+  pl.wcap_lds = plain ? 0 : (int32_t)std::max<int64_t>(0, std::min<int64_t>(wl, pl.wcap));
+  pl.lds_score_bytes = (int32_t)(fixed + (int64_t)pl.R * 3 * pl.wcap_lds * 4);
+  pl.ring_slot_words = (int64_t)pl.R * 3 * pl.wcap;
+  pl.ring_slots = (int32_t)std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * 8, budget_bytes / 4 / (pl.ring_slot_words * 4)));
+  // full-store arena classes
+  pl.lds_arena_words = plain ? 0 : (int32_t)((lds_budget - 2 * (int64_t)pl.seq_words * 8) / 4);
+  pl.need_cap[0] = pl.lds_arena_words;
+  pl.need_cap[1] = (int64_t)1 << 20;
+  pl.need_cap[2] = std::max<int64_t>(pl.need_cap[1], budget_bytes / 4 / 4);
+  pl.arena_slots[0] = cus * 8;
+  pl.arena_slots[1] = (int32_t)std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * 4, budget_bytes / 4 / (pl.need_cap[1] * 4)));
+  pl.arena_slots[2] = 1;
+  return pl;
+}
+
+hipError_t launch_wfa_score(const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk,
+                            const WfaLaunch &L, int32_t *hbm, bool ring_in_lds, int32_t nslots,
+                            hipStream_t s) {
+  const size_t lds = 2 * (size_t)L.seq_words * 8 + (size_t)L.R * ENTRY * 4 +
+                     (ring_in_lds ? (size_t)L.R * 3 * L.wcap * 4 : 0);
+  hipLaunchKernelGGL(k_wfa_score, dim3(nslots), dim3(WG), lds, s, S, O, P, Wk, L, hbm,
+                     (int32_t)ring_in_lds);
+  return hipGetLastError();
+}
+
+hipError_t launch_wfa_trace(const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk,
+                            const WfaLaunch &L, int32_t *hbm, int32_t nslots, hipStream_t s) {
+  const size_t lds = 2 * (size_t)L.seq_words * 8 + (L.full_in_lds ? (size_t)L.slot_words * 4 : 0);
+  hipLaunchKernelGGL(k_wfa_trace, dim3(nslots), dim3(WG), lds, s, S, O, P, Wk, L, hbm);
+  return hipGetLastError();
 }
 
 }  // namespace aim

@@ -1,0 +1,135 @@
+"""Bit-exact parity of the GPU wavefront kernels against the CPU oracle.
+
+The oracle of the WFA path is the Gotoh definition (the wavefront algorithm
+reaches the same optimum and, with the canonical tie order, the same CIGAR);
+pairs too long for the full-matrix oracle's memory are checked against the
+scalar WFA, which the CPU tests pin to Gotoh.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+import synth  # noqa: E402
+import paper_2208_01243_amd as aim  # noqa: E402
+from gpu_util import compare, describe, run  # noqa: E402
+
+AFF = (0, 4, 6, 2)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = aim.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def ctx_plain():
+    c = aim.Context(0, kernel="plain")
+    yield c
+    c.close()
+
+
+def check(ctx, batch, pen=AFF, max_score=-1, **kw):
+    got = run(ctx, batch, "wfa", pen, max_score, **kw)
+    want = oracle.align_batch(batch, "wfa", pen, max_score)
+    bad = compare(got, want)
+    assert not bad, "%d mismatches, first: %s" % (len(bad), describe(batch, bad[0], got, want))
+    return got
+
+
+def _tiny_all(alphabet, maxlen):
+    seqs = [np.array(s, np.uint8) for L in range(maxlen + 1) for s in itertools.product(alphabet, repeat=L)]
+    pats, txts = zip(*[(p, t) for p in seqs for t in seqs])
+    return synth.from_lists(list(pats), list(txts))
+
+
+@pytest.mark.parametrize("pen", [AFF, (0, 3, 4, 1), (0, 2, 1, 1), (0, 9, 1, 1), (0, 1, 0, 1), (0, 5, 0, 2)])
+def test_exhaustive_tiny(ctx, pen):
+    check(ctx, _tiny_all(range(4), 3), pen)
+
+
+def test_exhaustive_tiny_binary(ctx):
+    b = _tiny_all(range(2), 5)
+    for pen in [AFF, (0, 2, 1, 1)]:
+        check(ctx, b, pen)
+        check(ctx, b, pen, max_score=6)
+
+
+def test_wfa250_first_20k(ctx):
+    w = synth.WORKLOADS["wfa250"]
+    b = synth.workload("wfa250", n=20_000)
+    got = check(ctx, b, w["pen"], w["max_score"])
+    rej = (got[1] == aim.PAIR_REJECTED).mean()
+    assert 0.15 < rej < 0.25  # the unrelated fifth of the pairs
+
+
+def test_plain_equals_oracle(ctx_plain):
+    w = synth.WORKLOADS["wfa250"]
+    check(ctx_plain, synth.workload("wfa250", n=2000), w["pen"], w["max_score"])
+
+
+def _mixed(seed, count, lmin, lmax, rates):
+    rng = np.random.default_rng(seed)
+    pats, txts = [], []
+    for _ in range(count):
+        L = int(rng.integers(lmin, lmax + 1))
+        T = rng.integers(0, 4, L).astype(np.uint8)
+        r = float(rng.choice(rates))
+        if r >= 1.0:
+            P = rng.integers(0, 4, int(rng.integers(lmin, lmax + 1))).astype(np.uint8)
+        else:
+            bb = synth.from_lists([T], [T])
+            P, _ = synth.mutate(rng, bb.txt, bb.txt_off, [r])
+        pats.append(P)
+        txts.append(T)
+    return synth.from_lists(pats, txts)
+
+
+@pytest.mark.parametrize("smax", [-1, 0, 8, 40, 200])
+def test_thresholds_and_noise(ctx, smax):
+    check(ctx, _mixed(41, 600, 0, 300, [0.0, 0.02, 0.08, 0.3, 1.0]), AFF, smax)
+
+
+def test_degenerate_pairs(ctx):
+    pats = ["", "", "A", "", "ACGT", "A" * 300, "", "ACGTACGT" * 40, "T" * 200, "G"]
+    txts = ["", "A", "", "ACGTACGTAC", "", "", "C" * 257, "ACGTACGT" * 40, "A" * 200, "G" * 500]
+    b = synth.from_lists(pats, txts)
+    check(ctx, b)
+    check(ctx, b, max_score=10)
+    check(ctx, b, (0, 3, 4, 1))
+
+
+def test_long_reads_vs_scalar_wfa(ctx):
+    # 1-6 kbp at 1-10 %: the full store goes to HBM arenas; compared against
+    # the scalar WFA, which the CPU suite pins to the Gotoh oracle
+    b = _mixed(42, 24, 1000, 6000, [0.01, 0.05, 0.1])
+    s, st, cg, off = run(ctx, b, "wfa", AFF)
+    for i in range(b.n):
+        ws, wsc, wr, _ = oracle.wfa_pair(b.pattern(i), b.text(i), AFF)
+        assert (st[i], s[i]) == (ws, wsc), i
+        assert cg[off[i]:off[i + 1]].tolist() == wr, i
+
+
+def test_many_runs_spill_path(ctx):
+    rng = np.random.default_rng(7)
+    pats, txts = [], []
+    for _ in range(64):
+        T = rng.integers(0, 4, 160).astype(np.uint8)
+        P = T.copy()
+        P[::3] = (P[::3] + 1) % 4
+        pats.append(P)
+        txts.append(T)
+    check(ctx, synth.from_lists(pats, txts), (0, 1, 6, 2))
+
+
+def test_score_only_matches(ctx):
+    b = synth.workload("wfa250", n=3000)
+    full = run(ctx, b, "wfa", AFF, 200)
+    s, st, _, off = run(ctx, b, "wfa", AFF, 200, want_cigar=False)
+    assert np.array_equal(s, full[0]) and np.array_equal(st, full[1]) and not off.any()
