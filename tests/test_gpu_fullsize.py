@@ -1,0 +1,55 @@
+"""Full-size workloads in the launch configuration bench.py times.
+
+Every pair is checked against properties that hold at any size (each CIGAR
+consumes exactly its pair's bases, its rescored cost equals the reported
+score, statuses are consistent); a seeded random sample of pairs is compared
+bit for bit with the oracle, pair by pair.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+import synth  # noqa: E402
+import paper_2208_01243_amd as aim  # noqa: E402
+from gpu_util import run  # noqa: E402
+
+
+def vector_invariants(batch, score, status, cigar, off, pen):
+    """CIGAR consumption and gap-model cost for every aligned pair, vectorised."""
+    _, x, o, e = pen
+    ok = status == aim.PAIR_ALIGNED
+    nr = np.diff(off)
+    assert (nr[~ok] == 0).all()
+    runs = cigar[:off[-1]].astype(np.int64)
+    op, ln = runs & 15, runs >> 4
+    assert (op <= 3).all() and (ln > 0).all()
+    pair = np.repeat(np.arange(batch.n), nr)
+    cons_p = np.bincount(pair, weights=ln * ((op == 0) | (op == 1) | (op == 2)), minlength=batch.n)
+    cons_t = np.bincount(pair, weights=ln * ((op == 0) | (op == 1) | (op == 3)), minlength=batch.n)
+    cost = np.bincount(pair, weights=np.where(op == 1, x * ln, np.where(op >= 2, o + e * ln, 0)),
+                       minlength=batch.n)
+    assert np.array_equal(cons_p[ok], batch.pat_len[ok]) and np.array_equal(cons_t[ok], batch.txt_len[ok])
+    assert np.array_equal(cost[ok].astype(np.int64), score[ok].astype(np.int64))
+    # adjacent runs never repeat an op
+    same = (op[1:] == op[:-1]) & (pair[1:] == pair[:-1])
+    assert not same.any()
+
+
+@pytest.mark.parametrize("name,sample", [("swg150", 3000), ("wfa250", 3000), ("nw100", 10_000)])
+def test_full_workload(name, sample):
+    w = synth.WORKLOADS[name]
+    b = synth.workload(name)
+    with aim.Context(0) as ctx:
+        s, st, cg, off = run(ctx, b, w["alg"], w["pen"], w["max_score"], enc=w["enc"])
+    assert (st != aim.PAIR_INVALID).all() and (st != aim.PAIR_CIGAR_OVERFLOW).all()
+    vector_invariants(b, s, st, cg, off, w["pen"])
+    rng = np.random.default_rng(99)
+    idx = np.sort(rng.choice(b.n, size=min(sample, b.n), replace=False))
+    sub = b.subset(idx)
+    ws, wst, wc, wo = oracle.align_batch(sub, w["alg"], w["pen"], w["max_score"])
+    for t, i in enumerate(idx):
+        assert (s[i], st[i]) == (ws[t], wst[t]), (name, i)
+        assert np.array_equal(cg[off[i]:off[i + 1]], wc[wo[t]:wo[t + 1]]), (name, i)
