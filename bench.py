@@ -94,14 +94,20 @@ def main():
                         cigar_off=cigar_off, want_cigar=True, stream=stream)
 
     ctx = aim.Context(0, timing=True)
-    for _ in range(args.warmup):
+    for k in range(args.warmup):
+        t1 = time.perf_counter()
         step(ctx)
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        log("warmup step %d: %.1f ms" % (k, (time.perf_counter() - t1) * 1000))
     ctx.timing_reset()
     torch.cuda.synchronize()
+    elapsed_hint_ms = (time.perf_counter() - t1) * 1000 if args.warmup else 1e9
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for k in range(args.steps):
         step(ctx)
+        if elapsed_hint_ms > 20000:  # long workloads: show progress (syncs each step)
+            torch.cuda.synchronize()
+            log("step %d done at %.1f s" % (k, time.perf_counter() - t0))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     phases = ctx.timing()

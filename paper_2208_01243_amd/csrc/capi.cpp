@@ -182,7 +182,7 @@ struct Phase {
 };
 
 constexpr int32_t MAX_LEN_LIMIT = 1 << 20;
-constexpr int32_t SLOT_CAP = 48;  // runs per pair held before compaction
+constexpr int32_t SLOT_CAP = 128;  // at most this many runs per pair held before compaction
 
 
 
@@ -191,7 +191,7 @@ constexpr int32_t SLOT_CAP = 48;  // runs per pair held before compaction
 aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const aim::Scoring &P,
                    int64_t n, int32_t L, bool plain, int32_t *cnt, hipStream_t s) {
   aim_status st;
-  const aim::WfaPlan pl = aim::wfa_plan(L, P, c->opt.scratch_limit / 4, c->cus, plain);
+  const aim::WfaPlan pl = aim::wfa_plan(L, P, c->opt.scratch_limit, c->cus, plain);
   if ((st = ensure(c, c->wneed, (size_t)n * 8))) return st;
   if ((st = ensure(c, c->wlists, (size_t)n * 4 * 5))) return st;
   int32_t *lists = as<int32_t>(c->wlists);
@@ -376,7 +376,13 @@ aim_status aim_align_batch(aim_context *c, const aim_batch *B, int32_t alg, aim_
   if ((st = ensure(c, c->spill, (size_t)n * sizeof(int32_t)))) return st;
   if ((st = ensure(c, c->list2, (size_t)n * sizeof(int32_t)))) return st;
   if ((st = ensure(c, c->list3, (size_t)n * sizeof(int32_t)))) return st;
-  const int32_t slot_cap = std::min<int32_t>(SLOT_CAP, 2 * L + 1);
+  // runs held per pair before compaction: with a threshold S an optimal
+  // alignment has at most S / min(x, o + e) non-match runs, so at most twice
+  // that plus one runs in all; pairs with more are re-run in place
+  int64_t run_bound = 2 * (int64_t)L + 1;
+  const int32_t cmin = std::min(pen.mismatch, (alg == AIM_NW_LINEAR ? 0 : pen.gap_open) + pen.gap_extend);
+  if (max_score >= 0) run_bound = std::min<int64_t>(run_bound, 2 * (int64_t)(max_score / cmin) + 1);
+  const int32_t slot_cap = (int32_t)std::max<int64_t>(1, std::min<int64_t>(run_bound, SLOT_CAP));
   if (R->want_cigar && (st = ensure(c, c->slot, (size_t)n * slot_cap * sizeof(uint32_t)))) return st;
   int32_t *cnt = as<int32_t>(c->counters);
   HIP_TRY(aim::launch_fill_i32(cnt, 0, C_N, s));
@@ -476,7 +482,7 @@ aim_status aim_align_batch(aim_context *c, const aim_batch *B, int32_t alg, aim_
   // pairs whose runs exceeded the slot: recompute and write in place
   aim::Work WS{as<int32_t>(c->spill), cnt + C_SPILL, n, cnt + C_SPILL_W, nullptr, nullptr, 1};
   if (alg == AIM_WFA_AFFINE) {
-    aim::WfaPlan pl = aim::wfa_plan(L, P, c->opt.scratch_limit / 4, c->cus, plain);
+    aim::WfaPlan pl = aim::wfa_plan(L, P, c->opt.scratch_limit, c->cus, plain);
     aim::WfaLaunch WL{};
     WL.R = pl.R;
     WL.seq_words = pl.seq_words;

@@ -389,6 +389,7 @@ __global__ __launch_bounds__(WG) void k_wfa_trace(Seqs S, Outs O, Scoring P, Wor
 }  // namespace
 
 WfaPlan wfa_plan(int32_t max_len, const Scoring &P, int64_t budget_bytes, int32_t cus, bool plain) {
+  // budget split: HBM rings 1/8, medium arenas 1/8, large arenas 1/2
   WfaPlan pl{};
   const int32_t oe = P.o + P.e;
   pl.R = std::max(P.x, oe) + 1;
@@ -398,21 +399,24 @@ WfaPlan wfa_plan(int32_t max_len, const Scoring &P, int64_t budget_bytes, int32_
   pl.wcap = (int32_t)std::max<int64_t>(w, 1);
   const int64_t seqw = ((int64_t)max_len + 31) / 32;
   pl.seq_words = seqw <= 320 ? (int32_t)seqw : 0;
-  const int64_t lds_budget = 32 * 1024;
+  const int64_t lds_score = 32 * 1024, lds_trace = 40 * 1024;
   const int64_t fixed = 2 * (int64_t)pl.seq_words * 8 + (int64_t)pl.R * ENTRY * 4;
-  int64_t wl = (lds_budget - fixed) / ((int64_t)pl.R * 12);
+  const int64_t wl = (lds_score - fixed) / ((int64_t)pl.R * 12);
   pl.wcap_lds = plain ? 0 : (int32_t)std::max<int64_t>(0, std::min<int64_t>(wl, pl.wcap));
   pl.lds_score_bytes = (int32_t)(fixed + (int64_t)pl.R * 3 * pl.wcap_lds * 4);
   pl.ring_slot_words = (int64_t)pl.R * 3 * pl.wcap;
-  pl.ring_slots = (int32_t)std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * 8, budget_bytes / 4 / (pl.ring_slot_words * 4)));
-  // full-store arena classes
-  pl.lds_arena_words = plain ? 0 : (int32_t)((lds_budget - 2 * (int64_t)pl.seq_words * 8) / 4);
+  pl.ring_slots = (int32_t)std::max<int64_t>(
+      1, std::min<int64_t>((int64_t)cus * 8, budget_bytes / 8 / (pl.ring_slot_words * 4)));
+  // full-store arena classes (words): LDS, medium HBM slots, large HBM slots
+  pl.lds_arena_words = plain ? 0 : (int32_t)((lds_trace - 2 * (int64_t)pl.seq_words * 8) / 4);
   pl.need_cap[0] = pl.lds_arena_words;
-  pl.need_cap[1] = (int64_t)1 << 20;
-  pl.need_cap[2] = std::max<int64_t>(pl.need_cap[1], budget_bytes / 4 / 4);
+  pl.need_cap[1] = (int64_t)1 << 18;
+  pl.need_cap[2] = std::max<int64_t>(pl.need_cap[1], std::min<int64_t>((int64_t)48 << 20, budget_bytes / 2 / 4));
   pl.arena_slots[0] = cus * 8;
-  pl.arena_slots[1] = (int32_t)std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * 4, budget_bytes / 4 / (pl.need_cap[1] * 4)));
-  pl.arena_slots[2] = 1;
+  pl.arena_slots[1] = (int32_t)std::max<int64_t>(
+      1, std::min<int64_t>((int64_t)cus * 8, budget_bytes / 8 / (pl.need_cap[1] * 4)));
+  pl.arena_slots[2] = (int32_t)std::max<int64_t>(
+      1, std::min<int64_t>((int64_t)cus * 2, budget_bytes / 2 / (pl.need_cap[2] * 4)));
   return pl;
 }
 
