@@ -40,6 +40,51 @@ struct Outs {
   uint32_t *cigar;
   const int64_t *cigar_off;
   int64_t cigar_cap;
+  // Runs beyond slot_cap go to a shared pool: the first overflowing run of a
+  // pair reserves `bound` words with one atomic add; pool_off[p] is that
+  // offset (-1: none, -2: pool exhausted, the pair is re-run in place).
+  uint32_t *pool;
+  int64_t pool_cap;
+  unsigned long long *pool_top;
+  int64_t *pool_off;
+};
+
+// Appends runs of one pair (last op first) to its slot, then to the pool.
+struct RunSink {
+  uint32_t *slot;
+  int32_t cap;
+  uint32_t *pool;
+  int64_t pool_cap;
+  unsigned long long *pool_top;
+  int64_t *pool_off;  // &Outs::pool_off[p]
+  int64_t pbase;      // reserved pool offset, -1 none, -2 failed
+  __device__ void begin(const Outs &O, int64_t p) {
+    slot = O.slot + p * (int64_t)O.slot_cap;
+    cap = O.slot_cap;
+    pool = O.pool;
+    pool_cap = O.pool_cap;
+    pool_top = O.pool_top;
+    pool_off = O.pool_off + p;
+    pbase = -1;
+  }
+  // nr: index of this run; more: upper bound on the runs still to come
+  // (this one included) when the pool is first needed.
+  __device__ void put(int32_t nr, uint32_t run, int64_t more) {
+    if (nr < cap) {
+      slot[nr] = run;
+      return;
+    }
+    if (pbase == -1) {
+      const unsigned long long need = (unsigned long long)(more > 0 ? more : 1);
+      const unsigned long long at = atomicAdd(pool_top, need);
+      pbase = (at + need <= (unsigned long long)pool_cap) ? (int64_t)at : -2;
+      *pool_off = pbase;
+    }
+    if (pbase >= 0) pool[pbase + (nr - cap)] = run;
+  }
+  __device__ void finish() {
+    if (pbase == -1) *pool_off = -1;
+  }
 };
 
 struct Scoring {
@@ -92,28 +137,30 @@ struct WfaLaunch {
   int64_t slot_words;   // HBM slot per workgroup (pass 1 ring / pass 2 arena), or LDS arena words
   int32_t *ring_list;   // pass 1: pairs whose width passed wcap
   int32_t *ring_count;
-  int32_t *need_list[3];  // pass 1 -> pass 2: accepted pairs by full-store class
-  int32_t *need_count[3];
-  int64_t need_cap[3];    // class capacities in words
+  int32_t *need_list[4];  // pass 1 -> pass 2: accepted pairs by full-store class
+  int32_t *need_count[4];
+  int64_t need_cap[4];    // class capacities in words
   int64_t *need;          // per pair: words of the full store
 };
 
 struct WfaPlan {
-  int32_t R, wcap, wcap_lds, seq_words, lds_score_bytes, ring_slots, lds_arena_words;
+  int32_t R, wcap, wcap_lds, seq_words, lds_score_bytes, ring_slots, ring_threads, lds_arena_words;
   int64_t ring_slot_words;
-  int64_t need_cap[3];
-  int32_t arena_slots[3];
+  int64_t need_cap[4];
+  int32_t arena_slots[4];
+  int32_t threads[4];
 };
 
 WfaPlan wfa_plan(int32_t max_len, const Scoring &P, int64_t budget_bytes, int32_t cus, bool plain);
 hipError_t launch_wfa_score(const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk,
                             const WfaLaunch &L, int32_t *hbm, bool ring_in_lds, int32_t nslots,
-                            hipStream_t s);
+                            int32_t threads, hipStream_t s);
 hipError_t launch_wfa_trace(const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk,
-                            const WfaLaunch &L, int32_t *hbm, int32_t nslots, hipStream_t s);
+                            const WfaLaunch &L, int32_t *hbm, int32_t nslots, int32_t threads,
+                            hipStream_t s);
 
-// CIGAR compaction: cigar_off from nruns (with the cap cut), copy slot runs,
-// collect pairs whose runs exceeded the slot into spill list.
+// CIGAR compaction: cigar_off from nruns (with the cap cut), copy slot and
+// pool runs, collect pairs whose runs could not be held into the spill list.
 hipError_t launch_compact(int64_t n, const Outs &O, int64_t *cigar_off, uint32_t *cigar,
                           int64_t cigar_cap, int64_t *scan_tmp, int64_t *total_written,
                           int32_t *spill_idx, int32_t *spill_count, int8_t *status,

@@ -89,7 +89,7 @@ struct aim_context {
   int32_t cus = 256;
   PhaseTimer timer;
   Buf flags, pflag, tflag, pat2, txt2, pat2off, txt2off, nruns, slot, tb32, tb64, full, list2,
-      list3, counters, scan_tmp, spill, total, wring, warena1, warena2, wneed, wlists;
+      list3, counters, scan_tmp, spill, total, wring, warena1, warena2, warena3, wneed, wlists, pool, pooloff;
 };
 
 namespace {
@@ -138,7 +138,7 @@ struct DeviceGuard {
 
 enum Counter {
   C_T1 = 0, C_T2, C_T3, C_L2, C_L3, C_SPILL, C_SPILL_W,
-  C_W1, C_W1G, C_RL, C_FAIL, C_N0, C_N1, C_N2, C_P0, C_P1, C_P2,
+  C_W1, C_W1G, C_RL, C_FAIL, C_N0, C_N1, C_N2, C_N3, C_P0, C_P1, C_P2, C_P3,
   C_N = 32
 };
 
@@ -193,14 +193,14 @@ aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const
   aim_status st;
   const aim::WfaPlan pl = aim::wfa_plan(L, P, c->opt.scratch_limit, c->cus, plain);
   if ((st = ensure(c, c->wneed, (size_t)n * 8))) return st;
-  if ((st = ensure(c, c->wlists, (size_t)n * 4 * 5))) return st;
+  if ((st = ensure(c, c->wlists, (size_t)n * 4 * 6))) return st;
   int32_t *lists = as<int32_t>(c->wlists);
   aim::WfaLaunch WL{};
   WL.R = pl.R;
   WL.seq_words = pl.seq_words;
   WL.ring_list = lists;
   WL.ring_count = cnt + C_RL;
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < 4; ++k) {
     WL.need_list[k] = lists + (int64_t)n * (k + 1);
     WL.need_count[k] = cnt + C_N0 + k;
     WL.need_cap[k] = pl.need_cap[k];
@@ -212,7 +212,7 @@ aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const
     A.wcap = pl.wcap_lds;
     aim::Work W{nullptr, nullptr, n, cnt + C_W1, nullptr, nullptr, 0};
     Phase ph(c, s, "wfa_score");
-    HIP_TRY(aim::launch_wfa_score(S, O, P, W, A, nullptr, true, slots, s));
+    HIP_TRY(aim::launch_wfa_score(S, O, P, W, A, nullptr, true, slots, 64, s));
   }
   {
     // pairs whose wavefronts outgrew the LDS ring (all pairs for the plain path)
@@ -220,32 +220,33 @@ aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const
     aim::WfaLaunch B = WL;
     B.wcap = pl.wcap;
     B.slot_words = pl.ring_slot_words;
-    B.ring_list = lists + (int64_t)n * 4;  // never reached: wcap bounds every width
+    B.ring_list = lists + (int64_t)n * 5;  // never reached: wcap bounds every width
     B.ring_count = cnt + C_FAIL;
     const bool all = plain || pl.wcap_lds == 0;
     aim::Work W{all ? nullptr : lists, all ? nullptr : cnt + C_RL, n, cnt + C_W1G, nullptr, nullptr, 0};
     Phase ph(c, s, "wfa_score_hbm");
     HIP_TRY(aim::launch_wfa_score(S, O, P, W, B, as<int32_t>(c->wring), false,
-                                  all ? std::min<int32_t>(slots, pl.ring_slots) : pl.ring_slots, s));
+                                  all ? std::min<int32_t>(slots, pl.ring_slots) : pl.ring_slots,
+                                  plain ? 64 : pl.ring_threads, s));
   }
   if (!P.want_cigar) return AIM_OK;
-  // pass 2 by class: 0 LDS arena, 1 medium HBM slots, 2 large HBM slot
-  for (int k = 0; k < 3; ++k) {
+  // pass 2 by class: 0 LDS arena, 1-3 HBM slots of growing size
+  Buf *arena[4] = {nullptr, &c->warena1, &c->warena2, &c->warena3};
+  static const char *names[4] = {"wfa_trace_lds", "wfa_trace_1m", "wfa_trace_16m", "wfa_trace_192m"};
+  for (int k = 0; k < 4; ++k) {
     if (k == 0 && (plain || pl.lds_arena_words <= 0)) continue;
     aim::WfaLaunch T = WL;
     T.full_in_lds = k == 0;
     T.slot_words = k == 0 ? pl.lds_arena_words : pl.need_cap[k];
     int32_t *hbm = nullptr;
-    if (k == 1) {
-      if ((st = ensure(c, c->warena1, (size_t)pl.need_cap[1] * 4 * pl.arena_slots[1]))) return st;
-      hbm = as<int32_t>(c->warena1);
-    } else if (k == 2) {
-      if ((st = ensure(c, c->warena2, (size_t)pl.need_cap[2] * 4 * pl.arena_slots[2]))) return st;
-      hbm = as<int32_t>(c->warena2);
+    if (k > 0) {
+      if ((st = ensure(c, *arena[k], (size_t)pl.need_cap[k] * 4 * pl.arena_slots[k]))) return st;
+      hbm = as<int32_t>(*arena[k]);
     }
     aim::Work W{WL.need_list[k], WL.need_count[k], n, cnt + C_P0 + k, nullptr, nullptr, 0};
-    Phase ph(c, s, k == 0 ? "wfa_trace_lds" : (k == 1 ? "wfa_trace_hbm" : "wfa_trace_large"));
-    HIP_TRY(aim::launch_wfa_trace(S, O, P, W, T, hbm, k == 0 ? slots : pl.arena_slots[k], s));
+    Phase ph(c, s, names[k]);
+    HIP_TRY(aim::launch_wfa_trace(S, O, P, W, T, hbm, k == 0 ? slots : pl.arena_slots[k],
+                                  plain ? 64 : pl.threads[k], s));
   }
   return AIM_OK;
 }
@@ -311,7 +312,7 @@ void aim_destroy(aim_context *c) {
   Buf *all[] = {&c->flags, &c->pflag, &c->tflag, &c->pat2, &c->txt2, &c->pat2off, &c->txt2off,
                 &c->nruns, &c->slot, &c->tb32, &c->tb64, &c->full, &c->list2, &c->list3,
                 &c->counters, &c->scan_tmp, &c->spill, &c->total, &c->wring, &c->warena1,
-                &c->warena2, &c->wneed, &c->wlists};
+                &c->warena2, &c->warena3, &c->wneed, &c->wlists, &c->pool, &c->pooloff};
   for (Buf *b : all)
     if (b->p) (void)hipFree(b->p);
   delete c;
@@ -418,8 +419,14 @@ aim_status aim_align_batch(aim_context *c, const aim_batch *B, int32_t alg, aim_
   HIP_TRY(aim::launch_pair_flags(n, L, B->pat_len, B->txt_len, pf, tf, as<int8_t>(c->flags), s));
   }
 
+  // pool for runs beyond the per-pair slot (reset every call)
+  const int64_t pool_cap = R->want_cigar ? std::max<int64_t>(1 << 20, c->opt.scratch_limit / 32 / 4) : 1;
+  if ((st = ensure(c, c->pool, (size_t)pool_cap * 4))) return st;
+  if ((st = ensure(c, c->pooloff, (size_t)n * 8))) return st;
+  HIP_TRY(aim::launch_fill_i32(as<int32_t>(c->total) + 2, 0, 2, s));
   aim::Outs O{R->score, R->status, as<int32_t>(c->nruns), as<uint32_t>(c->slot), slot_cap,
-              as<int8_t>(c->flags), R->cigar, R->cigar_off, R->cigar_cap};
+              as<int8_t>(c->flags), R->cigar, R->cigar_off, R->cigar_cap, as<uint32_t>(c->pool),
+              pool_cap, (unsigned long long *)(as<int64_t>(c->total) + 1), as<int64_t>(c->pooloff)};
   const int64_t budget = c->opt.scratch_limit / 4;
   const bool plain = c->opt.kernel == AIM_KERNEL_PLAIN;
 
@@ -487,11 +494,12 @@ aim_status aim_align_batch(aim_context *c, const aim_batch *B, int32_t alg, aim_
     WL.R = pl.R;
     WL.seq_words = pl.seq_words;
     WL.full_in_lds = 0;
-    WL.slot_words = pl.need_cap[2];
+    WL.slot_words = pl.need_cap[3];
     WL.need = as<int64_t>(c->wneed);
-    if ((st = ensure(c, c->warena2, (size_t)pl.need_cap[2] * 4 * pl.arena_slots[2]))) return st;
+    if ((st = ensure(c, c->warena3, (size_t)pl.need_cap[3] * 4 * pl.arena_slots[3]))) return st;
     Phase ph(c, s, "wfa_rerun");
-    HIP_TRY(aim::launch_wfa_trace(S, O, P, WS, WL, as<int32_t>(c->warena2), pl.arena_slots[2], s));
+    HIP_TRY(aim::launch_wfa_trace(S, O, P, WS, WL, as<int32_t>(c->warena3), pl.arena_slots[3],
+                                  pl.threads[3], s));
   } else {
     if ((st = run_full(WS, n))) return st;
   }

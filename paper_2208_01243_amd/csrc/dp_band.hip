@@ -260,8 +260,8 @@ __global__ __launch_bounds__(64) void k_band(Seqs S, Outs O, Scoring P, Work Wk,
       int32_t i = m, j = n, b = bstar, st = 0;  // st: 0 H, 1 E (I run), 2 F (D run)
       uint32_t cur_op = 0xffu, cur_len = 0;
       int32_t nr = 0;
-      uint32_t *slot = O.slot + p * O.slot_cap;
-      const int32_t cap = O.slot_cap;
+      RunSink sink;
+      sink.begin(O, p);
       int64_t pq = -1, tq = -1;
       uint64_t pw = 0, tw = 0;
       int32_t rowi = -1;
@@ -271,7 +271,7 @@ __global__ __launch_bounds__(64) void k_band(Seqs S, Outs O, Scoring P, Work Wk,
           cur_len += len;
         } else {
           if (cur_len) {
-            if (nr < cap) slot[nr] = (cur_len << 4) | cur_op;
+            sink.put(nr, (cur_len << 4) | cur_op, (int64_t)i + j + 1);
             ++nr;
           }
           cur_op = op;
@@ -328,6 +328,7 @@ __global__ __launch_bounds__(64) void k_band(Seqs S, Outs O, Scoring P, Work Wk,
       if (i > 0) put(OP_I, (uint32_t)i);
       if (j > 0) put(OP_D, (uint32_t)j);
       put(0xfu, 0);  // flush the last run
+      sink.finish();
       O.nruns[p] = nr;
     }
   }

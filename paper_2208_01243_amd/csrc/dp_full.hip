@@ -154,11 +154,11 @@ __global__ __launch_bounds__(NT) void k_full(Seqs S, Outs O, Scoring P, Work Wk,
 
     // ---------------- traceback ----------------
     const int32_t total = Wk.direct ? O.nruns[p] : 0;
-    uint32_t *dst = Wk.direct ? (O.cigar + O.cigar_off[p]) : (O.slot + p * O.slot_cap);
-    const int32_t cap = O.slot_cap;
+    uint32_t *dst = Wk.direct ? (O.cigar + O.cigar_off[p]) : nullptr;
+    __shared__ long long sh_pbase;
     if (t == 0) {
       sh_i = m; sh_j = n; sh_st = 0; sh_nr = 0; sh_done = 0;
-      sh_op = 0xffu; sh_len = 0;
+      sh_op = 0xffu; sh_len = 0; sh_pbase = -1;
     }
     for (;;) {
       __syncthreads();
@@ -177,6 +177,9 @@ __global__ __launch_bounds__(NT) void k_full(Seqs S, Outs O, Scoring P, Work Wk,
       if (t == 0) {
         int32_t i = i0, j = j0, st = sh_st, nr = sh_nr;
         uint32_t cur_op = sh_op, cur_len = sh_len;
+        RunSink sink;
+        sink.begin(O, p);
+        sink.pbase = sh_pbase;
         auto put = [&](uint32_t op, uint32_t len) {
           if (op == cur_op) {
             cur_len += len;
@@ -184,7 +187,7 @@ __global__ __launch_bounds__(NT) void k_full(Seqs S, Outs O, Scoring P, Work Wk,
             if (cur_len) {
               const uint32_t run = (cur_len << 4) | cur_op;
               if (Wk.direct) { if (nr < total) dst[total - 1 - nr] = run; }
-              else if (nr < cap) dst[nr] = run;
+              else sink.put(nr, run, (int64_t)i + j + 1);
               ++nr;
             }
             cur_op = op;
@@ -227,9 +230,13 @@ __global__ __launch_bounds__(NT) void k_full(Seqs S, Outs O, Scoring P, Work Wk,
           i = 0;
           j = 0;
           sh_done = 1;
-          if (!Wk.direct) O.nruns[p] = nr;
+          if (!Wk.direct) {
+            sink.finish();
+            O.nruns[p] = nr;
+          }
         }
         sh_i = i; sh_j = j; sh_st = st; sh_nr = nr; sh_op = cur_op; sh_len = cur_len;
+        sh_pbase = sink.pbase;
       }
     }
   }

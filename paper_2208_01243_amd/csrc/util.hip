@@ -168,8 +168,9 @@ __global__ void k_cut(int64_t n, const int64_t *excl, int64_t cap, unsigned long
 
 __global__ void k_scatter(int64_t n, const int64_t *excl, const unsigned long long *tw_p,
                           const int32_t *nruns, const uint32_t *slot, int32_t slot_cap,
-                          int64_t *cigar_off, uint32_t *cigar, int32_t *spill_idx,
-                          int32_t *spill_count, int8_t *status) {
+                          const uint32_t *pool, const int64_t *pool_off, int64_t *cigar_off,
+                          uint32_t *cigar, int32_t *spill_idx, int32_t *spill_count,
+                          int8_t *status) {
   const int64_t tw = (int64_t)*tw_p;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
@@ -182,13 +183,16 @@ __global__ void k_scatter(int64_t n, const int64_t *excl, const unsigned long lo
       status[i] = ST_OVERFLOW;
       continue;
     }
-    if (r > slot_cap) {
+    const int64_t pb = r > slot_cap ? pool_off[i] : -1;
+    if (r > slot_cap && pb < 0) {
       const int32_t k = atomicAdd(spill_count, 1);
       spill_idx[k] = (int32_t)i;
       continue;
     }
     const uint32_t *src = slot + i * (int64_t)slot_cap;
-    for (int32_t k = 0; k < r; ++k) cigar[a + r - 1 - k] = src[k];
+    const int32_t r0 = r < slot_cap ? r : slot_cap;
+    for (int32_t k = 0; k < r0; ++k) cigar[a + r - 1 - k] = src[k];
+    for (int32_t k = r0; k < r; ++k) cigar[a + r - 1 - k] = pool[pb + (k - slot_cap)];
   }
 }
 
@@ -268,8 +272,8 @@ hipError_t launch_compact(int64_t n, const Outs &O, int64_t *cigar_off, uint32_t
   if (n > 0) {
     hipLaunchKernelGGL(k_cut, grid_for(n, 256), dim3(256), 0, s, n, excl, cigar_cap, tw);
     hipLaunchKernelGGL(k_scatter, grid_for(n, 256), dim3(256), 0, s, n, excl,
-                       (const unsigned long long *)tw, O.nruns, O.slot, O.slot_cap, cigar_off,
-                       cigar, spill_idx, spill_count, status);
+                       (const unsigned long long *)tw, O.nruns, O.slot, O.slot_cap, O.pool,
+                       O.pool_off, cigar_off, cigar, spill_idx, spill_count, status);
   } else {
     hipLaunchKernelGGL(k_zero_offsets, dim3(1), dim3(64), 0, s, (int64_t)0, cigar_off);
   }

@@ -34,7 +34,7 @@ namespace aim {
 namespace {
 
 constexpr int32_t NEG = INT32_MIN / 4;  // absent / invalid offset
-constexpr int WG = 64;
+constexpr int WGMAX = 256;             // largest workgroup (wide pairs)
 constexpr int ENTRY = 4;                // table entry: lo, hi, base, present-bits
 
 
@@ -119,7 +119,8 @@ __device__ __forceinline__ int wf_step(int32_t s, int32_t x, int32_t oe, int32_t
   int32_t *dM = dst_base_store + dst_base;
   int32_t *dI = dM + w;
   int32_t *dD = dI + w;
-  for (int32_t k = lo + lane; k <= hi; k += WG) {
+  const int32_t nt = (int32_t)blockDim.x;
+  for (int32_t k = lo + lane; k <= hi; k += nt) {
     int32_t vi = NEG, vd = NEG, vx = NEG;
     // I: from k + 1
     if (fo && k + 1 >= olo && k + 1 <= ohi) vi = store[ob + (k + 1 - olo)];
@@ -145,7 +146,7 @@ __device__ __forceinline__ int wf_step(int32_t s, int32_t x, int32_t oe, int32_t
 }
 
 __device__ __forceinline__ void stage_seq(uint64_t *lds, const uint64_t *g, int64_t nw) {
-  for (int64_t q = threadIdx.x; q < nw; q += WG) lds[q] = g[q];
+  for (int64_t q = threadIdx.x; q < nw; q += blockDim.x) lds[q] = g[q];
 }
 
 __device__ __forceinline__ void wave_append1(bool pred, int32_t v, int32_t *list, int32_t *cnt) {
@@ -157,7 +158,7 @@ __device__ __forceinline__ void wave_append1(bool pred, int32_t v, int32_t *list
 
 // ---------------------------------------------------------------- pass 1
 // ring_in_lds: ring lives in dynamic LDS; else in the HBM slot of this WG.
-__global__ __launch_bounds__(WG) void k_wfa_score(Seqs S, Outs O, Scoring P, Work Wk, WfaLaunch L,
+__global__ __launch_bounds__(WGMAX) void k_wfa_score(Seqs S, Outs O, Scoring P, Work Wk, WfaLaunch L,
                                                   int32_t *hbm, int32_t ring_in_lds) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int32_t sh_pair;
@@ -247,8 +248,9 @@ __global__ __launch_bounds__(WG) void k_wfa_score(Seqs S, Outs O, Scoring P, Wor
         O.nruns[p] = 0;
         if (P.want_cigar) {
           L.need[p] = need;
-          int c = need <= L.need_cap[0] ? 0 : (need <= L.need_cap[1] ? 1 : 2);
-          if (need > L.need_cap[2]) {
+          int c = 0;
+          while (c < 3 && need > L.need_cap[c]) ++c;
+          if (need > L.need_cap[3]) {
             O.status[p] = ST_OVERFLOW;  // full store larger than any arena class
           } else {
             const int32_t k = atomicAdd(L.need_count[c], 1);
@@ -261,7 +263,7 @@ __global__ __launch_bounds__(WG) void k_wfa_score(Seqs S, Outs O, Scoring P, Wor
 }
 
 // ---------------------------------------------------------------- pass 2
-__global__ __launch_bounds__(WG) void k_wfa_trace(Seqs S, Outs O, Scoring P, Work Wk, WfaLaunch L,
+__global__ __launch_bounds__(WGMAX) void k_wfa_trace(Seqs S, Outs O, Scoring P, Work Wk, WfaLaunch L,
                                                   int32_t *hbm) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int32_t sh_pair, sh_top;
@@ -321,10 +323,14 @@ __global__ __launch_bounds__(WG) void k_wfa_trace(Seqs S, Outs O, Scoring P, Wor
     // ---- backtrace (one lane) ----
     if (lane == 0) {
       const int32_t total = Wk.direct ? O.nruns[p] : 0;
-      uint32_t *dst = Wk.direct ? (O.cigar + O.cigar_off[p]) : (O.slot + p * O.slot_cap);
-      const int32_t cap = O.slot_cap;
+      uint32_t *dst = Wk.direct ? (O.cigar + O.cigar_off[p]) : nullptr;
+      RunSink sink;
+      sink.begin(O, p);
       uint32_t cur_op = 0xffu, cur_len = 0;
       int32_t nr = 0;
+      // runs still to come are at most 2 * (score left) / min(x, o + e) + 2
+      const int32_t cmin = max(1, min(x, oe));
+      int32_t cs = sfin;
       auto put = [&](uint32_t op, uint32_t len) {
         if (len == 0) return;
         if (op == cur_op) {
@@ -333,7 +339,7 @@ __global__ __launch_bounds__(WG) void k_wfa_trace(Seqs S, Outs O, Scoring P, Wor
           if (cur_len) {
             const uint32_t run = (cur_len << 4) | cur_op;
             if (Wk.direct) { if (nr < total) dst[total - 1 - nr] = run; }
-            else if (nr < cap) dst[nr] = run;
+            else sink.put(nr, run, 2 * (int64_t)(cs / cmin) + 3);
             ++nr;
           }
           cur_op = op;
@@ -347,7 +353,7 @@ __global__ __launch_bounds__(WG) void k_wfa_trace(Seqs S, Outs O, Scoring P, Wor
         if (!(pr & (1 << comp)) || k < lo || k > hi) return NEG;
         return arena[tab[s2 * ENTRY + 2] + comp * (hi - lo + 1) + (k - lo)];
       };
-      int32_t cs = sfin, k = n - m, f = n, comp = 0;
+      int32_t k = n - m, f = n, comp = 0;
       // each step emits one op or closes a run; the walk has at most m + n ops
       int64_t guard = 2 * ((int64_t)m + n) + 8;
       while (guard-- > 0) {
@@ -380,7 +386,10 @@ __global__ __launch_bounds__(WG) void k_wfa_trace(Seqs S, Outs O, Scoring P, Wor
         if (cs < 0) break;
       }
       put(0xfu, 1);
-      if (!Wk.direct) O.nruns[p] = nr;
+      if (!Wk.direct) {
+        sink.finish();
+        O.nruns[p] = nr;
+      }
     }
     (void)o;
   }
@@ -389,7 +398,7 @@ __global__ __launch_bounds__(WG) void k_wfa_trace(Seqs S, Outs O, Scoring P, Wor
 }  // namespace
 
 WfaPlan wfa_plan(int32_t max_len, const Scoring &P, int64_t budget_bytes, int32_t cus, bool plain) {
-  // budget split: HBM rings 1/8, medium arenas 1/8, large arenas 1/2
+  // budget split: HBM rings 1/8, arena classes 1/8, 1/8 and 1/4
   WfaPlan pl{};
   const int32_t oe = P.o + P.e;
   pl.R = std::max(P.x, oe) + 1;
@@ -406,34 +415,42 @@ WfaPlan wfa_plan(int32_t max_len, const Scoring &P, int64_t budget_bytes, int32_
   pl.lds_score_bytes = (int32_t)(fixed + (int64_t)pl.R * 3 * pl.wcap_lds * 4);
   pl.ring_slot_words = (int64_t)pl.R * 3 * pl.wcap;
   pl.ring_slots = (int32_t)std::max<int64_t>(
-      1, std::min<int64_t>((int64_t)cus * 8, budget_bytes / 8 / (pl.ring_slot_words * 4)));
-  // full-store arena classes (words): LDS, medium HBM slots, large HBM slots
+      1, std::min<int64_t>((int64_t)cus * 4, budget_bytes / 8 / (pl.ring_slot_words * 4)));
+  pl.ring_threads = max_len > 1024 ? 256 : 64;
+  // full-store arena classes (words): LDS, then HBM slots of 1 MB, 16 MB and
+  // 192 MB, with fewer and wider workgroups for the larger classes
   pl.lds_arena_words = plain ? 0 : (int32_t)((lds_trace - 2 * (int64_t)pl.seq_words * 8) / 4);
   pl.need_cap[0] = pl.lds_arena_words;
   pl.need_cap[1] = (int64_t)1 << 18;
-  pl.need_cap[2] = std::max<int64_t>(pl.need_cap[1], std::min<int64_t>((int64_t)48 << 20, budget_bytes / 2 / 4));
+  pl.need_cap[2] = (int64_t)1 << 22;
+  pl.need_cap[3] = std::max<int64_t>(pl.need_cap[2], std::min<int64_t>((int64_t)48 << 20, budget_bytes / 4 / 4));
   pl.arena_slots[0] = cus * 8;
-  pl.arena_slots[1] = (int32_t)std::max<int64_t>(
-      1, std::min<int64_t>((int64_t)cus * 8, budget_bytes / 8 / (pl.need_cap[1] * 4)));
-  pl.arena_slots[2] = (int32_t)std::max<int64_t>(
-      1, std::min<int64_t>((int64_t)cus * 2, budget_bytes / 2 / (pl.need_cap[2] * 4)));
+  pl.threads[0] = 64;
+  const int64_t share[4] = {0, budget_bytes / 8, budget_bytes / 8, budget_bytes / 4};
+  const int64_t cap_slots[4] = {0, (int64_t)cus * 8, (int64_t)cus * 2, (int64_t)cus};
+  for (int k = 1; k < 4; ++k)
+    pl.arena_slots[k] = (int32_t)std::max<int64_t>(1, std::min<int64_t>(cap_slots[k], share[k] / (pl.need_cap[k] * 4)));
+  pl.threads[1] = 64;
+  pl.threads[2] = 256;
+  pl.threads[3] = 256;
   return pl;
 }
 
 hipError_t launch_wfa_score(const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk,
                             const WfaLaunch &L, int32_t *hbm, bool ring_in_lds, int32_t nslots,
-                            hipStream_t s) {
+                            int32_t threads, hipStream_t s) {
   const size_t lds = 2 * (size_t)L.seq_words * 8 + (size_t)L.R * ENTRY * 4 +
                      (ring_in_lds ? (size_t)L.R * 3 * L.wcap * 4 : 0);
-  hipLaunchKernelGGL(k_wfa_score, dim3(nslots), dim3(WG), lds, s, S, O, P, Wk, L, hbm,
+  hipLaunchKernelGGL(k_wfa_score, dim3(nslots), dim3(threads), lds, s, S, O, P, Wk, L, hbm,
                      (int32_t)ring_in_lds);
   return hipGetLastError();
 }
 
 hipError_t launch_wfa_trace(const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk,
-                            const WfaLaunch &L, int32_t *hbm, int32_t nslots, hipStream_t s) {
+                            const WfaLaunch &L, int32_t *hbm, int32_t nslots, int32_t threads,
+                            hipStream_t s) {
   const size_t lds = 2 * (size_t)L.seq_words * 8 + (L.full_in_lds ? (size_t)L.slot_words * 4 : 0);
-  hipLaunchKernelGGL(k_wfa_trace, dim3(nslots), dim3(WG), lds, s, S, O, P, Wk, L, hbm);
+  hipLaunchKernelGGL(k_wfa_trace, dim3(nslots), dim3(threads), lds, s, S, O, P, Wk, L, hbm);
   return hipGetLastError();
 }
 
