@@ -57,6 +57,8 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=2, help="steps of the plain kernel (0: skip)")
     ap.add_argument("--cpu-sample", type=int, default=200_000, help="pairs for the CPU baseline (0: skip)")
     ap.add_argument("--cpu-threads", type=int, default=16)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -66,6 +68,14 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.calibrate_copy:
+        x = torch.ones(1 << 28, dtype=torch.int32, device="cuda")  # 1 GiB
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        log("copied 3 x 1 GiB")
+        return
     import synth
     import paper_2208_01243_amd as aim
     sys.path.insert(0, os.path.join(ROOT, "tests"))
