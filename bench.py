@@ -31,6 +31,11 @@ HBM_PEAK_GBS = 8000.0
 # Gotoh: E 3, F 3, H 3 (diag add, two mins), 4 traceback bits 4 -> 13 (+1 for the
 # mismatch test) = 14; linear NW: 2 adds + 2 mins + diag add + 2 bits + test = 10
 OPS_PER_CELL = {"swg": 14, "nw": 10, "wfa": 14}
+# HBM bytes per launch of the dominant kernel from two rocprofv3 --pmc passes
+# (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0 after the copy-kernel calibration; see
+# profiles/k_band32_swg150_hbm_counters.md), valid only for the kernel source
+# they were taken on (first 16 hex of its SHA-256).
+MEASURED_TRAFFIC = {("swg150", "k_band<32>"): ("97f098b4c8c88d70", 7.982e9)}
 
 WORKLOAD_TEXT = {
     "swg150": "Gotoh 4/6/2 global, 1,000,000 pairs x 150 bp, 4% error (1/3 sub, ins, del), "
@@ -140,9 +145,14 @@ def main():
         if band_launches:
             t_launch = band_ms / band_launches / 1000.0
             achieved = ops / t_launch / 1e12
+            import hashlib
+            src = open(os.path.join(ROOT, "paper_2208_01243_amd", "csrc", "dp_band.hip"), "rb").read()
+            h = hashlib.sha256(src).hexdigest()[:16]
+            meas = MEASURED_TRAFFIC.get((args.workload, "k_band<32>"))
+            traffic = meas[1] if (meas and meas[0] == h and n == w["total"]) else None
             roof = {"bound": "alu", "kernel": "k_band<32>", "achieved": round(achieved, 3),
                     "peak": round(PEAK_INT32_TOPS, 1), "unit": "Tops/s (int32)",
-                    "frac": round(achieved / PEAK_INT32_TOPS, 4), "traffic": None,
+                    "frac": round(achieved / PEAK_INT32_TOPS, 4), "traffic": traffic,
                     "avg_launch_ms": round(band_ms / band_launches, 4),
                     "ops_per_cell": OPS_PER_CELL[w["alg"]], "cells_per_launch": cells_band}
     elif "wfa" in phases:
