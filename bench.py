@@ -62,6 +62,7 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=2, help="steps of the plain kernel (0: skip)")
     ap.add_argument("--cpu-sample", type=int, default=200_000, help="pairs for the CPU baseline (0: skip)")
     ap.add_argument("--cpu-threads", type=int, default=16)
+    ap.add_argument("--graph", action="store_true", help="time replays of a captured HIP graph")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -102,13 +103,23 @@ def main():
     cigar = torch.empty(cap, dtype=torch.int32, device="cuda")
     cigar_off = torch.empty(n + 1, dtype=torch.int64, device="cuda")
     stream = torch.cuda.current_stream()
+    step = None
 
-    def step(ctx):
+    def c_step(ctx):
         ctx.align_batch(*dev, enc=enc, max_len=max_len, alg=w["alg"], pen=w["pen"],
                         max_score=w["max_score"], score=score, status=status, cigar=cigar,
                         cigar_off=cigar_off, want_cigar=True, stream=stream)
 
-    ctx = aim.Context(0, timing=True)
+    step = c_step
+    ctx = aim.Context(0, timing=not args.graph)
+    graph = None
+    if args.graph:
+        stream = torch.cuda.Stream()
+        torch.cuda.set_stream(stream)
+        graph = ctx.graph_capture(*dev, enc=enc, max_len=max_len, alg=w["alg"], pen=w["pen"],
+                                  max_score=w["max_score"], score=score, status=status, cigar=cigar,
+                                  cigar_off=cigar_off, want_cigar=True, stream=stream)
+        step = lambda c: graph.launch(stream) if c is ctx else c_step(c)  # noqa: E731
     for k in range(args.warmup):
         t1 = time.perf_counter()
         step(ctx)

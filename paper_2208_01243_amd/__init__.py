@@ -62,6 +62,16 @@ SIGNATURES = {
     "aim_timing": ([vp, i32, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_double),
                     ctypes.POINTER(i64)], i32),
     "aim_timing_reset": ([vp], i32),
+    "aim_autotune": ([vp, ctypes.POINTER(Batch), i32, Penalties, i32, ctypes.POINTER(Results), vp, i32,
+                      ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)], i32),
+    "aim_tune_get": ([vp, i32, i32, ctypes.POINTER(i32)], i32),
+    "aim_tune_set": ([vp, i32, i32, ctypes.POINTER(i32)], i32),
+    "aim_tune_save": ([vp, ctypes.c_char_p], i32),
+    "aim_tune_load": ([vp, ctypes.c_char_p], i32),
+    "aim_graph_capture": ([vp, ctypes.POINTER(Batch), i32, Penalties, i32, ctypes.POINTER(Results), vp,
+                           ctypes.POINTER(vp)], i32),
+    "aim_graph_launch": ([vp, vp], i32),
+    "aim_graph_destroy": ([vp], None),
     "aim_last_error": ([], ctypes.c_char_p),
     "aim_version": ([], ctypes.c_char_p),
 }
@@ -136,18 +146,63 @@ class Context:
     def handle(self):
         return self._h
 
-    def align_batch(self, pat_seq, pat_off, pat_len, txt_seq, txt_off, txt_len, *, enc: int,
-                    max_len: int, alg, pen, max_score: int, score, status, cigar=None,
-                    cigar_off=None, want_cigar: bool = True, stream=None):
-        """aim_align_batch on device tensors; outputs are written in place."""
+    @staticmethod
+    def _args(pat_seq, pat_off, pat_len, txt_seq, txt_off, txt_len, enc, max_len, alg, score,
+              status, cigar, cigar_off, want_cigar):
         n = pat_len.numel()
         b = Batch(n, enc, max_len, _ptr(pat_seq), _ptr(pat_off), _ptr(pat_len),
                   _ptr(txt_seq), _ptr(txt_off), _ptr(txt_len))
         r = Results(_ptr(score), _ptr(status), _ptr(cigar), _ptr(cigar_off),
                     cigar.numel() if cigar is not None else 0, int(bool(want_cigar)))
         a = ALGORITHMS[alg] if isinstance(alg, str) else int(alg)
+        return b, r, a
+
+    def align_batch(self, pat_seq, pat_off, pat_len, txt_seq, txt_off, txt_len, *, enc: int,
+                    max_len: int, alg, pen, max_score: int, score, status, cigar=None,
+                    cigar_off=None, want_cigar: bool = True, stream=None):
+        """aim_align_batch on device tensors; outputs are written in place."""
+        b, r, a = self._args(pat_seq, pat_off, pat_len, txt_seq, txt_off, txt_len, enc, max_len, alg,
+                             score, status, cigar, cigar_off, want_cigar)
         _check(lib().aim_align_batch(self._h, ctypes.byref(b), a, Penalties(*pen), max_score,
                                      ctypes.byref(r), _stream(stream)))
+
+    def autotune(self, pat_seq, pat_off, pat_len, txt_seq, txt_off, txt_len, *, enc, max_len, alg,
+                 pen, max_score, score, status, cigar=None, cigar_off=None, want_cigar=True,
+                 stream=None, reps=2):
+        """aim_autotune; returns (params list of 6, best ms)."""
+        b, r, a = self._args(pat_seq, pat_off, pat_len, txt_seq, txt_off, txt_len, enc, max_len, alg,
+                             score, status, cigar, cigar_off, want_cigar)
+        params = (i32 * 6)()
+        ms = ctypes.c_double()
+        _check(lib().aim_autotune(self._h, ctypes.byref(b), a, Penalties(*pen), max_score,
+                                  ctypes.byref(r), _stream(stream), reps, params, ctypes.byref(ms)))
+        return list(params), ms.value
+
+    def tune_get(self, alg, max_len):
+        params = (i32 * 6)()
+        _check(lib().aim_tune_get(self._h, ALGORITHMS[alg] if isinstance(alg, str) else alg, max_len, params))
+        return list(params)
+
+    def tune_set(self, alg, max_len, params):
+        arr = (i32 * 6)(*params)
+        _check(lib().aim_tune_set(self._h, ALGORITHMS[alg] if isinstance(alg, str) else alg, max_len, arr))
+
+    def tune_save(self, path):
+        _check(lib().aim_tune_save(self._h, path.encode()))
+
+    def tune_load(self, path):
+        _check(lib().aim_tune_load(self._h, path.encode()))
+
+    def graph_capture(self, pat_seq, pat_off, pat_len, txt_seq, txt_off, txt_len, *, enc, max_len,
+                      alg, pen, max_score, score, status, cigar=None, cigar_off=None, want_cigar=True,
+                      stream=None):
+        """aim_graph_capture; returns a Graph."""
+        b, r, a = self._args(pat_seq, pat_off, pat_len, txt_seq, txt_off, txt_len, enc, max_len, alg,
+                             score, status, cigar, cigar_off, want_cigar)
+        h = vp()
+        _check(lib().aim_graph_capture(self._h, ctypes.byref(b), a, Penalties(*pen), max_score,
+                                       ctypes.byref(r), _stream(stream), ctypes.byref(h)))
+        return Graph(h)
 
     def timing(self):
         """{phase: (total_ms, launches)} since the last reset (AIM_FLAG_TIMING)."""
@@ -170,6 +225,27 @@ class Context:
         _check(lib().aim_pack_2bit(self._h, length.numel(), enc, _ptr(seq), _ptr(off), _ptr(length),
                                    _ptr(out_words), out_words.numel(), _ptr(out_off), _ptr(seq_flags),
                                    _stream(stream)))
+
+
+class Graph:
+    """A captured aim_align_batch call (aim_graph)."""
+
+    def __init__(self, h):
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(lib().aim_graph_launch(self._h, _stream(stream)))
+
+    def close(self):
+        if self._h:
+            lib().aim_graph_destroy(self._h)
+            self._h = vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def version() -> str:

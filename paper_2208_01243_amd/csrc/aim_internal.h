@@ -151,7 +151,8 @@ struct WfaPlan {
   int32_t threads[4];
 };
 
-WfaPlan wfa_plan(int32_t max_len, const Scoring &P, int64_t budget_bytes, int32_t cus, bool plain);
+WfaPlan wfa_plan(int32_t max_len, const Scoring &P, int64_t budget_bytes, int32_t cus, bool plain,
+                 int32_t ring_kb, int32_t trace_kb, int32_t long_threads);
 hipError_t launch_wfa_score(const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk,
                             const WfaLaunch &L, int32_t *hbm, bool ring_in_lds, int32_t nslots,
                             int32_t threads, hipStream_t s);
@@ -166,5 +167,12 @@ hipError_t launch_compact(int64_t n, const Outs &O, int64_t *cigar_off, uint32_t
                           int32_t *spill_idx, int32_t *spill_count, int8_t *status,
                           hipStream_t s);
 hipError_t launch_zero_offsets(int64_t n, int64_t *cigar_off, hipStream_t s);
+
+// Length buckets: order[] = pair indices sorted by max(m, n), longest first
+// (128 buckets, 8 per octave; order within a bucket unspecified).  hist needs
+// 128 int32.
+constexpr int LEN_BUCKETS = 128;
+hipError_t launch_length_sort(int64_t n, const int32_t *pl, const int32_t *tl, int32_t *hist,
+                              int32_t *order, hipStream_t s);
 
 }  // namespace aim

@@ -6,7 +6,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <map>
+#include <sstream>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -83,11 +85,34 @@ struct PhaseTimer {
   }
 };
 
+// Launch parameters chosen per (algorithm, length bucket) by aim_autotune.
+struct Tune {
+  int32_t band_w0 = 32;       // first band width (32: 32 then 64; 64: 64 only)
+  int32_t band_wpc = 16;      // resident wavefronts per CU for the first band tier
+  int32_t sort = -1;          // length-sort the pairs first (-1: auto)
+  int32_t wfa_ring_kb = 32;   // LDS per workgroup for the WFA score ring
+  int32_t wfa_trace_kb = 40;  // LDS per workgroup for the WFA full store
+  int32_t wfa_long_threads = 256;  // workgroup size for long WFA pairs
+};
+
+struct aim_graph {
+  aim_context *c = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int64_t generation = 0;
+};
+
 struct aim_context {
   int32_t device = 0;
+  std::string arch;
   aim_options opt{};
   int32_t cus = 256;
   PhaseTimer timer;
+  std::map<std::pair<int32_t, int32_t>, Tune> tunes;  // (alg, length bucket) -> tune
+  const Tune *force = nullptr;  // set while the autotuner tries a candidate
+  bool capturing = false;       // inside a hipGraph capture: no timing events
+  int64_t generation = 0;       // bumped whenever scratch is reallocated
+  Buf order, hist;
   Buf flags, pflag, tflag, pat2, txt2, pat2off, txt2off, nruns, slot, tb32, tb64, full, list2,
       list3, counters, scan_tmp, spill, total, wring, warena1, warena2, warena3, wneed, wlists, pool, pooloff;
 };
@@ -97,6 +122,7 @@ namespace {
 aim_status ensure(aim_context *c, Buf &b, size_t bytes) {
   if (bytes == 0) bytes = 256;
   if (b.bytes >= bytes) return AIM_OK;
+  if (c->capturing) return fail(AIM_ERR_INVALID_ARG, "scratch would grow during graph capture");
   if (b.p) {
     // previously enqueued work may still use the old buffer
     HIP_TRY(hipDeviceSynchronize());
@@ -105,6 +131,7 @@ aim_status ensure(aim_context *c, Buf &b, size_t bytes) {
     b.bytes = 0;
   }
   size_t want = bytes + bytes / 8;
+  c->generation += 1;
   hipError_t e = hipMalloc(&b.p, want);
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -166,7 +193,7 @@ struct Phase {
   const char *name;
   hipEvent_t a = nullptr;
   Phase(aim_context *c_, hipStream_t s_, const char *n) : c(c_), s(s_), name(n) {
-    if (c->opt.flags & AIM_FLAG_TIMING) {
+    if ((c->opt.flags & AIM_FLAG_TIMING) && !c->capturing) {
       a = c->timer.get();
       if (a) (void)hipEventRecord(a, s);
     }
@@ -186,12 +213,26 @@ constexpr int32_t SLOT_CAP = 128;  // at most this many runs per pair held befor
 
 
 
+int32_t len_bucket_host(int32_t L) {
+  int32_t b = 0;
+  while ((1 << b) < L + 1 && b < 30) ++b;
+  return b;
+}
+
+Tune tune_for(aim_context *c, int32_t alg, int32_t L) {
+  if (c->force) return *c->force;
+  auto it = c->tunes.find({alg, len_bucket_host(L)});
+  return it == c->tunes.end() ? Tune{} : it->second;
+}
+
 // WFA: pass 1 (score) with the ring in LDS, then with the ring in HBM for
 // pairs too wide for LDS; pass 2 (full store + backtrace) by store-size class.
 aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const aim::Scoring &P,
-                   int64_t n, int32_t L, bool plain, int32_t *cnt, hipStream_t s) {
+                   int64_t n, int32_t L, bool plain, int32_t *cnt, const int32_t *order,
+                   const Tune &tu, hipStream_t s) {
   aim_status st;
-  const aim::WfaPlan pl = aim::wfa_plan(L, P, c->opt.scratch_limit, c->cus, plain);
+  const aim::WfaPlan pl = aim::wfa_plan(L, P, c->opt.scratch_limit, c->cus, plain, tu.wfa_ring_kb,
+                                        tu.wfa_trace_kb, tu.wfa_long_threads);
   if ((st = ensure(c, c->wneed, (size_t)n * 8))) return st;
   if ((st = ensure(c, c->wlists, (size_t)n * 4 * 6))) return st;
   int32_t *lists = as<int32_t>(c->wlists);
@@ -210,7 +251,7 @@ aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const
   if (!plain && pl.wcap_lds > 0) {
     aim::WfaLaunch A = WL;
     A.wcap = pl.wcap_lds;
-    aim::Work W{nullptr, nullptr, n, cnt + C_W1, nullptr, nullptr, 0};
+    aim::Work W{order, nullptr, n, cnt + C_W1, nullptr, nullptr, 0};
     Phase ph(c, s, "wfa_score");
     HIP_TRY(aim::launch_wfa_score(S, O, P, W, A, nullptr, true, slots, 64, s));
   }
@@ -223,7 +264,7 @@ aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const
     B.ring_list = lists + (int64_t)n * 5;  // never reached: wcap bounds every width
     B.ring_count = cnt + C_FAIL;
     const bool all = plain || pl.wcap_lds == 0;
-    aim::Work W{all ? nullptr : lists, all ? nullptr : cnt + C_RL, n, cnt + C_W1G, nullptr, nullptr, 0};
+    aim::Work W{all ? order : lists, all ? nullptr : cnt + C_RL, n, cnt + C_W1G, nullptr, nullptr, 0};
     Phase ph(c, s, "wfa_score_hbm");
     HIP_TRY(aim::launch_wfa_score(S, O, P, W, B, as<int32_t>(c->wring), false,
                                   all ? std::min<int32_t>(slots, pl.ring_slots) : pl.ring_slots,
@@ -299,8 +340,10 @@ aim_status aim_create(aim_context **ctx, int32_t device, const aim_options *opt)
   c->device = device;
   c->opt = o;
   hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
-    c->cus = prop.multiProcessorCount;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+    if (prop.multiProcessorCount > 0) c->cus = prop.multiProcessorCount;
+    c->arch = prop.gcnArchName;
+  }
   *ctx = c;
   return AIM_OK;
 }
@@ -309,7 +352,7 @@ void aim_destroy(aim_context *c) {
   if (!c) return;
   DeviceGuard g(c->device);
   (void)hipDeviceSynchronize();
-  Buf *all[] = {&c->flags, &c->pflag, &c->tflag, &c->pat2, &c->txt2, &c->pat2off, &c->txt2off,
+  Buf *all[] = {&c->order, &c->hist, &c->flags, &c->pflag, &c->tflag, &c->pat2, &c->txt2, &c->pat2off, &c->txt2off,
                 &c->nruns, &c->slot, &c->tb32, &c->tb64, &c->full, &c->list2, &c->list3,
                 &c->counters, &c->scan_tmp, &c->spill, &c->total, &c->wring, &c->warena1,
                 &c->warena2, &c->warena3, &c->wneed, &c->wlists, &c->pool, &c->pooloff};
@@ -424,6 +467,18 @@ aim_status aim_align_batch(aim_context *c, const aim_batch *B, int32_t alg, aim_
   if ((st = ensure(c, c->pool, (size_t)pool_cap * 4))) return st;
   if ((st = ensure(c, c->pooloff, (size_t)n * 8))) return st;
   HIP_TRY(aim::launch_fill_i32(as<int32_t>(c->total) + 2, 0, 2, s));
+  // a2: length buckets, longest first (LPT order for the persistent queues)
+  const Tune tu = tune_for(c, alg, L);
+  const bool do_sort = tu.sort >= 0 ? tu.sort != 0 : (alg == AIM_WFA_AFFINE || L >= 512);
+  const int32_t *order = nullptr;
+  if (do_sort && c->opt.kernel != AIM_KERNEL_PLAIN) {
+    if ((st = ensure(c, c->order, (size_t)n * 4))) return st;
+    if ((st = ensure(c, c->hist, aim::LEN_BUCKETS * 4))) return st;
+    Phase ph(c, s, "sort");
+    HIP_TRY(aim::launch_length_sort(n, B->pat_len, B->txt_len, as<int32_t>(c->hist),
+                                    as<int32_t>(c->order), s));
+    order = as<int32_t>(c->order);
+  }
   aim::Outs O{R->score, R->status, as<int32_t>(c->nruns), as<uint32_t>(c->slot), slot_cap,
               as<int8_t>(c->flags), R->cigar, R->cigar_off, R->cigar_cap, as<uint32_t>(c->pool),
               pool_cap, (unsigned long long *)(as<int64_t>(c->total) + 1), as<int64_t>(c->pooloff)};
@@ -443,36 +498,44 @@ aim_status aim_align_batch(aim_context *c, const aim_batch *B, int32_t alg, aim_
   };
 
   if (alg == AIM_WFA_AFFINE) {
-    if ((st = run_wfa(c, S, O, P, n, L, plain, cnt, s))) return st;
+    if ((st = run_wfa(c, S, O, P, n, L, plain, cnt, order, tu, s))) return st;
   } else if (plain) {
     aim::Work W1{nullptr, nullptr, n, cnt + C_T1, nullptr, nullptr, 0};
     if ((st = run_full(W1, n))) return st;
   } else {
-    // tier 1: 32-diagonal band, one pair per lane
+    // tier 1: 32-diagonal band, one pair per lane (64 when tuned so)
     const int32_t rows_cap = L + 1;
     const int64_t chunks = (n + 63) / 64;
-    const int64_t sw32 = aim::band_tb_slot_words(32, affine, rows_cap);
-    int64_t slots = std::min<int64_t>(chunks, (int64_t)c->cus * 16);
-    slots = std::max<int64_t>(1, std::min<int64_t>(slots, budget / (sw32 * 4)));
-    if ((st = ensure(c, c->tb32, (size_t)(slots * sw32 * 4)))) return st;
-    aim::Work W1{nullptr, nullptr, n, cnt + C_T1, as<int32_t>(c->list2), cnt + C_L2, 0};
+    const int32_t w0 = tu.band_w0 == 64 ? 64 : 32;
+    Buf &tbA = w0 == 32 ? c->tb32 : c->tb64;
+    const int64_t swA = aim::band_tb_slot_words(w0, affine, rows_cap);
+    int64_t slots = std::min<int64_t>(chunks, (int64_t)c->cus * std::max(1, tu.band_wpc));
+    slots = std::max<int64_t>(1, std::min<int64_t>(slots, budget / (swA * 4)));
+    if ((st = ensure(c, tbA, (size_t)(slots * swA * 4)))) return st;
+    aim::Work W1{order, nullptr, n, cnt + C_T1, as<int32_t>(c->list2), cnt + C_L2, 0};
     {
-    Phase ph(c, s, "band32");
-    HIP_TRY(aim::launch_band(32, affine, S, O, P, W1, as<uint32_t>(c->tb32), sw32, rows_cap,
-                             (int32_t)slots, s));
+      Phase ph(c, s, w0 == 32 ? "band32" : "band64");
+      HIP_TRY(aim::launch_band(w0, affine, S, O, P, W1, as<uint32_t>(tbA), swA, rows_cap,
+                               (int32_t)slots, s));
     }
-    // tier 2: 64-diagonal band for the pairs tier 1 could not decide
-    const int64_t sw64 = aim::band_tb_slot_words(64, affine, rows_cap);
-    int64_t slots2 = std::min<int64_t>(chunks, (int64_t)c->cus * 4);
-    slots2 = std::max<int64_t>(1, std::min<int64_t>(slots2, budget / (sw64 * 4)));
-    if ((st = ensure(c, c->tb64, (size_t)(slots2 * sw64 * 4)))) return st;
-    Phase ph2(c, s, "band64");
-    aim::Work W2{as<int32_t>(c->list2), cnt + C_L2, n, cnt + C_T2, as<int32_t>(c->list3),
-                 cnt + C_L3, 0};
-    HIP_TRY(aim::launch_band(64, affine, S, O, P, W2, as<uint32_t>(c->tb64), sw64, rows_cap,
-                             (int32_t)slots2, s));
+    int32_t *full_list = as<int32_t>(c->list2);
+    int32_t *full_count = cnt + C_L2;
+    if (w0 == 32) {
+      // tier 2: 64-diagonal band for the pairs tier 1 could not decide
+      const int64_t sw64 = aim::band_tb_slot_words(64, affine, rows_cap);
+      int64_t slots2 = std::min<int64_t>(chunks, (int64_t)c->cus * 4);
+      slots2 = std::max<int64_t>(1, std::min<int64_t>(slots2, budget / (sw64 * 4)));
+      if ((st = ensure(c, c->tb64, (size_t)(slots2 * sw64 * 4)))) return st;
+      Phase ph2(c, s, "band64");
+      aim::Work W2{as<int32_t>(c->list2), cnt + C_L2, n, cnt + C_T2, as<int32_t>(c->list3),
+                   cnt + C_L3, 0};
+      HIP_TRY(aim::launch_band(64, affine, S, O, P, W2, as<uint32_t>(c->tb64), sw64, rows_cap,
+                               (int32_t)slots2, s));
+      full_list = as<int32_t>(c->list3);
+      full_count = cnt + C_L3;
+    }
     // tier 3: full matrix
-    aim::Work W3{as<int32_t>(c->list3), cnt + C_L3, n, cnt + C_T3, nullptr, nullptr, 0};
+    aim::Work W3{full_list, full_count, n, cnt + C_T3, nullptr, nullptr, 0};
     if ((st = run_full(W3, n))) return st;
   }
 
@@ -489,7 +552,8 @@ aim_status aim_align_batch(aim_context *c, const aim_batch *B, int32_t alg, aim_
   // pairs whose runs exceeded the slot: recompute and write in place
   aim::Work WS{as<int32_t>(c->spill), cnt + C_SPILL, n, cnt + C_SPILL_W, nullptr, nullptr, 1};
   if (alg == AIM_WFA_AFFINE) {
-    aim::WfaPlan pl = aim::wfa_plan(L, P, c->opt.scratch_limit, c->cus, plain);
+    aim::WfaPlan pl = aim::wfa_plan(L, P, c->opt.scratch_limit, c->cus, plain, tu.wfa_ring_kb,
+                                    tu.wfa_trace_kb, tu.wfa_long_threads);
     aim::WfaLaunch WL{};
     WL.R = pl.R;
     WL.seq_words = pl.seq_words;
@@ -504,6 +568,218 @@ aim_status aim_align_batch(aim_context *c, const aim_batch *B, int32_t alg, aim_
     if ((st = run_full(WS, n))) return st;
   }
   return AIM_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- autotuner
+namespace {
+const int32_t TUNE_FIELDS = 6;
+void tune_to(const Tune &t, int32_t *v) {
+  v[0] = t.band_w0; v[1] = t.band_wpc; v[2] = t.sort;
+  v[3] = t.wfa_ring_kb; v[4] = t.wfa_trace_kb; v[5] = t.wfa_long_threads;
+}
+Tune tune_from(const int32_t *v) {
+  Tune t;
+  t.band_w0 = v[0]; t.band_wpc = v[1]; t.sort = v[2];
+  t.wfa_ring_kb = v[3]; t.wfa_trace_kb = v[4]; t.wfa_long_threads = v[5];
+  return t;
+}
+bool tune_valid(const Tune &t) {
+  return (t.band_w0 == 32 || t.band_w0 == 64) && t.band_wpc >= 1 && t.band_wpc <= 64 &&
+         t.sort >= -1 && t.sort <= 1 && t.wfa_ring_kb >= 8 && t.wfa_ring_kb <= 60 &&
+         t.wfa_trace_kb >= 8 && t.wfa_trace_kb <= 60 &&
+         (t.wfa_long_threads == 64 || t.wfa_long_threads == 128 || t.wfa_long_threads == 256);
+}
+std::string tune_key() {
+  int v = 0;
+  (void)hipRuntimeGetVersion(&v);
+  return std::to_string(v);
+}
+}  // namespace
+
+extern "C" {
+
+aim_status aim_autotune(aim_context *c, const aim_batch *B, int32_t alg, aim_penalties pen,
+                        int32_t max_score, aim_results *R, void *stream, int32_t reps,
+                        int32_t *best_params, double *best_ms) {
+  g_err.clear();
+  if (!c || !B || !R) return fail(AIM_ERR_INVALID_ARG, "NULL context, batch or results");
+  if (reps < 1 || reps > 100) return fail(AIM_ERR_INVALID_ARG, "reps must be in [1, 100]");
+  std::vector<Tune> cand;
+  if (alg == AIM_WFA_AFFINE) {
+    for (int ring : {16, 32, 48})
+      for (int trace : {24, 40})
+        for (int th : {128, 256}) {
+          Tune t;
+          t.sort = 1;
+          t.wfa_ring_kb = ring;
+          t.wfa_trace_kb = trace;
+          t.wfa_long_threads = th;
+          cand.push_back(t);
+        }
+  } else {
+    for (int w0 : {32, 64})
+      for (int wpc : {8, 16, 32})
+        for (int so : {0, 1}) {
+          Tune t;
+          t.band_w0 = w0;
+          t.band_wpc = wpc;
+          t.sort = so;
+          cand.push_back(t);
+        }
+  }
+  DeviceGuard g(c->device);
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  double best = 1e300;
+  size_t bi = 0;
+  aim_status st = AIM_OK;
+  for (size_t k = 0; k < cand.size() && st == AIM_OK; ++k) {
+    c->force = &cand[k];
+    st = aim_align_batch(c, B, alg, pen, max_score, R, stream);  // warm-up, sizes scratch
+    std::vector<double> ms;
+    for (int r = 0; r < reps && st == AIM_OK; ++r) {
+      (void)hipEventRecord(e0, s);
+      st = aim_align_batch(c, B, alg, pen, max_score, R, stream);
+      (void)hipEventRecord(e1, s);
+      float t = 0.f;
+      if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
+        st = fail(AIM_ERR_HIP, "timing the candidate failed");
+        break;
+      }
+      ms.push_back(t);
+    }
+    if (st == AIM_OK) {
+      std::sort(ms.begin(), ms.end());
+      const double med = ms[ms.size() / 2];
+      if (med < best) { best = med; bi = k; }
+    }
+  }
+  c->force = nullptr;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != AIM_OK) return st;
+  c->tunes[{alg, len_bucket_host(B->max_len)}] = cand[bi];
+  if (best_params) tune_to(cand[bi], best_params);
+  if (best_ms) *best_ms = best;
+  // leave the outputs of the chosen configuration in `out`
+  return aim_align_batch(c, B, alg, pen, max_score, R, stream);
+}
+
+aim_status aim_tune_get(aim_context *c, int32_t alg, int32_t max_len, int32_t *params) {
+  g_err.clear();
+  if (!c || !params) return fail(AIM_ERR_INVALID_ARG, "NULL argument");
+  tune_to(tune_for(c, alg, max_len), params);
+  return AIM_OK;
+}
+
+aim_status aim_tune_set(aim_context *c, int32_t alg, int32_t max_len, const int32_t *params) {
+  g_err.clear();
+  if (!c || !params) return fail(AIM_ERR_INVALID_ARG, "NULL argument");
+  Tune t = tune_from(params);
+  if (!tune_valid(t)) return fail(AIM_ERR_INVALID_ARG, "tune parameters out of range");
+  c->tunes[{alg, len_bucket_host(max_len)}] = t;
+  return AIM_OK;
+}
+
+aim_status aim_tune_save(aim_context *c, const char *path) {
+  g_err.clear();
+  if (!c || !path) return fail(AIM_ERR_INVALID_ARG, "NULL argument");
+  std::ofstream f(path);
+  if (!f) return fail(AIM_ERR_INVALID_ARG, "cannot write %s", path);
+  f << "aim-tune 1 " << c->arch << " " << tune_key() << "\n";
+  for (auto &kv : c->tunes) {
+    int32_t v[TUNE_FIELDS];
+    tune_to(kv.second, v);
+    f << kv.first.first << " " << kv.first.second;
+    for (int k = 0; k < TUNE_FIELDS; ++k) f << " " << v[k];
+    f << "\n";
+  }
+  return f ? AIM_OK : fail(AIM_ERR_INVALID_ARG, "write failed: %s", path);
+}
+
+aim_status aim_tune_load(aim_context *c, const char *path) {
+  g_err.clear();
+  if (!c || !path) return fail(AIM_ERR_INVALID_ARG, "NULL argument");
+  std::ifstream f(path);
+  if (!f) return fail(AIM_ERR_NOT_FOUND, "cannot read %s", path);
+  std::string magic, ver, arch, key;
+  f >> magic >> ver >> arch >> key;
+  if (magic != "aim-tune" || ver != "1") return fail(AIM_ERR_INVALID_ARG, "not a tune file: %s", path);
+  if (arch != c->arch || key != tune_key())
+    return fail(AIM_ERR_NOT_FOUND, "tune file is for %s / runtime %s", arch.c_str(), key.c_str());
+  std::map<std::pair<int32_t, int32_t>, Tune> loaded;
+  int32_t alg, bucket, v[TUNE_FIELDS];
+  while (f >> alg >> bucket) {
+    for (int k = 0; k < TUNE_FIELDS; ++k) f >> v[k];
+    if (!f) return fail(AIM_ERR_INVALID_ARG, "truncated tune file");
+    Tune t = tune_from(v);
+    if (!tune_valid(t)) return fail(AIM_ERR_INVALID_ARG, "bad tune entry in %s", path);
+    loaded[{alg, bucket}] = t;
+  }
+  for (auto &kv : loaded) c->tunes[kv.first] = kv.second;
+  return AIM_OK;
+}
+
+// ---------------------------------------------------------------- graphs
+aim_status aim_graph_capture(aim_context *c, const aim_batch *B, int32_t alg, aim_penalties pen,
+                             int32_t max_score, aim_results *R, void *stream, aim_graph **out) {
+  g_err.clear();
+  if (!c || !out) return fail(AIM_ERR_INVALID_ARG, "NULL context or graph handle");
+  if (!stream) return fail(AIM_ERR_INVALID_ARG, "graph capture needs a non-null stream");
+  *out = nullptr;
+  DeviceGuard g(c->device);
+  hipStream_t s = (hipStream_t)stream;
+  aim_status st = aim_align_batch(c, B, alg, pen, max_score, R, stream);  // sizes scratch
+  if (st) return st;
+  HIP_TRY(hipStreamSynchronize(s));
+  const int64_t gen = c->generation;
+  HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  c->capturing = true;
+  st = aim_align_batch(c, B, alg, pen, max_score, R, stream);
+  c->capturing = false;
+  hipGraph_t graph = nullptr;
+  hipError_t ee = hipStreamEndCapture(s, &graph);
+  if (st != AIM_OK || ee != hipSuccess || c->generation != gen) {
+    if (graph) (void)hipGraphDestroy(graph);
+    if (st != AIM_OK) return st;
+    if (ee != hipSuccess) return fail(AIM_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(ee));
+    return fail(AIM_ERR_HIP, "scratch changed during capture");
+  }
+  hipGraphExec_t exec = nullptr;
+  hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (ei != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return fail(AIM_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(ei));
+  }
+  auto *gr = new aim_graph();
+  gr->c = c;
+  gr->graph = graph;
+  gr->exec = exec;
+  gr->generation = gen;
+  *out = gr;
+  return AIM_OK;
+}
+
+aim_status aim_graph_launch(aim_graph *gr, void *stream) {
+  g_err.clear();
+  if (!gr) return fail(AIM_ERR_INVALID_ARG, "NULL graph");
+  if (gr->c->generation != gr->generation)
+    return fail(AIM_ERR_INVALID_ARG, "the context's scratch was reallocated since capture; capture again");
+  DeviceGuard g(gr->c->device);
+  HIP_TRY(hipGraphLaunch(gr->exec, (hipStream_t)stream));
+  return AIM_OK;
+}
+
+void aim_graph_destroy(aim_graph *gr) {
+  if (!gr) return;
+  DeviceGuard g(gr->c->device);
+  if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
+  if (gr->graph) (void)hipGraphDestroy(gr->graph);
+  delete gr;
 }
 
 }  // extern "C"

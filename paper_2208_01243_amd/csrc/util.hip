@@ -204,6 +204,51 @@ __global__ void k_zero_offsets(int64_t n, int64_t *off) {
 
 __global__ void k_zero_u64(unsigned long long *p) { *p = 0ull; }
 
+// ---- length buckets: counting sort of pairs, longest first ----
+constexpr int NBUCKET = 128;
+
+__device__ __forceinline__ int len_bucket(int32_t m, int32_t n) {
+  // 8 buckets per octave of max(m, n); reversed so that long pairs come first
+  const uint32_t L = (uint32_t)max(max(m, n), 0) + 1u;
+  const int lg = 31 - __clz(L);
+  const int frac = lg >= 3 ? (int)((L >> (lg - 3)) & 7u) : (int)((L << (3 - lg)) & 7u);
+  const int b = min(lg * 8 + frac, NBUCKET - 1);
+  return NBUCKET - 1 - b;
+}
+
+__global__ void k_bucket_hist(int64_t n, const int32_t *pl, const int32_t *tl, int32_t *hist) {
+  __shared__ int32_t h[NBUCKET];
+  for (int k = threadIdx.x; k < NBUCKET; k += blockDim.x) h[k] = 0;
+  __syncthreads();
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    atomicAdd(&h[len_bucket(pl[i], tl[i])], 1);
+  __syncthreads();
+  for (int k = threadIdx.x; k < NBUCKET; k += blockDim.x)
+    if (h[k]) atomicAdd(&hist[k], h[k]);
+}
+
+// hist -> exclusive offsets in place (one block)
+__global__ void k_bucket_scan(int32_t *hist) {
+  if (threadIdx.x == 0) {
+    int32_t acc = 0;
+    for (int k = 0; k < NBUCKET; ++k) {
+      const int32_t v = hist[k];
+      hist[k] = acc;
+      acc += v;
+    }
+  }
+}
+
+__global__ void k_bucket_scatter(int64_t n, const int32_t *pl, const int32_t *tl, int32_t *cursor,
+                                 int32_t *order) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int b = len_bucket(pl[i], tl[i]);
+    order[atomicAdd(&cursor[b], 1)] = (int32_t)i;
+  }
+}
+
 inline dim3 grid_for(int64_t n, int block) {
   int64_t g = (n + block - 1) / block;
   if (g < 1) g = 1;
@@ -277,6 +322,16 @@ hipError_t launch_compact(int64_t n, const Outs &O, int64_t *cigar_off, uint32_t
   } else {
     hipLaunchKernelGGL(k_zero_offsets, dim3(1), dim3(64), 0, s, (int64_t)0, cigar_off);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_length_sort(int64_t n, const int32_t *pl, const int32_t *tl, int32_t *hist,
+                              int32_t *order, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(NBUCKET), 0, s, hist, 0, (int64_t)NBUCKET);
+  hipLaunchKernelGGL(k_bucket_hist, grid_for(n, 256), dim3(256), 0, s, n, pl, tl, hist);
+  hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(64), 0, s, hist);
+  hipLaunchKernelGGL(k_bucket_scatter, grid_for(n, 256), dim3(256), 0, s, n, pl, tl, hist, order);
   return hipGetLastError();
 }
 

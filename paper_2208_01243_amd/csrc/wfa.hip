@@ -397,7 +397,8 @@ __global__ __launch_bounds__(WGMAX) void k_wfa_trace(Seqs S, Outs O, Scoring P, 
 
 }  // namespace
 
-WfaPlan wfa_plan(int32_t max_len, const Scoring &P, int64_t budget_bytes, int32_t cus, bool plain) {
+WfaPlan wfa_plan(int32_t max_len, const Scoring &P, int64_t budget_bytes, int32_t cus, bool plain,
+                 int32_t ring_kb, int32_t trace_kb, int32_t long_threads) {
   // budget split: HBM rings 1/8, arena classes 1/8, 1/8 and 1/4
   WfaPlan pl{};
   const int32_t oe = P.o + P.e;
@@ -408,7 +409,7 @@ WfaPlan wfa_plan(int32_t max_len, const Scoring &P, int64_t budget_bytes, int32_
   pl.wcap = (int32_t)std::max<int64_t>(w, 1);
   const int64_t seqw = ((int64_t)max_len + 31) / 32;
   pl.seq_words = seqw <= 320 ? (int32_t)seqw : 0;
-  const int64_t lds_score = 32 * 1024, lds_trace = 40 * 1024;
+  const int64_t lds_score = (int64_t)ring_kb * 1024, lds_trace = (int64_t)trace_kb * 1024;
   const int64_t fixed = 2 * (int64_t)pl.seq_words * 8 + (int64_t)pl.R * ENTRY * 4;
   const int64_t wl = (lds_score - fixed) / ((int64_t)pl.R * 12);
   pl.wcap_lds = plain ? 0 : (int32_t)std::max<int64_t>(0, std::min<int64_t>(wl, pl.wcap));
@@ -416,7 +417,7 @@ WfaPlan wfa_plan(int32_t max_len, const Scoring &P, int64_t budget_bytes, int32_
   pl.ring_slot_words = (int64_t)pl.R * 3 * pl.wcap;
   pl.ring_slots = (int32_t)std::max<int64_t>(
       1, std::min<int64_t>((int64_t)cus * 4, budget_bytes / 8 / (pl.ring_slot_words * 4)));
-  pl.ring_threads = max_len > 1024 ? 256 : 64;
+  pl.ring_threads = max_len > 1024 ? long_threads : 64;
   // full-store arena classes (words): LDS, then HBM slots of 1 MB, 16 MB and
   // 192 MB, with fewer and wider workgroups for the larger classes
   pl.lds_arena_words = plain ? 0 : (int32_t)((lds_trace - 2 * (int64_t)pl.seq_words * 8) / 4);
@@ -431,8 +432,8 @@ WfaPlan wfa_plan(int32_t max_len, const Scoring &P, int64_t budget_bytes, int32_
   for (int k = 1; k < 4; ++k)
     pl.arena_slots[k] = (int32_t)std::max<int64_t>(1, std::min<int64_t>(cap_slots[k], share[k] / (pl.need_cap[k] * 4)));
   pl.threads[1] = 64;
-  pl.threads[2] = 256;
-  pl.threads[3] = 256;
+  pl.threads[2] = long_threads;
+  pl.threads[3] = long_threads;
   return pl;
 }
 

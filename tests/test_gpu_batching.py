@@ -1,0 +1,148 @@
+"""Batching form: length-sorted queues, autotuned launch parameters and
+captured HIP graphs, each bit-exact against the oracle."""
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+import synth  # noqa: E402
+import paper_2208_01243_amd as aim  # noqa: E402
+from gpu_util import compare, describe, run, to_device  # noqa: E402
+
+
+def _outputs(b):
+    n = b.n
+    score = torch.empty(n, dtype=torch.int32, device="cuda")
+    status = torch.empty(n, dtype=torch.int8, device="cuda")
+    cap = int((b.pat_len.astype(np.int64) + b.txt_len + 1).sum()) + 1
+    cigar = torch.empty(cap, dtype=torch.int32, device="cuda")
+    off = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+    return score, status, cigar, off
+
+
+def _host(outs):
+    s, st, cg, off = outs
+    torch.cuda.synchronize()
+    return s.cpu().numpy(), st.cpu().numpy(), cg.cpu().numpy().view(np.uint32), off.cpu().numpy()
+
+
+def _same_shape_batch(b, seed):
+    """A batch with the same lengths as b but different bases."""
+    rng = np.random.default_rng(seed)
+    pat = b.pat.copy()
+    txt = b.txt.copy()
+    flip = rng.random(len(txt)) < 0.03
+    txt[flip] = (txt[flip] + 1) % 4
+    flip = rng.random(len(pat)) < 0.03
+    pat[flip] = (pat[flip] + 2) % 4
+    return synth.PairBatch(pat, b.pat_off.copy(), txt, b.txt_off.copy())
+
+
+@pytest.mark.parametrize("name", ["nw100", "swg150"])
+def test_graph_replays(name):
+    w = synth.WORKLOADS[name]
+    b = synth.workload(name, n=4000)
+    dev, enc = to_device(b, w["enc"])
+    outs = _outputs(b)
+    max_len = int(max(b.pat_len.max(), b.txt_len.max()))
+    stream = torch.cuda.Stream()
+    with aim.Context(0) as ctx, torch.cuda.stream(stream):
+        g = ctx.graph_capture(*dev, enc=enc, max_len=max_len, alg=w["alg"], pen=w["pen"],
+                              max_score=w["max_score"], score=outs[0], status=outs[1], cigar=outs[2],
+                              cigar_off=outs[3], stream=stream)
+        want = oracle.align_batch(b, w["alg"], w["pen"], w["max_score"])
+        for rep in range(3):
+            for t in outs:
+                t.zero_()  # eager work between replays
+            stream.synchronize()
+            g.launch(stream)
+            got = _host(outs)
+            bad = compare(got, want)
+            assert not bad, (rep, describe(b, bad[0], got, want))
+        # new contents in the captured input buffers: the replay aligns them
+        b2 = _same_shape_batch(b, 3)
+        dev2, _ = to_device(b2, w["enc"])
+        for dst, src in zip(dev, dev2):
+            dst.copy_(src)
+        stream.synchronize()
+        g.launch(stream)
+        got = _host(outs)
+        want2 = oracle.align_batch(b2, w["alg"], w["pen"], w["max_score"])
+        bad = compare(got, want2)
+        assert not bad, describe(b2, bad[0], got, want2)
+        g.close()
+
+
+@pytest.mark.parametrize("name,n", [("swg150", 20000), ("wfa250", 5000)])
+def test_autotune_is_exact_and_cached(name, n, tmp_path):
+    w = synth.WORKLOADS[name]
+    b = synth.workload(name, n=n)
+    dev, enc = to_device(b, w["enc"])
+    outs = _outputs(b)
+    max_len = int(max(b.pat_len.max(), b.txt_len.max()))
+    with aim.Context(0) as ctx:
+        params, ms = ctx.autotune(*dev, enc=enc, max_len=max_len, alg=w["alg"], pen=w["pen"],
+                                  max_score=w["max_score"], score=outs[0], status=outs[1],
+                                  cigar=outs[2], cigar_off=outs[3], reps=1)
+        assert ms > 0 and ctx.tune_get(w["alg"], max_len) == params
+        want = oracle.align_batch(b, w["alg"], w["pen"], w["max_score"])
+        bad = compare(_host(outs), want)
+        assert not bad
+        path = str(tmp_path / "tune.txt")
+        ctx.tune_save(path)
+    with aim.Context(0) as ctx2:
+        ctx2.tune_load(path)
+        assert ctx2.tune_get(w["alg"], max_len) == params
+        got = run(ctx2, b, w["alg"], w["pen"], w["max_score"], enc=w["enc"])
+        assert not compare(got, want)
+
+
+def _mixed(seed, count, lmin, lmax, rates):
+    rng = np.random.default_rng(seed)
+    pats, txts = [], []
+    for _ in range(count):
+        L = int(np.exp(rng.uniform(np.log(lmin), np.log(lmax))))
+        T = rng.integers(0, 4, L).astype(np.uint8)
+        bb = synth.from_lists([T], [T])
+        P, _ = synth.mutate(rng, bb.txt, bb.txt_off, [float(rng.choice(rates))])
+        pats.append(P)
+        txts.append(T)
+    return synth.from_lists(pats, txts)
+
+
+@pytest.mark.parametrize("alg,pen", [("swg", (0, 4, 6, 2)), ("nw", (0, 1, 0, 1)), ("wfa", (0, 4, 6, 2))])
+@pytest.mark.parametrize("sort", [0, 1])
+def test_length_sort_exact(alg, pen, sort):
+    b = _mixed(50, 1500, 20, 1200, [0.005, 0.02, 0.06])
+    with aim.Context(0) as ctx:
+        L = int(max(b.pat_len.max(), b.txt_len.max()))
+        p = ctx.tune_get(alg, L)
+        p[2] = sort
+        ctx.tune_set(alg, L, p)
+        got = run(ctx, b, alg, pen)
+    want = oracle.align_batch(b, alg, pen)
+    bad = compare(got, want)
+    assert not bad, describe(b, bad[0], got, want)
+
+
+def test_wfa_mixed_sample():
+    # the batching-form workload (100 bp - 10 kbp, 0.5-10 %): first 3000 pairs,
+    # checked pair by pair (pairs above 2.5 kbp against the scalar WFA)
+    w = synth.WORKLOADS["wfa_mixed"]
+    b = synth.workload("wfa_mixed", n=3000)
+    with aim.Context(0) as ctx:
+        s, st, cg, off = run(ctx, b, "wfa", w["pen"], w["max_score"])
+    short = np.nonzero(np.maximum(b.pat_len, b.txt_len) <= 2500)[0]
+    sub = b.subset(short)
+    ws, wst, wc, wo = oracle.align_batch(sub, "wfa", w["pen"], -1)
+    for t, i in enumerate(short):
+        assert (s[i], st[i]) == (ws[t], wst[t]) and np.array_equal(cg[off[i]:off[i + 1]], wc[wo[t]:wo[t + 1]]), i
+    longi = np.nonzero(np.maximum(b.pat_len, b.txt_len) > 2500)[0]
+    rng = np.random.default_rng(1)
+    for i in rng.choice(longi, size=min(40, len(longi)), replace=False):
+        r = oracle.wfa_pair(b.pattern(i), b.text(i), w["pen"])
+        assert (st[i], s[i]) == (r[0], r[1]) and cg[off[i]:off[i + 1]].tolist() == r[2], i
