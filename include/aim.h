@@ -135,7 +135,7 @@ typedef enum { AIM_KERNEL_AUTO = 0, AIM_KERNEL_PLAIN = 1 } aim_kernel;
 typedef struct {
   int32_t kernel;        /* aim_kernel */
   int32_t flags;         /* AIM_FLAG_* */
-  int64_t scratch_limit; /* soft cap on library scratch in bytes (0: 8 GiB) */
+  int64_t scratch_limit; /* soft cap on library scratch in bytes (0: 64 GiB) */
 } aim_options;
 
 typedef struct aim_context aim_context;
@@ -226,6 +226,76 @@ aim_status aim_graph_capture(aim_context *ctx, const aim_batch *pairs, int32_t a
                              aim_graph **graph);
 aim_status aim_graph_launch(aim_graph *graph, void *stream);
 void aim_graph_destroy(aim_graph *graph);
+
+/* ---- serving form ---------------------------------------------------------
+ * A request server: alignment requests of any size arrive on host threads,
+ * wait in a FIFO until their device-memory footprint fits the budget (never
+ * dropped, never bypassed), and are merged -- across requests, per
+ * (algorithm, penalties, threshold, CIGAR wanted) -- into device batches by
+ * n_streams workers, each with its own context, stream and buffers, so
+ * batches overlap on the GPU and requests that arrive while others run join
+ * the next batch.  Paper: Overall Workflow (the host gathers pairs,
+ * dispatches them, retrieves score and operations), run continuously. */
+typedef struct aim_server aim_server;
+
+typedef struct {
+  int32_t n_streams;       /* concurrent device batches, 1..16 (0: 4) */
+  int32_t flags;           /* reserved, 0 */
+  int64_t budget_bytes;    /* device bytes for admitted requests (0: 64 GiB) */
+  int64_t max_batch_pairs; /* pairs merged into one device batch (0: 1M) */
+} aim_server_options;
+
+/* One request: host arrays (copied at submit; the caller may reuse them
+ * after aim_server_submit returns).  Offsets are in bytes. */
+typedef struct {
+  int32_t alg;
+  aim_penalties pen;
+  int32_t max_score;
+  int32_t want_cigar;
+  int32_t enc; /* AIM_ENC_ASCII or AIM_ENC_CODE */
+  int64_t n_pairs;
+  const uint8_t *pat;
+  const int64_t *pat_off;
+  const int32_t *pat_len;
+  const uint8_t *txt;
+  const int64_t *txt_off;
+  const int32_t *txt_len;
+} aim_request;
+
+/* Results of a finished request: host arrays owned by the server until
+ * aim_server_release; same meaning as aim_results (cigar_off starts at 0). */
+typedef struct {
+  int64_t n_pairs;
+  const int32_t *score;
+  const int8_t *status;
+  const uint32_t *cigar;
+  const int64_t *cigar_off;
+  double latency_us; /* completion minus submission */
+} aim_request_result;
+
+typedef struct {
+  int64_t submitted, completed, pairs_completed, batches, queued;
+  double p50_us, p99_us, mean_us, max_us; /* latency of completed requests */
+  int64_t bytes_in_use, peak_bytes, budget_bytes;
+  double elapsed_s; /* since the first submission after the last reset */
+} aim_server_stats;
+
+/* Errors of the aim_server_* calls are described by aim_server_last_error. */
+aim_status aim_server_create(int32_t device, const aim_server_options *opt, aim_server **srv);
+/* Queues a request; returns at once with its id.  AIM_ERR_INVALID_ARG for a
+ * request whose footprint exceeds the whole budget. */
+aim_status aim_server_submit(aim_server *srv, const aim_request *req, int64_t *id);
+/* AIM_ERR_BUSY while the request runs; AIM_ERR_NOT_FOUND for unknown ids. */
+aim_status aim_server_poll(aim_server *srv, int64_t id, aim_request_result *res);
+/* Blocks until done (timeout_ms < 0: no timeout; AIM_ERR_BUSY on timeout). */
+aim_status aim_server_wait(aim_server *srv, int64_t id, int32_t timeout_ms, aim_request_result *res);
+/* Frees a finished request's results. */
+aim_status aim_server_release(aim_server *srv, int64_t id);
+aim_status aim_server_stats_get(aim_server *srv, aim_server_stats *st);
+aim_status aim_server_reset_stats(aim_server *srv);
+const char *aim_server_last_error(void);
+/* Finishes every queued request, then stops the workers and frees all. */
+void aim_server_destroy(aim_server *srv);
 
 /* Description of the last error on this host thread ("" if none).  Valid
  * until the next library call on the same thread. */

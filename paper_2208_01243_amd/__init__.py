@@ -47,6 +47,28 @@ class Options(ctypes.Structure):
     _fields_ = [("kernel", i32), ("flags", i32), ("scratch_limit", i64)]
 
 
+class ServerOptions(ctypes.Structure):
+    _fields_ = [("n_streams", i32), ("flags", i32), ("budget_bytes", i64), ("max_batch_pairs", i64)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("alg", i32), ("pen", Penalties), ("max_score", i32), ("want_cigar", i32), ("enc", i32),
+                ("n_pairs", i64), ("pat", vp), ("pat_off", vp), ("pat_len", vp),
+                ("txt", vp), ("txt_off", vp), ("txt_len", vp)]
+
+
+class RequestResult(ctypes.Structure):
+    _fields_ = [("n_pairs", i64), ("score", vp), ("status", vp), ("cigar", vp), ("cigar_off", vp),
+                ("latency_us", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", i64), ("completed", i64), ("pairs_completed", i64), ("batches", i64),
+                ("queued", i64), ("p50_us", ctypes.c_double), ("p99_us", ctypes.c_double),
+                ("mean_us", ctypes.c_double), ("max_us", ctypes.c_double), ("bytes_in_use", i64),
+                ("peak_bytes", i64), ("budget_bytes", i64), ("elapsed_s", ctypes.c_double)]
+
+
 class AimError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__("%s (%d): %s" % (ERRORS.get(code, "AIM_ERR"), code, msg))
@@ -72,6 +94,15 @@ SIGNATURES = {
                            ctypes.POINTER(vp)], i32),
     "aim_graph_launch": ([vp, vp], i32),
     "aim_graph_destroy": ([vp], None),
+    "aim_server_create": ([i32, ctypes.POINTER(ServerOptions), ctypes.POINTER(vp)], i32),
+    "aim_server_submit": ([vp, ctypes.POINTER(Request), ctypes.POINTER(i64)], i32),
+    "aim_server_poll": ([vp, i64, ctypes.POINTER(RequestResult)], i32),
+    "aim_server_wait": ([vp, i64, i32, ctypes.POINTER(RequestResult)], i32),
+    "aim_server_release": ([vp, i64], i32),
+    "aim_server_stats_get": ([vp, ctypes.POINTER(ServerStats)], i32),
+    "aim_server_reset_stats": ([vp], i32),
+    "aim_server_last_error": ([], ctypes.c_char_p),
+    "aim_server_destroy": ([vp], None),
     "aim_last_error": ([], ctypes.c_char_p),
     "aim_version": ([], ctypes.c_char_p),
 }
@@ -246,6 +277,89 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+def _scheck(code):
+    if code != 0:
+        raise AimError(code, lib().aim_server_last_error().decode())
+
+
+class Server:
+    """aim_server: continuous batching of alignment requests (host arrays in,
+    host arrays out)."""
+
+    def __init__(self, device: int = 0, n_streams: int = 4, budget_bytes: int = 0,
+                 max_batch_pairs: int = 0):
+        h = vp()
+        _scheck(lib().aim_server_create(device, ctypes.byref(ServerOptions(n_streams, 0, budget_bytes,
+                                                                          max_batch_pairs)),
+                                        ctypes.byref(h)))
+        self._h = h
+
+    def submit(self, alg, pen, max_score, pat, pat_off, pat_len, txt, txt_off, txt_len, *,
+               enc=ENC_CODE, want_cigar=True) -> int:
+        """Numpy arrays (uint8 bytes, int64 byte offsets, int32 lengths); copied at submit."""
+        import numpy as np
+        arrs = [np.ascontiguousarray(a) for a in (pat, pat_off, pat_len, txt, txt_off, txt_len)]
+        ptr = lambda a: vp(a.ctypes.data) if a.size else None  # noqa: E731
+        q = Request(ALGORITHMS[alg] if isinstance(alg, str) else alg, Penalties(*pen), max_score,
+                    int(bool(want_cigar)), enc, len(arrs[2]), *[ptr(a) for a in arrs])
+        rid = i64()
+        _scheck(lib().aim_server_submit(self._h, ctypes.byref(q), ctypes.byref(rid)))
+        return rid.value
+
+    @staticmethod
+    def _copy(res):
+        import numpy as np
+        n = res.n_pairs
+
+        def arr(p, ct, cnt):
+            if cnt == 0 or not p:
+                return np.zeros(cnt, dtype=np.ctypeslib.as_array((ct * 1)()).dtype)
+            return np.ctypeslib.as_array(ctypes.cast(p, ctypes.POINTER(ct)), shape=(cnt,)).copy()
+        off = arr(res.cigar_off, ctypes.c_int64, n + 1)
+        return (arr(res.score, ctypes.c_int32, n), arr(res.status, ctypes.c_int8, n),
+                arr(res.cigar, ctypes.c_uint32, int(off[-1]) if n >= 0 and len(off) else 0), off,
+                res.latency_us)
+
+    def wait(self, rid: int, timeout_ms: int = -1, release: bool = True):
+        """(score, status, cigar, cigar_off, latency_us) as numpy copies."""
+        res = RequestResult()
+        _scheck(lib().aim_server_wait(self._h, rid, timeout_ms, ctypes.byref(res)))
+        out = self._copy(res)
+        if release:
+            _scheck(lib().aim_server_release(self._h, rid))
+        return out
+
+    def poll(self, rid: int):
+        """None while running, else the wait() tuple (results released)."""
+        res = RequestResult()
+        rc = lib().aim_server_poll(self._h, rid, ctypes.byref(res))
+        if rc == -5:
+            return None
+        _scheck(rc)
+        out = self._copy(res)
+        _scheck(lib().aim_server_release(self._h, rid))
+        return out
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _scheck(lib().aim_server_stats_get(self._h, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+    def reset_stats(self):
+        _scheck(lib().aim_server_reset_stats(self._h))
+
+    def close(self):
+        if self._h:
+            lib().aim_server_destroy(self._h)
+            self._h = vp()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
 
 
 def version() -> str:

@@ -335,7 +335,7 @@ aim_status aim_create(aim_context **ctx, int32_t device, const aim_options *opt)
   if (o.kernel != AIM_KERNEL_AUTO && o.kernel != AIM_KERNEL_PLAIN)
     return fail(AIM_ERR_INVALID_ARG, "unknown kernel option %d", o.kernel);
   if (o.scratch_limit < 0) return fail(AIM_ERR_INVALID_ARG, "scratch_limit < 0");
-  if (o.scratch_limit == 0) o.scratch_limit = (int64_t)8 << 30;
+  if (o.scratch_limit == 0) o.scratch_limit = (int64_t)64 << 30;
   auto *c = new aim_context();
   c->device = device;
   c->opt = o;
@@ -463,7 +463,13 @@ aim_status aim_align_batch(aim_context *c, const aim_batch *B, int32_t alg, aim_
   }
 
   // pool for runs beyond the per-pair slot (reset every call)
-  const int64_t pool_cap = R->want_cigar ? std::max<int64_t>(1 << 20, c->opt.scratch_limit / 32 / 4) : 1;
+  // sized from the batch (a quarter of the worst-case run count per pair),
+  // between 4 MiB and 1/64 of the scratch budget; exhaustion falls back to
+  // the exact in-place re-run
+  const int64_t pool_cap =
+      R->want_cigar ? std::max<int64_t>(1 << 20, std::min<int64_t>(c->opt.scratch_limit / 64 / 4,
+                                                                   n * std::min<int64_t>(2 * (int64_t)L + 1, 1024) / 4))
+                    : 1;
   if ((st = ensure(c, c->pool, (size_t)pool_cap * 4))) return st;
   if ((st = ensure(c, c->pooloff, (size_t)n * 8))) return st;
   HIP_TRY(aim::launch_fill_i32(as<int32_t>(c->total) + 2, 0, 2, s));

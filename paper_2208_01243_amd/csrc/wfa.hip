@@ -399,7 +399,7 @@ __global__ __launch_bounds__(WGMAX) void k_wfa_trace(Seqs S, Outs O, Scoring P, 
 
 WfaPlan wfa_plan(int32_t max_len, const Scoring &P, int64_t budget_bytes, int32_t cus, bool plain,
                  int32_t ring_kb, int32_t trace_kb, int32_t long_threads) {
-  // budget split: HBM rings 1/8, arena classes 1/8, 1/8 and 1/4
+  // budget split: HBM rings 1/8, arena classes 1/16, 1/8 and 1/2
   WfaPlan pl{};
   const int32_t oe = P.o + P.e;
   pl.R = std::max(P.x, oe) + 1;
@@ -424,10 +424,10 @@ WfaPlan wfa_plan(int32_t max_len, const Scoring &P, int64_t budget_bytes, int32_
   pl.need_cap[0] = pl.lds_arena_words;
   pl.need_cap[1] = (int64_t)1 << 18;
   pl.need_cap[2] = (int64_t)1 << 22;
-  pl.need_cap[3] = std::max<int64_t>(pl.need_cap[2], std::min<int64_t>((int64_t)48 << 20, budget_bytes / 4 / 4));
+  pl.need_cap[3] = std::max<int64_t>(pl.need_cap[2], std::min<int64_t>((int64_t)48 << 20, budget_bytes / 2 / 4));
   pl.arena_slots[0] = cus * 8;
   pl.threads[0] = 64;
-  const int64_t share[4] = {0, budget_bytes / 8, budget_bytes / 8, budget_bytes / 4};
+  const int64_t share[4] = {0, budget_bytes / 16, budget_bytes / 8, budget_bytes / 2};
   const int64_t cap_slots[4] = {0, (int64_t)cus * 8, (int64_t)cus * 2, (int64_t)cus};
   for (int k = 1; k < 4; ++k)
     pl.arena_slots[k] = (int32_t)std::max<int64_t>(1, std::min<int64_t>(cap_slots[k], share[k] / (pl.need_cap[k] * 4)));

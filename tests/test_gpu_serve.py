@@ -1,0 +1,95 @@
+"""Serving form: continuous batching of requests of mixed sizes and
+algorithms.  Each request's results must equal the oracle's and the same
+request aligned alone; admission must keep the device footprint under the
+budget without dropping or starving anyone."""
+import threading
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+import synth  # noqa: E402
+import paper_2208_01243_amd as aim  # noqa: E402
+from gpu_util import compare, run  # noqa: E402
+
+ALGS = [("nw", (0, 1, 0, 1), -1), ("swg", (0, 4, 6, 2), -1), ("wfa", (0, 4, 6, 2), -1),
+        ("wfa", (0, 4, 6, 2), 60), ("nw", (0, 1, 0, 1), 8)]
+
+
+def _requests(seed, count, lmax=400):
+    rng = np.random.default_rng(seed)
+    out = []
+    for r in range(count):
+        alg, pen, smax = ALGS[int(rng.integers(0, len(ALGS)))]
+        n = int(synth.log_uniform_int(rng, 1, 300, 1)[0])
+        lens = rng.integers(0, lmax + 1, n)
+        txts = [rng.integers(0, 4, int(L)).astype(np.uint8) for L in lens]
+        pats = []
+        for T in txts:
+            bb = synth.from_lists([T], [T])
+            P, _ = synth.mutate(rng, bb.txt, bb.txt_off, [float(rng.uniform(0.0, 0.1))])
+            pats.append(P)
+        out.append((alg, pen, smax, synth.from_lists(pats, txts)))
+    return out
+
+
+def _submit(srv, alg, pen, smax, b, enc="code"):
+    data = (lambda c: synth.ascii_from_codes(c)) if enc == "ascii" else (lambda c: c)
+    return srv.submit(alg, pen, smax, data(b.pat), b.pat_off[:-1], b.pat_len, data(b.txt), b.txt_off[:-1],
+                      b.txt_len, enc=aim.ENC_ASCII if enc == "ascii" else aim.ENC_CODE)
+
+
+def test_mix_equals_alone_and_oracle():
+    reqs = _requests(1, 60)
+    with aim.Server(0, n_streams=4) as srv:
+        ids = [_submit(srv, a, p, s, b, enc="ascii" if k % 2 else "code") for k, (a, p, s, b) in enumerate(reqs)]
+        results = [srv.wait(i) for i in ids]
+        st = srv.stats()
+    assert st["completed"] == 60 and st["p99_us"] >= st["p50_us"] > 0
+    with aim.Context(0) as ctx:
+        for (alg, pen, smax, b), res in zip(reqs, results):
+            got = res[:4]
+            want = oracle.align_batch(b, alg, pen, smax)
+            assert not compare(got, want)
+            alone = run(ctx, b, alg, pen, smax, enc="code")
+            assert not compare(got, alone)
+
+
+def test_budget_admission_and_no_starvation():
+    reqs = _requests(2, 40, lmax=300)
+    budget = 24 << 20  # forces requests to wait for earlier ones to finish
+    with aim.Server(0, n_streams=3, budget_bytes=budget) as srv:
+        ids = [_submit(srv, a, p, s, b) for a, p, s, b in reqs]
+        results = [srv.wait(i) for i in ids]
+        st = srv.stats()
+    assert st["peak_bytes"] <= budget and st["completed"] == len(reqs) and st["bytes_in_use"] == 0
+    for (alg, pen, smax, b), res in zip(reqs, results):
+        assert not compare(res[:4], oracle.align_batch(b, alg, pen, smax))
+
+
+def test_oversized_request_is_refused():
+    b = synth.workload("swg150", n=2000)
+    with aim.Server(0, n_streams=1, budget_bytes=1 << 20) as srv:
+        with pytest.raises(aim.AimError) as ei:
+            _submit(srv, "swg", (0, 4, 6, 2), -1, b)
+        assert ei.value.code == -1
+
+
+def test_concurrent_submitters():
+    reqs = _requests(3, 48, lmax=250)
+    ids = [None] * len(reqs)
+    with aim.Server(0, n_streams=4) as srv:
+        def sub(k0):
+            for k in range(k0, len(reqs), 4):
+                a, p, s, b = reqs[k]
+                ids[k] = _submit(srv, a, p, s, b)
+        th = [threading.Thread(target=sub, args=(k,)) for k in range(4)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        for (alg, pen, smax, b), i in zip(reqs, ids):
+            assert not compare(srv.wait(i)[:4], oracle.align_batch(b, alg, pen, smax))
