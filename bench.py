@@ -26,6 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_INT32_TOPS = 256 * 64 * 2.4e9 / 1e12  # 256 CUs x 64 lanes x 2.4 GHz = 39.3 T int32 ops/s
+PEAK_PK16_TOPS = 2 * PEAK_INT32_TOPS       # packed 16-bit: two halves per lane = 78.6 T ops/s
 HBM_PEAK_GBS = 8000.0
 # algorithmic integer ops per DP cell (fill recurrences + traceback code):
 # Gotoh: E 3, F 3, H 3 (diag add, two mins), 4 traceback bits 4 -> 13 (+1 for the
@@ -156,9 +157,12 @@ def main():
     # roofline of the dominant kernel
     roof = None
     if w["alg"] in ("swg", "nw"):
-        band_ms, band_launches = phases.get("band32", (0.0, 0))
-        # algorithmic cells of the 32-diagonal band over the pairs it decided:
-        # pairs escalated to wider tiers are counted at their own tier
+        # dominant kernel: the first band tier (packed 16-bit when the value
+        # bound allows, else 32-bit)
+        kname, phase, peak, unit = ("k_band16<32>", "band16", PEAK_PK16_TOPS, "Tops/s (packed int16)") \
+            if "band16" in phases else ("k_band<32>", "band32", PEAK_INT32_TOPS, "Tops/s (int32)")
+        band_ms, band_launches = phases.get(phase, (0.0, 0))
+        # algorithmic cells of the 32-diagonal band: every pair's rows x 32
         m = batch.pat_len.astype(np.int64)
         cells_band = float((m * 32).sum())
         ops = OPS_PER_CELL[w["alg"]] * cells_band
@@ -166,13 +170,14 @@ def main():
             t_launch = band_ms / band_launches / 1000.0
             achieved = ops / t_launch / 1e12
             import hashlib
-            src = open(os.path.join(ROOT, "paper_2208_01243_amd", "csrc", "dp_band.hip"), "rb").read()
+            src_name = "dp_band16.hip" if phase == "band16" else "dp_band.hip"
+            src = open(os.path.join(ROOT, "paper_2208_01243_amd", "csrc", src_name), "rb").read()
             h = hashlib.sha256(src).hexdigest()[:16]
-            meas = MEASURED_TRAFFIC.get((args.workload, "k_band<32>"))
+            meas = MEASURED_TRAFFIC.get((args.workload, kname))
             traffic = meas[1] if (meas and meas[0] == h and n == w["total"]) else None
-            roof = {"bound": "alu", "kernel": "k_band<32>", "achieved": round(achieved, 3),
-                    "peak": round(PEAK_INT32_TOPS, 1), "unit": "Tops/s (int32)",
-                    "frac": round(achieved / PEAK_INT32_TOPS, 4), "traffic": traffic,
+            roof = {"bound": "alu", "kernel": kname, "achieved": round(achieved, 3),
+                    "peak": round(peak, 1), "unit": unit,
+                    "frac": round(achieved / peak, 4), "traffic": traffic,
                     "avg_launch_ms": round(band_ms / band_launches, 4),
                     "ops_per_cell": OPS_PER_CELL[w["alg"]], "cells_per_launch": cells_band}
     elif "wfa" in phases:

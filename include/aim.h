@@ -193,20 +193,22 @@ aim_status aim_timing_reset(aim_context *ctx);
 /* Time every candidate launch configuration on this batch and keep the
  * fastest for (alg, length bucket of pairs->max_len); later calls with that
  * key use it.  Candidates: NW/SWG -- first band width {32, 64}, resident
- * wavefronts per CU {8, 16, 32}, length sort {off, on}; WFA -- LDS for the
+ * wavefronts per CU {8, 16, 32}, length sort {off, on}, packed 16-bit cells
+ * {off, on} (32 diagonals only); WFA -- LDS for the
  * score ring {16, 32, 48} KB, for the full store {24, 40} KB, workgroup size
  * for long pairs {128, 256}.  Each candidate runs once to warm up and `reps`
  * times timed (median).  Synchronous.  On return `out` holds the results of
- * the chosen configuration; best_params (6 int32, see aim_tune_get) and
+ * the chosen configuration; best_params (7 int32, see aim_tune_get) and
  * best_ms may be NULL.  Paper: Data Management (the framework picks the
  * number of DPU threads from the algorithm, read length and error rate). */
 aim_status aim_autotune(aim_context *ctx, const aim_batch *pairs, int32_t alg, aim_penalties pen,
                         int32_t max_score, aim_results *out, void *stream, int32_t reps,
                         int32_t *best_params, double *best_ms);
 
-/* Launch parameters for (alg, max_len): params[0] first band width,
+/* Launch parameters for (alg, max_len), 7 int32: params[0] first band width,
  * [1] wavefronts per CU, [2] length sort (-1 auto, 0 off, 1 on), [3] WFA ring
- * LDS KB, [4] WFA full-store LDS KB, [5] WFA long-pair workgroup size. */
+ * LDS KB, [4] WFA full-store LDS KB, [5] WFA long-pair workgroup size,
+ * [6] packed 16-bit band cells (0 off, 1 on when the value bound allows). */
 aim_status aim_tune_get(aim_context *ctx, int32_t alg, int32_t max_len, int32_t *params);
 aim_status aim_tune_set(aim_context *ctx, int32_t alg, int32_t max_len, const int32_t *params);
 /* Tune cache as text, keyed by GPU architecture and HIP runtime version; a

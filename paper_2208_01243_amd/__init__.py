@@ -200,22 +200,22 @@ class Context:
     def autotune(self, pat_seq, pat_off, pat_len, txt_seq, txt_off, txt_len, *, enc, max_len, alg,
                  pen, max_score, score, status, cigar=None, cigar_off=None, want_cigar=True,
                  stream=None, reps=2):
-        """aim_autotune; returns (params list of 6, best ms)."""
+        """aim_autotune; returns (params list of 7, best ms)."""
         b, r, a = self._args(pat_seq, pat_off, pat_len, txt_seq, txt_off, txt_len, enc, max_len, alg,
                              score, status, cigar, cigar_off, want_cigar)
-        params = (i32 * 6)()
+        params = (i32 * 7)()
         ms = ctypes.c_double()
         _check(lib().aim_autotune(self._h, ctypes.byref(b), a, Penalties(*pen), max_score,
                                   ctypes.byref(r), _stream(stream), reps, params, ctypes.byref(ms)))
         return list(params), ms.value
 
     def tune_get(self, alg, max_len):
-        params = (i32 * 6)()
+        params = (i32 * 7)()
         _check(lib().aim_tune_get(self._h, ALGORITHMS[alg] if isinstance(alg, str) else alg, max_len, params))
         return list(params)
 
     def tune_set(self, alg, max_len, params):
-        arr = (i32 * 6)(*params)
+        arr = (i32 * 7)(*params)
         _check(lib().aim_tune_set(self._h, ALGORITHMS[alg] if isinstance(alg, str) else alg, max_len, arr))
 
     def tune_save(self, path):

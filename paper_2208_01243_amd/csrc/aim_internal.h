@@ -122,6 +122,14 @@ hipError_t launch_band(int W, bool affine, const Seqs &S, const Outs &O, const S
                        int32_t nslots, hipStream_t s);
 int64_t band_tb_slot_words(int W, bool affine, int32_t rows_cap);
 
+// Banded DP with packed 16-bit cells, two pairs per lane, 32 diagonals
+// (traceback slot layout of the 64-diagonal kernel).  band16_fits: whether
+// pairs of length <= max_len provably stay within 16 bits.
+bool band16_fits(int32_t max_len, const Scoring &P, bool affine);
+hipError_t launch_band16(bool affine, const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk,
+                         uint32_t *tb, int64_t tb_slot_words, int32_t rows_cap, int32_t nslots,
+                         hipStream_t s);
+
 // Full-matrix DP, one pair per workgroup.
 hipError_t launch_full(bool affine, const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk,
                        uint32_t *scratch, int64_t slot_words, int32_t max_len, int32_t nslots,

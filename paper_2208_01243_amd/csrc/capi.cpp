@@ -93,6 +93,7 @@ struct Tune {
   int32_t wfa_ring_kb = 32;   // LDS per workgroup for the WFA score ring
   int32_t wfa_trace_kb = 40;  // LDS per workgroup for the WFA full store
   int32_t wfa_long_threads = 256;  // workgroup size for long WFA pairs
+  int32_t band16 = 1;         // packed 16-bit band kernel when the value bound allows
 };
 
 struct aim_graph {
@@ -513,16 +514,24 @@ aim_status aim_align_batch(aim_context *c, const aim_batch *B, int32_t alg, aim_
     const int32_t rows_cap = L + 1;
     const int64_t chunks = (n + 63) / 64;
     const int32_t w0 = tu.band_w0 == 64 ? 64 : 32;
+    // 32 diagonals in packed 16-bit arithmetic (two pairs per lane) when the
+    // value bound allows, else 32-bit
+    const bool b16 = w0 == 32 && tu.band16 && aim::band16_fits(L, P, affine);
     Buf &tbA = w0 == 32 ? c->tb32 : c->tb64;
-    const int64_t swA = aim::band_tb_slot_words(w0, affine, rows_cap);
-    int64_t slots = std::min<int64_t>(chunks, (int64_t)c->cus * std::max(1, tu.band_wpc));
+    const int64_t swA = aim::band_tb_slot_words(b16 ? 64 : w0, affine, rows_cap);
+    const int64_t chunksA = b16 ? (n + 127) / 128 : chunks;
+    int64_t slots = std::min<int64_t>(chunksA, (int64_t)c->cus * std::max(1, tu.band_wpc));
     slots = std::max<int64_t>(1, std::min<int64_t>(slots, budget / (swA * 4)));
     if ((st = ensure(c, tbA, (size_t)(slots * swA * 4)))) return st;
     aim::Work W1{order, nullptr, n, cnt + C_T1, as<int32_t>(c->list2), cnt + C_L2, 0};
     {
-      Phase ph(c, s, w0 == 32 ? "band32" : "band64");
-      HIP_TRY(aim::launch_band(w0, affine, S, O, P, W1, as<uint32_t>(tbA), swA, rows_cap,
-                               (int32_t)slots, s));
+      Phase ph(c, s, b16 ? "band16" : (w0 == 32 ? "band32" : "band64"));
+      if (b16)
+        HIP_TRY(aim::launch_band16(affine, S, O, P, W1, as<uint32_t>(tbA), swA, rows_cap,
+                                   (int32_t)slots, s));
+      else
+        HIP_TRY(aim::launch_band(w0, affine, S, O, P, W1, as<uint32_t>(tbA), swA, rows_cap,
+                                 (int32_t)slots, s));
     }
     int32_t *full_list = as<int32_t>(c->list2);
     int32_t *full_count = cnt + C_L2;
@@ -580,22 +589,23 @@ aim_status aim_align_batch(aim_context *c, const aim_batch *B, int32_t alg, aim_
 
 // ---------------------------------------------------------------- autotuner
 namespace {
-const int32_t TUNE_FIELDS = 6;
+const int32_t TUNE_FIELDS = 7;
 void tune_to(const Tune &t, int32_t *v) {
   v[0] = t.band_w0; v[1] = t.band_wpc; v[2] = t.sort;
-  v[3] = t.wfa_ring_kb; v[4] = t.wfa_trace_kb; v[5] = t.wfa_long_threads;
+  v[3] = t.wfa_ring_kb; v[4] = t.wfa_trace_kb; v[5] = t.wfa_long_threads; v[6] = t.band16;
 }
 Tune tune_from(const int32_t *v) {
   Tune t;
   t.band_w0 = v[0]; t.band_wpc = v[1]; t.sort = v[2];
-  t.wfa_ring_kb = v[3]; t.wfa_trace_kb = v[4]; t.wfa_long_threads = v[5];
+  t.wfa_ring_kb = v[3]; t.wfa_trace_kb = v[4]; t.wfa_long_threads = v[5]; t.band16 = v[6];
   return t;
 }
 bool tune_valid(const Tune &t) {
   return (t.band_w0 == 32 || t.band_w0 == 64) && t.band_wpc >= 1 && t.band_wpc <= 64 &&
          t.sort >= -1 && t.sort <= 1 && t.wfa_ring_kb >= 8 && t.wfa_ring_kb <= 60 &&
          t.wfa_trace_kb >= 8 && t.wfa_trace_kb <= 60 &&
-         (t.wfa_long_threads == 64 || t.wfa_long_threads == 128 || t.wfa_long_threads == 256);
+         (t.wfa_long_threads == 64 || t.wfa_long_threads == 128 || t.wfa_long_threads == 256) &&
+         (t.band16 == 0 || t.band16 == 1);
 }
 std::string tune_key() {
   int v = 0;
@@ -627,13 +637,16 @@ aim_status aim_autotune(aim_context *c, const aim_batch *B, int32_t alg, aim_pen
   } else {
     for (int w0 : {32, 64})
       for (int wpc : {8, 16, 32})
-        for (int so : {0, 1}) {
-          Tune t;
-          t.band_w0 = w0;
-          t.band_wpc = wpc;
-          t.sort = so;
-          cand.push_back(t);
-        }
+        for (int so : {0, 1})
+          for (int b16 : {0, 1}) {
+            if (w0 == 64 && b16) continue;
+            Tune t;
+            t.band_w0 = w0;
+            t.band_wpc = wpc;
+            t.sort = so;
+            t.band16 = b16;
+            cand.push_back(t);
+          }
   }
   DeviceGuard g(c->device);
   hipStream_t s = (hipStream_t)stream;

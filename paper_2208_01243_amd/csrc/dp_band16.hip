@@ -1,0 +1,331 @@
+// Banded NW / SWG-Gotoh with packed 16-bit arithmetic: two pairs per lane.
+//
+// The same algorithm as the 32-diagonal band kernel (one pair per lane, band
+// of W diagonals proven exact per pair, 2-4 traceback bit-planes per cell,
+// canonical traceback), but each 32-bit register holds the cell of pair A in
+// its low half and of pair B in its high half, so every packed instruction
+// (v_pk_add_i16 with clamp, v_pk_min_i16, v_pk_sub_i16) advances two cells.
+// Additions saturate at 32767, which plays the role of +infinity.  A pair
+// takes this path only when every finite value of its band is provably below
+// 32000: any band cell (i,j) is reached by one gap run and a diagonal walk, so
+// H(i,j) <= x*max(m,n) + o + e*(m+n), and no register holds more than that
+// plus 2 (o + e) + x (E, F and the diagonal candidate on top of H + o + e);
+// pairs above the bound go to the 32-bit kernels.  Differences of two values
+// in [0, 32767] never wrap, so the sign bit of each 16-bit difference is the
+// traceback decision; sign bits are shifted into the top of each half, so
+// after 16 cells bit c of a half is cell c.
+//
+// Traceback words: row i, plane q, cell group h (cells 16h..16h+15) at
+// ((i * planes + q) * 2 + h) * 64 + lane, pair A in bits 0..15, B in 16..31.
+#include "aim_internal.h"
+#include "dev_util.h"
+
+namespace aim {
+namespace {
+
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+constexpr int W = 32;
+constexpr int32_t VMAX = 32000;
+constexpr short INF16 = 32767;
+
+__device__ __forceinline__ uint32_t U(s16x2 v) { return __builtin_bit_cast(uint32_t, v); }
+__device__ __forceinline__ s16x2 S(uint32_t v) { return __builtin_bit_cast(s16x2, v); }
+__device__ __forceinline__ s16x2 adds(s16x2 a, s16x2 b) { return __builtin_elementwise_add_sat(a, b); }
+__device__ __forceinline__ s16x2 mn(s16x2 a, s16x2 b) { return __builtin_elementwise_min(a, b); }
+__device__ __forceinline__ s16x2 spl(int32_t v) { return (s16x2){(short)v, (short)v}; }
+// shift the sign bit of each half of d into the top of acc's halves
+__device__ __forceinline__ uint32_t push_sign(uint32_t acc, s16x2 d) {
+  const u16x2 a = __builtin_bit_cast(u16x2, acc) >> (u16x2){1, 1};
+  return __builtin_bit_cast(uint32_t, a) | (U(d) & 0x80008000u);
+}
+
+template <bool AFF>
+__global__ __launch_bounds__(64) void k_band16(Seqs Sq, Outs O, Scoring P, Work Wk, uint32_t *tb_all,
+                                              int64_t tb_slot_words, int32_t rows_cap) {
+  constexpr int NP = AFF ? 4 : 2;
+  const int lane = threadIdx.x;
+  uint32_t *tb = tb_all + (int64_t)blockIdx.x * tb_slot_words;
+  const int32_t x = P.x, o = P.o, e = P.e, oe = P.o + P.e;
+  const int32_t hoff = AFF ? oe : e;
+  const int64_t count = Wk.count ? (int64_t)(*(volatile const int32_t *)Wk.count) : Wk.n;
+  const s16x2 vx = spl(x), ve = spl(e), voe = spl(oe), vinf = spl(INF16);
+
+  for (;;) {
+    int chunk = 0;
+    if (lane == 0) chunk = atomicAdd(Wk.counter, 1);
+    chunk = __shfl(chunk, 0);
+    if ((int64_t)chunk * 128 >= count) break;
+
+    int64_t p[2];
+    int32_t m[2], n[2], kmin[2], bstar[2];
+    bool run[2], esc[2];
+    const uint64_t *pat[2], *txt[2];
+    int64_t pnw[2], tnw[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int64_t li = (int64_t)chunk * 128 + 64 * h + lane;
+      bool has = li < count;
+      p[h] = has ? (Wk.idx ? (int64_t)Wk.idx[li] : li) : 0;
+      m[h] = n[h] = kmin[h] = 0;
+      run[h] = esc[h] = false;
+      if (has) {
+        if (O.flags && O.flags[p[h]]) {
+          O.score[p[h]] = -1;
+          O.status[p[h]] = ST_INVALID;
+          O.nruns[p[h]] = 0;
+        } else {
+          m[h] = Sq.pat_len[p[h]];
+          n[h] = Sq.txt_len[p[h]];
+          const int32_t d = n[h] - m[h], ad = d < 0 ? -d : d;
+          const int32_t lb_any = ad ? o + ad * e : 0;
+          // largest finite register value: H + 2 (o + e) + x (see the header)
+          const int64_t vbound = (int64_t)x * max(m[h], n[h]) + 2 * (int64_t)o +
+                                 (int64_t)e * (m[h] + n[h]) + 2 * (int64_t)hoff + 2 * (int64_t)x;
+          if (P.max_score >= 0 && lb_any > P.max_score) {
+            O.score[p[h]] = -1;
+            O.status[p[h]] = ST_REJECTED;
+            O.nruns[p[h]] = 0;
+          } else if (ad > W - 1 || m[h] > rows_cap - 1 || vbound > VMAX) {
+            esc[h] = true;
+          } else {
+            run[h] = true;
+            kmin[h] = min(0, d) - (W - 1 - ad) / 2;
+          }
+        }
+      }
+      pat[h] = Sq.pat + (run[h] ? Sq.pat_off[p[h]] : 0);
+      txt[h] = Sq.txt + (run[h] ? Sq.txt_off[p[h]] : 0);
+      pnw[h] = run[h] ? (m[h] + 31) >> 5 : 0;
+      tnw[h] = run[h] ? (n[h] + 31) >> 5 : 0;
+      bstar[h] = n[h] - m[h] - kmin[h];
+    }
+    if (Wk.next_idx) {
+      dev::wave_append(esc[0], (int32_t)p[0], Wk.next_idx, Wk.next_count);
+      dev::wave_append(esc[1], (int32_t)p[1], Wk.next_idx, Wk.next_count);
+    }
+    const int Mmax = dev::wave_max(max(run[0] ? m[0] : 0, run[1] ? m[1] : 0));
+
+    s16x2 Hs[W], E[W];
+    auto border = [&](int32_t j) -> int32_t {
+      return j < 0 ? INF16 : min((j == 0 ? 0 : (AFF ? o + j * e : j * e)) + hoff, (int32_t)INF16);
+    };
+#pragma unroll
+    for (int b = 0; b < W; ++b) {
+      Hs[b] = (s16x2){(short)border(kmin[0] + b), (short)border(kmin[1] + b)};
+      E[b] = vinf;
+    }
+    int32_t score[2] = {DP_INF, DP_INF};
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+      if (run[h] && m[h] == 0) {
+#pragma unroll
+        for (int b = 0; b < W; ++b)
+          if (b == bstar[h]) score[h] = (h ? Hs[b].y : Hs[b].x) - hoff;
+      }
+
+    uint64_t pword[2] = {0, 0};
+    for (int i = 1; i <= Mmax; ++i) {
+      uint32_t mlo[2], mhi[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        if (((i - 1) & 31) == 0) pword[h] = run[h] ? dev::ld_word(pat[h], pnw[h], (i - 1) >> 5) : 0ull;
+        const uint64_t prep = (uint64_t)((uint32_t)(pword[h] >> (2 * ((i - 1) & 31))) & 3u) * dev::K55;
+        const uint64_t X = dev::window32(txt[h], tnw[h], (int64_t)i + kmin[h] - 1) ^ prep;
+        const uint64_t mm = (X | (X >> 1)) & dev::K55;
+        mlo[h] = (uint32_t)mm;
+        mhi[h] = (uint32_t)(mm >> 32);
+      }
+      // packed mismatch bits, 8 cells per word: cell c of the group at bit 2c
+      // of the low half (pair A) and of the high half (pair B)
+      uint32_t X[4] = {(mlo[0] & 0xFFFFu) | (mlo[1] << 16), (mlo[0] >> 16) | (mlo[1] & 0xFFFF0000u),
+                       (mhi[0] & 0xFFFFu) | (mhi[1] << 16), (mhi[0] >> 16) | (mhi[1] & 0xFFFF0000u)};
+      uint32_t bits[NP][2];
+#pragma unroll
+      for (int q = 0; q < NP; ++q) bits[q][0] = bits[q][1] = 0u;
+      s16x2 Hsl = vinf, Fl = vinf;
+#pragma unroll
+      for (int b = 0; b < W; ++b) {
+        const int g = b >> 3, hw = b >> 4;
+        const s16x2 mmp = S(X[g] & 0x00010001u);
+        X[g] >>= 2;
+        const s16x2 Hsd = Hs[b];
+        const s16x2 Hsu = (b + 1 < W) ? Hs[b + 1] : vinf;
+        const s16x2 diag = adds(Hsd, mmp * vx);  // H(i-1,j-1) + cost + hoff
+        const s16x2 dg = diag - mmp;              // ... with the match/mismatch tie offset
+        if (AFF) {
+          const s16x2 Eu = (b + 1 < W) ? E[b + 1] : vinf;
+          const s16x2 bE = adds(Eu, ve), Ev = mn(Hsu, bE);
+          const s16x2 bF = adds(Fl, ve), Fv = mn(Hsl, bF);
+          const s16x2 G = mn(Ev, Fv);
+          const s16x2 Gs = adds(G, voe);
+          const s16x2 Hsv = mn(diag, Gs);
+          bits[0][hw] = push_sign(bits[0][hw], dg - Gs);
+          bits[1][hw] = push_sign(bits[1][hw], Fv - Ev);
+          bits[2][hw] = push_sign(bits[2][hw], bE - Hsu);
+          bits[3][hw] = push_sign(bits[3][hw], bF - Hsl);
+          Hs[b] = Hsv;
+          E[b] = Ev;
+          Hsl = Hsv;
+          Fl = Fv;
+        } else {
+          const s16x2 G = mn(Hsu, Hsl);
+          const s16x2 Gs = adds(G, ve);
+          const s16x2 Hsv = mn(diag, Gs);
+          bits[0][hw] = push_sign(bits[0][hw], dg - Gs);
+          bits[1][hw] = push_sign(bits[1][hw], Hsl - Hsu);
+          Hs[b] = Hsv;
+          Hsl = Hsv;
+        }
+        // keep each cell's bit packing next to its arithmetic (see the
+        // 32-bit band kernel); the empty asm emits nothing
+#pragma unroll
+        for (int q = 0; q < NP; ++q) asm volatile("" : "+v"(bits[q][hw]));
+      }
+      if (P.want_cigar) {
+        uint32_t *row = tb + ((int64_t)i * NP * 2) * 64 + lane;
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+          row[(q * 2) * 64] = bits[q][0];
+          row[(q * 2 + 1) * 64] = bits[q][1];
+        }
+      }
+      const bool cap0 = run[0] && i == m[0], cap1 = run[1] && i == m[1];
+      if (__ballot(cap0 || cap1)) {
+#pragma unroll
+        for (int b = 0; b < W; ++b) {
+          if (cap0 && b == bstar[0]) score[0] = Hs[b].x - hoff;
+          if (cap1 && b == bstar[1]) score[1] = Hs[b].y - hoff;
+        }
+      }
+    }
+
+    bool accept[2] = {false, false};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (!run[h]) continue;
+      const int32_t d = n[h] - m[h], kmax = kmin[h] + W - 1;
+      const int32_t lb_up = kmax + 1 > n[h] ? DP_INF : 2 * o + e * (2 * (kmax + 1) - d);
+      const int32_t lb_lo = kmin[h] - 1 < -m[h] ? DP_INF : 2 * o + e * (2 * (1 - kmin[h]) + d);
+      const int32_t LB = min(lb_up, lb_lo);
+      esc[h] = false;
+      if (score[h] < LB) {
+        if (P.max_score >= 0 && score[h] > P.max_score) {
+          O.score[p[h]] = -1;
+          O.status[p[h]] = ST_REJECTED;
+          O.nruns[p[h]] = 0;
+        } else {
+          accept[h] = true;
+          O.score[p[h]] = score[h];
+          O.status[p[h]] = ST_ALIGNED;
+          O.nruns[p[h]] = 0;
+        }
+      } else if (P.max_score >= 0 && LB > P.max_score) {
+        O.score[p[h]] = -1;
+        O.status[p[h]] = ST_REJECTED;
+        O.nruns[p[h]] = 0;
+      } else {
+        esc[h] = true;
+      }
+    }
+    if (Wk.next_idx) {
+      dev::wave_append(run[0] && esc[0], (int32_t)p[0], Wk.next_idx, Wk.next_count);
+      dev::wave_append(run[1] && esc[1], (int32_t)p[1], Wk.next_idx, Wk.next_count);
+    }
+    if (!P.want_cigar) continue;
+
+    // ---- traceback, pair A then pair B of this lane ----
+    for (int h = 0; h < 2; ++h) {
+      if (!accept[h]) continue;
+      int32_t i = m[h], j = n[h], b = bstar[h], st = 0;
+      uint32_t cur_op = 0xffu, cur_len = 0;
+      int32_t nr = 0;
+      RunSink sink;
+      sink.begin(O, p[h]);
+      int64_t pq = -1, tq = -1;
+      uint64_t pw = 0, tw = 0;
+      int32_t rowi = -1;
+      uint32_t rw[NP][2];
+      auto put = [&](uint32_t op, uint32_t len) {
+        if (op == cur_op) {
+          cur_len += len;
+        } else {
+          if (cur_len) {
+            sink.put(nr, (cur_len << 4) | cur_op, (int64_t)i + j + 1);
+            ++nr;
+          }
+          cur_op = op;
+          cur_len = len;
+        }
+      };
+      const int sh = 16 * h;
+      while (i > 0 && j > 0) {
+        if (rowi != i) {
+          const uint32_t *row = tb + ((int64_t)i * NP * 2) * 64 + lane;
+#pragma unroll
+          for (int q = 0; q < NP; ++q) {
+            rw[q][0] = row[(q * 2) * 64];
+            rw[q][1] = row[(q * 2 + 1) * 64];
+          }
+          rowi = i;
+        }
+        uint32_t bq[NP];
+#pragma unroll
+        for (int q = 0; q < NP; ++q) bq[q] = ((b >> 4) ? rw[q][1] : rw[q][0]) >> (sh + (b & 15)) & 1u;
+        if (st == 0) {
+          if (bq[0]) {
+            if (((i - 1) >> 5) != pq) { pq = (i - 1) >> 5; pw = pat[h][pq]; }
+            if (((j - 1) >> 5) != tq) { tq = (j - 1) >> 5; tw = txt[h][tq]; }
+            const uint32_t a = (uint32_t)(pw >> (2 * ((i - 1) & 31))) & 3u;
+            const uint32_t c = (uint32_t)(tw >> (2 * ((j - 1) & 31))) & 3u;
+            put(a == c ? OP_EQ : OP_X, 1);
+            --i;
+            --j;
+          } else if (!AFF) {
+            if (bq[1]) { put(OP_D, 1); --j; --b; }
+            else { put(OP_I, 1); --i; ++b; }
+          } else {
+            st = bq[1] ? 2 : 1;
+          }
+        } else if (st == 1) {
+          put(OP_I, 1);
+          st = bq[2] ? 1 : 0;
+          --i;
+          ++b;
+        } else {
+          put(OP_D, 1);
+          st = bq[3] ? 2 : 0;
+          --j;
+          --b;
+        }
+      }
+      if (i > 0) put(OP_I, (uint32_t)i);
+      if (j > 0) put(OP_D, (uint32_t)j);
+      put(0xfu, 0);
+      sink.finish();
+      O.nruns[p[h]] = nr;
+    }
+  }
+}
+
+}  // namespace
+
+bool band16_fits(int32_t max_len, const Scoring &P, bool affine) {
+  const int64_t hoff = affine ? P.o + P.e : P.e;
+  return (int64_t)P.x * max_len + 2 * (int64_t)P.o + (int64_t)P.e * 2 * max_len + 2 * hoff +
+             2 * (int64_t)P.x <= VMAX;
+}
+
+hipError_t launch_band16(bool affine, const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk,
+                         uint32_t *tb, int64_t tb_slot_words, int32_t rows_cap, int32_t nslots,
+                         hipStream_t s) {
+  dim3 grid(nslots), block(64);
+  if (affine)
+    hipLaunchKernelGGL((k_band16<true>), grid, block, 0, s, S, O, P, Wk, tb, tb_slot_words, rows_cap);
+  else
+    hipLaunchKernelGGL((k_band16<false>), grid, block, 0, s, S, O, P, Wk, tb, tb_slot_words, rows_cap);
+  return hipGetLastError();
+}
+
+}  // namespace aim
