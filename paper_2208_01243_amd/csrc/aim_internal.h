@@ -126,9 +126,15 @@ int64_t band_tb_slot_words(int W, bool affine, int32_t rows_cap);
 // (traceback slot layout of the 64-diagonal kernel).  band16_fits: whether
 // pairs of length <= max_len provably stay within 16 bits.
 bool band16_fits(int32_t max_len, const Scoring &P, bool affine);
-hipError_t launch_band16(bool affine, const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk,
-                         uint32_t *tb, int64_t tb_slot_words, int32_t rows_cap, int32_t nslots,
-                         hipStream_t s);
+// split: traceback bits kept per chunk of 128 pairs (tb_slot_words per
+// chunk) and walked afterwards by launch_band16_tb; else per workgroup slot,
+// walked in the fill kernel.
+hipError_t launch_band16(bool affine, bool split, const Seqs &S, const Outs &O, const Scoring &P,
+                         const Work &Wk, uint32_t *tb, int64_t tb_slot_words, int32_t rows_cap,
+                         int32_t nslots, hipStream_t s);
+// One workgroup of 128 threads per chunk at a time (persistent, nslots).
+hipError_t launch_band16_tb(bool affine, const Seqs &S, const Outs &O, const Work &Wk, const uint32_t *tb,
+                            int64_t tb_chunk_words, int32_t nslots, hipStream_t s);
 
 // Full-matrix DP, one pair per workgroup.
 hipError_t launch_full(bool affine, const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk,

@@ -166,7 +166,7 @@ struct DeviceGuard {
 
 enum Counter {
   C_T1 = 0, C_T2, C_T3, C_L2, C_L3, C_SPILL, C_SPILL_W,
-  C_W1, C_W1G, C_RL, C_FAIL, C_N0, C_N1, C_N2, C_N3, C_P0, C_P1, C_P2, C_P3,
+  C_W1, C_W1G, C_RL, C_FAIL, C_N0, C_N1, C_N2, C_N3, C_P0, C_P1, C_P2, C_P3, C_TB,
   C_N = 32
 };
 
@@ -522,16 +522,24 @@ aim_status aim_align_batch(aim_context *c, const aim_batch *B, int32_t alg, aim_
     const int64_t chunksA = b16 ? (n + 127) / 128 : chunks;
     int64_t slots = std::min<int64_t>(chunksA, (int64_t)c->cus * std::max(1, tu.band_wpc));
     slots = std::max<int64_t>(1, std::min<int64_t>(slots, budget / (swA * 4)));
-    if ((st = ensure(c, tbA, (size_t)(slots * swA * 4)))) return st;
+    // split fill / traceback when every chunk can keep its own bits
+    const bool split = b16 && R->want_cigar && chunksA * swA * 4 <= budget;
+    if ((st = ensure(c, tbA, (size_t)((split ? chunksA : slots) * swA * 4)))) return st;
     aim::Work W1{order, nullptr, n, cnt + C_T1, as<int32_t>(c->list2), cnt + C_L2, 0};
     {
       Phase ph(c, s, b16 ? "band16" : (w0 == 32 ? "band32" : "band64"));
       if (b16)
-        HIP_TRY(aim::launch_band16(affine, S, O, P, W1, as<uint32_t>(tbA), swA, rows_cap,
+        HIP_TRY(aim::launch_band16(affine, split, S, O, P, W1, as<uint32_t>(tbA), swA, rows_cap,
                                    (int32_t)slots, s));
       else
         HIP_TRY(aim::launch_band(w0, affine, S, O, P, W1, as<uint32_t>(tbA), swA, rows_cap,
                                  (int32_t)slots, s));
+    }
+    if (split) {
+      aim::Work WT{order, nullptr, n, cnt + C_TB, nullptr, nullptr, 0};
+      Phase ph(c, s, "band16_tb");
+      HIP_TRY(aim::launch_band16_tb(affine, S, O, WT, as<uint32_t>(tbA), swA,
+                                    (int32_t)std::min<int64_t>(chunksA, (int64_t)c->cus * 8), s));
     }
     int32_t *full_list = as<int32_t>(c->list2);
     int32_t *full_count = cnt + C_L2;

@@ -25,6 +25,7 @@ namespace {
 
 typedef short s16x2 __attribute__((ext_vector_type(2)));
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int W = 32;
 constexpr int32_t VMAX = 32000;
@@ -41,12 +42,91 @@ __device__ __forceinline__ uint32_t push_sign(uint32_t acc, s16x2 d) {
   return __builtin_bit_cast(uint32_t, a) | (U(d) & 0x80008000u);
 }
 
+// Traceback of one pair (half h of the lane's packed words) over the bits of
+// its wavefront's rows.
 template <bool AFF>
+__device__ __forceinline__ int32_t walk16(const uint32_t *tb, int lane, int h, int32_t m, int32_t n,
+                                         int32_t bstar, const uint64_t *pat, const uint64_t *txt,
+                                         const Outs &O, int64_t p) {
+  constexpr int NP = AFF ? 4 : 2;
+  int32_t i = m, j = n, b = bstar, st = 0;
+  uint32_t cur_op = 0xffu, cur_len = 0;
+  int32_t nr = 0;
+  RunSink sink;
+  sink.begin(O, p);
+  int64_t pq = -1, tq = -1;
+  uint64_t pw = 0, tw = 0;
+  int32_t rowi = -1;
+  uint32_t rw[NP][2];
+  auto put = [&](uint32_t op, uint32_t len) {
+    if (op == cur_op) {
+      cur_len += len;
+    } else {
+      if (cur_len) {
+        sink.put(nr, (cur_len << 4) | cur_op, (int64_t)i + j + 1);
+        ++nr;
+      }
+      cur_op = op;
+      cur_len = len;
+    }
+  };
+  const int sh = 16 * h;
+  while (i > 0 && j > 0) {
+    if (rowi != i) {
+      const uint32_t *row = tb + ((int64_t)i * NP * 2) * 64 + lane;
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+        rw[q][0] = row[(q * 2) * 64];
+        rw[q][1] = row[(q * 2 + 1) * 64];
+      }
+      rowi = i;
+    }
+    uint32_t bq[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) bq[q] = ((b >> 4) ? rw[q][1] : rw[q][0]) >> (sh + (b & 15)) & 1u;
+    if (st == 0) {
+      if (bq[0]) {
+        if (((i - 1) >> 5) != pq) { pq = (i - 1) >> 5; pw = pat[pq]; }
+        if (((j - 1) >> 5) != tq) { tq = (j - 1) >> 5; tw = txt[tq]; }
+        const uint32_t a = (uint32_t)(pw >> (2 * ((i - 1) & 31))) & 3u;
+        const uint32_t c = (uint32_t)(tw >> (2 * ((j - 1) & 31))) & 3u;
+        put(a == c ? OP_EQ : OP_X, 1);
+        --i;
+        --j;
+      } else if (!AFF) {
+        if (bq[1]) { put(OP_D, 1); --j; --b; }
+        else { put(OP_I, 1); --i; ++b; }
+      } else {
+        st = bq[1] ? 2 : 1;
+      }
+    } else if (st == 1) {
+      put(OP_I, 1);
+      st = bq[2] ? 1 : 0;
+      --i;
+      ++b;
+    } else {
+      put(OP_D, 1);
+      st = bq[3] ? 2 : 0;
+      --j;
+      --b;
+    }
+  }
+  if (i > 0) put(OP_I, (uint32_t)i);
+  if (j > 0) put(OP_D, (uint32_t)j);
+  put(0xfu, 0);
+  sink.finish();
+  return nr;
+}
+
+// SPLIT: the traceback bits of chunk c (128 pairs) go to a region of their
+// own and the traceback runs in k_band16_tb; accepted pairs are marked with
+// nruns = -1 until then.  Otherwise a wavefront reuses one slot and walks its
+// pairs itself.
+template <bool AFF, bool SPLIT>
 __global__ __launch_bounds__(64) void k_band16(Seqs Sq, Outs O, Scoring P, Work Wk, uint32_t *tb_all,
                                               int64_t tb_slot_words, int32_t rows_cap) {
   constexpr int NP = AFF ? 4 : 2;
   const int lane = threadIdx.x;
-  uint32_t *tb = tb_all + (int64_t)blockIdx.x * tb_slot_words;
   const int32_t x = P.x, o = P.o, e = P.e, oe = P.o + P.e;
   const int32_t hoff = AFF ? oe : e;
   const int64_t count = Wk.count ? (int64_t)(*(volatile const int32_t *)Wk.count) : Wk.n;
@@ -57,6 +137,7 @@ __global__ __launch_bounds__(64) void k_band16(Seqs Sq, Outs O, Scoring P, Work 
     if (lane == 0) chunk = atomicAdd(Wk.counter, 1);
     chunk = __shfl(chunk, 0);
     if ((int64_t)chunk * 128 >= count) break;
+    uint32_t *tb = tb_all + (SPLIT ? (int64_t)chunk : (int64_t)blockIdx.x) * tb_slot_words;
 
     int64_t p[2];
     int32_t m[2], n[2], kmin[2], bstar[2];
@@ -219,7 +300,7 @@ __global__ __launch_bounds__(64) void k_band16(Seqs Sq, Outs O, Scoring P, Work 
           accept[h] = true;
           O.score[p[h]] = score[h];
           O.status[p[h]] = ST_ALIGNED;
-          O.nruns[p[h]] = 0;
+          O.nruns[p[h]] = (SPLIT && P.want_cigar) ? -1 : 0;
         }
       } else if (P.max_score >= 0 && LB > P.max_score) {
         O.score[p[h]] = -1;
@@ -227,6 +308,8 @@ __global__ __launch_bounds__(64) void k_band16(Seqs Sq, Outs O, Scoring P, Work 
         O.nruns[p[h]] = 0;
       } else {
         esc[h] = true;
+        // the split traceback must not take a stale -1 for its mark
+        if (SPLIT) O.nruns[p[h]] = 0;
       }
     }
     if (Wk.next_idx) {
@@ -235,79 +318,148 @@ __global__ __launch_bounds__(64) void k_band16(Seqs Sq, Outs O, Scoring P, Work 
     }
     if (!P.want_cigar) continue;
 
+    if (SPLIT) continue;
     // ---- traceback, pair A then pair B of this lane ----
+#pragma unroll 1
     for (int h = 0; h < 2; ++h) {
       if (!accept[h]) continue;
-      int32_t i = m[h], j = n[h], b = bstar[h], st = 0;
-      uint32_t cur_op = 0xffu, cur_len = 0;
-      int32_t nr = 0;
-      RunSink sink;
-      sink.begin(O, p[h]);
-      int64_t pq = -1, tq = -1;
-      uint64_t pw = 0, tw = 0;
-      int32_t rowi = -1;
-      uint32_t rw[NP][2];
-      auto put = [&](uint32_t op, uint32_t len) {
-        if (op == cur_op) {
-          cur_len += len;
-        } else {
-          if (cur_len) {
-            sink.put(nr, (cur_len << 4) | cur_op, (int64_t)i + j + 1);
-            ++nr;
-          }
-          cur_op = op;
-          cur_len = len;
+      O.nruns[p[h]] = walk16<AFF>(tb, lane, h, m[h], n[h], bstar[h], pat[h], txt[h], O, p[h]);
+    }
+  }
+}
+
+// Traceback of the pairs the split fill accepted.  A workgroup of two
+// wavefronts takes one chunk of 128 pairs; wavefront h walks the pairs held in
+// half h of the packed words.  The chunk's rows are staged in LDS, TB_ROWS at
+// a time from its last row down, with full-line loads, and every lane walks
+// until its path leaves the staged rows; the sequence words the staged rows
+// can touch are loaded into registers beside them.  A lane's row index only
+// decreases, so each row is read from HBM once.
+constexpr int TB_ROWS = 8;
+
+template <bool AFF>
+__global__ __launch_bounds__(128) void k_band16_tb(Seqs Sq, Outs O, Work Wk, const uint32_t *tb_all,
+                                                  int64_t tb_chunk_words) {
+  constexpr int NP = AFF ? 4 : 2;
+  constexpr int ROW = NP * 2 * 64;  // words per row
+  __shared__ u32x4 stage[TB_ROWS * ROW / 4];
+  __shared__ int32_t s_chunk, s_top;
+  const uint32_t *lds = reinterpret_cast<const uint32_t *>(stage);
+  const int tid = threadIdx.x, lane = tid & 63, h = tid >> 6;
+  const int64_t count = Wk.count ? (int64_t)(*(volatile const int32_t *)Wk.count) : Wk.n;
+  for (;;) {
+    if (tid == 0) {
+      s_chunk = atomicAdd(Wk.counter, 1);
+      s_top = 0;
+    }
+    __syncthreads();
+    const int64_t chunk = s_chunk;
+    if (chunk * 128 >= count) break;
+    const int64_t li = chunk * 128 + 64 * h + lane;
+    bool act = false;
+    int64_t p = 0;
+    if (li < count) {
+      p = Wk.idx ? (int64_t)Wk.idx[li] : li;
+      act = O.nruns[p] == -1;
+    }
+    int32_t m = 0, n = 0, kmin = 0;
+    const uint64_t *pat = Sq.pat, *txt = Sq.txt;
+    if (act) {
+      m = Sq.pat_len[p];
+      n = Sq.txt_len[p];
+      const int32_t d = n - m, ad = d < 0 ? -d : d;
+      kmin = min(0, d) - (W - 1 - ad) / 2;
+      pat += Sq.pat_off[p];
+      txt += Sq.txt_off[p];
+    }
+    const int32_t wm = dev::wave_max(m);
+    if (lane == 0) atomicMax(&s_top, wm);
+    __syncthreads();
+    const int32_t top = s_top;
+    const uint32_t *src = tb_all + chunk * tb_chunk_words;
+    const int64_t pnw = (m + 31) >> 5, tnw = (n + 31) >> 5;
+
+    int32_t i = m, j = n, b = n - m - kmin, st = 0;
+    uint32_t cur_op = 0xffu, cur_len = 0;
+    int32_t nr = 0;
+    RunSink sink;
+    if (act) sink.begin(O, p);
+    auto put = [&](uint32_t op, uint32_t len) {
+      if (op == cur_op) {
+        cur_len += len;
+      } else {
+        if (cur_len) {
+          sink.put(nr, (cur_len << 4) | cur_op, (int64_t)i + j + 1);
+          ++nr;
         }
-      };
-      const int sh = 16 * h;
-      while (i > 0 && j > 0) {
-        if (rowi != i) {
-          const uint32_t *row = tb + ((int64_t)i * NP * 2) * 64 + lane;
-#pragma unroll
-          for (int q = 0; q < NP; ++q) {
-            rw[q][0] = row[(q * 2) * 64];
-            rw[q][1] = row[(q * 2 + 1) * 64];
-          }
-          rowi = i;
-        }
-        uint32_t bq[NP];
-#pragma unroll
-        for (int q = 0; q < NP; ++q) bq[q] = ((b >> 4) ? rw[q][1] : rw[q][0]) >> (sh + (b & 15)) & 1u;
-        if (st == 0) {
-          if (bq[0]) {
-            if (((i - 1) >> 5) != pq) { pq = (i - 1) >> 5; pw = pat[h][pq]; }
-            if (((j - 1) >> 5) != tq) { tq = (j - 1) >> 5; tw = txt[h][tq]; }
-            const uint32_t a = (uint32_t)(pw >> (2 * ((i - 1) & 31))) & 3u;
-            const uint32_t c = (uint32_t)(tw >> (2 * ((j - 1) & 31))) & 3u;
-            put(a == c ? OP_EQ : OP_X, 1);
-            --i;
-            --j;
-          } else if (!AFF) {
-            if (bq[1]) { put(OP_D, 1); --j; --b; }
-            else { put(OP_I, 1); --i; ++b; }
-          } else {
-            st = bq[1] ? 2 : 1;
-          }
-        } else if (st == 1) {
-          put(OP_I, 1);
-          st = bq[2] ? 1 : 0;
-          --i;
-          ++b;
-        } else {
-          put(OP_D, 1);
-          st = bq[3] ? 2 : 0;
-          --j;
-          --b;
-        }
+        cur_op = op;
+        cur_len = len;
       }
+    };
+    // rows lo+1 .. hi of the block below `hi` go through registers: the
+    // next block's loads are in flight while the lanes walk this one
+    constexpr int PRE = TB_ROWS * ROW / 4 / 128;
+    u32x4 pre[PRE];
+#define AIM_TB_FETCH(BHI)                                                              \
+  do {                                                                                 \
+    const int32_t bhi_ = (BHI), blo_ = max(bhi_ - TB_ROWS, 0);                         \
+    const int nq_ = (bhi_ - blo_) * (ROW / 4);                                         \
+    const u32x4 *g_ = reinterpret_cast<const u32x4 *>(src + (int64_t)(blo_ + 1) * ROW); \
+    _Pragma("unroll") for (int k = 0; k < PRE; ++k) pre[k] = g_[min(tid + 128 * k, nq_ - 1)]; \
+  } while (0)
+    if (top > 0) AIM_TB_FETCH(top);
+#pragma unroll 1
+    for (int32_t hi = top; hi > 0; hi -= TB_ROWS) {
+      const int32_t lo = max(hi - TB_ROWS, 0);  // rows lo+1 .. hi
+      // the whole stage is written; entries past nq (copies of the block's
+      // last quad) belong to no staged row and are never read
+#pragma unroll
+      for (int k = 0; k < PRE; ++k) stage[tid + 128 * k] = pre[k];
+      // pattern bases lo .. hi-1; text bases lo+kmin .. hi-1+kmin+W-1
+      const int64_t pq0 = lo >> 5, tq0 = ((int64_t)lo + kmin) >> 5;
+      const uint64_t pw0 = dev::ld_word(pat, pnw, pq0), pw1 = dev::ld_word(pat, pnw, pq0 + 1);
+      const uint64_t tw0 = dev::ld_word(txt, tnw, tq0), tw1 = dev::ld_word(txt, tnw, tq0 + 1),
+                     tw2 = dev::ld_word(txt, tnw, tq0 + 2);
+      __syncthreads();
+      AIM_TB_FETCH(lo > 0 ? lo : hi);
+      // One op per iteration, chosen with selects: at a cell in state H
+      // either the diagonal, or (entering a gap) the gap run the D/I plane
+      // names, continued while the cell's extension plane says so.
+      while (act && i > lo && j > 0) {
+        const uint32_t *rw = lds + ((i - lo - 1) * NP * 2 + ((b >> 4) & 1)) * 64 + lane;
+        const int sh = 16 * h + (b & 15);
+        const uint32_t bd = (rw[0] >> sh) & 1u, b1 = (rw[128] >> sh) & 1u;
+        uint32_t b2 = 0, b3 = 0;
+        if (AFF) {
+          b2 = (rw[256] >> sh) & 1u;
+          b3 = (rw[384] >> sh) & 1u;
+        }
+        const int32_t g = (st == 0 && !bd) ? (b1 ? 2 : 1) : st;  // 0 diag, 1 I, 2 D
+        const uint64_t pw = (((i - 1) >> 5) == pq0) ? pw0 : pw1;
+        const int64_t tq = (int64_t)(j - 1) >> 5;
+        const uint64_t tw = tq == tq0 ? tw0 : (tq == tq0 + 1 ? tw1 : tw2);
+        const uint32_t ca = (uint32_t)(pw >> (2 * ((i - 1) & 31))) & 3u;
+        const uint32_t cb = (uint32_t)(tw >> (2 * ((j - 1) & 31))) & 3u;
+        const uint32_t op = g == 0 ? (ca == cb ? OP_EQ : OP_X) : (g == 1 ? OP_I : OP_D);
+        put(op, 1);
+        st = AFF ? (g == 1 ? (b2 ? 1 : 0) : (g == 2 ? (b3 ? 2 : 0) : 0)) : 0;
+        i -= g != 2;
+        j -= g != 1;
+        b += g == 1 ? 1 : (g == 2 ? -1 : 0);
+      }
+      __syncthreads();
+    }
+    if (act) {
       if (i > 0) put(OP_I, (uint32_t)i);
       if (j > 0) put(OP_D, (uint32_t)j);
       put(0xfu, 0);
       sink.finish();
-      O.nruns[p[h]] = nr;
+      O.nruns[p] = nr;
     }
+    __syncthreads();
   }
 }
+#undef AIM_TB_FETCH
 
 }  // namespace
 
@@ -317,14 +469,28 @@ bool band16_fits(int32_t max_len, const Scoring &P, bool affine) {
              2 * (int64_t)P.x <= VMAX;
 }
 
-hipError_t launch_band16(bool affine, const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk,
-                         uint32_t *tb, int64_t tb_slot_words, int32_t rows_cap, int32_t nslots,
-                         hipStream_t s) {
+hipError_t launch_band16(bool affine, bool split, const Seqs &S, const Outs &O, const Scoring &P,
+                         const Work &Wk, uint32_t *tb, int64_t tb_slot_words, int32_t rows_cap,
+                         int32_t nslots, hipStream_t s) {
   dim3 grid(nslots), block(64);
-  if (affine)
-    hipLaunchKernelGGL((k_band16<true>), grid, block, 0, s, S, O, P, Wk, tb, tb_slot_words, rows_cap);
+  if (affine && split)
+    hipLaunchKernelGGL((k_band16<true, true>), grid, block, 0, s, S, O, P, Wk, tb, tb_slot_words, rows_cap);
+  else if (affine)
+    hipLaunchKernelGGL((k_band16<true, false>), grid, block, 0, s, S, O, P, Wk, tb, tb_slot_words, rows_cap);
+  else if (split)
+    hipLaunchKernelGGL((k_band16<false, true>), grid, block, 0, s, S, O, P, Wk, tb, tb_slot_words, rows_cap);
   else
-    hipLaunchKernelGGL((k_band16<false>), grid, block, 0, s, S, O, P, Wk, tb, tb_slot_words, rows_cap);
+    hipLaunchKernelGGL((k_band16<false, false>), grid, block, 0, s, S, O, P, Wk, tb, tb_slot_words, rows_cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_band16_tb(bool affine, const Seqs &S, const Outs &O, const Work &Wk, const uint32_t *tb,
+                            int64_t tb_chunk_words, int32_t nslots, hipStream_t s) {
+  dim3 grid(nslots), block(128);
+  if (affine)
+    hipLaunchKernelGGL((k_band16_tb<true>), grid, block, 0, s, S, O, Wk, tb, tb_chunk_words);
+  else
+    hipLaunchKernelGGL((k_band16_tb<false>), grid, block, 0, s, S, O, Wk, tb, tb_chunk_words);
   return hipGetLastError();
 }
 
