@@ -112,6 +112,10 @@ struct aim_context {
   std::map<std::pair<int32_t, int32_t>, Tune> tunes;  // (alg, length bucket) -> tune
   const Tune *force = nullptr;  // set while the autotuner tries a candidate
   bool capturing = false;       // inside a hipGraph capture: no timing events
+  // second stream (default priority) for the escalation tiers, which run
+  // beside the first tier's traceback; fork / join through the two events
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int64_t generation = 0;       // bumped whenever scratch is reallocated
   Buf order, hist;
   Buf flags, pflag, tflag, pat2, txt2, pat2off, txt2off, nruns, slot, tb32, tb64, full, list2,
@@ -345,6 +349,17 @@ aim_status aim_create(aim_context **ctx, int32_t device, const aim_options *opt)
     if (prop.multiProcessorCount > 0) c->cus = prop.multiProcessorCount;
     c->arch = prop.gcnArchName;
   }
+  {
+    DeviceGuard g(device);
+    if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+      if (c->aux) (void)hipStreamDestroy(c->aux);
+      if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+      delete c;
+      return fail(AIM_ERR_HIP, "could not create the context's stream and events");
+    }
+  }
   *ctx = c;
   return AIM_OK;
 }
@@ -359,6 +374,9 @@ void aim_destroy(aim_context *c) {
                 &c->warena2, &c->warena3, &c->wneed, &c->wlists, &c->pool, &c->pooloff};
   for (Buf *b : all)
     if (b->p) (void)hipFree(b->p);
+  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  if (c->aux) (void)hipStreamDestroy(c->aux);
   delete c;
 }
 
@@ -492,7 +510,7 @@ aim_status aim_align_batch(aim_context *c, const aim_batch *B, int32_t alg, aim_
   const int64_t budget = c->opt.scratch_limit / 4;
   const bool plain = c->opt.kernel == AIM_KERNEL_PLAIN;
 
-  auto run_full = [&](const aim::Work &Wk, int64_t max_items) -> aim_status {
+  auto run_full = [&](const aim::Work &Wk, int64_t max_items, hipStream_t s) -> aim_status {
     const int64_t sw = aim::full_slot_words(L);
     int64_t slots = std::min<int64_t>(max_items, (int64_t)c->cus * 8);
     slots = std::min<int64_t>(slots, std::max<int64_t>(1, budget / (sw * 4)));
@@ -508,7 +526,7 @@ aim_status aim_align_batch(aim_context *c, const aim_batch *B, int32_t alg, aim_
     if ((st = run_wfa(c, S, O, P, n, L, plain, cnt, order, tu, s))) return st;
   } else if (plain) {
     aim::Work W1{nullptr, nullptr, n, cnt + C_T1, nullptr, nullptr, 0};
-    if ((st = run_full(W1, n))) return st;
+    if ((st = run_full(W1, n, s))) return st;
   } else {
     // tier 1: 32-diagonal band, one pair per lane (64 when tuned so)
     const int32_t rows_cap = L + 1;
@@ -535,11 +553,14 @@ aim_status aim_align_batch(aim_context *c, const aim_batch *B, int32_t alg, aim_
         HIP_TRY(aim::launch_band(w0, affine, S, O, P, W1, as<uint32_t>(tbA), swA, rows_cap,
                                  (int32_t)slots, s));
     }
+    // Tier 1's traceback and tiers 2 and 3 work on disjoint pairs, so the
+    // traceback runs on the second stream beside them.  Tiers 2 and 3 stay on
+    // `s` right behind the fill: their few long-running wavefronts are then
+    // dispatched first and hold their slots while the traceback takes the rest.
+    hipStream_t s2 = c->aux;
     if (split) {
-      aim::Work WT{order, nullptr, n, cnt + C_TB, nullptr, nullptr, 0};
-      Phase ph(c, s, "band16_tb");
-      HIP_TRY(aim::launch_band16_tb(affine, S, O, WT, as<uint32_t>(tbA), swA,
-                                    (int32_t)std::min<int64_t>(chunksA, (int64_t)c->cus * 8), s));
+      HIP_TRY(hipEventRecord(c->ev_fork, s));
+      HIP_TRY(hipStreamWaitEvent(s2, c->ev_fork, 0));
     }
     int32_t *full_list = as<int32_t>(c->list2);
     int32_t *full_count = cnt + C_L2;
@@ -557,9 +578,19 @@ aim_status aim_align_batch(aim_context *c, const aim_batch *B, int32_t alg, aim_
       full_list = as<int32_t>(c->list3);
       full_count = cnt + C_L3;
     }
+    if (split) {
+      aim::Work WT{order, nullptr, n, cnt + C_TB, nullptr, nullptr, 0};
+      Phase ph(c, s2, "band16_tb");
+      HIP_TRY(aim::launch_band16_tb(affine, S, O, WT, as<uint32_t>(tbA), swA,
+                                    (int32_t)std::min<int64_t>(chunksA, (int64_t)c->cus * 8), s2));
+    }
     // tier 3: full matrix
     aim::Work W3{full_list, full_count, n, cnt + C_T3, nullptr, nullptr, 0};
-    if ((st = run_full(W3, n))) return st;
+    if ((st = run_full(W3, n, s))) return st;
+    if (split) {
+      HIP_TRY(hipEventRecord(c->ev_join, s2));
+      HIP_TRY(hipStreamWaitEvent(s, c->ev_join, 0));
+    }
   }
 
   if (!R->want_cigar) {
@@ -588,7 +619,7 @@ aim_status aim_align_batch(aim_context *c, const aim_batch *B, int32_t alg, aim_
     HIP_TRY(aim::launch_wfa_trace(S, O, P, WS, WL, as<int32_t>(c->warena3), pl.arena_slots[3],
                                   pl.threads[3], s));
   } else {
-    if ((st = run_full(WS, n))) return st;
+    if ((st = run_full(WS, n, s))) return st;
   }
   return AIM_OK;
 }
