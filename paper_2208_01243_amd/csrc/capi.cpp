@@ -445,7 +445,9 @@ aim_status aim_align_batch(aim_context *c, const aim_batch *B, int32_t alg, aim_
   int64_t run_bound = 2 * (int64_t)L + 1;
   const int32_t cmin = std::min(pen.mismatch, (alg == AIM_NW_LINEAR ? 0 : pen.gap_open) + pen.gap_extend);
   if (max_score >= 0) run_bound = std::min<int64_t>(run_bound, 2 * (int64_t)(max_score / cmin) + 1);
-  const int32_t slot_cap = (int32_t)std::max<int64_t>(1, std::min<int64_t>(run_bound, SLOT_CAP));
+  // a multiple of 4 words, so the compaction reads slots with 16-byte loads
+  const int32_t slot_cap =
+      (int32_t)((std::max<int64_t>(1, std::min<int64_t>(run_bound, SLOT_CAP)) + 3) & ~int64_t(3));
   if (R->want_cigar && (st = ensure(c, c->slot, (size_t)n * slot_cap * sizeof(uint32_t)))) return st;
   int32_t *cnt = as<int32_t>(c->counters);
   HIP_TRY(aim::launch_fill_i32(cnt, 0, C_N, s));

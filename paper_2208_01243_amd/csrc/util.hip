@@ -166,11 +166,17 @@ __global__ void k_cut(int64_t n, const int64_t *excl, int64_t cap, unsigned long
   }
 }
 
-__global__ void k_scatter(int64_t n, const int64_t *excl, const unsigned long long *tw_p,
-                          const int32_t *nruns, const uint32_t *slot, int32_t slot_cap,
-                          const uint32_t *pool, const int64_t *pool_off, int64_t *cigar_off,
-                          uint32_t *cigar, int32_t *spill_idx, int32_t *spill_count,
-                          int8_t *status) {
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// One pair per thread.  Slots hold a pair's runs last-op-first; slot_cap is a
+// multiple of 4 and slots are 16-byte aligned, so each 16-byte load stays in
+// the pair's slot.
+__global__ __launch_bounds__(256) void k_scatter(
+    int64_t n, const int64_t *__restrict__ excl, const unsigned long long *__restrict__ tw_p,
+    const int32_t *__restrict__ nruns, const uint32_t *__restrict__ slot, int32_t slot_cap,
+    const uint32_t *__restrict__ pool, const int64_t *__restrict__ pool_off,
+    int64_t *__restrict__ cigar_off, uint32_t *__restrict__ cigar, int32_t *spill_idx,
+    int32_t *spill_count, int8_t *__restrict__ status) {
   const int64_t tw = (int64_t)*tw_p;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
@@ -190,9 +196,16 @@ __global__ void k_scatter(int64_t n, const int64_t *excl, const unsigned long lo
       continue;
     }
     const uint32_t *src = slot + i * (int64_t)slot_cap;
+    uint32_t *dst = cigar + a + r - 1;  // run k goes to dst[-k]
     const int32_t r0 = r < slot_cap ? r : slot_cap;
-    for (int32_t k = 0; k < r0; ++k) cigar[a + r - 1 - k] = src[k];
-    for (int32_t k = r0; k < r; ++k) cigar[a + r - 1 - k] = pool[pb + (k - slot_cap)];
+    for (int32_t k = 0; k < r0; k += 4) {
+      const u32x4 v = *reinterpret_cast<const u32x4 *>(src + k);
+      dst[-k] = v.x;
+      if (k + 1 < r0) dst[-k - 1] = v.y;
+      if (k + 2 < r0) dst[-k - 2] = v.z;
+      if (k + 3 < r0) dst[-k - 3] = v.w;
+    }
+    for (int32_t k = r0; k < r; ++k) dst[-k] = pool[pb + (k - slot_cap)];
   }
 }
 
