@@ -12,11 +12,14 @@
 // plus 2 (o + e) + x (E, F and the diagonal candidate on top of H + o + e);
 // pairs above the bound go to the 32-bit kernels.  Differences of two values
 // in [0, 32767] never wrap, so the sign bit of each 16-bit difference is the
-// traceback decision; sign bits are shifted into the top of each half, so
-// after 16 cells bit c of a half is cell c.
+// traceback decision.  One byte permute gathers the sign bytes of two planes'
+// differences (four bit streams: plane pair x pair A/B) into one word, and a
+// shift plus a bit-field insert appends them to an accumulator, so after a
+// group of 8 cells bit c of each byte is cell c of the group.
 //
-// Traceback words: row i, plane q, cell group h (cells 16h..16h+15) at
-// ((i * planes + q) * 2 + h) * 64 + lane, pair A in bits 0..15, B in 16..31.
+// Traceback words: row i, cell group g (cells 8g..8g+7), plane pair pp
+// (planes 2pp and 2pp+1) at ((i * 2 * planes) + g * planes / 2 + pp) * 64 +
+// lane; byte (q & 1) * 2 + h holds plane q of pair h (A = 0, B = 1).
 #include "aim_internal.h"
 #include "dev_util.h"
 
@@ -36,10 +39,23 @@ __device__ __forceinline__ s16x2 S(uint32_t v) { return __builtin_bit_cast(s16x2
 __device__ __forceinline__ s16x2 adds(s16x2 a, s16x2 b) { return __builtin_elementwise_add_sat(a, b); }
 __device__ __forceinline__ s16x2 mn(s16x2 a, s16x2 b) { return __builtin_elementwise_min(a, b); }
 __device__ __forceinline__ s16x2 spl(int32_t v) { return (s16x2){(short)v, (short)v}; }
-// shift the sign bit of each half of d into the top of acc's halves
-__device__ __forceinline__ uint32_t push_sign(uint32_t acc, s16x2 d) {
-  const u16x2 a = __builtin_bit_cast(u16x2, acc) >> (u16x2){1, 1};
-  return __builtin_bit_cast(uint32_t, a) | (U(d) & 0x80008000u);
+// a * b + c per half, saturated to the int16 range (v_pk_mad_i16 with clamp;
+// the compiler does not form it from a multiply and a saturating add)
+__device__ __forceinline__ s16x2 mad_sat(s16x2 a, s16x2 b, s16x2 c) {
+  uint32_t r;
+  asm("v_pk_mad_i16 %0, %1, %2, %3 clamp" : "=v"(r) : "v"(U(a)), "v"(U(b)), "v"(U(c)));
+  return S(r);
+}
+// append the sign bits of the halves of d_lo (plane 2pp) and d_hi (plane
+// 2pp+1) at bit 7 of the four bytes of acc, after shifting every byte right
+// by one (the bit a byte takes from the byte above is overwritten)
+__device__ __forceinline__ uint32_t push_signs(uint32_t acc, s16x2 d_lo, s16x2 d_hi) {
+  const uint32_t sg = __builtin_amdgcn_perm(U(d_hi), U(d_lo), 0x07050301u);
+  return (sg & 0x80808080u) | ((acc >> 1) & 0x7f7f7f7fu);
+}
+// bit of plane q, pair h, band cell b in the words of one row (w[g*NP/2+pp])
+__device__ __forceinline__ uint32_t tb_bit(uint32_t w, int q, int h, int b) {
+  return (w >> (((q & 1) * 2 + h) * 8 + (b & 7))) & 1u;
 }
 
 // Traceback of one pair (half h of the lane's packed words) over the bits of
@@ -56,8 +72,6 @@ __device__ __forceinline__ int32_t walk16(const uint32_t *tb, int lane, int h, i
   sink.begin(O, p);
   int64_t pq = -1, tq = -1;
   uint64_t pw = 0, tw = 0;
-  int32_t rowi = -1;
-  uint32_t rw[NP][2];
   auto put = [&](uint32_t op, uint32_t len) {
     if (op == cur_op) {
       cur_len += len;
@@ -70,20 +84,11 @@ __device__ __forceinline__ int32_t walk16(const uint32_t *tb, int lane, int h, i
       cur_len = len;
     }
   };
-  const int sh = 16 * h;
   while (i > 0 && j > 0) {
-    if (rowi != i) {
-      const uint32_t *row = tb + ((int64_t)i * NP * 2) * 64 + lane;
-#pragma unroll
-      for (int q = 0; q < NP; ++q) {
-        rw[q][0] = row[(q * 2) * 64];
-        rw[q][1] = row[(q * 2 + 1) * 64];
-      }
-      rowi = i;
-    }
+    const uint32_t *w = tb + ((int64_t)i * NP * 2 + ((b >> 3) & 3) * (NP / 2)) * 64 + lane;
     uint32_t bq[NP];
 #pragma unroll
-    for (int q = 0; q < NP; ++q) bq[q] = ((b >> 4) ? rw[q][1] : rw[q][0]) >> (sh + (b & 15)) & 1u;
+    for (int q = 0; q < NP; ++q) bq[q] = tb_bit(w[(q >> 1) * 64], q, h, b);
     if (st == 0) {
       if (bq[0]) {
         if (((i - 1) >> 5) != pq) { pq = (i - 1) >> 5; pw = pat[pq]; }
@@ -123,14 +128,14 @@ __device__ __forceinline__ int32_t walk16(const uint32_t *tb, int lane, int h, i
 // nruns = -1 until then.  Otherwise a wavefront reuses one slot and walks its
 // pairs itself.
 template <bool AFF, bool SPLIT>
-__global__ __launch_bounds__(64) void k_band16(Seqs Sq, Outs O, Scoring P, Work Wk, uint32_t *tb_all,
+__global__ __launch_bounds__(64, 3) void k_band16(Seqs Sq, Outs O, Scoring P, Work Wk, uint32_t *tb_all,
                                               int64_t tb_slot_words, int32_t rows_cap) {
   constexpr int NP = AFF ? 4 : 2;
   const int lane = threadIdx.x;
   const int32_t x = P.x, o = P.o, e = P.e, oe = P.o + P.e;
   const int32_t hoff = AFF ? oe : e;
   const int64_t count = Wk.count ? (int64_t)(*(volatile const int32_t *)Wk.count) : Wk.n;
-  const s16x2 vx = spl(x), ve = spl(e), voe = spl(oe), vinf = spl(INF16);
+  const s16x2 vx = spl(x), vxm1 = spl(x - 1), ve = spl(e), voe = spl(oe), vinf = spl(INF16);
 
   for (;;) {
     int chunk = 0;
@@ -222,54 +227,48 @@ __global__ __launch_bounds__(64) void k_band16(Seqs Sq, Outs O, Scoring P, Work 
       // of the low half (pair A) and of the high half (pair B)
       uint32_t X[4] = {(mlo[0] & 0xFFFFu) | (mlo[1] << 16), (mlo[0] >> 16) | (mlo[1] & 0xFFFF0000u),
                        (mhi[0] & 0xFFFFu) | (mhi[1] << 16), (mhi[0] >> 16) | (mhi[1] & 0xFFFF0000u)};
-      uint32_t bits[NP][2];
-#pragma unroll
-      for (int q = 0; q < NP; ++q) bits[q][0] = bits[q][1] = 0u;
+      uint32_t *row = tb + ((int64_t)i * NP * 2) * 64 + lane;
       s16x2 Hsl = vinf, Fl = vinf;
 #pragma unroll
-      for (int b = 0; b < W; ++b) {
-        const int g = b >> 3, hw = b >> 4;
-        const s16x2 mmp = S(X[g] & 0x00010001u);
-        X[g] >>= 2;
-        const s16x2 Hsd = Hs[b];
-        const s16x2 Hsu = (b + 1 < W) ? Hs[b + 1] : vinf;
-        const s16x2 diag = adds(Hsd, mmp * vx);  // H(i-1,j-1) + cost + hoff
-        const s16x2 dg = diag - mmp;              // ... with the match/mismatch tie offset
-        if (AFF) {
-          const s16x2 Eu = (b + 1 < W) ? E[b + 1] : vinf;
-          const s16x2 bE = adds(Eu, ve), Ev = mn(Hsu, bE);
-          const s16x2 bF = adds(Fl, ve), Fv = mn(Hsl, bF);
-          const s16x2 G = mn(Ev, Fv);
-          const s16x2 Gs = adds(G, voe);
-          const s16x2 Hsv = mn(diag, Gs);
-          bits[0][hw] = push_sign(bits[0][hw], dg - Gs);
-          bits[1][hw] = push_sign(bits[1][hw], Fv - Ev);
-          bits[2][hw] = push_sign(bits[2][hw], bE - Hsu);
-          bits[3][hw] = push_sign(bits[3][hw], bF - Hsl);
-          Hs[b] = Hsv;
-          E[b] = Ev;
-          Hsl = Hsv;
-          Fl = Fv;
-        } else {
-          const s16x2 G = mn(Hsu, Hsl);
-          const s16x2 Gs = adds(G, ve);
-          const s16x2 Hsv = mn(diag, Gs);
-          bits[0][hw] = push_sign(bits[0][hw], dg - Gs);
-          bits[1][hw] = push_sign(bits[1][hw], Hsl - Hsu);
-          Hs[b] = Hsv;
-          Hsl = Hsv;
+      for (int g = 0; g < 4; ++g) {
+        uint32_t acc01 = 0u, acc23 = 0u;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          const int b = 8 * g + c;
+          const s16x2 mmp = S((X[g] >> (2 * c)) & 0x00010001u);
+          const s16x2 Hsd = Hs[b];
+          const s16x2 Hsu = (b + 1 < W) ? Hs[b + 1] : vinf;
+          const s16x2 diag = mad_sat(mmp, vx, Hsd);  // H(i-1,j-1) + cost + hoff
+          const s16x2 dg = mmp * vxm1 + Hsd;         // ... with the match/mismatch tie offset
+          if (AFF) {
+            const s16x2 Eu = (b + 1 < W) ? E[b + 1] : vinf;
+            const s16x2 bE = adds(Eu, ve), Ev = mn(Hsu, bE);
+            const s16x2 bF = adds(Fl, ve), Fv = mn(Hsl, bF);
+            const s16x2 G = mn(Ev, Fv);
+            const s16x2 Gs = adds(G, voe);
+            const s16x2 Hsv = mn(diag, Gs);
+            acc01 = push_signs(acc01, dg - Gs, Fv - Ev);
+            acc23 = push_signs(acc23, bE - Hsu, bF - Hsl);
+            Hs[b] = Hsv;
+            E[b] = Ev;
+            Hsl = Hsv;
+            Fl = Fv;
+          } else {
+            const s16x2 G = mn(Hsu, Hsl);
+            const s16x2 Gs = adds(G, ve);
+            const s16x2 Hsv = mn(diag, Gs);
+            acc01 = push_signs(acc01, dg - Gs, Hsl - Hsu);
+            Hs[b] = Hsv;
+            Hsl = Hsv;
+          }
+          // keep each cell's bit packing next to its arithmetic (see the
+          // 32-bit band kernel); the empty asm emits nothing
+          asm volatile("" : "+v"(acc01));
+          if (AFF) asm volatile("" : "+v"(acc23));
         }
-        // keep each cell's bit packing next to its arithmetic (see the
-        // 32-bit band kernel); the empty asm emits nothing
-#pragma unroll
-        for (int q = 0; q < NP; ++q) asm volatile("" : "+v"(bits[q][hw]));
-      }
-      if (P.want_cigar) {
-        uint32_t *row = tb + ((int64_t)i * NP * 2) * 64 + lane;
-#pragma unroll
-        for (int q = 0; q < NP; ++q) {
-          row[(q * 2) * 64] = bits[q][0];
-          row[(q * 2 + 1) * 64] = bits[q][1];
+        if (P.want_cigar) {
+          row[(g * (NP / 2)) * 64] = acc01;
+          if (AFF) row[(g * (NP / 2) + 1) * 64] = acc23;
         }
       }
       const bool cap0 = run[0] && i == m[0], cap1 = run[1] && i == m[1];
@@ -426,13 +425,14 @@ __global__ __launch_bounds__(128) void k_band16_tb(Seqs Sq, Outs O, Work Wk, con
       // either the diagonal, or (entering a gap) the gap run the D/I plane
       // names, continued while the cell's extension plane says so.
       while (act && i > lo && j > 0) {
-        const uint32_t *rw = lds + ((i - lo - 1) * NP * 2 + ((b >> 4) & 1)) * 64 + lane;
-        const int sh = 16 * h + (b & 15);
-        const uint32_t bd = (rw[0] >> sh) & 1u, b1 = (rw[128] >> sh) & 1u;
+        const uint32_t *rw = lds + ((i - lo - 1) * NP * 2 + ((b >> 3) & 3) * (NP / 2)) * 64 + lane;
+        const uint32_t w01 = rw[0];
+        const uint32_t bd = tb_bit(w01, 0, h, b), b1 = tb_bit(w01, 1, h, b);
         uint32_t b2 = 0, b3 = 0;
         if (AFF) {
-          b2 = (rw[256] >> sh) & 1u;
-          b3 = (rw[384] >> sh) & 1u;
+          const uint32_t w23 = rw[64];
+          b2 = tb_bit(w23, 2, h, b);
+          b3 = tb_bit(w23, 3, h, b);
         }
         const int32_t g = (st == 0 && !bd) ? (b1 ? 2 : 1) : st;  // 0 diag, 1 I, 2 D
         const uint64_t pw = (((i - 1) >> 5) == pq0) ? pw0 : pw1;
