@@ -136,6 +136,21 @@ hipError_t launch_band16(bool affine, bool split, const Seqs &S, const Outs &O, 
 hipError_t launch_band16_tb(bool affine, const Seqs &S, const Outs &O, const Work &Wk, const uint32_t *tb,
                             int64_t tb_chunk_words, int32_t nslots, hipStream_t s);
 
+// Banded DP with 64 diagonals, one pair per 32 lanes along the anti-diagonal
+// (two pairs per wavefront).  Traceback bits of chunk c (the two pairs of
+// list positions 2c, 2c+1) in chunk_words words at tb + c * chunk_words, for
+// c < chunks_cap; pairs of later chunks are escalated when CIGARs are wanted.
+// Accepted pairs get nruns = -1 until launch_diag_tb walks them.
+int64_t diag_chunk_words(bool affine, int32_t max_len);
+hipError_t launch_diag(bool affine, const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk,
+                       uint32_t *tb, int64_t chunk_words, int64_t chunks_cap, int32_t nslots,
+                       hipStream_t s);
+// Walk of the pairs of the same list (same Work idx / count) with nruns == -1,
+// diag_tb_pairs_per_wave() list positions per wavefront.
+int32_t diag_tb_pairs_per_wave();
+hipError_t launch_diag_tb(bool affine, const Seqs &S, const Outs &O, const Work &Wk, const uint32_t *tb,
+                          int64_t chunk_words, int32_t nslots, hipStream_t s);
+
 // Full-matrix DP, one pair per workgroup.
 hipError_t launch_full(bool affine, const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk,
                        uint32_t *scratch, int64_t slot_words, int32_t max_len, int32_t nslots,

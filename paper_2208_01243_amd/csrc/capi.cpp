@@ -170,7 +170,7 @@ struct DeviceGuard {
 
 enum Counter {
   C_T1 = 0, C_T2, C_T3, C_L2, C_L3, C_SPILL, C_SPILL_W,
-  C_W1, C_W1G, C_RL, C_FAIL, C_N0, C_N1, C_N2, C_N3, C_P0, C_P1, C_P2, C_P3, C_TB,
+  C_W1, C_W1G, C_RL, C_FAIL, C_N0, C_N1, C_N2, C_N3, C_P0, C_P1, C_P2, C_P3, C_TB, C_DTB,
   C_N = 32
 };
 
@@ -567,24 +567,37 @@ aim_status aim_align_batch(aim_context *c, const aim_batch *B, int32_t alg, aim_
     int32_t *full_list = as<int32_t>(c->list2);
     int32_t *full_count = cnt + C_L2;
     if (w0 == 32) {
-      // tier 2: 64-diagonal band for the pairs tier 1 could not decide
-      const int64_t sw64 = aim::band_tb_slot_words(64, affine, rows_cap);
-      int64_t slots2 = std::min<int64_t>(chunks, (int64_t)c->cus * 4);
-      slots2 = std::max<int64_t>(1, std::min<int64_t>(slots2, budget / (sw64 * 4)));
-      if ((st = ensure(c, c->tb64, (size_t)(slots2 * sw64 * 4)))) return st;
-      Phase ph2(c, s, "band64");
+      // tier 2: 64-diagonal band for the pairs tier 1 could not decide, one
+      // pair per 32 lanes along the anti-diagonal, then a walk per lane
+      const int64_t cw = aim::diag_chunk_words(affine, L);
+      const int64_t need = (n + 1) / 2;
+      int64_t cap2 = std::min<int64_t>(need, std::max<int64_t>(1024, ((int64_t)512 << 20) / (cw * 4)));
+      cap2 = std::max<int64_t>(1, std::min<int64_t>(cap2, budget / (cw * 4)));
+      if (!R->want_cigar) cap2 = 1;
+      if ((st = ensure(c, c->tb64, (size_t)(cap2 * cw * 4)))) return st;
       aim::Work W2{as<int32_t>(c->list2), cnt + C_L2, n, cnt + C_T2, as<int32_t>(c->list3),
                    cnt + C_L3, 0};
-      HIP_TRY(aim::launch_band(64, affine, S, O, P, W2, as<uint32_t>(c->tb64), sw64, rows_cap,
-                               (int32_t)slots2, s));
+      {
+        Phase ph2(c, s, "diag");
+        HIP_TRY(aim::launch_diag(affine, S, O, P, W2, as<uint32_t>(c->tb64), cw, cap2,
+                                 (int32_t)std::min<int64_t>(need, (int64_t)c->cus * 16), s));
+      }
+      if (R->want_cigar) {
+        aim::Work W2t{as<int32_t>(c->list2), cnt + C_L2, n, cnt + C_DTB, nullptr, nullptr, 0};
+        Phase ph2(c, s, "diag_tb");
+        HIP_TRY(aim::launch_diag_tb(affine, S, O, W2t, as<uint32_t>(c->tb64), cw,
+                                    (int32_t)std::min<int64_t>((n + 15) / 16, (int64_t)c->cus * 8), s));
+      }
       full_list = as<int32_t>(c->list3);
       full_count = cnt + C_L3;
     }
     if (split) {
       aim::Work WT{order, nullptr, n, cnt + C_TB, nullptr, nullptr, 0};
       Phase ph(c, s2, "band16_tb");
+      // six of the eight workgroups a CU could hold: the persistent traceback
+      // must leave slots for the second tier's kernels beside it
       HIP_TRY(aim::launch_band16_tb(affine, S, O, WT, as<uint32_t>(tbA), swA,
-                                    (int32_t)std::min<int64_t>(chunksA, (int64_t)c->cus * 8), s2));
+                                    (int32_t)std::min<int64_t>(chunksA, (int64_t)c->cus * 6), s2));
     }
     // tier 3: full matrix
     aim::Work W3{full_list, full_count, n, cnt + C_T3, nullptr, nullptr, 0};

@@ -381,19 +381,19 @@ __global__ __launch_bounds__(128) void k_band16_tb(Seqs Sq, Outs O, Work Wk, con
     int32_t i = m, j = n, b = n - m - kmin, st = 0;
     uint32_t cur_op = 0xffu, cur_len = 0;
     int32_t nr = 0;
-    RunSink sink;
-    if (act) sink.begin(O, p);
+    // Runs go to the pair's slot only; a pair with more runs than the slot
+    // holds is marked for the in-place re-run of the compaction (pool offset
+    // -2), which recomputes it, so the common path is a single store.
+    uint32_t *slot = O.slot + p * (int64_t)O.slot_cap;
+    const int32_t cap = O.slot_cap;
     auto put = [&](uint32_t op, uint32_t len) {
-      if (op == cur_op) {
-        cur_len += len;
-      } else {
-        if (cur_len) {
-          sink.put(nr, (cur_len << 4) | cur_op, (int64_t)i + j + 1);
-          ++nr;
-        }
+      if (op != cur_op) {
+        if (cur_len && nr < cap) slot[nr] = (cur_len << 4) | cur_op;
+        nr += cur_len ? 1 : 0;
         cur_op = op;
-        cur_len = len;
+        cur_len = 0;
       }
+      cur_len += len;
     };
     // rows lo+1 .. hi of the block below `hi` go through registers: the
     // next block's loads are in flight while the lanes walk this one
@@ -453,7 +453,7 @@ __global__ __launch_bounds__(128) void k_band16_tb(Seqs Sq, Outs O, Work Wk, con
       if (i > 0) put(OP_I, (uint32_t)i);
       if (j > 0) put(OP_D, (uint32_t)j);
       put(0xfu, 0);
-      sink.finish();
+      if (nr > cap) O.pool_off[p] = -2;
       O.nruns[p] = nr;
     }
     __syncthreads();

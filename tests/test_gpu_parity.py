@@ -107,6 +107,50 @@ def test_tiers_and_fallback(ctx, alg, pen):
     check(ctx, b, alg, pen)
 
 
+def _length_gap_batch(seed, count, lmin, lmax, dmax, rates):
+    """Pairs whose lengths differ by up to dmax (one block inserted into or
+    deleted from the text) plus point noise: they pass the 32-diagonal band
+    and reach the 64-diagonal tier or the full-matrix tier."""
+    rng = np.random.default_rng(seed)
+    pats, txts = [], []
+    for _ in range(count):
+        L = int(rng.integers(lmin, lmax + 1))
+        T = rng.integers(0, 4, L).astype(np.uint8)
+        k = int(rng.integers(0, dmax + 1))
+        at = int(rng.integers(0, L + 1))
+        if rng.random() < 0.5:
+            P = np.concatenate([T[:at], rng.integers(0, 4, k).astype(np.uint8), T[at:]])
+        else:
+            P = np.concatenate([T[:at], T[min(L, at + k):]])
+        r = float(rng.choice(rates))
+        if r > 0:
+            b = synth.from_lists([P], [P])
+            P, _ = synth.mutate(rng, b.txt, b.txt_off, [r])
+        pats.append(P)
+        txts.append(T)
+    return synth.from_lists(pats, txts)
+
+
+@pytest.mark.parametrize("alg,pen", [("swg", SWG), ("nw", NW), ("swg", (0, 3, 4, 1))])
+def test_second_tier(ctx, alg, pen):
+    b = _length_gap_batch(40, 700, 40, 320, 80, [0.0, 0.02, 0.08])
+    full = check(ctx, b, alg, pen)
+    check(ctx, b, alg, pen, 150)
+    s_, st_, _, off = run(ctx, b, alg, pen, want_cigar=False)
+    assert np.array_equal(s_, full[0]) and np.array_equal(st_, full[1]) and not off.any()
+
+
+def test_second_tier_capacity():
+    # a small scratch limit leaves room for few second-tier chunks; the pairs
+    # beyond it go to the full-matrix tier
+    c = aim.Context(0, scratch_limit=4 << 20)
+    try:
+        b = _length_gap_batch(41, 300, 300, 400, 60, [0.0, 0.03])
+        check(c, b, "swg", SWG)
+    finally:
+        c.close()
+
+
 @pytest.mark.parametrize("smax", [0, 1, 6, 20, 200])
 def test_thresholds(ctx, smax):
     b = _mixed_batch(22, 800, 0, 160, [0.0, 0.01, 0.05, 0.2, 1.0])
