@@ -140,12 +140,13 @@ hipError_t launch_band16_tb(bool affine, const Seqs &S, const Outs &O, const Wor
 // (two pairs per wavefront).  Traceback bits of chunk c (the two pairs of
 // list positions 2c, 2c+1) in chunk_words words at tb + c * chunk_words, for
 // c < chunks_cap; pairs of later chunks are escalated when CIGARs are wanted.
-// Accepted pairs get nruns = -1 until launch_diag_tb walks them.
+// Accepted pairs get nruns = -2 until launch_diag_tb walks them (the first
+// tier's split walk, which may run at the same time, waits for -1).
 int64_t diag_chunk_words(bool affine, int32_t max_len);
 hipError_t launch_diag(bool affine, const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk,
                        uint32_t *tb, int64_t chunk_words, int64_t chunks_cap, int32_t nslots,
                        hipStream_t s);
-// Walk of the pairs of the same list (same Work idx / count) with nruns == -1,
+// Walk of the pairs of the same list (same Work idx / count) with nruns == -2,
 // diag_tb_pairs_per_wave() list positions per wavefront.
 int32_t diag_tb_pairs_per_wave();
 hipError_t launch_diag_tb(bool affine, const Seqs &S, const Outs &O, const Work &Wk, const uint32_t *tb,

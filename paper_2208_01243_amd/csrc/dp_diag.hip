@@ -23,7 +23,10 @@
 // iteration tau, slot s, plane q of lane l at bit 31 - (tau & 31) of word
 // ((tau >> 5) * 2 * planes + s * planes + q) * 64 + lane of the chunk's
 // region (a chunk is the two pairs a wavefront takes).  Accepted pairs are
-// marked with nruns = -1 and walked by k_diag_tb, one pair per lane.
+// marked with nruns = DIAG_MARK (-2) and walked by k_diag_tb, one pair per
+// lane.  The mark differs from the first tier's (-1): that tier's walk runs on
+// another stream at the same time and scans all pairs, so it must never take
+// a pair of this tier for one of its own.
 #include "aim_internal.h"
 #include "dev_util.h"
 
@@ -33,6 +36,7 @@ namespace {
 constexpr int LPP = 32;       // lanes per pair
 constexpr int W = 2 * LPP;    // diagonals
 constexpr int G = 64 / LPP;   // pairs per wavefront
+constexpr int32_t DIAG_MARK = -2;  // nruns of an accepted pair awaiting its walk
 
 __device__ __forceinline__ int32_t shr1(int32_t v, int32_t edge) {  // lane l gets lane l-1
   return __builtin_amdgcn_update_dpp(edge, v, 0x138, 0xF, 0xF, false);
@@ -90,7 +94,7 @@ __global__ __launch_bounds__(64) void k_diag(Seqs S, Outs O, Scoring P, Work Wk,
           }
         } else if (ad > W - 2 || (P.want_cigar && chunk >= chunks_cap)) {
           escalate = true;
-          if (l == 0) O.nruns[p] = 0;  // the walk must not take a stale -1 for its mark
+          if (l == 0) O.nruns[p] = 0;  // the walk must not take a stale mark for its own
         } else {
           run = true;
           kmin = diag_kmin(m, n);
@@ -259,7 +263,7 @@ __global__ __launch_bounds__(64) void k_diag(Seqs S, Outs O, Scoring P, Work Wk,
           if (l == 0) {
             O.score[p] = score;
             O.status[p] = ST_ALIGNED;
-            O.nruns[p] = P.want_cigar ? -1 : 0;
+            O.nruns[p] = P.want_cigar ? DIAG_MARK : 0;
           }
         }
       } else if (P.max_score >= 0 && LB > P.max_score) {
@@ -310,7 +314,7 @@ __global__ __launch_bounds__(64) void k_diag_tb(Seqs S, Outs O, Work Wk, const u
     int64_t p = 0;
     if (lane < TBP && li < count) {
       p = Wk.idx ? (int64_t)Wk.idx[li] : li;
-      act = O.nruns[p] == -1;
+      act = O.nruns[p] == DIAG_MARK;
     }
     // only accepted pairs have bits (their chunk lies below the capacity)
     const uint64_t actmask = __ballot(act);

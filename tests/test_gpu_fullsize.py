@@ -53,3 +53,17 @@ def test_full_workload(name, sample):
     for t, i in enumerate(idx):
         assert (s[i], st[i]) == (ws[t], wst[t]), (name, i)
         assert np.array_equal(cg[off[i]:off[i + 1]], wc[wo[t]:wo[t + 1]]), (name, i)
+
+
+def test_repeat_calls_swg150():
+    # The warm path: scratch no longer grows, so nothing synchronises inside a
+    # call and the first tier's traceback (second stream) runs beside the
+    # escalation tiers.  Both calls must give the same, valid results.
+    w = synth.WORKLOADS["swg150"]
+    b = synth.workload("swg150")
+    with aim.Context(0) as ctx:
+        first = run(ctx, b, w["alg"], w["pen"], w["max_score"], enc=w["enc"])
+        second = run(ctx, b, w["alg"], w["pen"], w["max_score"], enc=w["enc"])
+    for s, st, cg, off in (first, second):
+        vector_invariants(b, s, st, cg, off, w["pen"])
+    assert all(np.array_equal(u, v) for u, v in zip(first, second))
