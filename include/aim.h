@@ -208,7 +208,9 @@ aim_status aim_autotune(aim_context *ctx, const aim_batch *pairs, int32_t alg, a
 /* Launch parameters for (alg, max_len), 7 int32: params[0] first band width,
  * [1] wavefronts per CU, [2] length sort (-1 auto, 0 off, 1 on), [3] WFA ring
  * LDS KB, [4] WFA full-store LDS KB, [5] WFA long-pair workgroup size,
- * [6] packed 16-bit band cells (0 off, 1 on when the value bound allows). */
+ * [6] packed 16-bit band cells when the value bound allows (0 off; 1 on, each
+ * wavefront walking its own pairs' tracebacks; 2 on, the tracebacks walked by
+ * a second kernel beside the escalation tiers). */
 aim_status aim_tune_get(aim_context *ctx, int32_t alg, int32_t max_len, int32_t *params);
 aim_status aim_tune_set(aim_context *ctx, int32_t alg, int32_t max_len, const int32_t *params);
 /* Tune cache as text, keyed by GPU architecture and HIP runtime version; a

@@ -93,7 +93,8 @@ struct Tune {
   int32_t wfa_ring_kb = 32;   // LDS per workgroup for the WFA score ring
   int32_t wfa_trace_kb = 40;  // LDS per workgroup for the WFA full store
   int32_t wfa_long_threads = 256;  // workgroup size for long WFA pairs
-  int32_t band16 = 1;         // packed 16-bit band kernel when the value bound allows
+  int32_t band16 = 2;         // packed 16-bit band kernel when the value bound allows
+                              // (1: the fill walks its pairs, 2: a separate walk kernel)
 };
 
 struct aim_graph {
@@ -543,7 +544,7 @@ aim_status aim_align_batch(aim_context *c, const aim_batch *B, int32_t alg, aim_
     int64_t slots = std::min<int64_t>(chunksA, (int64_t)c->cus * std::max(1, tu.band_wpc));
     slots = std::max<int64_t>(1, std::min<int64_t>(slots, budget / (swA * 4)));
     // split fill / traceback when every chunk can keep its own bits
-    const bool split = b16 && R->want_cigar && chunksA * swA * 4 <= budget;
+    const bool split = b16 && tu.band16 == 2 && R->want_cigar && chunksA * swA * 4 <= budget;
     if ((st = ensure(c, tbA, (size_t)((split ? chunksA : slots) * swA * 4)))) return st;
     aim::Work W1{order, nullptr, n, cnt + C_T1, as<int32_t>(c->list2), cnt + C_L2, 0};
     {
@@ -659,7 +660,7 @@ bool tune_valid(const Tune &t) {
          t.sort >= -1 && t.sort <= 1 && t.wfa_ring_kb >= 8 && t.wfa_ring_kb <= 60 &&
          t.wfa_trace_kb >= 8 && t.wfa_trace_kb <= 60 &&
          (t.wfa_long_threads == 64 || t.wfa_long_threads == 128 || t.wfa_long_threads == 256) &&
-         (t.band16 == 0 || t.band16 == 1);
+         (t.band16 >= 0 && t.band16 <= 2);
 }
 std::string tune_key() {
   int v = 0;
@@ -692,7 +693,7 @@ aim_status aim_autotune(aim_context *c, const aim_batch *B, int32_t alg, aim_pen
     for (int w0 : {32, 64})
       for (int wpc : {8, 16, 32})
         for (int so : {0, 1})
-          for (int b16 : {0, 1}) {
+          for (int b16 : {0, 1, 2}) {
             if (w0 == 64 && b16) continue;
             Tune t;
             t.band_w0 = w0;

@@ -58,70 +58,83 @@ __device__ __forceinline__ uint32_t tb_bit(uint32_t w, int q, int h, int b) {
   return (w >> (((q & 1) * 2 + h) * 8 + (b & 7))) & 1u;
 }
 
-// Traceback of one pair (half h of the lane's packed words) over the bits of
-// its wavefront's rows.
+// Traceback of one pair (half h of its lane's packed words) over rows of
+// bits staged in LDS, row r of a block at lds + r * 2 * planes * 64 words.
+// The walk takes one op per step, chosen with selects: at a cell in state H
+// either the diagonal, or (entering a gap) the gap run the D/I plane names,
+// continued while the cell's extension plane says so.  Runs go to the pair's
+// slot only; a pair with more runs than the slot holds is marked for the
+// in-place re-run of the compaction (pool offset -2), which recomputes it.
 template <bool AFF>
-__device__ __forceinline__ int32_t walk16(const uint32_t *tb, int lane, int h, int32_t m, int32_t n,
-                                         int32_t bstar, const uint64_t *pat, const uint64_t *txt,
-                                         const Outs &O, int64_t p) {
-  constexpr int NP = AFF ? 4 : 2;
-  int32_t i = m, j = n, b = bstar, st = 0;
-  uint32_t cur_op = 0xffu, cur_len = 0;
-  int32_t nr = 0;
-  RunSink sink;
-  sink.begin(O, p);
-  int64_t pq = -1, tq = -1;
-  uint64_t pw = 0, tw = 0;
-  auto put = [&](uint32_t op, uint32_t len) {
-    if (op == cur_op) {
-      cur_len += len;
-    } else {
-      if (cur_len) {
-        sink.put(nr, (cur_len << 4) | cur_op, (int64_t)i + j + 1);
-        ++nr;
-      }
+struct Walker16 {
+  static constexpr int NP = AFF ? 4 : 2;
+  int32_t i, j, b, st, nr, kmin;
+  uint32_t cur_op, cur_len;
+  uint32_t *slot;
+  int32_t cap;
+
+  __device__ void begin(const Outs &O, int64_t p, int32_t m, int32_t n, int32_t kmin_) {
+    i = m;
+    j = n;
+    kmin = kmin_;
+    b = n - m - kmin;
+    st = 0;
+    nr = 0;
+    cur_op = 0xffu;
+    cur_len = 0;
+    slot = O.slot + p * (int64_t)O.slot_cap;
+    cap = O.slot_cap;
+  }
+  __device__ void put(uint32_t op, uint32_t len) {
+    if (op != cur_op) {
+      if (cur_len && nr < cap) slot[nr] = (cur_len << 4) | cur_op;
+      nr += cur_len ? 1 : 0;
       cur_op = op;
-      cur_len = len;
+      cur_len = 0;
     }
-  };
-  while (i > 0 && j > 0) {
-    const uint32_t *w = tb + ((int64_t)i * NP * 2 + ((b >> 3) & 3) * (NP / 2)) * 64 + lane;
-    uint32_t bq[NP];
-#pragma unroll
-    for (int q = 0; q < NP; ++q) bq[q] = tb_bit(w[(q >> 1) * 64], q, h, b);
-    if (st == 0) {
-      if (bq[0]) {
-        if (((i - 1) >> 5) != pq) { pq = (i - 1) >> 5; pw = pat[pq]; }
-        if (((j - 1) >> 5) != tq) { tq = (j - 1) >> 5; tw = txt[tq]; }
-        const uint32_t a = (uint32_t)(pw >> (2 * ((i - 1) & 31))) & 3u;
-        const uint32_t c = (uint32_t)(tw >> (2 * ((j - 1) & 31))) & 3u;
-        put(a == c ? OP_EQ : OP_X, 1);
-        --i;
-        --j;
-      } else if (!AFF) {
-        if (bq[1]) { put(OP_D, 1); --j; --b; }
-        else { put(OP_I, 1); --i; ++b; }
-      } else {
-        st = bq[1] ? 2 : 1;
+    cur_len += len;
+  }
+  // Steps while the path stays in rows lo+1 .. (the rows staged).  Pattern
+  // bases lo .. lo+31 are in pw0/pw1 (words pq0, pq0+1); text bases from
+  // lo+kmin on in tw0..tw2 (words tq0 ..).
+  __device__ void walk(const uint32_t *lds, int lane, int h, int32_t lo, uint64_t pw0, uint64_t pw1,
+                       uint64_t tw0, uint64_t tw1, uint64_t tw2, int64_t pq0, int64_t tq0) {
+    while (i > lo && j > 0) {
+      const uint32_t *rw = lds + ((i - lo - 1) * NP * 2 + ((b >> 3) & 3) * (NP / 2)) * 64 + lane;
+      const uint32_t w01 = rw[0];
+      const uint32_t bd = tb_bit(w01, 0, h, b), b1 = tb_bit(w01, 1, h, b);
+      uint32_t b2 = 0, b3 = 0;
+      if (AFF) {
+        const uint32_t w23 = rw[64];
+        b2 = tb_bit(w23, 2, h, b);
+        b3 = tb_bit(w23, 3, h, b);
       }
-    } else if (st == 1) {
-      put(OP_I, 1);
-      st = bq[2] ? 1 : 0;
-      --i;
-      ++b;
-    } else {
-      put(OP_D, 1);
-      st = bq[3] ? 2 : 0;
-      --j;
-      --b;
+      const int32_t g = (st == 0 && !bd) ? (b1 ? 2 : 1) : st;  // 0 diag, 1 I, 2 D
+      const uint64_t pw = (((i - 1) >> 5) == pq0) ? pw0 : pw1;
+      const int64_t tq = (int64_t)(j - 1) >> 5;
+      const uint64_t tw = tq == tq0 ? tw0 : (tq == tq0 + 1 ? tw1 : tw2);
+      const uint32_t ca = (uint32_t)(pw >> (2 * ((i - 1) & 31))) & 3u;
+      const uint32_t cb = (uint32_t)(tw >> (2 * ((j - 1) & 31))) & 3u;
+      const uint32_t op = g == 0 ? (ca == cb ? OP_EQ : OP_X) : (g == 1 ? OP_I : OP_D);
+      put(op, 1);
+      st = AFF ? (g == 1 ? (b2 ? 1 : 0) : (g == 2 ? (b3 ? 2 : 0) : 0)) : 0;
+      i -= g != 2;
+      j -= g != 1;
+      b += g == 1 ? 1 : (g == 2 ? -1 : 0);
     }
   }
-  if (i > 0) put(OP_I, (uint32_t)i);
-  if (j > 0) put(OP_D, (uint32_t)j);
-  put(0xfu, 0);
-  sink.finish();
-  return nr;
-}
+  __device__ void finish(const Outs &O, int64_t p) {
+    if (i > 0) put(OP_I, (uint32_t)i);
+    if (j > 0) put(OP_D, (uint32_t)j);
+    put(0xfu, 0);
+    if (nr > cap) O.pool_off[p] = -2;
+    O.nruns[p] = nr;
+  }
+};
+
+// Rows walked per staged block by the fill kernel's own walk (8 KB of LDS
+// for four affine planes).
+constexpr int FUSED_ROWS = 4;
 
 // SPLIT: the traceback bits of chunk c (128 pairs) go to a region of their
 // own and the traceback runs in k_band16_tb; accepted pairs are marked with
@@ -131,6 +144,8 @@ template <bool AFF, bool SPLIT>
 __global__ __launch_bounds__(64, 3) void k_band16(Seqs Sq, Outs O, Scoring P, Work Wk, uint32_t *tb_all,
                                               int64_t tb_slot_words, int32_t rows_cap) {
   constexpr int NP = AFF ? 4 : 2;
+  // rows staged for the traceback when the kernel walks its own pairs
+  __shared__ u32x4 fused_stage[SPLIT ? 1 : FUSED_ROWS * NP * 2 * 64 / 4];
   const int lane = threadIdx.x;
   const int32_t x = P.x, o = P.o, e = P.e, oe = P.o + P.e;
   const int32_t hoff = AFF ? oe : e;
@@ -318,11 +333,53 @@ __global__ __launch_bounds__(64, 3) void k_band16(Seqs Sq, Outs O, Scoring P, Wo
     if (!P.want_cigar) continue;
 
     if (SPLIT) continue;
-    // ---- traceback, pair A then pair B of this lane ----
+    // ---- traceback of both pairs of each lane over this wavefront's rows ----
+    // The rows were stored by this wavefront during the fill; the fence makes
+    // them visible to its loads (no stale L1 line from an earlier chunk).
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+    {
+      constexpr int ROW = NP * 2 * 64;
+      constexpr int PRE = FUSED_ROWS * ROW / 4 / 64;
+      Walker16<AFF> wk[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        if (accept[h]) wk[h].begin(O, p[h], m[h], n[h], kmin[h]);
+      const int32_t top = dev::wave_max(max(accept[0] ? m[0] : 0, accept[1] ? m[1] : 0));
 #pragma unroll 1
-    for (int h = 0; h < 2; ++h) {
-      if (!accept[h]) continue;
-      O.nruns[p[h]] = walk16<AFF>(tb, lane, h, m[h], n[h], bstar[h], pat[h], txt[h], O, p[h]);
+      for (int32_t hi = top; hi > 0; hi -= FUSED_ROWS) {
+        const int32_t lo = max(hi - FUSED_ROWS, 0);  // rows lo+1 .. hi
+        const int nq = (hi - lo) * (ROW / 4);
+        const u32x4 *g = reinterpret_cast<const u32x4 *>(tb + (int64_t)(lo + 1) * ROW);
+        u32x4 pre[PRE];
+#pragma unroll
+        for (int k = 0; k < PRE; ++k) pre[k] = g[min(lane + 64 * k, nq - 1)];
+        uint64_t w[2][5];
+        int64_t pq0[2], tq0[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          pq0[h] = lo >> 5;
+          tq0[h] = ((int64_t)lo + kmin[h]) >> 5;
+          const bool need = accept[h] && wk[h].i > lo && wk[h].j > 0;
+          const int64_t pn = need ? pnw[h] : 0, tn = need ? tnw[h] : 0;
+          w[h][0] = dev::ld_word(pat[h], pn, pq0[h]);
+          w[h][1] = dev::ld_word(pat[h], pn, pq0[h] + 1);
+          w[h][2] = dev::ld_word(txt[h], tn, tq0[h]);
+          w[h][3] = dev::ld_word(txt[h], tn, tq0[h] + 1);
+          w[h][4] = dev::ld_word(txt[h], tn, tq0[h] + 2);
+        }
+        __syncthreads();  // the previous block is no longer read
+#pragma unroll
+        for (int k = 0; k < PRE; ++k) fused_stage[lane + 64 * k] = pre[k];
+        __syncthreads();
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+          if (accept[h])
+            wk[h].walk(reinterpret_cast<const uint32_t *>(fused_stage), lane, h, lo, w[h][0], w[h][1],
+                       w[h][2], w[h][3], w[h][4], pq0[h], tq0[h]);
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        if (accept[h]) wk[h].finish(O, p[h]);
     }
   }
 }
@@ -378,23 +435,8 @@ __global__ __launch_bounds__(128) void k_band16_tb(Seqs Sq, Outs O, Work Wk, con
     const uint32_t *src = tb_all + chunk * tb_chunk_words;
     const int64_t pnw = (m + 31) >> 5, tnw = (n + 31) >> 5;
 
-    int32_t i = m, j = n, b = n - m - kmin, st = 0;
-    uint32_t cur_op = 0xffu, cur_len = 0;
-    int32_t nr = 0;
-    // Runs go to the pair's slot only; a pair with more runs than the slot
-    // holds is marked for the in-place re-run of the compaction (pool offset
-    // -2), which recomputes it, so the common path is a single store.
-    uint32_t *slot = O.slot + p * (int64_t)O.slot_cap;
-    const int32_t cap = O.slot_cap;
-    auto put = [&](uint32_t op, uint32_t len) {
-      if (op != cur_op) {
-        if (cur_len && nr < cap) slot[nr] = (cur_len << 4) | cur_op;
-        nr += cur_len ? 1 : 0;
-        cur_op = op;
-        cur_len = 0;
-      }
-      cur_len += len;
-    };
+    Walker16<AFF> wk;
+    if (act) wk.begin(O, p, m, n, kmin);
     // rows lo+1 .. hi of the block below `hi` go through registers: the
     // next block's loads are in flight while the lanes walk this one
     constexpr int PRE = TB_ROWS * ROW / 4 / 128;
@@ -421,41 +463,10 @@ __global__ __launch_bounds__(128) void k_band16_tb(Seqs Sq, Outs O, Work Wk, con
                      tw2 = dev::ld_word(txt, tnw, tq0 + 2);
       __syncthreads();
       AIM_TB_FETCH(lo > 0 ? lo : hi);
-      // One op per iteration, chosen with selects: at a cell in state H
-      // either the diagonal, or (entering a gap) the gap run the D/I plane
-      // names, continued while the cell's extension plane says so.
-      while (act && i > lo && j > 0) {
-        const uint32_t *rw = lds + ((i - lo - 1) * NP * 2 + ((b >> 3) & 3) * (NP / 2)) * 64 + lane;
-        const uint32_t w01 = rw[0];
-        const uint32_t bd = tb_bit(w01, 0, h, b), b1 = tb_bit(w01, 1, h, b);
-        uint32_t b2 = 0, b3 = 0;
-        if (AFF) {
-          const uint32_t w23 = rw[64];
-          b2 = tb_bit(w23, 2, h, b);
-          b3 = tb_bit(w23, 3, h, b);
-        }
-        const int32_t g = (st == 0 && !bd) ? (b1 ? 2 : 1) : st;  // 0 diag, 1 I, 2 D
-        const uint64_t pw = (((i - 1) >> 5) == pq0) ? pw0 : pw1;
-        const int64_t tq = (int64_t)(j - 1) >> 5;
-        const uint64_t tw = tq == tq0 ? tw0 : (tq == tq0 + 1 ? tw1 : tw2);
-        const uint32_t ca = (uint32_t)(pw >> (2 * ((i - 1) & 31))) & 3u;
-        const uint32_t cb = (uint32_t)(tw >> (2 * ((j - 1) & 31))) & 3u;
-        const uint32_t op = g == 0 ? (ca == cb ? OP_EQ : OP_X) : (g == 1 ? OP_I : OP_D);
-        put(op, 1);
-        st = AFF ? (g == 1 ? (b2 ? 1 : 0) : (g == 2 ? (b3 ? 2 : 0) : 0)) : 0;
-        i -= g != 2;
-        j -= g != 1;
-        b += g == 1 ? 1 : (g == 2 ? -1 : 0);
-      }
+      if (act) wk.walk(lds, lane, h, lo, pw0, pw1, tw0, tw1, tw2, pq0, tq0);
       __syncthreads();
     }
-    if (act) {
-      if (i > 0) put(OP_I, (uint32_t)i);
-      if (j > 0) put(OP_D, (uint32_t)j);
-      put(0xfu, 0);
-      if (nr > cap) O.pool_off[p] = -2;
-      O.nruns[p] = nr;
-    }
+    if (act) wk.finish(O, p);
     __syncthreads();
   }
 }

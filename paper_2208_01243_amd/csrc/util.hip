@@ -253,12 +253,28 @@ __global__ void k_bucket_scan(int32_t *hist) {
   }
 }
 
-__global__ void k_bucket_scatter(int64_t n, const int32_t *pl, const int32_t *tl, int32_t *cursor,
-                                 int32_t *order) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int b = len_bucket(pl[i], tl[i]);
-    order[atomicAdd(&cursor[b], 1)] = (int32_t)i;
+// Per tile of blockDim pairs: ranks within the tile's buckets from LDS
+// atomics, then one global atomic per non-empty bucket reserves the tile's
+// range (fixed-length batches put nearly every pair in one bucket, where one
+// global atomic per pair would serialise).
+__global__ __launch_bounds__(256) void k_bucket_scatter(int64_t n, const int32_t *pl, const int32_t *tl,
+                                                       int32_t *cursor, int32_t *order) {
+  __shared__ int32_t cnt[NBUCKET], base[NBUCKET];
+  for (int64_t t0 = blockIdx.x * (int64_t)blockDim.x; t0 < n; t0 += (int64_t)gridDim.x * blockDim.x) {
+    for (int k = threadIdx.x; k < NBUCKET; k += blockDim.x) cnt[k] = 0;
+    __syncthreads();
+    const int64_t i = t0 + threadIdx.x;
+    int b = 0, r = 0;
+    if (i < n) {
+      b = len_bucket(pl[i], tl[i]);
+      r = atomicAdd(&cnt[b], 1);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < NBUCKET; k += blockDim.x)
+      if (cnt[k]) base[k] = atomicAdd(&cursor[k], cnt[k]);
+    __syncthreads();
+    if (i < n) order[base[b] + r] = (int32_t)i;
+    __syncthreads();
   }
 }
 

@@ -129,6 +129,25 @@ def test_length_sort_exact(alg, pen, sort):
     assert not bad, describe(b, bad[0], got, want)
 
 
+@pytest.mark.parametrize("alg,pen", [("swg", (0, 4, 6, 2)), ("nw", (0, 1, 0, 1))])
+@pytest.mark.parametrize("band16", [0, 1, 2])
+def test_first_tier_variants_exact(alg, pen, band16):
+    # the first band tier in 32-bit cells (0), packed 16-bit cells walked by the
+    # fill itself (1) or by a separate kernel beside the escalation tiers (2);
+    # two calls in one context so the second runs on warm scratch
+    b = _mixed(51, 4000, 60, 260, [0.0, 0.02, 0.05, 0.12])
+    with aim.Context(0) as ctx:
+        L = int(max(b.pat_len.max(), b.txt_len.max()))
+        p = ctx.tune_get(alg, L)
+        p[6] = band16
+        ctx.tune_set(alg, L, p)
+        run(ctx, b, alg, pen)
+        got = run(ctx, b, alg, pen)
+    want = oracle.align_batch(b, alg, pen)
+    bad = compare(got, want)
+    assert not bad, describe(b, bad[0], got, want)
+
+
 def test_wfa_mixed_sample():
     # the batching-form workload (100 bp - 10 kbp, 0.5-10 %): first 3000 pairs,
     # checked pair by pair (pairs above 2.5 kbp against the scalar WFA)
