@@ -210,7 +210,8 @@ aim_status aim_autotune(aim_context *ctx, const aim_batch *pairs, int32_t alg, a
  * LDS KB, [4] WFA full-store LDS KB, [5] WFA long-pair workgroup size,
  * [6] packed 16-bit band cells when the value bound allows (0 off; 1 on, each
  * wavefront walking its own pairs' tracebacks; 2 on, the tracebacks walked by
- * a second kernel beside the escalation tiers). */
+ * a second kernel beside the escalation tiers; 3, the default: 2 for batches
+ * of at least 65536 pairs, else 1). */
 aim_status aim_tune_get(aim_context *ctx, int32_t alg, int32_t max_len, int32_t *params);
 aim_status aim_tune_set(aim_context *ctx, int32_t alg, int32_t max_len, const int32_t *params);
 /* Tune cache as text, keyed by GPU architecture and HIP runtime version; a

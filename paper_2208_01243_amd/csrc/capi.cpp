@@ -93,8 +93,9 @@ struct Tune {
   int32_t wfa_ring_kb = 32;   // LDS per workgroup for the WFA score ring
   int32_t wfa_trace_kb = 40;  // LDS per workgroup for the WFA full store
   int32_t wfa_long_threads = 256;  // workgroup size for long WFA pairs
-  int32_t band16 = 2;         // packed 16-bit band kernel when the value bound allows
-                              // (1: the fill walks its pairs, 2: a separate walk kernel)
+  int32_t band16 = 3;         // packed 16-bit band kernel when the value bound allows
+                              // (1: the fill walks its pairs, 2: a separate walk kernel,
+                              // 3: 2 for batches of at least SPLIT_MIN_PAIRS pairs, else 1)
 };
 
 struct aim_graph {
@@ -174,6 +175,10 @@ enum Counter {
   C_W1, C_W1G, C_RL, C_FAIL, C_N0, C_N1, C_N2, C_N3, C_P0, C_P1, C_P2, C_P3, C_TB, C_DTB,
   C_N = 32
 };
+
+// Smallest batch for which the packed band tier's traceback is walked by a
+// separate kernel beside the escalation tiers by default.
+constexpr int64_t SPLIT_MIN_PAIRS = 65536;
 
 // WFA requires a bounded ring of past wavefronts: max(x, o + e) <= this.
 constexpr int32_t WFA_MAX_STEP = 1024;
@@ -544,7 +549,10 @@ aim_status aim_align_batch(aim_context *c, const aim_batch *B, int32_t alg, aim_
     int64_t slots = std::min<int64_t>(chunksA, (int64_t)c->cus * std::max(1, tu.band_wpc));
     slots = std::max<int64_t>(1, std::min<int64_t>(slots, budget / (swA * 4)));
     // split fill / traceback when every chunk can keep its own bits
-    const bool split = b16 && tu.band16 == 2 && R->want_cigar && chunksA * swA * 4 <= budget;
+    // (the separate walk pays a second stream and two more launches, which
+    // only large batches repay)
+    const bool split = b16 && (tu.band16 == 2 || (tu.band16 == 3 && n >= SPLIT_MIN_PAIRS)) &&
+                       R->want_cigar && chunksA * swA * 4 <= budget;
     if ((st = ensure(c, tbA, (size_t)((split ? chunksA : slots) * swA * 4)))) return st;
     aim::Work W1{order, nullptr, n, cnt + C_T1, as<int32_t>(c->list2), cnt + C_L2, 0};
     {
@@ -660,7 +668,7 @@ bool tune_valid(const Tune &t) {
          t.sort >= -1 && t.sort <= 1 && t.wfa_ring_kb >= 8 && t.wfa_ring_kb <= 60 &&
          t.wfa_trace_kb >= 8 && t.wfa_trace_kb <= 60 &&
          (t.wfa_long_threads == 64 || t.wfa_long_threads == 128 || t.wfa_long_threads == 256) &&
-         (t.band16 >= 0 && t.band16 <= 2);
+         (t.band16 >= 0 && t.band16 <= 3);
 }
 std::string tune_key() {
   int v = 0;

@@ -91,6 +91,8 @@ __global__ __launch_bounds__(64) void k_band(Seqs S, Outs O, Scoring P, Work Wk,
   uint32_t *tb = tb_all + (int64_t)blockIdx.x * tb_slot_words;
   const int32_t x = P.x, o = P.o, e = P.e, oe = P.o + P.e;
   const int64_t count = Wk.count ? (int64_t)(*(volatile const int32_t *)Wk.count) : Wk.n;
+  // a workgroup the work can never reach leaves before touching the counter
+  if ((int64_t)blockIdx.x * 64 >= count) return;
 
   for (;;) {
     int chunk = 0;

@@ -150,6 +150,8 @@ __global__ __launch_bounds__(64, 3) void k_band16(Seqs Sq, Outs O, Scoring P, Wo
   const int32_t x = P.x, o = P.o, e = P.e, oe = P.o + P.e;
   const int32_t hoff = AFF ? oe : e;
   const int64_t count = Wk.count ? (int64_t)(*(volatile const int32_t *)Wk.count) : Wk.n;
+  // a workgroup the work can never reach leaves before touching the counter
+  if ((int64_t)blockIdx.x * 128 >= count) return;
   const s16x2 vx = spl(x), vxm1 = spl(x - 1), ve = spl(e), voe = spl(oe), vinf = spl(INF16);
 
   for (;;) {
@@ -403,6 +405,8 @@ __global__ __launch_bounds__(128) void k_band16_tb(Seqs Sq, Outs O, Work Wk, con
   const uint32_t *lds = reinterpret_cast<const uint32_t *>(stage);
   const int tid = threadIdx.x, lane = tid & 63, h = tid >> 6;
   const int64_t count = Wk.count ? (int64_t)(*(volatile const int32_t *)Wk.count) : Wk.n;
+  // a workgroup the work can never reach leaves before touching the counter
+  if ((int64_t)blockIdx.x * 128 >= count) return;
   for (;;) {
     if (tid == 0) {
       s_chunk = atomicAdd(Wk.counter, 1);

@@ -63,6 +63,8 @@ __global__ __launch_bounds__(64) void k_diag(Seqs S, Outs O, Scoring P, Work Wk,
   const int32_t hoff = AFF ? oe : e;
   const int32_t INF = DP_INF;
   const int64_t count = Wk.count ? (int64_t)(*(volatile const int32_t *)Wk.count) : Wk.n;
+  // a workgroup the work can never reach leaves before touching the counter
+  if ((int64_t)blockIdx.x * G >= count) return;
 
   for (;;) {
     int chunk = 0;
@@ -304,6 +306,8 @@ __global__ __launch_bounds__(64) void k_diag_tb(Seqs S, Outs O, Work Wk, const u
   const uint32_t *lds = reinterpret_cast<const uint32_t *>(stage);
   const int lane = threadIdx.x;
   const int64_t count = Wk.count ? (int64_t)(*(volatile const int32_t *)Wk.count) : Wk.n;
+  // a workgroup the work can never reach leaves before touching the counter
+  if ((int64_t)blockIdx.x * TBP >= count) return;
   for (;;) {
     int t = 0;
     if (lane == 0) t = atomicAdd(Wk.counter, 1);

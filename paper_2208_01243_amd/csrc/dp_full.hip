@@ -47,6 +47,8 @@ __global__ __launch_bounds__(NT) void k_full(Seqs S, Outs O, Scoring P, Work Wk,
   int32_t *rowE = rowH + (max_len + 1);
   uint32_t *codes = (uint32_t *)(rowE + (max_len + 1));
   const int64_t count = Wk.count ? (int64_t)(*(volatile const int32_t *)Wk.count) : Wk.n;
+  // a workgroup the work can never reach leaves before touching the counter
+  if ((int64_t)blockIdx.x * 1 >= count) return;
 
   for (;;) {
     __syncthreads();

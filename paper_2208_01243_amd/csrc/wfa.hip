@@ -170,6 +170,8 @@ __global__ __launch_bounds__(WGMAX) void k_wfa_score(Seqs S, Outs O, Scoring P, 
   int32_t *ring = ring_in_lds ? lds_ring : (hbm + (int64_t)blockIdx.x * L.slot_words);
   const int32_t x = P.x, oe = P.o + P.e, e = P.e, R = L.R;
   const int64_t count = Wk.count ? (int64_t)(*(volatile const int32_t *)Wk.count) : Wk.n;
+  // a workgroup the work can never reach leaves before touching the counter
+  if ((int64_t)blockIdx.x * 1 >= count) return;
   for (;;) {
     __syncthreads();
     if (lane == 0) sh_pair = atomicAdd(Wk.counter, 1);
@@ -273,6 +275,8 @@ __global__ __launch_bounds__(WGMAX) void k_wfa_trace(Seqs S, Outs O, Scoring P, 
   int32_t *arena = L.full_in_lds ? (int32_t *)(sT + L.seq_words) : (hbm + (int64_t)blockIdx.x * L.slot_words);
   const int32_t x = P.x, o = P.o, oe = P.o + P.e, e = P.e;
   const int64_t count = Wk.count ? (int64_t)(*(volatile const int32_t *)Wk.count) : Wk.n;
+  // a workgroup the work can never reach leaves before touching the counter
+  if ((int64_t)blockIdx.x * 1 >= count) return;
   for (;;) {
     __syncthreads();
     if (lane == 0) sh_pair = atomicAdd(Wk.counter, 1);

@@ -130,10 +130,11 @@ def test_length_sort_exact(alg, pen, sort):
 
 
 @pytest.mark.parametrize("alg,pen", [("swg", (0, 4, 6, 2)), ("nw", (0, 1, 0, 1))])
-@pytest.mark.parametrize("band16", [0, 1, 2])
+@pytest.mark.parametrize("band16", [0, 1, 2, 3])
 def test_first_tier_variants_exact(alg, pen, band16):
     # the first band tier in 32-bit cells (0), packed 16-bit cells walked by the
-    # fill itself (1) or by a separate kernel beside the escalation tiers (2);
+    # fill itself (1), by a separate kernel beside the escalation tiers (2), or
+    # the size-dependent default (3, the fill's own walk at this batch size);
     # two calls in one context so the second runs on warm scratch
     b = _mixed(51, 4000, 60, 260, [0.0, 0.02, 0.05, 0.12])
     with aim.Context(0) as ctx:
