@@ -453,6 +453,10 @@ __global__ __launch_bounds__(128) void k_band16_tb(Seqs Sq, Outs O, Work Wk, con
     _Pragma("unroll") for (int k = 0; k < PRE; ++k) pre[k] = g_[min(tid + 128 * k, nq_ - 1)]; \
   } while (0)
     if (top > 0) AIM_TB_FETCH(top);
+    // sequence words of the current block, reloaded only when the block's
+    // first word moves (every fourth block or so)
+    int64_t pq0 = INT64_MIN, tq0 = INT64_MIN;
+    uint64_t pw0 = 0, pw1 = 0, tw0 = 0, tw1 = 0, tw2 = 0;
 #pragma unroll 1
     for (int32_t hi = top; hi > 0; hi -= TB_ROWS) {
       const int32_t lo = max(hi - TB_ROWS, 0);  // rows lo+1 .. hi
@@ -461,12 +465,22 @@ __global__ __launch_bounds__(128) void k_band16_tb(Seqs Sq, Outs O, Work Wk, con
 #pragma unroll
       for (int k = 0; k < PRE; ++k) stage[tid + 128 * k] = pre[k];
       // pattern bases lo .. hi-1; text bases lo+kmin .. hi-1+kmin+W-1
-      const int64_t pq0 = lo >> 5, tq0 = ((int64_t)lo + kmin) >> 5;
-      const uint64_t pw0 = dev::ld_word(pat, pnw, pq0), pw1 = dev::ld_word(pat, pnw, pq0 + 1);
-      const uint64_t tw0 = dev::ld_word(txt, tnw, tq0), tw1 = dev::ld_word(txt, tnw, tq0 + 1),
-                     tw2 = dev::ld_word(txt, tnw, tq0 + 2);
+      const int64_t pq = lo >> 5, tq = ((int64_t)lo + kmin) >> 5;
+      if (pq != pq0) {
+        pq0 = pq;
+        pw0 = dev::ld_word(pat, pnw, pq);
+        pw1 = dev::ld_word(pat, pnw, pq + 1);
+      }
+      if (tq != tq0) {
+        tq0 = tq;
+        tw0 = dev::ld_word(txt, tnw, tq);
+        tw1 = dev::ld_word(txt, tnw, tq + 1);
+        tw2 = dev::ld_word(txt, tnw, tq + 2);
+      }
       __syncthreads();
-      AIM_TB_FETCH(lo > 0 ? lo : hi);
+      // the next block; after the last one, a one-row dummy that keeps the
+      // loads unconditional
+      AIM_TB_FETCH(lo > 0 ? lo : 1);
       if (act) wk.walk(lds, lane, h, lo, pw0, pw1, tw0, tw1, tw2, pq0, tq0);
       __syncthreads();
     }
