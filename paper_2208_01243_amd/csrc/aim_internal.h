@@ -186,6 +186,13 @@ WfaPlan wfa_plan(int32_t max_len, const Scoring &P, int64_t budget_bytes, int32_
 hipError_t launch_wfa_score(const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk,
                             const WfaLaunch &L, int32_t *hbm, bool ring_in_lds, int32_t nslots,
                             int32_t threads, hipStream_t s);
+// Pass 1 by one wavefront per pair with 16-bit offsets in LDS over a window of
+// 64 C diagonals (C <= 4); needs max_len <= WFA16_MAX_LEN.  Pairs that leave
+// the window go to L.ring_list.
+constexpr int32_t WFA16_MAX_LEN = 32000;
+size_t wfa_score16_lds(const WfaLaunch &L, int32_t e, int32_t C);
+hipError_t launch_wfa_score16(const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk,
+                              const WfaLaunch &L, int32_t C, int32_t nslots, hipStream_t s);
 hipError_t launch_wfa_trace(const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk,
                             const WfaLaunch &L, int32_t *hbm, int32_t nslots, int32_t threads,
                             hipStream_t s);

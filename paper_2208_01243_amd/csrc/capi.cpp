@@ -259,7 +259,16 @@ aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const
   }
   WL.need = as<int64_t>(c->wneed);
   const int32_t slots = (int32_t)std::min<int64_t>(n, (int64_t)c->cus * 8);
-  if (!plain && pl.wcap_lds > 0) {
+  // one wavefront per pair with 16-bit offsets over a window of 64 C diagonals
+  const int32_t C16 = (int32_t)std::min<int64_t>(4, std::max<int64_t>(1, (pl.wcap + 63) / 64));
+  const bool w16 = !plain && L <= aim::WFA16_MAX_LEN && pl.R <= 32 &&
+                   aim::wfa_score16_lds(WL, P.e, C16) <= 48 * 1024;
+  if (w16) {
+    aim::Work W{order, nullptr, n, cnt + C_W1, nullptr, nullptr, 0};
+    Phase ph(c, s, "wfa_score");
+    HIP_TRY(aim::launch_wfa_score16(S, O, P, W, WL, C16,
+                                    (int32_t)std::min<int64_t>(n, (int64_t)c->cus * 20), s));
+  } else if (!plain && pl.wcap_lds > 0) {
     aim::WfaLaunch A = WL;
     A.wcap = pl.wcap_lds;
     aim::Work W{order, nullptr, n, cnt + C_W1, nullptr, nullptr, 0};
@@ -274,7 +283,7 @@ aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const
     B.slot_words = pl.ring_slot_words;
     B.ring_list = lists + (int64_t)n * 5;  // never reached: wcap bounds every width
     B.ring_count = cnt + C_FAIL;
-    const bool all = plain || pl.wcap_lds == 0;
+    const bool all = plain || (!w16 && pl.wcap_lds == 0);
     aim::Work W{all ? order : lists, all ? nullptr : cnt + C_RL, n, cnt + C_W1G, nullptr, nullptr, 0};
     Phase ph(c, s, "wfa_score_hbm");
     HIP_TRY(aim::launch_wfa_score(S, O, P, W, B, as<int32_t>(c->wring), false,

@@ -264,6 +264,174 @@ __global__ __launch_bounds__(WGMAX) void k_wfa_score(Seqs S, Outs O, Scoring P, 
   }
 }
 
+// ------------------------------------------------- pass 1, one wavefront per pair
+// The wavefronts of k_wfa_score (same recurrences, bounds, presence bits and
+// full-store size), computed by a single 64-lane wavefront with no barrier
+// between waves: lane l owns diagonals kbase + l + 64 c for c < C, kbase =
+// -32 C.  M of the last R scores and I, D of the last e + 1 live in LDS as
+// 16-bit offsets (negative: absent), the per-score bounds and presence bits in
+// an R-entry LDS table; a source entry is read only inside that wavefront's
+// bounds, so stale slots never leak.  A wavefront that leaves the window goes
+// to the HBM-ring pass (ring_list), as does a pair whose end diagonal lies
+// outside it.  Offsets fit 16 bits because the host sends only batches with
+// max_len <= WFA16_MAX_LEN here.
+__global__ __launch_bounds__(64) void k_wfa_score16(Seqs S, Outs O, Scoring P, Work Wk, WfaLaunch L,
+                                                   int32_t C) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int lane = threadIdx.x;
+  const int32_t x = P.x, oe = P.o + P.e, e = P.e, R = L.R, RE = P.e + 1;
+  const int32_t W = 64 * C, kbase = -32 * C;
+  uint64_t *sP = (uint64_t *)smem;
+  uint64_t *sT = sP + L.seq_words;
+  int32_t *tab = (int32_t *)(sT + L.seq_words);  // per ring slot: lo, hi, present, -
+  int16_t *rM = (int16_t *)(tab + R * ENTRY);     // R x W
+  int16_t *rI = rM + R * W;                        // (e+1) x W
+  int16_t *rD = rI + RE * W;                       // (e+1) x W
+  const int32_t count = Wk.count ? __builtin_amdgcn_readfirstlane(*(volatile const int32_t *)Wk.count)
+                                 : (int32_t)Wk.n;
+  if ((int32_t)blockIdx.x >= count) return;
+  // Control flow is kept provably uniform (scalar values, no lane-dependent
+  // branch around the work counter, one loop latch, no continue).  With a
+  // lane-0-only atomic and a loop exit the compiler took for divergent, it
+  // split the loop so that lanes 1..63 looped back to the broadcast without a
+  // new index.  Every lane adds here (lane 0 one, the others zero), and lane
+  // 0's return value is the item.
+  for (;;) {
+    const int32_t t = atomicAdd(Wk.counter, lane == 0 ? 1 : 0);
+    const int32_t li = __builtin_amdgcn_readfirstlane(t);
+    if (li >= count) break;
+    const int64_t p = Wk.idx ? (int64_t)__builtin_amdgcn_readfirstlane(Wk.idx[li]) : li;
+    const bool invalid = O.flags && __builtin_amdgcn_readfirstlane((int32_t)O.flags[p]);
+    if (invalid) {
+      if (lane == 0) { O.score[p] = -1; O.status[p] = ST_INVALID; O.nruns[p] = 0; }
+    } else {
+    const int32_t m = __builtin_amdgcn_readfirstlane(S.pat_len[p]);
+    const int32_t n = __builtin_amdgcn_readfirstlane(S.txt_len[p]);
+    const int64_t pnw = (m + 31) >> 5, tnw = (n + 31) >> 5;
+    const uint64_t *Pw = S.pat + S.pat_off[p], *Tw = S.txt + S.txt_off[p];
+    __syncthreads();  // the previous pair's LDS is no longer read
+    if (pnw <= L.seq_words && tnw <= L.seq_words) {
+      stage_seq(sP, Pw, pnw);
+      stage_seq(sT, Tw, tnw);
+      Pw = sP;
+      Tw = sT;
+    }
+    __syncthreads();  // staged words visible to every lane
+    const int32_t kend = n - m;
+    const int64_t ad = m > n ? m - n : n - m;
+    const int64_t up1 = (int64_t)x * min(m, n) + (ad ? (int64_t)P.o + ad * e : 0);
+    const int64_t up2 = (m ? (int64_t)P.o + (int64_t)m * e : 0) + (n ? (int64_t)P.o + (int64_t)n * e : 0);
+    const int64_t s_upper = min(up1, up2);
+    int result = (kend < kbase || kend >= kbase + W) ? 3 : 0;  // 1 aligned, 2 rejected, 3 overflow, 4 bound
+    int32_t s = 0;
+    int64_t need = 0;
+    if (!result) {
+      if (lane == 0) {
+        const int32_t f = extend(Pw, pnw, m, Tw, tnw, n, 0, 0);
+        rM[0 - kbase] = (int16_t)f;
+        tab[0] = 0;
+        tab[1] = 0;
+        tab[2] = 1;
+      }
+      need = ENTRY + 3;
+      __syncthreads();
+      if (kend == 0 && __builtin_amdgcn_readfirstlane((int32_t)rM[0 - kbase]) >= n) result = 1;
+    }
+    while (!result) {
+      ++s;
+      if (P.max_score >= 0 && s > P.max_score) { result = 2; break; }
+      if (s > s_upper) { result = 4; break; }
+      const int32_t sl = s % R;
+      // the three source entries, read together (a slot whose score is
+      // negative is read but ignored)
+      const int32_t qx = max(s - x, 0) % R, qo = max(s - oe, 0) % R, qe = max(s - e, 0) % R;
+      const int32_t tx0 = tab[qx * ENTRY], tx1 = tab[qx * ENTRY + 1], tx2 = tab[qx * ENTRY + 2];
+      const int32_t to0 = tab[qo * ENTRY], to1 = tab[qo * ENTRY + 1], to2 = tab[qo * ENTRY + 2];
+      const int32_t te0 = tab[qe * ENTRY], te1 = tab[qe * ENTRY + 1], te2 = tab[qe * ENTRY + 2];
+      const int fx = s - x >= 0 ? (__builtin_amdgcn_readfirstlane(tx2) & 1) : 0;
+      const int fo = s - oe >= 0 ? (__builtin_amdgcn_readfirstlane(to2) & 1) : 0;
+      const int fe = s - e >= 0 ? (__builtin_amdgcn_readfirstlane(te2) & 6) : 0;
+      const int32_t xlo = __builtin_amdgcn_readfirstlane(tx0), xhi = __builtin_amdgcn_readfirstlane(tx1);
+      const int32_t olo = __builtin_amdgcn_readfirstlane(to0), ohi = __builtin_amdgcn_readfirstlane(to1);
+      const int32_t elo = __builtin_amdgcn_readfirstlane(te0), ehi = __builtin_amdgcn_readfirstlane(te1);
+      const int32_t bx = qx * W, bo = qo * W, beI = (max(s - e, 0) % RE) * W;
+      int32_t lo = INT32_MAX, hi = INT32_MIN;
+      if (fx) { lo = min(lo, xlo); hi = max(hi, xhi); }
+      if (fo) { lo = min(lo, olo); hi = max(hi, ohi); }
+      if (fe) { lo = min(lo, elo); hi = max(hi, ehi); }
+      int present = 0;
+      if (fx || fo || fe) {
+        lo = max(lo - 1, -m);
+        hi = min(hi + 1, n);
+        if (lo <= hi) present = 1 | ((fo || (fe & 2)) ? 2 : 0) | ((fo || (fe & 4)) ? 4 : 0);
+      }
+      if (present && (lo < kbase || hi >= kbase + W)) { result = 3; break; }
+      bool hit = false;  // this lane reached the end cell
+      if (present) {
+        const bool eI = fe & 2, eD = fe & 4;
+        const int32_t bM = sl * W, bID = (s % RE) * W;
+        const int32_t c_lo = (lo - kbase) >> 6, c_hi = (hi - kbase) >> 6;
+        for (int32_t c = c_lo; c <= c_hi; ++c) {
+          const int32_t idx = 64 * c + lane, k = kbase + idx;
+          // five source reads issued together, indices clamped into the window
+          const int32_t up = min(idx + 1, W - 1), dn = max(idx - 1, 0);
+          const int32_t a_ou = rM[bo + up], a_od = rM[bo + dn], a_x = rM[bx + idx];
+          const int32_t a_iu = rI[beI + up], a_dd = rD[beI + dn];
+          if (k < lo || k > hi) continue;
+          int32_t vi = (fo && k + 1 >= olo && k + 1 <= ohi) ? a_ou : NEG;
+          if (eI && k + 1 >= elo && k + 1 <= ehi) vi = max(vi, a_iu);
+          if (vi >= 0 && vi - k > m) vi = NEG;
+          int32_t vd = (fo && k - 1 >= olo && k - 1 <= ohi) ? a_od : NEG;
+          if (eD && k - 1 >= elo && k - 1 <= ehi) vd = max(vd, a_dd);
+          if (vd >= 0) { vd += 1; if (vd > n) vd = NEG; } else vd = NEG;
+          int32_t vx = (fx && k >= xlo && k <= xhi) ? a_x : NEG;
+          if (vx >= 0) { vx += 1; if (vx > n || vx - k > m) vx = NEG; } else vx = NEG;
+          if (vi < 0) vi = NEG;
+          int32_t vm = max(vx, max(vi, vd));
+          if (vm >= 0) vm = extend(Pw, pnw, m, Tw, tnw, n, k, vm);
+          rM[bM + idx] = (int16_t)(vm < 0 ? -1 : vm);
+          rI[bID + idx] = (int16_t)(vi < 0 ? -1 : vi);
+          rD[bID + idx] = (int16_t)(vd < 0 ? -1 : vd);
+          hit = hit || (k == kend && vm >= n);
+        }
+      }
+      if (lane == 0) {
+        tab[sl * ENTRY + 0] = present ? lo : 0;
+        tab[sl * ENTRY + 1] = present ? hi : -1;
+        tab[sl * ENTRY + 2] = present;
+      }
+      need += ENTRY + (present ? 3 * (int64_t)(hi - lo + 1) : 0);
+      __syncthreads();
+      if (__ballot(hit)) result = 1;
+    }
+    if (result == 3) {
+      wave_append1(true, (int32_t)p, L.ring_list, L.ring_count);
+    } else if (lane == 0) {
+      if (result == 2 || result == 4) {
+        O.score[p] = -1;
+        O.status[p] = result == 2 ? ST_REJECTED : ST_INVALID;
+        O.nruns[p] = 0;
+      } else {
+        O.score[p] = s;
+        O.status[p] = ST_ALIGNED;
+        O.nruns[p] = 0;
+        if (P.want_cigar) {
+          L.need[p] = need;
+          int cl = 0;
+          while (cl < 3 && need > L.need_cap[cl]) ++cl;
+          if (need > L.need_cap[3]) {
+            O.status[p] = ST_OVERFLOW;
+          } else {
+            const int32_t k = atomicAdd(L.need_count[cl], 1);
+            L.need_list[cl][k] = (int32_t)p;
+          }
+        }
+      }
+    }
+    }  // valid pair
+  }
+}
+
 // ---------------------------------------------------------------- pass 2
 __global__ __launch_bounds__(WGMAX) void k_wfa_trace(Seqs S, Outs O, Scoring P, Work Wk, WfaLaunch L,
                                                   int32_t *hbm) {
@@ -448,6 +616,16 @@ hipError_t launch_wfa_score(const Seqs &S, const Outs &O, const Scoring &P, cons
                      (ring_in_lds ? (size_t)L.R * 3 * L.wcap * 4 : 0);
   hipLaunchKernelGGL(k_wfa_score, dim3(nslots), dim3(threads), lds, s, S, O, P, Wk, L, hbm,
                      (int32_t)ring_in_lds);
+  return hipGetLastError();
+}
+
+size_t wfa_score16_lds(const WfaLaunch &L, int32_t e, int32_t C) {
+  return 2 * (size_t)L.seq_words * 8 + (size_t)L.R * ENTRY * 4 + (size_t)(L.R + 2 * (e + 1)) * 64 * C * 2;
+}
+
+hipError_t launch_wfa_score16(const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk,
+                              const WfaLaunch &L, int32_t C, int32_t nslots, hipStream_t s) {
+  hipLaunchKernelGGL(k_wfa_score16, dim3(nslots), dim3(64), wfa_score16_lds(L, P.e, C), s, S, O, P, Wk, L, C);
   return hipGetLastError();
 }
 
