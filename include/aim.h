@@ -195,7 +195,7 @@ aim_status aim_timing_reset(aim_context *ctx);
  * key use it.  Candidates: NW/SWG -- first band width {32, 64}, resident
  * wavefronts per CU {8, 16, 32}, length sort {off, on}, packed 16-bit cells
  * {off, on} (32 diagonals only); WFA -- LDS for the
- * score ring {16, 32, 48} KB, for the full store {24, 40} KB, workgroup size
+ * score ring {16, 32, 48} KB, for the full store {12, 16, 24} KB, workgroup size
  * for long pairs {128, 256}.  Each candidate runs once to warm up and `reps`
  * times timed (median).  Synchronous.  On return `out` holds the results of
  * the chosen configuration; best_params (7 int32, see aim_tune_get) and

@@ -193,9 +193,11 @@ constexpr int32_t WFA16_MAX_LEN = 32000;
 size_t wfa_score16_lds(const WfaLaunch &L, int32_t e, int32_t C);
 hipError_t launch_wfa_score16(const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk,
                               const WfaLaunch &L, int32_t C, int32_t nslots, hipStream_t s);
+// i16: wavefronts stored as 16-bit offsets (max_len <= WFA16_MAX_LEN); the
+// full-store sizes counted by the score passes then over-cover the store.
 hipError_t launch_wfa_trace(const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk,
                             const WfaLaunch &L, int32_t *hbm, int32_t nslots, int32_t threads,
-                            hipStream_t s);
+                            bool i16, hipStream_t s);
 
 // CIGAR compaction: cigar_off from nruns (with the cap cut), copy slot and
 // pool runs, collect pairs whose runs could not be held into the spill list.

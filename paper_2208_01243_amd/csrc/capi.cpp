@@ -91,7 +91,7 @@ struct Tune {
   int32_t band_wpc = 16;      // resident wavefronts per CU for the first band tier
   int32_t sort = -1;          // length-sort the pairs first (-1: auto)
   int32_t wfa_ring_kb = 32;   // LDS per workgroup for the WFA score ring
-  int32_t wfa_trace_kb = 40;  // LDS per workgroup for the WFA full store
+  int32_t wfa_trace_kb = 16;  // LDS per workgroup for the WFA full store
   int32_t wfa_long_threads = 256;  // workgroup size for long WFA pairs
   int32_t band16 = 3;         // packed 16-bit band kernel when the value bound allows
                               // (1: the fill walks its pairs, 2: a separate walk kernel,
@@ -307,7 +307,7 @@ aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const
     aim::Work W{WL.need_list[k], WL.need_count[k], n, cnt + C_P0 + k, nullptr, nullptr, 0};
     Phase ph(c, s, names[k]);
     HIP_TRY(aim::launch_wfa_trace(S, O, P, W, T, hbm, k == 0 ? slots : pl.arena_slots[k],
-                                  plain ? 64 : pl.threads[k], s));
+                                  plain ? 64 : pl.threads[k], w16, s));
   }
   return AIM_OK;
 }
@@ -650,7 +650,7 @@ aim_status aim_align_batch(aim_context *c, const aim_batch *B, int32_t alg, aim_
     if ((st = ensure(c, c->warena3, (size_t)pl.need_cap[3] * 4 * pl.arena_slots[3]))) return st;
     Phase ph(c, s, "wfa_rerun");
     HIP_TRY(aim::launch_wfa_trace(S, O, P, WS, WL, as<int32_t>(c->warena3), pl.arena_slots[3],
-                                  pl.threads[3], s));
+                                  pl.threads[3], L <= aim::WFA16_MAX_LEN && !plain, s));
   } else {
     if ((st = run_full(WS, n, s))) return st;
   }
@@ -697,7 +697,7 @@ aim_status aim_autotune(aim_context *c, const aim_batch *B, int32_t alg, aim_pen
   std::vector<Tune> cand;
   if (alg == AIM_WFA_AFFINE) {
     for (int ring : {16, 32, 48})
-      for (int trace : {24, 40})
+      for (int trace : {12, 16, 24})
         for (int th : {128, 256}) {
           Tune t;
           t.sort = 1;

@@ -74,7 +74,19 @@ __device__ __forceinline__ int32_t tab_get(const int32_t *tab, int32_t slot, int
 // arrays of width hi-lo+1 at dst, dst+w, dst+2w).  Source tables/arrays are
 // located through `tab`/`store` with slot(s') giving the table slot.
 // Returns present bits of the new wavefront (0: null) and its lo/hi.
-template <class SlotOf>
+// Element type of a stored wavefront component: int32, or int16 when every
+// offset fits (absent entries then read as -1; every reader treats negative
+// values as absent).  Bases in tables are in 32-bit words.
+template <class E>
+__device__ __forceinline__ E wf_put(int32_t v) {
+  return sizeof(E) == 4 ? (E)v : (E)(v < 0 ? -1 : v);
+}
+template <class E>
+__device__ __forceinline__ int32_t wf_words(int32_t elems) {
+  return sizeof(E) == 4 ? elems : (elems + 1) / 2;
+}
+
+template <class E, class SlotOf>
 __device__ __forceinline__ int wf_step(int32_t s, int32_t x, int32_t oe, int32_t e, int32_t m,
                                        int32_t n, const int32_t *tab, const int32_t *store,
                                        SlotOf slot_of, int32_t *dst_base_store, int32_t dst_base,
@@ -116,29 +128,32 @@ __device__ __forceinline__ int wf_step(int32_t s, int32_t x, int32_t oe, int32_t
   const int32_t elo = fe ? tab_get(tab, se, 0) : 0, ehi = fe ? tab_get(tab, se, 1) : -1;
   const int32_t eb = fe ? tab_get(tab, se, 2) : 0, ew = ehi - elo + 1;
   const bool eI = fe & 2, eD = fe & 4;
-  int32_t *dM = dst_base_store + dst_base;
-  int32_t *dI = dM + w;
-  int32_t *dD = dI + w;
+  E *dM = reinterpret_cast<E *>(dst_base_store + dst_base);
+  E *dI = dM + w;
+  E *dD = dI + w;
+  const E *so_ = reinterpret_cast<const E *>(store + ob);
+  const E *se_ = reinterpret_cast<const E *>(store + eb);
+  const E *sx_ = reinterpret_cast<const E *>(store + xb);
   const int32_t nt = (int32_t)blockDim.x;
   for (int32_t k = lo + lane; k <= hi; k += nt) {
     int32_t vi = NEG, vd = NEG, vx = NEG;
     // I: from k + 1
-    if (fo && k + 1 >= olo && k + 1 <= ohi) vi = store[ob + (k + 1 - olo)];
-    if (eI && k + 1 >= elo && k + 1 <= ehi) vi = max(vi, store[eb + ew + (k + 1 - elo)]);
+    if (fo && k + 1 >= olo && k + 1 <= ohi) vi = so_[k + 1 - olo];
+    if (eI && k + 1 >= elo && k + 1 <= ehi) vi = max(vi, (int32_t)se_[ew + (k + 1 - elo)]);
     if (vi >= 0 && vi - k > m) vi = NEG;
     // D: from k - 1
-    if (fo && k - 1 >= olo && k - 1 <= ohi) vd = store[ob + (k - 1 - olo)];
-    if (eD && k - 1 >= elo && k - 1 <= ehi) vd = max(vd, store[eb + 2 * ew + (k - 1 - elo)]);
+    if (fo && k - 1 >= olo && k - 1 <= ohi) vd = so_[k - 1 - olo];
+    if (eD && k - 1 >= elo && k - 1 <= ehi) vd = max(vd, (int32_t)se_[2 * ew + (k - 1 - elo)]);
     if (vd >= 0) { vd += 1; if (vd > n) vd = NEG; } else vd = NEG;
     // X: from k
-    if (fx && k >= xlo && k <= xhi) vx = store[xb + (k - xlo)];
+    if (fx && k >= xlo && k <= xhi) vx = sx_[k - xlo];
     if (vx >= 0) { vx += 1; if (vx > n || vx - k > m) vx = NEG; } else vx = NEG;
     if (vi < 0) vi = NEG;
     int32_t vm = max(vx, max(vi, vd));
     if (vm >= 0) vm = extend(P, pnw, m, T, tnw, n, k, vm);
-    dM[k - lo] = vm;
-    dI[k - lo] = vi;
-    dD[k - lo] = vd;
+    dM[k - lo] = wf_put<E>(vm);
+    dI[k - lo] = wf_put<E>(vi);
+    dD[k - lo] = wf_put<E>(vd);
   }
   lo_out = lo;
   hi_out = hi;
@@ -217,7 +232,7 @@ __global__ __launch_bounds__(WGMAX) void k_wfa_score(Seqs S, Outs O, Scoring P, 
         present = 1;
         lo = hi = 0;
       } else {
-        present = wf_step(s, x, oe, e, m, n, tab_ring, ring, slot_of, ring, sl * 3 * L.wcap, L.wcap,
+        present = wf_step<int32_t>(s, x, oe, e, m, n, tab_ring, ring, slot_of, ring, sl * 3 * L.wcap, L.wcap,
                           lo, hi, Pw, pnw, Tw, tnw, overflow);
       }
       if (overflow) { result = 3; break; }
@@ -333,7 +348,7 @@ __global__ __launch_bounds__(64) void k_wfa_score16(Seqs S, Outs O, Scoring P, W
         tab[1] = 0;
         tab[2] = 1;
       }
-      need = ENTRY + 3;
+      need = ENTRY + 2;  // s = 0: three 16-bit entries
       __syncthreads();
       if (kend == 0 && __builtin_amdgcn_readfirstlane((int32_t)rM[0 - kbase]) >= n) result = 1;
     }
@@ -400,7 +415,7 @@ __global__ __launch_bounds__(64) void k_wfa_score16(Seqs S, Outs O, Scoring P, W
         tab[sl * ENTRY + 1] = present ? hi : -1;
         tab[sl * ENTRY + 2] = present;
       }
-      need += ENTRY + (present ? 3 * (int64_t)(hi - lo + 1) : 0);
+      need += ENTRY + (present ? (3 * (int64_t)(hi - lo + 1) + 1) / 2 : 0);  // 16-bit store
       __syncthreads();
       if (__ballot(hit)) result = 1;
     }
@@ -433,6 +448,7 @@ __global__ __launch_bounds__(64) void k_wfa_score16(Seqs S, Outs O, Scoring P, W
 }
 
 // ---------------------------------------------------------------- pass 2
+template <class E>
 __global__ __launch_bounds__(WGMAX) void k_wfa_trace(Seqs S, Outs O, Scoring P, Work Wk, WfaLaunch L,
                                                   int32_t *hbm) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -475,12 +491,12 @@ __global__ __launch_bounds__(WGMAX) void k_wfa_trace(Seqs S, Outs O, Scoring P, 
       int present;
       bool overflow = false;
       if (s == 0) {
-        if (lane == 0) arena[base] = extend(Pw, pnw, m, Tw, tnw, n, 0, 0);
+        if (lane == 0) reinterpret_cast<E *>(arena + base)[0] = wf_put<E>(extend(Pw, pnw, m, Tw, tnw, n, 0, 0));
         present = 1;
         lo = hi = 0;
       } else {
-        present = wf_step(s, x, oe, e, m, n, tab, arena, slot_of, arena, base, INT32_MAX, lo, hi,
-                          Pw, pnw, Tw, tnw, overflow);
+        present = wf_step<E>(s, x, oe, e, m, n, tab, arena, slot_of, arena, base, INT32_MAX, lo, hi,
+                             Pw, pnw, Tw, tnw, overflow);
       }
       __syncthreads();
       if (lane == 0) {
@@ -488,7 +504,7 @@ __global__ __launch_bounds__(WGMAX) void k_wfa_trace(Seqs S, Outs O, Scoring P, 
         tab[s * ENTRY + 1] = hi;
         tab[s * ENTRY + 2] = base;
         tab[s * ENTRY + 3] = present;
-        if (present) sh_top = base + 3 * (hi - lo + 1);
+        if (present) sh_top = base + wf_words<E>(3 * (hi - lo + 1));
       }
       __syncthreads();
     }
@@ -523,7 +539,7 @@ __global__ __launch_bounds__(WGMAX) void k_wfa_trace(Seqs S, Outs O, Scoring P, 
         if (s2 < 0) return NEG;
         const int32_t lo = tab[s2 * ENTRY], hi = tab[s2 * ENTRY + 1], pr = tab[s2 * ENTRY + 3];
         if (!(pr & (1 << comp)) || k < lo || k > hi) return NEG;
-        return arena[tab[s2 * ENTRY + 2] + comp * (hi - lo + 1) + (k - lo)];
+        return (int32_t)reinterpret_cast<const E *>(arena + tab[s2 * ENTRY + 2])[comp * (hi - lo + 1) + (k - lo)];
       };
       int32_t k = n - m, f = n, comp = 0;
       // each step emits one op or closes a run; the walk has at most m + n ops
@@ -631,9 +647,12 @@ hipError_t launch_wfa_score16(const Seqs &S, const Outs &O, const Scoring &P, co
 
 hipError_t launch_wfa_trace(const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk,
                             const WfaLaunch &L, int32_t *hbm, int32_t nslots, int32_t threads,
-                            hipStream_t s) {
+                            bool i16, hipStream_t s) {
   const size_t lds = 2 * (size_t)L.seq_words * 8 + (L.full_in_lds ? (size_t)L.slot_words * 4 : 0);
-  hipLaunchKernelGGL(k_wfa_trace, dim3(nslots), dim3(threads), lds, s, S, O, P, Wk, L, hbm);
+  if (i16)
+    hipLaunchKernelGGL(k_wfa_trace<int16_t>, dim3(nslots), dim3(threads), lds, s, S, O, P, Wk, L, hbm);
+  else
+    hipLaunchKernelGGL(k_wfa_trace<int32_t>, dim3(nslots), dim3(threads), lds, s, S, O, P, Wk, L, hbm);
   return hipGetLastError();
 }
 
