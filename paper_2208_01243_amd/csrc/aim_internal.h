@@ -170,14 +170,21 @@ struct WfaLaunch {
   int32_t *need_list[4];  // pass 1 -> pass 2: accepted pairs by full-store class
   int32_t *need_count[4];
   int64_t need_cap[4];    // class capacities in words
+  int32_t *need_max[4];   // pass 1 -> pass 2: largest full store per class (words)
   int64_t *need;          // per pair: words of the full store
+  int32_t store16;        // pass 1 counts the full store in 16-bit entries
+  // pass 2, HBM arena: when set, each workgroup's slot is the class's largest
+  // full store (rounded up), and only pool_words / slot workgroups take pairs
+  const int32_t *slot_need_max;
+  int64_t pool_words;
 };
 
 struct WfaPlan {
   int32_t R, wcap, wcap_lds, seq_words, lds_score_bytes, ring_slots, ring_threads, lds_arena_words;
   int64_t ring_slot_words;
   int64_t need_cap[4];
-  int32_t arena_slots[4];
+  int64_t pool_words[4];  // HBM arena per class (words)
+  int32_t arena_slots[4];  // workgroups launched per class
   int32_t threads[4];
 };
 

@@ -173,6 +173,7 @@ struct DeviceGuard {
 enum Counter {
   C_T1 = 0, C_T2, C_T3, C_L2, C_L3, C_SPILL, C_SPILL_W,
   C_W1, C_W1G, C_RL, C_FAIL, C_N0, C_N1, C_N2, C_N3, C_P0, C_P1, C_P2, C_P3, C_TB, C_DTB,
+  C_M0, C_M1, C_M2, C_M3,
   C_N = 32
 };
 
@@ -256,6 +257,7 @@ aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const
     WL.need_list[k] = lists + (int64_t)n * (k + 1);
     WL.need_count[k] = cnt + C_N0 + k;
     WL.need_cap[k] = pl.need_cap[k];
+    WL.need_max[k] = cnt + C_M0 + k;
   }
   WL.need = as<int64_t>(c->wneed);
   const int32_t slots = (int32_t)std::min<int64_t>(n, (int64_t)c->cus * 8);
@@ -263,6 +265,7 @@ aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const
   const int32_t C16 = (int32_t)std::min<int64_t>(4, std::max<int64_t>(1, (pl.wcap + 63) / 64));
   const bool w16 = !plain && L <= aim::WFA16_MAX_LEN && pl.R <= 32 &&
                    aim::wfa_score16_lds(WL, P.e, C16) <= 48 * 1024;
+  WL.store16 = w16;  // the full store of pass 2 holds 16-bit offsets
   if (w16) {
     aim::Work W{order, nullptr, n, cnt + C_W1, nullptr, nullptr, 0};
     Phase ph(c, s, "wfa_score");
@@ -301,12 +304,17 @@ aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const
     T.slot_words = k == 0 ? pl.lds_arena_words : pl.need_cap[k];
     int32_t *hbm = nullptr;
     if (k > 0) {
-      if ((st = ensure(c, *arena[k], (size_t)pl.need_cap[k] * 4 * pl.arena_slots[k]))) return st;
+      if ((st = ensure(c, *arena[k], (size_t)pl.pool_words[k] * 4))) return st;
       hbm = as<int32_t>(*arena[k]);
+      T.slot_need_max = WL.need_max[k];
+      T.pool_words = pl.pool_words[k];
     }
     aim::Work W{WL.need_list[k], WL.need_count[k], n, cnt + C_P0 + k, nullptr, nullptr, 0};
     Phase ph(c, s, names[k]);
-    HIP_TRY(aim::launch_wfa_trace(S, O, P, W, T, hbm, k == 0 ? slots : pl.arena_slots[k],
+    // the LDS class: as many workgroups as the LDS of a CU holds (up to 20)
+    const int32_t lds_slots = (int32_t)std::min<int64_t>(
+        n, (int64_t)c->cus * std::max(1, std::min(20, 160 / std::max(1, tu.wfa_trace_kb))));
+    HIP_TRY(aim::launch_wfa_trace(S, O, P, W, T, hbm, k == 0 ? lds_slots : pl.arena_slots[k],
                                   plain ? 64 : pl.threads[k], w16, s));
   }
   return AIM_OK;
@@ -647,9 +655,10 @@ aim_status aim_align_batch(aim_context *c, const aim_batch *B, int32_t alg, aim_
     WL.full_in_lds = 0;
     WL.slot_words = pl.need_cap[3];
     WL.need = as<int64_t>(c->wneed);
-    if ((st = ensure(c, c->warena3, (size_t)pl.need_cap[3] * 4 * pl.arena_slots[3]))) return st;
+    if ((st = ensure(c, c->warena3, (size_t)pl.pool_words[3] * 4))) return st;
+    const int32_t rslots = (int32_t)std::max<int64_t>(1, pl.pool_words[3] / pl.need_cap[3]);
     Phase ph(c, s, "wfa_rerun");
-    HIP_TRY(aim::launch_wfa_trace(S, O, P, WS, WL, as<int32_t>(c->warena3), pl.arena_slots[3],
+    HIP_TRY(aim::launch_wfa_trace(S, O, P, WS, WL, as<int32_t>(c->warena3), rslots,
                                   pl.threads[3], L <= aim::WFA16_MAX_LEN && !plain, s));
   } else {
     if ((st = run_full(WS, n, s))) return st;

@@ -134,26 +134,50 @@ __device__ __forceinline__ int wf_step(int32_t s, int32_t x, int32_t oe, int32_t
   const E *so_ = reinterpret_cast<const E *>(store + ob);
   const E *se_ = reinterpret_cast<const E *>(store + eb);
   const E *sx_ = reinterpret_cast<const E *>(store + xb);
+  // Source reads are issued for U diagonals per lane before any of them is
+  // extended, so that up to 5 U loads are in flight.  Each index is clamped
+  // into its source array (an absent source has base 0 and reads element 0 of
+  // the store), and a value is used only under the bounds test of its source.
+  constexpr int U = 4;
+  const int32_t owm = max(ohi - olo, 0), ewm = max(ew - 1, 0), xwm = max(xhi - xlo, 0);
   const int32_t nt = (int32_t)blockDim.x;
-  for (int32_t k = lo + lane; k <= hi; k += nt) {
-    int32_t vi = NEG, vd = NEG, vx = NEG;
-    // I: from k + 1
-    if (fo && k + 1 >= olo && k + 1 <= ohi) vi = so_[k + 1 - olo];
-    if (eI && k + 1 >= elo && k + 1 <= ehi) vi = max(vi, (int32_t)se_[ew + (k + 1 - elo)]);
-    if (vi >= 0 && vi - k > m) vi = NEG;
-    // D: from k - 1
-    if (fo && k - 1 >= olo && k - 1 <= ohi) vd = so_[k - 1 - olo];
-    if (eD && k - 1 >= elo && k - 1 <= ehi) vd = max(vd, (int32_t)se_[2 * ew + (k - 1 - elo)]);
-    if (vd >= 0) { vd += 1; if (vd > n) vd = NEG; } else vd = NEG;
-    // X: from k
-    if (fx && k >= xlo && k <= xhi) vx = sx_[k - xlo];
-    if (vx >= 0) { vx += 1; if (vx > n || vx - k > m) vx = NEG; } else vx = NEG;
-    if (vi < 0) vi = NEG;
-    int32_t vm = max(vx, max(vi, vd));
-    if (vm >= 0) vm = extend(P, pnw, m, T, tnw, n, k, vm);
-    dM[k - lo] = wf_put<E>(vm);
-    dI[k - lo] = wf_put<E>(vi);
-    dD[k - lo] = wf_put<E>(vd);
+  for (int32_t kb = lo; kb <= hi; kb += U * nt) {  // kb: uniform batch start
+    int32_t a_ou[U], a_ie[U], a_od[U], a_de[U], a_x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      a_ou[u] = a_ie[u] = a_od[u] = a_de[u] = a_x[u] = NEG;
+      if (kb + u * nt <= hi) {
+        const int32_t k = kb + u * nt + lane;
+        a_ou[u] = so_[min(max(k + 1 - olo, 0), owm)];
+        a_ie[u] = se_[ew + min(max(k + 1 - elo, 0), ewm)];
+        a_od[u] = so_[min(max(k - 1 - olo, 0), owm)];
+        a_de[u] = se_[2 * ew + min(max(k - 1 - elo, 0), ewm)];
+        a_x[u] = sx_[min(max(k - xlo, 0), xwm)];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int32_t k = kb + u * nt + lane;
+      if (k > hi) continue;
+      int32_t vi = NEG, vd = NEG, vx = NEG;
+      // I: from k + 1
+      if (fo && k + 1 >= olo && k + 1 <= ohi) vi = a_ou[u];
+      if (eI && k + 1 >= elo && k + 1 <= ehi) vi = max(vi, a_ie[u]);
+      if (vi >= 0 && vi - k > m) vi = NEG;
+      // D: from k - 1
+      if (fo && k - 1 >= olo && k - 1 <= ohi) vd = a_od[u];
+      if (eD && k - 1 >= elo && k - 1 <= ehi) vd = max(vd, a_de[u]);
+      if (vd >= 0) { vd += 1; if (vd > n) vd = NEG; } else vd = NEG;
+      // X: from k
+      if (fx && k >= xlo && k <= xhi) vx = a_x[u];
+      if (vx >= 0) { vx += 1; if (vx > n || vx - k > m) vx = NEG; } else vx = NEG;
+      if (vi < 0) vi = NEG;
+      int32_t vm = max(vx, max(vi, vd));
+      if (vm >= 0) vm = extend(P, pnw, m, T, tnw, n, k, vm);
+      dM[k - lo] = wf_put<E>(vm);
+      dI[k - lo] = wf_put<E>(vi);
+      dD[k - lo] = wf_put<E>(vd);
+    }
   }
   lo_out = lo;
   hi_out = hi;
@@ -243,7 +267,12 @@ __global__ __launch_bounds__(WGMAX) void k_wfa_score(Seqs S, Outs O, Scoring P, 
         tab_ring[sl * ENTRY + 2] = sl * 3 * L.wcap;
         tab_ring[sl * ENTRY + 3] = present;
       }
-      need += ENTRY + (present ? 3 * (int64_t)(hi - lo + 1) : 0);
+      if (present) {
+        const int64_t w3 = 3 * (int64_t)(hi - lo + 1);
+        need += ENTRY + (L.store16 ? (w3 + 1) / 2 : w3);
+      } else {
+        need += ENTRY;
+      }
       __syncthreads();
       if (present && kend >= lo && kend <= hi && ring[sl * 3 * L.wcap + (kend - lo)] >= n) {
         result = 1;
@@ -272,6 +301,7 @@ __global__ __launch_bounds__(WGMAX) void k_wfa_score(Seqs S, Outs O, Scoring P, 
           } else {
             const int32_t k = atomicAdd(L.need_count[c], 1);
             L.need_list[c][k] = (int32_t)p;
+            atomicMax(L.need_max[c], (int32_t)need);
           }
         }
       }
@@ -439,6 +469,7 @@ __global__ __launch_bounds__(64) void k_wfa_score16(Seqs S, Outs O, Scoring P, W
           } else {
             const int32_t k = atomicAdd(L.need_count[cl], 1);
             L.need_list[cl][k] = (int32_t)p;
+            atomicMax(L.need_max[cl], (int32_t)need);
           }
         }
       }
@@ -456,11 +487,27 @@ __global__ __launch_bounds__(WGMAX) void k_wfa_trace(Seqs S, Outs O, Scoring P, 
   const int lane = threadIdx.x;
   uint64_t *sP = (uint64_t *)smem;
   uint64_t *sT = sP + L.seq_words;
-  int32_t *arena = L.full_in_lds ? (int32_t *)(sT + L.seq_words) : (hbm + (int64_t)blockIdx.x * L.slot_words);
   const int32_t x = P.x, o = P.o, oe = P.o + P.e, e = P.e;
   const int64_t count = Wk.count ? (int64_t)(*(volatile const int32_t *)Wk.count) : Wk.n;
-  // a workgroup the work can never reach leaves before touching the counter
-  if ((int64_t)blockIdx.x * 1 >= count) return;
+  // HBM slots sized by the largest full store of this launch's pairs: as many
+  // workgroups take pairs as such slots fit the pool (at least one, since the
+  // pool holds the class capacity)
+  int64_t slot_words = L.slot_words, nslots = gridDim.x;
+  if (!L.full_in_lds && L.slot_need_max) {
+    const int64_t mx = *(volatile const int32_t *)L.slot_need_max;
+    slot_words = (max<int64_t>(mx, 1) + 63) / 64 * 64;
+    nslots = min<int64_t>(nslots, L.pool_words / slot_words);
+  }
+  // a workgroup the work can never reach, or without a slot, leaves before
+  // touching the counter
+  if ((int64_t)blockIdx.x >= min<int64_t>(count, nslots)) return;
+  int32_t *arena = L.full_in_lds ? (int32_t *)(sT + L.seq_words) : (hbm + (int64_t)blockIdx.x * slot_words);
+  // With the store in HBM, the entries of the last R scores are also kept in
+  // an LDS ring, from which the steps read their sources; the full table in
+  // HBM serves the backtrace.
+  const bool ring = !L.full_in_lds;
+  const int32_t R = L.R;
+  int32_t *tab_ring = (int32_t *)(sT + L.seq_words);
   for (;;) {
     __syncthreads();
     if (lane == 0) sh_pair = atomicAdd(Wk.counter, 1);
@@ -484,7 +531,8 @@ __global__ __launch_bounds__(WGMAX) void k_wfa_trace(Seqs S, Outs O, Scoring P, 
     const int32_t data0 = (sfin + 1) * ENTRY;
     if (lane == 0) sh_top = data0;
     __syncthreads();
-    auto slot_of = [&](int32_t s2) { return s2; };
+    const int32_t *stab = ring ? tab_ring : tab;
+    auto slot_of = [&](int32_t s2) { return ring ? s2 % R : s2; };
     for (int32_t s = 0; s <= sfin; ++s) {
       const int32_t base = sh_top;
       int32_t lo = 0, hi = -1;
@@ -495,7 +543,7 @@ __global__ __launch_bounds__(WGMAX) void k_wfa_trace(Seqs S, Outs O, Scoring P, 
         present = 1;
         lo = hi = 0;
       } else {
-        present = wf_step<E>(s, x, oe, e, m, n, tab, arena, slot_of, arena, base, INT32_MAX, lo, hi,
+        present = wf_step<E>(s, x, oe, e, m, n, stab, arena, slot_of, arena, base, INT32_MAX, lo, hi,
                              Pw, pnw, Tw, tnw, overflow);
       }
       __syncthreads();
@@ -504,6 +552,13 @@ __global__ __launch_bounds__(WGMAX) void k_wfa_trace(Seqs S, Outs O, Scoring P, 
         tab[s * ENTRY + 1] = hi;
         tab[s * ENTRY + 2] = base;
         tab[s * ENTRY + 3] = present;
+        if (ring) {
+          const int32_t q = s % R;
+          tab_ring[q * ENTRY + 0] = lo;
+          tab_ring[q * ENTRY + 1] = hi;
+          tab_ring[q * ENTRY + 2] = base;
+          tab_ring[q * ENTRY + 3] = present;
+        }
         if (present) sh_top = base + wf_words<E>(3 * (hi - lo + 1));
       }
       __syncthreads();
@@ -587,7 +642,7 @@ __global__ __launch_bounds__(WGMAX) void k_wfa_trace(Seqs S, Outs O, Scoring P, 
 
 WfaPlan wfa_plan(int32_t max_len, const Scoring &P, int64_t budget_bytes, int32_t cus, bool plain,
                  int32_t ring_kb, int32_t trace_kb, int32_t long_threads) {
-  // budget split: HBM rings 1/8, arena classes 1/16, 1/8 and 1/2
+  // budget split: HBM rings 1/8, arena classes 1/16, 1/4 and 1/2
   WfaPlan pl{};
   const int32_t oe = P.o + P.e;
   pl.R = std::max(P.x, oe) + 1;
@@ -606,8 +661,8 @@ WfaPlan wfa_plan(int32_t max_len, const Scoring &P, int64_t budget_bytes, int32_
   pl.ring_slots = (int32_t)std::max<int64_t>(
       1, std::min<int64_t>((int64_t)cus * 4, budget_bytes / 8 / (pl.ring_slot_words * 4)));
   pl.ring_threads = max_len > 1024 ? long_threads : 64;
-  // full-store arena classes (words): LDS, then HBM slots of 1 MB, 16 MB and
-  // 192 MB, with fewer and wider workgroups for the larger classes
+  // full-store arena classes (words): LDS, then HBM stores of up to 1 MB,
+  // 16 MB and 192 MB, with wider workgroups for the larger classes
   pl.lds_arena_words = plain ? 0 : (int32_t)((lds_trace - 2 * (int64_t)pl.seq_words * 8) / 4);
   pl.need_cap[0] = pl.lds_arena_words;
   pl.need_cap[1] = (int64_t)1 << 18;
@@ -615,10 +670,16 @@ WfaPlan wfa_plan(int32_t max_len, const Scoring &P, int64_t budget_bytes, int32_
   pl.need_cap[3] = std::max<int64_t>(pl.need_cap[2], std::min<int64_t>((int64_t)48 << 20, budget_bytes / 2 / 4));
   pl.arena_slots[0] = cus * 8;
   pl.threads[0] = 64;
-  const int64_t share[4] = {0, budget_bytes / 16, budget_bytes / 8, budget_bytes / 2};
-  const int64_t cap_slots[4] = {0, (int64_t)cus * 8, (int64_t)cus * 2, (int64_t)cus};
-  for (int k = 1; k < 4; ++k)
-    pl.arena_slots[k] = (int32_t)std::max<int64_t>(1, std::min<int64_t>(cap_slots[k], share[k] / (pl.need_cap[k] * 4)));
+  // pools: 1/16, 1/4 and 1/2 of the budget, each at least one slot of its
+  // class capacity; the workgroups that take pairs are those whose slot (the
+  // class's largest store) fits the pool
+  const int64_t share[4] = {0, budget_bytes / 16, budget_bytes / 4, budget_bytes / 2};
+  const int64_t cap_slots[4] = {0, (int64_t)cus * 8, (int64_t)cus * 4, (int64_t)cus * 4};
+  for (int k = 1; k < 4; ++k) {
+    const int64_t cap = (pl.need_cap[k] + 63) / 64 * 64;
+    pl.pool_words[k] = std::max<int64_t>(cap, std::min<int64_t>(share[k] / 4, cap_slots[k] * cap));
+    pl.arena_slots[k] = (int32_t)cap_slots[k];
+  }
   pl.threads[1] = 64;
   pl.threads[2] = long_threads;
   pl.threads[3] = long_threads;
@@ -648,7 +709,8 @@ hipError_t launch_wfa_score16(const Seqs &S, const Outs &O, const Scoring &P, co
 hipError_t launch_wfa_trace(const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk,
                             const WfaLaunch &L, int32_t *hbm, int32_t nslots, int32_t threads,
                             bool i16, hipStream_t s) {
-  const size_t lds = 2 * (size_t)L.seq_words * 8 + (L.full_in_lds ? (size_t)L.slot_words * 4 : 0);
+  const size_t lds = 2 * (size_t)L.seq_words * 8 +
+                     (L.full_in_lds ? (size_t)L.slot_words * 4 : (size_t)L.R * ENTRY * 4);
   if (i16)
     hipLaunchKernelGGL(k_wfa_trace<int16_t>, dim3(nslots), dim3(threads), lds, s, S, O, P, Wk, L, hbm);
   else
