@@ -177,6 +177,11 @@ struct WfaLaunch {
   // full store (rounded up), and only pool_words / slot workgroups take pairs
   const int32_t *slot_need_max;
   int64_t pool_words;
+  // one-wavefront score pass with a CIGAR wanted: per workgroup, room for the
+  // origin codes of bits_steps scores (0: none); pairs that need more go to
+  // pass 2
+  uint8_t *bits;
+  int32_t bits_steps;
 };
 
 struct WfaPlan {
@@ -194,9 +199,12 @@ hipError_t launch_wfa_score(const Seqs &S, const Outs &O, const Scoring &P, cons
                             const WfaLaunch &L, int32_t *hbm, bool ring_in_lds, int32_t nslots,
                             int32_t threads, hipStream_t s);
 // Pass 1 by one wavefront per pair with 16-bit offsets in LDS over a window of
-// 64 C diagonals (C <= 4); needs max_len <= WFA16_MAX_LEN.  Pairs that leave
-// the window go to L.ring_list.
+// 64 C diagonals (C <= 4); needs max_len <= WFA16_MAX_LEN and L.seq_words > 0
+// (sequences staged in LDS).  Pairs that leave the window go to L.ring_list.
 constexpr int32_t WFA16_MAX_LEN = 32000;
+// Scores whose origin codes the one-wavefront pass keeps for its fused walk
+// (32 bytes per 64 diagonals per score and workgroup).
+constexpr int32_t WFA16_WALK_STEPS = 2048;
 size_t wfa_score16_lds(const WfaLaunch &L, int32_t e, int32_t C);
 hipError_t launch_wfa_score16(const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk,
                               const WfaLaunch &L, int32_t C, int32_t nslots, hipStream_t s);

@@ -121,7 +121,8 @@ struct aim_context {
   int64_t generation = 0;       // bumped whenever scratch is reallocated
   Buf order, hist;
   Buf flags, pflag, tflag, pat2, txt2, pat2off, txt2off, nruns, slot, tb32, tb64, full, list2,
-      list3, counters, scan_tmp, spill, total, wring, warena1, warena2, warena3, wneed, wlists, pool, pooloff;
+      list3, counters, scan_tmp, spill, total, wring, warena1, warena2, warena3, wneed, wlists, pool, pooloff,
+      wbits;
 };
 
 namespace {
@@ -263,14 +264,23 @@ aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const
   const int32_t slots = (int32_t)std::min<int64_t>(n, (int64_t)c->cus * 8);
   // one wavefront per pair with 16-bit offsets over a window of 64 C diagonals
   const int32_t C16 = (int32_t)std::min<int64_t>(4, std::max<int64_t>(1, (pl.wcap + 63) / 64));
-  const bool w16 = !plain && L <= aim::WFA16_MAX_LEN && pl.R <= 32 &&
+  const bool w16 = !plain && L <= aim::WFA16_MAX_LEN && pl.R <= 32 && pl.seq_words > 0 &&
                    aim::wfa_score16_lds(WL, P.e, C16) <= 48 * 1024;
   WL.store16 = w16;  // the full store of pass 2 holds 16-bit offsets
   if (w16) {
+    const int32_t nslots16 = (int32_t)std::min<int64_t>(n, (int64_t)c->cus * 20);
+    aim::WfaLaunch A = WL;
+    if (P.want_cigar) {
+      // origin codes for the fused walk: every score up to the threshold, at
+      // most WFA16_WALK_STEPS (pairs above go to the full-store pass)
+      A.bits_steps = P.max_score >= 0 ? std::min(P.max_score + 1, aim::WFA16_WALK_STEPS)
+                                      : aim::WFA16_WALK_STEPS;
+      if ((st = ensure(c, c->wbits, (size_t)nslots16 * A.bits_steps * C16 * 32))) return st;
+      A.bits = as<uint8_t>(c->wbits);
+    }
     aim::Work W{order, nullptr, n, cnt + C_W1, nullptr, nullptr, 0};
     Phase ph(c, s, "wfa_score");
-    HIP_TRY(aim::launch_wfa_score16(S, O, P, W, WL, C16,
-                                    (int32_t)std::min<int64_t>(n, (int64_t)c->cus * 20), s));
+    HIP_TRY(aim::launch_wfa_score16(S, O, P, W, A, C16, nslots16, s));
   } else if (!plain && pl.wcap_lds > 0) {
     aim::WfaLaunch A = WL;
     A.wcap = pl.wcap_lds;
@@ -394,7 +404,7 @@ void aim_destroy(aim_context *c) {
   Buf *all[] = {&c->order, &c->hist, &c->flags, &c->pflag, &c->tflag, &c->pat2, &c->txt2, &c->pat2off, &c->txt2off,
                 &c->nruns, &c->slot, &c->tb32, &c->tb64, &c->full, &c->list2, &c->list3,
                 &c->counters, &c->scan_tmp, &c->spill, &c->total, &c->wring, &c->warena1,
-                &c->warena2, &c->warena3, &c->wneed, &c->wlists, &c->pool, &c->pooloff};
+                &c->warena2, &c->warena3, &c->wneed, &c->wlists, &c->pool, &c->pooloff, &c->wbits};
   for (Buf *b : all)
     if (b->p) (void)hipFree(b->p);
   if (c->ev_join) (void)hipEventDestroy(c->ev_join);

@@ -36,6 +36,8 @@ namespace {
 constexpr int32_t NEG = INT32_MIN / 4;  // absent / invalid offset
 constexpr int WGMAX = 256;             // largest workgroup (wide pairs)
 constexpr int ENTRY = 4;                // table entry: lo, hi, base, present-bits
+constexpr int TAB16 = 8;                // one-wavefront score pass: ranges of I, D, M
+constexpr int32_t EMPTY_LO = 0x3fffffff, EMPTY_HI = -0x3fffffff;  // an empty range
 
 
 
@@ -66,8 +68,49 @@ __device__ __forceinline__ int32_t extend(const uint64_t *P, int64_t pnw, int32_
   return j;
 }
 
+// Sequence access for the extend step: words read in place (HBM or LDS), or
+// staged in LDS and compared 16 bases at a time.
+struct SeqInPlace {
+  const uint64_t *P, *T;
+  int64_t pnw, tnw;
+  __device__ __forceinline__ int32_t ext(int32_t m, int32_t n, int32_t k, int32_t f) const;
+};
+struct SeqStaged {
+  const uint32_t *P32, *T32;
+  __device__ __forceinline__ int32_t ext(int32_t m, int32_t n, int32_t k, int32_t f) const;
+};
+
 __device__ __forceinline__ int32_t tab_get(const int32_t *tab, int32_t slot, int f) {
   return tab[slot * ENTRY + f];
+}
+
+// extend() on sequences staged in LDS, 16 bases per step: the 32-bit window
+// at any base is one funnel shift of two adjacent 32-bit words.  It reads up
+// to one word past a sequence's last; the staged layout keeps that read inside
+// the workgroup's LDS, and bases past either end are cut by the limit.
+__device__ __forceinline__ int32_t extend_lds(const uint32_t *P32, int32_t m, const uint32_t *T32,
+                                              int32_t n, int32_t k, int32_t f) {
+  int32_t i = f - k, j = f;
+  for (;;) {
+    const int32_t lim = min(m - i, n - j);
+    if (lim <= 0) break;
+    const uint32_t pw = __builtin_amdgcn_alignbit(P32[(i >> 4) + 1], P32[i >> 4], (uint32_t)(i & 15) * 2);
+    const uint32_t tw = __builtin_amdgcn_alignbit(T32[(j >> 4) + 1], T32[j >> 4], (uint32_t)(j & 15) * 2);
+    const uint32_t d = pw ^ tw;
+    int32_t run = d ? (int32_t)(__builtin_ctz(d) >> 1) : 16;
+    if (run > lim) run = lim;
+    i += run;
+    j += run;
+    if (run < 16) break;
+  }
+  return j;
+}
+
+__device__ __forceinline__ int32_t SeqInPlace::ext(int32_t m, int32_t n, int32_t k, int32_t f) const {
+  return extend(P, pnw, m, T, tnw, n, k, f);
+}
+__device__ __forceinline__ int32_t SeqStaged::ext(int32_t m, int32_t n, int32_t k, int32_t f) const {
+  return extend_lds(P32, m, T32, n, k, f);
 }
 
 // One wavefront step: compute components of score s into `dst` (three
@@ -86,13 +129,12 @@ __device__ __forceinline__ int32_t wf_words(int32_t elems) {
   return sizeof(E) == 4 ? elems : (elems + 1) / 2;
 }
 
-template <class E, class SlotOf>
+template <class E, class Q, class SlotOf>
 __device__ __forceinline__ int wf_step(int32_t s, int32_t x, int32_t oe, int32_t e, int32_t m,
                                        int32_t n, const int32_t *tab, const int32_t *store,
                                        SlotOf slot_of, int32_t *dst_base_store, int32_t dst_base,
                                        int32_t wlimit, int32_t &lo_out, int32_t &hi_out,
-                                       const uint64_t *P, int64_t pnw, const uint64_t *T,
-                                       int64_t tnw, bool &overflow) {
+                                       const Q &q, bool &overflow) {
   const int lane = threadIdx.x;
   int sx = -1, so = -1, se = -1;
   int fx = 0, fo = 0, fe = 0;
@@ -173,7 +215,7 @@ __device__ __forceinline__ int wf_step(int32_t s, int32_t x, int32_t oe, int32_t
       if (vx >= 0) { vx += 1; if (vx > n || vx - k > m) vx = NEG; } else vx = NEG;
       if (vi < 0) vi = NEG;
       int32_t vm = max(vx, max(vi, vd));
-      if (vm >= 0) vm = extend(P, pnw, m, T, tnw, n, k, vm);
+      if (vm >= 0) vm = q.ext(m, n, k, vm);
       dM[k - lo] = wf_put<E>(vm);
       dI[k - lo] = wf_put<E>(vi);
       dD[k - lo] = wf_put<E>(vd);
@@ -225,12 +267,10 @@ __global__ __launch_bounds__(WGMAX) void k_wfa_score(Seqs S, Outs O, Scoring P, 
     const int32_t m = S.pat_len[p], n = S.txt_len[p];
     const int64_t pnw = (m + 31) >> 5, tnw = (n + 31) >> 5;
     const uint64_t *gP = S.pat + S.pat_off[p], *gT = S.txt + S.txt_off[p];
-    const uint64_t *Pw = gP, *Tw = gT;
-    if (pnw <= L.seq_words && tnw <= L.seq_words) {
+    const bool staged = pnw <= L.seq_words && tnw <= L.seq_words;
+    if (staged) {
       stage_seq(sP, gP, pnw);
       stage_seq(sT, gT, tnw);
-      Pw = sP;
-      Tw = sT;
     }
     __syncthreads();
     auto slot_of = [&](int32_t s) { return s % R; };
@@ -244,6 +284,8 @@ __global__ __launch_bounds__(WGMAX) void k_wfa_score(Seqs S, Outs O, Scoring P, 
     const int64_t up1 = (int64_t)x * min(m, n) + (ad ? (int64_t)P.o + ad * e : 0);
     const int64_t up2 = (m ? (int64_t)P.o + (int64_t)m * e : 0) + (n ? (int64_t)P.o + (int64_t)n * e : 0);
     const int64_t s_upper = min(up1, up2);
+    // the score loop, once per way of reading the sequences
+    auto run = [&](const auto &q) {
     for (;; ++s) {
       if (P.max_score >= 0 && s > P.max_score) { result = 2; break; }
       if (s > s_upper) { result = 4; break; }
@@ -252,12 +294,12 @@ __global__ __launch_bounds__(WGMAX) void k_wfa_score(Seqs S, Outs O, Scoring P, 
       int present;
       bool overflow = false;
       if (s == 0) {
-        if (lane == 0) ring[sl * 3 * L.wcap] = extend(Pw, pnw, m, Tw, tnw, n, 0, 0);
+        if (lane == 0) ring[sl * 3 * L.wcap] = q.ext(m, n, 0, 0);
         present = 1;
         lo = hi = 0;
       } else {
         present = wf_step<int32_t>(s, x, oe, e, m, n, tab_ring, ring, slot_of, ring, sl * 3 * L.wcap, L.wcap,
-                          lo, hi, Pw, pnw, Tw, tnw, overflow);
+                                   lo, hi, q, overflow);
       }
       if (overflow) { result = 3; break; }
       __syncthreads();
@@ -279,6 +321,11 @@ __global__ __launch_bounds__(WGMAX) void k_wfa_score(Seqs S, Outs O, Scoring P, 
         break;
       }
     }
+    };
+    if (staged)
+      run(SeqStaged{reinterpret_cast<const uint32_t *>(sP), reinterpret_cast<const uint32_t *>(sT)});
+    else
+      run(SeqInPlace{gP, gT, pnw, tnw});
     if (result == 3) {
       wave_append1(true, (int32_t)p, L.ring_list, L.ring_count);
       continue;
@@ -309,17 +356,113 @@ __global__ __launch_bounds__(WGMAX) void k_wfa_score(Seqs S, Outs O, Scoring P, 
   }
 }
 
+// ------------------------------------------- origin codes and the fused walk
+// The one-wavefront score pass can keep, per cell, how each component got its
+// value (4 bits: M from X, I or D in the canonical order; I and D opened from
+// M_{s-o-e} or extended), which is all the backtrace chooses.  The walk then
+// needs no offsets: it follows the codes back from the end cell, recording one
+// token per state (an M visit, or an X, I or D op), and a forward replay of
+// the tokens from (0, 0), extending every M visit as far as the bases match,
+// recovers the '=' runs -- the M offsets are exactly those maximal extensions.
+constexpr uint32_t TOK_M = 4;  // token of an M visit (its run length above bit 4)
+
+__device__ __forceinline__ int32_t origin_code(const uint8_t *bslot, int32_t C, int32_t kbase,
+                                               int32_t s, int32_t k) {
+  const int32_t idx = k - kbase;
+  const uint32_t b = bslot[((int64_t)s * C + (idx >> 6)) * 32 + ((idx & 63) >> 1)];
+  return __builtin_amdgcn_readfirstlane((int32_t)((idx & 1) ? (b >> 4) : (b & 15u)));
+}
+
+// Run by the whole wavefront on uniform values; lane 0 writes.  Returns false
+// (nothing written to the CIGAR outputs) when the tokens outgrow `tok`.
+__device__ bool wfa16_walk(const Outs &O, int64_t p, const uint8_t *bslot, int32_t C, int32_t kbase,
+                           int32_t x, int32_t oe, int32_t e, int32_t m, int32_t n, int32_t sfin,
+                           const uint32_t *P32, const uint32_t *T32, uint32_t *tok, int32_t tok_cap) {
+  const int lane = threadIdx.x;
+  const int32_t W = 64 * C;
+  int32_t cs = sfin, k = n - m, comp = 0, nt = 0, code = -1;
+  bool ok = true;
+  for (;;) {
+    if (nt + 2 > tok_cap || cs < 0 || (uint32_t)(k - kbase) >= (uint32_t)W) { ok = false; break; }
+    if (comp == 0) {
+      if (lane == 0) tok[nt] = TOK_M;
+      ++nt;
+      if (cs == 0) break;
+      if (code < 0) code = origin_code(bslot, C, kbase, cs, k);
+      const int32_t src = code & 3;
+      if (src == 0) {
+        if (lane == 0) tok[nt] = OP_X;
+        ++nt;
+        cs -= x;
+        code = -1;
+      } else {
+        comp = src;  // I or D of the same cell
+      }
+    } else {
+      if (code < 0) code = origin_code(bslot, C, kbase, cs, k);
+      const bool open = (code >> (comp + 1)) & 1;
+      if (lane == 0) tok[nt] = comp == 1 ? OP_I : OP_D;
+      ++nt;
+      k += comp == 1 ? 1 : -1;
+      if (open) { cs -= oe; comp = 0; } else { cs -= e; }
+      code = -1;
+    }
+  }
+  if (!ok) return false;
+  // forward replay: the '=' run of each M visit
+  int32_t i = 0, j = 0;
+  for (int32_t t = nt - 1; t >= 0; --t) {
+    const uint32_t tk = tok[t];
+    if (tk == TOK_M) {
+      const int32_t len = extend_lds(P32, m, T32, n, j - i, j) - j;
+      if (lane == 0) tok[t] = TOK_M | ((uint32_t)len << 4);
+      i += len;
+      j += len;
+    } else if (tk == OP_X) {
+      ++i; ++j;
+    } else if (tk == OP_I) {
+      ++i;
+    } else {
+      ++j;
+    }
+  }
+  if (i != m || j != n) return false;  // cannot happen for a reached end cell
+  if (lane == 0) {
+    RunSink sink;
+    sink.begin(O, p);
+    uint32_t cur_op = 0xffu, cur_len = 0;
+    int32_t nr = 0;
+    for (int32_t t = 0; t < nt; ++t) {
+      const uint32_t tk = tok[t];
+      const uint32_t op = (tk & 15u) == TOK_M ? (uint32_t)OP_EQ : (tk & 15u);
+      const uint32_t len = (tk & 15u) == TOK_M ? (tk >> 4) : 1u;
+      if (len == 0) continue;
+      if (op == cur_op) {
+        cur_len += len;
+      } else {
+        if (cur_len) sink.put(nr++, (cur_len << 4) | cur_op, nt - t + 1);
+        cur_op = op;
+        cur_len = len;
+      }
+    }
+    if (cur_len) sink.put(nr++, (cur_len << 4) | cur_op, 1);
+    sink.finish();
+    O.nruns[p] = nr;
+  }
+  return true;
+}
+
 // ------------------------------------------------- pass 1, one wavefront per pair
 // The wavefronts of k_wfa_score (same recurrences, bounds, presence bits and
 // full-store size), computed by a single 64-lane wavefront with no barrier
 // between waves: lane l owns diagonals kbase + l + 64 c for c < C, kbase =
 // -32 C.  M of the last R scores and I, D of the last e + 1 live in LDS as
-// 16-bit offsets (negative: absent), the per-score bounds and presence bits in
-// an R-entry LDS table; a source entry is read only inside that wavefront's
+// 16-bit offsets (INT16_MIN: absent), the per-score bounds and presence bits
+// in an R-entry LDS table; a source entry is read only inside that wavefront's
 // bounds, so stale slots never leak.  A wavefront that leaves the window goes
 // to the HBM-ring pass (ring_list), as does a pair whose end diagonal lies
-// outside it.  Offsets fit 16 bits because the host sends only batches with
-// max_len <= WFA16_MAX_LEN here.
+// outside it.  The host sends only batches with max_len <= WFA16_MAX_LEN (so
+// offsets fit 16 bits) whose sequences fit the LDS staging area.
 __global__ __launch_bounds__(64) void k_wfa_score16(Seqs S, Outs O, Scoring P, Work Wk, WfaLaunch L,
                                                    int32_t C) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -328,8 +471,10 @@ __global__ __launch_bounds__(64) void k_wfa_score16(Seqs S, Outs O, Scoring P, W
   const int32_t W = 64 * C, kbase = -32 * C;
   uint64_t *sP = (uint64_t *)smem;
   uint64_t *sT = sP + L.seq_words;
-  int32_t *tab = (int32_t *)(sT + L.seq_words);  // per ring slot: lo, hi, present, -
-  int16_t *rM = (int16_t *)(tab + R * ENTRY);     // R x W
+  // per ring slot, the diagonal range of each component (empty when the
+  // component is absent): I lo, hi, D lo, hi, M lo, hi, -, -
+  int32_t *tab = (int32_t *)(sT + L.seq_words);
+  int16_t *rM = (int16_t *)(tab + R * TAB16);     // R x W
   int16_t *rI = rM + R * W;                        // (e+1) x W
   int16_t *rD = rI + RE * W;                       // (e+1) x W
   const int32_t count = Wk.count ? __builtin_amdgcn_readfirstlane(*(volatile const int32_t *)Wk.count)
@@ -353,101 +498,142 @@ __global__ __launch_bounds__(64) void k_wfa_score16(Seqs S, Outs O, Scoring P, W
     const int32_t m = __builtin_amdgcn_readfirstlane(S.pat_len[p]);
     const int32_t n = __builtin_amdgcn_readfirstlane(S.txt_len[p]);
     const int64_t pnw = (m + 31) >> 5, tnw = (n + 31) >> 5;
-    const uint64_t *Pw = S.pat + S.pat_off[p], *Tw = S.txt + S.txt_off[p];
     __syncthreads();  // the previous pair's LDS is no longer read
-    if (pnw <= L.seq_words && tnw <= L.seq_words) {
-      stage_seq(sP, Pw, pnw);
-      stage_seq(sT, Tw, tnw);
-      Pw = sP;
-      Tw = sT;
-    }
+    // the host sends only batches whose sequences fit the staging area
+    stage_seq(sP, S.pat + S.pat_off[p], pnw);
+    stage_seq(sT, S.txt + S.txt_off[p], tnw);
+    const uint32_t *P32 = reinterpret_cast<const uint32_t *>(sP);
+    const uint32_t *T32 = reinterpret_cast<const uint32_t *>(sT);
     __syncthreads();  // staged words visible to every lane
     const int32_t kend = n - m;
+    const int32_t bits_steps = P.want_cigar ? L.bits_steps : 0;
+    uint8_t *bslot = L.bits + (int64_t)blockIdx.x * bits_steps * C * 32;
     const int64_t ad = m > n ? m - n : n - m;
     const int64_t up1 = (int64_t)x * min(m, n) + (ad ? (int64_t)P.o + ad * e : 0);
     const int64_t up2 = (m ? (int64_t)P.o + (int64_t)m * e : 0) + (n ? (int64_t)P.o + (int64_t)n * e : 0);
-    const int64_t s_upper = min(up1, up2);
+    const int32_t s_upper = (int32_t)min<int64_t>(min(up1, up2), INT32_MAX - 1);
+    // one test per score: past s_lim the pair is rejected (threshold) or
+    // out of its bound
+    const int32_t s_lim = P.max_score >= 0 ? min(P.max_score, s_upper) : s_upper;
     int result = (kend < kbase || kend >= kbase + W) ? 3 : 0;  // 1 aligned, 2 rejected, 3 overflow, 4 bound
     int32_t s = 0;
     int64_t need = 0;
     if (!result) {
+      // every slot starts empty, so a source of negative score (a slot not
+      // yet written for this pair, as R > max(x, o + e)) contributes nothing
+      if (lane < R) {
+        int32_t *t = tab + lane * TAB16;
+        t[0] = EMPTY_LO; t[1] = EMPTY_HI; t[2] = EMPTY_LO; t[3] = EMPTY_HI; t[4] = EMPTY_LO; t[5] = EMPTY_HI;
+      }
       if (lane == 0) {
-        const int32_t f = extend(Pw, pnw, m, Tw, tnw, n, 0, 0);
+        const int32_t f = extend_lds(P32, m, T32, n, 0, 0);
         rM[0 - kbase] = (int16_t)f;
-        tab[0] = 0;
-        tab[1] = 0;
-        tab[2] = 1;
+        tab[4] = 0;
+        tab[5] = 0;
       }
       need = ENTRY + 2;  // s = 0: three 16-bit entries
       __syncthreads();
       if (kend == 0 && __builtin_amdgcn_readfirstlane((int32_t)rM[0 - kbase]) >= n) result = 1;
     }
+    // ring slots kept incrementally: sl = s mod R, sE = s mod (e + 1)
+    int32_t sl = 0, sE = 0;
     while (!result) {
       ++s;
-      if (P.max_score >= 0 && s > P.max_score) { result = 2; break; }
-      if (s > s_upper) { result = 4; break; }
-      const int32_t sl = s % R;
-      // the three source entries, read together (a slot whose score is
-      // negative is read but ignored)
-      const int32_t qx = max(s - x, 0) % R, qo = max(s - oe, 0) % R, qe = max(s - e, 0) % R;
-      const int32_t tx0 = tab[qx * ENTRY], tx1 = tab[qx * ENTRY + 1], tx2 = tab[qx * ENTRY + 2];
-      const int32_t to0 = tab[qo * ENTRY], to1 = tab[qo * ENTRY + 1], to2 = tab[qo * ENTRY + 2];
-      const int32_t te0 = tab[qe * ENTRY], te1 = tab[qe * ENTRY + 1], te2 = tab[qe * ENTRY + 2];
-      const int fx = s - x >= 0 ? (__builtin_amdgcn_readfirstlane(tx2) & 1) : 0;
-      const int fo = s - oe >= 0 ? (__builtin_amdgcn_readfirstlane(to2) & 1) : 0;
-      const int fe = s - e >= 0 ? (__builtin_amdgcn_readfirstlane(te2) & 6) : 0;
-      const int32_t xlo = __builtin_amdgcn_readfirstlane(tx0), xhi = __builtin_amdgcn_readfirstlane(tx1);
-      const int32_t olo = __builtin_amdgcn_readfirstlane(to0), ohi = __builtin_amdgcn_readfirstlane(to1);
-      const int32_t elo = __builtin_amdgcn_readfirstlane(te0), ehi = __builtin_amdgcn_readfirstlane(te1);
-      const int32_t bx = qx * W, bo = qo * W, beI = (max(s - e, 0) % RE) * W;
-      int32_t lo = INT32_MAX, hi = INT32_MIN;
-      if (fx) { lo = min(lo, xlo); hi = max(hi, xhi); }
-      if (fo) { lo = min(lo, olo); hi = max(hi, ohi); }
-      if (fe) { lo = min(lo, elo); hi = max(hi, ehi); }
-      int present = 0;
-      if (fx || fo || fe) {
-        lo = max(lo - 1, -m);
-        hi = min(hi + 1, n);
-        if (lo <= hi) present = 1 | ((fo || (fe & 2)) ? 2 : 0) | ((fo || (fe & 4)) ? 4 : 0);
-      }
+      if (s > s_lim) { result = (P.max_score >= 0 && s > P.max_score) ? 2 : 4; break; }
+      sl = sl + 1 == R ? 0 : sl + 1;
+      sE = sE + 1 == RE ? 0 : sE + 1;
+      const int32_t qx = sl >= x ? sl - x : sl - x + R;
+      const int32_t qo = sl >= oe ? sl - oe : sl - oe + R;
+      const int32_t qe = sl >= e ? sl - e : sl - e + R;
+      const int32_t qeE = sE + 1 == RE ? 0 : sE + 1;  // (s - e) mod (e + 1)
+      // the source ranges: M of s - x and s - o - e, I and D of s - e
+      const int32_t xlo = __builtin_amdgcn_readfirstlane(tab[qx * TAB16 + 4]);
+      const int32_t xhi = __builtin_amdgcn_readfirstlane(tab[qx * TAB16 + 5]);
+      const int32_t olo = __builtin_amdgcn_readfirstlane(tab[qo * TAB16 + 4]);
+      const int32_t ohi = __builtin_amdgcn_readfirstlane(tab[qo * TAB16 + 5]);
+      const int32_t ilo = __builtin_amdgcn_readfirstlane(tab[qe * TAB16 + 0]);
+      const int32_t ihi = __builtin_amdgcn_readfirstlane(tab[qe * TAB16 + 1]);
+      const int32_t dlo = __builtin_amdgcn_readfirstlane(tab[qe * TAB16 + 2]);
+      const int32_t dhi = __builtin_amdgcn_readfirstlane(tab[qe * TAB16 + 3]);
+      const int32_t bx = qx * W, bo = qo * W, beI = qeE * W;
+      const int32_t lo = max(min(min(xlo, olo), min(ilo, dlo)) - 1, -m);
+      const int32_t hi = min(max(max(xhi, ohi), max(ihi, dhi)) + 1, n);
+      const bool present = lo <= hi;
       if (present && (lo < kbase || hi >= kbase + W)) { result = 3; break; }
+      // range widths (0 when empty): a range test is one unsigned compare
+      const int32_t xw = max(xhi - xlo + 1, 0), ow = max(ohi - olo + 1, 0);
+      const int32_t iw = max(ihi - ilo + 1, 0), dw = max(dhi - dlo + 1, 0);
+      const bool hasI = present && (ow | iw), hasD = present && (ow | dw);
       bool hit = false;  // this lane reached the end cell
+      const bool keep = s < bits_steps;  // origin codes of this score kept
       if (present) {
-        const bool eI = fe & 2, eD = fe & 4;
-        const int32_t bM = sl * W, bID = (s % RE) * W;
+        const int32_t bM = sl * W, bID = sE * W;
         const int32_t c_lo = (lo - kbase) >> 6, c_hi = (hi - kbase) >> 6;
+        // Every lane of a chunk runs the same code: a diagonal outside
+        // [lo, hi] finds no source in range (or only candidates the table
+        // bounds drop), so its offset comes out absent and it writes the
+        // absent mark into a part of the slot no reader takes.
         for (int32_t c = c_lo; c <= c_hi; ++c) {
           const int32_t idx = 64 * c + lane, k = kbase + idx;
           // five source reads issued together, indices clamped into the window
           const int32_t up = min(idx + 1, W - 1), dn = max(idx - 1, 0);
           const int32_t a_ou = rM[bo + up], a_od = rM[bo + dn], a_x = rM[bx + idx];
           const int32_t a_iu = rI[beI + up], a_dd = rD[beI + dn];
-          if (k < lo || k > hi) continue;
-          int32_t vi = (fo && k + 1 >= olo && k + 1 <= ohi) ? a_ou : NEG;
-          if (eI && k + 1 >= elo && k + 1 <= ehi) vi = max(vi, a_iu);
-          if (vi >= 0 && vi - k > m) vi = NEG;
-          int32_t vd = (fo && k - 1 >= olo && k - 1 <= ohi) ? a_od : NEG;
-          if (eD && k - 1 >= elo && k - 1 <= ehi) vd = max(vd, a_dd);
-          if (vd >= 0) { vd += 1; if (vd > n) vd = NEG; } else vd = NEG;
-          int32_t vx = (fx && k >= xlo && k <= xhi) ? a_x : NEG;
-          if (vx >= 0) { vx += 1; if (vx > n || vx - k > m) vx = NEG; } else vx = NEG;
-          if (vi < 0) vi = NEG;
+          // absent entries are stored as exactly INT16_MIN, so one added
+          // base keeps them negative
+          int32_t vi = max((uint32_t)(k + 1 - olo) < (uint32_t)ow ? a_ou : NEG,
+                           (uint32_t)(k + 1 - ilo) < (uint32_t)iw ? a_iu : NEG);
+          if (vi - k > m) vi = NEG;
+          int32_t vd = max((uint32_t)(k - 1 - olo) < (uint32_t)ow ? a_od : NEG,
+                           (uint32_t)(k - 1 - dlo) < (uint32_t)dw ? a_dd : NEG) + 1;
+          if (vd > n) vd = NEG;
+          int32_t vx = ((uint32_t)(k - xlo) < (uint32_t)xw ? a_x : NEG) + 1;
+          if (vx > n || vx - k > m) vx = NEG;
           int32_t vm = max(vx, max(vi, vd));
-          if (vm >= 0) vm = extend(Pw, pnw, m, Tw, tnw, n, k, vm);
-          rM[bM + idx] = (int16_t)(vm < 0 ? -1 : vm);
-          rI[bID + idx] = (int16_t)(vi < 0 ? -1 : vi);
-          rD[bID + idx] = (int16_t)(vd < 0 ? -1 : vd);
+          if (keep) {
+            // origin code of this cell; lanes 2q and 2q+1 share byte q
+            const int32_t code = (vx == vm ? 0 : (vi == vm ? 1 : 2)) |
+                                 ((vi >= 0 && (uint32_t)(k + 1 - olo) < (uint32_t)ow && a_ou == vi) ? 4 : 0) |
+                                 ((vd >= 0 && (uint32_t)(k - 1 - olo) < (uint32_t)ow && a_od >= 0 && a_od + 1 == vd) ? 8 : 0);
+            const int32_t hi_code = __builtin_amdgcn_update_dpp(0, code, 0x130, 0xF, 0xF, false);  // lane l + 1
+            if (!(lane & 1)) bslot[((int64_t)s * C + c) * 32 + (lane >> 1)] = (uint8_t)(code | (hi_code << 4));
+          }
+          // extend: the first 16 bases by every lane without a branch (a lane
+          // with no offset compares at base 0 under a zero limit), the rest
+          // only where all 16 matched
+          const bool live = vm >= 0;
+          const int32_t i0 = live ? vm - k : 0, j0 = live ? vm : 0;
+          const int32_t lim = live ? min(m - i0, n - j0) : 0;
+          const uint32_t d = __builtin_amdgcn_alignbit(P32[(i0 >> 4) + 1], P32[i0 >> 4], (uint32_t)(i0 & 15) * 2) ^
+                             __builtin_amdgcn_alignbit(T32[(j0 >> 4) + 1], T32[j0 >> 4], (uint32_t)(j0 & 15) * 2);
+          const int32_t run = min(d ? (int32_t)(__builtin_ctz(d) >> 1) : 16, lim);
+          int32_t f = j0 + run;
+          if (run == 16) f = extend_lds(P32, m, T32, n, k, f);
+          if (live) vm = f;
+          rM[bM + idx] = (int16_t)(vm < 0 ? -32768 : vm);
+          rI[bID + idx] = (int16_t)(vi < 0 ? -32768 : vi);
+          rD[bID + idx] = (int16_t)(vd < 0 ? -32768 : vd);
           hit = hit || (k == kend && vm >= n);
         }
       }
       if (lane == 0) {
-        tab[sl * ENTRY + 0] = present ? lo : 0;
-        tab[sl * ENTRY + 1] = present ? hi : -1;
-        tab[sl * ENTRY + 2] = present;
+        int32_t *t = tab + sl * TAB16;
+        t[0] = hasI ? lo : EMPTY_LO;
+        t[1] = hasI ? hi : EMPTY_HI;
+        t[2] = hasD ? lo : EMPTY_LO;
+        t[3] = hasD ? hi : EMPTY_HI;
+        t[4] = present ? lo : EMPTY_LO;
+        t[5] = present ? hi : EMPTY_HI;
       }
       need += ENTRY + (present ? (3 * (int64_t)(hi - lo + 1) + 1) / 2 : 0);  // 16-bit store
       __syncthreads();
       if (__ballot(hit)) result = 1;
+    }
+    bool walked = false;
+    if (result == 1 && s < bits_steps) {
+      __syncthreads();  // the origin codes stored by every lane, visible to the walk
+      walked = wfa16_walk(O, p, bslot, C, kbase, x, oe, e, m, n, s, P32, T32,
+                          reinterpret_cast<uint32_t *>(rM), (R + 2 * RE) * W / 2);
     }
     if (result == 3) {
       wave_append1(true, (int32_t)p, L.ring_list, L.ring_count);
@@ -459,8 +645,8 @@ __global__ __launch_bounds__(64) void k_wfa_score16(Seqs S, Outs O, Scoring P, W
       } else {
         O.score[p] = s;
         O.status[p] = ST_ALIGNED;
-        O.nruns[p] = 0;
-        if (P.want_cigar) {
+        if (!walked) O.nruns[p] = 0;
+        if (P.want_cigar && !walked) {
           L.need[p] = need;
           int cl = 0;
           while (cl < 3 && need > L.need_cap[cl]) ++cl;
@@ -479,7 +665,9 @@ __global__ __launch_bounds__(64) void k_wfa_score16(Seqs S, Outs O, Scoring P, W
 }
 
 // ---------------------------------------------------------------- pass 2
-template <class E>
+// LDSA: the full store lives in this workgroup's LDS (else in its HBM slot);
+// a compile-time choice, so that LDS traffic is issued as LDS instructions.
+template <class E, bool LDSA>
 __global__ __launch_bounds__(WGMAX) void k_wfa_trace(Seqs S, Outs O, Scoring P, Work Wk, WfaLaunch L,
                                                   int32_t *hbm) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -493,7 +681,7 @@ __global__ __launch_bounds__(WGMAX) void k_wfa_trace(Seqs S, Outs O, Scoring P, 
   // workgroups take pairs as such slots fit the pool (at least one, since the
   // pool holds the class capacity)
   int64_t slot_words = L.slot_words, nslots = gridDim.x;
-  if (!L.full_in_lds && L.slot_need_max) {
+  if (!LDSA && L.slot_need_max) {
     const int64_t mx = *(volatile const int32_t *)L.slot_need_max;
     slot_words = (max<int64_t>(mx, 1) + 63) / 64 * 64;
     nslots = min<int64_t>(nslots, L.pool_words / slot_words);
@@ -501,11 +689,11 @@ __global__ __launch_bounds__(WGMAX) void k_wfa_trace(Seqs S, Outs O, Scoring P, 
   // a workgroup the work can never reach, or without a slot, leaves before
   // touching the counter
   if ((int64_t)blockIdx.x >= min<int64_t>(count, nslots)) return;
-  int32_t *arena = L.full_in_lds ? (int32_t *)(sT + L.seq_words) : (hbm + (int64_t)blockIdx.x * slot_words);
+  int32_t *arena = LDSA ? (int32_t *)(sT + L.seq_words) : (hbm + (int64_t)blockIdx.x * slot_words);
   // With the store in HBM, the entries of the last R scores are also kept in
   // an LDS ring, from which the steps read their sources; the full table in
   // HBM serves the backtrace.
-  const bool ring = !L.full_in_lds;
+  constexpr bool ring = !LDSA;
   const int32_t R = L.R;
   int32_t *tab_ring = (int32_t *)(sT + L.seq_words);
   for (;;) {
@@ -519,12 +707,10 @@ __global__ __launch_bounds__(WGMAX) void k_wfa_trace(Seqs S, Outs O, Scoring P, 
     const int32_t sfin = O.score[p];
     const int64_t pnw = (m + 31) >> 5, tnw = (n + 31) >> 5;
     const uint64_t *gP = S.pat + S.pat_off[p], *gT = S.txt + S.txt_off[p];
-    const uint64_t *Pw = gP, *Tw = gT;
-    if (pnw <= L.seq_words && tnw <= L.seq_words) {
+    const bool staged = pnw <= L.seq_words && tnw <= L.seq_words;
+    if (staged) {
       stage_seq(sP, gP, pnw);
       stage_seq(sT, gT, tnw);
-      Pw = sP;
-      Tw = sT;
     }
     // table of sfin + 1 entries at the start of the arena, data after it
     int32_t *tab = arena;
@@ -533,18 +719,20 @@ __global__ __launch_bounds__(WGMAX) void k_wfa_trace(Seqs S, Outs O, Scoring P, 
     __syncthreads();
     const int32_t *stab = ring ? tab_ring : tab;
     auto slot_of = [&](int32_t s2) { return ring ? s2 % R : s2; };
+    // the forward steps, once per way of reading the sequences
+    auto forward = [&](const auto &q) {
     for (int32_t s = 0; s <= sfin; ++s) {
       const int32_t base = sh_top;
       int32_t lo = 0, hi = -1;
       int present;
       bool overflow = false;
       if (s == 0) {
-        if (lane == 0) reinterpret_cast<E *>(arena + base)[0] = wf_put<E>(extend(Pw, pnw, m, Tw, tnw, n, 0, 0));
+        if (lane == 0) reinterpret_cast<E *>(arena + base)[0] = wf_put<E>(q.ext(m, n, 0, 0));
         present = 1;
         lo = hi = 0;
       } else {
         present = wf_step<E>(s, x, oe, e, m, n, stab, arena, slot_of, arena, base, INT32_MAX, lo, hi,
-                             Pw, pnw, Tw, tnw, overflow);
+                             q, overflow);
       }
       __syncthreads();
       if (lane == 0) {
@@ -563,6 +751,11 @@ __global__ __launch_bounds__(WGMAX) void k_wfa_trace(Seqs S, Outs O, Scoring P, 
       }
       __syncthreads();
     }
+    };
+    if (staged)
+      forward(SeqStaged{reinterpret_cast<const uint32_t *>(sP), reinterpret_cast<const uint32_t *>(sT)});
+    else
+      forward(SeqInPlace{gP, gT, pnw, tnw});
     // ---- backtrace (one lane) ----
     if (lane == 0) {
       const int32_t total = Wk.direct ? O.nruns[p] : 0;
@@ -697,7 +890,7 @@ hipError_t launch_wfa_score(const Seqs &S, const Outs &O, const Scoring &P, cons
 }
 
 size_t wfa_score16_lds(const WfaLaunch &L, int32_t e, int32_t C) {
-  return 2 * (size_t)L.seq_words * 8 + (size_t)L.R * ENTRY * 4 + (size_t)(L.R + 2 * (e + 1)) * 64 * C * 2;
+  return 2 * (size_t)L.seq_words * 8 + (size_t)L.R * TAB16 * 4 + (size_t)(L.R + 2 * (e + 1)) * 64 * C * 2;
 }
 
 hipError_t launch_wfa_score16(const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk,
@@ -711,10 +904,17 @@ hipError_t launch_wfa_trace(const Seqs &S, const Outs &O, const Scoring &P, cons
                             bool i16, hipStream_t s) {
   const size_t lds = 2 * (size_t)L.seq_words * 8 +
                      (L.full_in_lds ? (size_t)L.slot_words * 4 : (size_t)L.R * ENTRY * 4);
-  if (i16)
-    hipLaunchKernelGGL(k_wfa_trace<int16_t>, dim3(nslots), dim3(threads), lds, s, S, O, P, Wk, L, hbm);
-  else
-    hipLaunchKernelGGL(k_wfa_trace<int32_t>, dim3(nslots), dim3(threads), lds, s, S, O, P, Wk, L, hbm);
+  if (L.full_in_lds) {
+    if (i16)
+      hipLaunchKernelGGL((k_wfa_trace<int16_t, true>), dim3(nslots), dim3(threads), lds, s, S, O, P, Wk, L, hbm);
+    else
+      hipLaunchKernelGGL((k_wfa_trace<int32_t, true>), dim3(nslots), dim3(threads), lds, s, S, O, P, Wk, L, hbm);
+  } else {
+    if (i16)
+      hipLaunchKernelGGL((k_wfa_trace<int16_t, false>), dim3(nslots), dim3(threads), lds, s, S, O, P, Wk, L, hbm);
+    else
+      hipLaunchKernelGGL((k_wfa_trace<int32_t, false>), dim3(nslots), dim3(threads), lds, s, S, O, P, Wk, L, hbm);
+  }
   return hipGetLastError();
 }
 
