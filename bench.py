@@ -36,7 +36,7 @@ OPS_PER_CELL = {"swg": 14, "nw": 10, "wfa": 14}
 # (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0 after the copy-kernel calibration; see
 # profiles/k_band16_swg150_hbm_counters.md), valid only for the kernel source
 # they were taken on (first 16 hex of its SHA-256).
-MEASURED_TRAFFIC = {("swg150", "k_band16<32>"): ("f5bd80a2d34dd15c", 3.0723e9)}
+MEASURED_TRAFFIC = {("swg150", "k_band16<32>"): ("32a97daf6917c56a", 3.0790e9)}
 
 WORKLOAD_TEXT = {
     "swg150": "Gotoh 4/6/2 global, 1,000,000 pairs x 150 bp, 4% error (1/3 sub, ins, del), "
