@@ -182,6 +182,12 @@ struct WfaLaunch {
   // pass 2
   uint8_t *bits;
   int32_t bits_steps;
+  // HBM-ring score pass with a CIGAR wanted: per workgroup, a table of
+  // walk_steps scores, walk_codes bytes of origin codes and walk_tok walk
+  // tokens, walk_slot bytes in all (walk_steps == 0: none)
+  uint8_t *walk;
+  int32_t walk_steps, walk_tok;
+  int64_t walk_codes, walk_slot;
 };
 
 struct WfaPlan {
@@ -205,6 +211,8 @@ constexpr int32_t WFA16_MAX_LEN = 32000;
 // Scores whose origin codes the one-wavefront pass keeps for its fused walk
 // (32 bytes per 64 diagonals per score and workgroup).
 constexpr int32_t WFA16_WALK_STEPS = 2048;
+// Scores whose origin codes the HBM-ring score pass keeps for its fused walk.
+constexpr int32_t WFA_WALK_STEPS = 16384;
 size_t wfa_score16_lds(const WfaLaunch &L, int32_t e, int32_t C);
 hipError_t launch_wfa_score16(const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk,
                               const WfaLaunch &L, int32_t C, int32_t nslots, hipStream_t s);

@@ -122,7 +122,7 @@ struct aim_context {
   Buf order, hist;
   Buf flags, pflag, tflag, pat2, txt2, pat2off, txt2off, nruns, slot, tb32, tb64, full, list2,
       list3, counters, scan_tmp, spill, total, wring, warena1, warena2, warena3, wneed, wlists, pool, pooloff,
-      wbits;
+      wbits, wwalk;
 };
 
 namespace {
@@ -297,10 +297,23 @@ aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const
     B.ring_list = lists + (int64_t)n * 5;  // never reached: wcap bounds every width
     B.ring_count = cnt + C_FAIL;
     const bool all = plain || (!w16 && pl.wcap_lds == 0);
+    const int32_t grid = all ? std::min<int32_t>(slots, pl.ring_slots) : pl.ring_slots;
+    if (P.want_cigar && !plain) {
+      // origin codes for the fused walk: 1/8 of the budget over the workgroups
+      B.walk_steps = P.max_score >= 0 ? std::min(P.max_score + 1, aim::WFA_WALK_STEPS) : aim::WFA_WALK_STEPS;
+      B.walk_tok = 2 * (2 * L + 1) + 8;
+      // (no more than every kept score at the widest wavefront needs)
+      const int64_t most = (int64_t)B.walk_steps * ((pl.wcap + 1) / 2) + 16;
+      B.walk_codes = std::min<int64_t>(
+          most, std::max<int64_t>(256 << 10, std::min<int64_t>(16 << 20, c->opt.scratch_limit / 8 / grid)));
+      B.walk_codes = (B.walk_codes + 15) / 16 * 16;
+      B.walk_slot = ((int64_t)B.walk_steps * 16 + B.walk_codes + (int64_t)B.walk_tok * 4 + 255) / 256 * 256;
+      if ((st = ensure(c, c->wwalk, (size_t)B.walk_slot * grid))) return st;
+      B.walk = as<uint8_t>(c->wwalk);
+    }
     aim::Work W{all ? order : lists, all ? nullptr : cnt + C_RL, n, cnt + C_W1G, nullptr, nullptr, 0};
     Phase ph(c, s, "wfa_score_hbm");
-    HIP_TRY(aim::launch_wfa_score(S, O, P, W, B, as<int32_t>(c->wring), false,
-                                  all ? std::min<int32_t>(slots, pl.ring_slots) : pl.ring_slots,
+    HIP_TRY(aim::launch_wfa_score(S, O, P, W, B, as<int32_t>(c->wring), false, grid,
                                   plain ? 64 : pl.ring_threads, s));
   }
   if (!P.want_cigar) return AIM_OK;
@@ -404,7 +417,7 @@ void aim_destroy(aim_context *c) {
   Buf *all[] = {&c->order, &c->hist, &c->flags, &c->pflag, &c->tflag, &c->pat2, &c->txt2, &c->pat2off, &c->txt2off,
                 &c->nruns, &c->slot, &c->tb32, &c->tb64, &c->full, &c->list2, &c->list3,
                 &c->counters, &c->scan_tmp, &c->spill, &c->total, &c->wring, &c->warena1,
-                &c->warena2, &c->warena3, &c->wneed, &c->wlists, &c->pool, &c->pooloff, &c->wbits};
+                &c->warena2, &c->warena3, &c->wneed, &c->wlists, &c->pool, &c->pooloff, &c->wbits, &c->wwalk};
   for (Buf *b : all)
     if (b->p) (void)hipFree(b->p);
   if (c->ev_join) (void)hipEventDestroy(c->ev_join);

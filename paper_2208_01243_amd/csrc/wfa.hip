@@ -113,6 +113,114 @@ __device__ __forceinline__ int32_t SeqStaged::ext(int32_t m, int32_t n, int32_t 
   return extend_lds(P32, m, T32, n, k, f);
 }
 
+// ------------------------------------------- origin codes and the fused walk
+// A score pass can keep, per cell, how each component got its value (4 bits:
+// bits 0-1 the source of M in the canonical order, 0 X, 1 I, 2 D; bit 2 I
+// opened from M_{s-o-e} rather than extended; bit 3 the same for D), which is
+// all the backtrace chooses.  The walk then needs no offsets: it follows the
+// codes back from the end cell, recording one token per state (an M visit, or
+// an X, I or D op), and a forward replay of the tokens from (0, 0), extending
+// every M visit as far as the bases match, recovers the '=' runs -- the M
+// offsets are exactly those maximal extensions.  Two neighbouring lanes hold
+// neighbouring diagonals; the even lane stores the byte of both codes.
+constexpr uint32_t TOK_M = 4;  // token of an M visit (its run length above bit 4)
+
+__device__ __forceinline__ int32_t origin_code_of(int32_t vx, int32_t vi, int32_t vd, int32_t vm,
+                                                  bool i_open, bool d_open) {
+  return (vx == vm ? 0 : (vi == vm ? 1 : 2)) | (i_open ? 4 : 0) | (d_open ? 8 : 0);
+}
+
+// The pair's neighbour code (lane l + 1) joined with this lane's, for the
+// even lane to store.
+__device__ __forceinline__ uint8_t code_pair(int32_t code) {
+  const int32_t up = __builtin_amdgcn_update_dpp(0, code, 0x130, 0xF, 0xF, false);  // lane l + 1
+  return (uint8_t)(code | (up << 4));
+}
+
+// Run by one whole wavefront on uniform values; its lane 0 writes.  code_of(s,
+// k) gives the code of a kept cell, or -1; ext(k, f) extends offset f on
+// diagonal k.  Returns false (nothing written to the CIGAR outputs) when a
+// code is missing or the tokens outgrow `tok`.
+template <class CodeOf, class Ext>
+__device__ bool walk_codes(const Outs &O, int64_t p, CodeOf code_of, Ext ext, int32_t x, int32_t oe,
+                           int32_t e, int32_t m, int32_t n, int32_t sfin, uint32_t *tok, int32_t tok_cap) {
+  const int lane = threadIdx.x & 63;
+  int32_t cs = sfin, k = n - m, comp = 0, nt = 0, code = -1;
+  bool ok = true;
+  for (;;) {
+    if (nt + 2 > tok_cap || cs < 0) { ok = false; break; }
+    if (comp == 0) {
+      if (lane == 0) tok[nt] = TOK_M;
+      ++nt;
+      if (cs == 0) { ok = k == 0; break; }
+      if (code < 0) code = code_of(cs, k);
+      if (code < 0) { ok = false; break; }
+      const int32_t src = code & 3;
+      if (src == 0) {
+        if (lane == 0) tok[nt] = OP_X;
+        ++nt;
+        cs -= x;
+        code = -1;
+      } else {
+        comp = src;  // I or D of the same cell
+      }
+    } else {
+      if (code < 0) code = code_of(cs, k);
+      if (code < 0) { ok = false; break; }
+      const bool open = (code >> (comp + 1)) & 1;
+      if (lane == 0) tok[nt] = comp == 1 ? OP_I : OP_D;
+      ++nt;
+      k += comp == 1 ? 1 : -1;
+      if (open) { cs -= oe; comp = 0; } else { cs -= e; }
+      code = -1;
+    }
+  }
+  if (!ok) return false;
+  __threadfence_block();  // lane 0's tokens visible to the wavefront
+  // forward replay: the '=' run of each M visit
+  int32_t i = 0, j = 0;
+  for (int32_t t = nt - 1; t >= 0; --t) {
+    const uint32_t tk = __builtin_amdgcn_readfirstlane(tok[t]);
+    if (tk == TOK_M) {
+      const int32_t len = __builtin_amdgcn_readfirstlane(ext(j - i, j)) - j;
+      if (lane == 0) tok[t] = TOK_M | ((uint32_t)len << 4);
+      i += len;
+      j += len;
+    } else if (tk == OP_X) {
+      ++i; ++j;
+    } else if (tk == OP_I) {
+      ++i;
+    } else {
+      ++j;
+    }
+  }
+  if (i != m || j != n) return false;  // cannot happen for a reached end cell
+  __threadfence_block();
+  if (lane == 0) {
+    RunSink sink;
+    sink.begin(O, p);
+    uint32_t cur_op = 0xffu, cur_len = 0;
+    int32_t nr = 0;
+    for (int32_t t = 0; t < nt; ++t) {
+      const uint32_t tk = tok[t];
+      const uint32_t op = (tk & 15u) == TOK_M ? (uint32_t)OP_EQ : (tk & 15u);
+      const uint32_t len = (tk & 15u) == TOK_M ? (tk >> 4) : 1u;
+      if (len == 0) continue;
+      if (op == cur_op) {
+        cur_len += len;
+      } else {
+        if (cur_len) sink.put(nr++, (cur_len << 4) | cur_op, nt - t + 1);
+        cur_op = op;
+        cur_len = len;
+      }
+    }
+    if (cur_len) sink.put(nr++, (cur_len << 4) | cur_op, 1);
+    sink.finish();
+    O.nruns[p] = nr;
+  }
+  return true;
+}
+
 // One wavefront step: compute components of score s into `dst` (three
 // arrays of width hi-lo+1 at dst, dst+w, dst+2w).  Source tables/arrays are
 // located through `tab`/`store` with slot(s') giving the table slot.
@@ -134,7 +242,8 @@ __device__ __forceinline__ int wf_step(int32_t s, int32_t x, int32_t oe, int32_t
                                        int32_t n, const int32_t *tab, const int32_t *store,
                                        SlotOf slot_of, int32_t *dst_base_store, int32_t dst_base,
                                        int32_t wlimit, int32_t &lo_out, int32_t &hi_out,
-                                       const Q &q, bool &overflow) {
+                                       const Q &q, bool &overflow, uint8_t *crow = nullptr,
+                                       int64_t cavail = 0, int32_t *cbytes = nullptr) {
   const int lane = threadIdx.x;
   int sx = -1, so = -1, se = -1;
   int fx = 0, fo = 0, fe = 0;
@@ -162,6 +271,15 @@ __device__ __forceinline__ int wf_step(int32_t s, int32_t x, int32_t oe, int32_t
   if (w > wlimit) {
     overflow = true;
     return 0;
+  }
+  // origin codes of this score into crow (ceil(w / 2) bytes) when they fit
+  if (crow) {
+    if ((w + 1) / 2 > cavail) {
+      crow = nullptr;
+      *cbytes = -1;
+    } else {
+      *cbytes = (w + 1) / 2;
+    }
   }
   const int32_t xlo = fx ? tab_get(tab, sx, 0) : 0, xhi = fx ? tab_get(tab, sx, 1) : -1;
   const int32_t xb = fx ? tab_get(tab, sx, 2) : 0;
@@ -200,7 +318,7 @@ __device__ __forceinline__ int wf_step(int32_t s, int32_t x, int32_t oe, int32_t
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int32_t k = kb + u * nt + lane;
-      if (k > hi) continue;
+      if (kb + u * nt > hi) continue;  // (uniform) no diagonal of this row in range
       int32_t vi = NEG, vd = NEG, vx = NEG;
       // I: from k + 1
       if (fo && k + 1 >= olo && k + 1 <= ohi) vi = a_ou[u];
@@ -215,6 +333,14 @@ __device__ __forceinline__ int wf_step(int32_t s, int32_t x, int32_t oe, int32_t
       if (vx >= 0) { vx += 1; if (vx > n || vx - k > m) vx = NEG; } else vx = NEG;
       if (vi < 0) vi = NEG;
       int32_t vm = max(vx, max(vi, vd));
+      if (crow) {
+        // every lane of the row takes part (k - lo has the parity of the lane)
+        const uint8_t b = code_pair(origin_code_of(
+            vx, vi, vd, vm, vi >= 0 && fo && k + 1 >= olo && k + 1 <= ohi && a_ou[u] == vi,
+            vd >= 0 && fo && k - 1 >= olo && k - 1 <= ohi && a_od[u] >= 0 && a_od[u] + 1 == vd));
+        if (!(lane & 1) && k <= hi) crow[(k - lo) >> 1] = b;
+      }
+      if (k > hi) continue;
       if (vm >= 0) vm = q.ext(m, n, k, vm);
       dM[k - lo] = wf_put<E>(vm);
       dI[k - lo] = wf_put<E>(vi);
@@ -277,6 +403,13 @@ __global__ __launch_bounds__(WGMAX) void k_wfa_score(Seqs S, Outs O, Scoring P, 
     int32_t s = 0;
     int64_t need = 0;
     int result = 0;  // 1 aligned, 2 rejected, 3 ring overflow, 4 internal bound
+    // origin codes for the fused walk: per score its range and code offset in
+    // wtab, the codes in wcodes; `keep` drops to false once they do not fit
+    bool keep = P.want_cigar && L.walk_steps > 0, walked = false;
+    int32_t *wtab = reinterpret_cast<int32_t *>(L.walk + (int64_t)blockIdx.x * L.walk_slot);
+    uint8_t *wcodes = reinterpret_cast<uint8_t *>(wtab + 4 * (int64_t)L.walk_steps);
+    uint32_t *wtok = reinterpret_cast<uint32_t *>(wcodes + L.walk_codes);
+    int64_t cbase = 0;
     const int32_t kend = n - m;
     // the cost of one concrete alignment bounds the optimum: all diagonal ops
     // plus one gap run for the length difference, or gap runs over both
@@ -298,8 +431,13 @@ __global__ __launch_bounds__(WGMAX) void k_wfa_score(Seqs S, Outs O, Scoring P, 
         present = 1;
         lo = hi = 0;
       } else {
+        if (keep && s >= L.walk_steps) keep = false;
+        int32_t cbytes = 0;
         present = wf_step<int32_t>(s, x, oe, e, m, n, tab_ring, ring, slot_of, ring, sl * 3 * L.wcap, L.wcap,
-                                   lo, hi, q, overflow);
+                                   lo, hi, q, overflow, keep ? wcodes + cbase : nullptr,
+                                   L.walk_codes - cbase, &cbytes);
+        if (cbytes < 0) keep = false;
+        cbase += cbytes > 0 ? cbytes : 0;
       }
       if (overflow) { result = 3; break; }
       __syncthreads();
@@ -308,6 +446,11 @@ __global__ __launch_bounds__(WGMAX) void k_wfa_score(Seqs S, Outs O, Scoring P, 
         tab_ring[sl * ENTRY + 1] = hi;
         tab_ring[sl * ENTRY + 2] = sl * 3 * L.wcap;
         tab_ring[sl * ENTRY + 3] = present;
+        if (keep) {
+          wtab[4 * s + 0] = lo;
+          wtab[4 * s + 1] = present ? hi : lo - 1;
+          wtab[4 * s + 2] = (int32_t)(cbase - (present && s > 0 ? (hi - lo + 2) / 2 : 0));
+        }
       }
       if (present) {
         const int64_t w3 = 3 * (int64_t)(hi - lo + 1);
@@ -320,6 +463,22 @@ __global__ __launch_bounds__(WGMAX) void k_wfa_score(Seqs S, Outs O, Scoring P, 
         result = 1;
         break;
       }
+    }
+    if (result == 1 && keep) {
+      __syncthreads();  // the codes and table of every wave visible to the walk
+      if (threadIdx.x < 64) {
+        auto code_of = [&](int32_t cs, int32_t k) -> int32_t {
+          const int32_t lo = __builtin_amdgcn_readfirstlane(wtab[4 * cs + 0]);
+          const int32_t hi = __builtin_amdgcn_readfirstlane(wtab[4 * cs + 1]);
+          const int32_t cb = __builtin_amdgcn_readfirstlane(wtab[4 * cs + 2]);
+          if (k < lo || k > hi) return -1;
+          const uint32_t b = wcodes[cb + ((k - lo) >> 1)];
+          return __builtin_amdgcn_readfirstlane((int32_t)(((k - lo) & 1) ? (b >> 4) : (b & 15u)));
+        };
+        auto ext = [&](int32_t k, int32_t f) { return q.ext(m, n, k, f); };
+        walked = walk_codes(O, p, code_of, ext, x, oe, e, m, n, s, wtok, L.walk_tok);
+      }
+      __syncthreads();
     }
     };
     if (staged)
@@ -338,8 +497,8 @@ __global__ __launch_bounds__(WGMAX) void k_wfa_score(Seqs S, Outs O, Scoring P, 
       } else {
         O.score[p] = s;
         O.status[p] = ST_ALIGNED;
-        O.nruns[p] = 0;
-        if (P.want_cigar) {
+        if (!walked) O.nruns[p] = 0;
+        if (P.want_cigar && !walked) {
           L.need[p] = need;
           int c = 0;
           while (c < 3 && need > L.need_cap[c]) ++c;
@@ -354,102 +513,6 @@ __global__ __launch_bounds__(WGMAX) void k_wfa_score(Seqs S, Outs O, Scoring P, 
       }
     }
   }
-}
-
-// ------------------------------------------- origin codes and the fused walk
-// The one-wavefront score pass can keep, per cell, how each component got its
-// value (4 bits: M from X, I or D in the canonical order; I and D opened from
-// M_{s-o-e} or extended), which is all the backtrace chooses.  The walk then
-// needs no offsets: it follows the codes back from the end cell, recording one
-// token per state (an M visit, or an X, I or D op), and a forward replay of
-// the tokens from (0, 0), extending every M visit as far as the bases match,
-// recovers the '=' runs -- the M offsets are exactly those maximal extensions.
-constexpr uint32_t TOK_M = 4;  // token of an M visit (its run length above bit 4)
-
-__device__ __forceinline__ int32_t origin_code(const uint8_t *bslot, int32_t C, int32_t kbase,
-                                               int32_t s, int32_t k) {
-  const int32_t idx = k - kbase;
-  const uint32_t b = bslot[((int64_t)s * C + (idx >> 6)) * 32 + ((idx & 63) >> 1)];
-  return __builtin_amdgcn_readfirstlane((int32_t)((idx & 1) ? (b >> 4) : (b & 15u)));
-}
-
-// Run by the whole wavefront on uniform values; lane 0 writes.  Returns false
-// (nothing written to the CIGAR outputs) when the tokens outgrow `tok`.
-__device__ bool wfa16_walk(const Outs &O, int64_t p, const uint8_t *bslot, int32_t C, int32_t kbase,
-                           int32_t x, int32_t oe, int32_t e, int32_t m, int32_t n, int32_t sfin,
-                           const uint32_t *P32, const uint32_t *T32, uint32_t *tok, int32_t tok_cap) {
-  const int lane = threadIdx.x;
-  const int32_t W = 64 * C;
-  int32_t cs = sfin, k = n - m, comp = 0, nt = 0, code = -1;
-  bool ok = true;
-  for (;;) {
-    if (nt + 2 > tok_cap || cs < 0 || (uint32_t)(k - kbase) >= (uint32_t)W) { ok = false; break; }
-    if (comp == 0) {
-      if (lane == 0) tok[nt] = TOK_M;
-      ++nt;
-      if (cs == 0) break;
-      if (code < 0) code = origin_code(bslot, C, kbase, cs, k);
-      const int32_t src = code & 3;
-      if (src == 0) {
-        if (lane == 0) tok[nt] = OP_X;
-        ++nt;
-        cs -= x;
-        code = -1;
-      } else {
-        comp = src;  // I or D of the same cell
-      }
-    } else {
-      if (code < 0) code = origin_code(bslot, C, kbase, cs, k);
-      const bool open = (code >> (comp + 1)) & 1;
-      if (lane == 0) tok[nt] = comp == 1 ? OP_I : OP_D;
-      ++nt;
-      k += comp == 1 ? 1 : -1;
-      if (open) { cs -= oe; comp = 0; } else { cs -= e; }
-      code = -1;
-    }
-  }
-  if (!ok) return false;
-  // forward replay: the '=' run of each M visit
-  int32_t i = 0, j = 0;
-  for (int32_t t = nt - 1; t >= 0; --t) {
-    const uint32_t tk = tok[t];
-    if (tk == TOK_M) {
-      const int32_t len = extend_lds(P32, m, T32, n, j - i, j) - j;
-      if (lane == 0) tok[t] = TOK_M | ((uint32_t)len << 4);
-      i += len;
-      j += len;
-    } else if (tk == OP_X) {
-      ++i; ++j;
-    } else if (tk == OP_I) {
-      ++i;
-    } else {
-      ++j;
-    }
-  }
-  if (i != m || j != n) return false;  // cannot happen for a reached end cell
-  if (lane == 0) {
-    RunSink sink;
-    sink.begin(O, p);
-    uint32_t cur_op = 0xffu, cur_len = 0;
-    int32_t nr = 0;
-    for (int32_t t = 0; t < nt; ++t) {
-      const uint32_t tk = tok[t];
-      const uint32_t op = (tk & 15u) == TOK_M ? (uint32_t)OP_EQ : (tk & 15u);
-      const uint32_t len = (tk & 15u) == TOK_M ? (tk >> 4) : 1u;
-      if (len == 0) continue;
-      if (op == cur_op) {
-        cur_len += len;
-      } else {
-        if (cur_len) sink.put(nr++, (cur_len << 4) | cur_op, nt - t + 1);
-        cur_op = op;
-        cur_len = len;
-      }
-    }
-    if (cur_len) sink.put(nr++, (cur_len << 4) | cur_op, 1);
-    sink.finish();
-    O.nruns[p] = nr;
-  }
-  return true;
 }
 
 // ------------------------------------------------- pass 1, one wavefront per pair
@@ -592,11 +655,11 @@ __global__ __launch_bounds__(64) void k_wfa_score16(Seqs S, Outs O, Scoring P, W
           int32_t vm = max(vx, max(vi, vd));
           if (keep) {
             // origin code of this cell; lanes 2q and 2q+1 share byte q
-            const int32_t code = (vx == vm ? 0 : (vi == vm ? 1 : 2)) |
-                                 ((vi >= 0 && (uint32_t)(k + 1 - olo) < (uint32_t)ow && a_ou == vi) ? 4 : 0) |
-                                 ((vd >= 0 && (uint32_t)(k - 1 - olo) < (uint32_t)ow && a_od >= 0 && a_od + 1 == vd) ? 8 : 0);
-            const int32_t hi_code = __builtin_amdgcn_update_dpp(0, code, 0x130, 0xF, 0xF, false);  // lane l + 1
-            if (!(lane & 1)) bslot[((int64_t)s * C + c) * 32 + (lane >> 1)] = (uint8_t)(code | (hi_code << 4));
+            const int32_t code = origin_code_of(
+                vx, vi, vd, vm, vi >= 0 && (uint32_t)(k + 1 - olo) < (uint32_t)ow && a_ou == vi,
+                vd >= 0 && (uint32_t)(k - 1 - olo) < (uint32_t)ow && a_od >= 0 && a_od + 1 == vd);
+            const uint8_t b = code_pair(code);
+            if (!(lane & 1)) bslot[((int64_t)s * C + c) * 32 + (lane >> 1)] = b;
           }
           // extend: the first 16 bases by every lane without a branch (a lane
           // with no offset compares at base 0 under a zero limit), the rest
@@ -632,8 +695,15 @@ __global__ __launch_bounds__(64) void k_wfa_score16(Seqs S, Outs O, Scoring P, W
     bool walked = false;
     if (result == 1 && s < bits_steps) {
       __syncthreads();  // the origin codes stored by every lane, visible to the walk
-      walked = wfa16_walk(O, p, bslot, C, kbase, x, oe, e, m, n, s, P32, T32,
-                          reinterpret_cast<uint32_t *>(rM), (R + 2 * RE) * W / 2);
+      auto code_of = [&](int32_t cs, int32_t k) -> int32_t {
+        const int32_t idx = k - kbase;
+        if ((uint32_t)idx >= (uint32_t)W) return -1;
+        const uint32_t b = bslot[((int64_t)cs * C + (idx >> 6)) * 32 + ((idx & 63) >> 1)];
+        return __builtin_amdgcn_readfirstlane((int32_t)((idx & 1) ? (b >> 4) : (b & 15u)));
+      };
+      auto ext = [&](int32_t k, int32_t f) { return extend_lds(P32, m, T32, n, k, f); };
+      walked = walk_codes(O, p, code_of, ext, x, oe, e, m, n, s, reinterpret_cast<uint32_t *>(rM),
+                          (R + 2 * RE) * W / 2);
     }
     if (result == 3) {
       wave_append1(true, (int32_t)p, L.ring_list, L.ring_count);
@@ -835,7 +905,8 @@ __global__ __launch_bounds__(WGMAX) void k_wfa_trace(Seqs S, Outs O, Scoring P, 
 
 WfaPlan wfa_plan(int32_t max_len, const Scoring &P, int64_t budget_bytes, int32_t cus, bool plain,
                  int32_t ring_kb, int32_t trace_kb, int32_t long_threads) {
-  // budget split: HBM rings 1/8, arena classes 1/16, 1/4 and 1/2
+  // budget split: HBM rings 1/8, origin codes 1/8, arena classes 1/16, 3/16
+  // and 3/8
   WfaPlan pl{};
   const int32_t oe = P.o + P.e;
   pl.R = std::max(P.x, oe) + 1;
@@ -863,10 +934,11 @@ WfaPlan wfa_plan(int32_t max_len, const Scoring &P, int64_t budget_bytes, int32_
   pl.need_cap[3] = std::max<int64_t>(pl.need_cap[2], std::min<int64_t>((int64_t)48 << 20, budget_bytes / 2 / 4));
   pl.arena_slots[0] = cus * 8;
   pl.threads[0] = 64;
-  // pools: 1/16, 1/4 and 1/2 of the budget, each at least one slot of its
-  // class capacity; the workgroups that take pairs are those whose slot (the
-  // class's largest store) fits the pool
-  const int64_t share[4] = {0, budget_bytes / 16, budget_bytes / 4, budget_bytes / 2};
+  // pools: 1/16, 3/16 and 3/8 of the budget (the origin codes of the HBM-ring
+  // pass take another 1/8), each at least one slot of its class capacity; the
+  // workgroups that take pairs are those whose slot (the class's largest
+  // store) fits the pool
+  const int64_t share[4] = {0, budget_bytes / 16, budget_bytes * 3 / 16, budget_bytes * 3 / 8};
   const int64_t cap_slots[4] = {0, (int64_t)cus * 8, (int64_t)cus * 4, (int64_t)cus * 4};
   for (int k = 1; k < 4; ++k) {
     const int64_t cap = (pl.need_cap[k] + 63) / 64 * 64;
