@@ -133,3 +133,44 @@ def test_score_only_matches(ctx):
     full = run(ctx, b, "wfa", AFF, 200)
     s, st, _, off = run(ctx, b, "wfa", AFF, 200, want_cigar=False)
     assert np.array_equal(s, full[0]) and np.array_equal(st, full[1]) and not off.any()
+
+
+def test_walk_fallback_to_full_store(ctx):
+    # A small scratch limit leaves the HBM-ring pass too little room for the
+    # origin codes of its longer pairs, which then take the full-store passes;
+    # the shorter ones are walked from their codes.
+    # (at 2 GiB each workgroup keeps about 1.4 MB of codes: the 10 % pairs of
+    # 4-6 kbp need more, the 1 % pairs less)
+    b = _mixed(43, 16, 4000, 6000, [0.01, 0.1])
+    small = aim.Context(0, scratch_limit=2 << 30)
+    try:
+        s, st, cg, off = run(small, b, "wfa", AFF)
+    finally:
+        small.close()
+    for i in range(b.n):
+        ws, wsc, wr, _ = oracle.wfa_pair(b.pattern(i), b.text(i), AFF)
+        assert (st[i], s[i]) == (ws, wsc), i
+        assert cg[off[i]:off[i + 1]].tolist() == wr, i
+
+
+def test_one_wave_walk_score_cap():
+    # Penalties with R = 32 and pairs of at most 127 bases stay in the
+    # one-wavefront pass's window; scores of 2048 and more exceed the scores
+    # whose origin codes it keeps, so those pairs take the full-store pass.
+    pen = (0, 31, 20, 11)
+    pats, txts = [], []
+    rng = np.random.default_rng(12)
+    for L in (100, 113, 120, 127):
+        pats += [np.zeros(L, np.uint8), np.tile(np.array([0, 1], np.uint8), L // 2)]
+        txts += [np.ones(L, np.uint8), np.tile(np.array([2, 3], np.uint8), L // 2)]
+    for _ in range(24):
+        pats.append(rng.integers(0, 4, int(rng.integers(60, 128))).astype(np.uint8))
+        txts.append(rng.integers(0, 4, int(rng.integers(60, 128))).astype(np.uint8))
+    b = synth.from_lists(pats, txts)
+    want = oracle.align_batch(b, "wfa", pen)
+    assert (want[0] >= 2048).sum() >= 4 and (want[0] < 2048).sum() >= 20
+    c = aim.Context(0)
+    try:
+        check(c, b, pen)
+    finally:
+        c.close()
