@@ -180,11 +180,18 @@ def main():
                     "frac": round(achieved / peak, 4), "traffic": traffic,
                     "avg_launch_ms": round(band_ms / band_launches, 4),
                     "ops_per_cell": OPS_PER_CELL[w["alg"]], "cells_per_launch": cells_band}
-    elif "wfa" in phases:
-        wfa_ms, wfa_launches = phases["wfa"]
-        roof = {"bound": "alu", "kernel": "k_wfa", "avg_launch_ms": round(wfa_ms / max(wfa_launches, 1), 4),
-                "achieved": None, "peak": round(PEAK_INT32_TOPS, 1), "unit": "Tops/s (int32)",
-                "frac": None, "traffic": None}
+    else:
+        # WFA: the dominant score pass (one wavefront per pair with its fused
+        # walk, or the HBM-ring pass for pairs too wide for its window); the
+        # wavefront cell count is not known without the scalar WFA, so the
+        # fraction of peak comes from the SQ counters in profiles/ instead
+        names = {"wfa_score": "k_wfa_score16", "wfa_score_hbm": "k_wfa_score"}
+        ph = max((k for k in names if k in phases), key=lambda k: phases[k][0], default=None)
+        if ph:
+            wfa_ms, wfa_launches = phases[ph]
+            roof = {"bound": "alu", "kernel": names[ph], "avg_launch_ms": round(wfa_ms / max(wfa_launches, 1), 4),
+                    "achieved": None, "peak": round(PEAK_INT32_TOPS, 1), "unit": "Tops/s (int32)",
+                    "frac": None, "traffic": None}
 
     # plain one-pair-per-workgroup kernel on the same pairs
     plain = None

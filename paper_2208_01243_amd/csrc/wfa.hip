@@ -70,14 +70,18 @@ __device__ __forceinline__ int32_t extend(const uint64_t *P, int64_t pnw, int32_
 
 // Sequence access for the extend step: words read in place (HBM or LDS), or
 // staged in LDS and compared 16 bases at a time.
+// ext_all(m, n, k, f) is called by every lane: it extends f when f >= 0 and
+// returns it unchanged otherwise.
 struct SeqInPlace {
   const uint64_t *P, *T;
   int64_t pnw, tnw;
   __device__ __forceinline__ int32_t ext(int32_t m, int32_t n, int32_t k, int32_t f) const;
+  __device__ __forceinline__ int32_t ext_all(int32_t m, int32_t n, int32_t k, int32_t f) const;
 };
 struct SeqStaged {
   const uint32_t *P32, *T32;
   __device__ __forceinline__ int32_t ext(int32_t m, int32_t n, int32_t k, int32_t f) const;
+  __device__ __forceinline__ int32_t ext_all(int32_t m, int32_t n, int32_t k, int32_t f) const;
 };
 
 __device__ __forceinline__ int32_t tab_get(const int32_t *tab, int32_t slot, int f) {
@@ -111,6 +115,22 @@ __device__ __forceinline__ int32_t SeqInPlace::ext(int32_t m, int32_t n, int32_t
 }
 __device__ __forceinline__ int32_t SeqStaged::ext(int32_t m, int32_t n, int32_t k, int32_t f) const {
   return extend_lds(P32, m, T32, n, k, f);
+}
+__device__ __forceinline__ int32_t SeqInPlace::ext_all(int32_t m, int32_t n, int32_t k, int32_t f) const {
+  return f >= 0 ? extend(P, pnw, m, T, tnw, n, k, f) : f;
+}
+// The first 16 bases by every lane without a branch (a lane with no offset
+// compares at base 0 under a zero limit), the rest only where all 16 matched.
+__device__ __forceinline__ int32_t SeqStaged::ext_all(int32_t m, int32_t n, int32_t k, int32_t f) const {
+  const bool live = f >= 0;
+  const int32_t i0 = live ? f - k : 0, j0 = live ? f : 0;
+  const int32_t lim = live ? min(m - i0, n - j0) : 0;
+  const uint32_t d = __builtin_amdgcn_alignbit(P32[(i0 >> 4) + 1], P32[i0 >> 4], (uint32_t)(i0 & 15) * 2) ^
+                     __builtin_amdgcn_alignbit(T32[(j0 >> 4) + 1], T32[j0 >> 4], (uint32_t)(j0 & 15) * 2);
+  const int32_t run = min(d ? (int32_t)(__builtin_ctz(d) >> 1) : 16, lim);
+  int32_t g = j0 + run;
+  if (run == 16) g = extend_lds(P32, m, T32, n, k, g);
+  return live ? g : f;
 }
 
 // ------------------------------------------- origin codes and the fused walk
@@ -300,6 +320,8 @@ __device__ __forceinline__ int wf_step(int32_t s, int32_t x, int32_t oe, int32_t
   // the store), and a value is used only under the bounds test of its source.
   constexpr int U = 4;
   const int32_t owm = max(ohi - olo, 0), ewm = max(ew - 1, 0), xwm = max(xhi - xlo, 0);
+  const uint32_t ow = fo ? (uint32_t)(ohi - olo + 1) : 0u, xw = fx ? (uint32_t)(xhi - xlo + 1) : 0u;
+  const uint32_t iw = eI ? (uint32_t)ew : 0u, dw = eD ? (uint32_t)ew : 0u;
   const int32_t nt = (int32_t)blockDim.x;
   for (int32_t kb = lo; kb <= hi; kb += U * nt) {  // kb: uniform batch start
     int32_t a_ou[U], a_ie[U], a_od[U], a_de[U], a_x[U];
@@ -319,32 +341,31 @@ __device__ __forceinline__ int wf_step(int32_t s, int32_t x, int32_t oe, int32_t
     for (int u = 0; u < U; ++u) {
       const int32_t k = kb + u * nt + lane;
       if (kb + u * nt > hi) continue;  // (uniform) no diagonal of this row in range
-      int32_t vi = NEG, vd = NEG, vx = NEG;
-      // I: from k + 1
-      if (fo && k + 1 >= olo && k + 1 <= ohi) vi = a_ou[u];
-      if (eI && k + 1 >= elo && k + 1 <= ehi) vi = max(vi, a_ie[u]);
-      if (vi >= 0 && vi - k > m) vi = NEG;
-      // D: from k - 1
-      if (fo && k - 1 >= olo && k - 1 <= ohi) vd = a_od[u];
-      if (eD && k - 1 >= elo && k - 1 <= ehi) vd = max(vd, a_de[u]);
-      if (vd >= 0) { vd += 1; if (vd > n) vd = NEG; } else vd = NEG;
-      // X: from k
-      if (fx && k >= xlo && k <= xhi) vx = a_x[u];
-      if (vx >= 0) { vx += 1; if (vx > n || vx - k > m) vx = NEG; } else vx = NEG;
-      if (vi < 0) vi = NEG;
+      // Selects rather than branches: every range test is one unsigned
+      // compare against a width that is 0 for an absent source, and a
+      // candidate is dropped (NEG) unless it lies in the table.
+      const int32_t vi0 = max((uint32_t)(k + 1 - olo) < ow ? a_ou[u] : NEG,
+                              (uint32_t)(k + 1 - elo) < iw ? a_ie[u] : NEG);
+      const int32_t vi = ((vi0 >= 0) & (vi0 - k <= m)) ? vi0 : NEG;
+      const int32_t vd0 = max((uint32_t)(k - 1 - olo) < ow ? a_od[u] : NEG,
+                              (uint32_t)(k - 1 - elo) < dw ? a_de[u] : NEG);
+      const int32_t vd = ((vd0 >= 0) & (vd0 < n)) ? vd0 + 1 : NEG;
+      const int32_t vx0 = (uint32_t)(k - xlo) < xw ? a_x[u] : NEG;
+      const int32_t vx = ((vx0 >= 0) & (vx0 < n) & (vx0 + 1 - k <= m)) ? vx0 + 1 : NEG;
       int32_t vm = max(vx, max(vi, vd));
       if (crow) {
         // every lane of the row takes part (k - lo has the parity of the lane)
         const uint8_t b = code_pair(origin_code_of(
-            vx, vi, vd, vm, vi >= 0 && fo && k + 1 >= olo && k + 1 <= ohi && a_ou[u] == vi,
-            vd >= 0 && fo && k - 1 >= olo && k - 1 <= ohi && a_od[u] >= 0 && a_od[u] + 1 == vd));
+            vx, vi, vd, vm, (vi >= 0) & ((uint32_t)(k + 1 - olo) < ow) & (a_ou[u] == vi),
+            (vd >= 0) & ((uint32_t)(k - 1 - olo) < ow) & (a_od[u] >= 0) & (a_od[u] + 1 == vd)));
         if (!(lane & 1) && k <= hi) crow[(k - lo) >> 1] = b;
       }
-      if (k > hi) continue;
-      if (vm >= 0) vm = q.ext(m, n, k, vm);
-      dM[k - lo] = wf_put<E>(vm);
-      dI[k - lo] = wf_put<E>(vi);
-      dD[k - lo] = wf_put<E>(vd);
+      vm = q.ext_all(m, n, k, vm);
+      if (k <= hi) {
+        dM[k - lo] = wf_put<E>(vm);
+        dI[k - lo] = wf_put<E>(vi);
+        dD[k - lo] = wf_put<E>(vd);
+      }
     }
   }
   lo_out = lo;
@@ -364,9 +385,12 @@ __device__ __forceinline__ void wave_append1(bool pred, int32_t v, int32_t *list
 }
 
 // ---------------------------------------------------------------- pass 1
-// ring_in_lds: ring lives in dynamic LDS; else in the HBM slot of this WG.
+// RING_LDS: the ring lives in dynamic LDS, else in the HBM slot of this
+// workgroup (a compile-time choice, so that each is reached with its own
+// instructions rather than generic ones).
+template <bool RING_LDS>
 __global__ __launch_bounds__(WGMAX) void k_wfa_score(Seqs S, Outs O, Scoring P, Work Wk, WfaLaunch L,
-                                                  int32_t *hbm, int32_t ring_in_lds) {
+                                                  int32_t *hbm) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int32_t sh_pair;
   const int lane = threadIdx.x;
@@ -374,7 +398,7 @@ __global__ __launch_bounds__(WGMAX) void k_wfa_score(Seqs S, Outs O, Scoring P, 
   uint64_t *sT = sP + L.seq_words;
   int32_t *tab_ring = (int32_t *)(sT + L.seq_words);       // R entries
   int32_t *lds_ring = tab_ring + L.R * ENTRY;
-  int32_t *ring = ring_in_lds ? lds_ring : (hbm + (int64_t)blockIdx.x * L.slot_words);
+  int32_t *ring = RING_LDS ? lds_ring : (hbm + (int64_t)blockIdx.x * L.slot_words);
   const int32_t x = P.x, oe = P.o + P.e, e = P.e, R = L.R;
   const int64_t count = Wk.count ? (int64_t)(*(volatile const int32_t *)Wk.count) : Wk.n;
   // a workgroup the work can never reach leaves before touching the counter
@@ -956,8 +980,10 @@ hipError_t launch_wfa_score(const Seqs &S, const Outs &O, const Scoring &P, cons
                             int32_t threads, hipStream_t s) {
   const size_t lds = 2 * (size_t)L.seq_words * 8 + (size_t)L.R * ENTRY * 4 +
                      (ring_in_lds ? (size_t)L.R * 3 * L.wcap * 4 : 0);
-  hipLaunchKernelGGL(k_wfa_score, dim3(nslots), dim3(threads), lds, s, S, O, P, Wk, L, hbm,
-                     (int32_t)ring_in_lds);
+  if (ring_in_lds)
+    hipLaunchKernelGGL(k_wfa_score<true>, dim3(nslots), dim3(threads), lds, s, S, O, P, Wk, L, hbm);
+  else
+    hipLaunchKernelGGL(k_wfa_score<false>, dim3(nslots), dim3(threads), lds, s, S, O, P, Wk, L, hbm);
   return hipGetLastError();
 }
 
