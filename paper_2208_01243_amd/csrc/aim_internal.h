@@ -201,9 +201,11 @@ struct WfaPlan {
 
 WfaPlan wfa_plan(int32_t max_len, const Scoring &P, int64_t budget_bytes, int32_t cus, bool plain,
                  int32_t ring_kb, int32_t trace_kb, int32_t long_threads);
+// ring16 (HBM ring only): 16-bit ring entries, for batches with max_len <=
+// WFA16_MAX_LEN.
 hipError_t launch_wfa_score(const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk,
                             const WfaLaunch &L, int32_t *hbm, bool ring_in_lds, int32_t nslots,
-                            int32_t threads, hipStream_t s);
+                            int32_t threads, bool ring16, hipStream_t s);
 // Pass 1 by one wavefront per pair with 16-bit offsets in LDS over a window of
 // 64 C diagonals (C <= 4); needs max_len <= WFA16_MAX_LEN and L.seq_words > 0
 // (sequences staged in LDS).  Pairs that leave the window go to L.ring_list.

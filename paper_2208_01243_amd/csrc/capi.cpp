@@ -286,7 +286,7 @@ aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const
     A.wcap = pl.wcap_lds;
     aim::Work W{order, nullptr, n, cnt + C_W1, nullptr, nullptr, 0};
     Phase ph(c, s, "wfa_score");
-    HIP_TRY(aim::launch_wfa_score(S, O, P, W, A, nullptr, true, slots, 64, s));
+    HIP_TRY(aim::launch_wfa_score(S, O, P, W, A, nullptr, true, slots, 64, false, s));
   }
   {
     // pairs whose wavefronts outgrew the LDS ring (all pairs for the plain path)
@@ -314,7 +314,7 @@ aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const
     aim::Work W{all ? order : lists, all ? nullptr : cnt + C_RL, n, cnt + C_W1G, nullptr, nullptr, 0};
     Phase ph(c, s, "wfa_score_hbm");
     HIP_TRY(aim::launch_wfa_score(S, O, P, W, B, as<int32_t>(c->wring), false, grid,
-                                  plain ? 64 : pl.ring_threads, s));
+                                  plain ? 64 : pl.ring_threads, !plain && L <= aim::WFA16_MAX_LEN, s));
   }
   if (!P.want_cigar) return AIM_OK;
   // pass 2 by class: 0 LDS arena, 1-3 HBM slots of growing size

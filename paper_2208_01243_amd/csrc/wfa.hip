@@ -388,7 +388,8 @@ __device__ __forceinline__ void wave_append1(bool pred, int32_t v, int32_t *list
 // RING_LDS: the ring lives in dynamic LDS, else in the HBM slot of this
 // workgroup (a compile-time choice, so that each is reached with its own
 // instructions rather than generic ones).
-template <bool RING_LDS>
+// E: element type of the ring (int16 when every offset of the batch fits).
+template <bool RING_LDS, class E>
 __global__ __launch_bounds__(WGMAX) void k_wfa_score(Seqs S, Outs O, Scoring P, Work Wk, WfaLaunch L,
                                                   int32_t *hbm) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -399,6 +400,7 @@ __global__ __launch_bounds__(WGMAX) void k_wfa_score(Seqs S, Outs O, Scoring P, 
   int32_t *tab_ring = (int32_t *)(sT + L.seq_words);       // R entries
   int32_t *lds_ring = tab_ring + L.R * ENTRY;
   int32_t *ring = RING_LDS ? lds_ring : (hbm + (int64_t)blockIdx.x * L.slot_words);
+  const int32_t slot_w = wf_words<E>(3 * L.wcap);  // words per ring slot
   const int32_t x = P.x, oe = P.o + P.e, e = P.e, R = L.R;
   const int64_t count = Wk.count ? (int64_t)(*(volatile const int32_t *)Wk.count) : Wk.n;
   // a workgroup the work can never reach leaves before touching the counter
@@ -451,13 +453,13 @@ __global__ __launch_bounds__(WGMAX) void k_wfa_score(Seqs S, Outs O, Scoring P, 
       int present;
       bool overflow = false;
       if (s == 0) {
-        if (lane == 0) ring[sl * 3 * L.wcap] = q.ext(m, n, 0, 0);
+        if (lane == 0) reinterpret_cast<E *>(ring + sl * slot_w)[0] = wf_put<E>(q.ext(m, n, 0, 0));
         present = 1;
         lo = hi = 0;
       } else {
         if (keep && s >= L.walk_steps) keep = false;
         int32_t cbytes = 0;
-        present = wf_step<int32_t>(s, x, oe, e, m, n, tab_ring, ring, slot_of, ring, sl * 3 * L.wcap, L.wcap,
+        present = wf_step<E>(s, x, oe, e, m, n, tab_ring, ring, slot_of, ring, sl * slot_w, L.wcap,
                                    lo, hi, q, overflow, keep ? wcodes + cbase : nullptr,
                                    L.walk_codes - cbase, &cbytes);
         if (cbytes < 0) keep = false;
@@ -468,7 +470,7 @@ __global__ __launch_bounds__(WGMAX) void k_wfa_score(Seqs S, Outs O, Scoring P, 
       if (lane == 0) {
         tab_ring[sl * ENTRY + 0] = lo;
         tab_ring[sl * ENTRY + 1] = hi;
-        tab_ring[sl * ENTRY + 2] = sl * 3 * L.wcap;
+        tab_ring[sl * ENTRY + 2] = sl * slot_w;
         tab_ring[sl * ENTRY + 3] = present;
         if (keep) {
           wtab[4 * s + 0] = lo;
@@ -483,7 +485,8 @@ __global__ __launch_bounds__(WGMAX) void k_wfa_score(Seqs S, Outs O, Scoring P, 
         need += ENTRY;
       }
       __syncthreads();
-      if (present && kend >= lo && kend <= hi && ring[sl * 3 * L.wcap + (kend - lo)] >= n) {
+      if (present && kend >= lo && kend <= hi &&
+          (int32_t)reinterpret_cast<const E *>(ring + sl * slot_w)[kend - lo] >= n) {
         result = 1;
         break;
       }
@@ -977,13 +980,15 @@ WfaPlan wfa_plan(int32_t max_len, const Scoring &P, int64_t budget_bytes, int32_
 
 hipError_t launch_wfa_score(const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk,
                             const WfaLaunch &L, int32_t *hbm, bool ring_in_lds, int32_t nslots,
-                            int32_t threads, hipStream_t s) {
+                            int32_t threads, bool ring16, hipStream_t s) {
   const size_t lds = 2 * (size_t)L.seq_words * 8 + (size_t)L.R * ENTRY * 4 +
                      (ring_in_lds ? (size_t)L.R * 3 * L.wcap * 4 : 0);
   if (ring_in_lds)
-    hipLaunchKernelGGL(k_wfa_score<true>, dim3(nslots), dim3(threads), lds, s, S, O, P, Wk, L, hbm);
+    hipLaunchKernelGGL((k_wfa_score<true, int32_t>), dim3(nslots), dim3(threads), lds, s, S, O, P, Wk, L, hbm);
+  else if (ring16)
+    hipLaunchKernelGGL((k_wfa_score<false, int16_t>), dim3(nslots), dim3(threads), lds, s, S, O, P, Wk, L, hbm);
   else
-    hipLaunchKernelGGL(k_wfa_score<false>, dim3(nslots), dim3(threads), lds, s, S, O, P, Wk, L, hbm);
+    hipLaunchKernelGGL((k_wfa_score<false, int32_t>), dim3(nslots), dim3(threads), lds, s, S, O, P, Wk, L, hbm);
   return hipGetLastError();
 }
 
