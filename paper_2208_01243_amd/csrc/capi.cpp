@@ -299,13 +299,13 @@ aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const
     const bool all = plain || (!w16 && pl.wcap_lds == 0);
     const int32_t grid = all ? std::min<int32_t>(slots, pl.ring_slots) : pl.ring_slots;
     if (P.want_cigar && !plain) {
-      // origin codes for the fused walk: 1/8 of the budget over the workgroups
+      // origin codes for the fused walk: 1/4 of the budget over the workgroups
       B.walk_steps = P.max_score >= 0 ? std::min(P.max_score + 1, aim::WFA_WALK_STEPS) : aim::WFA_WALK_STEPS;
       B.walk_tok = 2 * (2 * L + 1) + 8;
       // (no more than every kept score at the widest wavefront needs)
       const int64_t most = (int64_t)B.walk_steps * ((pl.wcap + 1) / 2) + 16;
       B.walk_codes = std::min<int64_t>(
-          most, std::max<int64_t>(256 << 10, std::min<int64_t>(16 << 20, c->opt.scratch_limit / 8 / grid)));
+          most, std::max<int64_t>(256 << 10, std::min<int64_t>(16 << 20, c->opt.scratch_limit / 4 / grid)));
       B.walk_codes = (B.walk_codes + 15) / 16 * 16;
       B.walk_slot = ((int64_t)B.walk_steps * 16 + B.walk_codes + (int64_t)B.walk_tok * 4 + 255) / 256 * 256;
       if ((st = ensure(c, c->wwalk, (size_t)B.walk_slot * grid))) return st;

@@ -932,8 +932,8 @@ __global__ __launch_bounds__(WGMAX) void k_wfa_trace(Seqs S, Outs O, Scoring P, 
 
 WfaPlan wfa_plan(int32_t max_len, const Scoring &P, int64_t budget_bytes, int32_t cus, bool plain,
                  int32_t ring_kb, int32_t trace_kb, int32_t long_threads) {
-  // budget split: HBM rings 1/8, origin codes 1/8, arena classes 1/16, 3/16
-  // and 3/8
+  // budget split: HBM rings 1/8, origin codes 1/4, arena classes 1/32, 1/8
+  // and 1/4
   WfaPlan pl{};
   const int32_t oe = P.o + P.e;
   pl.R = std::max(P.x, oe) + 1;
@@ -950,7 +950,7 @@ WfaPlan wfa_plan(int32_t max_len, const Scoring &P, int64_t budget_bytes, int32_
   pl.lds_score_bytes = (int32_t)(fixed + (int64_t)pl.R * 3 * pl.wcap_lds * 4);
   pl.ring_slot_words = (int64_t)pl.R * 3 * pl.wcap;
   pl.ring_slots = (int32_t)std::max<int64_t>(
-      1, std::min<int64_t>((int64_t)cus * 4, budget_bytes / 8 / (pl.ring_slot_words * 4)));
+      1, std::min<int64_t>((int64_t)cus * 6, budget_bytes / 8 / (pl.ring_slot_words * 4)));
   pl.ring_threads = max_len > 1024 ? long_threads : 64;
   // full-store arena classes (words): LDS, then HBM stores of up to 1 MB,
   // 16 MB and 192 MB, with wider workgroups for the larger classes
@@ -961,11 +961,11 @@ WfaPlan wfa_plan(int32_t max_len, const Scoring &P, int64_t budget_bytes, int32_
   pl.need_cap[3] = std::max<int64_t>(pl.need_cap[2], std::min<int64_t>((int64_t)48 << 20, budget_bytes / 2 / 4));
   pl.arena_slots[0] = cus * 8;
   pl.threads[0] = 64;
-  // pools: 1/16, 3/16 and 3/8 of the budget (the origin codes of the HBM-ring
-  // pass take another 1/8), each at least one slot of its class capacity; the
+  // pools: 1/32, 1/8 and 1/4 of the budget (the origin codes of the HBM-ring
+  // pass take another 1/4), each at least one slot of its class capacity; the
   // workgroups that take pairs are those whose slot (the class's largest
   // store) fits the pool
-  const int64_t share[4] = {0, budget_bytes / 16, budget_bytes * 3 / 16, budget_bytes * 3 / 8};
+  const int64_t share[4] = {0, budget_bytes / 32, budget_bytes / 8, budget_bytes / 4};
   const int64_t cap_slots[4] = {0, (int64_t)cus * 8, (int64_t)cus * 4, (int64_t)cus * 4};
   for (int k = 1; k < 4; ++k) {
     const int64_t cap = (pl.need_cap[k] + 63) / 64 * 64;

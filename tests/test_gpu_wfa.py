@@ -139,9 +139,9 @@ def test_walk_fallback_to_full_store(ctx):
     # A small scratch limit leaves the HBM-ring pass too little room for the
     # origin codes of its longer pairs, which then take the full-store passes;
     # the shorter ones are walked from their codes.
-    # (at 2 GiB each workgroup keeps about 1.4 MB of codes: the 10 % pairs of
-    # 4-6 kbp need more, the 1 % pairs less)
-    b = _mixed(43, 16, 4000, 6000, [0.01, 0.1])
+    # (at 2 GiB each workgroup keeps under 3 MB of codes: the 10 % pairs of
+    # 8-10 kbp need more, the 1 % pairs far less)
+    b = _mixed(43, 12, 8000, 10000, [0.01, 0.1])
     small = aim.Context(0, scratch_limit=2 << 30)
     try:
         s, st, cg, off = run(small, b, "wfa", AFF)
