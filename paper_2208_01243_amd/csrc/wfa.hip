@@ -390,8 +390,8 @@ __device__ __forceinline__ void wave_append1(bool pred, int32_t v, int32_t *list
 // instructions rather than generic ones).
 // E: element type of the ring (int16 when every offset of the batch fits).
 template <bool RING_LDS, class E>
-__global__ __launch_bounds__(WGMAX) void k_wfa_score(Seqs S, Outs O, Scoring P, Work Wk, WfaLaunch L,
-                                                  int32_t *hbm) {
+__global__ __launch_bounds__(WGMAX) __attribute__((amdgpu_waves_per_eu(7)))
+void k_wfa_score(Seqs S, Outs O, Scoring P, Work Wk, WfaLaunch L, int32_t *hbm) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int32_t sh_pair;
   const int lane = threadIdx.x;
@@ -950,7 +950,7 @@ WfaPlan wfa_plan(int32_t max_len, const Scoring &P, int64_t budget_bytes, int32_
   pl.lds_score_bytes = (int32_t)(fixed + (int64_t)pl.R * 3 * pl.wcap_lds * 4);
   pl.ring_slot_words = (int64_t)pl.R * 3 * pl.wcap;
   pl.ring_slots = (int32_t)std::max<int64_t>(
-      1, std::min<int64_t>((int64_t)cus * 6, budget_bytes / 8 / (pl.ring_slot_words * 4)));
+      1, std::min<int64_t>((int64_t)cus * 7, budget_bytes / 8 / (pl.ring_slot_words * 4)));
   pl.ring_threads = max_len > 1024 ? long_threads : 64;
   // full-store arena classes (words): LDS, then HBM stores of up to 1 MB,
   // 16 MB and 192 MB, with wider workgroups for the larger classes
