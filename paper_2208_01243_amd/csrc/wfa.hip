@@ -932,8 +932,8 @@ __global__ __launch_bounds__(WGMAX) void k_wfa_trace(Seqs S, Outs O, Scoring P, 
 
 WfaPlan wfa_plan(int32_t max_len, const Scoring &P, int64_t budget_bytes, int32_t cus, bool plain,
                  int32_t ring_kb, int32_t trace_kb, int32_t long_threads) {
-  // budget split: HBM rings 1/8, origin codes 1/4, arena classes 1/32, 1/8
-  // and 1/4
+  // budget split: HBM rings 1/8, origin codes 1/4 (HBM-ring pass) and 1/16
+  // (one-wavefront pass), arena classes 1/32, 1/8 and 1/4
   WfaPlan pl{};
   const int32_t oe = P.o + P.e;
   pl.R = std::max(P.x, oe) + 1;
