@@ -194,9 +194,8 @@ aim_status aim_timing_reset(aim_context *ctx);
  * fastest for (alg, length bucket of pairs->max_len); later calls with that
  * key use it.  Candidates: NW/SWG -- first band width {32, 64}, resident
  * wavefronts per CU {8, 16, 32}, length sort {off, on}, packed 16-bit cells
- * {off, on} (32 diagonals only); WFA -- LDS for the
- * score ring {16, 32, 48} KB, for the full store {12, 16, 24} KB, workgroup size
- * for long pairs {128, 256}.  Each candidate runs once to warm up and `reps`
+ * {off, on} (32 diagonals only); WFA -- length sort {off, on}, workgroup size
+ * for wide pairs {128, 256}.  Each candidate runs once to warm up and `reps`
  * times timed (median).  Synchronous.  On return `out` holds the results of
  * the chosen configuration; best_params (7 int32, see aim_tune_get) and
  * best_ms may be NULL.  Paper: Data Management (the framework picks the

@@ -731,16 +731,15 @@ aim_status aim_autotune(aim_context *c, const aim_batch *B, int32_t alg, aim_pen
   if (reps < 1 || reps > 100) return fail(AIM_ERR_INVALID_ARG, "reps must be in [1, 100]");
   std::vector<Tune> cand;
   if (alg == AIM_WFA_AFFINE) {
-    for (int ring : {16, 32, 48})
-      for (int trace : {12, 16, 24})
-        for (int th : {128, 256}) {
-          Tune t;
-          t.sort = 1;
-          t.wfa_ring_kb = ring;
-          t.wfa_trace_kb = trace;
-          t.wfa_long_threads = th;
-          cand.push_back(t);
-        }
+    // the LDS sizes only matter on the fallback paths; the order of the pairs
+    // and the workgroup of the wide-pair pass decide the time
+    for (int so : {0, 1})
+      for (int th : {128, 256}) {
+        Tune t;
+        t.sort = so;
+        t.wfa_long_threads = th;
+        cand.push_back(t);
+      }
   } else {
     for (int w0 : {32, 64})
       for (int wpc : {8, 16, 32})
