@@ -160,26 +160,26 @@ int64_t full_slot_words(int32_t max_len);
 
 // Wavefront algorithm, one pair per 64-lane wavefront, two passes.
 struct WfaLaunch {
-  int32_t R;            // ring slots (pass 1): max(x, o+e) + 1
-  int32_t wcap;         // ring width capacity of this launch (pass 1)
+  int32_t R;            // ring slots (score passes): max(x, o+e) + 1
+  int32_t wcap;         // ring width capacity of this launch (score passes)
   int32_t seq_words;    // words of LDS per staged sequence (0: read from HBM)
-  int32_t full_in_lds;  // pass 2: arena in LDS
-  int64_t slot_words;   // HBM slot per workgroup (pass 1 ring / pass 2 arena), or LDS arena words
-  int32_t *ring_list;   // pass 1: pairs whose width passed wcap
+  int32_t full_in_lds;  // fallback pass: arena in LDS
+  int64_t slot_words;   // HBM slot per workgroup (score ring / fallback arena), or LDS arena words
+  int32_t *ring_list;   // score pass: pairs whose width passed wcap
   int32_t *ring_count;
-  int32_t *need_list[4];  // pass 1 -> pass 2: accepted pairs by full-store class
+  int32_t *need_list[4];  // score -> fallback pass: accepted pairs by full-store class
   int32_t *need_count[4];
   int64_t need_cap[4];    // class capacities in words
-  int32_t *need_max[4];   // pass 1 -> pass 2: largest full store per class (words)
+  int32_t *need_max[4];   // score -> fallback pass: largest full store per class (words)
   int64_t *need;          // per pair: words of the full store
-  int32_t store16;        // pass 1 counts the full store in 16-bit entries
-  // pass 2, HBM arena: when set, each workgroup's slot is the class's largest
+  int32_t store16;        // score passes count the full store in 16-bit entries
+  // fallback pass, HBM arena: when set, each workgroup's slot is the class's largest
   // full store (rounded up), and only pool_words / slot workgroups take pairs
   const int32_t *slot_need_max;
   int64_t pool_words;
   // one-wavefront score pass with a CIGAR wanted: per workgroup, room for the
   // origin codes of bits_steps scores (0: none); pairs that need more go to
-  // pass 2
+  // the fallback pass
   uint8_t *bits;
   int32_t bits_steps;
   // HBM-ring score pass with a CIGAR wanted: per workgroup, a table of

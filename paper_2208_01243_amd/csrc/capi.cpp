@@ -238,8 +238,11 @@ Tune tune_for(aim_context *c, int32_t alg, int32_t L) {
   return it == c->tunes.end() ? Tune{} : it->second;
 }
 
-// WFA: pass 1 (score) with the ring in LDS, then with the ring in HBM for
-// pairs too wide for LDS; pass 2 (full store + backtrace) by store-size class.
+// WFA: the one-wavefront score pass (16-bit LDS ring, fused walk) when the
+// batch allows it, else the score pass with the ring in LDS; then the score
+// pass with the ring in HBM for pairs too wide for either (fused walk too);
+// then the fallback pass (full store + walk) by store-size class for pairs
+// whose origin codes did not fit.
 aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const aim::Scoring &P,
                    int64_t n, int32_t L, bool plain, int32_t *cnt, const int32_t *order,
                    const Tune &tu, hipStream_t s) {
@@ -266,7 +269,7 @@ aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const
   const int32_t C16 = (int32_t)std::min<int64_t>(4, std::max<int64_t>(1, (pl.wcap + 63) / 64));
   const bool w16 = !plain && L <= aim::WFA16_MAX_LEN && pl.R <= 32 && pl.seq_words > 0 &&
                    aim::wfa_score16_lds(WL, P.e, C16) <= 48 * 1024;
-  WL.store16 = w16;  // the full store of pass 2 holds 16-bit offsets
+  WL.store16 = w16;  // the full store of the fallback pass holds 16-bit offsets
   if (w16) {
     const int32_t nslots16 = (int32_t)std::min<int64_t>(n, (int64_t)c->cus * 20);
     aim::WfaLaunch A = WL;
@@ -320,7 +323,7 @@ aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const
                                   plain ? 64 : pl.ring_threads, !plain && L <= aim::WFA16_MAX_LEN, s));
   }
   if (!P.want_cigar) return AIM_OK;
-  // pass 2 by class: 0 LDS arena, 1-3 HBM slots of growing size
+  // fallback pass by class: 0 LDS arena, 1-3 HBM slots of growing size
   Buf *arena[4] = {nullptr, &c->warena1, &c->warena2, &c->warena3};
   static const char *names[4] = {"wfa_trace_lds", "wfa_trace_1m", "wfa_trace_16m", "wfa_trace_192m"};
   for (int k = 0; k < 4; ++k) {

@@ -1,12 +1,14 @@
-// Gap-affine wavefront alignment (WFA), one pair per 64-lane wavefront with
-// the diagonals of each wavefront spread over the lanes.
+// Gap-affine wavefront alignment (WFA): the diagonals of each wavefront spread
+// over the lanes of one wavefront (k_wfa_score16) or of a workgroup (wide
+// pairs, k_wfa_score).
 //
 // Paper: System and Methods, "Wavefront Algorithm (WFA)": successive
 // furthest-reaching wavefronts, one per score s, each computed from the
 // components of a few earlier wavefronts, until the end cell is reached; the
 // components are allocated dynamically as they grow (Data Management: the
-// per-thread bump allocator, here a per-pair arena with a bump pointer).  The
-// recurrences, restated on offsets j along diagonals k = j - i, are
+// per-thread bump allocator, here a per-pair arena with a bump pointer in the
+// fallback pass).  The recurrences, restated on offsets j along diagonals
+// k = j - i, are
 //   I_s[k] = max(M_{s-o-e}[k+1], I_{s-e}[k+1])         (consumes P)
 //   D_s[k] = max(M_{s-o-e}[k-1], D_{s-e}[k-1]) + 1     (consumes T)
 //   M_s[k] = max(M_{s-x}[k] + 1, I_s[k], D_s[k])
@@ -15,17 +17,16 @@
 // first s with M_s[n-m] >= n is the optimum; with a threshold the search stops
 // (rejected) once s exceeds it.
 //
-// Two passes:
-//   pass 1 (score): wavefronts in a ring of R = max(x, o+e) + 1 slots (the
-//     oldest source is s - max(x, o+e)), in LDS when it fits, else in an HBM
-//     slot.  Yields the score or the rejection, and the exact number of words
-//     the full store of pass 2 needs.
-//   pass 2 (accepted pairs, CIGAR wanted): recompute s = 0..score keeping every
-//     wavefront (arena in LDS when it fits, else an HBM slot sized by class),
-//     then one lane walks the canonical backtrace: from M at (s,k,f) emit
-//     f - f0 '=' ops, then the first of X, I, D whose candidate attains f0;
-//     from I (D) prefer the opening source M_{s-o-e} over extension.  This
-//     reproduces the DP oracle's canonical CIGAR (same tie order).
+// The score passes keep the last R = max(x, o+e) + 1 wavefronts in a ring (the
+// oldest source is s - max(x, o+e)) and, when a CIGAR is wanted, 4 bits per
+// cell recording how each component got its value (see walk_codes below).
+// After the end cell is reached the pass walks those codes itself: from M emit
+// the '=' run, then the first of X, I, D whose candidate attains the
+// pre-extension offset; from I (D) prefer the opening source M_{s-o-e} over
+// extension.  This reproduces the DP oracle's canonical CIGAR (same tie
+// order).  Pairs whose codes do not fit their slot take the fallback pass
+// (k_wfa_trace), which recomputes s = 0..score keeping every wavefront's
+// offsets and walks those.
 #include <algorithm>
 
 #include "aim_internal.h"
@@ -384,7 +385,7 @@ __device__ __forceinline__ void wave_append1(bool pred, int32_t v, int32_t *list
   }
 }
 
-// ---------------------------------------------------------------- pass 1
+// ------------------------------------------------ score pass, wide pairs
 // RING_LDS: the ring lives in dynamic LDS, else in the HBM slot of this
 // workgroup (a compile-time choice, so that each is reached with its own
 // instructions rather than generic ones).
@@ -542,7 +543,7 @@ void k_wfa_score(Seqs S, Outs O, Scoring P, Work Wk, WfaLaunch L, int32_t *hbm) 
   }
 }
 
-// ------------------------------------------------- pass 1, one wavefront per pair
+// -------------------------------------------- score pass, one wavefront per pair
 // The wavefronts of k_wfa_score (same recurrences, bounds, presence bits and
 // full-store size), computed by a single 64-lane wavefront with no barrier
 // between waves: lane l owns diagonals kbase + l + 64 c for c < C, kbase =
@@ -761,7 +762,7 @@ __global__ __launch_bounds__(64) void k_wfa_score16(Seqs S, Outs O, Scoring P, W
   }
 }
 
-// ---------------------------------------------------------------- pass 2
+// ----------------------------------------------- fallback: full-store walk
 // LDSA: the full store lives in this workgroup's LDS (else in its HBM slot);
 // a compile-time choice, so that LDS traffic is issued as LDS instructions.
 template <class E, bool LDSA>
