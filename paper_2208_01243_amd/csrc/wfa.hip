@@ -158,42 +158,100 @@ __device__ __forceinline__ uint8_t code_pair(int32_t code) {
   return (uint8_t)(code | (up << 4));
 }
 
-// Run by one whole wavefront on uniform values; its lane 0 writes.  code_of(s,
-// k) gives the code of a kept cell, or -1; ext(k, f) extends offset f on
-// diagonal k.  Returns false (nothing written to the CIGAR outputs) when a
-// code is missing or the tokens outgrow `tok`.
-template <class CodeOf, class Ext>
-__device__ bool walk_codes(const Outs &O, int64_t p, CodeOf code_of, Ext ext, int32_t x, int32_t oe,
+// Run by one whole wavefront on uniform values; its lane 0 writes.
+// code_at(s, k) is evaluated per lane and gives the code of a kept cell, or
+// -1; ext(k, f) extends offset f on diagonal k.  Returns false (nothing
+// written to the CIGAR outputs) when a code is missing or the tokens outgrow
+// `tok`.
+//
+// A move leaves a cell (s, k) for one of five cells: X (s-x, k), I opened
+// (s-o-e, k+1) or extended (s-e, k+1), D opened (s-o-e, k-1) or extended
+// (s-e, k-1).  With AHEAD, each round of loads fetches, one cell per lane, the
+// codes of the five successors of the current cell and of their 25 successors,
+// so that two moves follow every round trip to memory (worth it where the walk
+// is on the critical path: the few long pairs of a wide-pair pass); without,
+// each move loads the one code it needs.
+template <bool AHEAD, class CodeAt, class Ext>
+__device__ bool walk_codes(const Outs &O, int64_t p, CodeAt code_at, Ext ext, int32_t x, int32_t oe,
                            int32_t e, int32_t m, int32_t n, int32_t sfin, uint32_t *tok, int32_t tok_cap) {
   const int lane = threadIdx.x & 63;
-  int32_t cs = sfin, k = n - m, comp = 0, nt = 0, code = -1;
+  int32_t cs = sfin, k = n - m, comp = 0, nt = 0;
   bool ok = true;
-  for (;;) {
-    if (nt + 2 > tok_cap || cs < 0) { ok = false; break; }
-    if (comp == 0) {
-      if (lane == 0) tok[nt] = TOK_M;
-      ++nt;
-      if (cs == 0) { ok = k == 0; break; }
-      if (code < 0) code = code_of(cs, k);
-      if (code < 0) { ok = false; break; }
-      const int32_t src = code & 3;
-      if (src == 0) {
-        if (lane == 0) tok[nt] = OP_X;
+  if constexpr (!AHEAD) {
+    int32_t code = -1;
+    for (;;) {
+      if (nt + 2 > tok_cap || cs < 0) { ok = false; break; }
+      if (comp == 0) {
+        if (lane == 0) tok[nt] = TOK_M;
         ++nt;
-        cs -= x;
-        code = -1;
+        if (cs == 0) { ok = k == 0; break; }
+        if (code < 0) code = __builtin_amdgcn_readfirstlane(code_at(cs, k));
+        if (code < 0) { ok = false; break; }
+        const int32_t src = code & 3;
+        if (src == 0) {
+          if (lane == 0) tok[nt] = OP_X;
+          ++nt;
+          cs -= x;
+          code = -1;
+        } else {
+          comp = src;  // I or D of the same cell
+        }
       } else {
-        comp = src;  // I or D of the same cell
+        if (code < 0) code = __builtin_amdgcn_readfirstlane(code_at(cs, k));
+        if (code < 0) { ok = false; break; }
+        const bool open = (code >> (comp + 1)) & 1;
+        if (lane == 0) tok[nt] = comp == 1 ? OP_I : OP_D;
+        ++nt;
+        k += comp == 1 ? 1 : -1;
+        if (open) { cs -= oe; comp = 0; } else { cs -= e; }
+        code = -1;
       }
-    } else {
-      if (code < 0) code = code_of(cs, k);
-      if (code < 0) { ok = false; break; }
-      const bool open = (code >> (comp + 1)) & 1;
-      if (lane == 0) tok[nt] = comp == 1 ? OP_I : OP_D;
-      ++nt;
-      k += comp == 1 ? 1 : -1;
-      if (open) { cs -= oe; comp = 0; } else { cs -= e; }
-      code = -1;
+    }
+  } else {
+    auto dstep = [&](int j) { return j == 0 ? x : ((j & 1) ? oe : e); };  // score drop of move j
+    auto dkst = [&](int j) { return j == 0 ? 0 : (j <= 2 ? 1 : -1); };    // diagonal change of move j
+    // this lane's cell of a round: lanes 0..4 the successors, 5..29 theirs
+    const int j1 = lane < 5 ? lane : (lane - 5) / 5, j2 = lane < 5 ? -1 : (lane - 5) % 5;
+    const int32_t lds_ = lane < 30 ? dstep(j1) + (j2 >= 0 ? dstep(j2) : 0) : 0;
+    const int32_t ldk = lane < 30 ? dkst(j1) + (j2 >= 0 ? dkst(j2) : 0) : 0;
+    int32_t code = __builtin_amdgcn_readfirstlane(code_at(cs, k));
+    bool done = false;
+    while (ok && !done) {
+      // one round: the codes two moves ahead of (cs, k)
+      const int32_t v = lane < 30 ? code_at(cs - lds_, k + ldk) : -1;
+      int moves = 0, j0 = 0;
+      while (moves < 2) {
+        if (nt + 2 > tok_cap || cs < 0) { ok = false; break; }
+        int j = -1;  // move taken from this cell, if any
+        if (comp == 0) {
+          if (lane == 0) tok[nt] = TOK_M;
+          ++nt;
+          if (cs == 0) { ok = k == 0; done = true; break; }
+          if (code < 0) { ok = false; break; }
+          const int32_t src = code & 3;
+          if (src == 0) {
+            if (lane == 0) tok[nt] = OP_X;
+            ++nt;
+            j = 0;
+          } else {
+            comp = src;  // I or D of the same cell
+          }
+        } else {
+          if (code < 0) { ok = false; break; }
+          const bool open = (code >> (comp + 1)) & 1;
+          if (lane == 0) tok[nt] = comp == 1 ? OP_I : OP_D;
+          ++nt;
+          j = comp == 1 ? (open ? 1 : 2) : (open ? 3 : 4);
+          if (open) comp = 0;
+        }
+        if (j >= 0) {
+          cs -= dstep(j);
+          k += dkst(j);
+          code = __builtin_amdgcn_readlane(v, moves == 0 ? j : 5 + 5 * j0 + j);
+          j0 = j;
+          ++moves;
+        }
+      }
     }
   }
   if (!ok) return false;
@@ -495,16 +553,16 @@ void k_wfa_score(Seqs S, Outs O, Scoring P, Work Wk, WfaLaunch L, int32_t *hbm) 
     if (result == 1 && keep) {
       __syncthreads();  // the codes and table of every wave visible to the walk
       if (threadIdx.x < 64) {
-        auto code_of = [&](int32_t cs, int32_t k) -> int32_t {
-          const int32_t lo = __builtin_amdgcn_readfirstlane(wtab[4 * cs + 0]);
-          const int32_t hi = __builtin_amdgcn_readfirstlane(wtab[4 * cs + 1]);
-          const int32_t cb = __builtin_amdgcn_readfirstlane(wtab[4 * cs + 2]);
+        const int32_t sfin = s;
+        auto code_at = [&](int32_t cs, int32_t k) -> int32_t {  // per lane
+          if (cs < 1 || cs > sfin) return -1;
+          const int32_t lo = wtab[4 * cs + 0], hi = wtab[4 * cs + 1], cb = wtab[4 * cs + 2];
           if (k < lo || k > hi) return -1;
           const uint32_t b = wcodes[cb + ((k - lo) >> 1)];
-          return __builtin_amdgcn_readfirstlane((int32_t)(((k - lo) & 1) ? (b >> 4) : (b & 15u)));
+          return (int32_t)(((k - lo) & 1) ? (b >> 4) : (b & 15u));
         };
         auto ext = [&](int32_t k, int32_t f) { return q.ext(m, n, k, f); };
-        walked = walk_codes(O, p, code_of, ext, x, oe, e, m, n, s, wtok, L.walk_tok);
+        walked = walk_codes<true>(O, p, code_at, ext, x, oe, e, m, n, s, wtok, L.walk_tok);
       }
       __syncthreads();
     }
@@ -723,14 +781,15 @@ __global__ __launch_bounds__(64) void k_wfa_score16(Seqs S, Outs O, Scoring P, W
     bool walked = false;
     if (result == 1 && s < bits_steps) {
       __syncthreads();  // the origin codes stored by every lane, visible to the walk
-      auto code_of = [&](int32_t cs, int32_t k) -> int32_t {
+      const int32_t sfin = s;
+      auto code_at = [&](int32_t cs, int32_t k) -> int32_t {  // per lane
         const int32_t idx = k - kbase;
-        if ((uint32_t)idx >= (uint32_t)W) return -1;
+        if (cs < 1 || cs > sfin || (uint32_t)idx >= (uint32_t)W) return -1;
         const uint32_t b = bslot[((int64_t)cs * C + (idx >> 6)) * 32 + ((idx & 63) >> 1)];
-        return __builtin_amdgcn_readfirstlane((int32_t)((idx & 1) ? (b >> 4) : (b & 15u)));
+        return (int32_t)((idx & 1) ? (b >> 4) : (b & 15u));
       };
       auto ext = [&](int32_t k, int32_t f) { return extend_lds(P32, m, T32, n, k, f); };
-      walked = walk_codes(O, p, code_of, ext, x, oe, e, m, n, s, reinterpret_cast<uint32_t *>(rM),
+      walked = walk_codes<false>(O, p, code_at, ext, x, oe, e, m, n, s, reinterpret_cast<uint32_t *>(rM),
                           (R + 2 * RE) * W / 2);
     }
     if (result == 3) {
