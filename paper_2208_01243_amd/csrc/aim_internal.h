@@ -202,7 +202,8 @@ struct WfaPlan {
 WfaPlan wfa_plan(int32_t max_len, const Scoring &P, int64_t budget_bytes, int32_t cus, bool plain,
                  int32_t ring_kb, int32_t trace_kb, int32_t long_threads);
 // ring16 (HBM ring only): 16-bit ring entries, for batches with max_len <=
-// WFA16_MAX_LEN.
+// WFA16_MAX_LEN.  The HBM ring must be readable for wfa_ring_pad(wcap) words
+// before hbm and after its last slot (its steps read without clamping).
 hipError_t launch_wfa_score(const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk,
                             const WfaLaunch &L, int32_t *hbm, bool ring_in_lds, int32_t nslots,
                             int32_t threads, bool ring16, hipStream_t s);
@@ -216,6 +217,7 @@ constexpr int32_t WFA16_WALK_STEPS = 2048;
 // Scores whose origin codes the HBM-ring score pass keeps for its fused walk.
 constexpr int32_t WFA_WALK_STEPS = 16384;
 size_t wfa_score16_lds(const WfaLaunch &L, int32_t e, int32_t C);
+inline int64_t wfa_ring_pad(int32_t wcap) { return 4 * (int64_t)wcap + 1024; }
 hipError_t launch_wfa_score16(const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk,
                               const WfaLaunch &L, int32_t C, int32_t nslots, hipStream_t s);
 // i16: wavefronts stored as 16-bit offsets (max_len <= WFA16_MAX_LEN); the

@@ -296,7 +296,8 @@ aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const
   }
   {
     // pairs whose wavefronts outgrew the LDS ring (all pairs for the plain path)
-    if ((st = ensure(c, c->wring, (size_t)pl.ring_slot_words * 4 * pl.ring_slots))) return st;
+    const int64_t pad = aim::wfa_ring_pad(pl.wcap);  // read margin at both ends
+    if ((st = ensure(c, c->wring, (size_t)(pl.ring_slot_words * pl.ring_slots + 2 * pad) * 4))) return st;
     aim::WfaLaunch B = WL;
     B.wcap = pl.wcap;
     B.slot_words = pl.ring_slot_words;
@@ -319,7 +320,7 @@ aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const
     }
     aim::Work W{all ? order : lists, all ? nullptr : cnt + C_RL, n, cnt + C_W1G, nullptr, nullptr, 0};
     Phase ph(c, s, "wfa_score_hbm");
-    HIP_TRY(aim::launch_wfa_score(S, O, P, W, B, as<int32_t>(c->wring), false, grid,
+    HIP_TRY(aim::launch_wfa_score(S, O, P, W, B, as<int32_t>(c->wring) + pad, false, grid,
                                   plain ? 64 : pl.ring_threads, !plain && L <= aim::WFA16_MAX_LEN, s));
   }
   if (!P.want_cigar) return AIM_OK;

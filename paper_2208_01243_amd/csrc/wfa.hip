@@ -85,8 +85,10 @@ struct SeqStaged {
   __device__ __forceinline__ int32_t ext_all(int32_t m, int32_t n, int32_t k, int32_t f) const;
 };
 
+// Table entries are the same for every lane: read them as scalars, so that the
+// source arrays they locate are addressed from scalar bases.
 __device__ __forceinline__ int32_t tab_get(const int32_t *tab, int32_t slot, int f) {
-  return tab[slot * ENTRY + f];
+  return __builtin_amdgcn_readfirstlane(tab[slot * ENTRY + f]);
 }
 
 // extend() on sequences staged in LDS, 16 bases per step: the 32-bit window
@@ -316,7 +318,12 @@ __device__ __forceinline__ int32_t wf_words(int32_t elems) {
   return sizeof(E) == 4 ? elems : (elems + 1) / 2;
 }
 
-template <class E, class Q, class SlotOf>
+// CLAMP: clamp every source index into its array.  Without it, an index may
+// reach up to wlimit + 2 entries before a source array's start and up to
+// 3 wlimit + blockDim.x + 2 past it; the caller guarantees that memory (an HBM
+// ring padded by wfa_ring_pad(wcap) words at both ends), and a value read there is
+// never used (each is taken only under its source's range test).
+template <class E, bool CLAMP = true, class Q, class SlotOf>
 __device__ __forceinline__ int wf_step(int32_t s, int32_t x, int32_t oe, int32_t e, int32_t m,
                                        int32_t n, const int32_t *tab, const int32_t *store,
                                        SlotOf slot_of, int32_t *dst_base_store, int32_t dst_base,
@@ -389,11 +396,19 @@ __device__ __forceinline__ int wf_step(int32_t s, int32_t x, int32_t oe, int32_t
       a_ou[u] = a_ie[u] = a_od[u] = a_de[u] = a_x[u] = NEG;
       if (kb + u * nt <= hi) {
         const int32_t k = kb + u * nt + lane;
-        a_ou[u] = so_[min(max(k + 1 - olo, 0), owm)];
-        a_ie[u] = se_[ew + min(max(k + 1 - elo, 0), ewm)];
-        a_od[u] = so_[min(max(k - 1 - olo, 0), owm)];
-        a_de[u] = se_[2 * ew + min(max(k - 1 - elo, 0), ewm)];
-        a_x[u] = sx_[min(max(k - xlo, 0), xwm)];
+        if (CLAMP) {
+          a_ou[u] = so_[min(max(k + 1 - olo, 0), owm)];
+          a_ie[u] = se_[ew + min(max(k + 1 - elo, 0), ewm)];
+          a_od[u] = so_[min(max(k - 1 - olo, 0), owm)];
+          a_de[u] = se_[2 * ew + min(max(k - 1 - elo, 0), ewm)];
+          a_x[u] = sx_[min(max(k - xlo, 0), xwm)];
+        } else {
+          a_ou[u] = so_[k + 1 - olo];
+          a_ie[u] = se_[ew + (k + 1 - elo)];
+          a_od[u] = so_[k - 1 - olo];
+          a_de[u] = se_[2 * ew + (k - 1 - elo)];
+          a_x[u] = sx_[k - xlo];
+        }
       }
     }
 #pragma unroll
@@ -518,7 +533,7 @@ void k_wfa_score(Seqs S, Outs O, Scoring P, Work Wk, WfaLaunch L, int32_t *hbm) 
       } else {
         if (keep && s >= L.walk_steps) keep = false;
         int32_t cbytes = 0;
-        present = wf_step<E>(s, x, oe, e, m, n, tab_ring, ring, slot_of, ring, sl * slot_w, L.wcap,
+        present = wf_step<E, RING_LDS>(s, x, oe, e, m, n, tab_ring, ring, slot_of, ring, sl * slot_w, L.wcap,
                                    lo, hi, q, overflow, keep ? wcodes + cbase : nullptr,
                                    L.walk_codes - cbase, &cbytes);
         if (cbytes < 0) keep = false;
