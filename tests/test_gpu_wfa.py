@@ -174,3 +174,24 @@ def test_one_wave_walk_score_cap():
         check(c, b, pen)
     finally:
         c.close()
+
+
+def test_reads_beyond_16bit_offsets(ctx):
+    # A batch with reads over 32,000 bases takes the 32-bit paths throughout:
+    # the LDS-ring score pass with the full-store walk for narrow pairs, and
+    # the HBM-ring pass (32-bit ring, sequences read in place) with its code
+    # walk for the rest; checked against the scalar WFA.
+    rng = np.random.default_rng(44)
+    pats, txts = [], []
+    for L, r in [(33000, 0.001), (40000, 0.005), (36000, 0.003), (300, 0.02), (1200, 0.05), (50, 0.0)]:
+        T = rng.integers(0, 4, L).astype(np.uint8)
+        bb = synth.from_lists([T], [T])
+        P, _ = synth.mutate(rng, bb.txt, bb.txt_off, [r])
+        pats.append(P)
+        txts.append(T)
+    b = synth.from_lists(pats, txts)
+    s, st, cg, off = run(ctx, b, "wfa", AFF)
+    for i in range(b.n):
+        ws, wsc, wr, _ = oracle.wfa_pair(b.pattern(i), b.text(i), AFF)
+        assert (st[i], s[i]) == (ws, wsc), i
+        assert cg[off[i]:off[i + 1]].tolist() == wr, i
