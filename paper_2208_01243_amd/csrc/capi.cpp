@@ -243,9 +243,11 @@ Tune tune_for(aim_context *c, int32_t alg, int32_t L) {
 // pass with the ring in HBM for pairs too wide for either (fused walk too);
 // then the fallback pass (full store + walk) by store-size class for pairs
 // whose origin codes did not fit.
+// `order` lists the pairs to align (nullptr: all n), `order_count` its length
+// on the device (nullptr: n).
 aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const aim::Scoring &P,
                    int64_t n, int32_t L, bool plain, int32_t *cnt, const int32_t *order,
-                   const Tune &tu, hipStream_t s) {
+                   const int32_t *order_count, const Tune &tu, hipStream_t s) {
   aim_status st;
   const aim::WfaPlan pl = aim::wfa_plan(L, P, c->opt.scratch_limit, c->cus, plain, tu.wfa_ring_kb,
                                         tu.wfa_trace_kb, tu.wfa_long_threads);
@@ -284,13 +286,13 @@ aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const
       if ((st = ensure(c, c->wbits, (size_t)nslots16 * A.bits_steps * C16 * 32))) return st;
       A.bits = as<uint8_t>(c->wbits);
     }
-    aim::Work W{order, nullptr, n, cnt + C_W1, nullptr, nullptr, 0};
+    aim::Work W{order, order_count, n, cnt + C_W1, nullptr, nullptr, 0};
     Phase ph(c, s, "wfa_score");
     HIP_TRY(aim::launch_wfa_score16(S, O, P, W, A, C16, nslots16, s));
   } else if (!plain && pl.wcap_lds > 0) {
     aim::WfaLaunch A = WL;
     A.wcap = pl.wcap_lds;
-    aim::Work W{order, nullptr, n, cnt + C_W1, nullptr, nullptr, 0};
+    aim::Work W{order, order_count, n, cnt + C_W1, nullptr, nullptr, 0};
     Phase ph(c, s, "wfa_score");
     HIP_TRY(aim::launch_wfa_score(S, O, P, W, A, nullptr, true, slots, 64, false, s));
   }
@@ -318,7 +320,7 @@ aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const
       if ((st = ensure(c, c->wwalk, (size_t)B.walk_slot * grid))) return st;
       B.walk = as<uint8_t>(c->wwalk);
     }
-    aim::Work W{all ? order : lists, all ? nullptr : cnt + C_RL, n, cnt + C_W1G, nullptr, nullptr, 0};
+    aim::Work W{all ? order : lists, all ? order_count : cnt + C_RL, n, cnt + C_W1G, nullptr, nullptr, 0};
     Phase ph(c, s, "wfa_score_hbm");
     HIP_TRY(aim::launch_wfa_score(S, O, P, W, B, as<int32_t>(c->wring) + pad, false, grid,
                                   plain ? 64 : pl.ring_threads, !plain && L <= aim::WFA16_MAX_LEN, s));
@@ -578,7 +580,7 @@ aim_status aim_align_batch(aim_context *c, const aim_batch *B, int32_t alg, aim_
   };
 
   if (alg == AIM_WFA_AFFINE) {
-    if ((st = run_wfa(c, S, O, P, n, L, plain, cnt, order, tu, s))) return st;
+    if ((st = run_wfa(c, S, O, P, n, L, plain, cnt, order, nullptr, tu, s))) return st;
   } else if (plain) {
     aim::Work W1{nullptr, nullptr, n, cnt + C_T1, nullptr, nullptr, 0};
     if ((st = run_full(W1, n, s))) return st;
@@ -655,9 +657,18 @@ aim_status aim_align_batch(aim_context *c, const aim_batch *B, int32_t alg, aim_
       HIP_TRY(aim::launch_band16_tb(affine, S, O, WT, as<uint32_t>(tbA), swA,
                                     (int32_t)std::min<int64_t>(chunksA, (int64_t)c->cus * 6), s2));
     }
-    // tier 3: full matrix
-    aim::Work W3{full_list, full_count, n, cnt + C_T3, nullptr, nullptr, 0};
-    if ((st = run_full(W3, n, s))) return st;
+    // tier 3, the pairs no band certified: the wavefront algorithm, which
+    // reaches the same optimum and (with the same tie order) the same CIGAR
+    // in time growing with the score rather than with m x n; the full matrix
+    // when the penalties are beyond the wavefront ring's reach
+    if (P.x <= WFA_MAX_STEP && P.o + P.e <= WFA_MAX_STEP) {
+      if ((st = run_wfa(c, S, O, P, n, L, false, cnt, full_list, full_count,
+                        tune_for(c, AIM_WFA_AFFINE, L), s)))
+        return st;
+    } else {
+      aim::Work W3{full_list, full_count, n, cnt + C_T3, nullptr, nullptr, 0};
+      if ((st = run_full(W3, n, s))) return st;
+    }
     if (split) {
       HIP_TRY(hipEventRecord(c->ev_join, s2));
       HIP_TRY(hipStreamWaitEvent(s, c->ev_join, 0));
