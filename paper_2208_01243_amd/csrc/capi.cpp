@@ -657,11 +657,13 @@ aim_status aim_align_batch(aim_context *c, const aim_batch *B, int32_t alg, aim_
       HIP_TRY(aim::launch_band16_tb(affine, S, O, WT, as<uint32_t>(tbA), swA,
                                     (int32_t)std::min<int64_t>(chunksA, (int64_t)c->cus * 6), s2));
     }
-    // tier 3, the pairs no band certified: the wavefront algorithm, which
-    // reaches the same optimum and (with the same tie order) the same CIGAR
-    // in time growing with the score rather than with m x n; the full matrix
-    // when the penalties are beyond the wavefront ring's reach
-    if (P.x <= WFA_MAX_STEP && P.o + P.e <= WFA_MAX_STEP) {
+    // tier 3, the pairs no band certified: for reads over 256 bases the
+    // wavefront algorithm, which reaches the same optimum and (with the same
+    // tie order) the same CIGAR in time growing with the score rather than
+    // with m x n; the full matrix for short reads (one launch instead of the
+    // wavefront passes' six, which small batches notice) and for penalties
+    // beyond the wavefront ring's reach
+    if (L > 256 && P.x <= WFA_MAX_STEP && P.o + P.e <= WFA_MAX_STEP) {
       if ((st = run_wfa(c, S, O, P, n, L, false, cnt, full_list, full_count,
                         tune_for(c, AIM_WFA_AFFINE, L), s)))
         return st;
