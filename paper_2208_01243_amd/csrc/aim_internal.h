@@ -112,6 +112,11 @@ hipError_t launch_pair_flags(int64_t n, int32_t max_len, const int32_t *pl, cons
 hipError_t launch_pack(int64_t n, int32_t enc, const uint8_t *seq, const int64_t *off,
                        const int32_t *len, int32_t max_len, uint64_t *words, int64_t words_cap,
                        int64_t *out_off, int8_t *flags, int64_t *scan_tmp, hipStream_t s);
+// The same packing with sequence s at word s * ceil(max_len / 32) (one
+// launch, no scan); words_cap must cover n such strides.
+hipError_t launch_pack_strided(int64_t n, int32_t enc, const uint8_t *seq, const int64_t *off,
+                               const int32_t *len, int32_t max_len, uint64_t *words,
+                               int64_t words_cap, int64_t *out_off, int8_t *flags, hipStream_t s);
 size_t scan_tmp_elems(int64_t n);
 // exclusive scan of int32 counts into int64 out[n+1]
 hipError_t launch_scan_i32(const int32_t *in, int64_t n, int64_t *out, int64_t *tmp, hipStream_t s);

@@ -524,12 +524,14 @@ aim_status aim_align_batch(aim_context *c, const aim_batch *B, int32_t alg, aim_
     if ((st = ensure(c, c->pflag, n))) return st;
     if ((st = ensure(c, c->tflag, n))) return st;
     // lengths above max_len are flagged invalid below; clamp the packing bound
-    HIP_TRY(aim::launch_pack(n, B->enc, (const uint8_t *)B->pat_seq, B->pat_off, B->pat_len, L,
-                             as<uint64_t>(c->pat2), (int64_t)words, as<int64_t>(c->pat2off),
-                             as<int8_t>(c->pflag), as<int64_t>(c->scan_tmp), s));
-    HIP_TRY(aim::launch_pack(n, B->enc, (const uint8_t *)B->txt_seq, B->txt_off, B->txt_len, L,
-                             as<uint64_t>(c->txt2), (int64_t)words, as<int64_t>(c->txt2off),
-                             as<int8_t>(c->tflag), as<int64_t>(c->scan_tmp), s));
+    // one slot of ceil(max_len / 32) words per sequence (the buffers hold n
+    // of them): one launch per side, no offset scan
+    HIP_TRY(aim::launch_pack_strided(n, B->enc, (const uint8_t *)B->pat_seq, B->pat_off, B->pat_len, L,
+                                     as<uint64_t>(c->pat2), (int64_t)words, as<int64_t>(c->pat2off),
+                                     as<int8_t>(c->pflag), s));
+    HIP_TRY(aim::launch_pack_strided(n, B->enc, (const uint8_t *)B->txt_seq, B->txt_off, B->txt_len, L,
+                                     as<uint64_t>(c->txt2), (int64_t)words, as<int64_t>(c->txt2off),
+                                     as<int8_t>(c->tflag), s));
     S = {as<uint64_t>(c->pat2), as<int64_t>(c->pat2off), B->pat_len,
          as<uint64_t>(c->txt2), as<int64_t>(c->txt2off), B->txt_len};
     pf = as<int8_t>(c->pflag);

@@ -37,21 +37,27 @@ __global__ void k_word_counts(int64_t n, const int32_t *len, int32_t max_len, in
 
 // One wavefront per sequence; lane l packs bytes [32 l, 32 l + 32) of each
 // 64-word group, so a wave reads 2 KB of contiguous input per iteration.
+// stride > 0: sequence s starts at word s * stride, written to woff_set
+// (entries 0..n); else at woff[s].
 __global__ __launch_bounds__(256) void k_pack(int64_t n, int32_t enc, const uint8_t *seq,
                                               const int64_t *off, const int32_t *len,
                                               int32_t max_len, uint64_t *words,
                                               int64_t words_cap, const int64_t *woff,
-                                              int8_t *flags) {
+                                              int8_t *flags, int64_t stride, int64_t *woff_set) {
   const int lane = threadIdx.x & 63;
   const int64_t s = blockIdx.x * (int64_t)(blockDim.x / 64) + (threadIdx.x >> 6);
   if (s >= n) return;
+  if (stride > 0 && lane == 0) {
+    woff_set[s] = s * stride;
+    if (s == n - 1) woff_set[n] = n * stride;
+  }
   if (len[s] > max_len) {
     if (flags && lane == 0) flags[s] = 1;
     return;
   }
   const int32_t L = len[s] > 0 ? len[s] : 0;
   const uint8_t *src = seq + off[s];
-  const int64_t w0 = woff[s];
+  const int64_t w0 = stride > 0 ? s * stride : woff[s];
   const int32_t nw = (L + 31) >> 5;
   bool bad = false;
   for (int32_t w = lane; w < nw; w += 64) {
@@ -329,7 +335,21 @@ hipError_t launch_pack(int64_t n, int32_t enc, const uint8_t *seq, const int64_t
   if (err != hipSuccess) return err;
   const int64_t blocks = (n + 3) / 4;
   hipLaunchKernelGGL(k_pack, dim3((unsigned)blocks), dim3(256), 0, s, n, enc, seq, off, len, max_len,
-                     words, words_cap, out_off, flags);
+                     words, words_cap, out_off, flags, (int64_t)0, (int64_t *)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_strided(int64_t n, int32_t enc, const uint8_t *seq, const int64_t *off,
+                               const int32_t *len, int32_t max_len, uint64_t *words,
+                               int64_t words_cap, int64_t *out_off, int8_t *flags, hipStream_t s) {
+  if (n == 0) {
+    hipLaunchKernelGGL(k_zero_offsets, dim3(1), dim3(64), 0, s, (int64_t)0, out_off);
+    return hipGetLastError();
+  }
+  const int64_t stride = ((int64_t)max_len + 31) / 32 > 0 ? ((int64_t)max_len + 31) / 32 : 1;
+  const int64_t blocks = (n + 3) / 4;
+  hipLaunchKernelGGL(k_pack, dim3((unsigned)blocks), dim3(256), 0, s, n, enc, seq, off, len, max_len,
+                     words, words_cap, (const int64_t *)nullptr, flags, stride, out_off);
   return hipGetLastError();
 }
 
