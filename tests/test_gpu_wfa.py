@@ -49,7 +49,8 @@ def _tiny_all(alphabet, maxlen):
     return synth.from_lists(list(pats), list(txts))
 
 
-@pytest.mark.parametrize("pen", [AFF, (0, 3, 4, 1), (0, 2, 1, 1), (0, 9, 1, 1), (0, 1, 0, 1), (0, 5, 0, 2)])
+@pytest.mark.parametrize("pen", [AFF, (0, 3, 4, 1), (0, 2, 1, 1), (0, 9, 1, 1), (0, 1, 0, 1), (0, 5, 0, 2),
+                                 (0, 40, 10, 30)])  # the last: ring of 41 scores, no one-wavefront pass
 def test_exhaustive_tiny(ctx, pen):
     check(ctx, _tiny_all(range(4), 3), pen)
 
@@ -195,3 +196,10 @@ def test_reads_beyond_16bit_offsets(ctx):
         ws, wsc, wr, _ = oracle.wfa_pair(b.pattern(i), b.text(i), AFF)
         assert (st[i], s[i]) == (ws, wsc), i
         assert cg[off[i]:off[i + 1]].tolist() == wr, i
+
+
+@pytest.mark.parametrize("smax", [-1, 600])
+def test_large_ring_penalties(ctx, smax):
+    # max(x, o + e) = 40: a ring of 41 scores, beyond the one-wavefront pass,
+    # so the LDS-ring and HBM-ring score passes and the full-store walk run
+    check(ctx, _mixed(45, 300, 0, 400, [0.0, 0.02, 0.1, 1.0]), (0, 40, 10, 30), smax)
