@@ -122,7 +122,7 @@ struct aim_context {
   Buf order, hist;
   Buf flags, pflag, tflag, pat2, txt2, pat2off, txt2off, nruns, slot, tb32, tb64, full, list2,
       list3, counters, scan_tmp, spill, total, wring, warena1, warena2, warena3, wneed, wlists, pool, pooloff,
-      wbits, wwalk;
+      wbits, wwalk, warch, wtok;
 };
 
 namespace {
@@ -174,7 +174,8 @@ struct DeviceGuard {
 enum Counter {
   C_T1 = 0, C_T2, C_T3, C_L2, C_L3, C_SPILL, C_SPILL_W,
   C_W1, C_W1G, C_RL, C_FAIL, C_N0, C_N1, C_N2, C_N3, C_P0, C_P1, C_P2, C_P3, C_TB, C_DTB,
-  C_M0, C_M1, C_M2, C_M3,
+  C_M0, C_M1, C_M2, C_M3, C_PAD25,
+  C_ARCH = 26, C_ARCH_HI, C_WC, C_WK,  // C_ARCH: 64-bit archive top, 8-byte aligned
   C_N = 32
 };
 
@@ -252,7 +253,7 @@ aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const
   const aim::WfaPlan pl = aim::wfa_plan(L, P, c->opt.scratch_limit, c->cus, plain, tu.wfa_ring_kb,
                                         tu.wfa_trace_kb, tu.wfa_long_threads);
   if ((st = ensure(c, c->wneed, (size_t)n * 8))) return st;
-  if ((st = ensure(c, c->wlists, (size_t)n * 4 * 6))) return st;
+  if ((st = ensure(c, c->wlists, (size_t)n * 4 * 7))) return st;
   int32_t *lists = as<int32_t>(c->wlists);
   aim::WfaLaunch WL{};
   WL.R = pl.R;
@@ -285,10 +286,36 @@ aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const
           1, std::min<int64_t>(A.bits_steps, c->opt.scratch_limit / 16 / ((int64_t)nslots16 * C16 * 32)));
       if ((st = ensure(c, c->wbits, (size_t)nslots16 * A.bits_steps * C16 * 32))) return st;
       A.bits = as<uint8_t>(c->wbits);
+      // archive of accepted pairs' codes for the one-pair-per-lane walk:
+      // an eighth of the budget, no more than every pair at the cap needs
+      const int64_t arch = std::min<int64_t>(c->opt.scratch_limit / 8, n * (int64_t)A.bits_steps * C16 * 32);
+      if (arch >= (int64_t)C16 * 64 && P.x > 0 && P.e > 0) {
+        if ((st = ensure(c, c->warch, (size_t)arch))) return st;
+        A.arch = as<uint8_t>(c->warch);
+        A.arch_cap = arch;
+        A.arch_top = reinterpret_cast<unsigned long long *>(cnt + C_ARCH);
+        A.walk_list = lists + (int64_t)n * 6;
+        A.walk_count = cnt + C_WC;
+      }
     }
-    aim::Work W{order, order_count, n, cnt + C_W1, nullptr, nullptr, 0};
-    Phase ph(c, s, "wfa_score");
-    HIP_TRY(aim::launch_wfa_score16(S, O, P, W, A, C16, nslots16, s));
+    {
+      aim::Work W{order, order_count, n, cnt + C_W1, nullptr, nullptr, 0};
+      Phase ph(c, s, "wfa_score");
+      HIP_TRY(aim::launch_wfa_score16(S, O, P, W, A, C16, nslots16, s));
+    }
+    if (A.arch) {
+      // tokens per lane: each move lowers the score by at least min(x, e),
+      // and an M visit precedes every move and the end
+      const int32_t tok_cap = (int32_t)std::min<int64_t>(
+          2 * (2 * (int64_t)L + 1) + 8, 2 * ((int64_t)A.bits_steps / std::min(P.x, P.e) + 2) + 8);
+      const int64_t per_wg = (int64_t)64 * tok_cap * 4;
+      const int32_t grid = (int32_t)std::max<int64_t>(
+          1, std::min<int64_t>({(int64_t)c->cus * 8, (n + 63) / 64, c->opt.scratch_limit / 16 / per_wg}));
+      if ((st = ensure(c, c->wtok, (size_t)(grid * per_wg)))) return st;
+      aim::Work W{nullptr, nullptr, n, cnt + C_WK, nullptr, nullptr, 0};
+      Phase ph(c, s, "wfa_walk");
+      HIP_TRY(aim::launch_wfa_walk16(S, O, P, W, A, C16, as<uint32_t>(c->wtok), tok_cap, grid, s));
+    }
   } else if (!plain && pl.wcap_lds > 0) {
     aim::WfaLaunch A = WL;
     A.wcap = pl.wcap_lds;
@@ -426,7 +453,7 @@ void aim_destroy(aim_context *c) {
   Buf *all[] = {&c->order, &c->hist, &c->flags, &c->pflag, &c->tflag, &c->pat2, &c->txt2, &c->pat2off, &c->txt2off,
                 &c->nruns, &c->slot, &c->tb32, &c->tb64, &c->full, &c->list2, &c->list3,
                 &c->counters, &c->scan_tmp, &c->spill, &c->total, &c->wring, &c->warena1,
-                &c->warena2, &c->warena3, &c->wneed, &c->wlists, &c->pool, &c->pooloff, &c->wbits, &c->wwalk};
+                &c->warena2, &c->warena3, &c->wneed, &c->wlists, &c->pool, &c->pooloff, &c->wbits, &c->wwalk, &c->warch, &c->wtok};
   for (Buf *b : all)
     if (b->p) (void)hipFree(b->p);
   if (c->ev_join) (void)hipEventDestroy(c->ev_join);
