@@ -806,16 +806,21 @@ __global__ __launch_bounds__(64) void k_wfa_score16(Seqs S, Outs O, Scoring P, W
       const bool keep = s < bits_steps;  // origin codes of this score kept
       if (present) {
         const int32_t bM = sl * W, bID = sE * W;
-        const int32_t c_lo = (lo - kbase) >> 6, c_hi = (hi - kbase) >> 6;
-        // Every lane of a chunk runs the same code: a diagonal outside
-        // [lo, hi] finds no source in range (or only candidates the table
-        // bounds drop), so its offset comes out absent and it writes the
-        // absent mark into a part of the slot no reader takes.
-        for (int32_t c = c_lo; c <= c_hi; ++c) {
-          const int32_t idx = 64 * c + lane, k = kbase + idx;
+        // Chunks of 64 diagonals slide with the wavefront: the first starts
+        // at lo (rounded down to even, so that lanes 2q, 2q+1 share a code
+        // byte), which makes a wavefront of w diagonals cost ceil(w / 64)
+        // chunks wherever it lies in the window.  Every lane of a chunk runs
+        // the same code: a diagonal outside [lo, hi] finds no source in range
+        // (or only candidates the table bounds drop), so its offset comes out
+        // absent and it writes the absent mark into a part of the slot no
+        // reader takes; lanes past the window's end write nothing.
+        const int32_t start = (lo - kbase) & ~1, nch = ((hi - kbase - start) >> 6) + 1;
+        for (int32_t c = 0; c < nch; ++c) {
+          const int32_t idx = start + 64 * c + lane, k = kbase + idx;
+          const bool inw = idx < W;
           // five source reads issued together, indices clamped into the window
-          const int32_t up = min(idx + 1, W - 1), dn = max(idx - 1, 0);
-          const int32_t a_ou = rM[bo + up], a_od = rM[bo + dn], a_x = rM[bx + idx];
+          const int32_t up = min(idx + 1, W - 1), dn = min(max(idx - 1, 0), W - 1), ix = min(idx, W - 1);
+          const int32_t a_ou = rM[bo + up], a_od = rM[bo + dn], a_x = rM[bx + ix];
           const int32_t a_iu = rI[beI + up], a_dd = rD[beI + dn];
           // absent entries are stored as exactly INT16_MIN, so one added
           // base keeps them negative
@@ -834,7 +839,7 @@ __global__ __launch_bounds__(64) void k_wfa_score16(Seqs S, Outs O, Scoring P, W
                 vx, vi, vd, vm, vi >= 0 && (uint32_t)(k + 1 - olo) < (uint32_t)ow && a_ou == vi,
                 vd >= 0 && (uint32_t)(k - 1 - olo) < (uint32_t)ow && a_od >= 0 && a_od + 1 == vd);
             const uint8_t b = code_pair(code);
-            if (!(lane & 1)) bslot[((int64_t)s * C + c) * 32 + (lane >> 1)] = b;
+            if (!(lane & 1) && inw) bslot[(int64_t)s * C * 32 + (idx >> 1)] = b;
           }
           // extend: the first 16 bases by every lane without a branch (a lane
           // with no offset compares at base 0 under a zero limit), the rest
@@ -848,9 +853,11 @@ __global__ __launch_bounds__(64) void k_wfa_score16(Seqs S, Outs O, Scoring P, W
           int32_t f = j0 + run;
           if (run == 16) f = extend_lds(P32, m, T32, n, k, f);
           if (live) vm = f;
-          rM[bM + idx] = (int16_t)(vm < 0 ? -32768 : vm);
-          rI[bID + idx] = (int16_t)(vi < 0 ? -32768 : vi);
-          rD[bID + idx] = (int16_t)(vd < 0 ? -32768 : vd);
+          if (inw) {
+            rM[bM + idx] = (int16_t)(vm < 0 ? -32768 : vm);
+            rI[bID + idx] = (int16_t)(vi < 0 ? -32768 : vi);
+            rD[bID + idx] = (int16_t)(vd < 0 ? -32768 : vd);
+          }
           hit = hit || (k == kend && vm >= n);
         }
       }

@@ -177,6 +177,27 @@ def test_one_wave_walk_score_cap():
         c.close()
 
 
+def test_walk_archive_overflow():
+    # Threshold 60 at 4/6/2 gives a window of one chunk (C = 1) and codes for
+    # 61 scores per one-wavefront slot; a scratch limit of 16 x 32 bytes x 61
+    # scores per slot leaves the archive of accepted pairs' codes (an eighth
+    # of the limit) room for only part of this batch, so the other pairs are
+    # walked by the score pass itself.  Every pair checked against the oracle.
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    b = synth.mixed_length(71, 48000, 120, 160, 0.01, 0.08)
+    slots = min(b.n, cus * 20)
+    limit = 16 * slots * 32 * 61
+    want = oracle.align_batch(b, "wfa", AFF, 60)
+    acc = want[0][want[0] >= 0].astype(np.int64)
+    need = int(((acc + 1) * 32).sum())
+    assert need > (limit // 8) * 3 // 2 and len(acc) > 0.75 * b.n
+    c = aim.Context(0, scratch_limit=limit)
+    try:
+        check(c, b, AFF, 60)
+    finally:
+        c.close()
+
+
 def test_reads_beyond_16bit_offsets(ctx):
     # A batch with reads over 32,000 bases takes the 32-bit paths throughout:
     # the LDS-ring score pass with the full-store walk for narrow pairs, and
