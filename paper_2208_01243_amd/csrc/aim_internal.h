@@ -91,6 +91,11 @@ struct Scoring {
   int32_t x, o, e;     // linear NW: o == 0 and e == gap cost
   int32_t max_score;   // < 0: none
   int32_t want_cigar;
+  // The wavefront kernels run on penalties divided by their common divisor
+  // (every alignment cost is a multiple of it, so the optimum and the tie
+  // order are the same and no score step is empty); a score s of theirs is
+  // unit * s in O.score.  1 everywhere else.
+  int32_t unit = 1;
 };
 
 // A list of pair indices to work on, consumed through an atomic counter;
@@ -193,14 +198,6 @@ struct WfaLaunch {
   uint8_t *walk;
   int32_t walk_steps, walk_tok;
   int64_t walk_codes, walk_slot;
-  // one-wavefront pass: an accepted pair's codes (scores 0..s, C x 32 bytes
-  // each) are appended to arch (arch_cap bytes, bump counter arch_top), its
-  // offset kept in need[p] and the pair in walk_list, for the one-pair-per-lane
-  // walk kernel; a pair that does not fit is walked by the pass itself
-  uint8_t *arch;
-  int64_t arch_cap;
-  unsigned long long *arch_top;
-  int32_t *walk_list, *walk_count;
 };
 
 struct WfaPlan {
@@ -233,11 +230,6 @@ size_t wfa_score16_lds(const WfaLaunch &L, int32_t e, int32_t C);
 inline int64_t wfa_ring_pad(int32_t wcap) { return 4 * (int64_t)wcap + 1024; }
 hipError_t launch_wfa_score16(const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk,
                               const WfaLaunch &L, int32_t C, int32_t nslots, hipStream_t s);
-// The walk of the pairs the one-wavefront pass archived (L.walk_list), one
-// pair per lane; tok: tok_cap words of token scratch per lane of the grid.
-hipError_t launch_wfa_walk16(const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk,
-                             const WfaLaunch &L, int32_t C, uint32_t *tok, int32_t tok_cap,
-                             int32_t nslots, hipStream_t s);
 // i16: wavefronts stored as 16-bit offsets (max_len <= WFA16_MAX_LEN); the
 // full-store sizes counted by the score passes then over-cover the store.
 hipError_t launch_wfa_trace(const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk,

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <numeric>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -122,7 +123,7 @@ struct aim_context {
   Buf order, hist;
   Buf flags, pflag, tflag, pat2, txt2, pat2off, txt2off, nruns, slot, tb32, tb64, full, list2,
       list3, counters, scan_tmp, spill, total, wring, warena1, warena2, warena3, wneed, wlists, pool, pooloff,
-      wbits, wwalk, warch, wtok;
+      wbits, wwalk;
 };
 
 namespace {
@@ -174,8 +175,7 @@ struct DeviceGuard {
 enum Counter {
   C_T1 = 0, C_T2, C_T3, C_L2, C_L3, C_SPILL, C_SPILL_W,
   C_W1, C_W1G, C_RL, C_FAIL, C_N0, C_N1, C_N2, C_N3, C_P0, C_P1, C_P2, C_P3, C_TB, C_DTB,
-  C_M0, C_M1, C_M2, C_M3, C_PAD25,
-  C_ARCH = 26, C_ARCH_HI, C_WC, C_WK,  // C_ARCH: 64-bit archive top, 8-byte aligned
+  C_M0, C_M1, C_M2, C_M3,
   C_N = 32
 };
 
@@ -239,6 +239,25 @@ Tune tune_for(aim_context *c, int32_t alg, int32_t L) {
   return it == c->tunes.end() ? Tune{} : it->second;
 }
 
+// The penalties the wavefront kernels run on: x, o, e and the threshold
+// divided by g = gcd(x, o, e).  Every alignment costs a multiple of g, so the
+// optimum, the CIGAR (each comparison of the canonical order scales by g) and
+// the threshold test (g s' > S_max exactly when s' > floor(S_max / g)) are
+// unchanged, while the score loop takes 1/g of the steps (with 4/6/2, every
+// odd score was an empty wavefront) and the ring holds max(x, o + e) / g + 1
+// scores.  Scores go out as g s'.
+aim::Scoring wfa_scoring(const aim::Scoring &P) {
+  const int32_t g = std::gcd(P.x, std::gcd(P.o, P.e));
+  if (g <= 1) return P;
+  aim::Scoring R = P;
+  R.x /= g;
+  R.o /= g;
+  R.e /= g;
+  R.max_score = P.max_score >= 0 ? P.max_score / g : -1;
+  R.unit = g;
+  return R;
+}
+
 // WFA: the one-wavefront score pass (16-bit LDS ring, fused walk) when the
 // batch allows it, else the score pass with the ring in LDS; then the score
 // pass with the ring in HBM for pairs too wide for either (fused walk too);
@@ -246,14 +265,15 @@ Tune tune_for(aim_context *c, int32_t alg, int32_t L) {
 // whose origin codes did not fit.
 // `order` lists the pairs to align (nullptr: all n), `order_count` its length
 // on the device (nullptr: n).
-aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const aim::Scoring &P,
+aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const aim::Scoring &Pin,
                    int64_t n, int32_t L, bool plain, int32_t *cnt, const int32_t *order,
                    const int32_t *order_count, const Tune &tu, hipStream_t s) {
   aim_status st;
+  const aim::Scoring P = wfa_scoring(Pin);
   const aim::WfaPlan pl = aim::wfa_plan(L, P, c->opt.scratch_limit, c->cus, plain, tu.wfa_ring_kb,
                                         tu.wfa_trace_kb, tu.wfa_long_threads);
   if ((st = ensure(c, c->wneed, (size_t)n * 8))) return st;
-  if ((st = ensure(c, c->wlists, (size_t)n * 4 * 7))) return st;
+  if ((st = ensure(c, c->wlists, (size_t)n * 4 * 6))) return st;
   int32_t *lists = as<int32_t>(c->wlists);
   aim::WfaLaunch WL{};
   WL.R = pl.R;
@@ -286,36 +306,10 @@ aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const
           1, std::min<int64_t>(A.bits_steps, c->opt.scratch_limit / 16 / ((int64_t)nslots16 * C16 * 32)));
       if ((st = ensure(c, c->wbits, (size_t)nslots16 * A.bits_steps * C16 * 32))) return st;
       A.bits = as<uint8_t>(c->wbits);
-      // archive of accepted pairs' codes for the one-pair-per-lane walk:
-      // an eighth of the budget, no more than every pair at the cap needs
-      const int64_t arch = std::min<int64_t>(c->opt.scratch_limit / 8, n * (int64_t)A.bits_steps * C16 * 32);
-      if (arch >= (int64_t)C16 * 64 && P.x > 0 && P.e > 0) {
-        if ((st = ensure(c, c->warch, (size_t)arch))) return st;
-        A.arch = as<uint8_t>(c->warch);
-        A.arch_cap = arch;
-        A.arch_top = reinterpret_cast<unsigned long long *>(cnt + C_ARCH);
-        A.walk_list = lists + (int64_t)n * 6;
-        A.walk_count = cnt + C_WC;
-      }
     }
-    {
-      aim::Work W{order, order_count, n, cnt + C_W1, nullptr, nullptr, 0};
-      Phase ph(c, s, "wfa_score");
-      HIP_TRY(aim::launch_wfa_score16(S, O, P, W, A, C16, nslots16, s));
-    }
-    if (A.arch) {
-      // tokens per lane: each move lowers the score by at least min(x, e),
-      // and an M visit precedes every move and the end
-      const int32_t tok_cap = (int32_t)std::min<int64_t>(
-          2 * (2 * (int64_t)L + 1) + 8, 2 * ((int64_t)A.bits_steps / std::min(P.x, P.e) + 2) + 8);
-      const int64_t per_wg = (int64_t)64 * tok_cap * 4;
-      const int32_t grid = (int32_t)std::max<int64_t>(
-          1, std::min<int64_t>({(int64_t)c->cus * 8, (n + 63) / 64, c->opt.scratch_limit / 16 / per_wg}));
-      if ((st = ensure(c, c->wtok, (size_t)(grid * per_wg)))) return st;
-      aim::Work W{nullptr, nullptr, n, cnt + C_WK, nullptr, nullptr, 0};
-      Phase ph(c, s, "wfa_walk");
-      HIP_TRY(aim::launch_wfa_walk16(S, O, P, W, A, C16, as<uint32_t>(c->wtok), tok_cap, grid, s));
-    }
+    aim::Work W{order, order_count, n, cnt + C_W1, nullptr, nullptr, 0};
+    Phase ph(c, s, "wfa_score");
+    HIP_TRY(aim::launch_wfa_score16(S, O, P, W, A, C16, nslots16, s));
   } else if (!plain && pl.wcap_lds > 0) {
     aim::WfaLaunch A = WL;
     A.wcap = pl.wcap_lds;
@@ -453,7 +447,7 @@ void aim_destroy(aim_context *c) {
   Buf *all[] = {&c->order, &c->hist, &c->flags, &c->pflag, &c->tflag, &c->pat2, &c->txt2, &c->pat2off, &c->txt2off,
                 &c->nruns, &c->slot, &c->tb32, &c->tb64, &c->full, &c->list2, &c->list3,
                 &c->counters, &c->scan_tmp, &c->spill, &c->total, &c->wring, &c->warena1,
-                &c->warena2, &c->warena3, &c->wneed, &c->wlists, &c->pool, &c->pooloff, &c->wbits, &c->wwalk, &c->warch, &c->wtok};
+                &c->warena2, &c->warena3, &c->wneed, &c->wlists, &c->pool, &c->pooloff, &c->wbits, &c->wwalk};
   for (Buf *b : all)
     if (b->p) (void)hipFree(b->p);
   if (c->ev_join) (void)hipEventDestroy(c->ev_join);
@@ -719,7 +713,8 @@ aim_status aim_align_batch(aim_context *c, const aim_batch *B, int32_t alg, aim_
   // pairs whose runs exceeded the slot: recompute and write in place
   aim::Work WS{as<int32_t>(c->spill), cnt + C_SPILL, n, cnt + C_SPILL_W, nullptr, nullptr, 1};
   if (alg == AIM_WFA_AFFINE) {
-    aim::WfaPlan pl = aim::wfa_plan(L, P, c->opt.scratch_limit, c->cus, plain, tu.wfa_ring_kb,
+    const aim::Scoring PW = wfa_scoring(P);
+    aim::WfaPlan pl = aim::wfa_plan(L, PW, c->opt.scratch_limit, c->cus, plain, tu.wfa_ring_kb,
                                     tu.wfa_trace_kb, tu.wfa_long_threads);
     aim::WfaLaunch WL{};
     WL.R = pl.R;
@@ -730,7 +725,7 @@ aim_status aim_align_batch(aim_context *c, const aim_batch *B, int32_t alg, aim_
     if ((st = ensure(c, c->warena3, (size_t)pl.pool_words[3] * 4))) return st;
     const int32_t rslots = (int32_t)std::max<int64_t>(1, pl.pool_words[3] / pl.need_cap[3]);
     Phase ph(c, s, "wfa_rerun");
-    HIP_TRY(aim::launch_wfa_trace(S, O, P, WS, WL, as<int32_t>(c->warena3), rslots,
+    HIP_TRY(aim::launch_wfa_trace(S, O, PW, WS, WL, as<int32_t>(c->warena3), rslots,
                                   pl.threads[3], L <= aim::WFA16_MAX_LEN && !plain, s));
   } else {
     if ((st = run_full(WS, n, s))) return st;

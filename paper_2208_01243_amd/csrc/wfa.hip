@@ -302,80 +302,6 @@ __device__ bool walk_codes(const Outs &O, int64_t p, CodeAt code_at, Ext ext, in
   return true;
 }
 
-// The same walk by one lane for its own pair (every lane of a wavefront a
-// different pair); the lane writes its own tokens and runs.
-template <class CodeAt, class Ext>
-__device__ bool walk_codes_lane(const Outs &O, int64_t p, CodeAt code_at, Ext ext, int32_t x, int32_t oe,
-                                int32_t e, int32_t m, int32_t n, int32_t sfin, uint32_t *tok,
-                                int32_t tok_cap) {
-  int32_t cs = sfin, k = n - m, comp = 0, nt = 0, code = -1;
-  bool ok = true;
-  for (;;) {
-    if (nt + 2 > tok_cap || cs < 0) { ok = false; break; }
-    if (comp == 0) {
-      tok[nt++] = TOK_M;
-      if (cs == 0) { ok = k == 0; break; }
-      if (code < 0) code = code_at(cs, k);
-      if (code < 0) { ok = false; break; }
-      const int32_t src = code & 3;
-      if (src == 0) {
-        tok[nt++] = OP_X;
-        cs -= x;
-        code = -1;
-      } else {
-        comp = src;
-      }
-    } else {
-      if (code < 0) code = code_at(cs, k);
-      if (code < 0) { ok = false; break; }
-      const bool open = (code >> (comp + 1)) & 1;
-      tok[nt++] = comp == 1 ? OP_I : OP_D;
-      k += comp == 1 ? 1 : -1;
-      if (open) { cs -= oe; comp = 0; } else { cs -= e; }
-      code = -1;
-    }
-  }
-  if (!ok) return false;
-  int32_t i = 0, j = 0;
-  for (int32_t t = nt - 1; t >= 0; --t) {
-    const uint32_t tk = tok[t];
-    if (tk == TOK_M) {
-      const int32_t len = ext(j - i, j) - j;
-      tok[t] = TOK_M | ((uint32_t)len << 4);
-      i += len;
-      j += len;
-    } else if (tk == OP_X) {
-      ++i; ++j;
-    } else if (tk == OP_I) {
-      ++i;
-    } else {
-      ++j;
-    }
-  }
-  if (i != m || j != n) return false;
-  RunSink sink;
-  sink.begin(O, p);
-  uint32_t cur_op = 0xffu, cur_len = 0;
-  int32_t nr = 0;
-  for (int32_t t = 0; t < nt; ++t) {
-    const uint32_t tk = tok[t];
-    const uint32_t op = (tk & 15u) == TOK_M ? (uint32_t)OP_EQ : (tk & 15u);
-    const uint32_t len = (tk & 15u) == TOK_M ? (tk >> 4) : 1u;
-    if (len == 0) continue;
-    if (op == cur_op) {
-      cur_len += len;
-    } else {
-      if (cur_len) sink.put(nr++, (cur_len << 4) | cur_op, nt - t + 1);
-      cur_op = op;
-      cur_len = len;
-    }
-  }
-  if (cur_len) sink.put(nr++, (cur_len << 4) | cur_op, 1);
-  sink.finish();
-  O.nruns[p] = nr;
-  return true;
-}
-
 // One wavefront step: compute components of score s into `dst` (three
 // arrays of width hi-lo+1 at dst, dst+w, dst+2w).  Source tables/arrays are
 // located through `tab`/`store` with slot(s') giving the table slot.
@@ -670,7 +596,7 @@ void k_wfa_score(Seqs S, Outs O, Scoring P, Work Wk, WfaLaunch L, int32_t *hbm) 
         O.status[p] = result == 2 ? ST_REJECTED : ST_INVALID;
         O.nruns[p] = 0;
       } else {
-        O.score[p] = s;
+        O.score[p] = s * P.unit;
         O.status[p] = ST_ALIGNED;
         if (!walked) O.nruns[p] = 0;
         if (P.want_cigar && !walked) {
@@ -874,27 +800,9 @@ __global__ __launch_bounds__(64) void k_wfa_score16(Seqs S, Outs O, Scoring P, W
       __syncthreads();
       if (__ballot(hit)) result = 1;
     }
-    bool walked = false, archived = false;
-    unsigned long long arch_at = 0;
+    bool walked = false;
     if (result == 1 && s < bits_steps) {
-      __syncthreads();  // the origin codes stored by every lane, visible below
-      if (L.arch && P.want_cigar) {
-        // keep the codes for the walk kernel when the archive has room
-        const int64_t bytes = (int64_t)(s + 1) * C * 32;
-        unsigned long long at = 0;
-        if (lane == 0) at = atomicAdd(L.arch_top, (unsigned long long)bytes);
-        at = (unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)at) |
-             ((unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(at >> 32)) << 32);
-        if ((int64_t)at + bytes <= L.arch_cap) {
-          const uint4 *src = reinterpret_cast<const uint4 *>(bslot);
-          uint4 *dst = reinterpret_cast<uint4 *>(L.arch + at);
-          for (int64_t q = lane; q < bytes / 16; q += 64) dst[q] = src[q];
-          archived = true;
-          arch_at = at;
-        }
-      }
-    }
-    if (result == 1 && s < bits_steps && !archived) {
+      __syncthreads();  // the origin codes stored by every lane, visible to the walk
       const int32_t sfin = s;
       auto code_at = [&](int32_t cs, int32_t k) -> int32_t {  // per lane
         const int32_t idx = k - kbase;
@@ -914,13 +822,10 @@ __global__ __launch_bounds__(64) void k_wfa_score16(Seqs S, Outs O, Scoring P, W
         O.status[p] = result == 2 ? ST_REJECTED : ST_INVALID;
         O.nruns[p] = 0;
       } else {
-        O.score[p] = s;
+        O.score[p] = s * P.unit;
         O.status[p] = ST_ALIGNED;
         if (!walked) O.nruns[p] = 0;
-        if (archived) {
-          L.need[p] = (int64_t)arch_at;
-          L.walk_list[atomicAdd(L.walk_count, 1)] = (int32_t)p;
-        } else if (P.want_cigar && !walked) {
+        if (P.want_cigar && !walked) {
           L.need[p] = need;
           int cl = 0;
           while (cl < 3 && need > L.need_cap[cl]) ++cl;
@@ -935,46 +840,6 @@ __global__ __launch_bounds__(64) void k_wfa_score16(Seqs S, Outs O, Scoring P, W
       }
     }
     }  // valid pair
-  }
-}
-
-// ------------------------------------ walk of the archived pairs, one per lane
-// The pairs the one-wavefront pass archived, walked one per lane: each lane
-// follows its own pair's codes (kept at a fixed place per score and chunk of
-// 64 diagonals, as the pass wrote them) and replays its tokens against the
-// sequences in HBM, so that 64 chains of dependent loads are in flight per
-// wavefront.  A pair whose walk fails (it cannot, for codes of a reached end
-// cell) keeps its score and reports CIGAR_OVERFLOW.
-__global__ __launch_bounds__(64) void k_wfa_walk16(Seqs S, Outs O, Scoring P, Work Wk, WfaLaunch L,
-                                                  int32_t C, uint32_t *tok_all, int32_t tok_cap) {
-  const int lane = threadIdx.x;
-  const int32_t count = __builtin_amdgcn_readfirstlane(*(volatile const int32_t *)L.walk_count);
-  if ((int64_t)blockIdx.x * 64 >= count) return;
-  uint32_t *tok = tok_all + ((int64_t)blockIdx.x * 64 + lane) * tok_cap;
-  const int32_t x = P.x, oe = P.o + P.e, e = P.e, W = 64 * C, kbase = -32 * C;
-  for (;;) {
-    const int32_t t = atomicAdd(Wk.counter, lane == 0 ? 1 : 0);
-    const int32_t g = __builtin_amdgcn_readfirstlane(t);
-    if ((int64_t)g * 64 >= count) break;
-    const int32_t item = g * 64 + lane;
-    if (item < count) {
-      const int64_t p = L.walk_list[item];
-      const int32_t m = S.pat_len[p], n = S.txt_len[p], sfin = O.score[p];
-      const uint8_t *codes = L.arch + L.need[p];
-      auto code_at = [&](int32_t cs, int32_t k) -> int32_t {
-        const int32_t idx = k - kbase;
-        if (cs < 1 || cs > sfin || (uint32_t)idx >= (uint32_t)W) return -1;
-        const uint32_t b = codes[((int64_t)cs * C + (idx >> 6)) * 32 + ((idx & 63) >> 1)];
-        return (int32_t)((idx & 1) ? (b >> 4) : (b & 15u));
-      };
-      const uint64_t *Pw = S.pat + S.pat_off[p], *Tw = S.txt + S.txt_off[p];
-      const int64_t pnw = (m + 31) >> 5, tnw = (n + 31) >> 5;
-      auto ext = [&](int32_t k, int32_t f) { return extend(Pw, pnw, m, Tw, tnw, n, k, f); };
-      if (!walk_codes_lane(O, p, code_at, ext, x, oe, e, m, n, sfin, tok, tok_cap)) {
-        O.status[p] = ST_OVERFLOW;
-        O.nruns[p] = 0;
-      }
-    }
   }
 }
 
@@ -1018,7 +883,7 @@ __global__ __launch_bounds__(WGMAX) void k_wfa_trace(Seqs S, Outs O, Scoring P, 
     if (li >= count) break;
     const int64_t p = Wk.idx ? (int64_t)Wk.idx[li] : li;
     const int32_t m = S.pat_len[p], n = S.txt_len[p];
-    const int32_t sfin = O.score[p];
+    const int32_t sfin = O.score[p] / P.unit;
     const int64_t pnw = (m + 31) >> 5, tnw = (n + 31) >> 5;
     const uint64_t *gP = S.pat + S.pat_off[p], *gT = S.txt + S.txt_off[p];
     const bool staged = pnw <= L.seq_words && tnw <= L.seq_words;
@@ -1216,13 +1081,6 @@ size_t wfa_score16_lds(const WfaLaunch &L, int32_t e, int32_t C) {
 hipError_t launch_wfa_score16(const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk,
                               const WfaLaunch &L, int32_t C, int32_t nslots, hipStream_t s) {
   hipLaunchKernelGGL(k_wfa_score16, dim3(nslots), dim3(64), wfa_score16_lds(L, P.e, C), s, S, O, P, Wk, L, C);
-  return hipGetLastError();
-}
-
-hipError_t launch_wfa_walk16(const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk,
-                             const WfaLaunch &L, int32_t C, uint32_t *tok, int32_t tok_cap,
-                             int32_t nslots, hipStream_t s) {
-  hipLaunchKernelGGL(k_wfa_walk16, dim3(nslots), dim3(64), 0, s, S, O, P, Wk, L, C, tok, tok_cap);
   return hipGetLastError();
 }
 

@@ -50,7 +50,9 @@ def _tiny_all(alphabet, maxlen):
 
 
 @pytest.mark.parametrize("pen", [AFF, (0, 3, 4, 1), (0, 2, 1, 1), (0, 9, 1, 1), (0, 1, 0, 1), (0, 5, 0, 2),
-                                 (0, 40, 10, 30)])  # the last: ring of 41 scores, no one-wavefront pass
+                                 (0, 40, 10, 30), (0, 41, 10, 29)])
+# (0, 40, 10, 30) runs as (4, 1, 3) with scores times 10; (0, 41, 10, 29) has
+# a ring of 42 scores, beyond the one-wavefront pass
 def test_exhaustive_tiny(ctx, pen):
     check(ctx, _tiny_all(range(4), 3), pen)
 
@@ -92,7 +94,7 @@ def _mixed(seed, count, lmin, lmax, rates):
     return synth.from_lists(pats, txts)
 
 
-@pytest.mark.parametrize("smax", [-1, 0, 8, 40, 200])
+@pytest.mark.parametrize("smax", [-1, 0, 1, 8, 41, 200, 201])  # odd ones: not multiples of gcd(4, 6, 2)
 def test_thresholds_and_noise(ctx, smax):
     check(ctx, _mixed(41, 600, 0, 300, [0.0, 0.02, 0.08, 0.3, 1.0]), AFF, smax)
 
@@ -177,27 +179,6 @@ def test_one_wave_walk_score_cap():
         c.close()
 
 
-def test_walk_archive_overflow():
-    # Threshold 60 at 4/6/2 gives a window of one chunk (C = 1) and codes for
-    # 61 scores per one-wavefront slot; a scratch limit of 16 x 32 bytes x 61
-    # scores per slot leaves the archive of accepted pairs' codes (an eighth
-    # of the limit) room for only part of this batch, so the other pairs are
-    # walked by the score pass itself.  Every pair checked against the oracle.
-    cus = torch.cuda.get_device_properties(0).multi_processor_count
-    b = synth.mixed_length(71, 48000, 120, 160, 0.01, 0.08)
-    slots = min(b.n, cus * 20)
-    limit = 16 * slots * 32 * 61
-    want = oracle.align_batch(b, "wfa", AFF, 60)
-    acc = want[0][want[0] >= 0].astype(np.int64)
-    need = int(((acc + 1) * 32).sum())
-    assert need > (limit // 8) * 3 // 2 and len(acc) > 0.75 * b.n
-    c = aim.Context(0, scratch_limit=limit)
-    try:
-        check(c, b, AFF, 60)
-    finally:
-        c.close()
-
-
 def test_reads_beyond_16bit_offsets(ctx):
     # A batch with reads over 32,000 bases takes the 32-bit paths throughout:
     # the LDS-ring score pass with the full-store walk for narrow pairs, and
@@ -220,7 +201,10 @@ def test_reads_beyond_16bit_offsets(ctx):
 
 
 @pytest.mark.parametrize("smax", [-1, 600])
-def test_large_ring_penalties(ctx, smax):
-    # max(x, o + e) = 40: a ring of 41 scores, beyond the one-wavefront pass,
-    # so the LDS-ring and HBM-ring score passes and the full-store walk run
-    check(ctx, _mixed(45, 300, 0, 400, [0.0, 0.02, 0.1, 1.0]), (0, 40, 10, 30), smax)
+@pytest.mark.parametrize("pen", [(0, 41, 10, 29), (0, 40, 10, 30)])
+def test_large_ring_penalties(ctx, smax, pen):
+    # (0, 41, 10, 29): max(x, o + e) = 41, a ring of 42 scores, beyond the
+    # one-wavefront pass, so the LDS-ring and HBM-ring score passes and the
+    # full-store walk run.  (0, 40, 10, 30) has the common divisor 10 and runs
+    # as (4, 1, 3) in the one-wavefront pass.
+    check(ctx, _mixed(45, 300, 0, 400, [0.0, 0.02, 0.1, 1.0]), pen, smax)

@@ -162,6 +162,28 @@ def test_wfa_equals_gotoh_long():
         assert g == w[:3]
 
 
+def test_common_divisor_of_penalties():
+    # Every alignment cost is a combination of x, o and e with non-negative
+    # integer counts, so with g = gcd(x, o, e) the Gotoh optimum under
+    # (x/g, o/g, e/g) is the optimum under (x, o, e) divided by g, reached by
+    # the same canonical CIGAR (each comparison of the tie order scales by
+    # g), and a threshold S_max becomes floor(S_max / g).  The GPU wavefront
+    # kernels rely on this; here it is checked on the full-matrix oracle.
+    for P, T in _random_pairs(21, 200, 120, 0.08):
+        for pen, g in [((0, 4, 6, 2), 2), ((0, 40, 10, 30), 10), ((0, 6, 0, 3), 3)]:
+            red = (0, pen[1] // g, pen[2] // g, pen[3] // g)
+            alg = "nw" if pen[2] == 0 else "swg"
+            st, sc, r = align_pair(P, T, alg, pen)
+            st2, sc2, r2 = align_pair(P, T, alg, red)
+            assert (st2, sc2 * g, r2) == (st, sc, r)
+            for smax in [sc - 1, sc, sc + 1, sc + g]:
+                if smax < 0:
+                    continue
+                got = align_pair(P, T, alg, red, max_score=smax // g)
+                want = align_pair(P, T, alg, pen, max_score=smax)
+                assert (got[0], got[1] * g if got[1] >= 0 else -1, got[2]) == want
+
+
 # ---------------------------------------------------------------- invariants
 
 def test_rescore_and_bounds_random():
