@@ -294,7 +294,7 @@ aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const
                    aim::wfa_score16_lds(WL, P.e, C16) <= 48 * 1024;
   WL.store16 = w16;  // the full store of the fallback pass holds 16-bit offsets
   if (w16) {
-    const int32_t nslots16 = (int32_t)std::min<int64_t>(n, (int64_t)c->cus * 20);
+    const int32_t nslots16 = (int32_t)std::min<int64_t>(n, (int64_t)c->cus * 28);
     aim::WfaLaunch A = WL;
     if (P.want_cigar) {
       // origin codes for the fused walk: every score up to the threshold, at
