@@ -303,8 +303,9 @@ aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const
       A.bits_steps = P.max_score >= 0 ? std::min(P.max_score + 1, aim::WFA16_WALK_STEPS)
                                       : aim::WFA16_WALK_STEPS;
       A.bits_steps = (int32_t)std::max<int64_t>(
-          1, std::min<int64_t>(A.bits_steps, c->opt.scratch_limit / 16 / ((int64_t)nslots16 * C16 * 32)));
-      if ((st = ensure(c, c->wbits, (size_t)nslots16 * A.bits_steps * C16 * 32))) return st;
+          1, std::min<int64_t>(A.bits_steps, c->opt.scratch_limit / 16 / ((int64_t)nslots16 * (C16 * 32 + 32))));
+      // rows of C16 x 32 bytes plus 32 bytes of padding
+      if ((st = ensure(c, c->wbits, (size_t)nslots16 * A.bits_steps * (C16 * 32 + 32)))) return st;
       A.bits = as<uint8_t>(c->wbits);
     }
     aim::Work W{order, order_count, n, cnt + C_W1, nullptr, nullptr, 0};

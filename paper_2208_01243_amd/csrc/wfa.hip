@@ -633,14 +633,17 @@ __global__ __launch_bounds__(64) void k_wfa_score16(Seqs S, Outs O, Scoring P, W
   const int lane = threadIdx.x;
   const int32_t x = P.x, oe = P.o + P.e, e = P.e, R = L.R, RE = P.e + 1;
   const int32_t W = 64 * C, kbase = -32 * C;
+  // ring rows and code rows carry 64 entries / 32 bytes of padding past the
+  // window, where the lanes of a chunk that runs past it write unmasked
+  const int32_t WS = W + 64, BR = C * 32 + 32;
   uint64_t *sP = (uint64_t *)smem;
   uint64_t *sT = sP + L.seq_words;
   // per ring slot, the diagonal range of each component (empty when the
   // component is absent): I lo, hi, D lo, hi, M lo, hi, -, -
   int32_t *tab = (int32_t *)(sT + L.seq_words);
-  int16_t *rM = (int16_t *)(tab + R * TAB16);     // R x W
-  int16_t *rI = rM + R * W;                        // (e+1) x W
-  int16_t *rD = rI + RE * W;                       // (e+1) x W
+  int16_t *rM = (int16_t *)(tab + R * TAB16);     // R x WS
+  int16_t *rI = rM + R * WS;                       // (e+1) x WS
+  int16_t *rD = rI + RE * WS;                      // (e+1) x WS
   const int32_t count = Wk.count ? __builtin_amdgcn_readfirstlane(*(volatile const int32_t *)Wk.count)
                                  : (int32_t)Wk.n;
   if ((int32_t)blockIdx.x >= count) return;
@@ -671,7 +674,7 @@ __global__ __launch_bounds__(64) void k_wfa_score16(Seqs S, Outs O, Scoring P, W
     __syncthreads();  // staged words visible to every lane
     const int32_t kend = n - m;
     const int32_t bits_steps = P.want_cigar ? L.bits_steps : 0;
-    uint8_t *bslot = L.bits + (int64_t)blockIdx.x * bits_steps * C * 32;
+    uint8_t *bslot = L.bits + (int64_t)blockIdx.x * bits_steps * BR;
     const int64_t ad = m > n ? m - n : n - m;
     const int64_t up1 = (int64_t)x * min(m, n) + (ad ? (int64_t)P.o + ad * e : 0);
     const int64_t up2 = (m ? (int64_t)P.o + (int64_t)m * e : 0) + (n ? (int64_t)P.o + (int64_t)n * e : 0);
@@ -719,7 +722,7 @@ __global__ __launch_bounds__(64) void k_wfa_score16(Seqs S, Outs O, Scoring P, W
       const int32_t ihi = __builtin_amdgcn_readfirstlane(tab[qe * TAB16 + 1]);
       const int32_t dlo = __builtin_amdgcn_readfirstlane(tab[qe * TAB16 + 2]);
       const int32_t dhi = __builtin_amdgcn_readfirstlane(tab[qe * TAB16 + 3]);
-      const int32_t bx = qx * W, bo = qo * W, beI = qeE * W;
+      const int32_t bx = qx * WS, bo = qo * WS, beI = qeE * WS;
       const int32_t lo = max(min(min(xlo, olo), min(ilo, dlo)) - 1, -m);
       const int32_t hi = min(max(max(xhi, ohi), max(ihi, dhi)) + 1, n);
       const bool present = lo <= hi;
@@ -731,7 +734,7 @@ __global__ __launch_bounds__(64) void k_wfa_score16(Seqs S, Outs O, Scoring P, W
       bool hit = false;  // this lane reached the end cell
       const bool keep = s < bits_steps;  // origin codes of this score kept
       if (present) {
-        const int32_t bM = sl * W, bID = sE * W;
+        const int32_t bM = sl * WS, bID = sE * WS;
         // Chunks of 64 diagonals slide with the wavefront: the first starts
         // at lo (rounded down to even, so that lanes 2q, 2q+1 share a code
         // byte), which makes a wavefront of w diagonals cost ceil(w / 64)
@@ -739,11 +742,10 @@ __global__ __launch_bounds__(64) void k_wfa_score16(Seqs S, Outs O, Scoring P, W
         // the same code: a diagonal outside [lo, hi] finds no source in range
         // (or only candidates the table bounds drop), so its offset comes out
         // absent and it writes the absent mark into a part of the slot no
-        // reader takes; lanes past the window's end write nothing.
+        // reader takes; lanes past the window's end write into the padding.
         const int32_t start = (lo - kbase) & ~1, nch = ((hi - kbase - start) >> 6) + 1;
         for (int32_t c = 0; c < nch; ++c) {
           const int32_t idx = start + 64 * c + lane, k = kbase + idx;
-          const bool inw = idx < W;
           // five source reads issued together, indices clamped into the window
           const int32_t up = min(idx + 1, W - 1), dn = min(max(idx - 1, 0), W - 1), ix = min(idx, W - 1);
           const int32_t a_ou = rM[bo + up], a_od = rM[bo + dn], a_x = rM[bx + ix];
@@ -765,7 +767,8 @@ __global__ __launch_bounds__(64) void k_wfa_score16(Seqs S, Outs O, Scoring P, W
                 vx, vi, vd, vm, vi >= 0 && (uint32_t)(k + 1 - olo) < (uint32_t)ow && a_ou == vi,
                 vd >= 0 && (uint32_t)(k - 1 - olo) < (uint32_t)ow && a_od >= 0 && a_od + 1 == vd);
             const uint8_t b = code_pair(code);
-            if (!(lane & 1) && inw) bslot[(int64_t)s * C * 32 + (idx >> 1)] = b;
+            // odd lanes (and lanes past the window) write into the row's padding
+            bslot[(int64_t)s * BR + ((lane & 1) ? BR - 1 : (idx >> 1))] = b;
           }
           // extend: the first 16 bases by every lane without a branch (a lane
           // with no offset compares at base 0 under a zero limit), the rest
@@ -779,11 +782,9 @@ __global__ __launch_bounds__(64) void k_wfa_score16(Seqs S, Outs O, Scoring P, W
           int32_t f = j0 + run;
           if (run == 16) f = extend_lds(P32, m, T32, n, k, f);
           if (live) vm = f;
-          if (inw) {
-            rM[bM + idx] = (int16_t)(vm < 0 ? -32768 : vm);
-            rI[bID + idx] = (int16_t)(vi < 0 ? -32768 : vi);
-            rD[bID + idx] = (int16_t)(vd < 0 ? -32768 : vd);
-          }
+          rM[bM + idx] = (int16_t)(vm < 0 ? -32768 : vm);
+          rI[bID + idx] = (int16_t)(vi < 0 ? -32768 : vi);
+          rD[bID + idx] = (int16_t)(vd < 0 ? -32768 : vd);
           hit = hit || (k == kend && vm >= n);
         }
       }
@@ -807,12 +808,12 @@ __global__ __launch_bounds__(64) void k_wfa_score16(Seqs S, Outs O, Scoring P, W
       auto code_at = [&](int32_t cs, int32_t k) -> int32_t {  // per lane
         const int32_t idx = k - kbase;
         if (cs < 1 || cs > sfin || (uint32_t)idx >= (uint32_t)W) return -1;
-        const uint32_t b = bslot[((int64_t)cs * C + (idx >> 6)) * 32 + ((idx & 63) >> 1)];
+        const uint32_t b = bslot[(int64_t)cs * BR + (idx >> 1)];
         return (int32_t)((idx & 1) ? (b >> 4) : (b & 15u));
       };
       auto ext = [&](int32_t k, int32_t f) { return extend_lds(P32, m, T32, n, k, f); };
       walked = walk_codes<false>(O, p, code_at, ext, x, oe, e, m, n, s, reinterpret_cast<uint32_t *>(rM),
-                          (R + 2 * RE) * W / 2);
+                          (R + 2 * RE) * WS / 2);
     }
     if (result == 3) {
       wave_append1(true, (int32_t)p, L.ring_list, L.ring_count);
@@ -1075,7 +1076,7 @@ hipError_t launch_wfa_score(const Seqs &S, const Outs &O, const Scoring &P, cons
 }
 
 size_t wfa_score16_lds(const WfaLaunch &L, int32_t e, int32_t C) {
-  return 2 * (size_t)L.seq_words * 8 + (size_t)L.R * TAB16 * 4 + (size_t)(L.R + 2 * (e + 1)) * 64 * C * 2;
+  return 2 * (size_t)L.seq_words * 8 + (size_t)L.R * TAB16 * 4 + (size_t)(L.R + 2 * (e + 1)) * (64 * C + 64) * 2;
 }
 
 hipError_t launch_wfa_score16(const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk,
