@@ -246,7 +246,8 @@ typedef struct {
   int32_t n_streams;       /* concurrent device batches, 1..16 (0: 4) */
   int32_t flags;           /* reserved, 0 */
   int64_t budget_bytes;    /* device bytes for admitted requests (0: 64 GiB) */
-  int64_t max_batch_pairs; /* pairs merged into one device batch (0: 1M) */
+  int64_t max_batch_pairs; /* pairs merged into one device batch (0: 65,536); a single
+                              request larger than this still runs as one batch */
 } aim_server_options;
 
 /* One request: host arrays (copied at submit; the caller may reuse them

@@ -297,7 +297,9 @@ aim_status aim_server_create(int32_t device, const aim_server_options *opt, aim_
     o = *opt;
     if (o.n_streams == 0) o.n_streams = 4;
     if (o.budget_bytes == 0) o.budget_bytes = (int64_t)64 << 30;
-    if (o.max_batch_pairs == 0) o.max_batch_pairs = (int64_t)1 << 20;
+    // 65,536: batches stay large enough to fill the GPU at the serving load,
+    // and a merged batch no longer holds its requests for a million pairs
+    if (o.max_batch_pairs == 0) o.max_batch_pairs = (int64_t)1 << 16;
   }
   if (o.n_streams < 1 || o.n_streams > 16) return sfail(AIM_ERR_INVALID_ARG, "n_streams must be in [1, 16]");
   if (o.budget_bytes < ((int64_t)1 << 20)) return sfail(AIM_ERR_INVALID_ARG, "budget_bytes below 1 MiB");

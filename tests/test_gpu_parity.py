@@ -220,6 +220,17 @@ def test_long_runs_spill_path(ctx):
     check(ctx, synth.from_lists(pats, txts), "swg", (0, 1, 6, 2))
 
 
+@pytest.mark.parametrize("alg,pen,smax", [("nw", (0, 2, 0, 2), 41), ("swg", (0, 6, 3, 3), 100),
+                                         ("swg", (0, 6, 3, 3), -1), ("nw", (0, 2, 0, 2), -1)])
+def test_long_reads_common_divisor(ctx, alg, pen, smax):
+    # Reads over 256 bases that no band certifies go to the wavefront passes,
+    # which run on the penalties divided by their common divisor (2 and 3
+    # here); thresholds that are not multiples of it must still split
+    # accepted from rejected pairs exactly.
+    b = _mixed_batch(37, 80, 300, 700, [0.01, 0.04, 0.1, 1.0])
+    check(ctx, b, alg, pen, smax)
+
+
 @pytest.mark.parametrize("seed", [1, 2])
 def test_long_reads(ctx, seed):
     b = _mixed_batch(30 + seed, 60, 500, 1500, [0.01, 0.05])
