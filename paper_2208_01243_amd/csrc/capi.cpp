@@ -42,6 +42,7 @@ aim_status fail(aim_status code, const char *fmt, ...) {
 struct Buf {
   void *p = nullptr;
   size_t bytes = 0;
+  bool pooled = false;  // from the stream-ordered pool (hipMallocAsync)
 };
 
 }  // namespace
@@ -119,6 +120,14 @@ struct aim_context {
   // beside the first tier's traceback; fork / join through the two events
   hipStream_t aux = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // Scratch grows in stream order on the running call's stream (astream):
+  // the old buffer is freed and the new one allocated there, so a growing
+  // context does not synchronise the device (and stall the other contexts'
+  // streams).  ev_done marks the end of the last call's work; a call on
+  // another stream waits for it first.
+  hipStream_t astream = nullptr, done_stream = nullptr;
+  hipEvent_t ev_done = nullptr;
+  bool has_done = false;
   int64_t generation = 0;       // bumped whenever scratch is reallocated
   Buf order, hist;
   Buf flags, pflag, tflag, pat2, txt2, pat2off, txt2off, nruns, slot, tb32, tb64, full, list2,
@@ -132,19 +141,30 @@ aim_status ensure(aim_context *c, Buf &b, size_t bytes) {
   if (bytes == 0) bytes = 256;
   if (b.bytes >= bytes) return AIM_OK;
   if (c->capturing) return fail(AIM_ERR_INVALID_ARG, "scratch would grow during graph capture");
+  hipStream_t as = c->astream;
   if (b.p) {
-    // previously enqueued work may still use the old buffer
-    HIP_TRY(hipDeviceSynchronize());
-    HIP_TRY(hipFree(b.p));
+    // previously enqueued work may still use the old buffer: free it behind
+    // that work on the call's stream, or after a device synchronisation
+    if (b.pooled && as) {
+      HIP_TRY(hipFreeAsync(b.p, as));
+    } else {
+      HIP_TRY(hipDeviceSynchronize());
+      if (b.pooled)
+        HIP_TRY(hipFreeAsync(b.p, nullptr));
+      else
+        HIP_TRY(hipFree(b.p));
+    }
     b.p = nullptr;
     b.bytes = 0;
   }
   size_t want = bytes + bytes / 8;
   c->generation += 1;
-  hipError_t e = hipMalloc(&b.p, want);
+  auto alloc = [&](size_t sz) { return as ? hipMallocAsync(&b.p, sz, as) : hipMalloc(&b.p, sz); };
+  b.pooled = as != nullptr;
+  hipError_t e = alloc(want);
   if (e != hipSuccess) {
     (void)hipGetLastError();
-    e = hipMalloc(&b.p, bytes);
+    e = alloc(bytes);
     if (e != hipSuccess) {
       (void)hipGetLastError();
       b.p = nullptr;
@@ -430,9 +450,11 @@ aim_status aim_create(aim_context **ctx, int32_t device, const aim_options *opt)
     DeviceGuard g(device);
     if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_done, hipEventDisableTiming) != hipSuccess) {
       if (c->aux) (void)hipStreamDestroy(c->aux);
       if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+      if (c->ev_join) (void)hipEventDestroy(c->ev_join);
       delete c;
       return fail(AIM_ERR_HIP, "could not create the context's stream and events");
     }
@@ -450,7 +472,9 @@ void aim_destroy(aim_context *c) {
                 &c->counters, &c->scan_tmp, &c->spill, &c->total, &c->wring, &c->warena1,
                 &c->warena2, &c->warena3, &c->wneed, &c->wlists, &c->pool, &c->pooloff, &c->wbits, &c->wwalk};
   for (Buf *b : all)
-    if (b->p) (void)hipFree(b->p);
+    if (b->p) (void)(b->pooled ? hipFreeAsync(b->p, nullptr) : hipFree(b->p));
+  (void)hipDeviceSynchronize();
+  if (c->ev_done) (void)hipEventDestroy(c->ev_done);
   if (c->ev_join) (void)hipEventDestroy(c->ev_join);
   if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
   if (c->aux) (void)hipStreamDestroy(c->aux);
@@ -476,8 +500,8 @@ aim_status aim_pack_2bit(aim_context *c, int64_t n, int32_t enc, const uint8_t *
   return AIM_OK;
 }
 
-aim_status aim_align_batch(aim_context *c, const aim_batch *B, int32_t alg, aim_penalties pen,
-                           int32_t max_score, aim_results *R, void *stream) {
+static aim_status align_batch(aim_context *c, const aim_batch *B, int32_t alg, aim_penalties pen,
+                              int32_t max_score, aim_results *R, void *stream) {
   g_err.clear();
   // validation needs no device and happens before anything is enqueued
   if (!B || !R) return fail(AIM_ERR_INVALID_ARG, "NULL batch or results");
@@ -732,6 +756,23 @@ aim_status aim_align_batch(aim_context *c, const aim_batch *B, int32_t alg, aim_
     if ((st = run_full(WS, n, s))) return st;
   }
   return AIM_OK;
+}
+
+aim_status aim_align_batch(aim_context *c, const aim_batch *B, int32_t alg, aim_penalties pen,
+                           int32_t max_score, aim_results *R, void *stream) {
+  if (!c || c->capturing) return align_batch(c, B, alg, pen, max_score, R, stream);
+  DeviceGuard g(c->device);
+  hipStream_t s = (hipStream_t)stream;
+  // the previous call's work (on another stream) before this call's, so that
+  // scratch freed or reused in stream order on `s` is no longer in use
+  if (c->has_done && c->done_stream != s) HIP_TRY(hipStreamWaitEvent(s, c->ev_done, 0));
+  c->astream = s;
+  const aim_status st = align_batch(c, B, alg, pen, max_score, R, stream);
+  c->astream = nullptr;
+  HIP_TRY(hipEventRecord(c->ev_done, s));
+  c->has_done = true;
+  c->done_stream = s;
+  return st;
 }
 
 }  // extern "C"
