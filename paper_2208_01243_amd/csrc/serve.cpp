@@ -63,16 +63,20 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
-bool grow(DevBuf &b, size_t bytes, bool pinned) {
+// Grows a staging buffer.  Device buffers are freed and allocated in stream
+// order on the worker's stream (idle here: every batch ends with a stream
+// synchronisation), so a growing worker does not synchronise the device and
+// stall the others; pinned host buffers double, so they rarely grow.
+bool grow(DevBuf &b, size_t bytes, bool pinned, hipStream_t s) {
   if (b.bytes >= bytes) return true;
   if (b.p) {
     if (pinned) (void)hipHostFree(b.p);
-    else (void)hipFree(b.p);
+    else (void)hipFreeAsync(b.p, s);
   }
   b.p = nullptr;
   b.bytes = 0;
-  size_t want = bytes + bytes / 4 + 4096;
-  hipError_t e = pinned ? hipHostMalloc(&b.p, want, hipHostMallocDefault) : hipMalloc(&b.p, want);
+  size_t want = pinned ? 2 * bytes + 4096 : bytes + bytes / 4 + 4096;
+  hipError_t e = pinned ? hipHostMalloc(&b.p, want, hipHostMallocDefault) : hipMallocAsync(&b.p, want, s);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     b.p = nullptr;
@@ -162,8 +166,8 @@ aim_status run_batch(Worker &w, std::vector<Req *> &batch) {
   const int64_t cig_cap = k.want_cigar ? pb + tb + n : 0;
   const size_t q_score = 0, q_status = align256(4 * n), q_coff = align256(q_status + n),
                q_cig = align256(q_coff + 8 * (n + 1)), out_bytes = align256(q_cig + 4 * cig_cap);
-  if (!grow(w.hin, in_bytes, true) || !grow(w.din, in_bytes, false) ||
-      !grow(w.hout, out_bytes, true) || !grow(w.dout, out_bytes, false))
+  if (!grow(w.hin, in_bytes, true, w.stream) || !grow(w.din, in_bytes, false, w.stream) ||
+      !grow(w.hout, out_bytes, true, w.stream) || !grow(w.dout, out_bytes, false, w.stream))
     return sfail(AIM_ERR_OOM, "serving buffers");
   char *h = (char *)w.hin.p;
   int64_t ip = 0, it = 0, q = 0;
@@ -223,6 +227,10 @@ void worker_main(aim_server *s, int idx) {
   aim_options o{AIM_KERNEL_AUTO, 0, std::max<int64_t>((int64_t)1 << 30, s->opt.budget_bytes / std::max(1, s->opt.n_streams))};
   bool ok = aim_create(&w.ctx, s->device, &o) == AIM_OK &&
             hipStreamCreateWithFlags(&w.stream, hipStreamNonBlocking) == hipSuccess;
+  // staging for batches of up to 64 MiB in and out from the start
+  ok = ok && grow(w.hin, (size_t)64 << 20, true, w.stream) && grow(w.din, (size_t)64 << 20, false, w.stream) &&
+       grow(w.hout, (size_t)64 << 20, true, w.stream) && grow(w.dout, (size_t)64 << 20, false, w.stream) &&
+       hipStreamSynchronize(w.stream) == hipSuccess;
   {
     std::lock_guard<std::mutex> g(s->mu);
     if (!ok) {
@@ -266,12 +274,15 @@ void worker_main(aim_server *s, int idx) {
     admit_locked(s);
     s->cv_done.notify_all();
   }
-  if (w.stream) (void)hipStreamDestroy(w.stream);
+  if (w.stream) {
+    if (w.din.p) (void)hipFreeAsync(w.din.p, w.stream);
+    if (w.dout.p) (void)hipFreeAsync(w.dout.p, w.stream);
+    (void)hipStreamSynchronize(w.stream);
+    (void)hipStreamDestroy(w.stream);
+  }
   if (w.ctx) aim_destroy(w.ctx);
   if (w.hin.p) (void)hipHostFree(w.hin.p);
   if (w.hout.p) (void)hipHostFree(w.hout.p);
-  if (w.din.p) (void)hipFree(w.din.p);
-  if (w.dout.p) (void)hipFree(w.dout.p);
   (void)idx;
 }
 
