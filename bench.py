@@ -292,6 +292,10 @@ def serve_bench(args, aim, synth):
             submitted[k] = time.perf_counter() - start
             ids[k] = rid
 
+    # no collector pauses in the replay's threads while the schedule runs
+    import gc
+    gc.collect()
+    gc.disable()
     th = threading.Thread(target=producer)
     th.start()
     k = 0
@@ -310,6 +314,7 @@ def serve_bench(args, aim, synth):
             last_log = time.perf_counter()
     th.join()
     wall = time.perf_counter() - start
+    gc.enable()
     st = srv.stats()
     srv.close()
     lat = np.array([(submitted[k] - sched[k].t_arrival) * 1e6 + server_us[k] for k in range(len(sched))])
