@@ -26,7 +26,10 @@
  *     aim_last_error() then describes it.  Nothing throws across the ABI.
  *   - Device pointers are HIP device (or managed) memory of the context's
  *     device.  The caller owns every buffer it passes; the library owns its
- *     scratch, which lives in the context and grows on demand.
+ *     scratch, which lives in the context and grows on demand, in stream
+ *     order on the call's stream (hipFreeAsync / hipMallocAsync), so growing
+ *     one context does not synchronise the device.  A call on a different
+ *     stream than the context's previous call first waits for that call.
  *   - Work is enqueued asynchronously on `stream` (a hipStream_t; NULL = the
  *     null stream); outputs are valid once the stream is synchronised.  Calls
  *     that share a context must not run concurrently from several host
