@@ -274,6 +274,18 @@ def serve_bench(args, aim, synth):
             for r, b in list(zip(sched, batches))[:12]]
     for i in warm:
         srv.wait(i)
+    # and with batches of the merge cap at the schedule's longest reads, one per
+    # worker and algorithm, so that no worker grows its scratch mid-schedule
+    # (a server pays this once at start-up)
+    cap = args.serve_max_batch or 65536
+    rng = np.random.default_rng(7)
+    big = synth._gen_chunk(rng, cap, np.full(cap, 1000), np.full(cap, 0.08), None)
+    for alg, pen in sorted({(r.alg, r.pen) for r in sched}):
+        ws = [srv.submit(alg, pen, -1, big.pat, big.pat_off[:-1], big.pat_len, big.txt, big.txt_off[:-1],
+                         big.txt_len) for _ in range(args.serve_streams)]
+        for i in ws:
+            srv.wait(i)
+    log("warmed %d workers with %d-pair batches of 1000 bp" % (args.serve_streams, cap))
     srv.reset_stats()
     ids = [None] * len(sched)
     lateness = [0.0] * len(sched)
