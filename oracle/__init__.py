@@ -35,21 +35,26 @@ _lib = None
 _lock = threading.Lock()
 
 
-def build(force: bool = True) -> str:
-    """Compile the C oracle with gcc into ``oracle/liboracle.so``."""
-    if not force and os.path.exists(LIB):
-        return LIB
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-pthread", "-Wall", "-Wextra",
-           "-o", tmp] + SOURCES
+def build(force: bool = True, path: str = LIB, native: bool = False) -> str:
+    """Compile the C oracle with gcc into ``path`` (``oracle/liboracle.so``).
+    ``native``: -O3 -march=native for the host that runs it (the CPU baseline
+    builds such a copy where it is timed; the in-tree library stays portable,
+    since it is built on one machine and may run on another)."""
+    if not force and os.path.exists(path):
+        return path
+    tmp = path + ".tmp%d" % os.getpid()
+    opt = ["-O3", "-march=native"] if native else ["-O2"]
+    cmd = ["gcc"] + opt + ["-std=c11", "-fPIC", "-shared", "-pthread", "-Wall", "-Wextra",
+                           "-o", tmp] + SOURCES
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, path)
+    return path
 
 
 class WfaStats(ctypes.Structure):
     _fields_ = [("cells", ctypes.c_int64), ("compared", ctypes.c_int64),
-                ("wavefronts", ctypes.c_int64)]
+                ("wavefronts", ctypes.c_int64), ("words", ctypes.c_int64),
+                ("lo_min", ctypes.c_int32), ("hi_max", ctypes.c_int32)]
 
 
 def bind(path: str):
@@ -117,8 +122,10 @@ def align_pair(P, T, alg: str, pen, max_score: int = -1, want_cigar: bool = True
     return int(status[0]), int(score[0]), [int(r) for r in runs[:nr[0]]]
 
 
-def wfa_pair(P, T, pen, max_score: int = -1, want_cigar: bool = True):
-    """Scalar WFA.  Returns (status, score, runs, stats dict)."""
+def wfa_pair(P, T, pen, max_score: int = -1, want_cigar: bool = True, handle=None):
+    """Scalar WFA.  Returns (status, score, runs, stats dict); the stats are
+    the work counters of ``wfa_scalar.c`` (cells, wavefronts, compared, words,
+    lo_min, hi_max)."""
     _check_pen("wfa", pen)
     P, T = _codes(P), _codes(T)
     m, n = len(P), len(T)
@@ -130,19 +137,21 @@ def wfa_pair(P, T, pen, max_score: int = -1, want_cigar: bool = True):
     st = WfaStats()
     Pb = P if m else np.zeros(1, np.uint8)
     Tb = T if n else np.zeros(1, np.uint8)
-    rc = lib().oracle_wfa(_ptr(Pb), m, _ptr(Tb), n, pen[1], pen[2], pen[3], max_score,
+    rc = (handle or lib()).oracle_wfa(_ptr(Pb), m, _ptr(Tb), n, pen[1], pen[2], pen[3], max_score,
                           int(want_cigar), _ptr(score), _ptr(status), _ptr(runs), cap, _ptr(nr),
                           ctypes.byref(st))
     if rc != 0:
         raise RuntimeError("wfa oracle failure %d" % rc)
     return (int(status[0]), int(score[0]), [int(r) for r in runs[:nr[0]]],
-            {"cells": st.cells, "compared": st.compared, "wavefronts": st.wavefronts})
+            {"cells": st.cells, "compared": st.compared, "wavefronts": st.wavefronts,
+             "words": st.words, "lo_min": st.lo_min, "hi_max": st.hi_max})
 
 
 def align_batch(batch, alg: str, pen, max_score: int = -1, want_cigar: bool = True,
-                nthreads: int | None = None):
+                nthreads: int | None = None, handle=None):
     """Align every pair of a ``synth.PairBatch`` (codes).  Returns
-    (score int32[n], status int8[n], cigar uint32[...], cigar_off int64[n+1])."""
+    (score int32[n], status int8[n], cigar uint32[...], cigar_off int64[n+1]).
+    ``handle`` selects another build of the oracle (see ``bind``)."""
     _check_pen(alg, pen)
     n = batch.n
     if nthreads is None:
@@ -160,7 +169,7 @@ def align_batch(batch, alg: str, pen, max_score: int = -1, want_cigar: bool = Tr
         slot_arr = slot
     else:
         slot_arr = np.zeros(n + 1, np.int64)
-    rc = lib().oracle_align_batch(n, _ptr(pat), _ptr(np.ascontiguousarray(batch.pat_off)),
+    rc = (handle or lib()).oracle_align_batch(n, _ptr(pat), _ptr(np.ascontiguousarray(batch.pat_off)),
                                   _ptr(txt), _ptr(np.ascontiguousarray(batch.txt_off)), ALG[alg],
                                   pen[1], pen[2], pen[3], max_score, int(want_cigar), nthreads,
                                   _ptr(score), _ptr(status), _ptr(runs), _ptr(slot_arr), _ptr(nr))

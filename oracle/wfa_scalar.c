@@ -42,9 +42,19 @@ static int32_t wf_get(const wavefront *w, const int32_t *a, int32_t k) {
 
 static int32_t max2(int32_t a, int32_t b) { return a > b ? a : b; }
 
-/* Stats of the last call: cells computed (sum of wavefront widths over
- * non-null scores) and bases compared during extension. */
-typedef struct { int64_t cells, compared, wavefronts; } wfa_stats;
+/* Work of the last call, the units in which the wavefront algorithm's cost
+ * is stated (O(n s): one unit per diagonal of every wavefront it computes).
+ *   cells:      the widths hi_s - lo_s + 1 of every non-null wavefront,
+ *               s = 0 (one diagonal) included;
+ *   wavefronts: the non-null wavefronts;
+ *   compared:   bases compared by the extensions, one per matching base plus
+ *               one for the mismatch that stops a run (none when a run stops
+ *               at the end of either sequence);
+ *   words:      the same comparisons taken 32 bases at a time: a run of r
+ *               matches costs floor(r / 32) + 1 words when a mismatch stops
+ *               it and ceil(r / 32) when it stops at an end;
+ *   lo_min, hi_max: the outermost diagonals any wavefront spans. */
+typedef struct { int64_t cells, compared, wavefronts, words; int32_t lo_min, hi_max; } wfa_stats;
 
 int oracle_wfa(const uint8_t *P, int32_t m, const uint8_t *T, int32_t n, int32_t x, int32_t o,
                int32_t e, int32_t max_score, int32_t want_cigar, int32_t *score, int8_t *status,
@@ -53,7 +63,7 @@ int oracle_wfa(const uint8_t *P, int32_t m, const uint8_t *T, int32_t n, int32_t
   int32_t cap_s = 64;
   wavefront *W = (wavefront *)calloc((size_t)cap_s, sizeof(wavefront));
   if (!W) return -1;
-  wfa_stats S = {0, 0, 0};
+  wfa_stats S = {0, 0, 0, 0, 0, 0};
   int32_t kend = n - m;
   int32_t s = 0;
   int rc = 0, done = 0;
@@ -77,6 +87,7 @@ int oracle_wfa(const uint8_t *P, int32_t m, const uint8_t *T, int32_t n, int32_t
       w->M = (int32_t *)malloc(sizeof(int32_t));
       if (!w->M) { rc = -1; break; }
       w->M[0] = 0;
+      S.cells += 1;
     } else {
       int has_x = wx && wx->M, has_o = wo && wo->M, has_ie = we && we->I, has_de = we && we->D;
       if (!has_x && !has_o && !has_ie && !has_de) continue;
@@ -109,13 +120,21 @@ int oracle_wfa(const uint8_t *P, int32_t m, const uint8_t *T, int32_t n, int32_t
       S.cells += width;
     }
     S.wavefronts += 1;
+    if (w->lo < S.lo_min) S.lo_min = w->lo;
+    if (w->hi > S.hi_max) S.hi_max = w->hi;
     /* extend */
     for (int32_t k = w->lo; k <= w->hi; ++k) {
       int32_t f = w->M[k - w->lo];
       if (f < 0) continue;
-      int32_t i = f - k, j = f;
-      while (i < m && j < n && P[i] == T[j]) { ++i; ++j; ++S.compared; }
-      if (i < m && j < n) ++S.compared;
+      int32_t i = f - k, j = f, run = 0;
+      while (i < m && j < n && P[i] == T[j]) { ++i; ++j; ++run; }
+      S.compared += run;
+      if (i < m && j < n) {
+        S.compared += 1;
+        S.words += run / 32 + 1;
+      } else {
+        S.words += (run + 31) / 32;
+      }
       w->M[k - w->lo] = j;
     }
     if (kend >= w->lo && kend <= w->hi && w->M[kend - w->lo] >= n) { done = 1; break; }
