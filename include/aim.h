@@ -191,6 +191,37 @@ aim_status aim_timing(aim_context *ctx, int32_t idx, const char **name, double *
                       int64_t *launches);
 aim_status aim_timing_reset(aim_context *ctx);
 
+/* Work counters of the context's last aligning call (aim_align_batch, a graph
+ * replay, or aim_align_batch_static -- whose counters live in the shared
+ * static array, so a later static call on the same GPU overwrites them).
+ * Waits for that call to finish.  All zero before the first call or after
+ * an empty batch.  These say which paths the pairs took; they are not part of
+ * the results, which are the same whatever the path.
+ *   band_escalated / band_escalated2: NW/SWG pairs the 32-diagonal band passed
+ *     on to the 64-diagonal band, and that band on to the last tier;
+ *   wfa_wide: WFA pairs whose wavefronts left the one-wavefront window;
+ *   wfa_walk_failed: WFA pairs whose walk over the kept origin codes failed
+ *     (0 unless a code was read back wrong; each is re-walked from a full
+ *     store, so results stay exact and only time is lost);
+ *   wfa_walk_skipped: accepted WFA pairs whose codes were not kept (more
+ *     scores than the code slot holds);
+ *   full_store[c]: pairs walked by the full-store pass, per store class
+ *     (LDS, 1 MB, 16 MB, largest);
+ *   cigar_reruns: pairs whose runs outgrew their slot and the run pool,
+ *     re-aligned in place by the compaction;
+ *   wfa_window: the diagonals the one-wavefront WFA pass keeps, centred on
+ *     diagonal 0 (0: that pass did not run); pairs whose wavefronts stay
+ *     inside it are aligned there, the others by the wide-pair pass. */
+typedef struct {
+  int64_t n_pairs;
+  int32_t band_escalated, band_escalated2;
+  int32_t wfa_wide, wfa_walk_failed, wfa_walk_skipped;
+  int32_t full_store[4];
+  int32_t cigar_reruns;
+  int32_t wfa_window;
+} aim_call_stats;
+aim_status aim_last_call_stats(aim_context *ctx, aim_call_stats *out);
+
 /* ---- batching form: autotuner and captured graphs ---------------------- */
 
 /* Time every candidate launch configuration on this batch and keep the

@@ -69,6 +69,12 @@ class ServerStats(ctypes.Structure):
                 ("peak_bytes", i64), ("budget_bytes", i64), ("elapsed_s", ctypes.c_double)]
 
 
+class CallStats(ctypes.Structure):
+    _fields_ = [("n_pairs", i64), ("band_escalated", i32), ("band_escalated2", i32), ("wfa_wide", i32),
+                ("wfa_walk_failed", i32), ("wfa_walk_skipped", i32), ("full_store", i32 * 4),
+                ("cigar_reruns", i32), ("wfa_window", i32)]
+
+
 class AimError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__("%s (%d): %s" % (ERRORS.get(code, "AIM_ERR"), code, msg))
@@ -84,6 +90,7 @@ SIGNATURES = {
     "aim_timing": ([vp, i32, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_double),
                     ctypes.POINTER(i64)], i32),
     "aim_timing_reset": ([vp], i32),
+    "aim_last_call_stats": ([vp, ctypes.POINTER(CallStats)], i32),
     "aim_autotune": ([vp, ctypes.POINTER(Batch), i32, Penalties, i32, ctypes.POINTER(Results), vp, i32,
                       ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)], i32),
     "aim_tune_get": ([vp, i32, i32, ctypes.POINTER(i32)], i32),
@@ -247,6 +254,14 @@ class Context:
             _check(rc)
             out[name.value.decode()] = (ms.value, cnt.value)
             k += 1
+
+    def last_call_stats(self) -> dict:
+        """aim_last_call_stats as a dict (waits for the last call)."""
+        st = CallStats()
+        _check(lib().aim_last_call_stats(self._h, ctypes.byref(st)))
+        out = {k: getattr(st, k) for k, _ in CallStats._fields_}
+        out["full_store"] = list(st.full_store)
+        return out
 
     def timing_reset(self):
         _check(lib().aim_timing_reset(self._h))

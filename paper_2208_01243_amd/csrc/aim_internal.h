@@ -198,6 +198,11 @@ struct WfaLaunch {
   uint8_t *walk;
   int32_t walk_steps, walk_tok;
   int64_t walk_codes, walk_slot;
+  // score passes with a CIGAR wanted: counters of accepted pairs left to the
+  // full-store pass, because their fused walk failed (walk_fail; it cannot,
+  // for codes that were kept and read back intact) or because their codes
+  // were not kept (walk_skip: more scores than the code slot holds)
+  int32_t *walk_fail, *walk_skip;
 };
 
 struct WfaPlan {

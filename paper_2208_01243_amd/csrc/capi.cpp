@@ -100,6 +100,14 @@ struct Tune {
                               // 3: 2 for batches of at least SPLIT_MIN_PAIRS pairs, else 1)
 };
 
+// Every scratch buffer of one call.
+struct Scratch {
+  Buf order, hist;
+  Buf flags, pflag, tflag, pat2, txt2, pat2off, txt2off, nruns, slot, tb32, tb64, full, list2,
+      list3, counters, scan_tmp, spill, total, wring, warena1, warena2, warena3, wneed, wlists, pool, pooloff,
+      wbits, wwalk;
+};
+
 struct aim_graph {
   aim_context *c = nullptr;
   hipGraph_t graph = nullptr;
@@ -129,10 +137,15 @@ struct aim_context {
   hipEvent_t ev_done = nullptr;
   bool has_done = false;
   int64_t generation = 0;       // bumped whenever scratch is reallocated
-  Buf order, hist;
-  Buf flags, pflag, tflag, pat2, txt2, pat2off, txt2off, nruns, slot, tb32, tb64, full, list2,
-      list3, counters, scan_tmp, spill, total, wring, warena1, warena2, warena3, wneed, wlists, pool, pooloff,
-      wbits, wwalk;
+  // Scratch of the running call (the context's own, grown on demand).
+  Scratch own;
+  Scratch *sc = &own;
+  // the scratch budget the launch plans are sized for in this call
+  int64_t limit() const { return opt.scratch_limit; }
+  // the last call's work counters (device) and size, for aim_last_call_stats
+  const int32_t *last_cnt = nullptr;
+  int64_t last_n = 0;
+  int32_t last_window = 0;  // diagonals of the one-wavefront WFA window (0: not run)
 };
 
 namespace {
@@ -195,7 +208,7 @@ struct DeviceGuard {
 enum Counter {
   C_T1 = 0, C_T2, C_T3, C_L2, C_L3, C_SPILL, C_SPILL_W,
   C_W1, C_W1G, C_RL, C_FAIL, C_N0, C_N1, C_N2, C_N3, C_P0, C_P1, C_P2, C_P3, C_TB, C_DTB,
-  C_M0, C_M1, C_M2, C_M3,
+  C_M0, C_M1, C_M2, C_M3, C_WF, C_WS,
   C_N = 32
 };
 
@@ -290,11 +303,11 @@ aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const
                    const int32_t *order_count, const Tune &tu, hipStream_t s) {
   aim_status st;
   const aim::Scoring P = wfa_scoring(Pin);
-  const aim::WfaPlan pl = aim::wfa_plan(L, P, c->opt.scratch_limit, c->cus, plain, tu.wfa_ring_kb,
+  const aim::WfaPlan pl = aim::wfa_plan(L, P, c->limit(), c->cus, plain, tu.wfa_ring_kb,
                                         tu.wfa_trace_kb, tu.wfa_long_threads);
-  if ((st = ensure(c, c->wneed, (size_t)n * 8))) return st;
-  if ((st = ensure(c, c->wlists, (size_t)n * 4 * 6))) return st;
-  int32_t *lists = as<int32_t>(c->wlists);
+  if ((st = ensure(c, c->sc->wneed, (size_t)n * 8))) return st;
+  if ((st = ensure(c, c->sc->wlists, (size_t)n * 4 * 6))) return st;
+  int32_t *lists = as<int32_t>(c->sc->wlists);
   aim::WfaLaunch WL{};
   WL.R = pl.R;
   WL.seq_words = pl.seq_words;
@@ -306,7 +319,9 @@ aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const
     WL.need_cap[k] = pl.need_cap[k];
     WL.need_max[k] = cnt + C_M0 + k;
   }
-  WL.need = as<int64_t>(c->wneed);
+  WL.need = as<int64_t>(c->sc->wneed);
+  WL.walk_fail = cnt + C_WF;
+  WL.walk_skip = cnt + C_WS;
   const int32_t slots = (int32_t)std::min<int64_t>(n, (int64_t)c->cus * 8);
   // one wavefront per pair with 16-bit offsets over a window of 64 C diagonals
   const int32_t C16 = (int32_t)std::min<int64_t>(4, std::max<int64_t>(1, (pl.wcap + 63) / 64));
@@ -323,14 +338,15 @@ aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const
       A.bits_steps = P.max_score >= 0 ? std::min(P.max_score + 1, aim::WFA16_WALK_STEPS)
                                       : aim::WFA16_WALK_STEPS;
       A.bits_steps = (int32_t)std::max<int64_t>(
-          1, std::min<int64_t>(A.bits_steps, c->opt.scratch_limit / 16 / ((int64_t)nslots16 * (C16 * 32 + 32))));
+          1, std::min<int64_t>(A.bits_steps, c->limit() / 16 / ((int64_t)nslots16 * (C16 * 32 + 32))));
       // rows of C16 x 32 bytes plus 32 bytes of padding
-      if ((st = ensure(c, c->wbits, (size_t)nslots16 * A.bits_steps * (C16 * 32 + 32)))) return st;
-      A.bits = as<uint8_t>(c->wbits);
+      if ((st = ensure(c, c->sc->wbits, (size_t)nslots16 * A.bits_steps * (C16 * 32 + 32)))) return st;
+      A.bits = as<uint8_t>(c->sc->wbits);
     }
     aim::Work W{order, order_count, n, cnt + C_W1, nullptr, nullptr, 0};
     Phase ph(c, s, "wfa_score");
     HIP_TRY(aim::launch_wfa_score16(S, O, P, W, A, C16, nslots16, s));
+    c->last_window = 64 * C16;
   } else if (!plain && pl.wcap_lds > 0) {
     aim::WfaLaunch A = WL;
     A.wcap = pl.wcap_lds;
@@ -341,7 +357,7 @@ aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const
   {
     // pairs whose wavefronts outgrew the LDS ring (all pairs for the plain path)
     const int64_t pad = aim::wfa_ring_pad(pl.wcap);  // read margin at both ends
-    if ((st = ensure(c, c->wring, (size_t)(pl.ring_slot_words * pl.ring_slots + 2 * pad) * 4))) return st;
+    if ((st = ensure(c, c->sc->wring, (size_t)(pl.ring_slot_words * pl.ring_slots + 2 * pad) * 4))) return st;
     aim::WfaLaunch B = WL;
     B.wcap = pl.wcap;
     B.slot_words = pl.ring_slot_words;
@@ -356,20 +372,20 @@ aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const
       // (no more than every kept score at the widest wavefront needs)
       const int64_t most = (int64_t)B.walk_steps * ((pl.wcap + 1) / 2) + 16;
       B.walk_codes = std::min<int64_t>(
-          most, std::max<int64_t>(256 << 10, std::min<int64_t>(16 << 20, c->opt.scratch_limit / 4 / grid)));
+          most, std::max<int64_t>(256 << 10, std::min<int64_t>(16 << 20, c->limit() / 4 / grid)));
       B.walk_codes = (B.walk_codes + 15) / 16 * 16;
       B.walk_slot = ((int64_t)B.walk_steps * 16 + B.walk_codes + (int64_t)B.walk_tok * 4 + 255) / 256 * 256;
-      if ((st = ensure(c, c->wwalk, (size_t)B.walk_slot * grid))) return st;
-      B.walk = as<uint8_t>(c->wwalk);
+      if ((st = ensure(c, c->sc->wwalk, (size_t)B.walk_slot * grid))) return st;
+      B.walk = as<uint8_t>(c->sc->wwalk);
     }
     aim::Work W{all ? order : lists, all ? order_count : cnt + C_RL, n, cnt + C_W1G, nullptr, nullptr, 0};
     Phase ph(c, s, "wfa_score_hbm");
-    HIP_TRY(aim::launch_wfa_score(S, O, P, W, B, as<int32_t>(c->wring) + pad, false, grid,
+    HIP_TRY(aim::launch_wfa_score(S, O, P, W, B, as<int32_t>(c->sc->wring) + pad, false, grid,
                                   plain ? 64 : pl.ring_threads, !plain && L <= aim::WFA16_MAX_LEN, s));
   }
   if (!P.want_cigar) return AIM_OK;
   // fallback pass by class: 0 LDS arena, 1-3 HBM slots of growing size
-  Buf *arena[4] = {nullptr, &c->warena1, &c->warena2, &c->warena3};
+  Buf *arena[4] = {nullptr, &c->sc->warena1, &c->sc->warena2, &c->sc->warena3};
   static const char *names[4] = {"wfa_trace_lds", "wfa_trace_1m", "wfa_trace_16m", "wfa_trace_192m"};
   for (int k = 0; k < 4; ++k) {
     if (k == 0 && (plain || pl.lds_arena_words <= 0)) continue;
@@ -438,6 +454,8 @@ aim_status aim_create(aim_context **ctx, int32_t device, const aim_options *opt)
     return fail(AIM_ERR_INVALID_ARG, "unknown kernel option %d", o.kernel);
   if (o.scratch_limit < 0) return fail(AIM_ERR_INVALID_ARG, "scratch_limit < 0");
   if (o.scratch_limit == 0) o.scratch_limit = (int64_t)64 << 30;
+  if (o.flags & ~AIM_FLAG_TIMING)
+    return fail(AIM_ERR_INVALID_ARG, "unknown option flags 0x%x", o.flags);
   auto *c = new aim_context();
   c->device = device;
   c->opt = o;
@@ -467,10 +485,10 @@ void aim_destroy(aim_context *c) {
   if (!c) return;
   DeviceGuard g(c->device);
   (void)hipDeviceSynchronize();
-  Buf *all[] = {&c->order, &c->hist, &c->flags, &c->pflag, &c->tflag, &c->pat2, &c->txt2, &c->pat2off, &c->txt2off,
-                &c->nruns, &c->slot, &c->tb32, &c->tb64, &c->full, &c->list2, &c->list3,
-                &c->counters, &c->scan_tmp, &c->spill, &c->total, &c->wring, &c->warena1,
-                &c->warena2, &c->warena3, &c->wneed, &c->wlists, &c->pool, &c->pooloff, &c->wbits, &c->wwalk};
+  Buf *all[] = {&c->own.order, &c->own.hist, &c->own.flags, &c->own.pflag, &c->own.tflag, &c->own.pat2, &c->own.txt2, &c->own.pat2off, &c->own.txt2off,
+                &c->own.nruns, &c->own.slot, &c->own.tb32, &c->own.tb64, &c->own.full, &c->own.list2, &c->own.list3,
+                &c->own.counters, &c->own.scan_tmp, &c->own.spill, &c->own.total, &c->own.wring, &c->own.warena1,
+                &c->own.warena2, &c->own.warena3, &c->own.wneed, &c->own.wlists, &c->own.pool, &c->own.pooloff, &c->own.wbits, &c->own.wwalk};
   for (Buf *b : all)
     if (b->p) (void)(b->pooled ? hipFreeAsync(b->p, nullptr) : hipFree(b->p));
   (void)hipDeviceSynchronize();
@@ -493,10 +511,10 @@ aim_status aim_pack_2bit(aim_context *c, int64_t n, int32_t enc, const uint8_t *
   DeviceGuard g(c->device);
   hipStream_t s = (hipStream_t)stream;
   const size_t tmp = aim::scan_tmp_elems(n) + (size_t)n + 2;
-  aim_status st = ensure(c, c->scan_tmp, tmp * sizeof(int64_t));
+  aim_status st = ensure(c, c->sc->scan_tmp, tmp * sizeof(int64_t));
   if (st) return st;
   HIP_TRY(aim::launch_pack(n, enc, seq, off, len, INT32_MAX, out_words, words_cap, out_off, seq_flags,
-                           as<int64_t>(c->scan_tmp), s));
+                           as<int64_t>(c->sc->scan_tmp), s));
   return AIM_OK;
 }
 
@@ -522,6 +540,8 @@ static aim_status align_batch(aim_context *c, const aim_batch *B, int32_t alg, a
   hipStream_t s = (hipStream_t)stream;
 
   if (n == 0) {
+    c->last_cnt = nullptr;
+    c->last_n = 0;
     if (R->cigar_off) HIP_TRY(aim::launch_zero_offsets(0, R->cigar_off, s));
     return AIM_OK;
   }
@@ -532,14 +552,14 @@ static aim_status align_batch(aim_context *c, const aim_batch *B, int32_t alg, a
 
   // ---- common scratch ----
   const size_t tmp = aim::scan_tmp_elems(n) + (size_t)n + 2;
-  if ((st = ensure(c, c->scan_tmp, tmp * sizeof(int64_t)))) return st;
-  if ((st = ensure(c, c->counters, C_N * sizeof(int32_t) + 64))) return st;
-  if ((st = ensure(c, c->total, 64))) return st;
-  if ((st = ensure(c, c->flags, (size_t)n))) return st;
-  if ((st = ensure(c, c->nruns, (size_t)n * sizeof(int32_t)))) return st;
-  if ((st = ensure(c, c->spill, (size_t)n * sizeof(int32_t)))) return st;
-  if ((st = ensure(c, c->list2, (size_t)n * sizeof(int32_t)))) return st;
-  if ((st = ensure(c, c->list3, (size_t)n * sizeof(int32_t)))) return st;
+  if ((st = ensure(c, c->sc->scan_tmp, tmp * sizeof(int64_t)))) return st;
+  if ((st = ensure(c, c->sc->counters, C_N * sizeof(int32_t) + 64))) return st;
+  if ((st = ensure(c, c->sc->total, 64))) return st;
+  if ((st = ensure(c, c->sc->flags, (size_t)n))) return st;
+  if ((st = ensure(c, c->sc->nruns, (size_t)n * sizeof(int32_t)))) return st;
+  if ((st = ensure(c, c->sc->spill, (size_t)n * sizeof(int32_t)))) return st;
+  if ((st = ensure(c, c->sc->list2, (size_t)n * sizeof(int32_t)))) return st;
+  if ((st = ensure(c, c->sc->list3, (size_t)n * sizeof(int32_t)))) return st;
   // runs held per pair before compaction: with a threshold S an optimal
   // alignment has at most S / min(x, o + e) non-match runs, so at most twice
   // that plus one runs in all; pairs with more are re-run in place
@@ -549,8 +569,11 @@ static aim_status align_batch(aim_context *c, const aim_batch *B, int32_t alg, a
   // a multiple of 4 words, so the compaction reads slots with 16-byte loads
   const int32_t slot_cap =
       (int32_t)((std::max<int64_t>(1, std::min<int64_t>(run_bound, SLOT_CAP)) + 3) & ~int64_t(3));
-  if (R->want_cigar && (st = ensure(c, c->slot, (size_t)n * slot_cap * sizeof(uint32_t)))) return st;
-  int32_t *cnt = as<int32_t>(c->counters);
+  if (R->want_cigar && (st = ensure(c, c->sc->slot, (size_t)n * slot_cap * sizeof(uint32_t)))) return st;
+  int32_t *cnt = as<int32_t>(c->sc->counters);
+  c->last_cnt = cnt;
+  c->last_n = n;
+  c->last_window = 0;
   HIP_TRY(aim::launch_fill_i32(cnt, 0, C_N, s));
 
   // ---- input encoding ----
@@ -563,27 +586,27 @@ static aim_status align_batch(aim_context *c, const aim_batch *B, int32_t alg, a
          (const uint64_t *)B->txt_seq, B->txt_off, B->txt_len};
   } else {
     const size_t words = (size_t)n * ((L + 31) / 32) + 1;
-    if ((st = ensure(c, c->pat2, words * 8))) return st;
-    if ((st = ensure(c, c->txt2, words * 8))) return st;
-    if ((st = ensure(c, c->pat2off, (n + 1) * 8))) return st;
-    if ((st = ensure(c, c->txt2off, (n + 1) * 8))) return st;
-    if ((st = ensure(c, c->pflag, n))) return st;
-    if ((st = ensure(c, c->tflag, n))) return st;
+    if ((st = ensure(c, c->sc->pat2, words * 8))) return st;
+    if ((st = ensure(c, c->sc->txt2, words * 8))) return st;
+    if ((st = ensure(c, c->sc->pat2off, (n + 1) * 8))) return st;
+    if ((st = ensure(c, c->sc->txt2off, (n + 1) * 8))) return st;
+    if ((st = ensure(c, c->sc->pflag, n))) return st;
+    if ((st = ensure(c, c->sc->tflag, n))) return st;
     // lengths above max_len are flagged invalid below; clamp the packing bound
     // one slot of ceil(max_len / 32) words per sequence (the buffers hold n
     // of them): one launch per side, no offset scan
     HIP_TRY(aim::launch_pack_strided(n, B->enc, (const uint8_t *)B->pat_seq, B->pat_off, B->pat_len, L,
-                                     as<uint64_t>(c->pat2), (int64_t)words, as<int64_t>(c->pat2off),
-                                     as<int8_t>(c->pflag), s));
+                                     as<uint64_t>(c->sc->pat2), (int64_t)words, as<int64_t>(c->sc->pat2off),
+                                     as<int8_t>(c->sc->pflag), s));
     HIP_TRY(aim::launch_pack_strided(n, B->enc, (const uint8_t *)B->txt_seq, B->txt_off, B->txt_len, L,
-                                     as<uint64_t>(c->txt2), (int64_t)words, as<int64_t>(c->txt2off),
-                                     as<int8_t>(c->tflag), s));
-    S = {as<uint64_t>(c->pat2), as<int64_t>(c->pat2off), B->pat_len,
-         as<uint64_t>(c->txt2), as<int64_t>(c->txt2off), B->txt_len};
-    pf = as<int8_t>(c->pflag);
-    tf = as<int8_t>(c->tflag);
+                                     as<uint64_t>(c->sc->txt2), (int64_t)words, as<int64_t>(c->sc->txt2off),
+                                     as<int8_t>(c->sc->tflag), s));
+    S = {as<uint64_t>(c->sc->pat2), as<int64_t>(c->sc->pat2off), B->pat_len,
+         as<uint64_t>(c->sc->txt2), as<int64_t>(c->sc->txt2off), B->txt_len};
+    pf = as<int8_t>(c->sc->pflag);
+    tf = as<int8_t>(c->sc->tflag);
   }
-  HIP_TRY(aim::launch_pair_flags(n, L, B->pat_len, B->txt_len, pf, tf, as<int8_t>(c->flags), s));
+  HIP_TRY(aim::launch_pair_flags(n, L, B->pat_len, B->txt_len, pf, tf, as<int8_t>(c->sc->flags), s));
   }
 
   // pool for runs beyond the per-pair slot (reset every call)
@@ -591,28 +614,28 @@ static aim_status align_batch(aim_context *c, const aim_batch *B, int32_t alg, a
   // between 4 MiB and 1/64 of the scratch budget; exhaustion falls back to
   // the exact in-place re-run
   const int64_t pool_cap =
-      R->want_cigar ? std::max<int64_t>(1 << 20, std::min<int64_t>(c->opt.scratch_limit / 64 / 4,
+      R->want_cigar ? std::max<int64_t>(1 << 20, std::min<int64_t>(c->limit() / 64 / 4,
                                                                    n * std::min<int64_t>(2 * (int64_t)L + 1, 1024) / 4))
                     : 1;
-  if ((st = ensure(c, c->pool, (size_t)pool_cap * 4))) return st;
-  if ((st = ensure(c, c->pooloff, (size_t)n * 8))) return st;
-  HIP_TRY(aim::launch_fill_i32(as<int32_t>(c->total) + 2, 0, 2, s));
+  if ((st = ensure(c, c->sc->pool, (size_t)pool_cap * 4))) return st;
+  if ((st = ensure(c, c->sc->pooloff, (size_t)n * 8))) return st;
+  HIP_TRY(aim::launch_fill_i32(as<int32_t>(c->sc->total) + 2, 0, 2, s));
   // a2: length buckets, longest first (LPT order for the persistent queues)
   const Tune tu = tune_for(c, alg, L);
   const bool do_sort = tu.sort >= 0 ? tu.sort != 0 : (alg == AIM_WFA_AFFINE || L >= 512);
   const int32_t *order = nullptr;
   if (do_sort && c->opt.kernel != AIM_KERNEL_PLAIN) {
-    if ((st = ensure(c, c->order, (size_t)n * 4))) return st;
-    if ((st = ensure(c, c->hist, aim::LEN_BUCKETS * 4))) return st;
+    if ((st = ensure(c, c->sc->order, (size_t)n * 4))) return st;
+    if ((st = ensure(c, c->sc->hist, aim::LEN_BUCKETS * 4))) return st;
     Phase ph(c, s, "sort");
-    HIP_TRY(aim::launch_length_sort(n, B->pat_len, B->txt_len, as<int32_t>(c->hist),
-                                    as<int32_t>(c->order), s));
-    order = as<int32_t>(c->order);
+    HIP_TRY(aim::launch_length_sort(n, B->pat_len, B->txt_len, as<int32_t>(c->sc->hist),
+                                    as<int32_t>(c->sc->order), s));
+    order = as<int32_t>(c->sc->order);
   }
-  aim::Outs O{R->score, R->status, as<int32_t>(c->nruns), as<uint32_t>(c->slot), slot_cap,
-              as<int8_t>(c->flags), R->cigar, R->cigar_off, R->cigar_cap, as<uint32_t>(c->pool),
-              pool_cap, (unsigned long long *)(as<int64_t>(c->total) + 1), as<int64_t>(c->pooloff)};
-  const int64_t budget = c->opt.scratch_limit / 4;
+  aim::Outs O{R->score, R->status, as<int32_t>(c->sc->nruns), as<uint32_t>(c->sc->slot), slot_cap,
+              as<int8_t>(c->sc->flags), R->cigar, R->cigar_off, R->cigar_cap, as<uint32_t>(c->sc->pool),
+              pool_cap, (unsigned long long *)(as<int64_t>(c->sc->total) + 1), as<int64_t>(c->sc->pooloff)};
+  const int64_t budget = c->limit() / 4;
   const bool plain = c->opt.kernel == AIM_KERNEL_PLAIN;
 
   auto run_full = [&](const aim::Work &Wk, int64_t max_items, hipStream_t s) -> aim_status {
@@ -620,10 +643,10 @@ static aim_status align_batch(aim_context *c, const aim_batch *B, int32_t alg, a
     int64_t slots = std::min<int64_t>(max_items, (int64_t)c->cus * 8);
     slots = std::min<int64_t>(slots, std::max<int64_t>(1, budget / (sw * 4)));
     slots = std::max<int64_t>(slots, 1);
-    aim_status e = ensure(c, c->full, (size_t)(slots * sw * 4));
+    aim_status e = ensure(c, c->sc->full, (size_t)(slots * sw * 4));
     if (e) return e;
     Phase ph(c, s, Wk.direct ? "full_rerun" : "full");
-    HIP_TRY(aim::launch_full(affine, S, O, P, Wk, as<uint32_t>(c->full), sw, L, (int32_t)slots, s));
+    HIP_TRY(aim::launch_full(affine, S, O, P, Wk, as<uint32_t>(c->sc->full), sw, L, (int32_t)slots, s));
     return AIM_OK;
   };
 
@@ -640,7 +663,7 @@ static aim_status align_batch(aim_context *c, const aim_batch *B, int32_t alg, a
     // 32 diagonals in packed 16-bit arithmetic (two pairs per lane) when the
     // value bound allows, else 32-bit
     const bool b16 = w0 == 32 && tu.band16 && aim::band16_fits(L, P, affine);
-    Buf &tbA = w0 == 32 ? c->tb32 : c->tb64;
+    Buf &tbA = w0 == 32 ? c->sc->tb32 : c->sc->tb64;
     const int64_t swA = aim::band_tb_slot_words(b16 ? 64 : w0, affine, rows_cap);
     const int64_t chunksA = b16 ? (n + 127) / 128 : chunks;
     int64_t slots = std::min<int64_t>(chunksA, (int64_t)c->cus * std::max(1, tu.band_wpc));
@@ -651,7 +674,7 @@ static aim_status align_batch(aim_context *c, const aim_batch *B, int32_t alg, a
     const bool split = b16 && (tu.band16 == 2 || (tu.band16 == 3 && n >= SPLIT_MIN_PAIRS)) &&
                        R->want_cigar && chunksA * swA * 4 <= budget;
     if ((st = ensure(c, tbA, (size_t)((split ? chunksA : slots) * swA * 4)))) return st;
-    aim::Work W1{order, nullptr, n, cnt + C_T1, as<int32_t>(c->list2), cnt + C_L2, 0};
+    aim::Work W1{order, nullptr, n, cnt + C_T1, as<int32_t>(c->sc->list2), cnt + C_L2, 0};
     {
       Phase ph(c, s, b16 ? "band16" : (w0 == 32 ? "band32" : "band64"));
       if (b16)
@@ -670,7 +693,7 @@ static aim_status align_batch(aim_context *c, const aim_batch *B, int32_t alg, a
       HIP_TRY(hipEventRecord(c->ev_fork, s));
       HIP_TRY(hipStreamWaitEvent(s2, c->ev_fork, 0));
     }
-    int32_t *full_list = as<int32_t>(c->list2);
+    int32_t *full_list = as<int32_t>(c->sc->list2);
     int32_t *full_count = cnt + C_L2;
     if (w0 == 32) {
       // tier 2: 64-diagonal band for the pairs tier 1 could not decide, one
@@ -680,21 +703,21 @@ static aim_status align_batch(aim_context *c, const aim_batch *B, int32_t alg, a
       int64_t cap2 = std::min<int64_t>(need, std::max<int64_t>(1024, ((int64_t)512 << 20) / (cw * 4)));
       cap2 = std::max<int64_t>(1, std::min<int64_t>(cap2, budget / (cw * 4)));
       if (!R->want_cigar) cap2 = 1;
-      if ((st = ensure(c, c->tb64, (size_t)(cap2 * cw * 4)))) return st;
-      aim::Work W2{as<int32_t>(c->list2), cnt + C_L2, n, cnt + C_T2, as<int32_t>(c->list3),
+      if ((st = ensure(c, c->sc->tb64, (size_t)(cap2 * cw * 4)))) return st;
+      aim::Work W2{as<int32_t>(c->sc->list2), cnt + C_L2, n, cnt + C_T2, as<int32_t>(c->sc->list3),
                    cnt + C_L3, 0};
       {
         Phase ph2(c, s, "diag");
-        HIP_TRY(aim::launch_diag(affine, S, O, P, W2, as<uint32_t>(c->tb64), cw, cap2,
+        HIP_TRY(aim::launch_diag(affine, S, O, P, W2, as<uint32_t>(c->sc->tb64), cw, cap2,
                                  (int32_t)std::min<int64_t>(need, (int64_t)c->cus * 16), s));
       }
       if (R->want_cigar) {
-        aim::Work W2t{as<int32_t>(c->list2), cnt + C_L2, n, cnt + C_DTB, nullptr, nullptr, 0};
+        aim::Work W2t{as<int32_t>(c->sc->list2), cnt + C_L2, n, cnt + C_DTB, nullptr, nullptr, 0};
         Phase ph2(c, s, "diag_tb");
-        HIP_TRY(aim::launch_diag_tb(affine, S, O, W2t, as<uint32_t>(c->tb64), cw,
+        HIP_TRY(aim::launch_diag_tb(affine, S, O, W2t, as<uint32_t>(c->sc->tb64), cw,
                                     (int32_t)std::min<int64_t>((n + 15) / 16, (int64_t)c->cus * 8), s));
       }
-      full_list = as<int32_t>(c->list3);
+      full_list = as<int32_t>(c->sc->list3);
       full_count = cnt + C_L3;
     }
     if (split) {
@@ -731,26 +754,26 @@ static aim_status align_batch(aim_context *c, const aim_batch *B, int32_t alg, a
   }
   {
   Phase ph(c, s, "compact");
-  HIP_TRY(aim::launch_compact(n, O, R->cigar_off, R->cigar, R->cigar_cap, as<int64_t>(c->scan_tmp),
-                              as<int64_t>(c->total), as<int32_t>(c->spill), cnt + C_SPILL,
+  HIP_TRY(aim::launch_compact(n, O, R->cigar_off, R->cigar, R->cigar_cap, as<int64_t>(c->sc->scan_tmp),
+                              as<int64_t>(c->sc->total), as<int32_t>(c->sc->spill), cnt + C_SPILL,
                               R->status, s));
   }
   // pairs whose runs exceeded the slot: recompute and write in place
-  aim::Work WS{as<int32_t>(c->spill), cnt + C_SPILL, n, cnt + C_SPILL_W, nullptr, nullptr, 1};
+  aim::Work WS{as<int32_t>(c->sc->spill), cnt + C_SPILL, n, cnt + C_SPILL_W, nullptr, nullptr, 1};
   if (alg == AIM_WFA_AFFINE) {
     const aim::Scoring PW = wfa_scoring(P);
-    aim::WfaPlan pl = aim::wfa_plan(L, PW, c->opt.scratch_limit, c->cus, plain, tu.wfa_ring_kb,
+    aim::WfaPlan pl = aim::wfa_plan(L, PW, c->limit(), c->cus, plain, tu.wfa_ring_kb,
                                     tu.wfa_trace_kb, tu.wfa_long_threads);
     aim::WfaLaunch WL{};
     WL.R = pl.R;
     WL.seq_words = pl.seq_words;
     WL.full_in_lds = 0;
     WL.slot_words = pl.need_cap[3];
-    WL.need = as<int64_t>(c->wneed);
-    if ((st = ensure(c, c->warena3, (size_t)pl.pool_words[3] * 4))) return st;
+    WL.need = as<int64_t>(c->sc->wneed);
+    if ((st = ensure(c, c->sc->warena3, (size_t)pl.pool_words[3] * 4))) return st;
     const int32_t rslots = (int32_t)std::max<int64_t>(1, pl.pool_words[3] / pl.need_cap[3]);
     Phase ph(c, s, "wfa_rerun");
-    HIP_TRY(aim::launch_wfa_trace(S, O, PW, WS, WL, as<int32_t>(c->warena3), rslots,
+    HIP_TRY(aim::launch_wfa_trace(S, O, PW, WS, WL, as<int32_t>(c->sc->warena3), rslots,
                                   pl.threads[3], L <= aim::WFA16_MAX_LEN && !plain, s));
   } else {
     if ((st = run_full(WS, n, s))) return st;
@@ -773,6 +796,27 @@ aim_status aim_align_batch(aim_context *c, const aim_batch *B, int32_t alg, aim_
   c->has_done = true;
   c->done_stream = s;
   return st;
+}
+
+aim_status aim_last_call_stats(aim_context *c, aim_call_stats *out) {
+  g_err.clear();
+  if (!c || !out) return fail(AIM_ERR_INVALID_ARG, "NULL argument");
+  memset(out, 0, sizeof *out);
+  if (!c->has_done || !c->last_cnt) return AIM_OK;
+  DeviceGuard g(c->device);
+  HIP_TRY(hipEventSynchronize(c->ev_done));
+  int32_t v[C_N];
+  HIP_TRY(hipMemcpy(v, c->last_cnt, sizeof v, hipMemcpyDeviceToHost));
+  out->n_pairs = c->last_n;
+  out->band_escalated = v[C_L2];
+  out->band_escalated2 = v[C_L3];
+  out->wfa_wide = v[C_RL];
+  out->wfa_walk_failed = v[C_WF];
+  out->wfa_walk_skipped = v[C_WS];
+  for (int k = 0; k < 4; ++k) out->full_store[k] = v[C_N0 + k];
+  out->cigar_reruns = v[C_SPILL];
+  out->wfa_window = c->last_window;
+  return AIM_OK;
 }
 
 }  // extern "C"
@@ -977,8 +1021,17 @@ aim_status aim_graph_launch(aim_graph *gr, void *stream) {
   if (!gr) return fail(AIM_ERR_INVALID_ARG, "NULL graph");
   if (gr->c->generation != gr->generation)
     return fail(AIM_ERR_INVALID_ARG, "the context's scratch was reallocated since capture; capture again");
-  DeviceGuard g(gr->c->device);
-  HIP_TRY(hipGraphLaunch(gr->exec, (hipStream_t)stream));
+  aim_context *c = gr->c;
+  DeviceGuard g(c->device);
+  hipStream_t s = (hipStream_t)stream;
+  // the same ordering as aim_align_batch: a replay shares the context's
+  // scratch with its eager calls, so it waits for the last of them (or of
+  // the replays) issued on another stream, and the next call waits for it
+  if (c->has_done && c->done_stream != s) HIP_TRY(hipStreamWaitEvent(s, c->ev_done, 0));
+  HIP_TRY(hipGraphLaunch(gr->exec, s));
+  HIP_TRY(hipEventRecord(c->ev_done, s));
+  c->has_done = true;
+  c->done_stream = s;
   return AIM_OK;
 }
 

@@ -303,7 +303,7 @@ aim_status aim_server_create(int32_t device, const aim_server_options *opt, aim_
   s_err.clear();
   if (!out) return sfail(AIM_ERR_INVALID_ARG, "srv is NULL");
   *out = nullptr;
-  aim_server_options o{4, 0, (int64_t)64 << 30, (int64_t)1 << 20};
+  aim_server_options o{4, 0, (int64_t)64 << 30, (int64_t)1 << 16};
   if (opt) {
     o = *opt;
     if (o.n_streams == 0) o.n_streams = 4;

@@ -566,7 +566,11 @@ void k_wfa_score(Seqs S, Outs O, Scoring P, Work Wk, WfaLaunch L, int32_t *hbm) 
       }
     }
     if (result == 1 && keep) {
-      __syncthreads();  // the codes and table of every wave visible to the walk
+      // the codes and table of every wave visible to the walk: the barrier
+      // orders the stores, the agent-scope acquire drops L1 lines an earlier
+      // pair's walk may have left at these addresses
+      __syncthreads();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       if (threadIdx.x < 64) {
         const int32_t sfin = s;
         auto code_at = [&](int32_t cs, int32_t k) -> int32_t {  // per lane
@@ -578,8 +582,11 @@ void k_wfa_score(Seqs S, Outs O, Scoring P, Work Wk, WfaLaunch L, int32_t *hbm) 
         };
         auto ext = [&](int32_t k, int32_t f) { return q.ext(m, n, k, f); };
         walked = walk_codes<true>(O, p, code_at, ext, x, oe, e, m, n, s, wtok, L.walk_tok);
+        if (!walked && threadIdx.x == 0 && L.walk_fail) atomicAdd(L.walk_fail, 1);
       }
       __syncthreads();
+    } else if (result == 1 && P.want_cigar && lane == 0 && L.walk_skip) {
+      atomicAdd(L.walk_skip, 1);  // codes not kept: the full-store pass walks it
     }
     };
     if (staged)
@@ -803,7 +810,13 @@ __global__ __launch_bounds__(64) void k_wfa_score16(Seqs S, Outs O, Scoring P, W
     }
     bool walked = false;
     if (result == 1 && s < bits_steps) {
-      __syncthreads();  // the origin codes stored by every lane, visible to the walk
+      // The codes were stored by this wavefront's lanes; the walk reads them
+      // back, among addresses whose earlier contents (an earlier pair's
+      // codes) this workgroup's loads may have left in the CU's vector L1.
+      // The barrier orders the stores before the loads; the agent-scope
+      // acquire invalidates the L1 so that no load hits such a line.
+      __syncthreads();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       const int32_t sfin = s;
       auto code_at = [&](int32_t cs, int32_t k) -> int32_t {  // per lane
         const int32_t idx = k - kbase;
@@ -814,6 +827,9 @@ __global__ __launch_bounds__(64) void k_wfa_score16(Seqs S, Outs O, Scoring P, W
       auto ext = [&](int32_t k, int32_t f) { return extend_lds(P32, m, T32, n, k, f); };
       walked = walk_codes<false>(O, p, code_at, ext, x, oe, e, m, n, s, reinterpret_cast<uint32_t *>(rM),
                           (R + 2 * RE) * WS / 2);
+      if (!walked && lane == 0 && L.walk_fail) atomicAdd(L.walk_fail, 1);
+    } else if (result == 1 && P.want_cigar && lane == 0 && L.walk_skip) {
+      atomicAdd(L.walk_skip, 1);  // codes not kept: the full-store pass walks it
     }
     if (result == 3) {
       wave_append1(true, (int32_t)p, L.ring_list, L.ring_count);
