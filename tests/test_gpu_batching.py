@@ -166,3 +166,86 @@ def test_wfa_mixed_sample():
     for i in rng.choice(longi, size=min(40, len(longi)), replace=False):
         r = oracle.wfa_pair(b.pattern(i), b.text(i), w["pen"])
         assert (st[i], s[i]) == (r[0], r[1]) and cg[off[i]:off[i + 1]].tolist() == r[2], i
+
+
+def _capture(ctx, b, w, stream):
+    dev, enc = to_device(b, w["enc"])
+    outs = _outputs(b)
+    max_len = int(max(b.pat_len.max(), b.txt_len.max()))
+    g = ctx.graph_capture(*dev, enc=enc, max_len=max_len, alg=w["alg"], pen=w["pen"],
+                          max_score=w["max_score"], score=outs[0], status=outs[1], cigar=outs[2],
+                          cigar_off=outs[3], stream=stream)
+    return g, dev, outs, max_len, enc
+
+
+@pytest.mark.parametrize("name,n", [("swg150", 70_000), ("wfa250", 20_000), ("wfa_mixed", 3000)])
+def test_graph_replays_large_and_wfa(name, n):
+    # swg150 at 70,000 pairs takes the two-stream path (the first tier's walk
+    # on the context's second stream beside the escalation tiers), which the
+    # capture must record as graph dependencies; the WFA batches capture the
+    # wavefront passes and their fallbacks.  Every replay, with eager work
+    # between them, must reproduce the eager call.
+    w = dict(synth.WORKLOADS[name])
+    b = synth.workload(name, n=n)
+    print("graph replays: %s, %d pairs" % (name, n), flush=True)
+    stream = torch.cuda.Stream()
+    with aim.Context(0) as ctx, torch.cuda.stream(stream):
+        g, dev, outs, max_len, enc = _capture(ctx, b, w, stream)
+        want = _host(outs)
+        idx = np.arange(0, n, max(1, n // 300))
+        sub = b.subset(idx)
+        ws, wst, wc, wo = oracle.align_batch(sub, w["alg"], w["pen"], w["max_score"])
+        s, st, cg, off = want
+        for t, i in enumerate(idx):
+            assert (s[i], st[i]) == (ws[t], wst[t]) and np.array_equal(cg[off[i]:off[i + 1]], wc[wo[t]:wo[t + 1]])
+        for rep in range(3):
+            for t in outs:
+                t.zero_()
+            stream.synchronize()
+            g.launch(stream)
+            got = _host(outs)
+            assert all(np.array_equal(u, v) for u, v in zip(got, want)), rep
+        g.close()
+
+
+def test_graph_replay_on_another_stream_between_eager_calls():
+    # a replay shares the context's scratch with its eager calls: replays on a
+    # second stream interleaved with eager calls on the first (no host sync
+    # between them) must each give the eager results
+    w = synth.WORKLOADS["swg150"]
+    b = synth.workload("swg150", n=70_000)
+    b2 = synth.workload("swg150", start=70_000, n=90_000)  # larger: the eager call grows scratch
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    with aim.Context(0) as ctx:
+        with torch.cuda.stream(s1):
+            g, dev, outs, max_len, enc = _capture(ctx, b, w, s1)
+        want = _host(outs)
+        want2 = oracle.align_batch(b2.subset(np.arange(0, b2.n, 300)), w["alg"], w["pen"], w["max_score"])
+        outs2 = _outputs(b2)
+        dev2, _ = to_device(b2, w["enc"])
+        max_len2 = int(max(b2.pat_len.max(), b2.txt_len.max()))
+        for rep in range(2):
+            for t in outs:
+                t.zero_()
+            torch.cuda.synchronize()
+            g.launch(s2)  # replay on s2
+            # eager call on s1 right behind it (same context): must wait for the replay
+            ctx.align_batch(*dev2, enc=enc, max_len=max_len2, alg=w["alg"], pen=w["pen"], max_score=w["max_score"],
+                            score=outs2[0], status=outs2[1], cigar=outs2[2], cigar_off=outs2[3], stream=s1)
+            torch.cuda.synchronize()
+            got = _host(outs)
+            assert all(np.array_equal(u, v) for u, v in zip(got, want)), rep
+            g2 = _host(outs2)
+            idx = np.arange(0, b2.n, 300)
+            s, st, cg, off = g2
+            ws, wst, wc, wo = want2
+            for t, i in enumerate(idx):
+                assert (s[i], st[i]) == (ws[t], wst[t]) and np.array_equal(cg[off[i]:off[i + 1]], wc[wo[t]:wo[t + 1]])
+            if rep == 0:
+                # the eager call grew the scratch: the graph is refused until captured again
+                with pytest.raises(aim.AimError):
+                    g.launch(s2)
+                g.close()
+                with torch.cuda.stream(s1):
+                    g, dev, outs, max_len, enc = _capture(ctx, b, w, s1)
+        g.close()

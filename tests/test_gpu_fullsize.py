@@ -42,8 +42,12 @@ def vector_invariants(batch, score, status, cigar, off, pen):
 def test_full_workload(name, sample):
     w = synth.WORKLOADS[name]
     b = synth.workload(name)
+    print("full workload %s: %d pairs" % (name, b.n), flush=True)
     with aim.Context(0) as ctx:
         s, st, cg, off = run(ctx, b, w["alg"], w["pen"], w["max_score"], enc=w["enc"])
+        stats = ctx.last_call_stats()
+    # a fused walk over kept origin codes never fails
+    assert stats["wfa_walk_failed"] == 0, stats
     assert (st != aim.PAIR_INVALID).all() and (st != aim.PAIR_CIGAR_OVERFLOW).all()
     vector_invariants(b, s, st, cg, off, w["pen"])
     rng = np.random.default_rng(99)
@@ -67,3 +71,41 @@ def test_repeat_calls_swg150():
     for s, st, cg, off in (first, second):
         vector_invariants(b, s, st, cg, off, w["pen"])
     assert all(np.array_equal(u, v) for u, v in zip(first, second))
+
+
+def test_full_wfa_mixed():
+    # The batching-form workload in the call bench.py times: all 500,000 pairs
+    # (100 bp - 10 kbp, 0.5 - 10 %) in one call.  Every pair is checked by the
+    # vectorised invariants; a seeded sample spread over the whole index range
+    # is compared bit for bit: pairs up to 2,500 bp with the full-matrix
+    # oracle, longer ones with the scalar wavefront oracle.
+    from concurrent.futures import ThreadPoolExecutor
+    w = synth.WORKLOADS["wfa_mixed"]
+    b = synth.workload("wfa_mixed")
+    print("full workload wfa_mixed: %d pairs" % b.n, flush=True)
+    with aim.Context(0) as ctx:
+        s, st, cg, off = run(ctx, b, "wfa", w["pen"], w["max_score"])
+        stats = ctx.last_call_stats()
+    print("path counters", stats, flush=True)
+    assert stats["wfa_walk_failed"] == 0, stats
+    assert (st == aim.PAIR_ALIGNED).all()
+    vector_invariants(b, s, st, cg, off, w["pen"])
+    rng = np.random.default_rng(2024)
+    L = np.maximum(b.pat_len, b.txt_len)
+    short = np.nonzero(L <= 2500)[0]
+    longi = np.nonzero(L > 2500)[0]
+    idx_s = np.sort(rng.choice(short, size=400, replace=False))
+    idx_l = np.sort(rng.choice(longi, size=60, replace=False))
+    sub = b.subset(idx_s)
+    ws, wst, wc, wo = oracle.align_batch(sub, "wfa", w["pen"], -1)
+    for t, i in enumerate(idx_s):
+        assert (s[i], st[i]) == (ws[t], wst[t]), i
+        assert np.array_equal(cg[off[i]:off[i + 1]], wc[wo[t]:wo[t + 1]]), i
+
+    def one(i):
+        return oracle.wfa_pair(b.pattern(i), b.text(i), w["pen"])
+
+    with ThreadPoolExecutor(8) as ex:
+        res = list(ex.map(one, idx_l))
+    for i, r in zip(idx_l, res):
+        assert (st[i], s[i]) == (r[0], r[1]) and cg[off[i]:off[i + 1]].tolist() == r[2], i

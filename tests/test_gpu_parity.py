@@ -236,3 +236,49 @@ def test_long_reads(ctx, seed):
     b = _mixed_batch(30 + seed, 60, 500, 1500, [0.01, 0.05])
     check(ctx, b, "swg", SWG)
     check(ctx, b, "nw", NW)
+
+
+@pytest.mark.parametrize("enc", ["ascii", "code"])
+def test_pack_2bit_entry_point(ctx, enc):
+    # aim_pack_2bit against the host packer: compact word-aligned CSR, flags
+    # for bytes outside the alphabet, a capacity that cuts the last sequences
+    rng = np.random.default_rng(17)
+    lens = np.concatenate([[0, 1, 31, 32, 33, 64, 65], rng.integers(0, 700, 2000)]).astype(np.int64)
+    off = np.zeros(len(lens) + 1, np.int64)
+    off[1:] = np.cumsum(lens)
+    codes = rng.integers(0, 4, int(off[-1])).astype(np.uint8)
+    data = synth.ascii_from_codes(codes) if enc == "ascii" else codes.copy()
+    bad = [5, 100, 1500]
+    for i in bad:
+        if lens[i]:
+            data[off[i] + lens[i] // 2] = ord("N") if enc == "ascii" else 7
+    words, woff = synth.pack_2bit(codes, off)
+    d_seq = torch.from_numpy(data).cuda()
+    d_off = torch.from_numpy(off[:-1].copy()).cuda()
+    d_len = torch.from_numpy(lens.astype(np.int32)).cuda()
+    out = torch.zeros(len(words) + 4, dtype=torch.int64, device="cuda")
+    out_off = torch.zeros(len(lens) + 1, dtype=torch.int64, device="cuda")
+    flags = torch.zeros(len(lens), dtype=torch.int8, device="cuda")
+    e = aim.ENC_ASCII if enc == "ascii" else aim.ENC_CODE
+    ctx.pack_2bit(e, d_seq, d_off, d_len, out, out_off, flags)
+    torch.cuda.synchronize()
+    assert np.array_equal(out_off.cpu().numpy(), woff)
+    f = flags.cpu().numpy()
+    want_flags = np.zeros(len(lens), np.int8)
+    want_flags[[i for i in bad if lens[i]]] = 1
+    assert np.array_equal(f != 0, want_flags != 0)
+    got = out.cpu().numpy().view(np.uint64)[:len(words)]
+    ok = np.repeat(f == 0, np.diff(woff))
+    assert np.array_equal(got[ok], words[ok])
+    # capacity: only the words below words_cap are written, the rest are flagged
+    cap = int(woff[1000])
+    out2 = torch.zeros(cap, dtype=torch.int64, device="cuda")
+    flags2 = torch.zeros(len(lens), dtype=torch.int8, device="cuda")
+    ctx.pack_2bit(e, d_seq, d_off, d_len, out2, out_off, flags2)
+    torch.cuda.synchronize()
+    f2 = flags2.cpu().numpy()
+    cut = np.nonzero((woff[1:] > cap) & (np.diff(woff) > 0))[0]  # empty sequences write nothing
+    assert (f2[cut] != 0).all() and (f2[:1000][want_flags[:1000] == 0] == 0).all()
+    got2 = out2.cpu().numpy().view(np.uint64)
+    ok2 = np.repeat((f2 == 0)[:1000], np.diff(woff)[:1000])
+    assert np.array_equal(got2[:int(woff[1000])][ok2], words[:int(woff[1000])][ok2])

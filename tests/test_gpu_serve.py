@@ -93,3 +93,25 @@ def test_concurrent_submitters():
             t.join()
         for (alg, pen, smax, b), i in zip(reqs, ids):
             assert not compare(srv.wait(i)[:4], oracle.align_batch(b, alg, pen, smax))
+
+
+def test_schedule_distribution_mix_alone_and_oracle():
+    # The serving schedule's own request distribution (1-4096 pairs, 100-1000
+    # bp, 1-8 %, NW / SWG / WFA): the requests arriving in its first 0.25 s,
+    # submitted together (the mix), then every one of them again alone; a
+    # seeded 1 % of them (at least 5) is also checked against the oracle.
+    import serve_replay
+    sched = [r for r in synth.serving_schedule() if r.t_arrival < 0.25]
+    batches = [serve_replay.request_pairs(synth, r) for r in sched]
+    print("schedule check: %d requests, %d pairs" % (len(sched), sum(b.n for b in batches)), flush=True)
+    with aim.Server(0, n_streams=4) as srv:
+        ids = [serve_replay.submit(srv, r, b) for r, b in zip(sched, batches)]
+        mix = [srv.wait(i)[:4] for i in ids]
+        for k, (r, b) in enumerate(zip(sched, batches)):
+            alone = srv.wait(serve_replay.submit(srv, r, b))[:4]
+            assert not compare(mix[k], alone), k
+    rng = np.random.default_rng(55)
+    pick = rng.choice(len(sched), size=max(5, len(sched) // 100), replace=False)
+    for k in pick:
+        r, b = sched[k], batches[k]
+        assert not compare(mix[k], oracle.align_batch(b, r.alg, r.pen, -1)), k
