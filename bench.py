@@ -1,23 +1,36 @@
 """Benchmark: batched pairwise alignment throughput on one MI355X.
 
-Default workload (the configuration the headline metric is quoted on):
-Gotoh/SWG global alignment with penalties 4/6/2, 1,000,000 pairs of 150 bp
-reads at 4 % error (1/3 each substitution, insertion, deletion), 2-bit packed
-input, int32 scores and CIGARs.  One step = one aim_align_batch call over the
-whole batch (input encoding, band tiers with exactness certificate, full-matrix
-fallback, traceback, CIGAR compaction), inputs already resident in HBM.
+Default workload (the largest single-GPU configuration): gap-affine WFA with
+penalties 4/6/2, 500,000 pairs with read lengths log-uniform in
+[100, 10,000] bp and error rates uniform in [0.5 %, 10 %], 2-bit packed
+input, int32 scores and CIGARs, no threshold.  One step = one
+aim_align_batch call over the whole batch (validation, length sort, the
+wavefront passes with their fused CIGAR walks, the full-store fallback,
+CIGAR compaction), inputs already resident in HBM.
 
-Prints ONE JSON line.  Roofline: the dominant kernel is the 32-diagonal band
-kernel; its duration comes from HIP events recorded on the launch stream around
-every launch during the timed steps.  The CPU baseline is the oracle on a
-bounded sample of the same workload.
+Prints ONE JSON line.  Besides the headline it carries:
+  roofline      -- the dominant kernel's algorithmic integer ops per launch
+                   (wavefront cells x 8 + 32-base extension words x 10, the
+                   cells of the pairs that launch completes, from
+                   tests/golden/wfa_work.json) over its average launch time,
+                   measured with HIP events on its launch stream;
+  plain_kernel  -- the same pairs through the plain one-pair-per-workgroup
+                   kernel (identical results are asserted);
+  end_to_end    -- the rate with the host<->device transfers included;
+  cpu_baseline  -- the oracle, built -O3 -march=native on this host, on a
+                   bounded sample, on all granted cores and on one core;
+  other_configs -- the NW edit (10k x 100 bp), SWG (1M x 150 bp) and WFA
+                   (1M x 250 bp with 20 % unrelated pairs) workloads;
+  serving       -- the Poisson request schedule through aim_server.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -27,16 +40,18 @@ sys.path.insert(0, ROOT)
 
 PEAK_INT32_TOPS = 256 * 64 * 2.4e9 / 1e12  # 256 CUs x 64 lanes x 2.4 GHz = 39.3 T int32 ops/s
 PEAK_PK16_TOPS = 2 * PEAK_INT32_TOPS       # packed 16-bit: two halves per lane = 78.6 T ops/s
-HBM_PEAK_GBS = 8000.0
-# algorithmic integer ops per DP cell (fill recurrences + traceback code):
-# Gotoh: E 3, F 3, H 3 (diag add, two mins), 4 traceback bits 4 -> 13 (+1 for the
-# mismatch test) = 14; linear NW: 2 adds + 2 mins + diag add + 2 bits + test = 10
-OPS_PER_CELL = {"swg": 14, "nw": 10, "wfa": 14}
-# HBM bytes per launch of the dominant kernel from two rocprofv3 --pmc passes
-# (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0 after the copy-kernel calibration; see
-# profiles/k_band16_swg150_hbm_counters.md), valid only for the kernel source
-# they were taken on (first 16 hex of its SHA-256).
+# algorithmic integer ops per unit: a DP cell (fill recurrences + traceback
+# code; Gotoh 14, linear NW 10), a wavefront cell (I, D, X candidates with
+# their bounds, the max of M: 8) and a 32-base extension word (load, align,
+# xor, count trailing zeros, advance: 10)
+OPS_PER_CELL = {"swg": 14, "nw": 10}
+WFA_OPS_PER_CELL, WFA_OPS_PER_WORD = 8, 10
+# HBM bytes per launch of a kernel from two rocprofv3 --pmc passes (FETCH_SIZE
+# and WRITE_SIZE scaled by a copy-kernel calibration), valid only for the
+# kernel source they were taken on (first 16 hex of its SHA-256)
 MEASURED_TRAFFIC = {("swg150", "k_band16<32>"): ("32a97daf6917c56a", 3.0790e9)}
+KERNEL_SOURCE = {"k_band16<32>": "dp_band16.hip", "k_band<32>": "dp_band.hip",
+                 "k_wfa_score16": "wfa.hip", "k_wfa_score": "wfa.hip"}
 
 WORKLOAD_TEXT = {
     "swg150": "Gotoh 4/6/2 global, 1,000,000 pairs x 150 bp, 4% error (1/3 sub, ins, del), "
@@ -45,7 +60,8 @@ WORKLOAD_TEXT = {
              "int32 score + CIGAR",
     "wfa250": "WFA 4/6/2, 1,000,000 pairs x 250 bp, 80% at 5% error + 20% unrelated, "
               "threshold 200, 2-bit, score + CIGAR",
-    "wfa_mixed": "WFA 4/6/2, 500,000 pairs, 100-10,000 bp log-uniform, 0.5-10% error, 2-bit",
+    "wfa_mixed": "WFA 4/6/2, 500,000 pairs, 100-10,000 bp log-uniform, 0.5-10% error, 2-bit, "
+                 "score + CIGAR",
 }
 
 
@@ -53,24 +69,260 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def src_hash(kernel):
+    src = open(os.path.join(ROOT, "paper_2208_01243_amd", "csrc", KERNEL_SOURCE[kernel]), "rb").read()
+    return hashlib.sha256(src).hexdigest()[:16]
+
+
+def wfa_units(name, window):
+    """(cells, words) of the pairs the one-wavefront pass completes (extent <=
+    window / 2) and of the rest, from the oracle's counts; None if absent."""
+    path = os.path.join(ROOT, "tests", "golden", "wfa_work.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path)).get(name)
+    if not d:
+        return None
+    inside = [0, 0]
+    outside = [0, 0]
+    for ext_max, pairs, acc, cells, words in d["by_extent"]:
+        tgt = inside if (ext_max is not None and ext_max <= window // 2) else outside
+        tgt[0] += cells
+        tgt[1] += words
+    return {"inside": inside, "outside": outside, "cells": d["cells"], "words": d["words"]}
+
+
+class Run:
+    """A workload on the device with its outputs, and one aligning step."""
+
+    def __init__(self, aim, synth, name, n=None):
+        import torch
+        from gpu_util import to_device
+        self.torch = torch
+        self.name = name
+        self.w = synth.WORKLOADS[name]
+        self.n_total = n or self.w["total"]
+        t0 = time.time()
+        self.batch = synth.workload(name, n=self.n_total)
+        b = self.batch
+        self.dev, self.enc = to_device(b, self.w["enc"])
+        log("%s: generated and moved %d pairs in %.1f s" % (name, b.n, time.time() - t0))
+        self.n = b.n
+        self.max_len = int(max(b.pat_len.max(), b.txt_len.max()))
+        self.cells_matrix = float((b.pat_len.astype(np.float64) * b.txt_len).sum())
+        self.score = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        self.status = torch.empty(self.n, dtype=torch.int8, device="cuda")
+        cap = int((b.pat_len.astype(np.int64) + b.txt_len + 1).sum() // 4) + 1024
+        self.cigar = torch.empty(cap, dtype=torch.int32, device="cuda")
+        self.cigar_off = torch.empty(self.n + 1, dtype=torch.int64, device="cuda")
+
+    def step(self, ctx, stream=None):
+        w = self.w
+        ctx.align_batch(*self.dev, enc=self.enc, max_len=self.max_len, alg=w["alg"], pen=w["pen"],
+                        max_score=w["max_score"], score=self.score, status=self.status, cigar=self.cigar,
+                        cigar_off=self.cigar_off, want_cigar=True, stream=stream)
+
+    def timed(self, ctx, steps, warmup):
+        torch = self.torch
+        for k in range(warmup):
+            t1 = time.perf_counter()
+            self.step(ctx)
+            torch.cuda.synchronize()
+            log("%s warmup %d: %.1f ms" % (self.name, k, (time.perf_counter() - t1) * 1000))
+        ctx.timing_reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            self.step(ctx)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+
+def roofline(run, phases, stats, steps):
+    """Roofline of the dominant kernel (see the module docstring)."""
+    w = run.w
+    if w["alg"] in ("swg", "nw") and ("band16" in phases or "band32" in phases):
+        kname, phase, peak, unit = ("k_band16<32>", "band16", PEAK_PK16_TOPS, "Tops/s (packed int16)") \
+            if "band16" in phases else ("k_band<32>", "band32", PEAK_INT32_TOPS, "Tops/s (int32)")
+        ms, launches = phases[phase]
+        cells = float((run.batch.pat_len.astype(np.int64) * 32).sum())
+        ops = OPS_PER_CELL[w["alg"]] * cells
+        t = ms / launches / 1000.0
+        meas = MEASURED_TRAFFIC.get((run.name, kname))
+        traffic = meas[1] if (meas and meas[0] == src_hash(kname) and run.n == w["total"]) else None
+        return {"bound": "alu", "kernel": kname, "achieved": round(ops / t / 1e12, 3), "peak": round(peak, 1),
+                "unit": unit, "frac": round(ops / t / 1e12 / peak, 4), "traffic": traffic,
+                "avg_launch_ms": round(ms / launches, 4), "ops_per_unit": OPS_PER_CELL[w["alg"]],
+                "units_per_launch": cells, "unit_name": "band cells (m x 32 per pair)"}
+    if w["alg"] != "wfa":
+        return None
+    names = {"wfa_score": "k_wfa_score16", "wfa_score_hbm": "k_wfa_score"}
+    present = [k for k in names if k in phases]
+    if not present:
+        return None
+    ph = max(present, key=lambda k: phases[k][0])
+    ms, launches = phases[ph]
+    units = wfa_units(run.name, stats.get("wfa_window", 0)) if run.n == w["total"] else None
+    out = {"bound": "alu", "kernel": names[ph], "avg_launch_ms": round(ms / max(launches, 1), 4),
+           "peak": round(PEAK_INT32_TOPS, 1), "unit": "Tops/s (int32)",
+           "ops_per_unit": {"wavefront cell": WFA_OPS_PER_CELL, "extension word": WFA_OPS_PER_WORD},
+           "achieved": None, "frac": None, "traffic": None}
+    if units:
+        side = "inside" if ph == "wfa_score" else "outside"
+        cells, words = units[side]
+        ops = WFA_OPS_PER_CELL * cells + WFA_OPS_PER_WORD * words
+        t = ms / launches / 1000.0
+        out.update({"achieved": round(ops / t / 1e12, 3), "frac": round(ops / t / 1e12 / PEAK_INT32_TOPS, 4),
+                    "units_per_launch": {"cells": cells, "words": words},
+                    "unit_name": "wavefront cells of the pairs this launch completes (%s the %d-diagonal "
+                                 "window)" % (side, stats.get("wfa_window", 0))})
+        meas = MEASURED_TRAFFIC.get((run.name, names[ph]))
+        if meas and meas[0] == src_hash(names[ph]):
+            out["traffic"] = meas[1]
+        # every WFA kernel of the step together
+        tot_ms = sum(v[0] for k, v in phases.items() if k.startswith("wfa")) / steps
+        ops_all = WFA_OPS_PER_CELL * units["cells"] + WFA_OPS_PER_WORD * units["words"]
+        out["all_wfa_kernels"] = {"ms_per_step": round(tot_ms, 3), "cells": units["cells"],
+                                  "words": units["words"],
+                                  "achieved": round(ops_all / (tot_ms / 1000) / 1e12, 3),
+                                  "frac": round(ops_all / (tot_ms / 1000) / 1e12 / PEAK_INT32_TOPS, 4)}
+    return out
+
+
+def measure(aim, synth, name, steps, warmup, plain_steps=0, e2e_reps=0):
+    import torch
+    run = Run(aim, synth, name)
+    ctx = aim.Context(0, timing=True)
+    elapsed = run.timed(ctx, steps, warmup)
+    phases = ctx.timing()
+    stats = ctx.last_call_stats()
+    ms_step = elapsed * 1000.0 / steps
+    st = run.status.cpu().numpy()
+    res = {"workload": WORKLOAD_TEXT[name], "pairs": run.n, "max_len": run.max_len,
+           "pairs_per_s": round(run.n / (elapsed / steps), 1), "ms_per_step": round(ms_step, 4),
+           "aligned_pairs": int((st == 0).sum()), "rejected_pairs": int((st == 1).sum()),
+           "gcups_matrix": round(run.cells_matrix / (elapsed / steps) / 1e9, 1),
+           "phases_ms_per_step": {k: round(v[0] / steps, 4) for k, v in phases.items()},
+           "path_counters": stats}
+    log("%s: %.3f ms/step; phases %s" % (name, ms_step, res["phases_ms_per_step"]))
+    res["roofline"] = roofline(run, phases, stats, steps)
+    units = wfa_units(name, 0) if run.w["alg"] == "wfa" and run.n == run.w["total"] else None
+    if units:
+        res["wavefront_cells_per_s"] = round(units["cells"] / (elapsed / steps), 1)
+    if plain_steps > 0:
+        pctx = aim.Context(0, kernel="plain")
+        s1, st1, off1 = run.score.clone(), run.status.clone(), run.cigar_off.clone()
+        t0 = time.perf_counter()
+        run.step(pctx)
+        torch.cuda.synchronize()
+        log("%s: plain warm-up step %.1f s" % (name, time.perf_counter() - t0))
+        t0 = time.perf_counter()
+        for _ in range(plain_steps):
+            run.step(pctx)
+        torch.cuda.synchronize()
+        pel = (time.perf_counter() - t0) / plain_steps
+        assert torch.equal(s1, run.score) and torch.equal(st1, run.status) and torch.equal(off1, run.cigar_off)
+        pctx.close()
+        res["plain_kernel"] = {"pairs_per_s": round(run.n / pel, 1), "ms_per_step": round(pel * 1000, 3),
+                               "speedup_of_batched": round(pel / (elapsed / steps), 2),
+                               "identical_results": True}
+    if e2e_reps > 0:
+        res["end_to_end"] = end_to_end(run, ctx, e2e_reps)
+    ctx.close()
+    return run, res
+
+
+def end_to_end(run, ctx, reps):
+    """Host pinned inputs -> H2D -> align -> D2H of scores, statuses, offsets
+    and the CIGAR runs; median of `reps`."""
+    torch = run.torch
+    host = [t.cpu().pin_memory() for t in run.dev]
+    h_score = torch.empty(run.n, dtype=torch.int32).pin_memory()
+    h_status = torch.empty(run.n, dtype=torch.int8).pin_memory()
+    h_off = torch.empty(run.n + 1, dtype=torch.int64).pin_memory()
+    h_cig = torch.empty(run.cigar.numel(), dtype=torch.int32).pin_memory()
+    times = []
+    for _ in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for d, h in zip(run.dev, host):
+            d.copy_(h, non_blocking=True)
+        run.step(ctx)
+        h_score.copy_(run.score, non_blocking=True)
+        h_status.copy_(run.status, non_blocking=True)
+        h_off.copy_(run.cigar_off, non_blocking=True)
+        torch.cuda.synchronize()
+        k = int(h_off[-1])
+        h_cig[:k].copy_(run.cigar[:k], non_blocking=True)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    t = float(np.median(times[1:]))
+    in_b = sum(h.numel() * h.element_size() for h in host)
+    out_b = run.n * 13 + 4 * int(h_off[-1])
+    return {"pairs_per_s": round(run.n / t, 1), "ms_per_step": round(t * 1000, 3),
+            "bytes_in": in_b, "bytes_out": out_b, "reps": reps}
+
+
+def cpu_baseline(synth, name, n_all, n_one):
+    """The oracle on the first pairs of the workload: a -O3 -march=native build
+    on this host, on all granted cores (at most 16: the CPU share of one GPU
+    on the measurement boxes) and on one core; plus the scalar wavefront
+    oracle for the WFA workloads."""
+    import oracle
+    w = synth.WORKLOADS[name]
+    tmp = tempfile.mkdtemp(prefix="aim_oracle_")
+    h = oracle.bind(oracle.build(path=os.path.join(tmp, "liboracle_native.so"), native=True))
+    nproc = os.cpu_count() or 1
+    threads = max(1, min(nproc, 16))
+    out = {}
+    for label, k, th in (("all", n_all, threads), ("one", n_one, 1)):
+        sub = synth.workload(name, n=k)
+        t0 = time.perf_counter()
+        oracle.align_batch(sub, w["alg"], w["pen"], w["max_score"], nthreads=th, handle=h)
+        ct = time.perf_counter() - t0
+        out[label] = (k, th, ct)
+        log("cpu oracle %s: %d pairs on %d threads in %.1f s" % (name, k, th, ct))
+    k, th, ct = out["all"]
+    k1, _, ct1 = out["one"]
+    res = {"value": round(k / ct, 1), "unit": "pairs/s", "cores": th, "kind": "oracle",
+           "host_nproc": nproc,
+           "sample": "first %d pairs of the same workload: full-matrix int32 %s + canonical traceback, "
+                     "gcc -O3 -march=native, %d threads, %.1f s wall" % (
+                         k, "Gotoh" if w["alg"] != "nw" else "NW", th, ct),
+           "one_core": {"value": round(k1 / ct1, 1), "unit": "pairs/s", "cores": 1,
+                        "sample": "first %d pairs, %.1f s" % (k1, ct1)}}
+    if w["alg"] == "wfa":
+        from concurrent.futures import ThreadPoolExecutor
+        kw = min(10_000, w["total"])
+        sub = synth.workload(name, n=kw)
+
+        def one(i):
+            return oracle.wfa_pair(sub.pattern(i), sub.text(i), w["pen"], w["max_score"], handle=h)[0]
+
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(threads) as ex:
+            list(ex.map(one, range(sub.n)))
+        ct = time.perf_counter() - t0
+        res["scalar_wfa"] = {"value": round(kw / ct, 1), "unit": "pairs/s", "cores": threads,
+                             "sample": "first %d pairs, the scalar wavefront oracle with CIGAR, %.1f s" % (kw, ct)}
+        log("cpu scalar WFA: %d pairs in %.1f s" % (kw, ct))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="swg150", choices=sorted(WORKLOAD_TEXT))
-    ap.add_argument("--pairs", type=int, default=None, help="override the pair count")
-    ap.add_argument("--plain-steps", type=int, default=2, help="steps of the plain kernel (0: skip)")
-    ap.add_argument("--cpu-sample", type=int, default=200_000, help="pairs for the CPU baseline (0: skip)")
-    ap.add_argument("--cpu-threads", type=int, default=16)
-    ap.add_argument("--graph", action="store_true", help="time replays of a captured HIP graph")
-    ap.add_argument("--serve", action="store_true",
-                    help="serving form: Poisson request schedule through aim_server (own JSON line)")
-    ap.add_argument("--serve-seconds", type=float, default=3.0,
-                    help="seconds of the 60 s arrival schedule to replay")
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="wfa_mixed", choices=sorted(WORKLOAD_TEXT))
+    ap.add_argument("--plain-steps", type=int, default=1, help="steps of the plain kernel (0: skip)")
+    ap.add_argument("--e2e-reps", type=int, default=3, help="end-to-end reps with transfers (0: skip)")
+    ap.add_argument("--cpu", type=int, default=1, help="CPU baseline (0: skip)")
+    ap.add_argument("--others", type=int, default=1, help="also measure the other workloads (0: skip)")
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="seconds of the serving schedule to replay (0: skip)")
     ap.add_argument("--serve-streams", type=int, default=4)
-    ap.add_argument("--serve-max-batch", type=int, default=0,
-                    help="serving form: most pairs merged into one device batch (0: library default)")
+    ap.add_argument("--serve-only", action="store_true", help="only the serving replay (own JSON line)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -93,264 +345,57 @@ def main():
     import synth
     import paper_2208_01243_amd as aim
     sys.path.insert(0, os.path.join(ROOT, "tests"))
-    from gpu_util import to_device
+    import serve_replay
 
-    if args.serve:
-        serve_bench(args, aim, synth)
+    if args.serve_only:
+        print(json.dumps(serve_replay.replay(aim, synth, args.serve_seconds, args.serve_streams, log)), flush=True)
         return
 
+    run, main_res = measure(aim, synth, args.workload, args.steps, args.warmup,
+                            plain_steps=args.plain_steps, e2e_reps=args.e2e_reps)
+    del run
+    torch.cuda.empty_cache()
     w = synth.WORKLOADS[args.workload]
-    n_total = args.pairs or w["total"]
-    t0 = time.time()
-    batch = synth.workload(args.workload, n=n_total)
-    log("generated %d pairs in %.1fs" % (batch.n, time.time() - t0))
-    dev, enc = to_device(batch, w["enc"])
-    n = batch.n
-    max_len = int(max(batch.pat_len.max(), batch.txt_len.max()))
-    cells_matrix = float((batch.pat_len.astype(np.float64) * batch.txt_len).sum())
-
-    score = torch.empty(n, dtype=torch.int32, device="cuda")
-    status = torch.empty(n, dtype=torch.int8, device="cuda")
-    cap = int((batch.pat_len.astype(np.int64) + batch.txt_len + 1).sum() // 4) + 1024
-    cigar = torch.empty(cap, dtype=torch.int32, device="cuda")
-    cigar_off = torch.empty(n + 1, dtype=torch.int64, device="cuda")
-    stream = torch.cuda.current_stream()
-    step = None
-
-    def c_step(ctx):
-        ctx.align_batch(*dev, enc=enc, max_len=max_len, alg=w["alg"], pen=w["pen"],
-                        max_score=w["max_score"], score=score, status=status, cigar=cigar,
-                        cigar_off=cigar_off, want_cigar=True, stream=stream)
-
-    step = c_step
-    ctx = aim.Context(0, timing=not args.graph)
-    graph = None
-    if args.graph:
-        stream = torch.cuda.Stream()
-        torch.cuda.set_stream(stream)
-        graph = ctx.graph_capture(*dev, enc=enc, max_len=max_len, alg=w["alg"], pen=w["pen"],
-                                  max_score=w["max_score"], score=score, status=status, cigar=cigar,
-                                  cigar_off=cigar_off, want_cigar=True, stream=stream)
-        step = lambda c: graph.launch(stream) if c is ctx else c_step(c)  # noqa: E731
-    for k in range(args.warmup):
-        t1 = time.perf_counter()
-        step(ctx)
-        torch.cuda.synchronize()
-        log("warmup step %d: %.1f ms" % (k, (time.perf_counter() - t1) * 1000))
-    ctx.timing_reset()
-    torch.cuda.synchronize()
-    elapsed_hint_ms = (time.perf_counter() - t1) * 1000 if args.warmup else 1e9
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        step(ctx)
-        if elapsed_hint_ms > 20000:  # long workloads: show progress (syncs each step)
-            torch.cuda.synchronize()
-            log("step %d done at %.1f s" % (k, time.perf_counter() - t0))
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    phases = ctx.timing()
-    ms_per_step = elapsed * 1000.0 / args.steps
-    st = status.cpu().numpy()
-    aligned = int((st == 0).sum())
-    rejected = int((st == 1).sum())
-    pairs_per_s = n / (elapsed / args.steps)
-    log("phases (ms per step): " + ", ".join("%s %.3f" % (k, v[0] / args.steps) for k, v in phases.items()))
-
-    # roofline of the dominant kernel
-    roof = None
-    if w["alg"] in ("swg", "nw"):
-        # dominant kernel: the first band tier (packed 16-bit when the value
-        # bound allows, else 32-bit)
-        kname, phase, peak, unit = ("k_band16<32>", "band16", PEAK_PK16_TOPS, "Tops/s (packed int16)") \
-            if "band16" in phases else ("k_band<32>", "band32", PEAK_INT32_TOPS, "Tops/s (int32)")
-        band_ms, band_launches = phases.get(phase, (0.0, 0))
-        # algorithmic cells of the 32-diagonal band: every pair's rows x 32
-        m = batch.pat_len.astype(np.int64)
-        cells_band = float((m * 32).sum())
-        ops = OPS_PER_CELL[w["alg"]] * cells_band
-        if band_launches:
-            t_launch = band_ms / band_launches / 1000.0
-            achieved = ops / t_launch / 1e12
-            import hashlib
-            src_name = "dp_band16.hip" if phase == "band16" else "dp_band.hip"
-            src = open(os.path.join(ROOT, "paper_2208_01243_amd", "csrc", src_name), "rb").read()
-            h = hashlib.sha256(src).hexdigest()[:16]
-            meas = MEASURED_TRAFFIC.get((args.workload, kname))
-            traffic = meas[1] if (meas and meas[0] == h and n == w["total"]) else None
-            roof = {"bound": "alu", "kernel": kname, "achieved": round(achieved, 3),
-                    "peak": round(peak, 1), "unit": unit,
-                    "frac": round(achieved / peak, 4), "traffic": traffic,
-                    "avg_launch_ms": round(band_ms / band_launches, 4),
-                    "ops_per_cell": OPS_PER_CELL[w["alg"]], "cells_per_launch": cells_band}
-    else:
-        # WFA: the dominant score pass (one wavefront per pair with its fused
-        # walk, or the HBM-ring pass for pairs too wide for its window); the
-        # wavefront cell count is not known without the scalar WFA, so the
-        # fraction of peak comes from the SQ counters in profiles/ instead
-        names = {"wfa_score": "k_wfa_score16", "wfa_score_hbm": "k_wfa_score"}
-        ph = max((k for k in names if k in phases), key=lambda k: phases[k][0], default=None)
-        if ph:
-            wfa_ms, wfa_launches = phases[ph]
-            roof = {"bound": "alu", "kernel": names[ph], "avg_launch_ms": round(wfa_ms / max(wfa_launches, 1), 4),
-                    "achieved": None, "peak": round(PEAK_INT32_TOPS, 1), "unit": "Tops/s (int32)",
-                    "frac": None, "traffic": None}
-
-    # plain one-pair-per-workgroup kernel on the same pairs
-    plain = None
-    if args.plain_steps > 0:
-        pctx = aim.Context(0, kernel="plain")
-        step(pctx)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.plain_steps):
-            step(pctx)
-        torch.cuda.synchronize()
-        pel = (time.perf_counter() - t0) / args.plain_steps
-        plain = {"pairs_per_s": round(n / pel, 1), "ms_per_step": round(pel * 1000, 3),
-                 "speedup_of_auto": round(pel / (elapsed / args.steps), 2)}
-        pctx.close()
-        # the production path must reproduce the plain kernel bit for bit
-        s1, st1 = score.clone(), status.clone()
-        step(ctx)
-        torch.cuda.synchronize()
-        assert torch.equal(s1, score) and torch.equal(st1, status)
-
-    # CPU baseline: the oracle, on a bounded sample of the same workload
-    cpu = None
-    if args.cpu_sample > 0:
-        import oracle
-        k = min(args.cpu_sample, n)
-        sub = synth.workload(args.workload, n=k)
-        threads = max(1, min(args.cpu_threads, os.cpu_count() or 1))
-        t0 = time.perf_counter()
-        oracle.align_batch(sub, w["alg"], w["pen"], w["max_score"], nthreads=threads)
-        ct = time.perf_counter() - t0
-        cpu = {"value": round(k / ct, 1), "unit": "pairs/s", "cores": threads, "kind": "oracle",
-               "sample": "first %d pairs of the same workload (full-matrix int32 %s + canonical "
-                         "traceback, %.1f s wall)" % (k, "Gotoh" if w["alg"] != "nw" else "NW", ct)}
-
     out = {
         "metric": "aligned pairs/s + GCUPS at 1 MI355X",
-        "value": round(pairs_per_s, 1),
+        "value": main_res["pairs_per_s"],
         "unit": "pairs/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step": main_res["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic (seeded generator standing in for the paper's read sets)",
-        "config": {"workload": WORKLOAD_TEXT[args.workload], "pairs": n, "max_len": max_len,
-                   "algorithm": w["alg"], "penalties": list(w["pen"]), "max_score": w["max_score"]},
-        "aligned_pairs": aligned,
-        "rejected_pairs": rejected,
-        "gcups_matrix": round(cells_matrix / (elapsed / args.steps) / 1e9, 1),
-        "phases_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in phases.items()},
-        "roofline": roof,
-        "plain_kernel": plain,
-        "cpu_baseline": cpu,
+        "config": {"workload": WORKLOAD_TEXT[args.workload], "pairs": main_res["pairs"],
+                   "max_len": main_res["max_len"], "algorithm": w["alg"], "penalties": list(w["pen"]),
+                   "max_score": w["max_score"]},
     }
-    print(json.dumps(out), flush=True)
-
-
-def serve_bench(args, aim, synth):
-    """Open-loop replay of the seeded Poisson schedule (2,000 requests/s;
-    1..4096 pairs per request, 100..1000 bp, 1..8 %, NW / SWG / WFA) through
-    the serving loop; latency = completion minus scheduled arrival."""
-    import threading
-    sched = [r for r in synth.serving_schedule() if r.t_arrival < args.serve_seconds]
-    t0 = time.time()
-    batches = []
-    for r in sched:
-        b = synth.request_pairs(r)
-        batches.append(b)
-    log("generated %d requests, %d pairs in %.1fs" % (len(sched), sum(b.n for b in batches), time.time() - t0))
-    srv = aim.Server(0, n_streams=args.serve_streams, budget_bytes=64 << 30,
-                     max_batch_pairs=args.serve_max_batch)
-    # warm every worker's context and kernels on one small request per algorithm
-    warm = [srv.submit(r.alg, r.pen, -1, b.pat, b.pat_off[:-1], b.pat_len, b.txt, b.txt_off[:-1], b.txt_len)
-            for r, b in list(zip(sched, batches))[:12]]
-    for i in warm:
-        srv.wait(i)
-    # and with batches of the merge cap at the schedule's longest reads, one per
-    # worker and algorithm, so that no worker grows its scratch mid-schedule
-    # (a server pays this once at start-up)
-    cap = args.serve_max_batch or 65536
-    rng = np.random.default_rng(7)
-    big = synth._gen_chunk(rng, cap, np.full(cap, 1000), np.full(cap, 0.08), None)
-    for alg, pen in sorted({(r.alg, r.pen) for r in sched}):
-        ws = [srv.submit(alg, pen, -1, big.pat, big.pat_off[:-1], big.pat_len, big.txt, big.txt_off[:-1],
-                         big.txt_len) for _ in range(args.serve_streams)]
-        for i in ws:
-            srv.wait(i)
-    log("warmed %d workers with %d-pair batches of 1000 bp" % (args.serve_streams, cap))
-    srv.reset_stats()
-    ids = [None] * len(sched)
-    lateness = [0.0] * len(sched)
-    submitted = [0.0] * len(sched)
-    server_us = [0.0] * len(sched)
-    start = time.perf_counter()
-
-    def producer():
-        for k, (r, b) in enumerate(zip(sched, batches)):
-            now = time.perf_counter() - start
-            if r.t_arrival > now:
-                time.sleep(r.t_arrival - now)
-            lateness[k] = time.perf_counter() - start - r.t_arrival
-            rid = srv.submit(r.alg, r.pen, -1, b.pat, b.pat_off[:-1], b.pat_len, b.txt, b.txt_off[:-1],
-                             b.txt_len)
-            submitted[k] = time.perf_counter() - start
-            ids[k] = rid
-
-    # no collector pauses in the replay's threads while the schedule runs
-    import gc
-    gc.collect()
-    gc.disable()
-    th = threading.Thread(target=producer)
-    th.start()
-    k = 0
-    last_log = time.perf_counter()
-    while k < len(sched):
-        if ids[k] is None:
-            time.sleep(0.0005)
-            continue
-        # results are collected in arrival order, but each request's latency
-        # is its own: submission (client clock) plus the server's submission
-        # to completion time, so a slow request does not delay the later ones
-        server_us[k] = srv.wait(ids[k])[4]
-        k += 1
-        if time.perf_counter() - last_log > 10:
-            log("serving: %d/%d requests done" % (k, len(sched)))
-            last_log = time.perf_counter()
-    th.join()
-    wall = time.perf_counter() - start
-    gc.enable()
-    st = srv.stats()
-    srv.close()
-    lat = np.array([(submitted[k] - sched[k].t_arrival) * 1e6 + server_us[k] for k in range(len(sched))])
-    pairs = sum(b.n for b in batches)
-    out = {
-        "metric": "p50/p99 latency in serving loop (+ pairs/s)",
-        "value": round(float(np.percentile(lat, 99)), 1),
-        "unit": "us (p99, completion - scheduled arrival)",
-        "higher_is_better": False,
-        "n_gpus": 1,
-        "p50_us": round(float(np.percentile(lat, 50)), 1),
-        "p99_us": round(float(np.percentile(lat, 99)), 1),
-        "server_p50_us": round(st["p50_us"], 1), "server_p99_us": round(st["p99_us"], 1),
-        "pairs_per_s": round(pairs / wall, 1),
-        "offered_pairs_per_s": round(pairs / args.serve_seconds, 1),
-        "requests": len(sched), "pairs": pairs, "batches": st["batches"],
-        "peak_bytes": st["peak_bytes"], "budget_bytes": st["budget_bytes"],
-        "max_submit_lateness_ms": round(max(lateness) * 1000, 2),
-        "data": "synthetic", "dtype": "int32",
-        "config": {"workload": "Poisson 2,000 requests/s, first %.1f s of the 60 s schedule; 1-4096 pairs "
-                               "per request (log-uniform), 100-1000 bp, 1-8 %% error, NW 0/1/0/1 | SWG 4/6/2 | "
-                               "WFA 4/6/2, score + CIGAR, 64 GiB budget, %d streams"
-                               % (args.serve_seconds, args.serve_streams)},
-    }
+    for k in ("aligned_pairs", "rejected_pairs", "gcups_matrix", "wavefront_cells_per_s", "phases_ms_per_step",
+              "path_counters", "roofline", "plain_kernel", "end_to_end"):
+        if k in main_res:
+            out[k] = main_res[k]
+    if args.cpu:
+        n_all, n_one = {"wfa_mixed": (4000, 400), "swg150": (200_000, 20_000), "wfa250": (100_000, 10_000),
+                        "nw100": (10_000, 10_000)}[args.workload]
+        out["cpu_baseline"] = cpu_baseline(synth, args.workload, n_all, n_one)
+    if args.others:
+        others = {}
+        for name in ("nw100", "swg150", "wfa250"):
+            if name == args.workload:
+                continue
+            r, res = measure(aim, synth, name, 20, 3)
+            del r
+            torch.cuda.empty_cache()
+            others[name] = {k: res[k] for k in ("workload", "pairs_per_s", "ms_per_step", "gcups_matrix",
+                                                 "aligned_pairs", "rejected_pairs", "roofline",
+                                                 "phases_ms_per_step", "path_counters")
+                            if k in res}
+        out["other_configs"] = others
+    if args.serve_seconds > 0:
+        out["serving"] = serve_replay.replay(aim, synth, args.serve_seconds, args.serve_streams, log)
     print(json.dumps(out), flush=True)
 
 

@@ -29,6 +29,7 @@ from __future__ import annotations
 import dataclasses
 import hashlib
 import math
+import os
 
 import numpy as np
 
@@ -184,14 +185,25 @@ def _gen_chunk(rng, n, lens, rates, unrelated):
 def _chunked(seed, start, n, total, make):
     if n is None:
         n = total - start
-    out = []
     c0 = start // CHUNK
     c1 = (start + n - 1) // CHUNK if n > 0 else c0 - 1
-    for c in range(c0, c1 + 1):
+
+    def one(c):
         b = make(_chunk_rng(seed, c), c * CHUNK, min(CHUNK, total - c * CHUNK))
         lo = max(start, c * CHUNK) - c * CHUNK
         hi = min(start + n, c * CHUNK + b.n) - c * CHUNK
-        out.append(b.subset(range(lo, hi)) if (lo, hi) != (0, b.n) else b)
+        return b.subset(range(lo, hi)) if (lo, hi) != (0, b.n) else b
+
+    chunks = range(c0, c1 + 1)
+    if len(chunks) > 4:
+        # every chunk has its own generator, so generating them on a few
+        # threads (numpy releases the interpreter lock inside its loops)
+        # gives the same pairs
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(min(8, os.cpu_count() or 1)) as ex:
+            out = list(ex.map(one, chunks))
+    else:
+        out = [one(c) for c in chunks]
     return _concat(out) if out else from_lists([], [])
 
 
@@ -294,18 +306,25 @@ def pack_2bit(codes: np.ndarray, off: np.ndarray):
     nw = (lens + 31) // 32
     woff = np.zeros(len(lens) + 1, np.int64)
     woff[1:] = np.cumsum(nw)
-    padded = np.zeros(int(woff[-1]) * 32, np.uint64)
+    total = int(woff[-1])
+    # one byte per base slot, each sequence starting on a 32-slot boundary
+    slots = np.zeros(total * 32, np.uint8)
     if len(codes):
-        seq = np.repeat(np.arange(len(lens)), lens)
-        pos = np.arange(len(codes)) - np.repeat(off[:-1], lens)
-        padded[woff[seq] * 32 + pos] = codes
-    words = np.zeros(int(woff[-1]), np.uint64)
-    shifts = (2 * np.arange(32)).astype(np.uint64)
-    step = 1 << 20
-    for a in range(0, len(words), step):
-        blk = padded[a * 32:(a + step) * 32].reshape(-1, 32)
-        words[a:a + len(blk)] = np.bitwise_or.reduce(blk << shifts, axis=1)
-    return words, woff
+        if len(lens) * 64 < len(codes):
+            for i in range(len(lens)):
+                slots[woff[i] * 32:woff[i] * 32 + lens[i]] = codes[off[i]:off[i + 1]]
+        else:
+            seq = np.repeat(np.arange(len(lens)), lens)
+            pos = np.arange(len(codes)) - np.repeat(off[:-1], lens)
+            slots[woff[seq] * 32 + pos] = codes
+    # four slots per byte (slot t at bits 2 (t mod 4)); the little-endian
+    # uint64 view of 8 such bytes puts slot t at bits 2 (t mod 32)
+    packed = np.zeros(total * 8, np.uint8)
+    step = 1 << 24
+    for a in range(0, len(packed), step):
+        q = slots[4 * a:4 * (a + step)].reshape(-1, 4)
+        packed[a:a + len(q)] = q[:, 0] | (q[:, 1] << 2) | (q[:, 2] << 4) | (q[:, 3] << 6)
+    return packed.view("<u8").astype(np.uint64, copy=False), woff
 
 
 def unpack_2bit(words: np.ndarray, woff: np.ndarray, lens: np.ndarray) -> np.ndarray:
