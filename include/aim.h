@@ -134,6 +134,7 @@ typedef enum { AIM_KERNEL_AUTO = 0, AIM_KERNEL_PLAIN = 1 } aim_kernel;
 
 /* aim_options.flags bits */
 #define AIM_FLAG_TIMING 1 /* time every kernel launch with HIP events (aim_timing) */
+#define AIM_FLAG_STATIC_SCRATCH 2 /* set up aim_align_batch_static's array at create */
 
 typedef struct {
   int32_t kernel;        /* aim_kernel */
@@ -164,6 +165,25 @@ void aim_destroy(aim_context *ctx);
  * AIM_ERR_UNSUPPORTED (penalties), AIM_ERR_OOM, AIM_ERR_HIP. */
 aim_status aim_align_batch(aim_context *ctx, const aim_batch *pairs, int32_t alg,
                            aim_penalties pen, int32_t max_score, aim_results *out, void *stream);
+
+/* aim_align_batch for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * this call allocates and frees nothing.  Its scratch is carved from one
+ * static device array of 256 MiB per GPU, which that GPU holds from the first
+ * such call on it (or from aim_create with AIM_FLAG_STATIC_SCRATCH, which does
+ * the set-up there) until the process ends.  Launch plans are sized for a
+ * 96 MiB scratch budget.  A batch whose scratch would pass the 256 MiB returns
+ * AIM_ERR_INVALID_ARG; kernels enqueued before the check found it may have
+ * written parts of `out`, which is then unspecified -- split such a batch, or
+ * use aim_align_batch.  The caller owns inputs and outputs as for
+ * aim_align_batch; arguments, errors, asynchrony and results (bit for bit) are
+ * those of aim_align_batch, and calls on one context are ordered the same way.
+ * Every call on one GPU, from any context, shares that GPU's array, which
+ * keeps the last call's contents (each call clears what it needs zeroed):
+ * calls that overlap in time on one GPU race. */
+aim_status aim_align_batch_static(aim_context *ctx, const aim_batch *pairs, int32_t alg,
+                                  aim_penalties pen, int32_t max_score, aim_results *out,
+                                  void *stream);
 
 /* Encode sequences as 2-bit words (the "2BIT" layout above).
  *   enc: AIM_ENC_ASCII or AIM_ENC_CODE; seq/off/len: device CSR (byte offsets);

@@ -19,6 +19,7 @@ ALGORITHMS = {"nw": NW_LINEAR, "swg": SWG_AFFINE, "wfa": WFA_AFFINE}
 ENC_ASCII, ENC_CODE, ENC_2BIT = 0, 1, 2
 KERNEL_AUTO, KERNEL_PLAIN = 0, 1
 FLAG_TIMING = 1
+FLAG_STATIC_SCRATCH = 2
 PAIR_ALIGNED, PAIR_REJECTED, PAIR_CIGAR_OVERFLOW, PAIR_INVALID = 0, 1, 2, 3
 OP_MATCH, OP_MISMATCH, OP_INS, OP_DEL = 0, 1, 2, 3
 
@@ -86,6 +87,8 @@ SIGNATURES = {
     "aim_create": ([ctypes.POINTER(vp), i32, ctypes.POINTER(Options)], i32),
     "aim_destroy": ([vp], None),
     "aim_align_batch": ([vp, ctypes.POINTER(Batch), i32, Penalties, i32, ctypes.POINTER(Results), vp], i32),
+    "aim_align_batch_static": ([vp, ctypes.POINTER(Batch), i32, Penalties, i32, ctypes.POINTER(Results),
+                                vp], i32),
     "aim_pack_2bit": ([vp, i64, i32, vp, vp, vp, vp, i64, vp, vp, vp], i32),
     "aim_timing": ([vp, i32, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_double),
                     ctypes.POINTER(i64)], i32),
@@ -155,9 +158,10 @@ class Context:
     """An aim_context on one HIP device."""
 
     def __init__(self, device: int = 0, kernel: str = "auto", scratch_limit: int = 0,
-                 timing: bool = False):
+                 timing: bool = False, static_scratch: bool = False):
         opt = Options(KERNEL_PLAIN if kernel == "plain" else KERNEL_AUTO,
-                      FLAG_TIMING if timing else 0, scratch_limit)
+                      (FLAG_TIMING if timing else 0) | (FLAG_STATIC_SCRATCH if static_scratch else 0),
+                      scratch_limit)
         h = vp()
         _check(lib().aim_create(ctypes.byref(h), device, ctypes.byref(opt)))
         self._h = h
@@ -203,6 +207,15 @@ class Context:
                              score, status, cigar, cigar_off, want_cigar)
         _check(lib().aim_align_batch(self._h, ctypes.byref(b), a, Penalties(*pen), max_score,
                                      ctypes.byref(r), _stream(stream)))
+
+    def align_batch_static(self, pat_seq, pat_off, pat_len, txt_seq, txt_off, txt_len, *, enc: int,
+                           max_len: int, alg, pen, max_score: int, score, status, cigar=None,
+                           cigar_off=None, want_cigar: bool = True, stream=None):
+        """aim_align_batch_static (no device allocation) on device tensors."""
+        b, r, a = self._args(pat_seq, pat_off, pat_len, txt_seq, txt_off, txt_len, enc, max_len, alg,
+                             score, status, cigar, cigar_off, want_cigar)
+        _check(lib().aim_align_batch_static(self._h, ctypes.byref(b), a, Penalties(*pen), max_score,
+                                            ctypes.byref(r), _stream(stream)))
 
     def autotune(self, pat_seq, pat_off, pat_len, txt_seq, txt_off, txt_len, *, enc, max_len, alg,
                  pen, max_score, score, status, cigar=None, cigar_off=None, want_cigar=True,

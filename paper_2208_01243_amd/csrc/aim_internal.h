@@ -256,4 +256,15 @@ constexpr int LEN_BUCKETS = 128;
 hipError_t launch_length_sort(int64_t n, const int32_t *pl, const int32_t *tl, int32_t *hist,
                               int32_t *order, hipStream_t s);
 
+// ---- allocation-free entry point ------------------------------------------
+// Size of the static device array (one per GPU) that aim_align_batch_static
+// carves its scratch from, and the scratch budget its launch plans are sized
+// for (well below the array, since the plans' shares of a budget add up to
+// more than half of it and some buffers have fixed minimum sizes).
+constexpr size_t STATIC_SCRATCH_BYTES = (size_t)256 << 20;
+constexpr int64_t STATIC_PLAN_BUDGET = (int64_t)96 << 20;
+// The array's address on `device`, which must be the current device; looked
+// up once per device (hipGetSymbolAddress) and kept.
+hipError_t static_scratch_address(int device, void **out);
+
 }  // namespace aim

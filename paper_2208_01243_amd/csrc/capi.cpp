@@ -137,11 +137,15 @@ struct aim_context {
   hipEvent_t ev_done = nullptr;
   bool has_done = false;
   int64_t generation = 0;       // bumped whenever scratch is reallocated
-  // Scratch of the running call (the context's own, grown on demand).
+  // Scratch of the running call: the context's own (grown on demand), or,
+  // inside aim_align_batch_static, buffers carved from the static array.
   Scratch own;
   Scratch *sc = &own;
+  // carving state of aim_align_batch_static (arena == nullptr otherwise)
+  uint8_t *arena = nullptr;
+  size_t arena_cap = 0, arena_top = 0;
   // the scratch budget the launch plans are sized for in this call
-  int64_t limit() const { return opt.scratch_limit; }
+  int64_t limit() const { return arena ? aim::STATIC_PLAN_BUDGET : opt.scratch_limit; }
   // the last call's work counters (device) and size, for aim_last_call_stats
   const int32_t *last_cnt = nullptr;
   int64_t last_n = 0;
@@ -153,6 +157,19 @@ namespace {
 aim_status ensure(aim_context *c, Buf &b, size_t bytes) {
   if (bytes == 0) bytes = 256;
   if (b.bytes >= bytes) return AIM_OK;
+  if (c->arena) {
+    // static-array mode: carve, 256-byte aligned; never allocate or free
+    const size_t need = (bytes + 255) & ~(size_t)255;
+    if (c->arena_top + need > c->arena_cap)
+      return fail(AIM_ERR_INVALID_ARG,
+                  "this batch needs more scratch than the static array holds (%zu bytes): "
+                  "split it, or call aim_align_batch", c->arena_cap);
+    b.p = c->arena + c->arena_top;
+    b.bytes = need;
+    b.pooled = false;
+    c->arena_top += need;
+    return AIM_OK;
+  }
   if (c->capturing) return fail(AIM_ERR_INVALID_ARG, "scratch would grow during graph capture");
   hipStream_t as = c->astream;
   if (b.p) {
@@ -240,7 +257,7 @@ struct Phase {
   const char *name;
   hipEvent_t a = nullptr;
   Phase(aim_context *c_, hipStream_t s_, const char *n) : c(c_), s(s_), name(n) {
-    if ((c->opt.flags & AIM_FLAG_TIMING) && !c->capturing) {
+    if ((c->opt.flags & AIM_FLAG_TIMING) && !c->capturing && !c->arena) {
       a = c->timer.get();
       if (a) (void)hipEventRecord(a, s);
     }
@@ -454,7 +471,7 @@ aim_status aim_create(aim_context **ctx, int32_t device, const aim_options *opt)
     return fail(AIM_ERR_INVALID_ARG, "unknown kernel option %d", o.kernel);
   if (o.scratch_limit < 0) return fail(AIM_ERR_INVALID_ARG, "scratch_limit < 0");
   if (o.scratch_limit == 0) o.scratch_limit = (int64_t)64 << 30;
-  if (o.flags & ~AIM_FLAG_TIMING)
+  if (o.flags & ~(AIM_FLAG_TIMING | AIM_FLAG_STATIC_SCRATCH))
     return fail(AIM_ERR_INVALID_ARG, "unknown option flags 0x%x", o.flags);
   auto *c = new aim_context();
   c->device = device;
@@ -475,6 +492,19 @@ aim_status aim_create(aim_context **ctx, int32_t device, const aim_options *opt)
       if (c->ev_join) (void)hipEventDestroy(c->ev_join);
       delete c;
       return fail(AIM_ERR_HIP, "could not create the context's stream and events");
+    }
+    if (o.flags & AIM_FLAG_STATIC_SCRATCH) {
+      // set-up of aim_align_batch_static on this device
+      void *base = nullptr;
+      const hipError_t e = aim::static_scratch_address(device, &base);
+      if (e != hipSuccess) {
+        (void)hipEventDestroy(c->ev_done);
+        (void)hipEventDestroy(c->ev_join);
+        (void)hipEventDestroy(c->ev_fork);
+        (void)hipStreamDestroy(c->aux);
+        delete c;
+        return fail(AIM_ERR_HIP, "static scratch array: %s", hipGetErrorString(e));
+      }
     }
   }
   *ctx = c;
@@ -817,6 +847,35 @@ aim_status aim_last_call_stats(aim_context *c, aim_call_stats *out) {
   out->cigar_reruns = v[C_SPILL];
   out->wfa_window = c->last_window;
   return AIM_OK;
+}
+
+aim_status aim_align_batch_static(aim_context *c, const aim_batch *B, int32_t alg, aim_penalties pen,
+                                  int32_t max_score, aim_results *R, void *stream) {
+  g_err.clear();
+  if (!c) return fail(AIM_ERR_INVALID_ARG, "ctx is NULL");
+  if (c->capturing) return fail(AIM_ERR_INVALID_ARG, "aim_align_batch_static inside aim_graph_capture");
+  DeviceGuard g(c->device);
+  void *base = nullptr;
+  const hipError_t e = aim::static_scratch_address(c->device, &base);
+  if (e != hipSuccess) return fail(AIM_ERR_HIP, "static scratch array: %s", hipGetErrorString(e));
+  hipStream_t s = (hipStream_t)stream;
+  if (c->has_done && c->done_stream != s) HIP_TRY(hipStreamWaitEvent(s, c->ev_done, 0));
+  // this call's buffers, carved from the array from its start
+  Scratch carved;
+  c->sc = &carved;
+  c->arena = static_cast<uint8_t *>(base);
+  c->arena_cap = aim::STATIC_SCRATCH_BYTES;
+  c->arena_top = 0;
+  c->astream = s;
+  const aim_status st = align_batch(c, B, alg, pen, max_score, R, stream);
+  c->astream = nullptr;
+  c->arena = nullptr;
+  c->arena_cap = c->arena_top = 0;
+  c->sc = &c->own;
+  HIP_TRY(hipEventRecord(c->ev_done, s));
+  c->has_done = true;
+  c->done_stream = s;
+  return st;
 }
 
 }  // extern "C"
