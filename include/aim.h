@@ -231,7 +231,10 @@ aim_status aim_timing_reset(aim_context *ctx);
  *     re-aligned in place by the compaction;
  *   wfa_window: the diagonals the one-wavefront WFA pass keeps, centred on
  *     diagonal 0 (0: that pass did not run); pairs whose wavefronts stay
- *     inside it are aligned there, the others by the wide-pair pass. */
+ *     inside it are aligned there, the others go to wider windows;
+ *   wfa_class_pairs[c] / wfa_class_window[c]: pairs routed to the c-th LDS
+ *     window class, and its window in diagonals (0: no such class);
+ *     wfa_wide counts the pairs that outgrew them all (HBM-ring pass). */
 typedef struct {
   int64_t n_pairs;
   int32_t band_escalated, band_escalated2;
@@ -239,6 +242,8 @@ typedef struct {
   int32_t full_store[4];
   int32_t cigar_reruns;
   int32_t wfa_window;
+  int32_t wfa_class_pairs[4];
+  int32_t wfa_class_window[4];
 } aim_call_stats;
 aim_status aim_last_call_stats(aim_context *ctx, aim_call_stats *out);
 
@@ -251,20 +256,24 @@ aim_status aim_last_call_stats(aim_context *ctx, aim_call_stats *out);
  * {off, on} (32 diagonals only); WFA -- length sort {off, on}, workgroup size
  * for wide pairs {128, 256}.  Each candidate runs once to warm up and `reps`
  * times timed (median).  Synchronous.  On return `out` holds the results of
- * the chosen configuration; best_params (7 int32, see aim_tune_get) and
+ * the chosen configuration; best_params (12 int32, see aim_tune_get) and
  * best_ms may be NULL.  Paper: Data Management (the framework picks the
  * number of DPU threads from the algorithm, read length and error rate). */
 aim_status aim_autotune(aim_context *ctx, const aim_batch *pairs, int32_t alg, aim_penalties pen,
                         int32_t max_score, aim_results *out, void *stream, int32_t reps,
                         int32_t *best_params, double *best_ms);
 
-/* Launch parameters for (alg, max_len), 7 int32: params[0] first band width,
+/* Launch parameters for (alg, max_len), 12 int32: params[0] first band width,
  * [1] wavefronts per CU, [2] length sort (-1 auto, 0 off, 1 on), [3] WFA ring
  * LDS KB, [4] WFA full-store LDS KB, [5] WFA long-pair workgroup size,
  * [6] packed 16-bit band cells when the value bound allows (0 off; 1 on, each
  * wavefront walking its own pairs' tracebacks; 2 on, the tracebacks walked by
  * a second kernel beside the escalation tiers; 3, the default: 2 for batches
- * of at least 65536 pairs, else 1). */
+ * of at least 65536 pairs, else 1), [7] WFA pairs wider than the
+ * one-wavefront window go through LDS-window classes (1, the default) or
+ * straight to the HBM-ring pass (0), [8..10] workgroup size (64, 128, 256 or
+ * 512) of the three window classes (narrowest first), [11] bit c set: class
+ * c + 1 keeps its recent wavefronts in a global buffer rather than LDS. */
 aim_status aim_tune_get(aim_context *ctx, int32_t alg, int32_t max_len, int32_t *params);
 aim_status aim_tune_set(aim_context *ctx, int32_t alg, int32_t max_len, const int32_t *params);
 /* Tune cache as text, keyed by GPU architecture and HIP runtime version; a

@@ -73,7 +73,8 @@ class ServerStats(ctypes.Structure):
 class CallStats(ctypes.Structure):
     _fields_ = [("n_pairs", i64), ("band_escalated", i32), ("band_escalated2", i32), ("wfa_wide", i32),
                 ("wfa_walk_failed", i32), ("wfa_walk_skipped", i32), ("full_store", i32 * 4),
-                ("cigar_reruns", i32), ("wfa_window", i32)]
+                ("cigar_reruns", i32), ("wfa_window", i32), ("wfa_class_pairs", i32 * 4),
+                ("wfa_class_window", i32 * 4)]
 
 
 class AimError(RuntimeError):
@@ -220,22 +221,22 @@ class Context:
     def autotune(self, pat_seq, pat_off, pat_len, txt_seq, txt_off, txt_len, *, enc, max_len, alg,
                  pen, max_score, score, status, cigar=None, cigar_off=None, want_cigar=True,
                  stream=None, reps=2):
-        """aim_autotune; returns (params list of 7, best ms)."""
+        """aim_autotune; returns (params list of 12, best ms)."""
         b, r, a = self._args(pat_seq, pat_off, pat_len, txt_seq, txt_off, txt_len, enc, max_len, alg,
                              score, status, cigar, cigar_off, want_cigar)
-        params = (i32 * 7)()
+        params = (i32 * 12)()
         ms = ctypes.c_double()
         _check(lib().aim_autotune(self._h, ctypes.byref(b), a, Penalties(*pen), max_score,
                                   ctypes.byref(r), _stream(stream), reps, params, ctypes.byref(ms)))
         return list(params), ms.value
 
     def tune_get(self, alg, max_len):
-        params = (i32 * 7)()
+        params = (i32 * 12)()
         _check(lib().aim_tune_get(self._h, ALGORITHMS[alg] if isinstance(alg, str) else alg, max_len, params))
         return list(params)
 
     def tune_set(self, alg, max_len, params):
-        arr = (i32 * 7)(*params)
+        arr = (i32 * 12)(*params)
         _check(lib().aim_tune_set(self._h, ALGORITHMS[alg] if isinstance(alg, str) else alg, max_len, arr))
 
     def tune_save(self, path):
@@ -274,6 +275,8 @@ class Context:
         _check(lib().aim_last_call_stats(self._h, ctypes.byref(st)))
         out = {k: getattr(st, k) for k, _ in CallStats._fields_}
         out["full_store"] = list(st.full_store)
+        out["wfa_class_pairs"] = list(st.wfa_class_pairs)
+        out["wfa_class_window"] = list(st.wfa_class_window)
         return out
 
     def timing_reset(self):

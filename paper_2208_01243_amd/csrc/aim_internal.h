@@ -168,6 +168,19 @@ hipError_t launch_full(bool affine, const Seqs &S, const Outs &O, const Scoring 
                        hipStream_t s);
 int64_t full_slot_words(int32_t max_len);
 
+// Where a pair whose wavefronts leave a pass's window goes next: classes
+// 1..nclass, each with a wider window (half-width half[c] diagonals around
+// diagonal 0; the last class, the HBM-ring pass, has no bound); the pair
+// joins the first later class whose window holds its predicted extent.
+constexpr int WFA_MAX_CLASSES = 6;
+struct WfaRoute {
+  int32_t nclass;
+  int32_t half[WFA_MAX_CLASSES];
+  int32_t *list[WFA_MAX_CLASSES];
+  int32_t *count[WFA_MAX_CLASSES];
+  int32_t *pred;  // per pair: the extent predicted when it left its last window
+};
+
 // Wavefront algorithm, one pair per 64-lane wavefront, two passes.
 struct WfaLaunch {
   int32_t R;            // ring slots (score passes): max(x, o+e) + 1
@@ -198,12 +211,47 @@ struct WfaLaunch {
   uint8_t *walk;
   int32_t walk_steps, walk_tok;
   int64_t walk_codes, walk_slot;
+  // one-wavefront pass: where pairs that leave its window go (route.nclass
+  // == 0: to ring_list)
+  WfaRoute route;
   // score passes with a CIGAR wanted: counters of accepted pairs left to the
   // full-store pass, because their fused walk failed (walk_fail; it cannot,
   // for codes that were kept and read back intact) or because their codes
   // were not kept (walk_skip: more scores than the code slot holds)
   int32_t *walk_fail, *walk_skip;
 };
+
+// One LDS-window class of wide pairs (k_wfa_lds): the last R scores of M and
+// the last e + 1 of I and D are LDS rows of packed 16-bit offsets indexed by
+// absolute diagonal over the window [-W/2, W/2) plus MG entries of margin on
+// each side.  Origin codes and a per-score table go to a per-workgroup HBM
+// slot for the fused walk.
+struct WfaLds {
+  int32_t W, MG, R, seq_words;
+  int32_t s_cap;          // scores a pair may take in this class (16-bit absent marks)
+  int32_t my_class;       // this class's index in the route
+  WfaRoute route;
+  uint8_t *codes;         // per workgroup: steps_cap table entries (3 int32) + code_cap bytes
+  int64_t code_slot;      // bytes per workgroup slot
+  int32_t steps_cap;
+  int64_t code_cap;
+  // the full-store fallback, as in WfaLaunch
+  int64_t need_cap[4];
+  int32_t *need_list[4];
+  int32_t *need_count[4];
+  int32_t *need_max[4];
+  int64_t *need;
+  int32_t *walk_fail, *walk_skip;
+  // non-null: the ring rows live in a global buffer, gring_slot words per
+  // workgroup (wfa_ring_words), instead of LDS
+  uint32_t *gring;
+  int64_t gring_slot;
+};
+int64_t wfa_ring_words(int32_t W, int32_t MG, int32_t R, int32_t e);
+size_t wfa_lds_bytes(int32_t W, int32_t MG, int32_t R, int32_t e, int32_t seq_words, bool gring);
+// threads: 64, 128, 256 or 512
+hipError_t launch_wfa_lds(const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk, const WfaLds &L,
+                          int32_t threads, int32_t nslots, hipStream_t s);
 
 struct WfaPlan {
   int32_t R, wcap, wcap_lds, seq_words, lds_score_bytes, ring_slots, ring_threads, lds_arena_words;

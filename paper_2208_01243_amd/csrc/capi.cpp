@@ -98,6 +98,10 @@ struct Tune {
   int32_t band16 = 3;         // packed 16-bit band kernel when the value bound allows
                               // (1: the fill walks its pairs, 2: a separate walk kernel,
                               // 3: 2 for batches of at least SPLIT_MIN_PAIRS pairs, else 1)
+  int32_t wfa_classes = 1;    // WFA pairs wider than the one-wavefront window: LDS-window
+                              // classes (1) or straight to the HBM-ring pass (0)
+  int32_t wfa_cls_threads[3] = {64, 128, 256};  // workgroup size of each window class
+  int32_t wfa_cls_global = 7;  // bit c: class c + 1 keeps its ring in a global buffer, not LDS
 };
 
 // Every scratch buffer of one call.
@@ -105,7 +109,7 @@ struct Scratch {
   Buf order, hist;
   Buf flags, pflag, tflag, pat2, txt2, pat2off, txt2off, nruns, slot, tb32, tb64, full, list2,
       list3, counters, scan_tmp, spill, total, wring, warena1, warena2, warena3, wneed, wlists, pool, pooloff,
-      wbits, wwalk;
+      wbits, wwalk, wlds, wgring;
 };
 
 struct aim_graph {
@@ -150,6 +154,7 @@ struct aim_context {
   const int32_t *last_cnt = nullptr;
   int64_t last_n = 0;
   int32_t last_window = 0;  // diagonals of the one-wavefront WFA window (0: not run)
+  int32_t last_class_window[4] = {0, 0, 0, 0};  // windows of the LDS classes (0: none)
 };
 
 namespace {
@@ -226,7 +231,8 @@ enum Counter {
   C_T1 = 0, C_T2, C_T3, C_L2, C_L3, C_SPILL, C_SPILL_W,
   C_W1, C_W1G, C_RL, C_FAIL, C_N0, C_N1, C_N2, C_N3, C_P0, C_P1, C_P2, C_P3, C_TB, C_DTB,
   C_M0, C_M1, C_M2, C_M3, C_WF, C_WS,
-  C_N = 32
+  C_CL = 32,  // WFA window classes 1..4: list lengths, then their work counters (C_CL + 4)
+  C_N = 48
 };
 
 // Smallest batch for which the packed band tier's traceback is walked by a
@@ -323,7 +329,9 @@ aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const
   const aim::WfaPlan pl = aim::wfa_plan(L, P, c->limit(), c->cus, plain, tu.wfa_ring_kb,
                                         tu.wfa_trace_kb, tu.wfa_long_threads);
   if ((st = ensure(c, c->sc->wneed, (size_t)n * 8))) return st;
-  if ((st = ensure(c, c->sc->wlists, (size_t)n * 4 * 6))) return st;
+  // lists: [0] the HBM-ring pass, [1-4] full-store classes, [5] unused,
+  // [6-9] LDS-window classes, [10] predicted extents
+  if ((st = ensure(c, c->sc->wlists, (size_t)n * 4 * 11))) return st;
   int32_t *lists = as<int32_t>(c->sc->wlists);
   aim::WfaLaunch WL{};
   WL.R = pl.R;
@@ -345,6 +353,59 @@ aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const
   const bool w16 = !plain && L <= aim::WFA16_MAX_LEN && pl.R <= 32 && pl.seq_words > 0 &&
                    aim::wfa_score16_lds(WL, P.e, C16) <= 48 * 1024;
   WL.store16 = w16;  // the full store of the fallback pass holds 16-bit offsets
+  // Window classes for the pairs that leave the one-wavefront window: LDS
+  // windows of growing width, each pair routed to the first that holds its
+  // predicted extent, then the HBM-ring pass for the rest.
+  struct LdsClass {
+    int32_t W, threads, nslots;
+    bool global;
+    int32_t half;  // routing bound: pairs predicted to span at most this many diagonals each side
+  };
+  std::vector<LdsClass> cls;
+  const int32_t MG = 2 * pl.R + 4;
+  if (w16 && tu.wfa_classes) {
+    const size_t lds_cap = 160 * 1024;
+    int32_t wmax = 0;
+    for (int32_t w = 512; w <= 16384; w += 512)
+      if (aim::wfa_lds_bytes(w, MG, pl.R, P.e, pl.seq_words, false) <= lds_cap) wmax = w;
+    // classes by predicted extent: up to 512, 1536, then the rest.  An LDS
+    // class holds a window of twice its bound (the widest that fits LDS for
+    // the last); a global-ring class holds every diagonal of the batch's
+    // pairs (its window costs memory only), so no pair leaves it and the
+    // bound only picks the workgroup size.
+    const int32_t full = (int32_t)std::min<int64_t>(32768, (2 * (int64_t)L + 2 + 3) / 4 * 4 + 4);
+    const int32_t bound[3] = {512, 1536, INT32_MAX};
+    int32_t prev_half = 32 * C16;
+    for (int k = 0; k < 3; ++k) {
+      const bool glob = (tu.wfa_cls_global >> k) & 1;
+      const int32_t w = glob ? full : std::min<int64_t>((int64_t)2 * std::min(bound[k], wmax / 2), wmax);
+      const int32_t half = glob ? bound[k] : w / 2;
+      if (std::min(half, w / 2) <= prev_half) continue;
+      const size_t lds = aim::wfa_lds_bytes(w, MG, pl.R, P.e, pl.seq_words, glob);
+      if (lds > lds_cap) continue;
+      const int32_t th = tu.wfa_cls_threads[k];
+      const int32_t per_cu = (int32_t)std::max<size_t>(1, std::min<size_t>(lds_cap / lds, 2048 / th));
+      cls.push_back({w, th, (int32_t)std::min<int64_t>(n, (int64_t)c->cus * per_cu), glob, half});
+      prev_half = std::min(half, w / 2);
+      if (prev_half > L) break;  // every pair fits: no wider class needed
+    }
+    // a last class whose window holds every pair takes whatever the earlier
+    // ones do not
+    if (!cls.empty() && cls.back().W >= 2 * L + 2) cls.back().half = INT32_MAX;
+  }
+  aim::WfaRoute route{};
+  if (!plain && w16) {
+    route.nclass = (int32_t)cls.size() + 1;
+    for (size_t k = 0; k < cls.size(); ++k) {
+      route.half[k + 1] = cls[k].half;
+      route.list[k + 1] = lists + (int64_t)n * (6 + k);
+      route.count[k + 1] = cnt + C_CL + (int32_t)k;
+    }
+    route.half[route.nclass] = INT32_MAX;
+    route.list[route.nclass] = lists;  // the HBM-ring pass
+    route.count[route.nclass] = cnt + C_RL;
+    route.pred = lists + (int64_t)n * 10;
+  }
   if (w16) {
     const int32_t nslots16 = (int32_t)std::min<int64_t>(n, (int64_t)c->cus * 28);
     aim::WfaLaunch A = WL;
@@ -360,10 +421,69 @@ aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const
       if ((st = ensure(c, c->sc->wbits, (size_t)nslots16 * A.bits_steps * (C16 * 32 + 32)))) return st;
       A.bits = as<uint8_t>(c->sc->wbits);
     }
+    A.route = route;
     aim::Work W{order, order_count, n, cnt + C_W1, nullptr, nullptr, 0};
-    Phase ph(c, s, "wfa_score");
-    HIP_TRY(aim::launch_wfa_score16(S, O, P, W, A, C16, nslots16, s));
+    {
+      Phase ph(c, s, "wfa_score");
+      HIP_TRY(aim::launch_wfa_score16(S, O, P, W, A, C16, nslots16, s));
+    }
     c->last_window = 64 * C16;
+    // the LDS-window classes, narrowest first; origin codes in one buffer
+    // the classes share (they run one after the other on this stream)
+    std::vector<aim::WfaLds> LL(cls.size());
+    size_t code_bytes = 0, ring_bytes = 0;
+    for (size_t k = 0; k < cls.size(); ++k) {
+      aim::WfaLds &D = LL[k];
+      D.W = cls[k].W;
+      D.MG = MG;
+      D.R = pl.R;
+      D.seq_words = pl.seq_words;
+      D.s_cap = 16000;
+      D.my_class = (int32_t)k + 1;
+      D.route = route;
+      // scores and widest row a pair of this class is expected to need (a
+      // pair that needs more leaves its codes to the full-store pass)
+      const int32_t bnd = cls[k].half == INT32_MAX ? D.W / 2 : std::min(cls[k].half, D.W / 2);
+      D.steps_cap = P.want_cigar ? (int32_t)std::min<int64_t>(2 * (int64_t)D.W + 64, 8 * (int64_t)bnd + 64) : 0;
+      // Per workgroup slot: the score table, the ring when it is global, and
+      // the origin codes (at most every score's widest row).  The classes run
+      // in turn and share one code buffer and one ring buffer, each within a
+      // third of the scratch budget: fewer workgroups when the slots would
+      // not fit (at least one, with at least 64 KB of codes).
+      D.gring_slot = cls[k].global ? (aim::wfa_ring_words(D.W, MG, pl.R, P.e) + 63) / 64 * 64 : 0;
+      const int64_t share = c->limit() / 3;
+      const int64_t fixed = (int64_t)D.steps_cap * 12 + D.gring_slot * 4;
+      cls[k].nslots = (int32_t)std::max<int64_t>(1, std::min<int64_t>(cls[k].nslots, share / (fixed + (64 << 10))));
+      D.code_cap = P.want_cigar ? std::max<int64_t>(std::min<int64_t>((int64_t)D.steps_cap * (bnd / 2 + 1),
+                                                                      share / cls[k].nslots - fixed),
+                                                    64 << 10)
+                                : 0;
+      D.code_slot = ((int64_t)D.steps_cap * 12 + D.code_cap + 255) / 256 * 256;
+      ring_bytes = std::max(ring_bytes, (size_t)D.gring_slot * 4 * cls[k].nslots);
+      for (int q = 0; q < 4; ++q) {
+        D.need_cap[q] = WL.need_cap[q];
+        D.need_list[q] = WL.need_list[q];
+        D.need_count[q] = WL.need_count[q];
+        D.need_max[q] = WL.need_max[q];
+      }
+      D.need = WL.need;
+      D.walk_fail = WL.walk_fail;
+      D.walk_skip = WL.walk_skip;
+      code_bytes = std::max(code_bytes, (size_t)D.code_slot * cls[k].nslots);
+    }
+    for (size_t k = 0; k < cls.size() && k < 4; ++k) c->last_class_window[k] = cls[k].W;
+    if (!cls.empty()) {
+      if ((st = ensure(c, c->sc->wlds, std::max<size_t>(code_bytes, 256)))) return st;
+      if (ring_bytes && (st = ensure(c, c->sc->wgring, ring_bytes))) return st;
+      for (size_t k = 0; k < cls.size(); ++k) {
+        LL[k].codes = as<uint8_t>(c->sc->wlds);
+        LL[k].gring = cls[k].global ? as<uint32_t>(c->sc->wgring) : nullptr;
+        aim::Work WC{route.list[k + 1], route.count[k + 1], n, cnt + C_CL + 4 + (int32_t)k, nullptr, nullptr, 0};
+        static const char *cls_names[4] = {"wfa_lds1", "wfa_lds2", "wfa_lds3", "wfa_lds4"};
+        Phase ph(c, s, cls_names[k]);
+        HIP_TRY(aim::launch_wfa_lds(S, O, P, WC, LL[k], cls[k].threads, cls[k].nslots, s));
+      }
+    }
   } else if (!plain && pl.wcap_lds > 0) {
     aim::WfaLaunch A = WL;
     A.wcap = pl.wcap_lds;
@@ -518,7 +638,7 @@ void aim_destroy(aim_context *c) {
   Buf *all[] = {&c->own.order, &c->own.hist, &c->own.flags, &c->own.pflag, &c->own.tflag, &c->own.pat2, &c->own.txt2, &c->own.pat2off, &c->own.txt2off,
                 &c->own.nruns, &c->own.slot, &c->own.tb32, &c->own.tb64, &c->own.full, &c->own.list2, &c->own.list3,
                 &c->own.counters, &c->own.scan_tmp, &c->own.spill, &c->own.total, &c->own.wring, &c->own.warena1,
-                &c->own.warena2, &c->own.warena3, &c->own.wneed, &c->own.wlists, &c->own.pool, &c->own.pooloff, &c->own.wbits, &c->own.wwalk};
+                &c->own.warena2, &c->own.warena3, &c->own.wneed, &c->own.wlists, &c->own.pool, &c->own.pooloff, &c->own.wbits, &c->own.wwalk, &c->own.wlds, &c->own.wgring};
   for (Buf *b : all)
     if (b->p) (void)(b->pooled ? hipFreeAsync(b->p, nullptr) : hipFree(b->p));
   (void)hipDeviceSynchronize();
@@ -604,6 +724,7 @@ static aim_status align_batch(aim_context *c, const aim_batch *B, int32_t alg, a
   c->last_cnt = cnt;
   c->last_n = n;
   c->last_window = 0;
+  for (int k = 0; k < 4; ++k) c->last_class_window[k] = 0;
   HIP_TRY(aim::launch_fill_i32(cnt, 0, C_N, s));
 
   // ---- input encoding ----
@@ -846,6 +967,10 @@ aim_status aim_last_call_stats(aim_context *c, aim_call_stats *out) {
   for (int k = 0; k < 4; ++k) out->full_store[k] = v[C_N0 + k];
   out->cigar_reruns = v[C_SPILL];
   out->wfa_window = c->last_window;
+  for (int k = 0; k < 4; ++k) {
+    out->wfa_class_pairs[k] = v[C_CL + k];
+    out->wfa_class_window[k] = c->last_class_window[k];
+  }
   return AIM_OK;
 }
 
@@ -882,15 +1007,21 @@ aim_status aim_align_batch_static(aim_context *c, const aim_batch *B, int32_t al
 
 // ---------------------------------------------------------------- autotuner
 namespace {
-const int32_t TUNE_FIELDS = 7;
+const int32_t TUNE_FIELDS = 12;
 void tune_to(const Tune &t, int32_t *v) {
   v[0] = t.band_w0; v[1] = t.band_wpc; v[2] = t.sort;
   v[3] = t.wfa_ring_kb; v[4] = t.wfa_trace_kb; v[5] = t.wfa_long_threads; v[6] = t.band16;
+  v[7] = t.wfa_classes;
+  for (int k = 0; k < 3; ++k) v[8 + k] = t.wfa_cls_threads[k];
+  v[11] = t.wfa_cls_global;
 }
 Tune tune_from(const int32_t *v) {
   Tune t;
   t.band_w0 = v[0]; t.band_wpc = v[1]; t.sort = v[2];
   t.wfa_ring_kb = v[3]; t.wfa_trace_kb = v[4]; t.wfa_long_threads = v[5]; t.band16 = v[6];
+  t.wfa_classes = v[7];
+  for (int k = 0; k < 3; ++k) t.wfa_cls_threads[k] = v[8 + k];
+  t.wfa_cls_global = v[11];
   return t;
 }
 bool tune_valid(const Tune &t) {
@@ -898,7 +1029,14 @@ bool tune_valid(const Tune &t) {
          t.sort >= -1 && t.sort <= 1 && t.wfa_ring_kb >= 8 && t.wfa_ring_kb <= 60 &&
          t.wfa_trace_kb >= 8 && t.wfa_trace_kb <= 60 &&
          (t.wfa_long_threads == 64 || t.wfa_long_threads == 128 || t.wfa_long_threads == 256) &&
-         (t.band16 >= 0 && t.band16 <= 3);
+         (t.band16 >= 0 && t.band16 <= 3) && (t.wfa_classes == 0 || t.wfa_classes == 1) && t.wfa_cls_global >= 0 && t.wfa_cls_global <= 7 &&
+         [&] {
+           for (int k = 0; k < 3; ++k) {
+             const int32_t th = t.wfa_cls_threads[k];
+             if (th != 64 && th != 128 && th != 256 && th != 512) return false;
+           }
+           return true;
+         }();
 }
 std::string tune_key() {
   int v = 0;
@@ -1001,7 +1139,7 @@ aim_status aim_tune_save(aim_context *c, const char *path) {
   if (!c || !path) return fail(AIM_ERR_INVALID_ARG, "NULL argument");
   std::ofstream f(path);
   if (!f) return fail(AIM_ERR_INVALID_ARG, "cannot write %s", path);
-  f << "aim-tune 1 " << c->arch << " " << tune_key() << "\n";
+  f << "aim-tune 2 " << c->arch << " " << tune_key() << "\n";
   for (auto &kv : c->tunes) {
     int32_t v[TUNE_FIELDS];
     tune_to(kv.second, v);
@@ -1019,7 +1157,7 @@ aim_status aim_tune_load(aim_context *c, const char *path) {
   if (!f) return fail(AIM_ERR_NOT_FOUND, "cannot read %s", path);
   std::string magic, ver, arch, key;
   f >> magic >> ver >> arch >> key;
-  if (magic != "aim-tune" || ver != "1") return fail(AIM_ERR_INVALID_ARG, "not a tune file: %s", path);
+  if (magic != "aim-tune" || ver != "2") return fail(AIM_ERR_INVALID_ARG, "not a tune file: %s", path);
   if (arch != c->arch || key != tune_key())
     return fail(AIM_ERR_NOT_FOUND, "tune file is for %s / runtime %s", arch.c_str(), key.c_str());
   std::map<std::pair<int32_t, int32_t>, Tune> loaded;

@@ -1,0 +1,411 @@
+// Gap-affine wavefront alignment of pairs whose wavefronts outgrow the
+// one-wavefront pass, with the recent wavefronts resident in LDS (k_wfa_lds).
+//
+// Paper: System and Methods, "Wavefront Algorithm (WFA)" (the recurrences of
+// wfa.hip, restated there) and "Data Management" (the components a step
+// needs are kept in fast on-chip memory, the rest off chip): here the last
+// max(x, o+e) + 1 wavefronts of M and the last e + 1 of I and D live in the
+// workgroup's LDS, the origin codes of every cell (what the backtrace
+// chooses) go to an HBM slot, and the pair's CIGAR is walked from them.
+//
+// Layout.  A class has a window of W diagonals, [-W/2, W/2).  A ring row is
+// indexed by absolute diagonal (entry k + W/2 + MG), two 16-bit offsets per
+// 32-bit word (the even entry in the low half), with MG entries of margin at
+// each end.  Entries outside a wavefront's range hold a negative (absent)
+// value: each row is written over its range and over MG/2 words beyond each
+// end, which covers every later read of it (a row is read for at most
+// max(x, o+e) more scores, and the range grows by at most one diagonal per
+// score at each end), so a cell needs no range tests, only the table bound
+// j <= min(n, m + k).  Sources of a score that is absent (null, or negative)
+// read a row of absent marks.
+//
+// Arithmetic.  A lane computes the two diagonals of one word with packed
+// 16-bit max / add / subtract.  An absent mark starts at -32768 and can only
+// grow by one per score, so a pair stays below s_cap (16,000) scores here;
+// offsets are at most n <= 32,000.  The candidates are clipped as the oracle
+// clips them: I = max(M_{s-o-e}[k+1], I_{s-e}[k+1]), dropped when its row
+// passes m; D = max(M_{s-o-e}[k-1], D_{s-e}[k-1]) + 1, dropped past n;
+// X = M_{s-x}[k] + 1, dropped past either end.
+//
+// A pair whose wavefront leaves the window goes to the next class (route),
+// with a prediction of the window it needs.
+#include "aim_internal.h"
+
+namespace aim {
+namespace {
+
+#include "wfa_common.h"
+
+constexpr int ENTRY_WORDS = 4;  // full-store table entry, as counted by the other passes
+constexpr uint32_t ABSENT2 = 0x80008000u;
+
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ s16x2 as2(uint32_t v) { return __builtin_bit_cast(s16x2, v); }
+__device__ __forceinline__ uint32_t as1(s16x2 v) { return __builtin_bit_cast(uint32_t, v); }
+
+// c where c <= lim, else exactly the absent mark; an absent c stays negative.
+// The sign mask is one packed arithmetic shift (written out: left to itself
+// the compiler turns the shift-and-mask into a select, which it does half by
+// half), the choice one bitfield insert.
+__device__ __forceinline__ s16x2 clip2(s16x2 c, s16x2 lim) {
+  const uint32_t d = as1(lim - c);  // sign set in a half where c > lim
+  uint32_t bad;
+  asm("v_pk_ashrrev_i16 %0, %1, %2" : "=v"(bad) : "v"(0x000f000fu), "v"(d));
+  return as2((bad & ABSENT2) | (~bad & as1(c)));
+}
+
+// The origin codes of the two cells of a word as one byte (low nibble: the
+// even diagonal): bits 0-1 the first of X, I, D that attains M, bit 2 I
+// opened from M_{s-o-e} (also on a tie), bit 3 the same for D.  Computed
+// from the signs of saturated packed differences.
+__device__ __forceinline__ uint32_t codes2(s16x2 X, s16x2 I, s16x2 Mv, s16x2 Mo_up, s16x2 Ie_up,
+                                           s16x2 Mo_dn, s16x2 De_dn) {
+  const uint32_t sx = as1(__builtin_elementwise_sub_sat(X, Mv));         // sign: X < M
+  const uint32_t si = as1(__builtin_elementwise_sub_sat(I, Mv));         // sign: I < M
+  const uint32_t sio = as1(__builtin_elementwise_sub_sat(Mo_up, Ie_up));  // sign: I extended
+  const uint32_t sdo = as1(__builtin_elementwise_sub_sat(Mo_dn, De_dn));  // sign: D extended
+  const uint32_t a = (sx >> 15) & 0x10001u, b = (si >> 15) & 0x10001u;
+  const uint32_t c = (~sio >> 15) & 0x10001u, d = (~sdo >> 15) & 0x10001u;
+  const uint32_t nib = (a & ~b) | ((a & b) << 1) | (c << 2) | (d << 3);
+  return (nib | (nib >> 12)) & 0xffu;
+}
+
+// Extend offset f (absent when negative) on diagonal k of the staged pair;
+// lim = min(n, m + k).  The first 16 bases by every lane without a branch,
+// the rest only where all 16 matched.
+__device__ __forceinline__ int32_t ext_cell(const uint32_t *P32, const uint32_t *T32, int32_t m, int32_t n,
+                                            int32_t k, int32_t f, int32_t lim) {
+  const bool live = f >= 0;
+  const int32_t j0 = live ? f : 0, i0 = live ? f - k : 0;
+  const int32_t le = live ? lim - f : 0;
+  const uint32_t d = __builtin_amdgcn_alignbit(P32[(i0 >> 4) + 1], P32[i0 >> 4], (uint32_t)i0 << 1) ^
+                     __builtin_amdgcn_alignbit(T32[(j0 >> 4) + 1], T32[j0 >> 4], (uint32_t)j0 << 1);
+  const int32_t run = min(d ? (int32_t)(__builtin_ctz(d) >> 1) : 16, le);
+  int32_t g = j0 + run;
+  if (run == 16) g = extend_lds(P32, m, T32, n, k, g);
+  return live ? g : f;
+}
+
+// GRING: the ring rows live in this workgroup's slot of a global buffer
+// (HBM, cached in L2 and the infinity cache) instead of LDS, so that many
+// more workgroups fit a CU; the arithmetic is the same.
+template <int T, bool GRING>
+__global__ __launch_bounds__(T) void k_wfa_lds(Seqs S, Outs O, Scoring P, Work Wk, WfaLds L) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int tid = threadIdx.x;
+  const int32_t x = P.x, oe = P.o + P.e, e = P.e, R = L.R, RE = P.e + 1;
+  const int32_t W = L.W, kbase = -(W >> 1), MG = L.MG, MGW = L.MG >> 1;
+  const int32_t RW = (W + 2 * MG) >> 1;  // 32-bit words per ring row
+  const int32_t SW = L.seq_words + 1;     // staged words per sequence, one of padding
+  uint64_t *sP = (uint64_t *)smem;
+  uint64_t *sT = sP + SW;
+  int32_t *tab = (int32_t *)(sT + SW);  // per M slot: lo, hi, flags (1 present, 2 has I and D), -
+  int32_t *shv = tab + 4 * R;           // [0] work item, [1] end cell reached, [2] progress
+  uint32_t *ringM = GRING ? L.gring + (int64_t)blockIdx.x * L.gring_slot : (uint32_t *)(shv + 8);
+  uint32_t *ringI = ringM + (int64_t)R * RW;
+  uint32_t *ringD = ringI + (int64_t)RE * RW;
+  uint32_t *nullrow = ringD + (int64_t)RE * RW;
+  const uint32_t *P32 = reinterpret_cast<const uint32_t *>(sP);
+  const uint32_t *T32 = reinterpret_cast<const uint32_t *>(sT);
+  const int32_t count = Wk.count ? __builtin_amdgcn_readfirstlane(*(volatile const int32_t *)Wk.count)
+                                 : (int32_t)Wk.n;
+  // a workgroup the work can never reach leaves before touching the counter
+  if ((int32_t)blockIdx.x >= count) return;
+  for (int32_t q = tid; q < RW; q += T) nullrow[q] = ABSENT2;
+  uint8_t *cslot = L.codes + (int64_t)blockIdx.x * L.code_slot;
+  int32_t *ctab = reinterpret_cast<int32_t *>(cslot);  // per score: lowest kept diagonal, hi, code offset
+  uint8_t *cbytes = cslot + (int64_t)L.steps_cap * 12;
+  auto widx = [&](int32_t k) { return (k - kbase + MG) >> 1; };
+  for (;;) {
+    __syncthreads();
+    if (tid == 0) shv[0] = atomicAdd(Wk.counter, 1);
+    __syncthreads();
+    const int32_t li = __builtin_amdgcn_readfirstlane(shv[0]);
+    if (li >= count) break;
+    const int64_t p = Wk.idx ? (int64_t)__builtin_amdgcn_readfirstlane(Wk.idx[li]) : li;
+    if (O.flags && __builtin_amdgcn_readfirstlane((int32_t)O.flags[p])) {
+      if (tid == 0) { O.score[p] = -1; O.status[p] = ST_INVALID; O.nruns[p] = 0; }
+      continue;
+    }
+    const int32_t m = __builtin_amdgcn_readfirstlane(S.pat_len[p]);
+    const int32_t n = __builtin_amdgcn_readfirstlane(S.txt_len[p]);
+    const int64_t pnw = (m + 31) >> 5, tnw = (n + 31) >> 5;
+    {
+      // the host sends only batches whose sequences fit the staging area
+      const uint64_t *gP = S.pat + S.pat_off[p], *gT = S.txt + S.txt_off[p];
+      for (int64_t q = tid; q <= pnw; q += T) sP[q] = q < pnw ? gP[q] : 0ull;
+      for (int64_t q = tid; q <= tnw; q += T) sT[q] = q < tnw ? gT[q] : 0ull;
+    }
+    if (tid < R) tab[4 * tid + 2] = 0;
+    if (tid == 0) shv[1] = 0;
+    const int32_t kend = n - m;
+    const int64_t ad = m > n ? m - n : n - m;
+    const int64_t up1 = (int64_t)x * min(m, n) + (ad ? (int64_t)P.o + ad * e : 0);
+    const int64_t up2 = (m ? (int64_t)P.o + (int64_t)m * e : 0) + (n ? (int64_t)P.o + (int64_t)n * e : 0);
+    const int32_t s_upper = (int32_t)min<int64_t>(min(up1, up2), INT32_MAX - 1);
+    const int32_t s_lim = min(P.max_score >= 0 ? min(P.max_score, s_upper) : s_upper, L.s_cap);
+    // 1 aligned, 2 rejected, 3 left the window, 4 past its bound, 5 past s_cap
+    int result = (kend < kbase || kend >= kbase + W) ? 3 : 0;
+    int32_t ext_out = result ? max(-kend, kend + 1) : 0;
+    int32_t s = 0;
+    int64_t need = 0, cb = 0;
+    bool keep = P.want_cigar != 0;
+    __syncthreads();  // staged words, cleared table and flag visible
+    if (!result) {
+      // s = 0: M_0[0] = extend(0); absent marks around it
+      uint32_t *r0 = ringM;
+      const int32_t qc = widx(0);
+      for (int32_t q = qc - MGW - 1 + tid; q <= qc + MGW + 1; q += T)
+        if (q != qc) r0[q] = ABSENT2;
+      if (tid == 0) {
+        const int32_t f = extend_lds(P32, m, T32, n, 0, 0);
+        r0[qc] = (uint32_t)(f & 0xffff) | 0x80000000u;  // diagonal 1 (high half) absent
+        tab[0] = 0;
+        tab[1] = 0;
+        tab[2] = 1;  // present, no I or D
+        if (kend == 0 && f >= n) shv[1] = 1;
+      }
+      need = ENTRY_WORDS + 2;
+      __syncthreads();  // the step loop reads the end-cell flag first
+    }
+    int32_t sl = 0, sE = 0;  // s mod R, s mod (e + 1)
+    const s16x2 M2 = (s16x2)(short)m, N2 = (s16x2)(short)n;
+    const int4 *tab4 = reinterpret_cast<const int4 *>(tab);
+    // One word of score s (diagonals k0 = 2q - MG + kbase and k0 + 1) from
+    // its eight source words: candidates, codes, extension, stores.
+    auto word = [&](int32_t q, uint32_t o_m, uint32_t o_0, uint32_t o_p, uint32_t i_0, uint32_t i_p,
+                    uint32_t d_m, uint32_t d_0, uint32_t x_0, uint32_t *dM, uint32_t *dI, uint32_t *dD,
+                    uint8_t *crow, int32_t q_lo) {
+      const int32_t k0 = 2 * q - MG + kbase;
+      const s16x2 K2 = {(short)k0, (short)(k0 + 1)};
+      const s16x2 LIM = __builtin_elementwise_min(__builtin_elementwise_add_sat(M2, K2), N2);
+      const s16x2 Mo_up = as2(__builtin_amdgcn_alignbit(o_p, o_0, 16));  // M_{s-o-e}[k + 1]
+      const s16x2 Mo_dn = as2(__builtin_amdgcn_alignbit(o_0, o_m, 16));  // M_{s-o-e}[k - 1]
+      const s16x2 Ie_up = as2(__builtin_amdgcn_alignbit(i_p, i_0, 16));  // I_{s-e}[k + 1]
+      const s16x2 De_dn = as2(__builtin_amdgcn_alignbit(d_0, d_m, 16));  // D_{s-e}[k - 1]
+      const s16x2 I = clip2(__builtin_elementwise_max(Mo_up, Ie_up), LIM);
+      const s16x2 D = clip2(__builtin_elementwise_max(Mo_dn, De_dn) + (short)1, LIM);
+      const s16x2 X = clip2(as2(x_0) + (short)1, LIM);
+      const s16x2 Mv = __builtin_elementwise_max(X, __builtin_elementwise_max(I, D));
+      if (crow) crow[q - q_lo] = (uint8_t)codes2(X, I, Mv, Mo_up, Ie_up, Mo_dn, De_dn);
+      const int32_t f0 = ext_cell(P32, T32, m, n, k0, Mv.x, LIM.x);
+      const int32_t f1 = ext_cell(P32, T32, m, n, k0 + 1, Mv.y, LIM.y);
+      dM[q] = __builtin_amdgcn_perm((uint32_t)f1, (uint32_t)f0, 0x05040100u);
+      dI[q] = as1(I);
+      dD[q] = as1(D);
+      if ((k0 == kend && f0 >= n) || (k0 + 1 == kend && f1 >= n)) shv[1] = 1;
+    };
+    while (!result) {
+      // after a barrier: the end-cell flag of the last score and the table
+      // entries of this score's sources, in one round trip to LDS
+      const int32_t nsl = sl + 1 == R ? 0 : sl + 1;
+      const int32_t nsE = sE + 1 == RE ? 0 : sE + 1;
+      const int32_t qx = nsl >= x ? nsl - x : nsl - x + R;
+      const int32_t qo = nsl >= oe ? nsl - oe : nsl - oe + R;
+      const int32_t qe = nsl >= e ? nsl - e : nsl - e + R;
+      const int32_t qeE = nsE + 1 == RE ? 0 : nsE + 1;  // (s - e) mod (e + 1)
+      const int32_t hitv = shv[1];
+      const int4 ex = tab4[qx], eo = tab4[qo], ee = tab4[qe];
+      if (__builtin_amdgcn_readfirstlane(hitv)) {
+        result = 1;
+        break;
+      }
+      ++s;
+      if (s > s_lim) {
+        result = (P.max_score >= 0 && s > P.max_score) ? 2 : (s > s_upper ? 4 : 5);
+        break;
+      }
+      sl = nsl;
+      sE = nsE;
+      const int32_t fx = s >= x ? __builtin_amdgcn_readfirstlane(ex.z) : 0;
+      const int32_t fo = s >= oe ? __builtin_amdgcn_readfirstlane(eo.z) : 0;
+      const int32_t fe = s >= e ? __builtin_amdgcn_readfirstlane(ee.z) : 0;
+      // the range: over the non-null sources (the one of s - e only when it
+      // has I and D), widened by one diagonal and clipped to [-m, n]
+      int32_t lo = INT32_MAX, hi = INT32_MIN;
+      if (fx & 1) {
+        lo = min(lo, __builtin_amdgcn_readfirstlane(ex.x));
+        hi = max(hi, __builtin_amdgcn_readfirstlane(ex.y));
+      }
+      if (fo & 1) {
+        lo = min(lo, __builtin_amdgcn_readfirstlane(eo.x));
+        hi = max(hi, __builtin_amdgcn_readfirstlane(eo.y));
+      }
+      if (fe & 2) {
+        lo = min(lo, __builtin_amdgcn_readfirstlane(ee.x));
+        hi = max(hi, __builtin_amdgcn_readfirstlane(ee.y));
+      }
+      const bool present = ((fx | fo) & 1) || (fe & 2);
+      if (present) {
+        lo = max(lo - 1, -m);
+        hi = min(hi + 1, n);
+      }
+      if (!present || lo > hi) {
+        // a null wavefront: nothing to store, its readers take absent marks
+        if (tid == 0) {
+          tab[4 * sl + 2] = 0;
+          if (keep && s < L.steps_cap) { ctab[3 * s] = 1; ctab[3 * s + 1] = 0; ctab[3 * s + 2] = 0; }
+        }
+        need += ENTRY_WORDS;
+        __syncthreads();
+        continue;
+      }
+      if (lo < kbase || hi >= kbase + W) {
+        result = 3;
+        ext_out = max(-lo, hi + 1);
+        break;
+      }
+      const uint32_t *Mx = (fx & 1) ? ringM + (int64_t)qx * RW : nullrow;
+      const uint32_t *Mo = (fo & 1) ? ringM + (int64_t)qo * RW : nullrow;
+      const uint32_t *Ie = (fe & 2) ? ringI + (int64_t)qeE * RW : nullrow;
+      const uint32_t *De = (fe & 2) ? ringD + (int64_t)qeE * RW : nullrow;
+      uint32_t *dM = ringM + (int64_t)sl * RW;
+      uint32_t *dI = ringI + (int64_t)sE * RW;
+      uint32_t *dD = ringD + (int64_t)sE * RW;
+      const int32_t q_lo = widx(lo), q_hi = widx(hi);
+      const int32_t nbytes = q_hi - q_lo + 1;
+      if (keep && (s >= L.steps_cap || cb + nbytes > L.code_cap)) keep = false;
+      uint8_t *crow = keep ? cbytes + cb : nullptr;
+      // two words per lane and trip, their sixteen source loads issued first
+      for (int32_t qa = q_lo + tid; qa <= q_hi; qa += 2 * T) {
+        const bool vb = qa + T <= q_hi;
+        const int32_t qb = vb ? qa + T : qa;
+        const uint32_t a_om = Mo[qa - 1], a_o0 = Mo[qa], a_op = Mo[qa + 1];
+        const uint32_t a_i0 = Ie[qa], a_ip = Ie[qa + 1], a_dm = De[qa - 1], a_d0 = De[qa], a_x = Mx[qa];
+        const uint32_t b_om = Mo[qb - 1], b_o0 = Mo[qb], b_op = Mo[qb + 1];
+        const uint32_t b_i0 = Ie[qb], b_ip = Ie[qb + 1], b_dm = De[qb - 1], b_d0 = De[qb], b_x = Mx[qb];
+        word(qa, a_om, a_o0, a_op, a_i0, a_ip, a_dm, a_d0, a_x, dM, dI, dD, crow, q_lo);
+        if (vb) word(qb, b_om, b_o0, b_op, b_i0, b_ip, b_dm, b_d0, b_x, dM, dI, dD, crow, q_lo);
+      }
+      // absent marks for MG entries beyond each end of the three new rows
+      for (int32_t t = tid; t < 2 * MGW; t += T) {
+        const int32_t q = t < MGW ? q_lo - MGW + t : q_hi + 1 + (t - MGW);
+        dM[q] = ABSENT2;
+        dI[q] = ABSENT2;
+        dD[q] = ABSENT2;
+      }
+      if (tid == 0) {
+        tab[4 * sl] = lo;
+        tab[4 * sl + 1] = hi;
+        tab[4 * sl + 2] = 3;
+        if (keep) {
+          ctab[3 * s] = 2 * q_lo - MG + kbase;
+          ctab[3 * s + 1] = hi;
+          ctab[3 * s + 2] = (int32_t)cb;
+        }
+      }
+      if (keep) cb += nbytes;
+      need += ENTRY_WORDS + (3 * (int64_t)(hi - lo + 1) + 1) / 2;
+      __syncthreads();
+    }
+    if (result == 3 || result == 5) {
+      // on to a wider class, with the window the pair is predicted to need:
+      // from the furthest anti-diagonal i + j any kept M offset reaches
+      int32_t pred = INT32_MAX;
+      if (result == 3) {
+        if (tid == 0) shv[2] = 0;
+        __syncthreads();
+        int32_t prog = 0;
+        for (int32_t t = 0; t < R; ++t) {
+          const int32_t fl = __builtin_amdgcn_readfirstlane(tab[4 * t + 2]);
+          if (!(fl & 1)) continue;
+          const int32_t tlo = __builtin_amdgcn_readfirstlane(tab[4 * t]);
+          const int32_t thi = __builtin_amdgcn_readfirstlane(tab[4 * t + 1]);
+          const uint32_t *row = ringM + (int64_t)t * RW;
+          for (int32_t k = tlo + tid; k <= thi; k += T) {
+            const int32_t ix = k - kbase + MG;
+            const int32_t f = (int32_t)(int16_t)(row[ix >> 1] >> (16 * (ix & 1)));
+            if (f >= 0) prog = max(prog, 2 * f - k);
+          }
+        }
+        prog = wave_max_i32(prog);
+        if ((tid & 63) == 0) atomicMax(&shv[2], prog);
+        __syncthreads();
+        pred = predict_extent(ext_out, __builtin_amdgcn_readfirstlane(shv[2]), m, n);
+      }
+      if (tid == 0) route_pair(L.route, L.my_class, p, pred);
+      continue;
+    }
+    bool walked = false;
+    if (result == 1 && keep) {
+      // the codes and table are global stores of every wave of this
+      // workgroup: the barrier orders them before the walk's loads, the
+      // agent-scope acquire drops L1 lines of an earlier pair's walk
+      __syncthreads();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      const int32_t tok_cap = (R + 2 * RE) * RW;  // the ring, free now, holds the walk's tokens
+      if (tid < 64) {
+        const int32_t sfin = s;
+        auto code_at = [&](int32_t cs, int32_t k) -> int32_t {  // per lane
+          if (cs < 1 || cs > sfin) return -1;
+          const int32_t klo = ctab[3 * cs], khi = ctab[3 * cs + 1];
+          if (k < klo || k > khi) return -1;
+          const uint32_t b = cbytes[ctab[3 * cs + 2] + ((k - klo) >> 1)];
+          return (int32_t)(((k - klo) & 1) ? (b >> 4) : (b & 15u));
+        };
+        auto ext = [&](int32_t k, int32_t f) { return extend_lds(P32, m, T32, n, k, f); };
+        walked = walk_codes<true>(O, p, code_at, ext, x, oe, e, m, n, s, ringM, tok_cap);
+        if (!walked && tid == 0 && L.walk_fail) atomicAdd(L.walk_fail, 1);
+      }
+      __syncthreads();
+    } else if (result == 1 && P.want_cigar && tid == 0 && L.walk_skip) {
+      atomicAdd(L.walk_skip, 1);  // codes not kept: the full-store pass walks it
+    }
+    if (tid == 0) {
+      if (result == 2 || result == 4) {
+        O.score[p] = -1;
+        O.status[p] = result == 2 ? ST_REJECTED : ST_INVALID;
+        O.nruns[p] = 0;
+      } else {
+        O.score[p] = s * P.unit;
+        O.status[p] = ST_ALIGNED;
+        if (!walked) O.nruns[p] = 0;
+        if (P.want_cigar && !walked) {
+          L.need[p] = need;
+          int c = 0;
+          while (c < 3 && need > L.need_cap[c]) ++c;
+          if (need > L.need_cap[3]) {
+            O.status[p] = ST_OVERFLOW;  // full store larger than any arena class
+          } else {
+            const int32_t k = atomicAdd(L.need_count[c], 1);
+            L.need_list[c][k] = (int32_t)p;
+            atomicMax(L.need_max[c], (int32_t)need);
+          }
+        }
+      }
+    }
+  }
+}
+
+}  // namespace
+
+int64_t wfa_ring_words(int32_t W, int32_t MG, int32_t R, int32_t e) {
+  return (int64_t)(R + 2 * (e + 1) + 1) * ((W + 2 * MG) / 2);
+}
+
+size_t wfa_lds_bytes(int32_t W, int32_t MG, int32_t R, int32_t e, int32_t seq_words, bool gring) {
+  return 2 * (size_t)(seq_words + 1) * 8 + (size_t)R * 16 + 32 + (gring ? 0 : (size_t)wfa_ring_words(W, MG, R, e) * 4);
+}
+
+hipError_t launch_wfa_lds(const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk, const WfaLds &L,
+                          int32_t threads, int32_t nslots, hipStream_t s) {
+  const bool g = L.gring != nullptr;
+  const size_t lds = wfa_lds_bytes(L.W, L.MG, L.R, P.e, L.seq_words, g);
+#define AIM_LAUNCH_LDS(TT)                                                                      \
+  if (g)                                                                                        \
+    hipLaunchKernelGGL((k_wfa_lds<TT, true>), dim3(nslots), dim3(TT), lds, s, S, O, P, Wk, L);  \
+  else                                                                                          \
+    hipLaunchKernelGGL((k_wfa_lds<TT, false>), dim3(nslots), dim3(TT), lds, s, S, O, P, Wk, L);
+  switch (threads) {
+    case 64: AIM_LAUNCH_LDS(64) break;
+    case 128: AIM_LAUNCH_LDS(128) break;
+    case 256: AIM_LAUNCH_LDS(256) break;
+    case 512: AIM_LAUNCH_LDS(512) break;
+    default: return hipErrorInvalidValue;
+  }
+#undef AIM_LAUNCH_LDS
+  return hipGetLastError();
+}
+
+}  // namespace aim
