@@ -51,7 +51,7 @@ WFA_OPS_PER_CELL, WFA_OPS_PER_WORD = 8, 10
 # kernel source they were taken on (first 16 hex of its SHA-256)
 MEASURED_TRAFFIC = {("swg150", "k_band16<32>"): ("32a97daf6917c56a", 3.0790e9)}
 KERNEL_SOURCE = {"k_band16<32>": "dp_band16.hip", "k_band<32>": "dp_band.hip",
-                 "k_wfa_score16": "wfa.hip", "k_wfa_score": "wfa.hip"}
+                 "k_wfa_score16": "wfa.hip", "k_wfa_score": "wfa.hip", "k_wfa_lds": "wfa_lds.hip"}
 
 WORKLOAD_TEXT = {
     "swg150": "Gotoh 4/6/2 global, 1,000,000 pairs x 150 bp, 4% error (1/3 sub, ins, del), "
@@ -156,28 +156,36 @@ def roofline(run, phases, stats, steps):
                 "units_per_launch": cells, "unit_name": "band cells (m x 32 per pair)"}
     if w["alg"] != "wfa":
         return None
-    names = {"wfa_score": "k_wfa_score16", "wfa_score_hbm": "k_wfa_score"}
-    present = [k for k in names if k in phases]
-    if not present:
+    # the WFA passes of one call: the one-wavefront pass (k_wfa_score16) over
+    # every pair, completing those whose wavefronts stay in its window; the
+    # window classes (k_wfa_lds, one launch per class, taken together: the
+    # split of pairs between classes is a runtime prediction) completing the
+    # rest; the HBM-ring pass (k_wfa_score) for pairs past 16,000 scores
+    steps = max(1, phases.get("wfa_score", (0.0, 1))[1])
+    groups = {"k_wfa_score16": ["wfa_score"], "k_wfa_lds": [k for k in phases if k.startswith("wfa_lds")],
+              "k_wfa_score": ["wfa_score_hbm"]}
+    per_call = {g: sum(phases[k][0] for k in ks if k in phases) / steps for g, ks in groups.items()}
+    kname = max(per_call, key=per_call.get)
+    if per_call[kname] <= 0:
         return None
-    ph = max(present, key=lambda k: phases[k][0])
-    ms, launches = phases[ph]
+    ms = per_call[kname]
+    launches = sum(phases[k][1] for k in groups[kname] if k in phases) // steps
     units = wfa_units(run.name, stats.get("wfa_window", 0)) if run.n == w["total"] else None
-    out = {"bound": "alu", "kernel": names[ph], "avg_launch_ms": round(ms / max(launches, 1), 4),
+    out = {"bound": "alu", "kernel": kname, "avg_launch_ms": round(ms, 4), "launches_per_call": launches,
            "peak": round(PEAK_INT32_TOPS, 1), "unit": "Tops/s (int32)",
            "ops_per_unit": {"wavefront cell": WFA_OPS_PER_CELL, "extension word": WFA_OPS_PER_WORD},
            "achieved": None, "frac": None, "traffic": None}
-    if units:
-        side = "inside" if ph == "wfa_score" else "outside"
+    if units and kname != "k_wfa_score":
+        side = "inside" if kname == "k_wfa_score16" else "outside"
         cells, words = units[side]
         ops = WFA_OPS_PER_CELL * cells + WFA_OPS_PER_WORD * words
-        t = ms / launches / 1000.0
+        t = ms / 1000.0
         out.update({"achieved": round(ops / t / 1e12, 3), "frac": round(ops / t / 1e12 / PEAK_INT32_TOPS, 4),
                     "units_per_launch": {"cells": cells, "words": words},
-                    "unit_name": "wavefront cells of the pairs this launch completes (%s the %d-diagonal "
-                                 "window)" % (side, stats.get("wfa_window", 0))})
-        meas = MEASURED_TRAFFIC.get((run.name, names[ph]))
-        if meas and meas[0] == src_hash(names[ph]):
+                    "unit_name": "wavefront cells of the pairs %s completes (%s the %d-diagonal window), "
+                                 "its launches of one call together" % (kname, side, stats.get("wfa_window", 0))})
+        meas = MEASURED_TRAFFIC.get((run.name, kname))
+        if meas and meas[0] == src_hash(kname):
             out["traffic"] = meas[1]
         # every WFA kernel of the step together
         tot_ms = sum(v[0] for k, v in phases.items() if k.startswith("wfa")) / steps

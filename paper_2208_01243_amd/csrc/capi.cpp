@@ -100,7 +100,7 @@ struct Tune {
                               // 3: 2 for batches of at least SPLIT_MIN_PAIRS pairs, else 1)
   int32_t wfa_classes = 1;    // WFA pairs wider than the one-wavefront window: LDS-window
                               // classes (1) or straight to the HBM-ring pass (0)
-  int32_t wfa_cls_threads[3] = {64, 128, 256};  // workgroup size of each window class
+  int32_t wfa_cls_threads[3] = {64, 128, 128};  // workgroup size of each window class
   int32_t wfa_cls_global = 7;  // bit c: class c + 1 keeps its ring in a global buffer, not LDS
 };
 
@@ -450,7 +450,8 @@ aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const
       // in turn and share one code buffer and one ring buffer, each within a
       // third of the scratch budget: fewer workgroups when the slots would
       // not fit (at least one, with at least 64 KB of codes).
-      D.gring_slot = cls[k].global ? (aim::wfa_ring_words(D.W, MG, pl.R, P.e) + 63) / 64 * 64 : 0;
+      // (plus the guard word before the rows)
+      D.gring_slot = cls[k].global ? (aim::wfa_ring_words(D.W, MG, pl.R, P.e) + 1 + 63) / 64 * 64 : 0;
       const int64_t share = c->limit() / 3;
       const int64_t fixed = (int64_t)D.steps_cap * 12 + D.gring_slot * 4;
       cls[k].nslots = (int32_t)std::max<int64_t>(1, std::min<int64_t>(cls[k].nslots, share / (fixed + (64 << 10))));

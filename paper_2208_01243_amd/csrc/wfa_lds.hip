@@ -87,6 +87,41 @@ __device__ __forceinline__ int32_t ext_cell(const uint32_t *P32, const uint32_t 
   return live ? g : f;
 }
 
+// Buffer resource word 3 for raw (untyped) buffer access on CDNA: 32-bit
+// data format, so that loads return data and accesses past num_records read
+// zero / are dropped.
+constexpr int32_t BUF_FLAGS = 0x00027000;
+
+// The ring rows of one workgroup: R rows of M, e + 1 of I, e + 1 of D, then
+// a row of absent marks; row r, word q.  In LDS, or in a global slot reached
+// through a buffer resource (a 32-bit lane offset, the row in the scalar
+// offset), which spares the 64-bit address arithmetic per access.
+template <bool G>
+struct RingIO;
+template <>
+struct RingIO<false> {
+  uint32_t *base;
+  int32_t RW;
+  __device__ __forceinline__ uint32_t ld(int32_t row, int32_t q, int32_t delta) const {
+    return base[row * RW + q + delta];
+  }
+  __device__ __forceinline__ void st(int32_t row, int32_t q, uint32_t v) const { base[row * RW + q] = v; }
+};
+// The resource starts one word before row 0, so that the scalar offset of
+// row 0 word q - 1 is (1 + 0 - 1) * 4 = 0 and never negative (the hardware
+// adds it unsigned).
+template <>
+struct RingIO<true> {
+  __amdgpu_buffer_rsrc_t rs;
+  int32_t RW;
+  __device__ __forceinline__ uint32_t ld(int32_t row, int32_t q, int32_t delta) const {
+    return __builtin_amdgcn_raw_buffer_load_b32(rs, q * 4, (1 + row * RW + delta) * 4, 0);
+  }
+  __device__ __forceinline__ void st(int32_t row, int32_t q, uint32_t v) const {
+    __builtin_amdgcn_raw_buffer_store_b32(v, rs, q * 4, (1 + row * RW) * 4, 0);
+  }
+};
+
 // GRING: the ring rows live in this workgroup's slot of a global buffer
 // (HBM, cached in L2 and the infinity cache) instead of LDS, so that many
 // more workgroups fit a CU; the arithmetic is the same.
@@ -102,10 +137,16 @@ __global__ __launch_bounds__(T) void k_wfa_lds(Seqs S, Outs O, Scoring P, Work W
   uint64_t *sT = sP + SW;
   int32_t *tab = (int32_t *)(sT + SW);  // per M slot: lo, hi, flags (1 present, 2 has I and D), -
   int32_t *shv = tab + 4 * R;           // [0] work item, [1] end cell reached, [2] progress
-  uint32_t *ringM = GRING ? L.gring + (int64_t)blockIdx.x * L.gring_slot : (uint32_t *)(shv + 8);
-  uint32_t *ringI = ringM + (int64_t)R * RW;
-  uint32_t *ringD = ringI + (int64_t)RE * RW;
-  uint32_t *nullrow = ringD + (int64_t)RE * RW;
+  // a global slot: one guard word, then the rows (see RingIO<true>)
+  uint32_t *ringM = GRING ? L.gring + (int64_t)blockIdx.x * L.gring_slot + 1 : (uint32_t *)(shv + 8);
+  uint32_t *nullrow = ringM + (int64_t)(R + 2 * RE) * RW;
+  const int32_t NULLR = R + 2 * RE;  // the row of absent marks
+  RingIO<GRING> ring;
+  if constexpr (GRING)
+    ring.rs = __builtin_amdgcn_make_buffer_rsrc(ringM - 1, 0, (int32_t)(L.gring_slot * 4), BUF_FLAGS);
+  else
+    ring.base = ringM;
+  ring.RW = RW;
   const uint32_t *P32 = reinterpret_cast<const uint32_t *>(sP);
   const uint32_t *T32 = reinterpret_cast<const uint32_t *>(sT);
   const int32_t count = Wk.count ? __builtin_amdgcn_readfirstlane(*(volatile const int32_t *)Wk.count)
@@ -175,7 +216,7 @@ __global__ __launch_bounds__(T) void k_wfa_lds(Seqs S, Outs O, Scoring P, Work W
     // One word of score s (diagonals k0 = 2q - MG + kbase and k0 + 1) from
     // its eight source words: candidates, codes, extension, stores.
     auto word = [&](int32_t q, uint32_t o_m, uint32_t o_0, uint32_t o_p, uint32_t i_0, uint32_t i_p,
-                    uint32_t d_m, uint32_t d_0, uint32_t x_0, uint32_t *dM, uint32_t *dI, uint32_t *dD,
+                    uint32_t d_m, uint32_t d_0, uint32_t x_0, int32_t rM, int32_t rI, int32_t rD,
                     uint8_t *crow, int32_t q_lo) {
       const int32_t k0 = 2 * q - MG + kbase;
       const s16x2 K2 = {(short)k0, (short)(k0 + 1)};
@@ -188,12 +229,13 @@ __global__ __launch_bounds__(T) void k_wfa_lds(Seqs S, Outs O, Scoring P, Work W
       const s16x2 D = clip2(__builtin_elementwise_max(Mo_dn, De_dn) + (short)1, LIM);
       const s16x2 X = clip2(as2(x_0) + (short)1, LIM);
       const s16x2 Mv = __builtin_elementwise_max(X, __builtin_elementwise_max(I, D));
-      if (crow) crow[q - q_lo] = (uint8_t)codes2(X, I, Mv, Mo_up, Ie_up, Mo_dn, De_dn);
+      // a uniform row base and a 32-bit lane offset (a scalar-base store)
+      if (crow) crow[(uint32_t)(q - q_lo)] = (uint8_t)codes2(X, I, Mv, Mo_up, Ie_up, Mo_dn, De_dn);
       const int32_t f0 = ext_cell(P32, T32, m, n, k0, Mv.x, LIM.x);
       const int32_t f1 = ext_cell(P32, T32, m, n, k0 + 1, Mv.y, LIM.y);
-      dM[q] = __builtin_amdgcn_perm((uint32_t)f1, (uint32_t)f0, 0x05040100u);
-      dI[q] = as1(I);
-      dD[q] = as1(D);
+      ring.st(rM, q, __builtin_amdgcn_perm((uint32_t)f1, (uint32_t)f0, 0x05040100u));
+      ring.st(rI, q, as1(I));
+      ring.st(rD, q, as1(D));
       if ((k0 == kend && f0 >= n) || (k0 + 1 == kend && f1 >= n)) shv[1] = 1;
     };
     while (!result) {
@@ -256,13 +298,10 @@ __global__ __launch_bounds__(T) void k_wfa_lds(Seqs S, Outs O, Scoring P, Work W
         ext_out = max(-lo, hi + 1);
         break;
       }
-      const uint32_t *Mx = (fx & 1) ? ringM + (int64_t)qx * RW : nullrow;
-      const uint32_t *Mo = (fo & 1) ? ringM + (int64_t)qo * RW : nullrow;
-      const uint32_t *Ie = (fe & 2) ? ringI + (int64_t)qeE * RW : nullrow;
-      const uint32_t *De = (fe & 2) ? ringD + (int64_t)qeE * RW : nullrow;
-      uint32_t *dM = ringM + (int64_t)sl * RW;
-      uint32_t *dI = ringI + (int64_t)sE * RW;
-      uint32_t *dD = ringD + (int64_t)sE * RW;
+      // rows: sources (the absent row for a null source) and destinations
+      const int32_t rX = (fx & 1) ? qx : NULLR, rO = (fo & 1) ? qo : NULLR;
+      const int32_t rIe = (fe & 2) ? R + qeE : NULLR, rDe = (fe & 2) ? R + RE + qeE : NULLR;
+      const int32_t rM = sl, rI = R + sE, rD = R + RE + sE;
       const int32_t q_lo = widx(lo), q_hi = widx(hi);
       const int32_t nbytes = q_hi - q_lo + 1;
       if (keep && (s >= L.steps_cap || cb + nbytes > L.code_cap)) keep = false;
@@ -271,19 +310,21 @@ __global__ __launch_bounds__(T) void k_wfa_lds(Seqs S, Outs O, Scoring P, Work W
       for (int32_t qa = q_lo + tid; qa <= q_hi; qa += 2 * T) {
         const bool vb = qa + T <= q_hi;
         const int32_t qb = vb ? qa + T : qa;
-        const uint32_t a_om = Mo[qa - 1], a_o0 = Mo[qa], a_op = Mo[qa + 1];
-        const uint32_t a_i0 = Ie[qa], a_ip = Ie[qa + 1], a_dm = De[qa - 1], a_d0 = De[qa], a_x = Mx[qa];
-        const uint32_t b_om = Mo[qb - 1], b_o0 = Mo[qb], b_op = Mo[qb + 1];
-        const uint32_t b_i0 = Ie[qb], b_ip = Ie[qb + 1], b_dm = De[qb - 1], b_d0 = De[qb], b_x = Mx[qb];
-        word(qa, a_om, a_o0, a_op, a_i0, a_ip, a_dm, a_d0, a_x, dM, dI, dD, crow, q_lo);
-        if (vb) word(qb, b_om, b_o0, b_op, b_i0, b_ip, b_dm, b_d0, b_x, dM, dI, dD, crow, q_lo);
+        const uint32_t a_om = ring.ld(rO, qa, -1), a_o0 = ring.ld(rO, qa, 0), a_op = ring.ld(rO, qa, 1);
+        const uint32_t a_i0 = ring.ld(rIe, qa, 0), a_ip = ring.ld(rIe, qa, 1);
+        const uint32_t a_dm = ring.ld(rDe, qa, -1), a_d0 = ring.ld(rDe, qa, 0), a_x = ring.ld(rX, qa, 0);
+        const uint32_t b_om = ring.ld(rO, qb, -1), b_o0 = ring.ld(rO, qb, 0), b_op = ring.ld(rO, qb, 1);
+        const uint32_t b_i0 = ring.ld(rIe, qb, 0), b_ip = ring.ld(rIe, qb, 1);
+        const uint32_t b_dm = ring.ld(rDe, qb, -1), b_d0 = ring.ld(rDe, qb, 0), b_x = ring.ld(rX, qb, 0);
+        word(qa, a_om, a_o0, a_op, a_i0, a_ip, a_dm, a_d0, a_x, rM, rI, rD, crow, q_lo);
+        if (vb) word(qb, b_om, b_o0, b_op, b_i0, b_ip, b_dm, b_d0, b_x, rM, rI, rD, crow, q_lo);
       }
       // absent marks for MG entries beyond each end of the three new rows
       for (int32_t t = tid; t < 2 * MGW; t += T) {
         const int32_t q = t < MGW ? q_lo - MGW + t : q_hi + 1 + (t - MGW);
-        dM[q] = ABSENT2;
-        dI[q] = ABSENT2;
-        dD[q] = ABSENT2;
+        ring.st(rM, q, ABSENT2);
+        ring.st(rI, q, ABSENT2);
+        ring.st(rD, q, ABSENT2);
       }
       if (tid == 0) {
         tab[4 * sl] = lo;
