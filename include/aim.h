@@ -135,6 +135,7 @@ typedef enum { AIM_KERNEL_AUTO = 0, AIM_KERNEL_PLAIN = 1 } aim_kernel;
 /* aim_options.flags bits */
 #define AIM_FLAG_TIMING 1 /* time every kernel launch with HIP events (aim_timing) */
 #define AIM_FLAG_STATIC_SCRATCH 2 /* set up aim_align_batch_static's array at create */
+#define AIM_FLAG_NO_PREFILTER 4   /* aligning calls skip the pre-alignment filter */
 
 typedef struct {
   int32_t kernel;        /* aim_kernel */
@@ -185,6 +186,31 @@ aim_status aim_align_batch_static(aim_context *ctx, const aim_batch *pairs, int3
                                   aim_penalties pen, int32_t max_score, aim_results *out,
                                   void *stream);
 
+/* Exact pre-alignment filter (paper: Introduction, the third way to speed
+ * up alignment -- drop, before aligning them, the pairs that are too
+ * dissimilar, without losing any pair that meets the threshold).
+ * For each pair writes a lower bound of its optimal cost under (alg, pen):
+ *   lower[p] = max(A, B), where, for a pattern of m and a text of n bases,
+ *     B = gap_open + gap_extend * |m - n| if m != n, else 0  (a length
+ *         difference needs one gap run; gap_open counts as 0 for NW), and
+ *     A = min(mismatch, gap_extend) * lev + gap_open * [m != n], lev being
+ *         the Levenshtein distance (every alignment makes at least lev edits,
+ *         each costing at least min(mismatch, gap_extend)); A is taken only
+ *         when min(m, n) <= 1024, else lower = B;
+ *   pass[p]  = 1 if max_score < 0 or lower[p] <= max_score, else 0: a pair
+ *         with pass 0 is certain to be AIM_PAIR_REJECTED by aim_align_batch
+ *         with the same arguments.
+ * An invalid pair (see aim_batch) gets lower -1 and pass 0.
+ *   pairs: as for aim_align_batch; lower: device int32 [n_pairs];
+ *   pass: device int8 [n_pairs] (caller-owned).
+ * aim_align_batch runs the same filter in front of its aligners whenever
+ * max_score >= 0 (unless AIM_FLAG_NO_PREFILTER or AIM_KERNEL_PLAIN); its
+ * results do not change, only the work spent on rejected pairs.
+ * Asynchronous on `stream`, ordered with the context's other calls like
+ * aim_align_batch; errors as for aim_align_batch. */
+aim_status aim_prefilter(aim_context *ctx, const aim_batch *pairs, int32_t alg, aim_penalties pen,
+                         int32_t max_score, int32_t *lower, int8_t *pass, void *stream);
+
 /* Encode sequences as 2-bit words (the "2BIT" layout above).
  *   enc: AIM_ENC_ASCII or AIM_ENC_CODE; seq/off/len: device CSR (byte offsets);
  *   out_off: device int64 [n_seqs + 1], written: word offset of each output
@@ -234,7 +260,9 @@ aim_status aim_timing_reset(aim_context *ctx);
  *     inside it are aligned there, the others go to wider windows;
  *   wfa_class_pairs[c] / wfa_class_window[c]: pairs routed to the c-th LDS
  *     window class, and its window in diagonals (0: no such class);
- *     wfa_wide counts the pairs that outgrew them all (HBM-ring pass). */
+ *     wfa_wide counts the pairs that outgrew them all (HBM-ring pass);
+ *   prefilter_rejected: pairs rejected by the pre-alignment filter before
+ *     any aligner ran (see aim_prefilter). */
 typedef struct {
   int64_t n_pairs;
   int32_t band_escalated, band_escalated2;
@@ -244,6 +272,7 @@ typedef struct {
   int32_t wfa_window;
   int32_t wfa_class_pairs[4];
   int32_t wfa_class_window[4];
+  int32_t prefilter_rejected;
 } aim_call_stats;
 aim_status aim_last_call_stats(aim_context *ctx, aim_call_stats *out);
 

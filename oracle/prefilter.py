@@ -15,7 +15,7 @@ Levenshtein distance (the fewest edits of any alignment):
     B = o + e * |m - n|            if m != n, else 0
     lower(P, T) = max(A, B)  <=  the optimal cost.
 
-A is taken only for patterns of at most REACH bases (the filter's
+A is taken only when the shorter sequence has at most REACH bases (the
 bit-vectors); beyond that, lower = B.  A pair is rejected by the filter iff
 lower > max_score.
 """
@@ -41,5 +41,5 @@ def lower_bounds(batch, alg: str, pen, nthreads=None):
     diff = m != n
     a = min(x, e) * lev + np.where(diff, o, 0)
     b = np.where(diff, o + e * np.abs(m - n), 0)
-    out = np.where(m <= REACH, np.maximum(a, b), b)
+    out = np.where(np.minimum(m, n) <= REACH, np.maximum(a, b), b)
     return out.astype(np.int32)

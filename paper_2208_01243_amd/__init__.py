@@ -20,6 +20,7 @@ ENC_ASCII, ENC_CODE, ENC_2BIT = 0, 1, 2
 KERNEL_AUTO, KERNEL_PLAIN = 0, 1
 FLAG_TIMING = 1
 FLAG_STATIC_SCRATCH = 2
+FLAG_NO_PREFILTER = 4
 PAIR_ALIGNED, PAIR_REJECTED, PAIR_CIGAR_OVERFLOW, PAIR_INVALID = 0, 1, 2, 3
 OP_MATCH, OP_MISMATCH, OP_INS, OP_DEL = 0, 1, 2, 3
 
@@ -74,7 +75,7 @@ class CallStats(ctypes.Structure):
     _fields_ = [("n_pairs", i64), ("band_escalated", i32), ("band_escalated2", i32), ("wfa_wide", i32),
                 ("wfa_walk_failed", i32), ("wfa_walk_skipped", i32), ("full_store", i32 * 4),
                 ("cigar_reruns", i32), ("wfa_window", i32), ("wfa_class_pairs", i32 * 4),
-                ("wfa_class_window", i32 * 4)]
+                ("wfa_class_window", i32 * 4), ("prefilter_rejected", i32)]
 
 
 class AimError(RuntimeError):
@@ -90,6 +91,7 @@ SIGNATURES = {
     "aim_align_batch": ([vp, ctypes.POINTER(Batch), i32, Penalties, i32, ctypes.POINTER(Results), vp], i32),
     "aim_align_batch_static": ([vp, ctypes.POINTER(Batch), i32, Penalties, i32, ctypes.POINTER(Results),
                                 vp], i32),
+    "aim_prefilter": ([vp, ctypes.POINTER(Batch), i32, Penalties, i32, vp, vp, vp], i32),
     "aim_pack_2bit": ([vp, i64, i32, vp, vp, vp, vp, i64, vp, vp, vp], i32),
     "aim_timing": ([vp, i32, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_double),
                     ctypes.POINTER(i64)], i32),
@@ -159,9 +161,10 @@ class Context:
     """An aim_context on one HIP device."""
 
     def __init__(self, device: int = 0, kernel: str = "auto", scratch_limit: int = 0,
-                 timing: bool = False, static_scratch: bool = False):
+                 timing: bool = False, static_scratch: bool = False, prefilter: bool = True):
         opt = Options(KERNEL_PLAIN if kernel == "plain" else KERNEL_AUTO,
-                      (FLAG_TIMING if timing else 0) | (FLAG_STATIC_SCRATCH if static_scratch else 0),
+                      (FLAG_TIMING if timing else 0) | (FLAG_STATIC_SCRATCH if static_scratch else 0)
+                      | (0 if prefilter else FLAG_NO_PREFILTER),
                       scratch_limit)
         h = vp()
         _check(lib().aim_create(ctypes.byref(h), device, ctypes.byref(opt)))
@@ -217,6 +220,14 @@ class Context:
                              score, status, cigar, cigar_off, want_cigar)
         _check(lib().aim_align_batch_static(self._h, ctypes.byref(b), a, Penalties(*pen), max_score,
                                             ctypes.byref(r), _stream(stream)))
+
+    def prefilter(self, pat_seq, pat_off, pat_len, txt_seq, txt_off, txt_len, *, enc: int, max_len: int,
+                  alg, pen, max_score: int, lower, passed, stream=None):
+        """aim_prefilter on device tensors: lower (int32) and passed (int8) per pair, in place."""
+        b, _, a = self._args(pat_seq, pat_off, pat_len, txt_seq, txt_off, txt_len, enc, max_len, alg,
+                             None, None, None, None, False)
+        _check(lib().aim_prefilter(self._h, ctypes.byref(b), a, Penalties(*pen), max_score, _ptr(lower),
+                                   _ptr(passed), _stream(stream)))
 
     def autotune(self, pat_seq, pat_off, pat_len, txt_seq, txt_off, txt_len, *, enc, max_len, alg,
                  pen, max_score, score, status, cigar=None, cigar_off=None, want_cigar=True,

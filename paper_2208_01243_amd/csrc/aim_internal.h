@@ -304,6 +304,17 @@ constexpr int LEN_BUCKETS = 128;
 hipError_t launch_length_sort(int64_t n, const int32_t *pl, const int32_t *tl, int32_t *hist,
                               int32_t *order, hipStream_t s);
 
+// Exact pre-alignment filter (filter.hip).  Lower bound of each pair's
+// optimal cost from its Levenshtein distance (shorter side at most
+// FILTER_REACH bases) and its length difference.  O == nullptr: writes
+// lower[p] / pass[p] for every pair.  Otherwise, for the pairs of `idx`
+// (nullptr: all n): finishes the rejected and invalid ones in O, appends the
+// rest to list / count and counts the rejected in `rejected`.
+constexpr int32_t FILTER_REACH = 1024;
+hipError_t launch_prefilter(int64_t n, const Seqs &S, const int8_t *flags, int32_t max_len, int32_t x, int32_t o,
+                            int32_t e, int32_t max_score, const int32_t *idx, int32_t *lower, int8_t *pass,
+                            const Outs *O, int32_t *list, int32_t *count, int32_t *rejected, hipStream_t s);
+
 // ---- allocation-free entry point ------------------------------------------
 // Size of the static device array (one per GPU) that aim_align_batch_static
 // carves its scratch from, and the scratch budget its launch plans are sized

@@ -109,7 +109,7 @@ struct Scratch {
   Buf order, hist;
   Buf flags, pflag, tflag, pat2, txt2, pat2off, txt2off, nruns, slot, tb32, tb64, full, list2,
       list3, counters, scan_tmp, spill, total, wring, warena1, warena2, warena3, wneed, wlists, pool, pooloff,
-      wbits, wwalk, wlds, wgring;
+      wbits, wwalk, wlds, wgring, flist;
 };
 
 struct aim_graph {
@@ -230,7 +230,7 @@ struct DeviceGuard {
 enum Counter {
   C_T1 = 0, C_T2, C_T3, C_L2, C_L3, C_SPILL, C_SPILL_W,
   C_W1, C_W1G, C_RL, C_FAIL, C_N0, C_N1, C_N2, C_N3, C_P0, C_P1, C_P2, C_P3, C_TB, C_DTB,
-  C_M0, C_M1, C_M2, C_M3, C_WF, C_WS,
+  C_M0, C_M1, C_M2, C_M3, C_WF, C_WS, C_FL, C_FR,
   C_CL = 32,  // WFA window classes 1..4: list lengths, then their work counters (C_CL + 4)
   C_N = 48
 };
@@ -592,7 +592,7 @@ aim_status aim_create(aim_context **ctx, int32_t device, const aim_options *opt)
     return fail(AIM_ERR_INVALID_ARG, "unknown kernel option %d", o.kernel);
   if (o.scratch_limit < 0) return fail(AIM_ERR_INVALID_ARG, "scratch_limit < 0");
   if (o.scratch_limit == 0) o.scratch_limit = (int64_t)64 << 30;
-  if (o.flags & ~(AIM_FLAG_TIMING | AIM_FLAG_STATIC_SCRATCH))
+  if (o.flags & ~(AIM_FLAG_TIMING | AIM_FLAG_STATIC_SCRATCH | AIM_FLAG_NO_PREFILTER))
     return fail(AIM_ERR_INVALID_ARG, "unknown option flags 0x%x", o.flags);
   auto *c = new aim_context();
   c->device = device;
@@ -639,7 +639,7 @@ void aim_destroy(aim_context *c) {
   Buf *all[] = {&c->own.order, &c->own.hist, &c->own.flags, &c->own.pflag, &c->own.tflag, &c->own.pat2, &c->own.txt2, &c->own.pat2off, &c->own.txt2off,
                 &c->own.nruns, &c->own.slot, &c->own.tb32, &c->own.tb64, &c->own.full, &c->own.list2, &c->own.list3,
                 &c->own.counters, &c->own.scan_tmp, &c->own.spill, &c->own.total, &c->own.wring, &c->own.warena1,
-                &c->own.warena2, &c->own.warena3, &c->own.wneed, &c->own.wlists, &c->own.pool, &c->own.pooloff, &c->own.wbits, &c->own.wwalk, &c->own.wlds, &c->own.wgring};
+                &c->own.warena2, &c->own.warena3, &c->own.wneed, &c->own.wlists, &c->own.pool, &c->own.pooloff, &c->own.wbits, &c->own.wwalk, &c->own.wlds, &c->own.wgring, &c->own.flist};
   for (Buf *b : all)
     if (b->p) (void)(b->pooled ? hipFreeAsync(b->p, nullptr) : hipFree(b->p));
   (void)hipDeviceSynchronize();
@@ -669,13 +669,9 @@ aim_status aim_pack_2bit(aim_context *c, int64_t n, int32_t enc, const uint8_t *
   return AIM_OK;
 }
 
-static aim_status align_batch(aim_context *c, const aim_batch *B, int32_t alg, aim_penalties pen,
-                              int32_t max_score, aim_results *R, void *stream) {
-  g_err.clear();
-  // validation needs no device and happens before anything is enqueued
-  if (!B || !R) return fail(AIM_ERR_INVALID_ARG, "NULL batch or results");
-  aim_status st = check_pen(alg, pen);
-  if (st) return st;
+// Validation shared by the calls that take a batch (no device work).
+static aim_status check_batch(const aim_batch *B) {
+  if (!B) return fail(AIM_ERR_INVALID_ARG, "NULL batch");
   const int64_t n = B->n_pairs;
   if (n < 0 || n > (int64_t)INT32_MAX) return fail(AIM_ERR_INVALID_ARG, "n_pairs out of range");
   if (B->max_len < 0 || B->max_len > MAX_LEN_LIMIT)
@@ -683,6 +679,56 @@ static aim_status align_batch(aim_context *c, const aim_batch *B, int32_t alg, a
   if (B->enc < AIM_ENC_ASCII || B->enc > AIM_ENC_2BIT) return fail(AIM_ERR_INVALID_ARG, "unknown encoding %d", B->enc);
   if (n > 0 && (!B->pat_seq || !B->pat_off || !B->pat_len || !B->txt_seq || !B->txt_off || !B->txt_len))
     return fail(AIM_ERR_INVALID_ARG, "NULL sequence array");
+  return AIM_OK;
+}
+
+// The batch as 2-bit words (packed into scratch unless it already is) and
+// the per-pair validity flags in c->sc->flags.
+static aim_status prep_inputs(aim_context *c, const aim_batch *B, hipStream_t s, aim::Seqs &S) {
+  aim_status st;
+  const int64_t n = B->n_pairs;
+  const int32_t L = B->max_len;
+  if ((st = ensure(c, c->sc->flags, (size_t)n))) return st;
+  const int8_t *pf = nullptr, *tf = nullptr;
+  Phase ph_prep(c, s, "prep");
+  if (B->enc == AIM_ENC_2BIT) {
+    S = {(const uint64_t *)B->pat_seq, B->pat_off, B->pat_len,
+         (const uint64_t *)B->txt_seq, B->txt_off, B->txt_len};
+  } else {
+    const size_t words = (size_t)n * ((L + 31) / 32) + 1;
+    if ((st = ensure(c, c->sc->pat2, words * 8))) return st;
+    if ((st = ensure(c, c->sc->txt2, words * 8))) return st;
+    if ((st = ensure(c, c->sc->pat2off, (n + 1) * 8))) return st;
+    if ((st = ensure(c, c->sc->txt2off, (n + 1) * 8))) return st;
+    if ((st = ensure(c, c->sc->pflag, n))) return st;
+    if ((st = ensure(c, c->sc->tflag, n))) return st;
+    // lengths above max_len are flagged invalid below; one slot of
+    // ceil(max_len / 32) words per sequence (the buffers hold n of them):
+    // one launch per side, no offset scan
+    HIP_TRY(aim::launch_pack_strided(n, B->enc, (const uint8_t *)B->pat_seq, B->pat_off, B->pat_len, L,
+                                     as<uint64_t>(c->sc->pat2), (int64_t)words, as<int64_t>(c->sc->pat2off),
+                                     as<int8_t>(c->sc->pflag), s));
+    HIP_TRY(aim::launch_pack_strided(n, B->enc, (const uint8_t *)B->txt_seq, B->txt_off, B->txt_len, L,
+                                     as<uint64_t>(c->sc->txt2), (int64_t)words, as<int64_t>(c->sc->txt2off),
+                                     as<int8_t>(c->sc->tflag), s));
+    S = {as<uint64_t>(c->sc->pat2), as<int64_t>(c->sc->pat2off), B->pat_len,
+         as<uint64_t>(c->sc->txt2), as<int64_t>(c->sc->txt2off), B->txt_len};
+    pf = as<int8_t>(c->sc->pflag);
+    tf = as<int8_t>(c->sc->tflag);
+  }
+  HIP_TRY(aim::launch_pair_flags(n, L, B->pat_len, B->txt_len, pf, tf, as<int8_t>(c->sc->flags), s));
+  return AIM_OK;
+}
+
+static aim_status align_batch(aim_context *c, const aim_batch *B, int32_t alg, aim_penalties pen,
+                              int32_t max_score, aim_results *R, void *stream) {
+  g_err.clear();
+  // validation needs no device and happens before anything is enqueued
+  if (!B || !R) return fail(AIM_ERR_INVALID_ARG, "NULL batch or results");
+  aim_status st = check_pen(alg, pen);
+  if (st) return st;
+  if ((st = check_batch(B))) return st;
+  const int64_t n = B->n_pairs;
   if (n > 0 && (!R->score || !R->status)) return fail(AIM_ERR_INVALID_ARG, "NULL score/status");
   if (R->want_cigar && (!R->cigar_off || R->cigar_cap < 0 || (R->cigar_cap > 0 && !R->cigar)))
     return fail(AIM_ERR_INVALID_ARG, "want_cigar needs cigar_off and a cigar buffer of cigar_cap >= 0");
@@ -706,7 +752,6 @@ static aim_status align_batch(aim_context *c, const aim_batch *B, int32_t alg, a
   if ((st = ensure(c, c->sc->scan_tmp, tmp * sizeof(int64_t)))) return st;
   if ((st = ensure(c, c->sc->counters, C_N * sizeof(int32_t) + 64))) return st;
   if ((st = ensure(c, c->sc->total, 64))) return st;
-  if ((st = ensure(c, c->sc->flags, (size_t)n))) return st;
   if ((st = ensure(c, c->sc->nruns, (size_t)n * sizeof(int32_t)))) return st;
   if ((st = ensure(c, c->sc->spill, (size_t)n * sizeof(int32_t)))) return st;
   if ((st = ensure(c, c->sc->list2, (size_t)n * sizeof(int32_t)))) return st;
@@ -730,36 +775,7 @@ static aim_status align_batch(aim_context *c, const aim_batch *B, int32_t alg, a
 
   // ---- input encoding ----
   aim::Seqs S;
-  const int8_t *pf = nullptr, *tf = nullptr;
-  {
-  Phase ph_prep(c, s, "prep");
-  if (B->enc == AIM_ENC_2BIT) {
-    S = {(const uint64_t *)B->pat_seq, B->pat_off, B->pat_len,
-         (const uint64_t *)B->txt_seq, B->txt_off, B->txt_len};
-  } else {
-    const size_t words = (size_t)n * ((L + 31) / 32) + 1;
-    if ((st = ensure(c, c->sc->pat2, words * 8))) return st;
-    if ((st = ensure(c, c->sc->txt2, words * 8))) return st;
-    if ((st = ensure(c, c->sc->pat2off, (n + 1) * 8))) return st;
-    if ((st = ensure(c, c->sc->txt2off, (n + 1) * 8))) return st;
-    if ((st = ensure(c, c->sc->pflag, n))) return st;
-    if ((st = ensure(c, c->sc->tflag, n))) return st;
-    // lengths above max_len are flagged invalid below; clamp the packing bound
-    // one slot of ceil(max_len / 32) words per sequence (the buffers hold n
-    // of them): one launch per side, no offset scan
-    HIP_TRY(aim::launch_pack_strided(n, B->enc, (const uint8_t *)B->pat_seq, B->pat_off, B->pat_len, L,
-                                     as<uint64_t>(c->sc->pat2), (int64_t)words, as<int64_t>(c->sc->pat2off),
-                                     as<int8_t>(c->sc->pflag), s));
-    HIP_TRY(aim::launch_pack_strided(n, B->enc, (const uint8_t *)B->txt_seq, B->txt_off, B->txt_len, L,
-                                     as<uint64_t>(c->sc->txt2), (int64_t)words, as<int64_t>(c->sc->txt2off),
-                                     as<int8_t>(c->sc->tflag), s));
-    S = {as<uint64_t>(c->sc->pat2), as<int64_t>(c->sc->pat2off), B->pat_len,
-         as<uint64_t>(c->sc->txt2), as<int64_t>(c->sc->txt2off), B->txt_len};
-    pf = as<int8_t>(c->sc->pflag);
-    tf = as<int8_t>(c->sc->tflag);
-  }
-  HIP_TRY(aim::launch_pair_flags(n, L, B->pat_len, B->txt_len, pf, tf, as<int8_t>(c->sc->flags), s));
-  }
+  if ((st = prep_inputs(c, B, s, S))) return st;
 
   // pool for runs beyond the per-pair slot (reset every call)
   // sized from the batch (a quarter of the worst-case run count per pair),
@@ -790,6 +806,19 @@ static aim_status align_batch(aim_context *c, const aim_batch *B, int32_t alg, a
   const int64_t budget = c->limit() / 4;
   const bool plain = c->opt.kernel == AIM_KERNEL_PLAIN;
 
+  // exact pre-alignment filter: with a threshold, pairs whose lower bound
+  // already exceeds it are finished here and the aligners take the rest (in
+  // `order`, counted on the device)
+  const int32_t *order_count = nullptr;
+  if (max_score >= 0 && !plain && !(c->opt.flags & AIM_FLAG_NO_PREFILTER)) {
+    if ((st = ensure(c, c->sc->flist, (size_t)n * 4))) return st;
+    Phase ph(c, s, "prefilter");
+    HIP_TRY(aim::launch_prefilter(n, S, as<int8_t>(c->sc->flags), L, P.x, P.o, P.e, max_score, order, nullptr,
+                                  nullptr, &O, as<int32_t>(c->sc->flist), cnt + C_FL, cnt + C_FR, s));
+    order = as<int32_t>(c->sc->flist);
+    order_count = cnt + C_FL;
+  }
+
   auto run_full = [&](const aim::Work &Wk, int64_t max_items, hipStream_t s) -> aim_status {
     const int64_t sw = aim::full_slot_words(L);
     int64_t slots = std::min<int64_t>(max_items, (int64_t)c->cus * 8);
@@ -803,7 +832,7 @@ static aim_status align_batch(aim_context *c, const aim_batch *B, int32_t alg, a
   };
 
   if (alg == AIM_WFA_AFFINE) {
-    if ((st = run_wfa(c, S, O, P, n, L, plain, cnt, order, nullptr, tu, s))) return st;
+    if ((st = run_wfa(c, S, O, P, n, L, plain, cnt, order, order_count, tu, s))) return st;
   } else if (plain) {
     aim::Work W1{nullptr, nullptr, n, cnt + C_T1, nullptr, nullptr, 0};
     if ((st = run_full(W1, n, s))) return st;
@@ -826,7 +855,7 @@ static aim_status align_batch(aim_context *c, const aim_batch *B, int32_t alg, a
     const bool split = b16 && (tu.band16 == 2 || (tu.band16 == 3 && n >= SPLIT_MIN_PAIRS)) &&
                        R->want_cigar && chunksA * swA * 4 <= budget;
     if ((st = ensure(c, tbA, (size_t)((split ? chunksA : slots) * swA * 4)))) return st;
-    aim::Work W1{order, nullptr, n, cnt + C_T1, as<int32_t>(c->sc->list2), cnt + C_L2, 0};
+    aim::Work W1{order, order_count, n, cnt + C_T1, as<int32_t>(c->sc->list2), cnt + C_L2, 0};
     {
       Phase ph(c, s, b16 ? "band16" : (w0 == 32 ? "band32" : "band64"));
       if (b16)
@@ -873,7 +902,7 @@ static aim_status align_batch(aim_context *c, const aim_batch *B, int32_t alg, a
       full_count = cnt + C_L3;
     }
     if (split) {
-      aim::Work WT{order, nullptr, n, cnt + C_TB, nullptr, nullptr, 0};
+      aim::Work WT{order, order_count, n, cnt + C_TB, nullptr, nullptr, 0};
       Phase ph(c, s2, "band16_tb");
       // six of the eight workgroups a CU could hold: the persistent traceback
       // must leave slots for the second tier's kernels beside it
@@ -972,6 +1001,7 @@ aim_status aim_last_call_stats(aim_context *c, aim_call_stats *out) {
     out->wfa_class_pairs[k] = v[C_CL + k];
     out->wfa_class_window[k] = c->last_class_window[k];
   }
+  out->prefilter_rejected = v[C_FR];
   return AIM_OK;
 }
 
@@ -998,6 +1028,36 @@ aim_status aim_align_batch_static(aim_context *c, const aim_batch *B, int32_t al
   c->arena = nullptr;
   c->arena_cap = c->arena_top = 0;
   c->sc = &c->own;
+  HIP_TRY(hipEventRecord(c->ev_done, s));
+  c->has_done = true;
+  c->done_stream = s;
+  return st;
+}
+
+aim_status aim_prefilter(aim_context *c, const aim_batch *B, int32_t alg, aim_penalties pen, int32_t max_score,
+                         int32_t *lower, int8_t *pass, void *stream) {
+  g_err.clear();
+  aim_status st = check_pen(alg, pen);
+  if (st) return st;
+  if ((st = check_batch(B))) return st;
+  const int64_t n = B->n_pairs;
+  if (n > 0 && (!lower || !pass)) return fail(AIM_ERR_INVALID_ARG, "NULL lower or pass");
+  if (!c) return fail(AIM_ERR_INVALID_ARG, "ctx is NULL");
+  if (n == 0) return AIM_OK;
+  DeviceGuard g(c->device);
+  hipStream_t s = (hipStream_t)stream;
+  // ordered after the context's previous call like aim_align_batch
+  if (c->has_done && c->done_stream != s) HIP_TRY(hipStreamWaitEvent(s, c->ev_done, 0));
+  c->astream = s;
+  aim::Seqs S;
+  st = prep_inputs(c, B, s, S);
+  if (!st) {
+    const hipError_t e = aim::launch_prefilter(n, S, as<int8_t>(c->sc->flags), B->max_len, pen.mismatch,
+                                               alg == AIM_NW_LINEAR ? 0 : pen.gap_open, pen.gap_extend, max_score,
+                                               nullptr, lower, pass, nullptr, nullptr, nullptr, nullptr, s);
+    if (e != hipSuccess) st = fail(AIM_ERR_HIP, "prefilter launch: %s", hipGetErrorString(e));
+  }
+  c->astream = nullptr;
   HIP_TRY(hipEventRecord(c->ev_done, s));
   c->has_done = true;
   c->done_stream = s;
