@@ -66,7 +66,10 @@ typedef enum { AIM_ENC_ASCII = 0, AIM_ENC_CODE = 1, AIM_ENC_2BIT = 2 } aim_encod
 /* Per-pair status values written to aim_results.status. */
 #define AIM_PAIR_ALIGNED 0
 #define AIM_PAIR_REJECTED 1       /* optimum > max_score: score -1, empty CIGAR */
-#define AIM_PAIR_CIGAR_OVERFLOW 2 /* score valid, CIGAR did not fit cigar_cap */
+#define AIM_PAIR_CIGAR_OVERFLOW 2 /* score valid, no CIGAR: it did not fit cigar_cap, or
+                                     (WFA, scores in the tens of thousands) the
+                                     wavefronts its walk needs outgrow the largest
+                                     store the scratch budget allows */
 #define AIM_PAIR_INVALID 3        /* non-ACGT base or length beyond max_len */
 
 /* CIGAR run encoding: (run_length << 4) | op. */
@@ -136,21 +139,36 @@ typedef enum { AIM_KERNEL_AUTO = 0, AIM_KERNEL_PLAIN = 1 } aim_kernel;
 #define AIM_FLAG_TIMING 1 /* time every kernel launch with HIP events (aim_timing) */
 #define AIM_FLAG_STATIC_SCRATCH 2 /* set up aim_align_batch_static's array at create */
 #define AIM_FLAG_NO_PREFILTER 4   /* aligning calls skip the pre-alignment filter */
+#define AIM_FLAG_HARD_LIMIT 8     /* scratch_limit is a hard cap (see aim_options) */
 
 typedef struct {
   int32_t kernel;        /* aim_kernel */
   int32_t flags;         /* AIM_FLAG_* */
-  int64_t scratch_limit; /* soft cap on library scratch in bytes (0: 64 GiB) */
+  /* Library scratch budget in bytes (0: 64 GiB).  Launch plans are sized
+   * for it.  Without AIM_FLAG_HARD_LIMIT it is soft: buffers that grow with
+   * the batch (per-pair arrays) may pass it.  With the flag the device
+   * memory the context's scratch holds never exceeds it (launch plans are
+   * then sized for 3/8 of it, the rest holding the arrays that grow with the
+   * batch): a call that would need more fails with AIM_ERR_OOM (its outputs
+   * are then unspecified), and a smaller batch can be retried on the same
+   * context. */
+  int64_t scratch_limit;
 } aim_options;
 
 typedef struct aim_context aim_context;
 
 /* Create a context on HIP device `device`.  opt may be NULL (defaults).
+ * Paper: Data Management, dynamic memory allocation -- the framework gives
+ * each worker its own allocator instead of a shared one; a context is that
+ * owner here: its scratch (grown on demand, kept across calls) serves only
+ * the calls made with it.
  * Returns AIM_ERR_INVALID_ARG for a bad device or options, AIM_ERR_HIP if the
  * runtime refuses the device. */
 aim_status aim_create(aim_context **ctx, int32_t device, const aim_options *opt);
 
-/* Release the context and all its scratch.  Waits for its work to finish. */
+/* Release the context and all its scratch (paper: Data Management, the
+ * per-worker allocator frees everything at once).  Waits for its work to
+ * finish.  NULL is ignored. */
 void aim_destroy(aim_context *ctx);
 
 /* Align every pair of `pairs` (paper: workflow steps 3-5 for all pairs,
@@ -185,6 +203,14 @@ aim_status aim_align_batch(aim_context *ctx, const aim_batch *pairs, int32_t alg
 aim_status aim_align_batch_static(aim_context *ctx, const aim_batch *pairs, int32_t alg,
                                   aim_penalties pen, int32_t max_score, aim_results *out,
                                   void *stream);
+
+/* Device bytes the context's scratch holds now (`current`) and the most it
+ * has held at any time since aim_create (`peak`), from the context's own
+ * allocation accounting (buffers of aim_align_batch_static's static array
+ * excluded).  Either pointer may be NULL.  Paper: Data Management (the
+ * host decides what each processing unit's memory holds); this is the figure
+ * a caller budgets device memory with. */
+aim_status aim_scratch_usage(aim_context *ctx, int64_t *current, int64_t *peak);
 
 /* Exact pre-alignment filter (paper: Introduction, the third way to speed
  * up alignment -- drop, before aligning them, the pairs that are too
@@ -325,19 +351,28 @@ void aim_graph_destroy(aim_graph *graph);
 
 /* ---- serving form ---------------------------------------------------------
  * A request server: alignment requests of any size arrive on host threads,
- * wait in a FIFO until their device-memory footprint fits the budget (never
- * dropped, never bypassed), and are merged -- across requests, per
- * (algorithm, penalties, threshold, CIGAR wanted) -- into device batches by
- * n_streams workers, each with its own context, stream and buffers, so
- * batches overlap on the GPU and requests that arrive while others run join
- * the next batch.  Paper: Overall Workflow (the host gathers pairs,
- * dispatches them, retrieves score and operations), run continuously. */
+ * wait in one FIFO queue (never dropped, never bypassed by a request of the
+ * same kind), and are merged -- in queue order, per (algorithm, penalties,
+ * threshold, CIGAR wanted, encoding) -- into device batches by n_streams
+ * workers, each with its own context, stream and buffers, so batches
+ * overlap on the GPU and requests that arrive while others run join the
+ * next batch.  The device-memory budget is split evenly between the
+ * workers: of each share, an eighth holds input staging, an eighth output
+ * staging, and the rest is the hard scratch limit of the worker's context
+ * (AIM_FLAG_HARD_LIMIT), so the device memory the server holds never passes
+ * the budget; a request is admitted to the device when a worker, with its
+ * share, frees up.  A batch that needs more scratch than the share is split
+ * in two by request and each half run again; a single request that still
+ * does not fit fails with AIM_ERR_OOM.  Paper: Overall Workflow (the host
+ * gathers pairs, dispatches them, retrieves score and operations), run
+ * continuously. */
 typedef struct aim_server aim_server;
 
 typedef struct {
   int32_t n_streams;       /* concurrent device batches, 1..16 (0: 4) */
   int32_t flags;           /* reserved, 0 */
-  int64_t budget_bytes;    /* device bytes for admitted requests (0: 64 GiB) */
+  int64_t budget_bytes;    /* device bytes the server may hold (0: 64 GiB); at least
+                              64 MiB per stream */
   int64_t max_batch_pairs; /* pairs merged into one device batch (0: 65,536); a single
                               request larger than this still runs as one batch */
 } aim_server_options;
@@ -370,6 +405,10 @@ typedef struct {
   double latency_us; /* completion minus submission */
 } aim_request_result;
 
+/* bytes_in_use: device bytes the workers hold now (staging plus their
+ * contexts' scratch, from aim_scratch_usage); peak_bytes: the most they have
+ * held together since creation or the last reset (the sum of each worker's
+ * high-water mark, an upper bound of any instant's total). */
 typedef struct {
   int64_t submitted, completed, pairs_completed, batches, queued;
   double p50_us, p99_us, mean_us, max_us; /* latency of completed requests */
@@ -380,7 +419,8 @@ typedef struct {
 /* Errors of the aim_server_* calls are described by aim_server_last_error. */
 aim_status aim_server_create(int32_t device, const aim_server_options *opt, aim_server **srv);
 /* Queues a request; returns at once with its id.  AIM_ERR_INVALID_ARG for a
- * request whose footprint exceeds the whole budget. */
+ * request whose staging (sequences, offsets, lengths in; scores, statuses
+ * and worst-case CIGAR out) exceeds a worker's staging share. */
 aim_status aim_server_submit(aim_server *srv, const aim_request *req, int64_t *id);
 /* AIM_ERR_BUSY while the request runs; AIM_ERR_NOT_FOUND for unknown ids. */
 aim_status aim_server_poll(aim_server *srv, int64_t id, aim_request_result *res);
@@ -395,7 +435,8 @@ const char *aim_server_last_error(void);
 void aim_server_destroy(aim_server *srv);
 
 /* Description of the last error on this host thread ("" if none).  Valid
- * until the next library call on the same thread. */
+ * until the next library call on the same thread.  (Not an operation of the
+ * paper: the error channel of this C interface.) */
 const char *aim_last_error(void);
 
 /* Library version string. */

@@ -21,6 +21,7 @@ KERNEL_AUTO, KERNEL_PLAIN = 0, 1
 FLAG_TIMING = 1
 FLAG_STATIC_SCRATCH = 2
 FLAG_NO_PREFILTER = 4
+FLAG_HARD_LIMIT = 8
 PAIR_ALIGNED, PAIR_REJECTED, PAIR_CIGAR_OVERFLOW, PAIR_INVALID = 0, 1, 2, 3
 OP_MATCH, OP_MISMATCH, OP_INS, OP_DEL = 0, 1, 2, 3
 
@@ -92,6 +93,7 @@ SIGNATURES = {
     "aim_align_batch_static": ([vp, ctypes.POINTER(Batch), i32, Penalties, i32, ctypes.POINTER(Results),
                                 vp], i32),
     "aim_prefilter": ([vp, ctypes.POINTER(Batch), i32, Penalties, i32, vp, vp, vp], i32),
+    "aim_scratch_usage": ([vp, ctypes.POINTER(i64), ctypes.POINTER(i64)], i32),
     "aim_pack_2bit": ([vp, i64, i32, vp, vp, vp, vp, i64, vp, vp, vp], i32),
     "aim_timing": ([vp, i32, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_double),
                     ctypes.POINTER(i64)], i32),
@@ -161,10 +163,11 @@ class Context:
     """An aim_context on one HIP device."""
 
     def __init__(self, device: int = 0, kernel: str = "auto", scratch_limit: int = 0,
-                 timing: bool = False, static_scratch: bool = False, prefilter: bool = True):
+                 timing: bool = False, static_scratch: bool = False, prefilter: bool = True,
+                 hard_limit: bool = False):
         opt = Options(KERNEL_PLAIN if kernel == "plain" else KERNEL_AUTO,
                       (FLAG_TIMING if timing else 0) | (FLAG_STATIC_SCRATCH if static_scratch else 0)
-                      | (0 if prefilter else FLAG_NO_PREFILTER),
+                      | (0 if prefilter else FLAG_NO_PREFILTER) | (FLAG_HARD_LIMIT if hard_limit else 0),
                       scratch_limit)
         h = vp()
         _check(lib().aim_create(ctypes.byref(h), device, ctypes.byref(opt)))
@@ -220,6 +223,12 @@ class Context:
                              score, status, cigar, cigar_off, want_cigar)
         _check(lib().aim_align_batch_static(self._h, ctypes.byref(b), a, Penalties(*pen), max_score,
                                             ctypes.byref(r), _stream(stream)))
+
+    def scratch_usage(self):
+        """aim_scratch_usage: (current, peak) device bytes of the context's scratch."""
+        cur, peak = i64(), i64()
+        _check(lib().aim_scratch_usage(self._h, ctypes.byref(cur), ctypes.byref(peak)))
+        return cur.value, peak.value
 
     def prefilter(self, pat_seq, pat_off, pat_len, txt_seq, txt_off, txt_len, *, enc: int, max_len: int,
                   alg, pen, max_score: int, lower, passed, stream=None):

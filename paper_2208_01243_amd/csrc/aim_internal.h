@@ -262,8 +262,10 @@ struct WfaPlan {
   int32_t threads[4];
 };
 
+// strict: every pool (one slot of its class included) stays within its share
+// of budget_bytes, shrinking the store classes if need be
 WfaPlan wfa_plan(int32_t max_len, const Scoring &P, int64_t budget_bytes, int32_t cus, bool plain,
-                 int32_t ring_kb, int32_t trace_kb, int32_t long_threads);
+                 int32_t ring_kb, int32_t trace_kb, int32_t long_threads, bool strict = false);
 // ring16 (HBM ring only): 16-bit ring entries, for batches with max_len <=
 // WFA16_MAX_LEN.  The HBM ring must be readable for wfa_ring_pad(wcap) words
 // before hbm and after its last slot (its steps read without clamping).

@@ -145,11 +145,19 @@ struct aim_context {
   // inside aim_align_batch_static, buffers carved from the static array.
   Scratch own;
   Scratch *sc = &own;
+  // device bytes held by the context's own scratch, now and at most
+  int64_t dev_bytes = 0, dev_peak = 0;
   // carving state of aim_align_batch_static (arena == nullptr otherwise)
   uint8_t *arena = nullptr;
   size_t arena_cap = 0, arena_top = 0;
   // the scratch budget the launch plans are sized for in this call
-  int64_t limit() const { return arena ? aim::STATIC_PLAN_BUDGET : opt.scratch_limit; }
+  // (a hard limit leaves the other 5/8 to the arrays that grow with the
+  // batch, the proportion of the static array's plan budget to its size)
+  int64_t limit() const {
+    if (arena) return aim::STATIC_PLAN_BUDGET;
+    return strict() ? opt.scratch_limit / 8 * 3 : opt.scratch_limit;
+  }
+  bool strict() const { return !arena && (opt.flags & AIM_FLAG_HARD_LIMIT); }
   // the last call's work counters (device) and size, for aim_last_call_stats
   const int32_t *last_cnt = nullptr;
   int64_t last_n = 0;
@@ -189,10 +197,18 @@ aim_status ensure(aim_context *c, Buf &b, size_t bytes) {
       else
         HIP_TRY(hipFree(b.p));
     }
+    c->dev_bytes -= (int64_t)b.bytes;
     b.p = nullptr;
     b.bytes = 0;
   }
   size_t want = bytes + bytes / 8;
+  if (c->opt.flags & AIM_FLAG_HARD_LIMIT) {
+    const int64_t room = c->opt.scratch_limit - c->dev_bytes;
+    if ((int64_t)bytes > room)
+      return fail(AIM_ERR_OOM, "scratch limit of %lld bytes reached (%lld held, %zu more needed)",
+                  (long long)c->opt.scratch_limit, (long long)c->dev_bytes, bytes);
+    want = std::min<size_t>(want, (size_t)room);
+  }
   c->generation += 1;
   auto alloc = [&](size_t sz) { return as ? hipMallocAsync(&b.p, sz, as) : hipMalloc(&b.p, sz); };
   b.pooled = as != nullptr;
@@ -208,6 +224,8 @@ aim_status ensure(aim_context *c, Buf &b, size_t bytes) {
     want = bytes;
   }
   b.bytes = want;
+  c->dev_bytes += (int64_t)want;
+  c->dev_peak = std::max(c->dev_peak, c->dev_bytes);
   return AIM_OK;
 }
 
@@ -327,7 +345,7 @@ aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const
   aim_status st;
   const aim::Scoring P = wfa_scoring(Pin);
   const aim::WfaPlan pl = aim::wfa_plan(L, P, c->limit(), c->cus, plain, tu.wfa_ring_kb,
-                                        tu.wfa_trace_kb, tu.wfa_long_threads);
+                                        tu.wfa_trace_kb, tu.wfa_long_threads, c->strict());
   if ((st = ensure(c, c->sc->wneed, (size_t)n * 8))) return st;
   // lists: [0] the HBM-ring pass, [1-4] full-store classes, [5] unused,
   // [6-9] LDS-window classes, [10] predicted extents
@@ -502,7 +520,7 @@ aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const
     B.ring_list = lists + (int64_t)n * 5;  // never reached: wcap bounds every width
     B.ring_count = cnt + C_FAIL;
     const bool all = plain || (!w16 && pl.wcap_lds == 0);
-    const int32_t grid = all ? std::min<int32_t>(slots, pl.ring_slots) : pl.ring_slots;
+    int32_t grid = all ? std::min<int32_t>(slots, pl.ring_slots) : pl.ring_slots;
     if (P.want_cigar && !plain) {
       // origin codes for the fused walk: 1/4 of the budget over the workgroups
       B.walk_steps = P.max_score >= 0 ? std::min(P.max_score + 1, aim::WFA_WALK_STEPS) : aim::WFA_WALK_STEPS;
@@ -513,6 +531,9 @@ aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const
           most, std::max<int64_t>(256 << 10, std::min<int64_t>(16 << 20, c->limit() / 4 / grid)));
       B.walk_codes = (B.walk_codes + 15) / 16 * 16;
       B.walk_slot = ((int64_t)B.walk_steps * 16 + B.walk_codes + (int64_t)B.walk_tok * 4 + 255) / 256 * 256;
+      // the slots (each at least 256 KB of codes) within a quarter of the
+      // budget: fewer workgroups rather than more memory
+      grid = (int32_t)std::max<int64_t>(1, std::min<int64_t>(grid, c->limit() / 4 / B.walk_slot));
       if ((st = ensure(c, c->sc->wwalk, (size_t)B.walk_slot * grid))) return st;
       B.walk = as<uint8_t>(c->sc->wwalk);
     }
@@ -592,7 +613,7 @@ aim_status aim_create(aim_context **ctx, int32_t device, const aim_options *opt)
     return fail(AIM_ERR_INVALID_ARG, "unknown kernel option %d", o.kernel);
   if (o.scratch_limit < 0) return fail(AIM_ERR_INVALID_ARG, "scratch_limit < 0");
   if (o.scratch_limit == 0) o.scratch_limit = (int64_t)64 << 30;
-  if (o.flags & ~(AIM_FLAG_TIMING | AIM_FLAG_STATIC_SCRATCH | AIM_FLAG_NO_PREFILTER))
+  if (o.flags & ~(AIM_FLAG_TIMING | AIM_FLAG_STATIC_SCRATCH | AIM_FLAG_NO_PREFILTER | AIM_FLAG_HARD_LIMIT))
     return fail(AIM_ERR_INVALID_ARG, "unknown option flags 0x%x", o.flags);
   auto *c = new aim_context();
   c->device = device;
@@ -782,8 +803,9 @@ static aim_status align_batch(aim_context *c, const aim_batch *B, int32_t alg, a
   // between 4 MiB and 1/64 of the scratch budget; exhaustion falls back to
   // the exact in-place re-run
   const int64_t pool_cap =
-      R->want_cigar ? std::max<int64_t>(1 << 20, std::min<int64_t>(c->limit() / 64 / 4,
-                                                                   n * std::min<int64_t>(2 * (int64_t)L + 1, 1024) / 4))
+      R->want_cigar ? std::max<int64_t>(c->strict() ? 1 << 14 : 1 << 20,
+                                        std::min<int64_t>(c->limit() / 64 / 4,
+                                                          n * std::min<int64_t>(2 * (int64_t)L + 1, 1024) / 4))
                     : 1;
   if ((st = ensure(c, c->sc->pool, (size_t)pool_cap * 4))) return st;
   if ((st = ensure(c, c->sc->pooloff, (size_t)n * 8))) return st;
@@ -944,7 +966,7 @@ static aim_status align_batch(aim_context *c, const aim_batch *B, int32_t alg, a
   if (alg == AIM_WFA_AFFINE) {
     const aim::Scoring PW = wfa_scoring(P);
     aim::WfaPlan pl = aim::wfa_plan(L, PW, c->limit(), c->cus, plain, tu.wfa_ring_kb,
-                                    tu.wfa_trace_kb, tu.wfa_long_threads);
+                                    tu.wfa_trace_kb, tu.wfa_long_threads, c->strict());
     aim::WfaLaunch WL{};
     WL.R = pl.R;
     WL.seq_words = pl.seq_words;
@@ -1032,6 +1054,14 @@ aim_status aim_align_batch_static(aim_context *c, const aim_batch *B, int32_t al
   c->has_done = true;
   c->done_stream = s;
   return st;
+}
+
+aim_status aim_scratch_usage(aim_context *c, int64_t *current, int64_t *peak) {
+  g_err.clear();
+  if (!c) return fail(AIM_ERR_INVALID_ARG, "ctx is NULL");
+  if (current) *current = c->dev_bytes;
+  if (peak) *peak = c->dev_peak;
+  return AIM_OK;
 }
 
 aim_status aim_prefilter(aim_context *c, const aim_batch *B, int32_t alg, aim_penalties pen, int32_t max_score,

@@ -771,7 +771,7 @@ __global__ __launch_bounds__(WGMAX) void k_wfa_trace(Seqs S, Outs O, Scoring P, 
 }  // namespace
 
 WfaPlan wfa_plan(int32_t max_len, const Scoring &P, int64_t budget_bytes, int32_t cus, bool plain,
-                 int32_t ring_kb, int32_t trace_kb, int32_t long_threads) {
+                 int32_t ring_kb, int32_t trace_kb, int32_t long_threads, bool strict) {
   // budget split: HBM rings 1/8, origin codes 1/4 (HBM-ring pass) and 1/16
   // (one-wavefront pass), arena classes 1/32, 1/8 and 1/4
   WfaPlan pl{};
@@ -807,6 +807,12 @@ WfaPlan wfa_plan(int32_t max_len, const Scoring &P, int64_t budget_bytes, int32_
   // store) fits the pool
   const int64_t share[4] = {0, budget_bytes / 32, budget_bytes / 8, budget_bytes / 4};
   const int64_t cap_slots[4] = {0, (int64_t)cus * 8, (int64_t)cus * 4, (int64_t)cus * 4};
+  if (strict) {
+    // a pair whose store passes the last class then has no CIGAR (overflow)
+    for (int k = 1; k < 4; ++k)
+      pl.need_cap[k] = std::max<int64_t>(64, std::min<int64_t>(pl.need_cap[k], share[k] / 4 / 64 * 64));
+    for (int k = 2; k < 4; ++k) pl.need_cap[k] = std::max(pl.need_cap[k], pl.need_cap[k - 1]);
+  }
   for (int k = 1; k < 4; ++k) {
     const int64_t cap = (pl.need_cap[k] + 63) / 64 * 64;
     pl.pool_words[k] = std::max<int64_t>(cap, std::min<int64_t>(share[k] / 4, cap_slots[k] * cap));

@@ -7,7 +7,10 @@ s = 0 included), 32-base extension words and bases compared, and the same
 split by the pair's extent e = max(-lo_min, hi_max + 1), the half-width of
 the smallest window centred on diagonal 0 that holds all of its wavefronts
 (a kernel that keeps a window of W = 2e diagonals takes exactly the pairs of
-extent <= e).  The counts are penalty-scale free: dividing x, o and e by
+extent <= e).  With a threshold, each row also counts the pairs, cells and
+words of the pairs the pre-alignment filter lets through (lower bound from
+oracle.prefilter at most the threshold): the wavefront kernels see only
+those.  The counts are penalty-scale free: dividing x, o and e by
 their common divisor leaves the non-null wavefronts and their ranges as they
 are.
 
@@ -29,6 +32,7 @@ sys.path.insert(0, ROOT)
 
 import oracle  # noqa: E402
 import synth  # noqa: E402
+from oracle.prefilter import lower_bounds  # noqa: E402
 
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "wfa_work.json")
 # extent buckets (upper bounds, inclusive); the last catches the rest
@@ -40,7 +44,8 @@ def count(name: str, threads: int) -> dict:
     w = synth.WORKLOADS[name]
     total = w["total"]
     nb = len(EDGES)
-    agg = {k: np.zeros(nb, np.int64) for k in ("pairs", "accepted", "cells", "words", "compared")}
+    keys = ("pairs", "accepted", "cells", "words", "compared", "pass_pairs", "pass_cells", "pass_words")
+    agg = {k: np.zeros(nb, np.int64) for k in keys}
     t0 = time.time()
     for start in range(0, total, CHUNK):
         b = synth.workload(name, start=start, n=min(CHUNK, total - start))
@@ -52,21 +57,27 @@ def count(name: str, threads: int) -> dict:
 
         with ThreadPoolExecutor(threads) as ex:
             res = list(ex.map(one, range(b.n)))
-        for st, ext, cells, words, comp in res:
+        lb = lower_bounds(b, "wfa", w["pen"], nthreads=threads) if w["max_score"] >= 0 else None
+        for i, (st, ext, cells, words, comp) in enumerate(res):
             k = int(np.searchsorted(EDGES, ext))
             agg["pairs"][k] += 1
             agg["accepted"][k] += st == 0
             agg["cells"][k] += cells
             agg["words"][k] += words
             agg["compared"][k] += comp
+            if lb is None or lb[i] <= w["max_score"]:
+                agg["pass_pairs"][k] += 1
+                agg["pass_cells"][k] += cells
+                agg["pass_words"][k] += words
         print("%s: %d/%d pairs, %.0f s" % (name, start + b.n, total, time.time() - t0), flush=True)
     return {
         "penalties": list(w["pen"]), "max_score": w["max_score"], "pairs": total,
         "accepted": int(agg["accepted"].sum()), "cells": int(agg["cells"].sum()),
         "words": int(agg["words"].sum()), "compared": int(agg["compared"].sum()),
-        "by_extent": [[e if e < (1 << 30) else None, int(agg["pairs"][k]), int(agg["accepted"][k]),
-                       int(agg["cells"][k]), int(agg["words"][k])] for k, e in enumerate(EDGES)],
-        "by_extent_columns": ["extent_max", "pairs", "accepted", "cells", "words"],
+        "by_extent": [[e if e < (1 << 30) else None] + [int(agg[c][k]) for c in keys if c != "compared"]
+                      for k, e in enumerate(EDGES)],
+        "by_extent_columns": ["extent_max", "pairs", "accepted", "cells", "words", "pass_pairs", "pass_cells",
+                              "pass_words"],
     }
 
 

@@ -249,3 +249,28 @@ def test_graph_replay_on_another_stream_between_eager_calls():
                 with torch.cuda.stream(s1):
                     g, dev, outs, max_len, enc = _capture(ctx, b, w, s1)
         g.close()
+
+
+def test_hard_scratch_limit():
+    # AIM_FLAG_HARD_LIMIT: the context's scratch never passes the limit; a
+    # batch that would need more fails with AIM_ERR_OOM, and the context then
+    # still aligns a batch that fits, with the same results as an unbounded one
+    limit = 1 << 30
+    b = synth.workload("wfa_mixed", n=3000)
+    w = synth.WORKLOADS["wfa_mixed"]
+    with aim.Context(0, scratch_limit=limit, hard_limit=True) as hc, aim.Context(0) as free:
+        got = run(hc, b, "wfa", w["pen"], -1)
+        assert not compare(got, run(free, b, "wfa", w["pen"], -1))
+        cur, peak = hc.scratch_usage()
+        assert 0 < cur <= peak <= limit
+        assert free.scratch_usage()[1] > 0
+    # 64 MiB: 200,000 pairs need more (their run slots alone take 100 MB)
+    with aim.Context(0, scratch_limit=64 << 20, hard_limit=True) as hc:
+        big = synth.workload("swg150", n=200_000)
+        with pytest.raises(aim.AimError) as ei:
+            run(hc, big, "swg", (0, 4, 6, 2), -1)
+        assert ei.value.code == -3
+        assert hc.scratch_usage()[1] <= 64 << 20
+        small = synth.workload("swg150", n=5000)
+        assert not compare(run(hc, small, "swg", (0, 4, 6, 2), -1), oracle.align_batch(small, "swg", (0, 4, 6, 2), -1))
+        assert hc.scratch_usage()[1] <= 64 << 20

@@ -58,24 +58,56 @@ def test_mix_equals_alone_and_oracle():
             assert not compare(got, alone)
 
 
-def test_budget_admission_and_no_starvation():
-    reqs = _requests(2, 40, lmax=300)
-    budget = 24 << 20  # forces requests to wait for earlier ones to finish
-    with aim.Server(0, n_streams=3, budget_bytes=budget) as srv:
+def _long_requests(seed, count, n, L):
+    rng = np.random.default_rng(seed)
+    out = []
+    for r in range(count):
+        txts = [rng.integers(0, 4, int(rng.integers(L // 2, L + 1))).astype(np.uint8) for _ in range(n)]
+        pats = []
+        for T in txts:
+            bb = synth.from_lists([T], [T])
+            P, _ = synth.mutate(rng, bb.txt, bb.txt_off, [float(rng.uniform(0.0, 0.08))])
+            pats.append(P)
+        alg, pen = [("wfa", (0, 4, 6, 2)), ("swg", (0, 4, 6, 2)), ("nw", (0, 1, 0, 1))][r % 3]
+        out.append((alg, pen, -1, synth.from_lists(pats, txts)))
+    return out
+
+
+def test_budget_bounds_device_memory_and_no_starvation():
+    # two streams of 96 MiB each: requests queue behind the two workers, the
+    # device memory the server holds (staging plus each context's scratch,
+    # from the library's own accounting) stays within the budget, and every
+    # request completes with the oracle's results
+    reqs = _requests(2, 40, lmax=300) + _long_requests(9, 3, 600, 1000)
+    budget = 2 * (96 << 20)
+    with aim.Server(0, n_streams=2, budget_bytes=budget) as srv:
         ids = [_submit(srv, a, p, s, b) for a, p, s, b in reqs]
+        queued = srv.stats()["queued"]
         results = [srv.wait(i) for i in ids]
         st = srv.stats()
-    assert st["peak_bytes"] <= budget and st["completed"] == len(reqs) and st["bytes_in_use"] == 0
+    print("budget %d: peak %d, in use %d, queued after submit %d, batches %d" % (
+        budget, st["peak_bytes"], st["bytes_in_use"], queued, st["batches"]), flush=True)
+    assert 0 < st["peak_bytes"] <= budget and st["completed"] == len(reqs)
+    assert 0 < st["bytes_in_use"] <= st["peak_bytes"]
     for (alg, pen, smax, b), res in zip(reqs, results):
         assert not compare(res[:4], oracle.align_batch(b, alg, pen, smax))
 
 
-def test_oversized_request_is_refused():
-    b = synth.workload("swg150", n=2000)
-    with aim.Server(0, n_streams=1, budget_bytes=1 << 20) as srv:
+def test_oversized_request_and_budget_refused():
+    # 64 MiB for one stream: 8 MiB of input staging, which 60,000 pairs of
+    # 150 bp do not fit
+    b = synth.workload("swg150", n=60000)
+    with aim.Server(0, n_streams=1, budget_bytes=64 << 20) as srv:
         with pytest.raises(aim.AimError) as ei:
             _submit(srv, "swg", (0, 4, 6, 2), -1, b)
         assert ei.value.code == -1
+        # a request that fits is still served
+        small = synth.workload("swg150", n=500)
+        assert not compare(srv.wait(_submit(srv, "swg", (0, 4, 6, 2), -1, small))[:4],
+                           oracle.align_batch(small, "swg", (0, 4, 6, 2), -1))
+    with pytest.raises(aim.AimError) as ei:
+        aim.Server(0, n_streams=2, budget_bytes=100 << 20)  # under 64 MiB per stream
+    assert ei.value.code == -1
 
 
 def test_concurrent_submitters():
