@@ -9,7 +9,8 @@ imports it.
   Smith-Waterman-Gotoh (affine gaps) with the canonical traceback and the
   threshold rule; see that file's header for the definitions it writes out.
 * ``wfa_scalar.c`` -- a scalar wavefront algorithm, a second route to the
-  same optimum used to pin the first one (and to count wavefront work).
+  same optimum used to pin the first one (and to count wavefront work), and
+  its adaptive (heuristic) variant, WFA-adaptive.
 * ``rescore.py`` -- replays a CIGAR over the two sequences and recomputes its
   cost from the gap model, without any DP.
 """
@@ -54,7 +55,7 @@ def build(force: bool = True, path: str = LIB, native: bool = False) -> str:
 class WfaStats(ctypes.Structure):
     _fields_ = [("cells", ctypes.c_int64), ("compared", ctypes.c_int64),
                 ("wavefronts", ctypes.c_int64), ("words", ctypes.c_int64),
-                ("lo_min", ctypes.c_int32), ("hi_max", ctypes.c_int32)]
+                ("lo_min", ctypes.c_int32), ("hi_max", ctypes.c_int32), ("dropped", ctypes.c_int64)]
 
 
 def bind(path: str):
@@ -70,6 +71,9 @@ def bind(path: str):
     L.oracle_wfa.argtypes = [p, i32, p, i32, i32, i32, i32, i32, i32, p, p, p, i32, p,
                              ctypes.POINTER(WfaStats)]
     L.oracle_wfa.restype = ctypes.c_int
+    L.oracle_wfa_adaptive.argtypes = [p, i32, p, i32, i32, i32, i32, i32, i32, i32, i32, p, p, p, i32, p,
+                                      ctypes.POINTER(WfaStats)]
+    L.oracle_wfa_adaptive.restype = ctypes.c_int
     return L
 
 
@@ -122,10 +126,14 @@ def align_pair(P, T, alg: str, pen, max_score: int = -1, want_cigar: bool = True
     return int(status[0]), int(score[0]), [int(r) for r in runs[:nr[0]]]
 
 
-def wfa_pair(P, T, pen, max_score: int = -1, want_cigar: bool = True, handle=None):
+ADAPTIVE_DEFAULT = (10, 50)  # (min_len, max_dist) of the reduction, as wfa_scalar.c describes
+
+
+def wfa_pair(P, T, pen, max_score: int = -1, want_cigar: bool = True, handle=None, adaptive=None):
     """Scalar WFA.  Returns (status, score, runs, stats dict); the stats are
     the work counters of ``wfa_scalar.c`` (cells, wavefronts, compared, words,
-    lo_min, hi_max)."""
+    lo_min, hi_max, dropped).  ``adaptive`` = (min_len, max_dist) runs
+    WFA-adaptive instead (a heuristic: a valid alignment, cost >= optimum)."""
     _check_pen("wfa", pen)
     P, T = _codes(P), _codes(T)
     m, n = len(P), len(T)
@@ -137,14 +145,43 @@ def wfa_pair(P, T, pen, max_score: int = -1, want_cigar: bool = True, handle=Non
     st = WfaStats()
     Pb = P if m else np.zeros(1, np.uint8)
     Tb = T if n else np.zeros(1, np.uint8)
-    rc = (handle or lib()).oracle_wfa(_ptr(Pb), m, _ptr(Tb), n, pen[1], pen[2], pen[3], max_score,
+    L = handle or lib()
+    if adaptive is None:
+        rc = L.oracle_wfa(_ptr(Pb), m, _ptr(Tb), n, pen[1], pen[2], pen[3], max_score,
                           int(want_cigar), _ptr(score), _ptr(status), _ptr(runs), cap, _ptr(nr),
                           ctypes.byref(st))
+    else:
+        rc = L.oracle_wfa_adaptive(_ptr(Pb), m, _ptr(Tb), n, pen[1], pen[2], pen[3], max_score,
+                                   int(want_cigar), int(adaptive[0]), int(adaptive[1]), _ptr(score),
+                                   _ptr(status), _ptr(runs), cap, _ptr(nr), ctypes.byref(st))
     if rc != 0:
         raise RuntimeError("wfa oracle failure %d" % rc)
     return (int(status[0]), int(score[0]), [int(r) for r in runs[:nr[0]]],
             {"cells": st.cells, "compared": st.compared, "wavefronts": st.wavefronts,
-             "words": st.words, "lo_min": st.lo_min, "hi_max": st.hi_max})
+             "words": st.words, "lo_min": st.lo_min, "hi_max": st.hi_max, "dropped": st.dropped})
+
+
+def wfa_batch(batch, pen, max_score: int = -1, adaptive=None, want_cigar: bool = True,
+              nthreads: int | None = None):
+    """``wfa_pair`` over every pair of a ``synth.PairBatch`` on host threads.
+    Returns (score int32[n], status int8[n], cigar uint32[...], cigar_off
+    int64[n+1]) like ``align_batch``."""
+    from concurrent.futures import ThreadPoolExecutor
+    n = batch.n
+    L = lib()
+
+    def one(i):
+        st, sc, runs, _ = wfa_pair(batch.pattern(i), batch.text(i), pen, max_score, want_cigar, L, adaptive)
+        return st, sc, runs
+
+    with ThreadPoolExecutor(nthreads or os.cpu_count() or 1) as ex:
+        res = list(ex.map(one, range(n)))
+    score = np.array([r[1] for r in res], np.int32)
+    status = np.array([r[0] for r in res], np.int8)
+    off = np.zeros(n + 1, np.int64)
+    off[1:] = np.cumsum([len(r[2]) for r in res])
+    cigar = np.array([x for r in res for x in r[2]], np.uint32)
+    return score, status, cigar, off
 
 
 def align_batch(batch, alg: str, pen, max_score: int = -1, want_cigar: bool = True,

@@ -17,6 +17,19 @@
  * extend(0).  The first s with M_s[n-m] >= n is the optimum.  With
  * max_score >= 0 the search stops (REJECTED) once s exceeds it.
  *
+ * WFA-adaptive (paper: same subsection -- a heuristic variant that drops
+ * outer diagonals unlikely to lead to the optimum; its rule is not spelled
+ * out there, so the reading below is this library's, with the cited WFA
+ * work's usual parameters as defaults): after score s is computed and
+ * extended (and has not reached the end cell), if its range holds at least
+ * min_len diagonals, each diagonal k with an M offset f gets the distance
+ * d(k) = max(m - (f - k), n - f) -- the bases still to align along the longer
+ * side -- and diagonals are removed from each end of the range, inwards, as
+ * long as their M is absent or d(k) - min_k d(k) > max_dist.  The removed
+ * cells of M, I and D no longer exist for later scores (nor for the
+ * backtrace).  The result is a valid alignment whose cost is at least the
+ * optimum.  min_len <= 0 turns the reduction off (exact WFA).
+ *
  * Backtrace (reproduces the Gotoh oracle's canonical CIGAR): from M at
  * (s,k,f) let f0 = max of the three candidates; emit f - f0 '=' ops, then the
  * op of the first candidate attaining f0 in the order X, I, D.  From I (or D)
@@ -32,12 +45,13 @@ enum { OP_EQ = 0, OP_X = 1, OP_I = 2, OP_D = 3 };
 
 typedef struct {
   int32_t lo, hi; /* diagonal range; empty wavefront when lo > hi */
+  int32_t base;   /* diagonal of the arrays' first entry (lo before any reduction) */
   int32_t *M, *I, *D; /* NULL when the component is null */
 } wavefront;
 
 static int32_t wf_get(const wavefront *w, const int32_t *a, int32_t k) {
   if (!a || k < w->lo || k > w->hi) return NEG;
-  return a[k - w->lo];
+  return a[k - w->base];
 }
 
 static int32_t max2(int32_t a, int32_t b) { return a > b ? a : b; }
@@ -53,23 +67,30 @@ static int32_t max2(int32_t a, int32_t b) { return a > b ? a : b; }
  *   words:      the same comparisons taken 32 bases at a time: a run of r
  *               matches costs floor(r / 32) + 1 words when a mismatch stops
  *               it and ceil(r / 32) when it stops at an end;
- *   lo_min, hi_max: the outermost diagonals any wavefront spans. */
-typedef struct { int64_t cells, compared, wavefronts, words; int32_t lo_min, hi_max; } wfa_stats;
+ *   lo_min, hi_max: the outermost diagonals any wavefront spans;
+ *   dropped:    (adaptive) diagonals removed by the reduction. */
+typedef struct { int64_t cells, compared, wavefronts, words; int32_t lo_min, hi_max; int64_t dropped; } wfa_stats;
 
-int oracle_wfa(const uint8_t *P, int32_t m, const uint8_t *T, int32_t n, int32_t x, int32_t o,
-               int32_t e, int32_t max_score, int32_t want_cigar, int32_t *score, int8_t *status,
-               uint32_t *runs, int32_t cap, int32_t *nruns, wfa_stats *st) {
+static int wfa_run(const uint8_t *P, int32_t m, const uint8_t *T, int32_t n, int32_t x, int32_t o,
+                   int32_t e, int32_t max_score, int32_t want_cigar, int32_t min_len, int32_t max_dist,
+                   int32_t *score, int8_t *status, uint32_t *runs, int32_t cap, int32_t *nruns,
+                   wfa_stats *st) {
   int32_t oe = o + e;
   int32_t cap_s = 64;
   wavefront *W = (wavefront *)calloc((size_t)cap_s, sizeof(wavefront));
   if (!W) return -1;
-  wfa_stats S = {0, 0, 0, 0, 0, 0};
+  wfa_stats S = {0, 0, 0, 0, 0, 0, 0};
   int32_t kend = n - m;
   int32_t s = 0;
   int rc = 0, done = 0;
   *nruns = 0;
+  /* no alignment costs more than (m + n) ops at max(x, o + e) each: an
+   * adaptive search that passes that has lost the end cell (it cannot, with
+   * the rule above; the bound keeps a broken variant from running on) */
+  const int64_t s_hard = (int64_t)(m + n) * max2(x, oe) + 1;
   for (;; ++s) {
     if (max_score >= 0 && s > max_score) break;
+    if (min_len > 0 && s > s_hard) { rc = -4; break; }
     if (s >= cap_s) {
       int32_t nc = cap_s * 2;
       wavefront *nw = (wavefront *)realloc(W, sizeof(wavefront) * (size_t)nc);
@@ -83,7 +104,7 @@ int oracle_wfa(const uint8_t *P, int32_t m, const uint8_t *T, int32_t n, int32_t
     const wavefront *wo = s - oe >= 0 ? &W[s - oe] : NULL;
     const wavefront *we = s - e >= 0 ? &W[s - e] : NULL;
     if (s == 0) {
-      w->lo = w->hi = 0;
+      w->lo = w->hi = w->base = 0;
       w->M = (int32_t *)malloc(sizeof(int32_t));
       if (!w->M) { rc = -1; break; }
       w->M[0] = 0;
@@ -100,7 +121,7 @@ int oracle_wfa(const uint8_t *P, int32_t m, const uint8_t *T, int32_t n, int32_t
       if (hi > n) hi = n;
       if (lo > hi) continue;
       int32_t width = hi - lo + 1;
-      w->lo = lo; w->hi = hi;
+      w->lo = lo; w->hi = hi; w->base = lo;
       w->M = (int32_t *)malloc(sizeof(int32_t) * (size_t)width);
       w->I = (int32_t *)malloc(sizeof(int32_t) * (size_t)width);
       w->D = (int32_t *)malloc(sizeof(int32_t) * (size_t)width);
@@ -124,7 +145,7 @@ int oracle_wfa(const uint8_t *P, int32_t m, const uint8_t *T, int32_t n, int32_t
     if (w->hi > S.hi_max) S.hi_max = w->hi;
     /* extend */
     for (int32_t k = w->lo; k <= w->hi; ++k) {
-      int32_t f = w->M[k - w->lo];
+      int32_t f = w->M[k - w->base];
       if (f < 0) continue;
       int32_t i = f - k, j = f, run = 0;
       while (i < m && j < n && P[i] == T[j]) { ++i; ++j; ++run; }
@@ -135,9 +156,37 @@ int oracle_wfa(const uint8_t *P, int32_t m, const uint8_t *T, int32_t n, int32_t
       } else {
         S.words += (run + 31) / 32;
       }
-      w->M[k - w->lo] = j;
+      w->M[k - w->base] = j;
     }
-    if (kend >= w->lo && kend <= w->hi && w->M[kend - w->lo] >= n) { done = 1; break; }
+    if (kend >= w->lo && kend <= w->hi && w->M[kend - w->base] >= n) { done = 1; break; }
+    if (min_len > 0 && w->hi - w->lo + 1 >= min_len) {
+      /* adaptive reduction (see the header) */
+      int32_t dmin = INT32_MAX;
+      for (int32_t k = w->lo; k <= w->hi; ++k) {
+        int32_t f = w->M[k - w->base];
+        if (f < 0) continue;
+        int32_t d = max2(m - (f - k), n - f);
+        if (d < dmin) dmin = d;
+      }
+      if (dmin != INT32_MAX) {
+        /* (the diagonal of distance dmin always stays; the bounds only
+         * guard the loops) */
+        int32_t lo = w->lo, hi = w->hi;
+        while (lo < hi) {
+          int32_t f = w->M[lo - w->base];
+          if (f >= 0 && max2(m - (f - lo), n - f) - dmin <= max_dist) break;
+          ++lo;
+        }
+        while (hi > lo) {
+          int32_t f = w->M[hi - w->base];
+          if (f >= 0 && max2(m - (f - hi), n - f) - dmin <= max_dist) break;
+          --hi;
+        }
+        S.dropped += (int64_t)(lo - w->lo) + (int64_t)(w->hi - hi);
+        w->lo = lo;
+        w->hi = hi;
+      }
+    }
   }
   if (rc == 0 && !done) {
     *score = -1; *status = 1;
@@ -202,4 +251,18 @@ int oracle_wfa(const uint8_t *P, int32_t m, const uint8_t *T, int32_t n, int32_t
   if (st) *st = S;
   if (rc != 0) { *score = -1; *status = (int8_t)rc; }
   return rc;
+}
+
+int oracle_wfa(const uint8_t *P, int32_t m, const uint8_t *T, int32_t n, int32_t x, int32_t o,
+               int32_t e, int32_t max_score, int32_t want_cigar, int32_t *score, int8_t *status,
+               uint32_t *runs, int32_t cap, int32_t *nruns, wfa_stats *st) {
+  return wfa_run(P, m, T, n, x, o, e, max_score, want_cigar, 0, 0, score, status, runs, cap, nruns, st);
+}
+
+int oracle_wfa_adaptive(const uint8_t *P, int32_t m, const uint8_t *T, int32_t n, int32_t x, int32_t o,
+                        int32_t e, int32_t max_score, int32_t want_cigar, int32_t min_len, int32_t max_dist,
+                        int32_t *score, int8_t *status, uint32_t *runs, int32_t cap, int32_t *nruns,
+                        wfa_stats *st) {
+  return wfa_run(P, m, T, n, x, o, e, max_score, want_cigar, min_len, max_dist, score, status, runs, cap,
+                 nruns, st);
 }
