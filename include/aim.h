@@ -54,7 +54,7 @@ typedef int32_t aim_status;
 #define AIM_ERR_BUSY (-5)        /* serving: queue full / request still running */
 #define AIM_ERR_NOT_FOUND (-6)   /* serving: unknown request id */
 
-typedef enum { AIM_NW_LINEAR = 0, AIM_SWG_AFFINE = 1, AIM_WFA_AFFINE = 2 } aim_algorithm;
+typedef enum { AIM_NW_LINEAR = 0, AIM_SWG_AFFINE = 1, AIM_WFA_AFFINE = 2, AIM_WFA_ADAPTIVE = 3 } aim_algorithm;
 
 /* Sequence encodings.  ASCII: bytes 'A','C','G','T' (upper case only).
  * CODE: bytes 0..3 for A, C, G, T.  2BIT: 32 bases per uint64 word, base t of
@@ -69,7 +69,8 @@ typedef enum { AIM_ENC_ASCII = 0, AIM_ENC_CODE = 1, AIM_ENC_2BIT = 2 } aim_encod
 #define AIM_PAIR_CIGAR_OVERFLOW 2 /* score valid, no CIGAR: it did not fit cigar_cap, or
                                      (WFA, scores in the tens of thousands) the
                                      wavefronts its walk needs outgrow the largest
-                                     store the scratch budget allows */
+                                     store the scratch budget allows, or (WFA-
+                                     adaptive) its origin codes outgrew the slot */
 #define AIM_PAIR_INVALID 3        /* non-ACGT base or length beyond max_len */
 
 /* CIGAR run encoding: (run_length << 4) | op. */
@@ -174,7 +175,14 @@ void aim_destroy(aim_context *ctx);
 /* Align every pair of `pairs` (paper: workflow steps 3-5 for all pairs,
  * "Supported Alignment Algorithms" for `alg`), writing `out`.
  *   alg: AIM_NW_LINEAR (NW subsection), AIM_SWG_AFFINE (SWG subsection, global
- *        form), AIM_WFA_AFFINE (WFA subsection, exact gap-affine WFA);
+ *        form), AIM_WFA_AFFINE (WFA subsection, exact gap-affine WFA),
+ *        AIM_WFA_ADAPTIVE (WFA subsection, the heuristic variant that drops
+ *        outer diagonals; see aim_wfa_adaptive_params for the rule -- the
+ *        result is a valid alignment whose cost is at least the optimum and
+ *        at most the reported score, and is the same as exact WFA whenever
+ *        no diagonal is dropped; max_len <= 16,000, else
+ *        AIM_ERR_UNSUPPORTED; a pair whose score passes 16,000 times the
+ *        penalties' common divisor is AIM_PAIR_INVALID);
  *   pen: scoring parameters (see aim_penalties);
  *   max_score: threshold in penalty units; a pair whose optimum exceeds it is
  *        AIM_PAIR_REJECTED; < 0 means no threshold.  Results of accepted pairs
@@ -203,6 +211,19 @@ aim_status aim_align_batch(aim_context *ctx, const aim_batch *pairs, int32_t alg
 aim_status aim_align_batch_static(aim_context *ctx, const aim_batch *pairs, int32_t alg,
                                   aim_penalties pen, int32_t max_score, aim_results *out,
                                   void *stream);
+
+/* Parameters of AIM_WFA_ADAPTIVE on this context (defaults 10 and 50).
+ * Paper: WFA subsection -- WFA-adaptive removes the outer diagonals unlikely
+ * to lead to the optimum; the rule (a reading, the paper gives none): after
+ * each score's wavefront is computed and extended, if it spans at least
+ * min_len diagonals, each diagonal k whose M offset f reaches text position
+ * f and pattern position f - k gets the distance max(m - (f - k), n - f) to
+ * the end, and diagonals are removed from both ends of the range, inwards,
+ * while their M is absent or their distance exceeds the smallest by more
+ * than max_dist; removed cells no longer feed later scores.  The score is
+ * the first wavefront score that reaches the end cell.  min_len >= 1,
+ * max_dist >= 0, else AIM_ERR_INVALID_ARG. */
+aim_status aim_wfa_adaptive_params(aim_context *ctx, int32_t min_len, int32_t max_dist);
 
 /* Device bytes the context's scratch holds now (`current`) and the most it
  * has held at any time since aim_create (`peak`), from the context's own
@@ -288,7 +309,8 @@ aim_status aim_timing_reset(aim_context *ctx);
  *     window class, and its window in diagonals (0: no such class);
  *     wfa_wide counts the pairs that outgrew them all (HBM-ring pass);
  *   prefilter_rejected: pairs rejected by the pre-alignment filter before
- *     any aligner ran (see aim_prefilter). */
+ *     any aligner ran (see aim_prefilter);
+ *   wfa_adaptive_dropped: diagonals the WFA-adaptive reduction removed. */
 typedef struct {
   int64_t n_pairs;
   int32_t band_escalated, band_escalated2;
@@ -299,6 +321,7 @@ typedef struct {
   int32_t wfa_class_pairs[4];
   int32_t wfa_class_window[4];
   int32_t prefilter_rejected;
+  int64_t wfa_adaptive_dropped;
 } aim_call_stats;
 aim_status aim_last_call_stats(aim_context *ctx, aim_call_stats *out);
 

@@ -14,8 +14,8 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libaim.so")
 
-NW_LINEAR, SWG_AFFINE, WFA_AFFINE = 0, 1, 2
-ALGORITHMS = {"nw": NW_LINEAR, "swg": SWG_AFFINE, "wfa": WFA_AFFINE}
+NW_LINEAR, SWG_AFFINE, WFA_AFFINE, WFA_ADAPTIVE = 0, 1, 2, 3
+ALGORITHMS = {"nw": NW_LINEAR, "swg": SWG_AFFINE, "wfa": WFA_AFFINE, "wfa_adaptive": WFA_ADAPTIVE}
 ENC_ASCII, ENC_CODE, ENC_2BIT = 0, 1, 2
 KERNEL_AUTO, KERNEL_PLAIN = 0, 1
 FLAG_TIMING = 1
@@ -76,7 +76,7 @@ class CallStats(ctypes.Structure):
     _fields_ = [("n_pairs", i64), ("band_escalated", i32), ("band_escalated2", i32), ("wfa_wide", i32),
                 ("wfa_walk_failed", i32), ("wfa_walk_skipped", i32), ("full_store", i32 * 4),
                 ("cigar_reruns", i32), ("wfa_window", i32), ("wfa_class_pairs", i32 * 4),
-                ("wfa_class_window", i32 * 4), ("prefilter_rejected", i32)]
+                ("wfa_class_window", i32 * 4), ("prefilter_rejected", i32), ("wfa_adaptive_dropped", i64)]
 
 
 class AimError(RuntimeError):
@@ -94,6 +94,7 @@ SIGNATURES = {
                                 vp], i32),
     "aim_prefilter": ([vp, ctypes.POINTER(Batch), i32, Penalties, i32, vp, vp, vp], i32),
     "aim_scratch_usage": ([vp, ctypes.POINTER(i64), ctypes.POINTER(i64)], i32),
+    "aim_wfa_adaptive_params": ([vp, i32, i32], i32),
     "aim_pack_2bit": ([vp, i64, i32, vp, vp, vp, vp, i64, vp, vp, vp], i32),
     "aim_timing": ([vp, i32, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_double),
                     ctypes.POINTER(i64)], i32),
@@ -223,6 +224,10 @@ class Context:
                              score, status, cigar, cigar_off, want_cigar)
         _check(lib().aim_align_batch_static(self._h, ctypes.byref(b), a, Penalties(*pen), max_score,
                                             ctypes.byref(r), _stream(stream)))
+
+    def wfa_adaptive_params(self, min_len: int, max_dist: int):
+        """aim_wfa_adaptive_params: the reduction rule of alg "wfa_adaptive"."""
+        _check(lib().aim_wfa_adaptive_params(self._h, min_len, max_dist))
 
     def scratch_usage(self):
         """aim_scratch_usage: (current, peak) device bytes of the context's scratch."""

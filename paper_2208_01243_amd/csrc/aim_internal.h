@@ -246,6 +246,13 @@ struct WfaLds {
   // workgroup (wfa_ring_words), instead of LDS
   uint32_t *gring;
   int64_t gring_slot;
+  // WFA-adaptive (ad_min > 0): after each score, trim outer diagonals whose
+  // distance to the end lags the best by more than ad_max once the range
+  // spans ad_min diagonals; ad_dropped counts them.  A pair whose codes do
+  // not fit, or that passes s_cap, gets no fallback (the exact passes would
+  // compute another alignment).
+  int32_t ad_min, ad_max;
+  unsigned long long *ad_dropped;
 };
 int64_t wfa_ring_words(int32_t W, int32_t MG, int32_t R, int32_t e);
 size_t wfa_lds_bytes(int32_t W, int32_t MG, int32_t R, int32_t e, int32_t seq_words, bool gring);

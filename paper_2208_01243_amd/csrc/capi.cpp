@@ -163,6 +163,8 @@ struct aim_context {
   int64_t last_n = 0;
   int32_t last_window = 0;  // diagonals of the one-wavefront WFA window (0: not run)
   int32_t last_class_window[4] = {0, 0, 0, 0};  // windows of the LDS classes (0: none)
+  // WFA-adaptive reduction parameters (aim_wfa_adaptive_params)
+  int32_t ad_min = 10, ad_max = 50;
 };
 
 namespace {
@@ -259,9 +261,11 @@ constexpr int64_t SPLIT_MIN_PAIRS = 65536;
 
 // WFA requires a bounded ring of past wavefronts: max(x, o + e) <= this.
 constexpr int32_t WFA_MAX_STEP = 1024;
+// WFA-adaptive runs on 16-bit offsets over a window of every diagonal
+constexpr int32_t WFA_ADAPTIVE_MAX_LEN = 16000;
 
 aim_status check_pen(int32_t alg, const aim_penalties &pen) {
-  if (alg < AIM_NW_LINEAR || alg > AIM_WFA_AFFINE) return fail(AIM_ERR_INVALID_ARG, "unknown algorithm %d", alg);
+  if (alg < AIM_NW_LINEAR || alg > AIM_WFA_ADAPTIVE) return fail(AIM_ERR_INVALID_ARG, "unknown algorithm %d", alg);
   if (pen.match != 0) return fail(AIM_ERR_UNSUPPORTED, "match cost must be 0 (got %d)", pen.match);
   if (pen.mismatch <= 0 || pen.gap_extend <= 0 || pen.gap_open < 0)
     return fail(AIM_ERR_INVALID_ARG, "penalties need mismatch > 0, gap_extend > 0, gap_open >= 0");
@@ -269,7 +273,8 @@ aim_status check_pen(int32_t alg, const aim_penalties &pen) {
     return fail(AIM_ERR_INVALID_ARG, "penalties must not exceed 65535");
   if (alg == AIM_NW_LINEAR && pen.gap_open != 0)
     return fail(AIM_ERR_INVALID_ARG, "linear NW takes gap_open 0 (one gap base costs gap_extend)");
-  if (alg == AIM_WFA_AFFINE && (pen.mismatch > WFA_MAX_STEP || pen.gap_open + pen.gap_extend > WFA_MAX_STEP))
+  if ((alg == AIM_WFA_AFFINE || alg == AIM_WFA_ADAPTIVE) &&
+      (pen.mismatch > WFA_MAX_STEP || pen.gap_open + pen.gap_extend > WFA_MAX_STEP))
     return fail(AIM_ERR_UNSUPPORTED, "WFA needs mismatch and gap_open + gap_extend <= %d", WFA_MAX_STEP);
   return AIM_OK;
 }
@@ -339,6 +344,59 @@ aim::Scoring wfa_scoring(const aim::Scoring &P) {
 // whose origin codes did not fit.
 // `order` lists the pairs to align (nullptr: all n), `order_count` its length
 // on the device (nullptr: n).
+// WFA-adaptive: every pair through the packed wavefront kernel with its
+// ring in a global slot and a window of every diagonal the batch can reach,
+// plus the reduction step.  Wk lists the pairs (a re-run when Wk.direct).
+aim_status run_wfa_adaptive(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const aim::Scoring &Pin,
+                            int64_t n, int32_t L, int32_t *cnt, const aim::Work &Wk, const Tune &tu,
+                            hipStream_t s) {
+  aim_status st;
+  const aim::Scoring P = wfa_scoring(Pin);
+  aim::WfaLds D{};
+  D.R = std::max(P.x, P.o + P.e) + 1;
+  D.MG = 2 * D.R + 4;
+  D.W = (2 * L + 2 + 3) / 4 * 4 + 4;
+  D.seq_words = (L + 31) / 32;
+  D.s_cap = 16000;
+  D.my_class = 1;
+  D.ad_min = c->ad_min;
+  D.ad_max = c->ad_max;
+  D.ad_dropped = reinterpret_cast<unsigned long long *>(cnt + C_N);
+  D.walk_fail = cnt + C_WF;
+  D.walk_skip = cnt + C_WS;
+  const int32_t threads = tu.wfa_cls_threads[0];
+  const size_t lds = aim::wfa_lds_bytes(D.W, D.MG, D.R, P.e, D.seq_words, true);
+  if (lds > 160 * 1024) return fail(AIM_ERR_UNSUPPORTED, "WFA-adaptive: sequences too long to stage");
+  const int32_t per_cu = (int32_t)std::max<size_t>(1, std::min<size_t>(160 * 1024 / lds, 2048 / threads));
+  int32_t nslots = (int32_t)std::min<int64_t>(n, (int64_t)c->cus * per_cu);
+  // per workgroup slot: the ring (with its guard word) and, with CIGARs, the
+  // score table and the origin codes of every kept score, within a third of
+  // the budget each way (fewer workgroups when they do not fit)
+  D.gring_slot = (aim::wfa_ring_words(D.W, D.MG, D.R, P.e) + 1 + 63) / 64 * 64;
+  const int64_t share = c->limit() / 3;
+  nslots = (int32_t)std::max<int64_t>(1, std::min<int64_t>(nslots, share / (D.gring_slot * 4)));
+  // scores kept: up to what any alignment of the batch can cost (2 L ops at
+  // the dearest step), at most s_cap; codes: up to the widest row at every
+  // kept score, at most 4 MiB per slot (a pair needing more gets no CIGAR)
+  const int64_t steps = std::min<int64_t>(D.s_cap, 2 * (int64_t)L * std::max(P.x, P.o + P.e) + 1) + 1;
+  D.steps_cap = P.want_cigar ? (int32_t)steps : 0;
+  if (P.want_cigar) {
+    const int64_t fixed = (int64_t)D.steps_cap * 12;
+    nslots = (int32_t)std::max<int64_t>(1, std::min<int64_t>(nslots, share / (fixed + (256 << 10))));
+    const int64_t most = std::min<int64_t>(steps * (D.W / 2 + 1), (int64_t)4 << 20);
+    D.code_cap = std::max<int64_t>(std::min<int64_t>(share / nslots - fixed, most), 256 << 10);
+  }
+  D.code_slot = ((int64_t)D.steps_cap * 12 + D.code_cap + 255) / 256 * 256;
+  if ((st = ensure(c, c->sc->wgring, (size_t)D.gring_slot * 4 * nslots))) return st;
+  if ((st = ensure(c, c->sc->wlds, std::max<size_t>((size_t)D.code_slot * nslots, 256)))) return st;
+  D.gring = as<uint32_t>(c->sc->wgring);
+  D.codes = as<uint8_t>(c->sc->wlds);
+  c->last_class_window[0] = D.W;
+  Phase ph(c, s, Wk.direct ? "wfa_adaptive_rerun" : "wfa_adaptive");
+  HIP_TRY(aim::launch_wfa_lds(S, O, P, Wk, D, threads, nslots, s));
+  return AIM_OK;
+}
+
 aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const aim::Scoring &Pin,
                    int64_t n, int32_t L, bool plain, int32_t *cnt, const int32_t *order,
                    const int32_t *order_count, const Tune &tu, hipStream_t s) {
@@ -754,6 +812,8 @@ static aim_status align_batch(aim_context *c, const aim_batch *B, int32_t alg, a
   if (R->want_cigar && (!R->cigar_off || R->cigar_cap < 0 || (R->cigar_cap > 0 && !R->cigar)))
     return fail(AIM_ERR_INVALID_ARG, "want_cigar needs cigar_off and a cigar buffer of cigar_cap >= 0");
   if (!c) return fail(AIM_ERR_INVALID_ARG, "ctx is NULL");
+  if (alg == AIM_WFA_ADAPTIVE && B->max_len > WFA_ADAPTIVE_MAX_LEN)
+    return fail(AIM_ERR_UNSUPPORTED, "WFA-adaptive takes max_len <= %d", WFA_ADAPTIVE_MAX_LEN);
   DeviceGuard g(c->device);
   hipStream_t s = (hipStream_t)stream;
 
@@ -792,7 +852,7 @@ static aim_status align_batch(aim_context *c, const aim_batch *B, int32_t alg, a
   c->last_n = n;
   c->last_window = 0;
   for (int k = 0; k < 4; ++k) c->last_class_window[k] = 0;
-  HIP_TRY(aim::launch_fill_i32(cnt, 0, C_N, s));
+  HIP_TRY(aim::launch_fill_i32(cnt, 0, C_N + 2, s));  // + the 64-bit adaptive drop count
 
   // ---- input encoding ----
   aim::Seqs S;
@@ -812,7 +872,7 @@ static aim_status align_batch(aim_context *c, const aim_batch *B, int32_t alg, a
   HIP_TRY(aim::launch_fill_i32(as<int32_t>(c->sc->total) + 2, 0, 2, s));
   // a2: length buckets, longest first (LPT order for the persistent queues)
   const Tune tu = tune_for(c, alg, L);
-  const bool do_sort = tu.sort >= 0 ? tu.sort != 0 : (alg == AIM_WFA_AFFINE || L >= 512);
+  const bool do_sort = tu.sort >= 0 ? tu.sort != 0 : (alg != AIM_NW_LINEAR && alg != AIM_SWG_AFFINE) || L >= 512;
   const int32_t *order = nullptr;
   if (do_sort && c->opt.kernel != AIM_KERNEL_PLAIN) {
     if ((st = ensure(c, c->sc->order, (size_t)n * 4))) return st;
@@ -853,7 +913,10 @@ static aim_status align_batch(aim_context *c, const aim_batch *B, int32_t alg, a
     return AIM_OK;
   };
 
-  if (alg == AIM_WFA_AFFINE) {
+  if (alg == AIM_WFA_ADAPTIVE) {
+    aim::Work WA{order, order_count, n, cnt + C_W1, nullptr, nullptr, 0};
+    if ((st = run_wfa_adaptive(c, S, O, P, n, L, cnt, WA, tu, s))) return st;
+  } else if (alg == AIM_WFA_AFFINE) {
     if ((st = run_wfa(c, S, O, P, n, L, plain, cnt, order, order_count, tu, s))) return st;
   } else if (plain) {
     aim::Work W1{nullptr, nullptr, n, cnt + C_T1, nullptr, nullptr, 0};
@@ -963,7 +1026,9 @@ static aim_status align_batch(aim_context *c, const aim_batch *B, int32_t alg, a
   }
   // pairs whose runs exceeded the slot: recompute and write in place
   aim::Work WS{as<int32_t>(c->sc->spill), cnt + C_SPILL, n, cnt + C_SPILL_W, nullptr, nullptr, 1};
-  if (alg == AIM_WFA_AFFINE) {
+  if (alg == AIM_WFA_ADAPTIVE) {
+    if ((st = run_wfa_adaptive(c, S, O, P, n, L, cnt, WS, tu, s))) return st;
+  } else if (alg == AIM_WFA_AFFINE) {
     const aim::Scoring PW = wfa_scoring(P);
     aim::WfaPlan pl = aim::wfa_plan(L, PW, c->limit(), c->cus, plain, tu.wfa_ring_kb,
                                     tu.wfa_trace_kb, tu.wfa_long_threads, c->strict());
@@ -1024,6 +1089,9 @@ aim_status aim_last_call_stats(aim_context *c, aim_call_stats *out) {
     out->wfa_class_window[k] = c->last_class_window[k];
   }
   out->prefilter_rejected = v[C_FR];
+  unsigned long long dropped = 0;
+  HIP_TRY(hipMemcpy(&dropped, c->last_cnt + C_N, sizeof dropped, hipMemcpyDeviceToHost));
+  out->wfa_adaptive_dropped = (int64_t)dropped;
   return AIM_OK;
 }
 
@@ -1054,6 +1122,15 @@ aim_status aim_align_batch_static(aim_context *c, const aim_batch *B, int32_t al
   c->has_done = true;
   c->done_stream = s;
   return st;
+}
+
+aim_status aim_wfa_adaptive_params(aim_context *c, int32_t min_len, int32_t max_dist) {
+  g_err.clear();
+  if (!c) return fail(AIM_ERR_INVALID_ARG, "ctx is NULL");
+  if (min_len < 1 || max_dist < 0) return fail(AIM_ERR_INVALID_ARG, "need min_len >= 1 and max_dist >= 0");
+  c->ad_min = min_len;
+  c->ad_max = max_dist;
+  return AIM_OK;
 }
 
 aim_status aim_scratch_usage(aim_context *c, int64_t *current, int64_t *peak) {

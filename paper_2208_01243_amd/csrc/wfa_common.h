@@ -143,9 +143,12 @@ __device__ __forceinline__ uint8_t code_pair(int32_t code) {
 // so that two moves follow every round trip to memory (worth it where the walk
 // is on the critical path: the few long pairs of a wide-pair pass); without,
 // each move loads the one code it needs.
+// dst non-null: the runs go straight to dst (the pair's CIGAR range, `total`
+// runs, filled last run first as the slots are) and nruns is left as is.
 template <bool AHEAD, class CodeAt, class Ext>
 __device__ bool walk_codes(const Outs &O, int64_t p, CodeAt code_at, Ext ext, int32_t x, int32_t oe,
-                           int32_t e, int32_t m, int32_t n, int32_t sfin, uint32_t *tok, int32_t tok_cap) {
+                           int32_t e, int32_t m, int32_t n, int32_t sfin, uint32_t *tok, int32_t tok_cap,
+                           uint32_t *dst = nullptr, int32_t total = 0) {
   const int lane = threadIdx.x & 63;
   int32_t cs = sfin, k = n - m, comp = 0, nt = 0;
   bool ok = true;
@@ -249,7 +252,11 @@ __device__ bool walk_codes(const Outs &O, int64_t p, CodeAt code_at, Ext ext, in
   __threadfence_block();
   if (lane == 0) {
     RunSink sink;
-    sink.begin(O, p);
+    if (!dst) sink.begin(O, p);
+    auto put = [&](int32_t nr, uint32_t run, int64_t more) {
+      if (!dst) sink.put(nr, run, more);
+      else if (nr < total) dst[total - 1 - nr] = run;
+    };
     uint32_t cur_op = 0xffu, cur_len = 0;
     int32_t nr = 0;
     for (int32_t t = 0; t < nt; ++t) {
@@ -260,14 +267,16 @@ __device__ bool walk_codes(const Outs &O, int64_t p, CodeAt code_at, Ext ext, in
       if (op == cur_op) {
         cur_len += len;
       } else {
-        if (cur_len) sink.put(nr++, (cur_len << 4) | cur_op, nt - t + 1);
+        if (cur_len) put(nr++, (cur_len << 4) | cur_op, nt - t + 1);
         cur_op = op;
         cur_len = len;
       }
     }
-    if (cur_len) sink.put(nr++, (cur_len << 4) | cur_op, 1);
-    sink.finish();
-    O.nruns[p] = nr;
+    if (cur_len) put(nr++, (cur_len << 4) | cur_op, 1);
+    if (!dst) {
+      sink.finish();
+      O.nruns[p] = nr;
+    }
   }
   return true;
 }

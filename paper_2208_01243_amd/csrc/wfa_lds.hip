@@ -125,7 +125,7 @@ struct RingIO<true> {
 // GRING: the ring rows live in this workgroup's slot of a global buffer
 // (HBM, cached in L2 and the infinity cache) instead of LDS, so that many
 // more workgroups fit a CU; the arithmetic is the same.
-template <int T, bool GRING>
+template <int T, bool GRING, bool ADAPT>
 __global__ __launch_bounds__(T) void k_wfa_lds(Seqs S, Outs O, Scoring P, Work Wk, WfaLds L) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x;
@@ -326,6 +326,79 @@ __global__ __launch_bounds__(T) void k_wfa_lds(Seqs S, Outs O, Scoring P, Work W
         ring.st(rI, q, ABSENT2);
         ring.st(rD, q, ABSENT2);
       }
+      if constexpr (ADAPT) {
+        if (hi - lo + 1 >= L.ad_min) __syncthreads();  // the rows of this score, and shv, are settled
+        // (a score that reached the end cell is the last: no reduction)
+        if (hi - lo + 1 >= L.ad_min && !__builtin_amdgcn_readfirstlane(shv[1])) {
+          // WFA-adaptive reduction of this score's range, from the extended
+          // M row: d(k) = max(m - i, n - j) of its offset; the ends go while
+          // absent or more than ad_max behind the best d
+          __syncthreads();  // every lane has read the end flag
+          if (tid == 0) {
+            shv[3] = INT32_MAX;
+            shv[4] = INT32_MAX;
+            shv[5] = INT32_MIN;
+          }
+          __syncthreads();
+          auto dist = [&](int32_t k, int32_t f) { return max(m - (f - k), n - f); };
+          auto entry = [&](uint32_t wv, int32_t h) { return (int32_t)(int16_t)(h ? (wv >> 16) : (wv & 0xffffu)); };
+          int32_t dl = INT32_MAX;
+          for (int32_t q = q_lo + tid; q <= q_hi; q += T) {
+            const uint32_t wv = ring.ld(rM, q, 0);
+            const int32_t k0 = 2 * q - MG + kbase;
+            for (int32_t h = 0; h < 2; ++h) {
+              const int32_t k = k0 + h, f = entry(wv, h);
+              if (k >= lo && k <= hi && f >= 0) dl = min(dl, dist(k, f));
+            }
+          }
+          dl = -wave_max_i32(-dl);
+          if ((tid & 63) == 0) atomicMin(&shv[3], dl);
+          __syncthreads();
+          const int32_t dmin = __builtin_amdgcn_readfirstlane(shv[3]);
+          if (dmin != INT32_MAX) {
+            int32_t kl = INT32_MAX, kh = INT32_MIN;
+            for (int32_t q = q_lo + tid; q <= q_hi; q += T) {
+              const uint32_t wv = ring.ld(rM, q, 0);
+              const int32_t k0 = 2 * q - MG + kbase;
+              for (int32_t h = 0; h < 2; ++h) {
+                const int32_t k = k0 + h, f = entry(wv, h);
+                if (k >= lo && k <= hi && f >= 0 && dist(k, f) - dmin <= L.ad_max) {
+                  kl = min(kl, k);
+                  kh = max(kh, k);
+                }
+              }
+            }
+            kl = -wave_max_i32(-kl);
+            kh = wave_max_i32(kh);
+            if ((tid & 63) == 0) {
+              atomicMin(&shv[4], kl);
+              atomicMax(&shv[5], kh);
+            }
+            __syncthreads();
+            const int32_t nlo = __builtin_amdgcn_readfirstlane(shv[4]);
+            const int32_t nhi = __builtin_amdgcn_readfirstlane(shv[5]);
+            // absent marks over the dropped diagonals of the three rows; a
+            // word is rewritten by one lane, its kept half unchanged
+            auto trim = [&](int32_t ka, int32_t kb) {  // drop [ka, kb]
+              if (ka > kb) return;
+              for (int32_t q = widx(ka) + tid; q <= widx(kb); q += T) {
+                const int32_t k0 = 2 * q - MG + kbase;
+                const uint32_t mask = ((k0 >= ka && k0 <= kb) ? 0xffffu : 0u) |
+                                      ((k0 + 1 >= ka && k0 + 1 <= kb) ? 0xffff0000u : 0u);
+                ring.st(rM, q, (ring.ld(rM, q, 0) & ~mask) | (ABSENT2 & mask));
+                ring.st(rI, q, (ring.ld(rI, q, 0) & ~mask) | (ABSENT2 & mask));
+                ring.st(rD, q, (ring.ld(rD, q, 0) & ~mask) | (ABSENT2 & mask));
+              }
+            };
+            trim(lo, nlo - 1);
+            trim(nhi + 1, hi);
+            if (tid == 0 && L.ad_dropped && (nlo - lo) + (hi - nhi) > 0)
+              atomicAdd(L.ad_dropped, (unsigned long long)((nlo - lo) + (hi - nhi)));
+            lo = nlo;
+            hi = nhi;
+          }
+        }
+      }
       if (tid == 0) {
         tab[4 * sl] = lo;
         tab[4 * sl + 1] = hi;
@@ -339,6 +412,12 @@ __global__ __launch_bounds__(T) void k_wfa_lds(Seqs S, Outs O, Scoring P, Work W
       if (keep) cb += nbytes;
       need += ENTRY_WORDS + (3 * (int64_t)(hi - lo + 1) + 1) / 2;
       __syncthreads();
+    }
+    if (ADAPT && (result == 3 || result == 5)) {
+      // the window holds every diagonal of the batch, so only s_cap ends
+      // here: a score this class cannot represent
+      if (tid == 0) { O.score[p] = -1; O.status[p] = ST_INVALID; O.nruns[p] = 0; }
+      continue;
     }
     if (result == 3 || result == 5) {
       // on to a wider class, with the window the pair is predicted to need:
@@ -386,13 +465,18 @@ __global__ __launch_bounds__(T) void k_wfa_lds(Seqs S, Outs O, Scoring P, Work W
           return (int32_t)(((k - klo) & 1) ? (b >> 4) : (b & 15u));
         };
         auto ext = [&](int32_t k, int32_t f) { return extend_lds(P32, m, T32, n, k, f); };
-        walked = walk_codes<true>(O, p, code_at, ext, x, oe, e, m, n, s, ringM, tok_cap);
+        // a re-run of a pair whose runs outgrew its slot and the pool writes
+        // them straight into its CIGAR range
+        uint32_t *dst = (ADAPT && Wk.direct) ? O.cigar + O.cigar_off[p] : nullptr;
+        walked = walk_codes<true>(O, p, code_at, ext, x, oe, e, m, n, s, ringM, tok_cap, dst,
+                                  dst ? O.nruns[p] : 0);
         if (!walked && tid == 0 && L.walk_fail) atomicAdd(L.walk_fail, 1);
       }
       __syncthreads();
     } else if (result == 1 && P.want_cigar && tid == 0 && L.walk_skip) {
       atomicAdd(L.walk_skip, 1);  // codes not kept: the full-store pass walks it
     }
+    if (ADAPT && Wk.direct) continue;  // a re-run: the other outputs are final
     if (tid == 0) {
       if (result == 2 || result == 4) {
         O.score[p] = -1;
@@ -402,7 +486,9 @@ __global__ __launch_bounds__(T) void k_wfa_lds(Seqs S, Outs O, Scoring P, Work W
         O.score[p] = s * P.unit;
         O.status[p] = ST_ALIGNED;
         if (!walked) O.nruns[p] = 0;
-        if (P.want_cigar && !walked) {
+        if (ADAPT && P.want_cigar && !walked) {
+          O.status[p] = ST_OVERFLOW;  // no exact fallback for a heuristic alignment
+        } else if (P.want_cigar && !walked) {
           L.need[p] = need;
           int c = 0;
           while (c < 3 && need > L.need_cap[c]) ++c;
@@ -433,11 +519,22 @@ hipError_t launch_wfa_lds(const Seqs &S, const Outs &O, const Scoring &P, const 
                           int32_t threads, int32_t nslots, hipStream_t s) {
   const bool g = L.gring != nullptr;
   const size_t lds = wfa_lds_bytes(L.W, L.MG, L.R, P.e, L.seq_words, g);
-#define AIM_LAUNCH_LDS(TT)                                                                      \
-  if (g)                                                                                        \
-    hipLaunchKernelGGL((k_wfa_lds<TT, true>), dim3(nslots), dim3(TT), lds, s, S, O, P, Wk, L);  \
-  else                                                                                          \
-    hipLaunchKernelGGL((k_wfa_lds<TT, false>), dim3(nslots), dim3(TT), lds, s, S, O, P, Wk, L);
+  if (L.ad_min > 0) {
+    // WFA-adaptive: global ring only
+    if (!g) return hipErrorInvalidValue;
+    switch (threads) {
+      case 64: hipLaunchKernelGGL((k_wfa_lds<64, true, true>), dim3(nslots), dim3(64), lds, s, S, O, P, Wk, L); break;
+      case 128: hipLaunchKernelGGL((k_wfa_lds<128, true, true>), dim3(nslots), dim3(128), lds, s, S, O, P, Wk, L); break;
+      case 256: hipLaunchKernelGGL((k_wfa_lds<256, true, true>), dim3(nslots), dim3(256), lds, s, S, O, P, Wk, L); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
+#define AIM_LAUNCH_LDS(TT)                                                                             \
+  if (g)                                                                                               \
+    hipLaunchKernelGGL((k_wfa_lds<TT, true, false>), dim3(nslots), dim3(TT), lds, s, S, O, P, Wk, L);  \
+  else                                                                                                 \
+    hipLaunchKernelGGL((k_wfa_lds<TT, false, false>), dim3(nslots), dim3(TT), lds, s, S, O, P, Wk, L);
   switch (threads) {
     case 64: AIM_LAUNCH_LDS(64) break;
     case 128: AIM_LAUNCH_LDS(128) break;
