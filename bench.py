@@ -20,7 +20,8 @@ Prints ONE JSON line.  Besides the headline it carries:
   cpu_baseline  -- the oracle, built -O3 -march=native on this host, on a
                    bounded sample, on all granted cores and on one core;
   other_configs -- the NW edit (10k x 100 bp), SWG (1M x 150 bp) and WFA
-                   (1M x 250 bp with 20 % unrelated pairs) workloads;
+                   (1M x 250 bp with 20 % unrelated pairs) workloads, and
+                   WFA-adaptive at 150 bp / 2 %, 1 kbp / 5 %, 10 kbp / 5 %;
   serving       -- the Poisson request schedule through aim_server.
 """
 from __future__ import annotations
@@ -62,6 +63,10 @@ WORKLOAD_TEXT = {
               "threshold 200, 2-bit, score + CIGAR",
     "wfa_mixed": "WFA 4/6/2, 500,000 pairs, 100-10,000 bp log-uniform, 0.5-10% error, 2-bit, "
                  "score + CIGAR",
+    "wfa_adaptive_150": "WFA-adaptive 4/6/2 (10, 50), 1,000,000 pairs x 150 bp, 2% error, 2-bit, score + CIGAR",
+    "wfa_adaptive_1k": "WFA-adaptive 4/6/2 (10, 50), 100,000 pairs x 1,000 bp, 5% error, 2-bit, score + CIGAR",
+    "wfa_adaptive_10k": "WFA-adaptive 4/6/2 (10, 50), 10,000 pairs x 10,000 bp, 5% error, 2-bit, "
+                        "score + CIGAR",
 }
 
 
@@ -74,22 +79,27 @@ def src_hash(kernel):
     return hashlib.sha256(src).hexdigest()[:16]
 
 
-def wfa_units(name, window):
+def wfa_units(name, window, filtered=False):
     """(cells, words) of the pairs the one-wavefront pass completes (extent <=
-    window / 2) and of the rest, from the oracle's counts; None if absent."""
+    window / 2) and of the rest, from the oracle's counts; None if absent.
+    filtered: only the pairs the pre-alignment filter lets through (the
+    wavefront kernels see no others)."""
     path = os.path.join(ROOT, "tests", "golden", "wfa_work.json")
     if not os.path.exists(path):
         return None
     d = json.load(open(path)).get(name)
     if not d:
         return None
+    cols = d["by_extent_columns"]
+    ci, wi = cols.index("pass_cells" if filtered else "cells"), cols.index("pass_words" if filtered else "words")
     inside = [0, 0]
     outside = [0, 0]
-    for ext_max, pairs, acc, cells, words in d["by_extent"]:
+    for row in d["by_extent"]:
+        ext_max = row[0]
         tgt = inside if (ext_max is not None and ext_max <= window // 2) else outside
-        tgt[0] += cells
-        tgt[1] += words
-    return {"inside": inside, "outside": outside, "cells": d["cells"], "words": d["words"]}
+        tgt[0] += row[ci]
+        tgt[1] += row[wi]
+    return {"inside": inside, "outside": outside, "cells": inside[0] + outside[0], "words": inside[1] + outside[1]}
 
 
 class Run:
@@ -154,6 +164,24 @@ def roofline(run, phases, stats, steps):
                 "unit": unit, "frac": round(ops / t / 1e12 / peak, 4), "traffic": traffic,
                 "avg_launch_ms": round(ms / launches, 4), "ops_per_unit": OPS_PER_CELL[w["alg"]],
                 "units_per_launch": cells, "unit_name": "band cells (m x 32 per pair)"}
+    if w["alg"] == "wfa_adaptive":
+        # one kernel (k_wfa_lds with the reduction step) over every pair
+        if "wfa_adaptive" not in phases:
+            return None
+        ms, launches = phases["wfa_adaptive"]
+        ms /= max(1, launches)
+        units = wfa_units(run.name, 0) if run.n == w["total"] else None
+        out = {"bound": "alu", "kernel": "k_wfa_lds (adaptive)", "avg_launch_ms": round(ms, 4),
+               "peak": round(PEAK_INT32_TOPS, 1), "unit": "Tops/s (int32)",
+               "ops_per_unit": {"wavefront cell": WFA_OPS_PER_CELL, "extension word": WFA_OPS_PER_WORD},
+               "achieved": None, "frac": None, "traffic": None}
+        if units:
+            ops = WFA_OPS_PER_CELL * units["cells"] + WFA_OPS_PER_WORD * units["words"]
+            out.update({"achieved": round(ops / (ms / 1000) / 1e12, 3),
+                        "frac": round(ops / (ms / 1000) / 1e12 / PEAK_INT32_TOPS, 4),
+                        "units_per_launch": {"cells": units["cells"], "words": units["words"]},
+                        "unit_name": "cells of the reduced wavefronts (adaptive oracle) of every pair"})
+        return out
     if w["alg"] != "wfa":
         return None
     # the WFA passes of one call: the one-wavefront pass (k_wfa_score16) over
@@ -170,7 +198,8 @@ def roofline(run, phases, stats, steps):
         return None
     ms = per_call[kname]
     launches = sum(phases[k][1] for k in groups[kname] if k in phases) // steps
-    units = wfa_units(run.name, stats.get("wfa_window", 0)) if run.n == w["total"] else None
+    filtered = w["max_score"] >= 0  # the pre-alignment filter runs in front
+    units = wfa_units(run.name, stats.get("wfa_window", 0), filtered) if run.n == w["total"] else None
     out = {"bound": "alu", "kernel": kname, "avg_launch_ms": round(ms, 4), "launches_per_call": launches,
            "peak": round(PEAK_INT32_TOPS, 1), "unit": "Tops/s (int32)",
            "ops_per_unit": {"wavefront cell": WFA_OPS_PER_CELL, "extension word": WFA_OPS_PER_WORD},
@@ -182,8 +211,10 @@ def roofline(run, phases, stats, steps):
         t = ms / 1000.0
         out.update({"achieved": round(ops / t / 1e12, 3), "frac": round(ops / t / 1e12 / PEAK_INT32_TOPS, 4),
                     "units_per_launch": {"cells": cells, "words": words},
-                    "unit_name": "wavefront cells of the pairs %s completes (%s the %d-diagonal window), "
-                                 "its launches of one call together" % (kname, side, stats.get("wfa_window", 0))})
+                    "unit_name": "wavefront cells of the pairs %s completes (%s the %d-diagonal window%s), "
+                                 "its launches of one call together" % (
+                                     kname, side, stats.get("wfa_window", 0),
+                                     "; pairs past the pre-alignment filter" if filtered else "")})
         meas = MEASURED_TRAFFIC.get((run.name, kname))
         if meas and meas[0] == src_hash(kname):
             out["traffic"] = meas[1]
@@ -214,7 +245,7 @@ def measure(aim, synth, name, steps, warmup, plain_steps=0, e2e_reps=0):
            "path_counters": stats}
     log("%s: %.3f ms/step; phases %s" % (name, ms_step, res["phases_ms_per_step"]))
     res["roofline"] = roofline(run, phases, stats, steps)
-    units = wfa_units(name, 0) if run.w["alg"] == "wfa" and run.n == run.w["total"] else None
+    units = wfa_units(name, 0) if run.w["alg"].startswith("wfa") and run.n == run.w["total"] else None
     if units:
         res["wavefront_cells_per_s"] = round(units["cells"] / (elapsed / steps), 1)
     if plain_steps > 0:
@@ -391,7 +422,7 @@ def main():
         out["cpu_baseline"] = cpu_baseline(synth, args.workload, n_all, n_one)
     if args.others:
         others = {}
-        for name in ("nw100", "swg150", "wfa250"):
+        for name in ("nw100", "swg150", "wfa250", "wfa_adaptive_150", "wfa_adaptive_1k", "wfa_adaptive_10k"):
             if name == args.workload:
                 continue
             r, res = measure(aim, synth, name, 20, 3)

@@ -365,16 +365,20 @@ aim_status run_wfa_adaptive(aim_context *c, const aim::Seqs &S, const aim::Outs 
   D.walk_fail = cnt + C_WF;
   D.walk_skip = cnt + C_WS;
   const int32_t threads = tu.wfa_cls_threads[0];
-  const size_t lds = aim::wfa_lds_bytes(D.W, D.MG, D.R, P.e, D.seq_words, true);
+  // the ring in LDS when a window of every diagonal is small (short reads:
+  // no global round trips per score, and the walk's tokens in LDS too),
+  // else in a global slot
+  const bool lds_ring = aim::wfa_lds_bytes(D.W, D.MG, D.R, P.e, D.seq_words, false) <= 24 * 1024;
+  const size_t lds = aim::wfa_lds_bytes(D.W, D.MG, D.R, P.e, D.seq_words, !lds_ring);
   if (lds > 160 * 1024) return fail(AIM_ERR_UNSUPPORTED, "WFA-adaptive: sequences too long to stage");
   const int32_t per_cu = (int32_t)std::max<size_t>(1, std::min<size_t>(160 * 1024 / lds, 2048 / threads));
   int32_t nslots = (int32_t)std::min<int64_t>(n, (int64_t)c->cus * per_cu);
   // per workgroup slot: the ring (with its guard word) and, with CIGARs, the
   // score table and the origin codes of every kept score, within a third of
   // the budget each way (fewer workgroups when they do not fit)
-  D.gring_slot = (aim::wfa_ring_words(D.W, D.MG, D.R, P.e) + 1 + 63) / 64 * 64;
+  D.gring_slot = lds_ring ? 0 : (aim::wfa_ring_words(D.W, D.MG, D.R, P.e) + 1 + 63) / 64 * 64;
   const int64_t share = c->limit() / 3;
-  nslots = (int32_t)std::max<int64_t>(1, std::min<int64_t>(nslots, share / (D.gring_slot * 4)));
+  if (!lds_ring) nslots = (int32_t)std::max<int64_t>(1, std::min<int64_t>(nslots, share / (D.gring_slot * 4)));
   // scores kept: up to what any alignment of the batch can cost (2 L ops at
   // the dearest step), at most s_cap; codes: up to the widest row at every
   // kept score, at most 4 MiB per slot (a pair needing more gets no CIGAR)
@@ -387,9 +391,9 @@ aim_status run_wfa_adaptive(aim_context *c, const aim::Seqs &S, const aim::Outs 
     D.code_cap = std::max<int64_t>(std::min<int64_t>(share / nslots - fixed, most), 256 << 10);
   }
   D.code_slot = ((int64_t)D.steps_cap * 12 + D.code_cap + 255) / 256 * 256;
-  if ((st = ensure(c, c->sc->wgring, (size_t)D.gring_slot * 4 * nslots))) return st;
+  if (!lds_ring && (st = ensure(c, c->sc->wgring, (size_t)D.gring_slot * 4 * nslots))) return st;
   if ((st = ensure(c, c->sc->wlds, std::max<size_t>((size_t)D.code_slot * nslots, 256)))) return st;
-  D.gring = as<uint32_t>(c->sc->wgring);
+  D.gring = lds_ring ? nullptr : as<uint32_t>(c->sc->wgring);
   D.codes = as<uint8_t>(c->sc->wlds);
   c->last_class_window[0] = D.W;
   Phase ph(c, s, Wk.direct ? "wfa_adaptive_rerun" : "wfa_adaptive");
@@ -865,7 +869,7 @@ static aim_status align_batch(aim_context *c, const aim_batch *B, int32_t alg, a
   const int64_t pool_cap =
       R->want_cigar ? std::max<int64_t>(c->strict() ? 1 << 14 : 1 << 20,
                                         std::min<int64_t>(c->limit() / 64 / 4,
-                                                          n * std::min<int64_t>(2 * (int64_t)L + 1, 1024) / 4))
+                                                          n * std::min<int64_t>(2 * (int64_t)L + 1, 8192) / 4))
                     : 1;
   if ((st = ensure(c, c->sc->pool, (size_t)pool_cap * 4))) return st;
   if ((st = ensure(c, c->sc->pooloff, (size_t)n * 8))) return st;

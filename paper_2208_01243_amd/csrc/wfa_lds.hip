@@ -71,20 +71,57 @@ __device__ __forceinline__ uint32_t codes2(s16x2 X, s16x2 I, s16x2 Mv, s16x2 Mo_
   return (nib | (nib >> 12)) & 0xffu;
 }
 
-// Extend offset f (absent when negative) on diagonal k of the staged pair;
-// lim = min(n, m + k).  The first 16 bases by every lane without a branch,
-// the rest only where all 16 matched.
-__device__ __forceinline__ int32_t ext_cell(const uint32_t *P32, const uint32_t *T32, int32_t m, int32_t n,
-                                            int32_t k, int32_t f, int32_t lim) {
-  const bool live = f >= 0;
-  const int32_t j0 = live ? f : 0, i0 = live ? f - k : 0;
-  const int32_t le = live ? lim - f : 0;
-  const uint32_t d = __builtin_amdgcn_alignbit(P32[(i0 >> 4) + 1], P32[i0 >> 4], (uint32_t)i0 << 1) ^
-                     __builtin_amdgcn_alignbit(T32[(j0 >> 4) + 1], T32[j0 >> 4], (uint32_t)j0 << 1);
-  const int32_t run = min(d ? (int32_t)(__builtin_ctz(d) >> 1) : 16, le);
-  int32_t g = j0 + run;
-  if (run == 16) g = extend_lds(P32, m, T32, n, k, g);
-  return live ? g : f;
+// Index of the lowest set bit, all ones for 0 (the instruction's own result;
+// the C builtins leave 0 undefined or add a select for it).
+__device__ __forceinline__ uint32_t ffbl_raw(uint32_t d) {
+  uint32_t r;
+  asm("v_ffbl_b32 %0, %1" : "=v"(r) : "v"(d));
+  return r;
+}
+
+// Equal bases (at most 16, at most le) from pattern base i and text base j.
+__device__ __forceinline__ uint32_t run16(const uint32_t *P32, const uint32_t *T32, int32_t i, int32_t j,
+                                          uint32_t le) {
+  const uint32_t d = __builtin_amdgcn_alignbit(P32[(i >> 4) + 1], P32[i >> 4], (uint32_t)i << 1) ^
+                     __builtin_amdgcn_alignbit(T32[(j >> 4) + 1], T32[j >> 4], (uint32_t)j << 1);
+  return min(min(ffbl_raw(d) >> 1, 16u), le);
+}
+
+// Extension of both offsets of a word (diagonals k0 and k0 + 1; absent when
+// negative; LIM = min(n, m + k) per half).  The first 16 bases of each by
+// every lane without a branch -- an absent offset compares at base 0 under a
+// zero limit (an absent mark is below -16,000 and |k| <= 16,001, so it
+// clamps to 0) -- then one branch for the rare runs of 16 matches.
+__device__ __forceinline__ void ext_pair(const uint32_t *P32, const uint32_t *T32, int32_t m, int32_t n,
+                                         int32_t k0, s16x2 Mv, s16x2 LIM, int32_t &f0, int32_t &f1) {
+  const int32_t a = Mv.x, b = Mv.y;
+  const int32_t ja = max(a, 0), jb = max(b, 0);
+  const int32_t ia = max(a - k0, 0), ib = max(b - k0 - 1, 0);
+  const uint32_t lea = a >= 0 ? (uint32_t)(LIM.x - a) : 0u, leb = b >= 0 ? (uint32_t)(LIM.y - b) : 0u;
+  const uint32_t ra = run16(P32, T32, ia, ja, lea), rb = run16(P32, T32, ib, jb, leb);
+  int32_t ga = ja + (int32_t)ra, gb = jb + (int32_t)rb;
+  if (ra == 16u || rb == 16u) {
+    if (ra == 16u) ga = extend_lds(P32, m, T32, n, k0, ga);
+    if (rb == 16u) gb = extend_lds(P32, m, T32, n, k0 + 1, gb);
+  }
+  f0 = a >= 0 ? ga : a;
+  f1 = b >= 0 ? gb : b;
+}
+
+// Minimum (MAX false) or maximum over the 64 lanes of a wavefront, all
+// active: shifts within rows of 16, then the row broadcasts of lanes 15 and
+// 31 (lanes without a source keep the identity); lane 63 ends with the result.
+template <bool MAX>
+__device__ __forceinline__ int32_t wave_reduce(int32_t v) {
+  constexpr int32_t id = MAX ? INT32_MIN : INT32_MAX;
+  auto op = [](int32_t a, int32_t b) { return MAX ? max(a, b) : min(a, b); };
+  v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x111, 0xf, 0xf, false));  // row_shr:1
+  v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x112, 0xf, 0xf, false));  // row_shr:2
+  v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x114, 0xf, 0xf, false));  // row_shr:4
+  v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x118, 0xf, 0xf, false));  // row_shr:8
+  v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x142, 0xa, 0xf, false));  // row_bcast:15
+  v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x143, 0xc, 0xf, false));  // row_bcast:31
+  return __builtin_amdgcn_readlane(v, 63);
 }
 
 // Buffer resource word 3 for raw (untyped) buffer access on CDNA: 32-bit
@@ -158,6 +195,10 @@ __global__ __launch_bounds__(T) void k_wfa_lds(Seqs S, Outs O, Scoring P, Work W
   int32_t *ctab = reinterpret_cast<int32_t *>(cslot);  // per score: lowest kept diagonal, hi, code offset
   uint8_t *cbytes = cslot + (int64_t)L.steps_cap * 12;
   auto widx = [&](int32_t k) { return (k - kbase + MG) >> 1; };
+  // (adaptive) diagonals this workgroup dropped: one atomic at the end, not
+  // one per score -- thousands of workgroups adding to one address every
+  // score serialise on it
+  uint64_t ad_drop = 0;
   for (;;) {
     __syncthreads();
     if (tid == 0) shv[0] = atomicAdd(Wk.counter, 1);
@@ -215,9 +256,16 @@ __global__ __launch_bounds__(T) void k_wfa_lds(Seqs S, Outs O, Scoring P, Work W
     const int4 *tab4 = reinterpret_cast<const int4 *>(tab);
     // One word of score s (diagonals k0 = 2q - MG + kbase and k0 + 1) from
     // its eight source words: candidates, codes, extension, stores.
+    // what a word leaves behind: whether it reached the end cell, its three
+    // stored words, and (adaptive) the distance to the end of each offset
+    struct WordRes {
+      bool hit;
+      uint32_t mw, iw, dw;
+      int32_t d0, d1;
+    };
     auto word = [&](int32_t q, uint32_t o_m, uint32_t o_0, uint32_t o_p, uint32_t i_0, uint32_t i_p,
                     uint32_t d_m, uint32_t d_0, uint32_t x_0, int32_t rM, int32_t rI, int32_t rD,
-                    uint8_t *crow, int32_t q_lo) {
+                    bool kc, uint8_t *crow, int32_t q_lo) -> WordRes {
       const int32_t k0 = 2 * q - MG + kbase;
       const s16x2 K2 = {(short)k0, (short)(k0 + 1)};
       const s16x2 LIM = __builtin_elementwise_min(__builtin_elementwise_add_sat(M2, K2), N2);
@@ -229,14 +277,23 @@ __global__ __launch_bounds__(T) void k_wfa_lds(Seqs S, Outs O, Scoring P, Work W
       const s16x2 D = clip2(__builtin_elementwise_max(Mo_dn, De_dn) + (short)1, LIM);
       const s16x2 X = clip2(as2(x_0) + (short)1, LIM);
       const s16x2 Mv = __builtin_elementwise_max(X, __builtin_elementwise_max(I, D));
-      // a uniform row base and a 32-bit lane offset (a scalar-base store)
-      if (crow) crow[(uint32_t)(q - q_lo)] = (uint8_t)codes2(X, I, Mv, Mo_up, Ie_up, Mo_dn, De_dn);
-      const int32_t f0 = ext_cell(P32, T32, m, n, k0, Mv.x, LIM.x);
-      const int32_t f1 = ext_cell(P32, T32, m, n, k0 + 1, Mv.y, LIM.y);
-      ring.st(rM, q, __builtin_amdgcn_perm((uint32_t)f1, (uint32_t)f0, 0x05040100u));
+      // a uniform row base and a 32-bit lane offset (a scalar-base store);
+      // kc is uniform, so this is a scalar branch
+      if (kc) crow[(uint32_t)(q - q_lo)] = (uint8_t)codes2(X, I, Mv, Mo_up, Ie_up, Mo_dn, De_dn);
+      int32_t f0, f1;
+      ext_pair(P32, T32, m, n, k0, Mv, LIM, f0, f1);
+      const uint32_t mw = __builtin_amdgcn_perm((uint32_t)f1, (uint32_t)f0, 0x05040100u);
+      ring.st(rM, q, mw);
       ring.st(rI, q, as1(I));
       ring.st(rD, q, as1(D));
-      if ((k0 == kend && f0 >= n) || (k0 + 1 == kend && f1 >= n)) shv[1] = 1;
+      WordRes r;
+      r.hit = (k0 == kend && f0 >= n) || (k0 + 1 == kend && f1 >= n);
+      r.mw = mw;
+      r.iw = as1(I);
+      r.dw = as1(D);
+      r.d0 = f0 >= 0 ? max(m - (f0 - k0), n - f0) : INT32_MAX;
+      r.d1 = f1 >= 0 ? max(m - (f1 - k0 - 1), n - f1) : INT32_MAX;
+      return r;
     };
     while (!result) {
       // after a barrier: the end-cell flag of the last score and the table
@@ -306,6 +363,12 @@ __global__ __launch_bounds__(T) void k_wfa_lds(Seqs S, Outs O, Scoring P, Work W
       const int32_t nbytes = q_hi - q_lo + 1;
       if (keep && (s >= L.steps_cap || cb + nbytes > L.code_cap)) keep = false;
       uint8_t *crow = keep ? cbytes + cb : nullptr;
+      const bool kc = __builtin_amdgcn_readfirstlane((int32_t)keep) != 0;
+      bool hit = false;  // this lane reached the end cell
+      // (adaptive) this lane's words of the first trip, kept for the reduction
+      int32_t fq[2] = {-1, -1};
+      uint32_t fm[2] = {0u, 0u}, fi[2] = {0u, 0u}, fd[2] = {0u, 0u};
+      int32_t fdist[4] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MAX};
       // two words per lane and trip, their sixteen source loads issued first
       for (int32_t qa = q_lo + tid; qa <= q_hi; qa += 2 * T) {
         const bool vb = qa + T <= q_hi;
@@ -316,9 +379,21 @@ __global__ __launch_bounds__(T) void k_wfa_lds(Seqs S, Outs O, Scoring P, Work W
         const uint32_t b_om = ring.ld(rO, qb, -1), b_o0 = ring.ld(rO, qb, 0), b_op = ring.ld(rO, qb, 1);
         const uint32_t b_i0 = ring.ld(rIe, qb, 0), b_ip = ring.ld(rIe, qb, 1);
         const uint32_t b_dm = ring.ld(rDe, qb, -1), b_d0 = ring.ld(rDe, qb, 0), b_x = ring.ld(rX, qb, 0);
-        word(qa, a_om, a_o0, a_op, a_i0, a_ip, a_dm, a_d0, a_x, rM, rI, rD, crow, q_lo);
-        if (vb) word(qb, b_om, b_o0, b_op, b_i0, b_ip, b_dm, b_d0, b_x, rM, rI, rD, crow, q_lo);
+        const WordRes ra = word(qa, a_om, a_o0, a_op, a_i0, a_ip, a_dm, a_d0, a_x, rM, rI, rD, kc, crow, q_lo);
+        hit |= ra.hit;
+        const bool first = qa == q_lo + tid;
+        if (ADAPT && first) {
+          fq[0] = qa; fm[0] = ra.mw; fi[0] = ra.iw; fd[0] = ra.dw; fdist[0] = ra.d0; fdist[1] = ra.d1;
+        }
+        if (vb) {
+          const WordRes rb = word(qb, b_om, b_o0, b_op, b_i0, b_ip, b_dm, b_d0, b_x, rM, rI, rD, kc, crow, q_lo);
+          hit |= rb.hit;
+          if (ADAPT && first) {
+            fq[1] = qb; fm[1] = rb.mw; fi[1] = rb.iw; fd[1] = rb.dw; fdist[2] = rb.d0; fdist[3] = rb.d1;
+          }
+        }
       }
+      if (hit) shv[1] = 1;
       // absent marks for MG entries beyond each end of the three new rows
       for (int32_t t = tid; t < 2 * MGW; t += T) {
         const int32_t q = t < MGW ? q_lo - MGW + t : q_hi + 1 + (t - MGW);
@@ -327,9 +402,44 @@ __global__ __launch_bounds__(T) void k_wfa_lds(Seqs S, Outs O, Scoring P, Work W
         ring.st(rD, q, ABSENT2);
       }
       if constexpr (ADAPT) {
-        if (hi - lo + 1 >= L.ad_min) __syncthreads();  // the rows of this score, and shv, are settled
-        // (a score that reached the end cell is the last: no reduction)
-        if (hi - lo + 1 >= L.ad_min && !__builtin_amdgcn_readfirstlane(shv[1])) {
+        // one wavefront whose lanes hold every word of this score (one trip):
+        // the reduction in registers, no barrier; each lane rewrites the
+        // dropped halves of its own words.  (A score that reached the end
+        // cell is the last: no reduction.)
+        const bool fast = T == 64 && q_hi - q_lo + 1 <= 2 * T;
+        if (fast && hi - lo + 1 >= L.ad_min && !__ballot(hit)) {
+          const int32_t dmin = wave_reduce<false>(min(min(fdist[0], fdist[1]), min(fdist[2], fdist[3])));
+          if (dmin != INT32_MAX) {
+            int32_t kl = INT32_MAX, kh = INT32_MIN;
+            for (int32_t w = 0; w < 2; ++w) {
+              const int32_t k0 = 2 * fq[w] - MG + kbase;
+              for (int32_t h = 0; h < 2; ++h) {
+                const int32_t d = fdist[2 * w + h];
+                if (fq[w] >= 0 && d != INT32_MAX && d - dmin <= L.ad_max) {
+                  kl = min(kl, k0 + h);
+                  kh = max(kh, k0 + h);
+                }
+              }
+            }
+            const int32_t nlo = wave_reduce<false>(kl), nhi = wave_reduce<true>(kh);
+            for (int32_t w = 0; w < 2; ++w) {
+              if (fq[w] < 0) continue;
+              const int32_t k0 = 2 * fq[w] - MG + kbase;
+              const uint32_t mask = ((k0 < nlo || k0 > nhi) ? 0xffffu : 0u) |
+                                    ((k0 + 1 < nlo || k0 + 1 > nhi) ? 0xffff0000u : 0u);
+              if (mask) {
+                ring.st(rM, fq[w], (fm[w] & ~mask) | (ABSENT2 & mask));
+                ring.st(rI, fq[w], (fi[w] & ~mask) | (ABSENT2 & mask));
+                ring.st(rD, fq[w], (fd[w] & ~mask) | (ABSENT2 & mask));
+              }
+            }
+            ad_drop += (nlo - lo) + (hi - nhi);
+            lo = nlo;
+            hi = nhi;
+          }
+        }
+        if (!fast && hi - lo + 1 >= L.ad_min) __syncthreads();  // the rows of this score, and shv, are settled
+        if (!fast && hi - lo + 1 >= L.ad_min && !__builtin_amdgcn_readfirstlane(shv[1])) {
           // WFA-adaptive reduction of this score's range, from the extended
           // M row: d(k) = max(m - i, n - j) of its offset; the ends go while
           // absent or more than ad_max behind the best d
@@ -392,8 +502,7 @@ __global__ __launch_bounds__(T) void k_wfa_lds(Seqs S, Outs O, Scoring P, Work W
             };
             trim(lo, nlo - 1);
             trim(nhi + 1, hi);
-            if (tid == 0 && L.ad_dropped && (nlo - lo) + (hi - nhi) > 0)
-              atomicAdd(L.ad_dropped, (unsigned long long)((nlo - lo) + (hi - nhi)));
+            ad_drop += (nlo - lo) + (hi - nhi);
             lo = nlo;
             hi = nhi;
           }
@@ -503,6 +612,7 @@ __global__ __launch_bounds__(T) void k_wfa_lds(Seqs S, Outs O, Scoring P, Work W
       }
     }
   }
+  if (ADAPT && tid == 0 && L.ad_dropped && ad_drop) atomicAdd(L.ad_dropped, (unsigned long long)ad_drop);
 }
 
 }  // namespace
@@ -520,14 +630,19 @@ hipError_t launch_wfa_lds(const Seqs &S, const Outs &O, const Scoring &P, const 
   const bool g = L.gring != nullptr;
   const size_t lds = wfa_lds_bytes(L.W, L.MG, L.R, P.e, L.seq_words, g);
   if (L.ad_min > 0) {
-    // WFA-adaptive: global ring only
-    if (!g) return hipErrorInvalidValue;
+    // WFA-adaptive
+#define AIM_LAUNCH_AD(TT)                                                                              \
+  if (g)                                                                                               \
+    hipLaunchKernelGGL((k_wfa_lds<TT, true, true>), dim3(nslots), dim3(TT), lds, s, S, O, P, Wk, L);   \
+  else                                                                                                 \
+    hipLaunchKernelGGL((k_wfa_lds<TT, false, true>), dim3(nslots), dim3(TT), lds, s, S, O, P, Wk, L);
     switch (threads) {
-      case 64: hipLaunchKernelGGL((k_wfa_lds<64, true, true>), dim3(nslots), dim3(64), lds, s, S, O, P, Wk, L); break;
-      case 128: hipLaunchKernelGGL((k_wfa_lds<128, true, true>), dim3(nslots), dim3(128), lds, s, S, O, P, Wk, L); break;
-      case 256: hipLaunchKernelGGL((k_wfa_lds<256, true, true>), dim3(nslots), dim3(256), lds, s, S, O, P, Wk, L); break;
+      case 64: AIM_LAUNCH_AD(64) break;
+      case 128: AIM_LAUNCH_AD(128) break;
+      case 256: AIM_LAUNCH_AD(256) break;
       default: return hipErrorInvalidValue;
     }
+#undef AIM_LAUNCH_AD
     return hipGetLastError();
   }
 #define AIM_LAUNCH_LDS(TT)                                                                             \

@@ -243,6 +243,15 @@ WORKLOADS = {
     # WFA 4/6/2, 500k pairs, 100..10k bp log-uniform, 0.5..10 %
     "wfa_mixed": dict(seed=4, total=500_000, lmin=100, lmax=10_000, rmin=0.005, rmax=0.10,
                       alg="wfa", pen=AFFINE_462, max_score=-1, enc="2bit"),
+    # WFA-adaptive 4/6/2 (reduction after 10 diagonals, 50 bases of slack) at
+    # the read lengths and error rates of the paper's GPU comparison: 150 bp
+    # at 2 %, 1,000 bp at 5 %, 10,000 bp at 5 %
+    "wfa_adaptive_150": dict(seed=6, total=1_000_000, L=150, rate=0.02, alg="wfa_adaptive", pen=AFFINE_462,
+                             max_score=-1, enc="2bit", adaptive=(10, 50)),
+    "wfa_adaptive_1k": dict(seed=7, total=100_000, L=1000, rate=0.05, alg="wfa_adaptive", pen=AFFINE_462,
+                            max_score=-1, enc="2bit", adaptive=(10, 50)),
+    "wfa_adaptive_10k": dict(seed=8, total=10_000, L=10_000, rate=0.05, alg="wfa_adaptive", pen=AFFINE_462,
+                             max_score=-1, enc="2bit", adaptive=(10, 50)),
 }
 
 

@@ -14,6 +14,9 @@ those.  The counts are penalty-scale free: dividing x, o and e by
 their common divisor leaves the non-null wavefronts and their ranges as they
 are.
 
+For the WFA-adaptive workloads the counts are those of the adaptive oracle
+(the reduced wavefronts).
+
 Runs the oracle only (no GPU code); about 10 minutes on 8 cores:
     python tests/golden/make_wfa_work.py [workload ...]
 """
@@ -51,7 +54,8 @@ def count(name: str, threads: int) -> dict:
         b = synth.workload(name, start=start, n=min(CHUNK, total - start))
 
         def one(i):
-            st, sc, _, c = oracle.wfa_pair(b.pattern(i), b.text(i), w["pen"], w["max_score"], want_cigar=False)
+            st, sc, _, c = oracle.wfa_pair(b.pattern(i), b.text(i), w["pen"], w["max_score"], want_cigar=False,
+                                           adaptive=w.get("adaptive"))
             ext = max(-c["lo_min"], c["hi_max"] + 1)
             return st, ext, c["cells"], c["words"], c["compared"]
 
