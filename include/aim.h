@@ -331,17 +331,24 @@ aim_status aim_last_call_stats(aim_context *ctx, aim_call_stats *out);
  * fastest for (alg, length bucket of pairs->max_len); later calls with that
  * key use it.  Candidates: NW/SWG -- first band width {32, 64}, resident
  * wavefronts per CU {8, 16, 32}, length sort {off, on}, packed 16-bit cells
- * {off, on} (32 diagonals only); WFA -- length sort {off, on}, workgroup size
- * for wide pairs {128, 256}.  Each candidate runs once to warm up and `reps`
+ * {off, on} (32 diagonals only); WFA -- length sort {off, on}, one-wavefront
+ * window {64, 128, 256} diagonals, workgroup size for the widest pairs {128,
+ * 256}, then, for each window class the batch uses, its workgroup size {64,
+ * 128, 256} (pairs per workgroup: one; lanes per pair: the size) and where its
+ * ring lives (LDS or a global slot), kept per class length bucket (the
+ * class's extent bound, or max_len for the last class), so one mixed batch
+ * runs each bucket with its own configuration; WFA-adaptive -- length sort,
+ * workgroup size {64, 128}.  Each candidate runs once to warm up and `reps`
  * times timed (median).  Synchronous.  On return `out` holds the results of
- * the chosen configuration; best_params (12 int32, see aim_tune_get) and
- * best_ms may be NULL.  Paper: Data Management (the framework picks the
- * number of DPU threads from the algorithm, read length and error rate). */
+ * the chosen configuration; best_params (13 int32, see aim_tune_get) and
+ * best_ms (the fastest candidate's time) may be NULL.  Paper: Data
+ * Management (the framework picks the number of DPU threads from the
+ * algorithm, read length and error rate; WRAM or MRAM per read length). */
 aim_status aim_autotune(aim_context *ctx, const aim_batch *pairs, int32_t alg, aim_penalties pen,
                         int32_t max_score, aim_results *out, void *stream, int32_t reps,
                         int32_t *best_params, double *best_ms);
 
-/* Launch parameters for (alg, max_len), 12 int32: params[0] first band width,
+/* Launch parameters for (alg, max_len), 13 int32: params[0] first band width,
  * [1] wavefronts per CU, [2] length sort (-1 auto, 0 off, 1 on), [3] WFA ring
  * LDS KB, [4] WFA full-store LDS KB, [5] WFA long-pair workgroup size,
  * [6] packed 16-bit band cells when the value bound allows (0 off; 1 on, each
@@ -351,9 +358,17 @@ aim_status aim_autotune(aim_context *ctx, const aim_batch *pairs, int32_t alg, a
  * one-wavefront window go through LDS-window classes (1, the default) or
  * straight to the HBM-ring pass (0), [8..10] workgroup size (64, 128, 256 or
  * 512) of the three window classes (narrowest first), [11] bit c set: class
- * c + 1 keeps its recent wavefronts in a global buffer rather than LDS. */
+ * c + 1 keeps its recent wavefronts in a global buffer rather than LDS, [12]
+ * the one-wavefront window in units of 64 diagonals (0: from the batch; at
+ * most 4).  A class tune kept for a class's length bucket (aim_autotune)
+ * overrides [8..11] for that class. */
 aim_status aim_tune_get(aim_context *ctx, int32_t alg, int32_t max_len, int32_t *params);
 aim_status aim_tune_set(aim_context *ctx, int32_t alg, int32_t max_len, const int32_t *params);
+/* The kept tunes: for entry i < min(cap, *count), kind[i] 0 (batch tune) or
+ * 1 (WFA class tune), alg[i] and bucket[i] (a length bucket: the smallest b
+ * with 2^b > length).  *count is the number of entries. */
+aim_status aim_tune_entries(aim_context *ctx, int32_t cap, int32_t *kind, int32_t *alg, int32_t *bucket,
+                            int32_t *count);
 /* Tune cache as text, keyed by GPU architecture and HIP runtime version; a
  * file for another architecture or runtime is refused (AIM_ERR_NOT_FOUND). */
 aim_status aim_tune_save(aim_context *ctx, const char *path);

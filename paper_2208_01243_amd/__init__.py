@@ -105,6 +105,7 @@ SIGNATURES = {
     "aim_tune_get": ([vp, i32, i32, ctypes.POINTER(i32)], i32),
     "aim_tune_set": ([vp, i32, i32, ctypes.POINTER(i32)], i32),
     "aim_tune_save": ([vp, ctypes.c_char_p], i32),
+    "aim_tune_entries": ([vp, i32, vp, vp, vp, ctypes.POINTER(i32)], i32),
     "aim_tune_load": ([vp, ctypes.c_char_p], i32),
     "aim_graph_capture": ([vp, ctypes.POINTER(Batch), i32, Penalties, i32, ctypes.POINTER(Results), vp,
                            ctypes.POINTER(vp)], i32),
@@ -246,22 +247,32 @@ class Context:
     def autotune(self, pat_seq, pat_off, pat_len, txt_seq, txt_off, txt_len, *, enc, max_len, alg,
                  pen, max_score, score, status, cigar=None, cigar_off=None, want_cigar=True,
                  stream=None, reps=2):
-        """aim_autotune; returns (params list of 12, best ms)."""
+        """aim_autotune; returns (params list of 13, best ms)."""
         b, r, a = self._args(pat_seq, pat_off, pat_len, txt_seq, txt_off, txt_len, enc, max_len, alg,
                              score, status, cigar, cigar_off, want_cigar)
-        params = (i32 * 12)()
+        params = (i32 * 13)()
         ms = ctypes.c_double()
         _check(lib().aim_autotune(self._h, ctypes.byref(b), a, Penalties(*pen), max_score,
                                   ctypes.byref(r), _stream(stream), reps, params, ctypes.byref(ms)))
         return list(params), ms.value
 
+    def tune_entries(self):
+        """aim_tune_entries: [(kind, alg, bucket)], kind 0 batch tune, 1 WFA class tune."""
+        cnt = i32()
+        _check(lib().aim_tune_entries(self._h, 0, None, None, None, ctypes.byref(cnt)))
+        k = (i32 * max(cnt.value, 1))()
+        a = (i32 * max(cnt.value, 1))()
+        b = (i32 * max(cnt.value, 1))()
+        _check(lib().aim_tune_entries(self._h, cnt.value, k, a, b, ctypes.byref(cnt)))
+        return [(k[i], a[i], b[i]) for i in range(cnt.value)]
+
     def tune_get(self, alg, max_len):
-        params = (i32 * 12)()
+        params = (i32 * 13)()
         _check(lib().aim_tune_get(self._h, ALGORITHMS[alg] if isinstance(alg, str) else alg, max_len, params))
         return list(params)
 
     def tune_set(self, alg, max_len, params):
-        arr = (i32 * 12)(*params)
+        arr = (i32 * 13)(*params)
         _check(lib().aim_tune_set(self._h, ALGORITHMS[alg] if isinstance(alg, str) else alg, max_len, arr))
 
     def tune_save(self, path):

@@ -102,6 +102,15 @@ struct Tune {
                               // classes (1) or straight to the HBM-ring pass (0)
   int32_t wfa_cls_threads[3] = {64, 128, 128};  // workgroup size of each window class
   int32_t wfa_cls_global = 7;  // bit c: class c + 1 keeps its ring in a global buffer, not LDS
+  int32_t wfa_c16 = 0;         // one-wavefront window in units of 64 diagonals (0: from the batch)
+};
+
+// Launch parameters of one WFA window class, keyed by the class's length
+// bucket (its extent bound, or the batch's max_len for the last class), so
+// that one mixed batch runs each class with its own tuned configuration.
+struct ClassTune {
+  int32_t threads = 0;  // workgroup size (0: the batch tune's)
+  int32_t global = -1;  // ring in a global slot (1) or LDS (0); -1: the batch tune's
 };
 
 // Every scratch buffer of one call.
@@ -126,6 +135,7 @@ struct aim_context {
   int32_t cus = 256;
   PhaseTimer timer;
   std::map<std::pair<int32_t, int32_t>, Tune> tunes;  // (alg, length bucket) -> tune
+  std::map<std::pair<int32_t, int32_t>, ClassTune> class_tunes;  // (alg, class length bucket)
   const Tune *force = nullptr;  // set while the autotuner tries a candidate
   bool capturing = false;       // inside a hipGraph capture: no timing events
   // second stream (default priority) for the escalation tiers, which run
@@ -163,6 +173,7 @@ struct aim_context {
   int64_t last_n = 0;
   int32_t last_window = 0;  // diagonals of the one-wavefront WFA window (0: not run)
   int32_t last_class_window[4] = {0, 0, 0, 0};  // windows of the LDS classes (0: none)
+  int32_t last_class_bucket[4] = {-1, -1, -1, -1};  // their class-tune buckets
   // WFA-adaptive reduction parameters (aim_wfa_adaptive_params)
   int32_t ad_min = 10, ad_max = 50;
 };
@@ -429,7 +440,8 @@ aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const
   WL.walk_skip = cnt + C_WS;
   const int32_t slots = (int32_t)std::min<int64_t>(n, (int64_t)c->cus * 8);
   // one wavefront per pair with 16-bit offsets over a window of 64 C diagonals
-  const int32_t C16 = (int32_t)std::min<int64_t>(4, std::max<int64_t>(1, (pl.wcap + 63) / 64));
+  int32_t C16 = (int32_t)std::min<int64_t>(4, std::max<int64_t>(1, (pl.wcap + 63) / 64));
+  if (tu.wfa_c16 > 0) C16 = std::min(C16, tu.wfa_c16);
   const bool w16 = !plain && L <= aim::WFA16_MAX_LEN && pl.R <= 32 && pl.seq_words > 0 &&
                    aim::wfa_score16_lds(WL, P.e, C16) <= 48 * 1024;
   WL.store16 = w16;  // the full store of the fallback pass holds 16-bit offsets
@@ -457,13 +469,18 @@ aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const
     const int32_t bound[3] = {512, 1536, INT32_MAX};
     int32_t prev_half = 32 * C16;
     for (int k = 0; k < 3; ++k) {
-      const bool glob = (tu.wfa_cls_global >> k) & 1;
+      // this class's own tune, if one is kept for its length bucket
+      const int32_t cb = len_bucket_host(k < 2 ? bound[k] : L);
+      const auto ct = c->class_tunes.find({AIM_WFA_AFFINE, cb});
+      const ClassTune *ctp = ct == c->class_tunes.end() ? nullptr : &ct->second;
+      const bool glob = (ctp && ctp->global >= 0) ? ctp->global != 0 : ((tu.wfa_cls_global >> k) & 1) != 0;
       const int32_t w = glob ? full : std::min<int64_t>((int64_t)2 * std::min(bound[k], wmax / 2), wmax);
       const int32_t half = glob ? bound[k] : w / 2;
       if (std::min(half, w / 2) <= prev_half) continue;
       const size_t lds = aim::wfa_lds_bytes(w, MG, pl.R, P.e, pl.seq_words, glob);
       if (lds > lds_cap) continue;
-      const int32_t th = tu.wfa_cls_threads[k];
+      const int32_t th = (ctp && ctp->threads > 0) ? ctp->threads : tu.wfa_cls_threads[k];
+      c->last_class_bucket[cls.size()] = cb;
       const int32_t per_cu = (int32_t)std::max<size_t>(1, std::min<size_t>(lds_cap / lds, 2048 / th));
       cls.push_back({w, th, (int32_t)std::min<int64_t>(n, (int64_t)c->cus * per_cu), glob, half});
       prev_half = std::min(half, w / 2);
@@ -855,7 +872,10 @@ static aim_status align_batch(aim_context *c, const aim_batch *B, int32_t alg, a
   c->last_cnt = cnt;
   c->last_n = n;
   c->last_window = 0;
-  for (int k = 0; k < 4; ++k) c->last_class_window[k] = 0;
+  for (int k = 0; k < 4; ++k) {
+    c->last_class_window[k] = 0;
+    c->last_class_bucket[k] = -1;
+  }
   HIP_TRY(aim::launch_fill_i32(cnt, 0, C_N + 2, s));  // + the 64-bit adaptive drop count
 
   // ---- input encoding ----
@@ -1179,13 +1199,14 @@ aim_status aim_prefilter(aim_context *c, const aim_batch *B, int32_t alg, aim_pe
 
 // ---------------------------------------------------------------- autotuner
 namespace {
-const int32_t TUNE_FIELDS = 12;
+const int32_t TUNE_FIELDS = 13;
 void tune_to(const Tune &t, int32_t *v) {
   v[0] = t.band_w0; v[1] = t.band_wpc; v[2] = t.sort;
   v[3] = t.wfa_ring_kb; v[4] = t.wfa_trace_kb; v[5] = t.wfa_long_threads; v[6] = t.band16;
   v[7] = t.wfa_classes;
   for (int k = 0; k < 3; ++k) v[8 + k] = t.wfa_cls_threads[k];
   v[11] = t.wfa_cls_global;
+  v[12] = t.wfa_c16;
 }
 Tune tune_from(const int32_t *v) {
   Tune t;
@@ -1194,6 +1215,7 @@ Tune tune_from(const int32_t *v) {
   t.wfa_classes = v[7];
   for (int k = 0; k < 3; ++k) t.wfa_cls_threads[k] = v[8 + k];
   t.wfa_cls_global = v[11];
+  t.wfa_c16 = v[12];
   return t;
 }
 bool tune_valid(const Tune &t) {
@@ -1202,6 +1224,7 @@ bool tune_valid(const Tune &t) {
          t.wfa_trace_kb >= 8 && t.wfa_trace_kb <= 60 &&
          (t.wfa_long_threads == 64 || t.wfa_long_threads == 128 || t.wfa_long_threads == 256) &&
          (t.band16 >= 0 && t.band16 <= 3) && (t.wfa_classes == 0 || t.wfa_classes == 1) && t.wfa_cls_global >= 0 && t.wfa_cls_global <= 7 &&
+         t.wfa_c16 >= 0 && t.wfa_c16 <= 4 &&
          [&] {
            for (int k = 0; k < 3; ++k) {
              const int32_t th = t.wfa_cls_threads[k];
@@ -1226,16 +1249,26 @@ aim_status aim_autotune(aim_context *c, const aim_batch *B, int32_t alg, aim_pen
   if (!c || !B || !R) return fail(AIM_ERR_INVALID_ARG, "NULL context, batch or results");
   if (reps < 1 || reps > 100) return fail(AIM_ERR_INVALID_ARG, "reps must be in [1, 100]");
   std::vector<Tune> cand;
-  if (alg == AIM_WFA_AFFINE) {
-    // the LDS sizes only matter on the fallback paths; the order of the pairs
-    // and the workgroup of the wide-pair pass decide the time
+  if (alg == AIM_WFA_AFFINE || alg == AIM_WFA_ADAPTIVE) {
+    // the batch-level choices: the order of the pairs, the one-wavefront
+    // window (64, 128 or 256 diagonals) and the workgroup of the pairs no
+    // window class takes; the classes' own configurations follow
     for (int so : {0, 1})
-      for (int th : {128, 256}) {
-        Tune t;
-        t.sort = so;
-        t.wfa_long_threads = th;
-        cand.push_back(t);
-      }
+      for (int c16 : {1, 2, 4})
+        for (int th : {128, 256}) {
+          if (alg == AIM_WFA_ADAPTIVE && (c16 != 1 || th != 128)) continue;
+          Tune t;
+          t.sort = so;
+          t.wfa_c16 = c16;
+          t.wfa_long_threads = th;
+          if (alg == AIM_WFA_ADAPTIVE)
+            for (int w : {64, 128}) {
+              t.wfa_cls_threads[0] = w;
+              cand.push_back(t);
+            }
+          else
+            cand.push_back(t);
+        }
   } else {
     for (int w0 : {32, 64})
       for (int wpc : {8, 16, 32})
@@ -1279,6 +1312,55 @@ aim_status aim_autotune(aim_context *c, const aim_batch *B, int32_t alg, aim_pen
       if (med < best) { best = med; bi = k; }
     }
   }
+  // WFA: then each window class of this batch in turn, with the batch tune
+  // chosen: workgroup size {64, 128, 256} x ring in a global slot or LDS,
+  // kept per class length bucket
+  if (st == AIM_OK && alg == AIM_WFA_AFFINE) {
+    c->force = &cand[bi];
+    st = aim_align_batch(c, B, alg, pen, max_score, R, stream);
+    int32_t buckets[4];
+    for (int k = 0; k < 4; ++k) buckets[k] = c->last_class_bucket[k];
+    for (int k = 0; k < 4 && st == AIM_OK; ++k) {
+      if (buckets[k] < 0) continue;
+      const std::pair<int32_t, int32_t> key{AIM_WFA_AFFINE, buckets[k]};
+      const auto had = c->class_tunes.find(key);
+      const bool had_entry = had != c->class_tunes.end();
+      const ClassTune prev = had_entry ? had->second : ClassTune{};
+      ClassTune bestc{};
+      double bestk = 1e300;
+      for (int th : {64, 128, 256})
+        for (int gl : {1, 0}) {
+          c->class_tunes[key] = ClassTune{th, gl};
+          st = aim_align_batch(c, B, alg, pen, max_score, R, stream);
+          std::vector<double> ms;
+          for (int r = 0; r < reps && st == AIM_OK; ++r) {
+            (void)hipEventRecord(e0, s);
+            st = aim_align_batch(c, B, alg, pen, max_score, R, stream);
+            (void)hipEventRecord(e1, s);
+            float t = 0.f;
+            if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
+              st = fail(AIM_ERR_HIP, "timing the candidate failed");
+              break;
+            }
+            ms.push_back(t);
+          }
+          if (st != AIM_OK) break;
+          std::sort(ms.begin(), ms.end());
+          if (ms[ms.size() / 2] < bestk) {
+            bestk = ms[ms.size() / 2];
+            bestc = ClassTune{th, gl};
+          }
+        }
+      if (st == AIM_OK) {
+        c->class_tunes[key] = bestc;
+        best = std::min(best, bestk);
+      } else if (had_entry) {
+        c->class_tunes[key] = prev;
+      } else {
+        c->class_tunes.erase(key);
+      }
+    }
+  }
   c->force = nullptr;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -1306,19 +1388,40 @@ aim_status aim_tune_set(aim_context *c, int32_t alg, int32_t max_len, const int3
   return AIM_OK;
 }
 
+aim_status aim_tune_entries(aim_context *c, int32_t cap, int32_t *kind, int32_t *alg, int32_t *bucket,
+                            int32_t *count) {
+  g_err.clear();
+  if (!c || !count || cap < 0 || (cap > 0 && (!kind || !alg || !bucket)))
+    return fail(AIM_ERR_INVALID_ARG, "NULL argument or negative cap");
+  int32_t k = 0;
+  for (auto &kv : c->tunes) {
+    if (k < cap) { kind[k] = 0; alg[k] = kv.first.first; bucket[k] = kv.first.second; }
+    ++k;
+  }
+  for (auto &kv : c->class_tunes) {
+    if (k < cap) { kind[k] = 1; alg[k] = kv.first.first; bucket[k] = kv.first.second; }
+    ++k;
+  }
+  *count = k;
+  return AIM_OK;
+}
+
 aim_status aim_tune_save(aim_context *c, const char *path) {
   g_err.clear();
   if (!c || !path) return fail(AIM_ERR_INVALID_ARG, "NULL argument");
   std::ofstream f(path);
   if (!f) return fail(AIM_ERR_INVALID_ARG, "cannot write %s", path);
-  f << "aim-tune 2 " << c->arch << " " << tune_key() << "\n";
+  f << "aim-tune 3 " << c->arch << " " << tune_key() << "\n";
   for (auto &kv : c->tunes) {
     int32_t v[TUNE_FIELDS];
     tune_to(kv.second, v);
-    f << kv.first.first << " " << kv.first.second;
+    f << "T " << kv.first.first << " " << kv.first.second;
     for (int k = 0; k < TUNE_FIELDS; ++k) f << " " << v[k];
     f << "\n";
   }
+  for (auto &kv : c->class_tunes)
+    f << "C " << kv.first.first << " " << kv.first.second << " " << kv.second.threads << " " << kv.second.global
+      << "\n";
   return f ? AIM_OK : fail(AIM_ERR_INVALID_ARG, "write failed: %s", path);
 }
 
@@ -1329,19 +1432,34 @@ aim_status aim_tune_load(aim_context *c, const char *path) {
   if (!f) return fail(AIM_ERR_NOT_FOUND, "cannot read %s", path);
   std::string magic, ver, arch, key;
   f >> magic >> ver >> arch >> key;
-  if (magic != "aim-tune" || ver != "2") return fail(AIM_ERR_INVALID_ARG, "not a tune file: %s", path);
+  if (magic != "aim-tune" || ver != "3") return fail(AIM_ERR_INVALID_ARG, "not a tune file: %s", path);
   if (arch != c->arch || key != tune_key())
     return fail(AIM_ERR_NOT_FOUND, "tune file is for %s / runtime %s", arch.c_str(), key.c_str());
   std::map<std::pair<int32_t, int32_t>, Tune> loaded;
+  std::map<std::pair<int32_t, int32_t>, ClassTune> loaded_cls;
+  std::string kind;
   int32_t alg, bucket, v[TUNE_FIELDS];
-  while (f >> alg >> bucket) {
-    for (int k = 0; k < TUNE_FIELDS; ++k) f >> v[k];
-    if (!f) return fail(AIM_ERR_INVALID_ARG, "truncated tune file");
-    Tune t = tune_from(v);
-    if (!tune_valid(t)) return fail(AIM_ERR_INVALID_ARG, "bad tune entry in %s", path);
-    loaded[{alg, bucket}] = t;
+  while (f >> kind >> alg >> bucket) {
+    if (kind == "T") {
+      for (int k = 0; k < TUNE_FIELDS; ++k) f >> v[k];
+      if (!f) return fail(AIM_ERR_INVALID_ARG, "truncated tune file");
+      Tune t = tune_from(v);
+      if (!tune_valid(t)) return fail(AIM_ERR_INVALID_ARG, "bad tune entry in %s", path);
+      loaded[{alg, bucket}] = t;
+    } else if (kind == "C") {
+      ClassTune ct;
+      f >> ct.threads >> ct.global;
+      if (!f) return fail(AIM_ERR_INVALID_ARG, "truncated tune file");
+      if ((ct.threads != 0 && ct.threads != 64 && ct.threads != 128 && ct.threads != 256 && ct.threads != 512) ||
+          ct.global < -1 || ct.global > 1)
+        return fail(AIM_ERR_INVALID_ARG, "bad class entry in %s", path);
+      loaded_cls[{alg, bucket}] = ct;
+    } else {
+      return fail(AIM_ERR_INVALID_ARG, "bad tune line in %s", path);
+    }
   }
   for (auto &kv : loaded) c->tunes[kv.first] = kv.second;
+  for (auto &kv : loaded_cls) c->class_tunes[kv.first] = kv.second;
   return AIM_OK;
 }
 

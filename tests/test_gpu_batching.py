@@ -274,3 +274,34 @@ def test_hard_scratch_limit():
         small = synth.workload("swg150", n=5000)
         assert not compare(run(hc, small, "swg", (0, 4, 6, 2), -1), oracle.align_batch(small, "swg", (0, 4, 6, 2), -1))
         assert hc.scratch_usage()[1] <= 64 << 20
+
+
+def test_autotune_wfa_mixed_per_bucket(tmp_path):
+    # one mixed batch (100 bp - 10 kbp): the tuner keeps a batch tune and a
+    # tune per window-class length bucket; the tuned calls return exactly what
+    # the untuned ones do (a sample of which the scalar WFA oracle checks)
+    w = synth.WORKLOADS["wfa_mixed"]
+    b = synth.workload("wfa_mixed", n=20000)
+    dev, enc = to_device(b, w["enc"])
+    L = int(max(b.pat_len.max(), b.txt_len.max()))
+    with aim.Context(0) as ref:
+        want = run(ref, b, "wfa", w["pen"], -1, dev=(dev, enc))
+    outs = _outputs(b)
+    with aim.Context(0) as ctx:
+        params, ms = ctx.autotune(*dev, enc=enc, max_len=L, alg="wfa", pen=w["pen"], max_score=-1,
+                                  score=outs[0], status=outs[1], cigar=outs[2], cigar_off=outs[3], reps=1)
+        assert ms > 0 and ctx.tune_get("wfa", L) == params
+        assert not compare(_host(outs), want)
+        ents = ctx.tune_entries()
+        assert len([e for e in ents if e[0] == 1 and e[1] == aim.WFA_AFFINE]) >= 2, ents
+        assert not compare(run(ctx, b, "wfa", w["pen"], -1, dev=(dev, enc)), want)
+        path = str(tmp_path / "tune.txt")
+        ctx.tune_save(path)
+    with aim.Context(0) as ctx2:
+        ctx2.tune_load(path)
+        assert sorted(ctx2.tune_entries()) == sorted(ents)
+        assert not compare(run(ctx2, b, "wfa", w["pen"], -1, dev=(dev, enc)), want)
+    rng = np.random.default_rng(8)
+    for i in rng.choice(b.n, 30, replace=False):
+        st, sc, runs, _ = oracle.wfa_pair(b.pattern(i), b.text(i), w["pen"])
+        assert (want[1][i], want[0][i]) == (st, sc) and want[2][want[3][i]:want[3][i + 1]].tolist() == runs, i
