@@ -149,8 +149,9 @@ typedef struct {
    * for it.  Without AIM_FLAG_HARD_LIMIT it is soft: buffers that grow with
    * the batch (per-pair arrays) may pass it.  With the flag the device
    * memory the context's scratch holds never exceeds it (launch plans are
-   * then sized for 3/8 of it, the rest holding the arrays that grow with the
-   * batch): a call that would need more fails with AIM_ERR_OOM (its outputs
+   * then sized for half of it, 3/8 below 1 GiB, the rest holding the arrays
+   * that grow with the batch): a call that would need more fails with
+   * AIM_ERR_OOM (its outputs
    * are then unspecified), and a smaller batch can be retried on the same
    * context. */
   int64_t scratch_limit;
@@ -251,7 +252,8 @@ aim_status aim_scratch_usage(aim_context *ctx, int64_t *current, int64_t *peak);
  *   pairs: as for aim_align_batch; lower: device int32 [n_pairs];
  *   pass: device int8 [n_pairs] (caller-owned).
  * aim_align_batch runs the same filter in front of its aligners whenever
- * max_score >= 0 (unless AIM_FLAG_NO_PREFILTER or AIM_KERNEL_PLAIN); its
+ * max_score >= 0, for WFA and WFA-adaptive always and for NW and SWG when
+ * max_len > 256 (unless AIM_FLAG_NO_PREFILTER or AIM_KERNEL_PLAIN); its
  * results do not change, only the work spent on rejected pairs.
  * Asynchronous on `stream`, ordered with the context's other calls like
  * aim_align_batch; errors as for aim_align_batch. */
@@ -395,8 +397,8 @@ void aim_graph_destroy(aim_graph *graph);
  * workers, each with its own context, stream and buffers, so batches
  * overlap on the GPU and requests that arrive while others run join the
  * next batch.  The device-memory budget is split evenly between the
- * workers: of each share, an eighth holds input staging, an eighth output
- * staging, and the rest is the hard scratch limit of the worker's context
+ * workers: of each share, an eighth (at most 1 GiB) holds input staging, as
+ * much output staging, and the rest is the hard scratch limit of the worker's context
  * (AIM_FLAG_HARD_LIMIT), so the device memory the server holds never passes
  * the budget; a request is admitted to the device when a worker, with its
  * share, frees up.  A batch that needs more scratch than the share is split

@@ -161,11 +161,13 @@ struct aim_context {
   uint8_t *arena = nullptr;
   size_t arena_cap = 0, arena_top = 0;
   // the scratch budget the launch plans are sized for in this call
-  // (a hard limit leaves the other 5/8 to the arrays that grow with the
-  // batch, the proportion of the static array's plan budget to its size)
+  // (a hard limit leaves the rest to the arrays that grow with the batch and
+  // to the plans' own margins and minimum sizes: half, or 5/8 of a limit
+  // under 1 GiB, where those minimums weigh more)
   int64_t limit() const {
     if (arena) return aim::STATIC_PLAN_BUDGET;
-    return strict() ? opt.scratch_limit / 8 * 3 : opt.scratch_limit;
+    if (!strict()) return opt.scratch_limit;
+    return opt.scratch_limit >= ((int64_t)1 << 30) ? opt.scratch_limit / 2 : opt.scratch_limit / 8 * 3;
   }
   bool strict() const { return !arena && (opt.flags & AIM_FLAG_HARD_LIMIT); }
   // the last call's work counters (device) and size, for aim_last_call_stats
@@ -509,11 +511,11 @@ aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const
     if (P.want_cigar) {
       // origin codes for the fused walk: every score up to the threshold, at
       // most WFA16_WALK_STEPS (pairs above go to the full-store pass)
-      // and within a sixteenth of the scratch budget
+      // and within an eighth of the scratch budget
       A.bits_steps = P.max_score >= 0 ? std::min(P.max_score + 1, aim::WFA16_WALK_STEPS)
                                       : aim::WFA16_WALK_STEPS;
       A.bits_steps = (int32_t)std::max<int64_t>(
-          1, std::min<int64_t>(A.bits_steps, c->limit() / 16 / ((int64_t)nslots16 * (C16 * 32 + 32))));
+          1, std::min<int64_t>(A.bits_steps, c->limit() / 8 / ((int64_t)nslots16 * (C16 * 32 + 32))));
       // rows of C16 x 32 bytes plus 32 bytes of padding
       if ((st = ensure(c, c->sc->wbits, (size_t)nslots16 * A.bits_steps * (C16 * 32 + 32)))) return st;
       A.bits = as<uint8_t>(c->sc->wbits);
@@ -916,7 +918,11 @@ static aim_status align_batch(aim_context *c, const aim_batch *B, int32_t alg, a
   // already exceeds it are finished here and the aligners take the rest (in
   // `order`, counted on the device)
   const int32_t *order_count = nullptr;
-  if (max_score >= 0 && !plain && !(c->opt.flags & AIM_FLAG_NO_PREFILTER)) {
+  // (the band tiers reject short pairs about as fast as the filter would:
+  // for NW/SWG it runs on reads over 256 bases, where a hopeless pair would
+  // otherwise escalate to the wider tiers)
+  const bool filter_pays = alg == AIM_WFA_AFFINE || alg == AIM_WFA_ADAPTIVE || L > 256;
+  if (max_score >= 0 && !plain && filter_pays && !(c->opt.flags & AIM_FLAG_NO_PREFILTER)) {
     if ((st = ensure(c, c->sc->flist, (size_t)n * 4))) return st;
     Phase ph(c, s, "prefilter");
     HIP_TRY(aim::launch_prefilter(n, S, as<int8_t>(c->sc->flags), L, P.x, P.o, P.e, max_score, order, nullptr,

@@ -327,10 +327,11 @@ aim_status aim_server_create(int32_t device, const aim_server_options *opt, aim_
   auto *s = new aim_server();
   s->device = device;
   s->opt = o;
-  // each worker's share: an eighth each way for staging, the rest for its
+  // each worker's share: an eighth each way for staging (at most 1 GiB,
+  // far more than a batch of the merge cap needs), the rest for its
   // context's scratch (a hard limit)
   const int64_t share = o.budget_bytes / o.n_streams;
-  s->in_cap = s->out_cap = share / 8;
+  s->in_cap = s->out_cap = std::min<int64_t>(share / 8, (int64_t)1 << 30);
   s->scratch_cap = share - s->in_cap - s->out_cap;
   s->sched = new aim_serve::Scheduler(aim_serve::Limits{o.max_batch_pairs, s->in_cap, s->out_cap});
   s->wbytes.assign(o.n_streams, 0);
