@@ -103,6 +103,9 @@ __device__ __forceinline__ int32_t lev_dispatch(int32_t nw, const uint64_t *s, i
   if (nw <= 4) return lev_bits<4>(s, sl, t, tl, tmax, on);
   if constexpr (NWMAX == 8) {
     return lev_bits<8>(s, sl, t, tl, tmax, on);
+  } else if constexpr (NWMAX == 16) {
+    if (nw <= 8) return lev_bits<8>(s, sl, t, tl, tmax, on);
+    return lev_bits<16>(s, sl, t, tl, tmax, on);
   } else {
     if (nw <= 8) return lev_bits<8>(s, sl, t, tl, tmax, on);
     if (nw <= 16) return lev_bits<16>(s, sl, t, tl, tmax, on);
@@ -187,9 +190,11 @@ hipError_t launch_prefilter(int64_t n, const Seqs &S, const int8_t *flags, int32
                             const Outs *O, int32_t *list, int32_t *count, int32_t *rejected, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   // the widest word count the batch can need picks the register budget: 8
-  // words (256 bases) keeps occupancy high for short reads
+  // words (256 bases) or 16 keep occupancy high for short reads
   if (max_len <= 256)
     return launch_nw<8>(n, S, flags, x, o, e, max_score, idx, lower, pass, O, list, count, rejected, s);
+  if (max_len <= 512)
+    return launch_nw<16>(n, S, flags, x, o, e, max_score, idx, lower, pass, O, list, count, rejected, s);
   return launch_nw<32>(n, S, flags, x, o, e, max_score, idx, lower, pass, O, list, count, rejected, s);
 }
 
