@@ -11,6 +11,9 @@ imports it.
 * ``wfa_scalar.c`` -- a scalar wavefront algorithm, a second route to the
   same optimum used to pin the first one (and to count wavefront work), and
   its adaptive (heuristic) variant, WFA-adaptive.
+* ``genasm.c`` -- GenASM: windowed bitap distance calculation with a
+  traceback over its intermediate bit-vectors (unit edits, threshold k); see
+  that file's header for the reading it writes out.
 * ``rescore.py`` -- replays a CIGAR over the two sequences and recomputes its
   cost from the gap model, without any DP.
 """
@@ -27,7 +30,7 @@ from .rescore import rescore, cigar_string, parse_runs  # noqa: F401
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
-SOURCES = [os.path.join(HERE, f) for f in ("aim_oracle.c", "wfa_scalar.c")]
+SOURCES = [os.path.join(HERE, f) for f in ("aim_oracle.c", "wfa_scalar.c", "genasm.c")]
 
 ALG = {"nw": 0, "swg": 1, "wfa": 2}
 ALIGNED, REJECTED = 0, 1
@@ -74,6 +77,12 @@ def bind(path: str):
     L.oracle_wfa_adaptive.argtypes = [p, i32, p, i32, i32, i32, i32, i32, i32, i32, i32, p, p, p, i32, p,
                                       ctypes.POINTER(WfaStats)]
     L.oracle_wfa_adaptive.restype = ctypes.c_int
+    L.oracle_genasm.argtypes = [p, i32, p, i32, i32, i32, i32, i32, p, p, p, i32, p]
+    L.oracle_genasm.restype = ctypes.c_int
+    L.oracle_genasm_dc.argtypes = [p, i32, p, i32, i32, i32, p]
+    L.oracle_genasm_dc.restype = ctypes.c_int
+    L.oracle_genasm_batch.argtypes = [i64, p, p, p, p, i32, i32, i32, i32, i32, p, p, p, p, p]
+    L.oracle_genasm_batch.restype = ctypes.c_int
     return L
 
 
@@ -212,6 +221,77 @@ def align_batch(batch, alg: str, pen, max_score: int = -1, want_cigar: bool = Tr
                                   _ptr(score), _ptr(status), _ptr(runs), _ptr(slot_arr), _ptr(nr))
     if rc != 0 or (status < 0).any():
         raise RuntimeError("oracle batch failure")
+    off = np.zeros(n + 1, np.int64)
+    off[1:] = np.cumsum(nr)
+    if want_cigar and n:
+        idx = np.repeat(slot[:-1], nr) + (np.arange(int(off[-1])) - np.repeat(off[:-1], nr))
+        cigar = runs[idx]
+    else:
+        cigar = np.zeros(0, np.uint32)
+    return score, status, cigar, off
+
+
+GENASM_WINDOW, GENASM_OVERLAP = 64, 24  # window bases and overlap of the GPU library
+
+
+def genasm_pair(P, T, k: int = -1, window: int = GENASM_WINDOW, overlap: int = GENASM_OVERLAP,
+                want_cigar: bool = True, handle=None):
+    """GenASM of one pair (``genasm.c``): unit edits, at most ``k`` of them
+    (-1: no threshold).  Returns (status, score, runs)."""
+    P, T = _codes(P), _codes(T)
+    m, n = len(P), len(T)
+    cap = m + n + 1
+    runs = np.zeros(cap, np.uint32)
+    score = np.zeros(1, np.int32)
+    status = np.zeros(1, np.int8)
+    nr = np.zeros(1, np.int32)
+    Pb = P if m else np.zeros(1, np.uint8)
+    Tb = T if n else np.zeros(1, np.uint8)
+    rc = (handle or lib()).oracle_genasm(_ptr(Pb), m, _ptr(Tb), n, int(k), int(window), int(overlap),
+                                         int(want_cigar), _ptr(score), _ptr(status), _ptr(runs), cap, _ptr(nr))
+    if rc != 0:
+        raise RuntimeError("genasm oracle failure %d" % rc)
+    return int(status[0]), int(score[0]), [int(r) for r in runs[:nr[0]]]
+
+
+def genasm_dc(p, t, anchored: bool, levels: int, handle=None):
+    """Status bits of one GenASM window: array [b + 1, levels + 1, a + 1]
+    with [j, d, i] = [D(i, j) <= d] (``genasm.c``'s distance calculation)."""
+    p, t = _codes(p), _codes(t)
+    a, b = len(p), len(t)
+    out = np.zeros((b + 1) * (levels + 1) * (a + 1), np.uint8)
+    pb = p if a else np.zeros(1, np.uint8)
+    tb = t if b else np.zeros(1, np.uint8)
+    rc = (handle or lib()).oracle_genasm_dc(_ptr(pb), a, _ptr(tb), b, int(anchored), int(levels), _ptr(out))
+    if rc != 0:
+        raise RuntimeError("genasm dc failure %d" % rc)
+    return out.reshape(b + 1, levels + 1, a + 1)
+
+
+def genasm_batch(batch, k: int = -1, want_cigar: bool = True, window: int = GENASM_WINDOW,
+                 overlap: int = GENASM_OVERLAP, nthreads: int | None = None, handle=None):
+    """``genasm_pair`` over every pair of a ``synth.PairBatch`` on host
+    threads.  Returns (score int32[n], status int8[n], cigar uint32[...],
+    cigar_off int64[n+1]) like ``align_batch``."""
+    n = batch.n
+    if nthreads is None:
+        nthreads = os.cpu_count() or 1
+    plen, tlen = batch.pat_len.astype(np.int64), batch.txt_len.astype(np.int64)
+    slot = np.zeros(n + 1, np.int64)
+    if want_cigar:
+        slot[1:] = np.cumsum(plen + tlen + 1)
+    runs = np.zeros(max(int(slot[-1]), 1), np.uint32)
+    score = np.zeros(n, np.int32)
+    status = np.zeros(n, np.int8)
+    nr = np.zeros(n, np.int32)
+    pat = batch.pat if len(batch.pat) else np.zeros(1, np.uint8)
+    txt = batch.txt if len(batch.txt) else np.zeros(1, np.uint8)
+    rc = (handle or lib()).oracle_genasm_batch(
+        n, _ptr(pat), _ptr(np.ascontiguousarray(batch.pat_off)), _ptr(txt),
+        _ptr(np.ascontiguousarray(batch.txt_off)), int(k), int(window), int(overlap), int(want_cigar),
+        nthreads, _ptr(score), _ptr(status), _ptr(runs), _ptr(slot), _ptr(nr))
+    if rc != 0 or (status < 0).any():
+        raise RuntimeError("genasm oracle batch failure %d" % rc)
     off = np.zeros(n + 1, np.int64)
     off[1:] = np.cumsum(nr)
     if want_cigar and n:

@@ -273,12 +273,13 @@ def test_pins_catch_planted_mistakes(tmp_path, idx):
     fname, old, new = MUTANTS[idx]
     src = open(os.path.join(oracle.HERE, fname)).read()
     assert src.count(old) == 1, "mutation anchor not found"
-    for f in ("aim_oracle.c", "wfa_scalar.c"):
+    for f in ("aim_oracle.c", "wfa_scalar.c", "genasm.c"):
         shutil.copy(os.path.join(oracle.HERE, f), tmp_path / f)
     (tmp_path / fname).write_text(src.replace(old, new))
     so = str(tmp_path / "libmut.so")
     subprocess.run(["gcc", "-O1", "-fPIC", "-shared", "-pthread", "-o", so,
-                    str(tmp_path / "aim_oracle.c"), str(tmp_path / "wfa_scalar.c")], check=True)
+                    str(tmp_path / "aim_oracle.c"), str(tmp_path / "wfa_scalar.c"),
+                    str(tmp_path / "genasm.c")], check=True)
     h = oracle.bind(so)
     caught = False
     seqs = list(_all_seqs(range(2), 4))

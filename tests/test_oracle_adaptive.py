@@ -136,9 +136,10 @@ def test_planted_mistakes_fail(tmp_path, name):
     bad = src.replace(a, b)
     (tmp_path / "wfa_scalar.c").write_text(bad)
     so = str(tmp_path / "libmut.so")
-    subprocess.run(["gcc", "-O1", "-std=c11", "-fPIC", "-shared", "-o", so,
+    subprocess.run(["gcc", "-O1", "-std=c11", "-fPIC", "-shared", "-pthread", "-o", so,
                     os.path.join(os.path.dirname(oracle.__file__), "aim_oracle.c"),
-                    str(tmp_path / "wfa_scalar.c")], check=True)
+                    str(tmp_path / "wfa_scalar.c"),
+                    os.path.join(os.path.dirname(oracle.__file__), "genasm.c")], check=True)
     h = oracle.bind(so)
     caught = False
     try:
