@@ -54,7 +54,13 @@ typedef int32_t aim_status;
 #define AIM_ERR_BUSY (-5)        /* serving: queue full / request still running */
 #define AIM_ERR_NOT_FOUND (-6)   /* serving: unknown request id */
 
-typedef enum { AIM_NW_LINEAR = 0, AIM_SWG_AFFINE = 1, AIM_WFA_AFFINE = 2, AIM_WFA_ADAPTIVE = 3 } aim_algorithm;
+typedef enum {
+  AIM_NW_LINEAR = 0,
+  AIM_SWG_AFFINE = 1,
+  AIM_WFA_AFFINE = 2,
+  AIM_WFA_ADAPTIVE = 3,
+  AIM_GENASM = 4
+} aim_algorithm;
 
 /* Sequence encodings.  ASCII: bytes 'A','C','G','T' (upper case only).
  * CODE: bytes 0..3 for A, C, G, T.  2BIT: 32 bases per uint64 word, base t of
@@ -183,11 +189,31 @@ void aim_destroy(aim_context *ctx);
  *        at most the reported score, and is the same as exact WFA whenever
  *        no diagonal is dropped; max_len <= 16,000, else
  *        AIM_ERR_UNSUPPORTED; a pair whose score passes 16,000 times the
- *        penalties' common divisor is AIM_PAIR_INVALID);
- *   pen: scoring parameters (see aim_penalties);
- *   max_score: threshold in penalty units; a pair whose optimum exceeds it is
+ *        penalties' common divisor is AIM_PAIR_INVALID),
+ *        AIM_GENASM (GenASM subsection: bitap with a traceback under a bound
+ *        k on the edits; the library's reading, unit edits in windows of 64
+ *        bases overlapping by 24, is spelled out below);
+ *   pen: scoring parameters (see aim_penalties; validated but unused by
+ *        AIM_GENASM, which counts edits);
+ *   max_score: threshold in penalty units (AIM_GENASM: k, in edits); a pair
+ *        whose optimum (AIM_GENASM, WFA-adaptive: whose result) exceeds it is
  *        AIM_PAIR_REJECTED; < 0 means no threshold.  Results of accepted pairs
  *        do not depend on it.
+ * AIM_GENASM aligns a pair from its end towards its start in windows of at
+ * most 64 pattern and 64 text bases taken from the end of what is still to
+ * align.  The last window (64 bases or fewer of each left) must reach the
+ * start of both sequences; the others may begin anywhere on their first row
+ * or column.  In each window the bitap distance calculation finds the fewest
+ * edits d (status bit i of text position j at level d says whether the
+ * window's first i pattern and j text bases align within d edits), and a
+ * traceback from the window's end spends that budget taking, at each cell,
+ * the first available of: the previous op again if it was 'I' or 'D'; '=';
+ * 'X'; 'I'; 'D'.  A window other than the last commits ops until 40 bases of
+ * either sequence are consumed or its first row or column is reached; when
+ * either sequence runs out the rest of the other is one gap.  The score is
+ * the number of edits (at least the Levenshtein distance; equal to it when
+ * both sequences fit one window), and a window that needs more edits than k
+ * still allows, or a total above k, rejects the pair.
  * Asynchronous on `stream`.  Errors: AIM_ERR_INVALID_ARG (NULL pointers,
  * n_pairs < 0, max_len out of range, cigar_cap < 0 with want_cigar),
  * AIM_ERR_UNSUPPORTED (penalties), AIM_ERR_OOM, AIM_ERR_HIP. */
@@ -248,12 +274,15 @@ aim_status aim_scratch_usage(aim_context *ctx, int64_t *current, int64_t *peak);
  *   pass[p]  = 1 if max_score < 0 or lower[p] <= max_score, else 0: a pair
  *         with pass 0 is certain to be AIM_PAIR_REJECTED by aim_align_batch
  *         with the same arguments.
+ * For AIM_GENASM the bound is taken with unit edits (mismatch and
+ * gap_extend 1, gap_open 0) against max_score = k: GenASM's edits are at
+ * least the Levenshtein distance.
  * An invalid pair (see aim_batch) gets lower -1 and pass 0.
  *   pairs: as for aim_align_batch; lower: device int32 [n_pairs];
  *   pass: device int8 [n_pairs] (caller-owned).
  * aim_align_batch runs the same filter in front of its aligners whenever
  * max_score >= 0, for WFA and WFA-adaptive always and for NW and SWG when
- * max_len > 256 (unless AIM_FLAG_NO_PREFILTER or AIM_KERNEL_PLAIN); its
+ * max_len > 256 (never for GenASM) (unless AIM_FLAG_NO_PREFILTER or AIM_KERNEL_PLAIN); its
  * results do not change, only the work spent on rejected pairs.
  * Asynchronous on `stream`, ordered with the context's other calls like
  * aim_align_batch; errors as for aim_align_batch. */
@@ -351,7 +380,7 @@ aim_status aim_autotune(aim_context *ctx, const aim_batch *pairs, int32_t alg, a
                         int32_t *best_params, double *best_ms);
 
 /* Launch parameters for (alg, max_len), 13 int32: params[0] first band width,
- * [1] wavefronts per CU, [2] length sort (-1 auto, 0 off, 1 on), [3] WFA ring
+ * [1] wavefronts per CU (first band tier; GenASM), [2] length sort (-1 auto, 0 off, 1 on), [3] WFA ring
  * LDS KB, [4] WFA full-store LDS KB, [5] WFA long-pair workgroup size,
  * [6] packed 16-bit band cells when the value bound allows (0 off; 1 on, each
  * wavefront walking its own pairs' tracebacks; 2 on, the tracebacks walked by

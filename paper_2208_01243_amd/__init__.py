@@ -14,8 +14,9 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libaim.so")
 
-NW_LINEAR, SWG_AFFINE, WFA_AFFINE, WFA_ADAPTIVE = 0, 1, 2, 3
-ALGORITHMS = {"nw": NW_LINEAR, "swg": SWG_AFFINE, "wfa": WFA_AFFINE, "wfa_adaptive": WFA_ADAPTIVE}
+NW_LINEAR, SWG_AFFINE, WFA_AFFINE, WFA_ADAPTIVE, GENASM = 0, 1, 2, 3, 4
+ALGORITHMS = {"nw": NW_LINEAR, "swg": SWG_AFFINE, "wfa": WFA_AFFINE, "wfa_adaptive": WFA_ADAPTIVE,
+              "genasm": GENASM}
 ENC_ASCII, ENC_CODE, ENC_2BIT = 0, 1, 2
 KERNEL_AUTO, KERNEL_PLAIN = 0, 1
 FLAG_TIMING = 1

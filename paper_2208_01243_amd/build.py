@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libaim.so")
-SOURCES = ["capi.cpp", "util.hip", "dp_band.hip", "dp_band16.hip", "dp_diag.hip", "dp_full.hip", "wfa.hip", "wfa_lds.hip", "filter.hip", "serve.cpp", "static_scratch.hip"]
+SOURCES = ["capi.cpp", "util.hip", "dp_band.hip", "dp_band16.hip", "dp_diag.hip", "dp_full.hip", "wfa.hip", "wfa_lds.hip", "filter.hip", "genasm.hip", "serve.cpp", "static_scratch.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -324,6 +324,16 @@ hipError_t launch_prefilter(int64_t n, const Seqs &S, const int8_t *flags, int32
                             int32_t e, int32_t max_score, const int32_t *idx, int32_t *lower, int8_t *pass,
                             const Outs *O, int32_t *list, int32_t *count, int32_t *rejected, hipStream_t s);
 
+// GenASM (windowed bitap with traceback, unit edits, threshold max_score),
+// one pair per lane, 64 pairs per wavefront from Wk's counter.  Each
+// wavefront keeps `levels` edit levels of 64 x 64 status words in its slot of
+// `store`: genasm_block_words(levels) words per 256-thread block, nblocks
+// blocks.  levels = genasm_levels(max_score).
+int32_t genasm_levels(int32_t max_score);
+int64_t genasm_block_words(int32_t levels);
+hipError_t launch_genasm(const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk, uint64_t *store,
+                         int32_t levels, int32_t nblocks, hipStream_t s);
+
 // ---- allocation-free entry point ------------------------------------------
 // Size of the static device array (one per GPU) that aim_align_batch_static
 // carves its scratch from, and the scratch budget its launch plans are sized

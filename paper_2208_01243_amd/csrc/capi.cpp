@@ -118,7 +118,7 @@ struct Scratch {
   Buf order, hist;
   Buf flags, pflag, tflag, pat2, txt2, pat2off, txt2off, nruns, slot, tb32, tb64, full, list2,
       list3, counters, scan_tmp, spill, total, wring, warena1, warena2, warena3, wneed, wlists, pool, pooloff,
-      wbits, wwalk, wlds, wgring, flist;
+      wbits, wwalk, wlds, wgring, flist, genasm;
 };
 
 struct aim_graph {
@@ -278,7 +278,7 @@ constexpr int32_t WFA_MAX_STEP = 1024;
 constexpr int32_t WFA_ADAPTIVE_MAX_LEN = 16000;
 
 aim_status check_pen(int32_t alg, const aim_penalties &pen) {
-  if (alg < AIM_NW_LINEAR || alg > AIM_WFA_ADAPTIVE) return fail(AIM_ERR_INVALID_ARG, "unknown algorithm %d", alg);
+  if (alg < AIM_NW_LINEAR || alg > AIM_GENASM) return fail(AIM_ERR_INVALID_ARG, "unknown algorithm %d", alg);
   if (pen.match != 0) return fail(AIM_ERR_UNSUPPORTED, "match cost must be 0 (got %d)", pen.match);
   if (pen.mismatch <= 0 || pen.gap_extend <= 0 || pen.gap_open < 0)
     return fail(AIM_ERR_INVALID_ARG, "penalties need mismatch > 0, gap_extend > 0, gap_open >= 0");
@@ -411,6 +411,24 @@ aim_status run_wfa_adaptive(aim_context *c, const aim::Seqs &S, const aim::Outs 
   c->last_class_window[0] = D.W;
   Phase ph(c, s, Wk.direct ? "wfa_adaptive_rerun" : "wfa_adaptive");
   HIP_TRY(aim::launch_wfa_lds(S, O, P, Wk, D, threads, nslots, s));
+  return AIM_OK;
+}
+
+// GenASM: one launch over the listed pairs, each wavefront with a slot of
+// every edit level a window can need (k + 1, at most 65, in whole sweeps).  The tune's
+// wavefronts per CU (in 256-thread blocks), fewer when the slots would pass a
+// quarter of the budget.
+aim_status run_genasm(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const aim::Scoring &P, int64_t n,
+                      const aim::Work &Wk, const Tune &tu, hipStream_t s) {
+  const int32_t levels = aim::genasm_levels(P.max_score);
+  const int64_t block_bytes = aim::genasm_block_words(levels) * 8;
+  const int64_t per_cu = std::max<int64_t>(1, tu.band_wpc / 4);
+  int64_t blocks = std::min<int64_t>((n + 255) / 256, (int64_t)c->cus * per_cu);
+  blocks = std::max<int64_t>(1, std::min<int64_t>(blocks, c->limit() / 4 / block_bytes));
+  aim_status st = ensure(c, c->sc->genasm, (size_t)(blocks * block_bytes));
+  if (st) return st;
+  Phase ph(c, s, Wk.direct ? "genasm_rerun" : "genasm");
+  HIP_TRY(aim::launch_genasm(S, O, P, Wk, as<uint64_t>(c->sc->genasm), levels, (int32_t)blocks, s));
   return AIM_OK;
 }
 
@@ -741,7 +759,8 @@ void aim_destroy(aim_context *c) {
   Buf *all[] = {&c->own.order, &c->own.hist, &c->own.flags, &c->own.pflag, &c->own.tflag, &c->own.pat2, &c->own.txt2, &c->own.pat2off, &c->own.txt2off,
                 &c->own.nruns, &c->own.slot, &c->own.tb32, &c->own.tb64, &c->own.full, &c->own.list2, &c->own.list3,
                 &c->own.counters, &c->own.scan_tmp, &c->own.spill, &c->own.total, &c->own.wring, &c->own.warena1,
-                &c->own.warena2, &c->own.warena3, &c->own.wneed, &c->own.wlists, &c->own.pool, &c->own.pooloff, &c->own.wbits, &c->own.wwalk, &c->own.wlds, &c->own.wgring, &c->own.flist};
+                &c->own.warena2, &c->own.warena3, &c->own.wneed, &c->own.wlists, &c->own.pool, &c->own.pooloff, &c->own.wbits, &c->own.wwalk, &c->own.wlds, &c->own.wgring, &c->own.flist,
+                &c->own.genasm};
   for (Buf *b : all)
     if (b->p) (void)(b->pooled ? hipFreeAsync(b->p, nullptr) : hipFree(b->p));
   (void)hipDeviceSynchronize();
@@ -864,7 +883,7 @@ static aim_status align_batch(aim_context *c, const aim_batch *B, int32_t alg, a
   // alignment has at most S / min(x, o + e) non-match runs, so at most twice
   // that plus one runs in all; pairs with more are re-run in place
   int64_t run_bound = 2 * (int64_t)L + 1;
-  const int32_t cmin = std::min(pen.mismatch, (alg == AIM_NW_LINEAR ? 0 : pen.gap_open) + pen.gap_extend);
+  const int32_t cmin = alg == AIM_GENASM ? 1 : std::min(pen.mismatch, (alg == AIM_NW_LINEAR ? 0 : pen.gap_open) + pen.gap_extend);
   if (max_score >= 0) run_bound = std::min<int64_t>(run_bound, 2 * (int64_t)(max_score / cmin) + 1);
   // a multiple of 4 words, so the compaction reads slots with 16-byte loads
   const int32_t slot_cap =
@@ -921,7 +940,8 @@ static aim_status align_batch(aim_context *c, const aim_batch *B, int32_t alg, a
   // (the band tiers reject short pairs about as fast as the filter would:
   // for NW/SWG it runs on reads over 256 bases, where a hopeless pair would
   // otherwise escalate to the wider tiers)
-  const bool filter_pays = alg == AIM_WFA_AFFINE || alg == AIM_WFA_ADAPTIVE || L > 256;
+  // (GenASM rejects a hopeless pair in its first window)
+  const bool filter_pays = alg != AIM_GENASM && (alg == AIM_WFA_AFFINE || alg == AIM_WFA_ADAPTIVE || L > 256);
   if (max_score >= 0 && !plain && filter_pays && !(c->opt.flags & AIM_FLAG_NO_PREFILTER)) {
     if ((st = ensure(c, c->sc->flist, (size_t)n * 4))) return st;
     Phase ph(c, s, "prefilter");
@@ -943,7 +963,10 @@ static aim_status align_batch(aim_context *c, const aim_batch *B, int32_t alg, a
     return AIM_OK;
   };
 
-  if (alg == AIM_WFA_ADAPTIVE) {
+  if (alg == AIM_GENASM) {
+    aim::Work WG{order, order_count, n, cnt + C_W1, nullptr, nullptr, 0};
+    if ((st = run_genasm(c, S, O, P, n, WG, tu, s))) return st;
+  } else if (alg == AIM_WFA_ADAPTIVE) {
     aim::Work WA{order, order_count, n, cnt + C_W1, nullptr, nullptr, 0};
     if ((st = run_wfa_adaptive(c, S, O, P, n, L, cnt, WA, tu, s))) return st;
   } else if (alg == AIM_WFA_AFFINE) {
@@ -1056,7 +1079,9 @@ static aim_status align_batch(aim_context *c, const aim_batch *B, int32_t alg, a
   }
   // pairs whose runs exceeded the slot: recompute and write in place
   aim::Work WS{as<int32_t>(c->sc->spill), cnt + C_SPILL, n, cnt + C_SPILL_W, nullptr, nullptr, 1};
-  if (alg == AIM_WFA_ADAPTIVE) {
+  if (alg == AIM_GENASM) {
+    if ((st = run_genasm(c, S, O, P, n, WS, tu, s))) return st;
+  } else if (alg == AIM_WFA_ADAPTIVE) {
     if ((st = run_wfa_adaptive(c, S, O, P, n, L, cnt, WS, tu, s))) return st;
   } else if (alg == AIM_WFA_AFFINE) {
     const aim::Scoring PW = wfa_scoring(P);
@@ -1189,8 +1214,11 @@ aim_status aim_prefilter(aim_context *c, const aim_batch *B, int32_t alg, aim_pe
   aim::Seqs S;
   st = prep_inputs(c, B, s, S);
   if (!st) {
-    const hipError_t e = aim::launch_prefilter(n, S, as<int8_t>(c->sc->flags), B->max_len, pen.mismatch,
-                                               alg == AIM_NW_LINEAR ? 0 : pen.gap_open, pen.gap_extend, max_score,
+    // GenASM counts edits: its result is at least the unit-cost bound
+    const bool unit = alg == AIM_GENASM;
+    const hipError_t e = aim::launch_prefilter(n, S, as<int8_t>(c->sc->flags), B->max_len, unit ? 1 : pen.mismatch,
+                                               (alg == AIM_NW_LINEAR || unit) ? 0 : pen.gap_open,
+                                               unit ? 1 : pen.gap_extend, max_score,
                                                nullptr, lower, pass, nullptr, nullptr, nullptr, nullptr, s);
     if (e != hipSuccess) st = fail(AIM_ERR_HIP, "prefilter launch: %s", hipGetErrorString(e));
   }
@@ -1275,6 +1303,15 @@ aim_status aim_autotune(aim_context *c, const aim_batch *B, int32_t alg, aim_pen
           else
             cand.push_back(t);
         }
+  } else if (alg == AIM_GENASM) {
+    // wavefronts per CU (the slots scale with them) and the order
+    for (int wpc : {4, 8, 12, 16})
+      for (int so : {0, 1}) {
+        Tune t;
+        t.band_wpc = wpc;
+        t.sort = so;
+        cand.push_back(t);
+      }
   } else {
     for (int w0 : {32, 64})
       for (int wpc : {8, 16, 32})

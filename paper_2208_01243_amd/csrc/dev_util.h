@@ -22,6 +22,17 @@ __device__ __forceinline__ uint64_t window32(const uint64_t *s, int64_t nw, int6
   return r ? ((w0 >> (2 * r)) | (w1 << (64 - 2 * r))) : w0;
 }
 
+// even bits of w gathered into 32 bits (bit 2i -> bit i)
+__device__ __forceinline__ uint32_t even_bits(uint64_t w) {
+  w &= K55;
+  w = (w | (w >> 1)) & 0x3333333333333333ull;
+  w = (w | (w >> 2)) & 0x0F0F0F0F0F0F0F0Full;
+  w = (w | (w >> 4)) & 0x00FF00FF00FF00FFull;
+  w = (w | (w >> 8)) & 0x0000FFFF0000FFFFull;
+  w = (w | (w >> 16)) & 0x00000000FFFFFFFFull;
+  return (uint32_t)w;
+}
+
 __device__ __forceinline__ int wave_max(int v) {
 #pragma unroll
   for (int s = 32; s > 0; s >>= 1) v = max(v, __shfl_xor(v, s));

@@ -28,18 +28,8 @@
 namespace aim {
 namespace {
 
+using dev::even_bits;
 using dev::wave_max;
-
-// even bits of w gathered into 32 bits (bit 2i -> bit i)
-__device__ __forceinline__ uint32_t even_bits(uint64_t w) {
-  w &= 0x5555555555555555ull;
-  w = (w | (w >> 1)) & 0x3333333333333333ull;
-  w = (w | (w >> 2)) & 0x0F0F0F0F0F0F0F0Full;
-  w = (w | (w >> 4)) & 0x00FF00FF00FF00FFull;
-  w = (w | (w >> 8)) & 0x0000FFFF0000FFFFull;
-  w = (w | (w >> 16)) & 0x00000000FFFFFFFFull;
-  return (uint32_t)w;
-}
 
 // Levenshtein distance of the short side s (sl bases, sl <= 32 * NW) against
 // the long side t (tl bases).  All lanes of the wavefront call it; `tmax` is

@@ -1,0 +1,287 @@
+// GenASM: windowed bitap distance calculation with a traceback, one pair
+// per lane.
+//
+// Paper, System and Methods, "GenASM": bitap extended with a traceback, a
+// bound k on the edits, and per thread a bit-mask of the pattern per
+// character, two status bit-vectors and four intermediate bit-vectors (match,
+// substitution, deletion, insertion).  The library's reading (unit edits,
+// windows of 64 bases with an overlap of 24, the traceback's order, the
+// threshold) is the following:
+//
+// The pair is aligned from its end towards its start in windows of at most
+// 64 pattern and 64 text bases, taken from the end of the bases still to
+// align (me pattern, ne text bases).  The final window (me, ne <= 64) starts
+// at the start of both sequences; any other may start anywhere on its first
+// row or column.  With D(i, j) the fewest edits aligning the window's first
+// i pattern and j text bases, the status vector of text position j at level
+// d holds bit i - 1 = [D(i, j) <= d] for i = 1..a; the start row D(0, j) is
+// implicit.  Level d at position j follows from level d at j - 1 and level
+// d - 1 at j - 1 and j:
+//   match        = ((R_d[j-1] << 1) | [D(0, j-1) <= d]) & PM[t_j]
+//   substitution =  (R_{d-1}[j-1] << 1) | [D(0, j-1) <= d-1]
+//   insertion    =  (R_{d-1}[j] << 1)   | [D(0, j) <= d-1]
+//   deletion     =   R_{d-1}[j-1]
+// The window's distance is the least d whose vector at j = b has bit a - 1
+// set, searched up to max(a, b) (and the edits k still allows).  The
+// traceback walks from (a, b) back with that budget and takes the first of:
+// the previous op again if it was a gap ('I' / 'D') and still within budget;
+// '='; 'X'; 'I'; 'D'.  A window other than the final commits ops until 40
+// bases of either sequence are consumed or its first row or column is
+// reached.  When either sequence runs out, the rest of the other is one gap.
+// The score is the number of edits; more than k rejects the pair.
+//
+// MI355X mapping.  A lane owns a pair: the pattern masks (4 x 64 bits) live
+// in registers.  A sweep over the window's text builds LB consecutive levels
+// at once, each level's vector at j - 1 in a register, reading only the
+// level below the block (stored by the previous sweep) once per text
+// position; sweeps stop at the first block holding the window's distance,
+// so a window costs about (distance + 1) x 64 level steps, rounded up to LB.
+// Every level's vectors are stored for the traceback in the wavefront's
+// slot, entry (d, j) of lane l at word (d * 64 + j - 1) * 64 + l, so a
+// wavefront's loads and stores at one text position are one contiguous
+// 512-byte group.  The traceback reads the stored vectors it needs (usually
+// one per '=' step).  Work comes 64 pairs at a time from an atomic counter.
+#include "aim_internal.h"
+#include "dev_util.h"
+
+namespace aim {
+namespace {
+
+constexpr int32_t GW = 64;       // window bases
+constexpr int32_t GC = GW - 24;  // bases a window other than the final one commits
+constexpr int32_t LB = 4;        // edit levels built per sweep over a window's text
+constexpr uint32_t OP_NONE = 4;
+
+__device__ __forceinline__ uint64_t low_bits(int32_t q) {
+  return q >= 64 ? ~0ull : (q <= 0 ? 0ull : ((1ull << q) - 1ull));
+}
+
+// Masks of the a pattern bases from s0: bit q of pm[c] = [base s0 + q == c].
+__device__ __forceinline__ void pattern_masks(const uint64_t *s, int64_t nw, int64_t s0, int32_t a,
+                                              uint64_t pm[4]) {
+  const uint64_t lo = dev::window32(s, nw, s0), hi = dev::window32(s, nw, s0 + 32);
+  const uint64_t am = low_bits(a);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const uint64_t cc = (uint64_t)c * dev::K55;
+    const uint64_t xl = lo ^ cc, xh = hi ^ cc;
+    const uint64_t zl = ~(xl | (xl >> 1)) & dev::K55, zh = ~(xh | (xh >> 1)) & dev::K55;
+    pm[c] = (((uint64_t)dev::even_bits(zh) << 32) | dev::even_bits(zl)) & am;
+  }
+}
+
+// text base j (1-based) of a window whose bases are lo (1..32), hi (33..64)
+__device__ __forceinline__ uint32_t base_at(uint64_t lo, uint64_t hi, int32_t j) {
+  return (uint32_t)(((j <= 32) ? (lo >> (2 * (j - 1))) : (hi >> (2 * (j - 33)))) & 3u);
+}
+
+__device__ __forceinline__ uint64_t pick(const uint64_t pm[4], uint32_t c) {
+  const uint64_t a = (c & 1u) ? pm[1] : pm[0];
+  const uint64_t b = (c & 1u) ? pm[3] : pm[2];
+  return (c & 2u) ? b : a;
+}
+
+__global__ __launch_bounds__(256) void k_genasm(Seqs S, Outs O, int32_t k, int32_t want_cigar, Work Wk,
+                                                uint64_t *store, int32_t levels) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  uint64_t *mine = store + wave * (int64_t)levels * 64 * 64 + lane;
+  const int64_t count = Wk.count ? (int64_t)(*(volatile const int32_t *)Wk.count) : Wk.n;
+  // a wavefront the work can never reach leaves before touching the counter
+  if (wave * 64 >= count) return;
+
+  for (;;) {
+    int32_t chunk = 0;
+    if (lane == 0) chunk = atomicAdd(Wk.counter, 1);
+    chunk = __shfl(chunk, 0);
+    if ((int64_t)chunk * 64 >= count) break;
+    const int64_t li = (int64_t)chunk * 64 + lane;
+    const bool has = li < count;
+    const int64_t p = has ? (Wk.idx ? (int64_t)Wk.idx[li] : li) : 0;
+    bool live = has;
+    if (has && !Wk.direct && O.flags && O.flags[p]) {
+      O.score[p] = -1;
+      O.status[p] = ST_INVALID;
+      O.nruns[p] = 0;
+      live = false;
+    }
+    const int32_t m = live ? S.pat_len[p] : 0, n = live ? S.txt_len[p] : 0;
+    const uint64_t *pat = S.pat + (live ? S.pat_off[p] : 0);
+    const uint64_t *txt = S.txt + (live ? S.txt_off[p] : 0);
+    const int64_t pnw = (m + 31) >> 5, tnw = (n + 31) >> 5;
+    const bool cig = live && want_cigar;
+    const bool direct = Wk.direct != 0;
+    const int32_t total = (cig && direct) ? O.nruns[p] : 0;
+    uint32_t *dst = (cig && direct) ? O.cigar + O.cigar_off[p] : nullptr;
+    RunSink sink;
+    if (cig && !direct) sink.begin(O, p);
+    uint32_t cur_op = 0xffu, cur_len = 0;
+    int32_t nr = 0;
+    int32_t me = m, ne = n, used = 0;
+    uint32_t prev = OP_NONE;
+    bool rej = false;
+    // runs still to come, this one included, at most: one per base left, and
+    // with a threshold two per edit left plus the current and a last '=' run
+    auto put = [&](uint32_t op, uint32_t len, int64_t left) {
+      if (!cig) return;
+      if (op == cur_op) {
+        cur_len += len;
+        return;
+      }
+      if (cur_len) {
+        const uint32_t run = (cur_len << 4) | cur_op;
+        if (direct) {
+          if (nr < total) dst[total - 1 - nr] = run;
+        } else {
+          int64_t more = left;
+          if (k >= 0) more = min<int64_t>(more, 2 * (int64_t)(k - used) + 3);
+          sink.put(nr, run, more);
+        }
+        ++nr;
+      }
+      cur_op = op;
+      cur_len = len;
+    };
+
+    while (live && me > 0 && ne > 0) {
+      const bool anchored = me <= GW && ne <= GW;
+      const int32_t a = min(GW, me), b = min(GW, ne);
+      uint64_t pm[4];
+      pattern_masks(pat, pnw, me - a, a, pm);
+      const uint64_t tlo = dev::window32(txt, tnw, ne - b), thi = dev::window32(txt, tnw, ne - b + 32);
+      const uint64_t am = low_bits(a);
+      int32_t lw = max(a, b);
+      if (k >= 0) lw = min(lw, k - used);
+      // ---- distance calculation, LB levels per sweep over the text ----
+      int32_t dist = -1;
+      for (int32_t d0 = 0; d0 <= lw && dist < 0; d0 += LB) {
+        uint64_t v[LB];  // R_{d0+q}[j-1]
+#pragma unroll
+        for (int q = 0; q < LB; ++q) v[q] = anchored ? (low_bits(d0 + q) & am) : am;
+        uint64_t pp = d0 > 0 ? (anchored ? (low_bits(d0 - 1) & am) : am) : 0ull;  // R_{d0-1}[j-1]
+        // R_{d0-1}[j] at [(j-1) * 64] (read only when d0 > 0)
+        const uint64_t *below = mine + (int64_t)max(d0 - 1, 0) * 64 * 64;
+        uint64_t *col = mine + (int64_t)d0 * 64 * 64;
+        for (int32_t j = 1; j <= b; ++j) {
+          const uint64_t pmc = pick(pm, base_at(tlo, thi, j));
+          const uint64_t lowc = d0 > 0 ? below[(j - 1) * 64] : 0ull;  // R_{d0-1}[j]
+          uint64_t old_lo = pp, new_lo = lowc;  // the level below at j - 1 and at j
+#pragma unroll
+          for (int q = 0; q < LB; ++q) {
+            const int32_t d = d0 + q;
+            // [D(0, j - 1) <= d]
+            uint64_t nv = ((v[q] << 1) | ((!anchored || j - 1 <= d) ? 1ull : 0ull)) & pmc;
+            if (d > 0) {
+              // substitution | insertion | deletion; [D(0, j) <= d - 1]
+              // implies [D(0, j - 1) <= d - 1], so one start bit serves both
+              nv |= ((old_lo | new_lo) << 1) | ((!anchored || j - 1 <= d - 1) ? 1ull : 0ull) | old_lo;
+            }
+            nv &= am;
+            old_lo = v[q];
+            new_lo = nv;
+            v[q] = nv;
+            col[((int64_t)q * 64 + j - 1) * 64] = nv;
+          }
+          pp = lowc;
+        }
+#pragma unroll
+        for (int q = 0; q < LB; ++q)
+          if (dist < 0 && d0 + q <= lw && ((v[q] >> (a - 1)) & 1ull)) dist = d0 + q;
+      }
+      if (dist < 0) {
+        rej = true;
+        break;
+      }
+      if (!cig && anchored) {
+        // score only: the final window adds its distance, no walk needed
+        used += dist;
+        me = ne = 0;
+        break;
+      }
+      // ---- traceback over the stored levels ----
+      int32_t i = a, j = b, d = dist;
+      auto R = [&](int32_t dd, int32_t jj) -> uint64_t {  // R_dd[jj]
+        if (jj == 0) return anchored ? (low_bits(dd) & am) : am;
+        return mine[((int64_t)max(dd, 0) * 64 + jj - 1) * 64];
+      };
+      // [D(ii - 1, jj) <= dd] from v = R_dd[jj] (ii >= 1)
+      auto up = [&](uint64_t v, int32_t dd, int32_t jj, int32_t ii) -> bool {
+        if (ii == 1) return !anchored || jj <= dd;
+        return (v >> (ii - 2)) & 1ull;
+      };
+      for (;;) {
+        if (anchored) {
+          if (i == 0 && j == 0) break;
+        } else if (a - i >= GC || b - j >= GC || i == 0 || j == 0) {
+          break;
+        }
+        uint32_t op;
+        if (i == 0) {
+          op = OP_D;
+        } else if (j == 0) {
+          op = OP_I;
+        } else {
+          const bool eq = (pick(pm, base_at(tlo, thi, j)) >> (i - 1)) & 1ull;
+          const uint64_t r1 = d > 0 ? R(d - 1, j - 1) : 0ull;
+          const bool del = d > 0 && ((r1 >> (i - 1)) & 1ull);
+          if (prev == OP_I && d > 0 && up(R(d - 1, j), d - 1, j, i)) {
+            op = OP_I;
+          } else if (prev == OP_D && del) {
+            op = OP_D;
+          } else if (eq && up(R(d, j - 1), d, j - 1, i)) {
+            op = OP_EQ;
+          } else if (d > 0 && up(r1, d - 1, j - 1, i)) {
+            op = OP_X;
+          } else if (d > 0 && up(R(d - 1, j), d - 1, j, i)) {
+            op = OP_I;
+          } else {
+            op = OP_D;
+          }
+        }
+        if (op != OP_EQ) {
+          d -= 1;
+          used += 1;
+        }
+        if (op != OP_D) --i;
+        if (op != OP_I) --j;
+        put(op, 1, (int64_t)(me - a + i) + (ne - b + j) + 2);
+        prev = op;
+      }
+      me -= a - i;
+      ne -= b - j;
+    }
+    if (live && !rej) {
+      if (me > 0) put(OP_I, (uint32_t)me, 2);
+      if (ne > 0) put(OP_D, (uint32_t)ne, 2);
+      used += me + ne;
+      if (k >= 0 && used > k) rej = true;
+      if (!rej) put(0xfu, 0, 1);  // flush the last run
+    }
+    if (!live || direct) continue;
+    if (cig) sink.finish();
+    O.score[p] = rej ? -1 : used;
+    O.status[p] = rej ? ST_REJECTED : ST_ALIGNED;
+    O.nruns[p] = rej ? 0 : nr;
+  }
+}
+
+}  // namespace
+
+// levels 0..min(k, 64), rounded up to whole sweeps (the last sweep may build
+// levels past the cap; they are stored but never used)
+int32_t genasm_levels(int32_t max_score) {
+  const int32_t top = max_score < 0 ? 64 : min(max_score, 64);
+  return (top + 1 + LB - 1) / LB * LB;
+}
+
+int64_t genasm_block_words(int32_t levels) { return (int64_t)4 * levels * 64 * 64; }
+
+hipError_t launch_genasm(const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk, uint64_t *store,
+                         int32_t levels, int32_t nblocks, hipStream_t s) {
+  if (nblocks <= 0 || levels < genasm_levels(P.max_score)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_genasm, dim3(nblocks), dim3(256), 0, s, S, O, P.max_score, P.want_cigar, Wk, store,
+                     levels);
+  return hipGetLastError();
+}
+
+}  // namespace aim

@@ -345,7 +345,7 @@ aim_status aim_server_submit(aim_server *s, const aim_request *q, int64_t *id) {
   s_err.clear();
   if (!s || !q || !id) return sfail(AIM_ERR_INVALID_ARG, "NULL argument");
   if (q->enc != AIM_ENC_ASCII && q->enc != AIM_ENC_CODE) return sfail(AIM_ERR_INVALID_ARG, "enc must be ASCII or CODE");
-  if (q->alg < AIM_NW_LINEAR || q->alg > AIM_WFA_ADAPTIVE) return sfail(AIM_ERR_INVALID_ARG, "unknown algorithm");
+  if (q->alg < AIM_NW_LINEAR || q->alg > AIM_GENASM) return sfail(AIM_ERR_INVALID_ARG, "unknown algorithm");
   if (q->n_pairs < 0) return sfail(AIM_ERR_INVALID_ARG, "n_pairs < 0");
   if (q->n_pairs > 0 && (!q->pat || !q->pat_off || !q->pat_len || !q->txt || !q->txt_off || !q->txt_len))
     return sfail(AIM_ERR_INVALID_ARG, "NULL sequence array");

@@ -252,6 +252,12 @@ WORKLOADS = {
                             max_score=-1, enc="2bit", adaptive=(10, 50)),
     "wfa_adaptive_10k": dict(seed=8, total=10_000, L=10_000, rate=0.05, alg="wfa_adaptive", pen=AFFINE_462,
                              max_score=-1, enc="2bit", adaptive=(10, 50)),
+    # GenASM (unit edits, k = 10 % of the read length): 1M x 150 bp at 4 %,
+    # 100k x 1,000 bp at 5 %
+    "genasm150": dict(seed=9, total=1_000_000, L=150, rate=0.04, alg="genasm", pen=NW_EDIT,
+                      max_score=15, enc="2bit"),
+    "genasm1k": dict(seed=10, total=100_000, L=1000, rate=0.05, alg="genasm", pen=NW_EDIT,
+                     max_score=100, enc="2bit"),
 }
 
 

@@ -1,0 +1,124 @@
+"""GenASM on the GPU (alg "genasm", k_genasm) against the CPU GenASM oracle
+(oracle.genasm_batch, windows of 64 bases overlapping by 24): scores,
+statuses and CIGARs element by element, on tiny pairs exhaustively, mixed
+lengths with window edges, thresholds from 0 up, unrelated and lopsided
+pairs, score-only calls, ASCII input, long pairs, and the in-place re-run of
+pairs whose runs outgrow their slot and the pool.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+import synth  # noqa: E402
+import paper_2208_01243_amd as aim  # noqa: E402
+from gpu_util import compare, describe, run  # noqa: E402
+
+EDIT = (0, 1, 0, 1)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = aim.Context(0)
+    yield c
+    c.close()
+
+
+def _pairs(seed, n, lmin, lmax, rmax, unrelated=0.0, lopsided=0, lens=None):
+    rng = np.random.default_rng(seed)
+    pats, txts = [], []
+    for q in range(n):
+        L = int(lens[q % len(lens)]) if lens is not None else int(rng.integers(lmin, lmax + 1))
+        T = rng.integers(0, 4, L).astype(np.uint8)
+        if rng.random() < unrelated:
+            P = rng.integers(0, 4, int(rng.integers(lmin, lmax + 1))).astype(np.uint8)
+        else:
+            bb = synth.from_lists([T], [T])
+            P, _ = synth.mutate(rng, bb.txt, bb.txt_off, [float(rng.uniform(0, rmax))])
+        if lopsided and q % 3 == 0:
+            cut = int(rng.integers(0, min(lopsided, len(P)) + 1))
+            P = P[cut:] if q % 2 else P[:len(P) - cut]
+        pats.append(P)
+        txts.append(T)
+    return synth.from_lists(pats, txts)
+
+
+def check(ctx, b, k=-1, want_cigar=True, enc="2bit"):
+    got = run(ctx, b, "genasm", EDIT, k, want_cigar=want_cigar, enc=enc)
+    want = oracle.genasm_batch(b, k, want_cigar=want_cigar)
+    if not want_cigar:
+        assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1])
+        return got
+    bad = compare(got, want)
+    assert not bad, "%d mismatches, first: %s" % (len(bad), describe(b, bad[0], got, want))
+    return got
+
+
+def test_exhaustive_tiny(ctx):
+    seqs = [np.array(s, np.uint8) for L in range(4) for s in itertools.product(range(4), repeat=L)]
+    pats, txts = zip(*[(p, t) for p in seqs for t in seqs])
+    b = synth.from_lists(list(pats), list(txts))
+    for k in [-1, 0, 1, 2]:
+        check(ctx, b, k)
+
+
+@pytest.mark.parametrize("k", [-1, 0, 3, 15, 64, 100])
+def test_mixed_pairs(ctx, k):
+    b = _pairs(21, 1200, 0, 500, 0.2, unrelated=0.1, lopsided=100)
+    got = check(ctx, b, k)
+    if k == 15:
+        assert (got[1] == 0).sum() > 100 and (got[1] == 1).sum() > 100
+
+
+def test_window_edges(ctx):
+    # lengths around one window (64), a window plus a commit (104) and two
+    # windows (128), at low error so that the windows line up with the ends
+    edges = [1, 2, 39, 40, 41, 63, 64, 65, 103, 104, 105, 127, 128, 129, 144, 145, 184, 185]
+    b = _pairs(22, 1800, 0, 0, 0.06, lens=edges, lopsided=3)
+    check(ctx, b, -1)
+    check(ctx, b, 8)
+
+
+def test_score_only_and_ascii(ctx):
+    b = _pairs(23, 2000, 50, 400, 0.12, unrelated=0.05)
+    full = check(ctx, b, 30)
+    so = check(ctx, b, 30, want_cigar=False)
+    assert np.array_equal(full[0], so[0]) and np.array_equal(full[1], so[1])
+    check(ctx, b, 30, enc="ascii")
+
+
+def test_workload_sample(ctx):
+    for name in ["genasm150", "genasm1k"]:
+        w = synth.WORKLOADS[name]
+        b = synth.workload(name, n=3000 if name == "genasm150" else 300)
+        got = check(ctx, b, w["max_score"])
+        assert (got[1] == 0).mean() > 0.9
+
+
+def test_long_pairs(ctx):
+    b = _pairs(24, 40, 2000, 6000, 0.1, lopsided=300)
+    check(ctx, b, -1)
+    check(ctx, b, 200)
+
+
+def test_runs_beyond_slot_and_pool_are_rerun():
+    # 240 pairs of 4-5 kbp at up to 30 % error need about 2,000 runs each and
+    # reserve pool space for what their remaining bases could still need: a
+    # 256 MiB scratch limit leaves a pool of 2^20 words, which they exhaust,
+    # so some are re-aligned in place
+    b = _pairs(25, 240, 4000, 5000, 0.3)
+    with aim.Context(0, scratch_limit=256 << 20) as c:
+        check(c, b, -1)
+        assert c.last_call_stats()["cigar_reruns"] > 0
+
+
+def test_invalid_and_empty(ctx):
+    pats = [synth.codes_from_ascii("ACGT"), np.zeros(0, np.uint8), synth.codes_from_ascii("ACGTACGT")]
+    txts = [synth.codes_from_ascii("ACGA"), synth.codes_from_ascii("ACG"), np.zeros(0, np.uint8)]
+    b = synth.from_lists(pats, txts)
+    check(ctx, b, -1)
+    check(ctx, b, 3)
