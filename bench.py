@@ -20,8 +20,9 @@ Prints ONE JSON line.  Besides the headline it carries:
   cpu_baseline  -- the oracle, built -O3 -march=native on this host, on a
                    bounded sample, on all granted cores and on one core;
   other_configs -- the NW edit (10k x 100 bp), SWG (1M x 150 bp) and WFA
-                   (1M x 250 bp with 20 % unrelated pairs) workloads, and
-                   WFA-adaptive at 150 bp / 2 %, 1 kbp / 5 %, 10 kbp / 5 %;
+                   (1M x 250 bp with 20 % unrelated pairs) workloads,
+                   WFA-adaptive at 150 bp / 2 %, 1 kbp / 5 %, 10 kbp / 5 %,
+                   and GenASM at 150 bp / 4 % (k 15) and 1 kbp / 5 % (k 100);
   serving       -- the Poisson request schedule through aim_server.
 """
 from __future__ import annotations
@@ -47,6 +48,13 @@ PEAK_PK16_TOPS = 2 * PEAK_INT32_TOPS       # packed 16-bit: two halves per lane 
 # xor, count trailing zeros, advance: 10)
 OPS_PER_CELL = {"swg": 14, "nw": 10}
 WFA_OPS_PER_CELL, WFA_OPS_PER_WORD = 8, 10
+# GenASM: a status-vector update (one 64-bit vector at one text position and
+# edit level: match shift, start bit and text mask; the level below's
+# substitution, insertion and deletion terms; the window mask: 14 int32 ops)
+# stores its 8-byte vector for the traceback; a traceback step (12 ops) reads
+# at least one stored vector
+GENASM_OPS_PER_UPDATE, GENASM_OPS_PER_STEP, GENASM_BYTES_PER_UPDATE, GENASM_BYTES_PER_STEP = 14, 12, 8, 8
+PEAK_HBM_GBS = 8000.0
 # HBM bytes per launch of a kernel from two rocprofv3 --pmc passes (FETCH_SIZE
 # and WRITE_SIZE scaled by a copy-kernel calibration), valid only for the
 # kernel source they were taken on (first 16 hex of its SHA-256)
@@ -69,6 +77,10 @@ WORKLOAD_TEXT = {
     "wfa_adaptive_1k": "WFA-adaptive 4/6/2 (10, 50), 100,000 pairs x 1,000 bp, 5% error, 2-bit, score + CIGAR",
     "wfa_adaptive_10k": "WFA-adaptive 4/6/2 (10, 50), 10,000 pairs x 10,000 bp, 5% error, 2-bit, "
                         "score + CIGAR",
+    "genasm150": "GenASM (windows of 64, overlap 24), k = 15 edits, 1,000,000 pairs x 150 bp, 4% error, "
+                 "2-bit, score + CIGAR",
+    "genasm1k": "GenASM (windows of 64, overlap 24), k = 100 edits, 100,000 pairs x 1,000 bp, 5% error, "
+                "2-bit, score + CIGAR",
 }
 
 
@@ -79,6 +91,15 @@ def log(*a):
 def src_hash(kernel):
     src = open(os.path.join(ROOT, "paper_2208_01243_amd", "csrc", KERNEL_SOURCE[kernel]), "rb").read()
     return hashlib.sha256(src).hexdigest()[:16]
+
+
+def genasm_units(name):
+    """GenASM work totals of a whole workload from the oracle's counters
+    (tests/golden/genasm_work.json), or None."""
+    path = os.path.join(ROOT, "tests", "golden", "genasm_work.json")
+    if not os.path.exists(path):
+        return None
+    return json.load(open(path)).get(name)
 
 
 def wfa_units(name, window, filtered=False):
@@ -184,6 +205,38 @@ def roofline(run, phases, stats, steps):
                         "units_per_launch": {"cells": units["cells"], "words": units["words"]},
                         "unit_name": "cells of the reduced wavefronts (adaptive oracle) of every pair"})
         return out
+    if w["alg"] == "genasm":
+        # one kernel, k_genasm, over every pair: the distance calculation is
+        # integer ALU work, and every status vector it builds is stored for
+        # the traceback, so both rooflines are given; `bound` is the tighter
+        if "genasm" not in phases:
+            return None
+        ms, launches = phases["genasm"]
+        ms /= max(1, launches)
+        u = genasm_units(run.name) if run.n == w["total"] else None
+        out = {"kernel": "k_genasm", "avg_launch_ms": round(ms, 4), "bound": "alu", "achieved": None,
+               "peak": round(PEAK_INT32_TOPS, 1), "unit": "Tops/s (int32)", "frac": None, "traffic": None,
+               "ops_per_unit": {"status-vector update": GENASM_OPS_PER_UPDATE,
+                                "traceback step": GENASM_OPS_PER_STEP},
+               "bytes_per_unit": {"status-vector update": GENASM_BYTES_PER_UPDATE,
+                                  "traceback step": GENASM_BYTES_PER_STEP, "base": 0.25}}
+        if u:
+            t = ms / 1000.0
+            ops = GENASM_OPS_PER_UPDATE * u["updates"] + GENASM_OPS_PER_STEP * u["tb_steps"]
+            byts = GENASM_BYTES_PER_UPDATE * u["updates"] + GENASM_BYTES_PER_STEP * u["tb_steps"] + u["bases"] / 4
+            alu = {"achieved": round(ops / t / 1e12, 3), "peak": round(PEAK_INT32_TOPS, 1), "unit": "Tops/s (int32)",
+                   "frac": round(ops / t / 1e12 / PEAK_INT32_TOPS, 4)}
+            hbm = {"achieved": round(byts / t / 1e9, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                   "frac": round(byts / t / 1e9 / PEAK_HBM_GBS, 4)}
+            top = hbm if hbm["frac"] > alu["frac"] else alu
+            out.update(top)
+            out["bound"] = "hbm" if top is hbm else "alu"
+            out.update({"alu": alu, "hbm": hbm,
+                        "units_per_launch": {"updates": u["updates"], "tb_steps": u["tb_steps"],
+                                             "windows": u["windows"], "bases": u["bases"]},
+                        "unit_name": "status-vector updates (distance + 1) x text bases per window and "
+                                     "traceback steps, from the oracle's counters over every pair"})
+        return out
     if w["alg"] != "wfa":
         return None
     # the WFA passes of one call: the one-wavefront pass (k_wfa_score16) over
@@ -250,7 +303,7 @@ def measure(aim, synth, name, steps, warmup, plain_steps=0, e2e_reps=0):
     units = wfa_units(name, 0) if run.w["alg"].startswith("wfa") and run.n == run.w["total"] else None
     if units:
         res["wavefront_cells_per_s"] = round(units["cells"] / (elapsed / steps), 1)
-    if plain_steps > 0:
+    if plain_steps > 0 and run.w["alg"] in ("nw", "swg", "wfa"):
         pctx = aim.Context(0, kernel="plain")
         s1, st1, off1 = run.score.clone(), run.status.clone(), run.cigar_off.clone()
         t0 = time.perf_counter()
@@ -319,7 +372,10 @@ def cpu_baseline(synth, name, n_all, n_one):
     for label, k, th in (("all", n_all, threads), ("one", n_one, 1)):
         sub = synth.workload(name, n=k)
         t0 = time.perf_counter()
-        oracle.align_batch(sub, w["alg"], w["pen"], w["max_score"], nthreads=th, handle=h)
+        if w["alg"] == "genasm":
+            oracle.genasm_batch(sub, w["max_score"], nthreads=th, handle=h)
+        else:
+            oracle.align_batch(sub, w["alg"], w["pen"], w["max_score"], nthreads=th, handle=h)
         ct = time.perf_counter() - t0
         out[label] = (k, th, ct)
         log("cpu oracle %s: %d pairs on %d threads in %.1f s" % (name, k, th, ct))
@@ -327,9 +383,10 @@ def cpu_baseline(synth, name, n_all, n_one):
     k1, _, ct1 = out["one"]
     res = {"value": round(k / ct, 1), "unit": "pairs/s", "cores": th, "kind": "oracle",
            "host_nproc": nproc,
-           "sample": "first %d pairs of the same workload: full-matrix int32 %s + canonical traceback, "
-                     "gcc -O3 -march=native, %d threads, %.1f s wall" % (
-                         k, "Gotoh" if w["alg"] != "nw" else "NW", th, ct),
+           "sample": "first %d pairs of the same workload: %s, gcc -O3 -march=native, %d threads, %.1f s wall" % (
+                         k, {"nw": "full-matrix int32 NW + canonical traceback",
+                             "genasm": "the plain windowed bitap + traceback (byte per bit, all k + 1 levels)"}.get(
+                             w["alg"], "full-matrix int32 Gotoh + canonical traceback"), th, ct),
            "one_core": {"value": round(k1 / ct1, 1), "unit": "pairs/s", "cores": 1,
                         "sample": "first %d pairs, %.1f s" % (k1, ct1)}}
     if w["alg"] == "wfa":
@@ -420,11 +477,13 @@ def main():
             out[k] = main_res[k]
     if args.cpu:
         n_all, n_one = {"wfa_mixed": (4000, 400), "swg150": (200_000, 20_000), "wfa250": (100_000, 10_000),
-                        "nw100": (10_000, 10_000)}[args.workload]
+                        "nw100": (10_000, 10_000), "genasm150": (200_000, 20_000),
+                        "genasm1k": (10_000, 1000)}.get(args.workload, (2000, 200))
         out["cpu_baseline"] = cpu_baseline(synth, args.workload, n_all, n_one)
     if args.others:
         others = {}
-        for name in ("nw100", "swg150", "wfa250", "wfa_adaptive_150", "wfa_adaptive_1k", "wfa_adaptive_10k"):
+        for name in ("nw100", "swg150", "wfa250", "wfa_adaptive_150", "wfa_adaptive_1k", "wfa_adaptive_10k",
+                     "genasm150", "genasm1k"):
             if name == args.workload:
                 continue
             r, res = measure(aim, synth, name, 20, 3)

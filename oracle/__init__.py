@@ -77,11 +77,11 @@ def bind(path: str):
     L.oracle_wfa_adaptive.argtypes = [p, i32, p, i32, i32, i32, i32, i32, i32, i32, i32, p, p, p, i32, p,
                                       ctypes.POINTER(WfaStats)]
     L.oracle_wfa_adaptive.restype = ctypes.c_int
-    L.oracle_genasm.argtypes = [p, i32, p, i32, i32, i32, i32, i32, p, p, p, i32, p]
+    L.oracle_genasm.argtypes = [p, i32, p, i32, i32, i32, i32, i32, p, p, p, i32, p, p]
     L.oracle_genasm.restype = ctypes.c_int
     L.oracle_genasm_dc.argtypes = [p, i32, p, i32, i32, i32, p]
     L.oracle_genasm_dc.restype = ctypes.c_int
-    L.oracle_genasm_batch.argtypes = [i64, p, p, p, p, i32, i32, i32, i32, i32, p, p, p, p, p]
+    L.oracle_genasm_batch.argtypes = [i64, p, p, p, p, i32, i32, i32, i32, i32, p, p, p, p, p, p]
     L.oracle_genasm_batch.restype = ctypes.c_int
     return L
 
@@ -235,9 +235,10 @@ GENASM_WINDOW, GENASM_OVERLAP = 64, 24  # window bases and overlap of the GPU li
 
 
 def genasm_pair(P, T, k: int = -1, window: int = GENASM_WINDOW, overlap: int = GENASM_OVERLAP,
-                want_cigar: bool = True, handle=None):
+                want_cigar: bool = True, handle=None, stats: bool = False):
     """GenASM of one pair (``genasm.c``): unit edits, at most ``k`` of them
-    (-1: no threshold).  Returns (status, score, runs)."""
+    (-1: no threshold).  Returns (status, score, runs), plus the work
+    counters {windows, updates, tb_steps} when ``stats``."""
     P, T = _codes(P), _codes(T)
     m, n = len(P), len(T)
     cap = m + n + 1
@@ -247,11 +248,16 @@ def genasm_pair(P, T, k: int = -1, window: int = GENASM_WINDOW, overlap: int = G
     nr = np.zeros(1, np.int32)
     Pb = P if m else np.zeros(1, np.uint8)
     Tb = T if n else np.zeros(1, np.uint8)
+    st = np.zeros(3, np.int64)
     rc = (handle or lib()).oracle_genasm(_ptr(Pb), m, _ptr(Tb), n, int(k), int(window), int(overlap),
-                                         int(want_cigar), _ptr(score), _ptr(status), _ptr(runs), cap, _ptr(nr))
+                                         int(want_cigar), _ptr(score), _ptr(status), _ptr(runs), cap, _ptr(nr),
+                                         _ptr(st))
     if rc != 0:
         raise RuntimeError("genasm oracle failure %d" % rc)
-    return int(status[0]), int(score[0]), [int(r) for r in runs[:nr[0]]]
+    out = (int(status[0]), int(score[0]), [int(r) for r in runs[:nr[0]]])
+    if stats:
+        return out + ({"windows": int(st[0]), "updates": int(st[1]), "tb_steps": int(st[2])},)
+    return out
 
 
 def genasm_dc(p, t, anchored: bool, levels: int, handle=None):
@@ -269,10 +275,11 @@ def genasm_dc(p, t, anchored: bool, levels: int, handle=None):
 
 
 def genasm_batch(batch, k: int = -1, want_cigar: bool = True, window: int = GENASM_WINDOW,
-                 overlap: int = GENASM_OVERLAP, nthreads: int | None = None, handle=None):
+                 overlap: int = GENASM_OVERLAP, nthreads: int | None = None, handle=None, stats=None):
     """``genasm_pair`` over every pair of a ``synth.PairBatch`` on host
     threads.  Returns (score int32[n], status int8[n], cigar uint32[...],
-    cigar_off int64[n+1]) like ``align_batch``."""
+    cigar_off int64[n+1]) like ``align_batch``.  ``stats``: an int64 array
+    [n, 3] that receives each pair's work counters."""
     n = batch.n
     if nthreads is None:
         nthreads = os.cpu_count() or 1
@@ -289,7 +296,8 @@ def genasm_batch(batch, k: int = -1, want_cigar: bool = True, window: int = GENA
     rc = (handle or lib()).oracle_genasm_batch(
         n, _ptr(pat), _ptr(np.ascontiguousarray(batch.pat_off)), _ptr(txt),
         _ptr(np.ascontiguousarray(batch.txt_off)), int(k), int(window), int(overlap), int(want_cigar),
-        nthreads, _ptr(score), _ptr(status), _ptr(runs), _ptr(slot), _ptr(nr))
+        nthreads, _ptr(score), _ptr(status), _ptr(runs), _ptr(slot), _ptr(nr),
+        _ptr(stats) if stats is not None else None)
     if rc != 0 or (status < 0).any():
         raise RuntimeError("genasm oracle batch failure %d" % rc)
     off = np.zeros(n + 1, np.int64)

@@ -58,6 +58,12 @@
  *
  * Rejected pairs: score -1, no runs.  Runs are `len << 4 | op`, first op
  * first (ops '=' 0, 'X' 1, 'I' 2, 'D' 3).
+ *
+ * Work counters (the units in which the GPU kernel's work is stated), when
+ * `stats` is not NULL: stats[0] windows aligned, stats[1] status-vector
+ * updates the distance calculation needs -- (distance + 1) x b per window,
+ * the levels up to the one that reaches bit a at every text position --
+ * stats[2] traceback steps (ops committed inside windows).
  */
 #include <pthread.h>
 #include <stdint.h>
@@ -153,8 +159,9 @@ int oracle_genasm_dc(const uint8_t *p, int32_t a, const uint8_t *t, int32_t b, i
 
 int oracle_genasm(const uint8_t *P, int32_t m, const uint8_t *T, int32_t n, int32_t k, int32_t W, int32_t Ov,
                   int32_t want_cigar, int32_t *score, int8_t *status, uint32_t *runs, int32_t cap,
-                  int32_t *nruns) {
+                  int32_t *nruns, int64_t *stats) {
   if (m < 0 || n < 0 || W < 1 || Ov < 0 || Ov >= W) return -2;
+  if (stats) stats[0] = stats[1] = stats[2] = 0;
   const int32_t C = W - Ov;
   /* ops, last op first */
   uint8_t *rev = (uint8_t *)malloc((size_t)m + (size_t)n + 1);
@@ -178,6 +185,10 @@ int oracle_genasm(const uint8_t *P, int32_t m, const uint8_t *T, int32_t n, int3
       rejected = 1;
       dc_free(&w);
       break;
+    }
+    if (stats) {
+      stats[0] += 1;
+      stats[1] += (int64_t)(d + 1) * b;
     }
     int32_t i = a, j = b;
     for (;;) {
@@ -205,6 +216,7 @@ int oracle_genasm(const uint8_t *P, int32_t m, const uint8_t *T, int32_t n, int3
       if (op != G_I) j -= 1;
       rev[nops++] = (uint8_t)op;
       prev = op;
+      if (stats) stats[2] += 1;
     }
     me -= a - i;
     ne -= b - j;
@@ -254,6 +266,7 @@ typedef struct {
   uint32_t *runs;
   const int64_t *slot_off;
   int32_t *nruns;
+  int64_t *stats;
   int64_t next;
   int32_t fail;
   pthread_mutex_t mu;
@@ -274,7 +287,8 @@ static void *genasm_worker(void *arg) {
       const int64_t so = J->want_cigar ? J->slot_off[q] : 0;
       const int32_t cap = J->want_cigar ? (int32_t)(J->slot_off[q + 1] - J->slot_off[q]) : 0;
       const int rc = oracle_genasm(J->pat + J->pat_off[q], m, J->txt + J->txt_off[q], n, J->k, J->W, J->Ov,
-                                   J->want_cigar, J->score + q, J->status + q, J->runs + so, cap, J->nruns + q);
+                                   J->want_cigar, J->score + q, J->status + q, J->runs + so, cap, J->nruns + q,
+                                   J->stats ? J->stats + 3 * q : NULL);
       if (rc) {
         J->status[q] = -1;
         pthread_mutex_lock(&J->mu);
@@ -285,12 +299,13 @@ static void *genasm_worker(void *arg) {
   }
 }
 
+/* stats: NULL, or 3 counters per pair (see oracle_genasm). */
 int oracle_genasm_batch(int64_t n, const uint8_t *pat, const int64_t *pat_off, const uint8_t *txt,
                         const int64_t *txt_off, int32_t k, int32_t W, int32_t Ov, int32_t want_cigar,
                         int32_t nthreads, int32_t *score, int8_t *status, uint32_t *runs,
-                        const int64_t *slot_off, int32_t *nruns) {
+                        const int64_t *slot_off, int32_t *nruns, int64_t *stats) {
   genasm_job J = {n, pat, txt, pat_off, txt_off, k, W, Ov, want_cigar, score, status, runs, slot_off, nruns,
-                  0, 0, PTHREAD_MUTEX_INITIALIZER};
+                  stats, 0, 0, PTHREAD_MUTEX_INITIALIZER};
   if (nthreads < 1) nthreads = 1;
   pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)nthreads);
   if (!th) return -1;

@@ -31,16 +31,19 @@
 // The score is the number of edits; more than k rejects the pair.
 //
 // MI355X mapping.  A lane owns a pair: the pattern masks (4 x 64 bits) live
-// in registers.  A sweep over the window's text builds LB consecutive levels
-// at once, each level's vector at j - 1 in a register, reading only the
-// level below the block (stored by the previous sweep) once per text
-// position; sweeps stop at the first block holding the window's distance,
-// so a window costs about (distance + 1) x 64 level steps, rounded up to LB.
-// Every level's vectors are stored for the traceback in the wavefront's
-// slot, entry (d, j) of lane l at word (d * 64 + j - 1) * 64 + l, so a
+// in registers.  The window's distance comes first, from a register-only
+// pass over its text (Myers' recurrence on the vertical deltas of the same
+// table).  Then only the levels the traceback can read (0 .. distance - 1)
+// are built: a sweep over the window's text builds LB consecutive levels at
+// once, each level's vector at j - 1 in a register, reading only the level
+// below the block (stored by the previous sweep) once per text position.
+// The vectors of those levels are stored for the traceback in the
+// wavefront's slot, entry (d, j) of lane l at word (d * 64 + j - 1) * 64 + l, so a
 // wavefront's loads and stores at one text position are one contiguous
-// 512-byte group.  The traceback reads the stored vectors it needs (usually
-// one per '=' step).  Work comes 64 pairs at a time from an atomic counter.
+// 512-byte group.  The traceback compares bases on '=' steps and reads
+// stored vectors only around edits, in rounds in which every lane of the
+// wavefront that needs them reads them together.  Work comes 64 pairs at a
+// time from an atomic counter.
 #include "aim_internal.h"
 #include "dev_util.h"
 
@@ -50,6 +53,7 @@ namespace {
 constexpr int32_t GW = 64;       // window bases
 constexpr int32_t GC = GW - 24;  // bases a window other than the final one commits
 constexpr int32_t LB = 4;        // edit levels built per sweep over a window's text
+constexpr int32_t JB = 8;        // text positions whose lower-level vectors are read ahead
 constexpr uint32_t OP_NONE = 4;
 
 __device__ __forceinline__ uint64_t low_bits(int32_t q) {
@@ -81,11 +85,67 @@ __device__ __forceinline__ uint64_t pick(const uint64_t pm[4], uint32_t c) {
   return (c & 2u) ? b : a;
 }
 
+// A wavefront's slot through a buffer resource: entry (d, j) of lane l at
+// byte ((d * 64 + j - 1) * 64 + l) * 8.  Raw buffer accesses at or past the
+// resource's size are dropped (stores) or read zero (loads), so a lane that
+// must not store passes OFF_NONE instead of branching around the store.
+constexpr uint32_t OFF_NONE = 0x80000000u;
+constexpr int32_t BUF_FLAGS = 0x00027000;  // word 3 of a raw CDNA buffer resource (32-bit format)
+
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+struct Slot {
+  __amdgpu_buffer_rsrc_t rs;
+  __device__ __forceinline__ uint64_t ld(uint32_t off) const {
+    const u32x2 r = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
+    return ((uint64_t)r.y << 32) | r.x;
+  }
+  __device__ __forceinline__ void st(uint64_t v, uint32_t off) const {
+    u32x2 w;
+    w.x = (uint32_t)v;
+    w.y = (uint32_t)(v >> 32);
+    __builtin_amdgcn_raw_buffer_store_b64(w, rs, off, 0, 0);
+  }
+};
+
+__device__ __forceinline__ uint32_t slot_off(int32_t d, int32_t j, int lane) {
+  return (uint32_t)((d * 64 + j - 1) * 64 + lane) * 8u;
+}
+
+// D(a, b) of a window: fewest edits aligning its a pattern bases (masks pm)
+// with its b text bases, its start anchored (D(i, 0) = i, D(0, j) = j) or
+// free (both 0).  Myers' bit-vector recurrence on the vertical deltas of one
+// text position after another (bit i - 1: D(i, j) - D(i - 1, j) = +1 in pv,
+// -1 in mv); the horizontal delta entering at the start row is +1 when
+// anchored, 0 when free; bits at and above a only carry upwards and are
+// masked off at the end.
+__device__ __forceinline__ int32_t window_distance(const uint64_t pm[4], uint64_t tlo, uint64_t thi, int32_t a,
+                                                   int32_t b, bool anchored) {
+  uint64_t pv = anchored ? ~0ull : 0ull, mv = 0ull;
+  const uint64_t hin = anchored ? 1ull : 0ull;
+  for (int32_t j = 1; j <= b; ++j) {
+    const uint64_t eq = pick(pm, base_at(tlo, thi, j));
+    const uint64_t xv = eq | mv;
+    const uint64_t xh = (((eq & pv) + pv) ^ pv) | eq;
+    uint64_t ph = mv | ~(xh | pv);
+    uint64_t mh = pv & xh;
+    ph = (ph << 1) | hin;
+    mh = mh << 1;
+    pv = mh | ~(xv | ph);
+    mv = ph & xv;
+  }
+  const uint64_t am = low_bits(a);
+  return (anchored ? b : 0) + __popcll(pv & am) - __popcll(mv & am);
+}
+
 __global__ __launch_bounds__(256) void k_genasm(Seqs S, Outs O, int32_t k, int32_t want_cigar, Work Wk,
                                                 uint64_t *store, int32_t levels) {
   const int lane = threadIdx.x & 63;
-  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  uint64_t *mine = store + wave * (int64_t)levels * 64 * 64 + lane;
+  // wavefront-uniform (kept in scalar registers, as the slot's resource must be)
+  const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  Slot slot;
+  slot.rs = __builtin_amdgcn_make_buffer_rsrc(store + wave * (int64_t)levels * 64 * 64, 0, levels * 64 * 64 * 8,
+                                              BUF_FLAGS);
   const int64_t count = Wk.count ? (int64_t)(*(volatile const int32_t *)Wk.count) : Wk.n;
   // a wavefront the work can never reach leaves before touching the counter
   if (wave * 64 >= count) return;
@@ -149,45 +209,11 @@ __global__ __launch_bounds__(256) void k_genasm(Seqs S, Outs O, int32_t k, int32
       uint64_t pm[4];
       pattern_masks(pat, pnw, me - a, a, pm);
       const uint64_t tlo = dev::window32(txt, tnw, ne - b), thi = dev::window32(txt, tnw, ne - b + 32);
-      const uint64_t am = low_bits(a);
       int32_t lw = max(a, b);
       if (k >= 0) lw = min(lw, k - used);
-      // ---- distance calculation, LB levels per sweep over the text ----
-      int32_t dist = -1;
-      for (int32_t d0 = 0; d0 <= lw && dist < 0; d0 += LB) {
-        uint64_t v[LB];  // R_{d0+q}[j-1]
-#pragma unroll
-        for (int q = 0; q < LB; ++q) v[q] = anchored ? (low_bits(d0 + q) & am) : am;
-        uint64_t pp = d0 > 0 ? (anchored ? (low_bits(d0 - 1) & am) : am) : 0ull;  // R_{d0-1}[j-1]
-        // R_{d0-1}[j] at [(j-1) * 64] (read only when d0 > 0)
-        const uint64_t *below = mine + (int64_t)max(d0 - 1, 0) * 64 * 64;
-        uint64_t *col = mine + (int64_t)d0 * 64 * 64;
-        for (int32_t j = 1; j <= b; ++j) {
-          const uint64_t pmc = pick(pm, base_at(tlo, thi, j));
-          const uint64_t lowc = d0 > 0 ? below[(j - 1) * 64] : 0ull;  // R_{d0-1}[j]
-          uint64_t old_lo = pp, new_lo = lowc;  // the level below at j - 1 and at j
-#pragma unroll
-          for (int q = 0; q < LB; ++q) {
-            const int32_t d = d0 + q;
-            // [D(0, j - 1) <= d]
-            uint64_t nv = ((v[q] << 1) | ((!anchored || j - 1 <= d) ? 1ull : 0ull)) & pmc;
-            if (d > 0) {
-              // substitution | insertion | deletion; [D(0, j) <= d - 1]
-              // implies [D(0, j - 1) <= d - 1], so one start bit serves both
-              nv |= ((old_lo | new_lo) << 1) | ((!anchored || j - 1 <= d - 1) ? 1ull : 0ull) | old_lo;
-            }
-            nv &= am;
-            old_lo = v[q];
-            new_lo = nv;
-            v[q] = nv;
-            col[((int64_t)q * 64 + j - 1) * 64] = nv;
-          }
-          pp = lowc;
-        }
-#pragma unroll
-        for (int q = 0; q < LB; ++q)
-          if (dist < 0 && d0 + q <= lw && ((v[q] >> (a - 1)) & 1ull)) dist = d0 + q;
-      }
+      // ---- the window's distance, from vertical deltas alone ----
+      int32_t dist = window_distance(pm, tlo, thi, a, b, anchored);
+      if (dist > lw) dist = -1;
       if (dist < 0) {
         rej = true;
         break;
@@ -198,46 +224,68 @@ __global__ __launch_bounds__(256) void k_genasm(Seqs S, Outs O, int32_t k, int32
         me = ne = 0;
         break;
       }
+      // ---- status vectors of the levels the traceback reads, 0..dist-1,
+      // LB levels per sweep over the text ----
+      for (int32_t d0 = 0; d0 < dist; d0 += LB) {
+        uint64_t v[LB];  // R_{d0+q}[j-1]; bits at and above a are never read
+#pragma unroll
+        for (int q = 0; q < LB; ++q) v[q] = anchored ? low_bits(d0 + q) : ~0ull;
+        uint64_t pp = d0 > 0 ? (anchored ? low_bits(d0 - 1) : ~0ull) : 0ull;  // R_{d0-1}[j-1]
+        // R_{d0-1}[j], read (only when d0 > 0) JB positions ahead of use
+        uint64_t nxt[JB];
+#pragma unroll
+        for (int u = 0; u < JB; ++u) nxt[u] = slot.ld((d0 > 0 && u < b) ? slot_off(d0 - 1, u + 1, lane) : OFF_NONE);
+        for (int32_t j0 = 1; j0 <= b; j0 += JB) {
+          uint64_t cur[JB];
+#pragma unroll
+          for (int u = 0; u < JB; ++u) {
+            cur[u] = nxt[u];
+            const int32_t jn = j0 + JB + u;  // next chunk's position
+            nxt[u] = slot.ld((d0 > 0 && jn <= b) ? slot_off(d0 - 1, jn, lane) : OFF_NONE);
+          }
+          // positions past b (the last chunk of a short window) compute
+          // values nobody reads and store nothing
+#pragma unroll
+          for (int u = 0; u < JB; ++u) {
+            const int32_t j = j0 + u;
+            const uint64_t pmc = pick(pm, base_at(tlo, thi, j));
+            uint64_t old_lo = pp, new_lo = cur[u];  // the level below at j - 1 and at j
+#pragma unroll
+            for (int q = 0; q < LB; ++q) {
+              const int32_t d = d0 + q;
+              // [D(0, j - 1) <= d]
+              uint64_t nv = ((v[q] << 1) | ((!anchored || j - 1 <= d) ? 1ull : 0ull)) & pmc;
+              if (d > 0) {
+                // substitution | insertion | deletion; [D(0, j) <= d - 1]
+                // implies [D(0, j - 1) <= d - 1], so one start bit serves both
+                nv |= ((old_lo | new_lo) << 1) | ((!anchored || j - 1 <= d - 1) ? 1ull : 0ull) | old_lo;
+              }
+              old_lo = v[q];
+              new_lo = nv;
+              v[q] = nv;
+              slot.st(nv, (d < dist && j <= b) ? slot_off(d, j, lane) : OFF_NONE);
+            }
+            pp = cur[u];
+          }
+        }
+      }
       // ---- traceback over the stored levels ----
       int32_t i = a, j = b, d = dist;
       auto R = [&](int32_t dd, int32_t jj) -> uint64_t {  // R_dd[jj]
-        if (jj == 0) return anchored ? (low_bits(dd) & am) : am;
-        return mine[((int64_t)max(dd, 0) * 64 + jj - 1) * 64];
+        if (jj == 0) return anchored ? low_bits(dd) : ~0ull;
+        return slot.ld(slot_off(dd, jj, lane));
       };
       // [D(ii - 1, jj) <= dd] from v = R_dd[jj] (ii >= 1)
       auto up = [&](uint64_t v, int32_t dd, int32_t jj, int32_t ii) -> bool {
         if (ii == 1) return !anchored || jj <= dd;
         return (v >> (ii - 2)) & 1ull;
       };
-      for (;;) {
-        if (anchored) {
-          if (i == 0 && j == 0) break;
-        } else if (a - i >= GC || b - j >= GC || i == 0 || j == 0) {
-          break;
-        }
-        uint32_t op;
-        if (i == 0) {
-          op = OP_D;
-        } else if (j == 0) {
-          op = OP_I;
-        } else {
-          const bool eq = (pick(pm, base_at(tlo, thi, j)) >> (i - 1)) & 1ull;
-          const uint64_t r1 = d > 0 ? R(d - 1, j - 1) : 0ull;
-          const bool del = d > 0 && ((r1 >> (i - 1)) & 1ull);
-          if (prev == OP_I && d > 0 && up(R(d - 1, j), d - 1, j, i)) {
-            op = OP_I;
-          } else if (prev == OP_D && del) {
-            op = OP_D;
-          } else if (eq && up(R(d, j - 1), d, j - 1, i)) {
-            op = OP_EQ;
-          } else if (d > 0 && up(r1, d - 1, j - 1, i)) {
-            op = OP_X;
-          } else if (d > 0 && up(R(d - 1, j), d - 1, j, i)) {
-            op = OP_I;
-          } else {
-            op = OP_D;
-          }
-        }
+      // a window other than the final one stops after GC bases of either
+      // sequence or at its first row or column
+      auto stop = [&]() -> bool {
+        return anchored ? (i == 0 && j == 0) : (a - i >= GC || b - j >= GC || i == 0 || j == 0);
+      };
+      auto apply = [&](uint32_t op) {
         if (op != OP_EQ) {
           d -= 1;
           used += 1;
@@ -246,6 +294,48 @@ __global__ __launch_bounds__(256) void k_genasm(Seqs S, Outs O, int32_t k, int32
         if (op != OP_I) --j;
         put(op, 1, (int64_t)(me - a + i) + (ne - b + j) + 2);
         prev = op;
+      };
+      // In rounds: every lane first takes the steps that need no stored
+      // vector, then the lanes at a decision read theirs together (one memory
+      // wait per round for the wavefront rather than one per step).
+      for (;;) {
+        bool done = false;
+        for (;;) {
+          if (stop()) {
+            done = true;
+            break;
+          }
+          uint32_t op;
+          if (i == 0) {
+            op = OP_D;
+          } else if (j == 0) {
+            op = OP_I;
+          } else if (prev != OP_I && prev != OP_D && ((pick(pm, base_at(tlo, thi, j)) >> (i - 1)) & 1ull)) {
+            // The walk only visits cells whose distance equals its budget d
+            // (it starts at the window's distance and every op keeps to an
+            // optimal continuation).  Adjacent cells of an edit-distance
+            // table differ by at most one and D(i-1, j-1) <= D(i, j), so
+            // where the bases match D(i-1, j-1) = d: '=' is available.
+            op = OP_EQ;
+          } else {
+            break;
+          }
+          apply(op);
+        }
+        if (done) break;
+        const uint64_t ri = d > 0 ? R(d - 1, j) : 0ull;      // [D(., j) <= d - 1]
+        const uint64_t rd = d > 0 ? R(d - 1, j - 1) : 0ull;  // [D(., j - 1) <= d - 1]
+        const bool eq = (pick(pm, base_at(tlo, thi, j)) >> (i - 1)) & 1ull;
+        const bool ins = d > 0 && up(ri, d - 1, j, i);
+        const bool del = d > 0 && ((rd >> (i - 1)) & 1ull);
+        uint32_t op;
+        if (prev == OP_I && ins) op = OP_I;
+        else if (prev == OP_D && del) op = OP_D;
+        else if (eq) op = OP_EQ;
+        else if (d > 0 && up(rd, d - 1, j - 1, i)) op = OP_X;
+        else if (ins) op = OP_I;
+        else op = OP_D;
+        apply(op);
       }
       me -= a - i;
       ne -= b - j;

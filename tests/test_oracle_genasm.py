@@ -147,6 +147,25 @@ def test_empty_sides():
     assert genasm_pair(_c(""), _c("ACG"), 3)[0] == 0
 
 
+# ------------------------------------------------------------ work counters
+
+
+def test_work_counters():
+    rng = np.random.default_rng(13)
+    # identical 150-base pair: windows end at 150, 110, 70 (each commits 40
+    # '=' ops) and the final one covers 30 bases; every distance is 0, so the
+    # updates are 64 + 64 + 64 + 30
+    p = rng.integers(0, 4, 150).astype(np.uint8)
+    assert genasm_pair(p, p, stats=True)[3] == {"windows": 4, "updates": 222, "tb_steps": 150}
+    # one window: (Levenshtein + 1) x n updates, one step per op
+    for _ in range(30):
+        a, b = _rand_pair(rng, int(rng.integers(1, 60)), 0.2)
+        st, sc, runs, c = genasm_pair(a, b, stats=True)
+        assert c == {"windows": 1, "updates": (lev(a, b) + 1) * len(b), "tb_steps": sum(r >> 4 for r in runs)}
+    # an empty side aligns no window
+    assert genasm_pair(_c(""), _c("ACG"), stats=True)[3] == {"windows": 0, "updates": 0, "tb_steps": 0}
+
+
 # ------------------------------------------------------------ windowed pairs
 
 
@@ -275,6 +294,7 @@ MUTANTS = {
     "no gap-extension preference": ("if (prev == G_I && w.In[c]) op = G_I;", "if (0) op = G_I;"),
     "commit length off by one": ("const int32_t C = W - Ov;", "const int32_t C = W - Ov + 1;"),
     "free start taken as anchored": ("const int anchored = me <= W && ne <= W;", "const int anchored = 1;"),
+    "updates without level 0": ("stats[1] += (int64_t)(d + 1) * b;", "stats[1] += (int64_t)d * b;"),
 }
 
 
@@ -293,7 +313,10 @@ def test_planted_mistakes_fail(tmp_path, name):
     h = oracle.bind(so)
     caught = False
     try:
+        ident = np.random.default_rng(13).integers(0, 4, 150).astype(np.uint8)
         if genasm_pair(_c("AAC"), _c("A"), handle=h) != (0, 2, [16, 34]):
+            caught = True
+        elif genasm_pair(ident, ident, handle=h, stats=True)[3] != {"windows": 4, "updates": 222, "tb_steps": 150}:
             caught = True
         elif genasm_pair(_c("ACGTA"), _c("ACTA"), -1, 3, 1, handle=h) != (0, 1, [32, 18, 32]):
             caught = True
