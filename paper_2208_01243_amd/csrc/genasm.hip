@@ -60,10 +60,13 @@ __device__ __forceinline__ uint64_t low_bits(int32_t q) {
   return q >= 64 ? ~0ull : (q <= 0 ? 0ull : ((1ull << q) - 1ull));
 }
 
-// Masks of the a pattern bases from s0: bit q of pm[c] = [base s0 + q == c].
+// Masks of the a pattern bases from s0: bit q of pm[c] = [base s0 + q == c];
+// lo / hi receive the bases themselves (2-bit codes of window positions
+// 1..32 and 33..64).
 __device__ __forceinline__ void pattern_masks(const uint64_t *s, int64_t nw, int64_t s0, int32_t a,
-                                              uint64_t pm[4]) {
-  const uint64_t lo = dev::window32(s, nw, s0), hi = dev::window32(s, nw, s0 + 32);
+                                              uint64_t pm[4], uint64_t &lo, uint64_t &hi) {
+  lo = dev::window32(s, nw, s0);
+  hi = dev::window32(s, nw, s0 + 32);
   const uint64_t am = low_bits(a);
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
@@ -72,6 +75,15 @@ __device__ __forceinline__ void pattern_masks(const uint64_t *s, int64_t nw, int
     const uint64_t zl = ~(xl | (xl >> 1)) & dev::K55, zh = ~(xh | (xh >> 1)) & dev::K55;
     pm[c] = (((uint64_t)dev::even_bits(zh) << 32) | dev::even_bits(zl)) & am;
   }
+}
+
+// The 32 bases of a window ending at position q (1-based; bases lo = 1..32,
+// hi = 33..64), position q in the top two bits; positions before 1 read 0.
+__device__ __forceinline__ uint64_t tail32(uint64_t lo, uint64_t hi, int32_t q) {
+  const int32_t sh = 2 * (q - 32);
+  if (sh <= 0) return sh == 0 ? lo : (lo << (-sh));
+  if (sh >= 64) return hi;
+  return (lo >> sh) | (hi << (64 - sh));
 }
 
 // text base j (1-based) of a window whose bases are lo (1..32), hi (33..64)
@@ -85,31 +97,58 @@ __device__ __forceinline__ uint64_t pick(const uint64_t pm[4], uint32_t c) {
   return (c & 2u) ? b : a;
 }
 
-// A wavefront's slot through a buffer resource: entry (d, j) of lane l at
-// byte ((d * 64 + j - 1) * 64 + l) * 8.  Raw buffer accesses at or past the
-// resource's size are dropped (stores) or read zero (loads), so a lane that
-// must not store passes OFF_NONE instead of branching around the store.
+// A wavefront's slot, reached through a buffer resource.  Raw buffer
+// accesses at or past the resource's size are dropped (stores) or read zero
+// (loads), so a lane that must not store passes OFF_NONE instead of
+// branching around the store.  Byte layout (L levels):
+//   narrow: entry (d, j) of lane l, 32 bits at ((d * 64 + j - 1) * 64 + l) * 4:
+//           bits j + delta - 16 .. j + delta + 15 of R_d[j] (delta = a - b),
+//           all the traceback reads when the window's distance is <= 14;
+//   wide:   the same entries as whole 64-bit vectors, at L * 16 KiB + 8 x
+//           that index, for wavefronts with a window of distance > 14;
+//   carry:  two rows of 64 64-bit vectors per lane, at L * 48 KiB: a sweep's
+//           top level, the level below of the next sweep (alternating).
 constexpr uint32_t OFF_NONE = 0x80000000u;
 constexpr int32_t BUF_FLAGS = 0x00027000;  // word 3 of a raw CDNA buffer resource (32-bit format)
+constexpr int32_t NARROW_MAX = 14;         // largest distance the 32-bit slices serve
 
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 struct Slot {
   __amdgpu_buffer_rsrc_t rs;
-  __device__ __forceinline__ uint64_t ld(uint32_t off) const {
+  uint32_t wide_base, carry_base;
+  __device__ __forceinline__ uint64_t ld64(uint32_t off) const {
     const u32x2 r = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
     return ((uint64_t)r.y << 32) | r.x;
   }
-  __device__ __forceinline__ void st(uint64_t v, uint32_t off) const {
+  __device__ __forceinline__ void st64(uint64_t v, uint32_t off) const {
     u32x2 w;
     w.x = (uint32_t)v;
     w.y = (uint32_t)(v >> 32);
     __builtin_amdgcn_raw_buffer_store_b64(w, rs, off, 0, 0);
   }
+  __device__ __forceinline__ uint32_t ld32(uint32_t off) const {
+    return __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0);
+  }
+  __device__ __forceinline__ void st32(uint32_t v, uint32_t off) const {
+    __builtin_amdgcn_raw_buffer_store_b32(v, rs, off, 0, 0);
+  }
+  __device__ __forceinline__ static uint32_t entry(int32_t d, int32_t j, int lane) {
+    return (uint32_t)((d * 64 + j - 1) * 64 + lane);
+  }
+  __device__ __forceinline__ uint32_t narrow_off(int32_t d, int32_t j, int lane) const { return entry(d, j, lane) * 4u; }
+  __device__ __forceinline__ uint32_t wide_off(int32_t d, int32_t j, int lane) const {
+    return wide_base + entry(d, j, lane) * 8u;
+  }
+  __device__ __forceinline__ uint32_t carry_off(int32_t par, int32_t j, int lane) const {
+    return carry_base + entry(par, j, lane) * 8u;
+  }
 };
 
-__device__ __forceinline__ uint32_t slot_off(int32_t d, int32_t j, int lane) {
-  return (uint32_t)((d * 64 + j - 1) * 64 + lane) * 8u;
+// bits lo .. lo + 31 of v (bits outside 0..63 read 0)
+__device__ __forceinline__ uint32_t slice32(uint64_t v, int32_t lo) {
+  if (lo >= 64 || lo <= -32) return 0u;
+  return (uint32_t)(lo >= 0 ? (v >> lo) : (v << (-lo)));
 }
 
 // D(a, b) of a window: fewest edits aligning its a pattern bases (masks pm)
@@ -138,14 +177,22 @@ __device__ __forceinline__ int32_t window_distance(const uint64_t pm[4], uint64_
   return (anchored ? b : 0) + __popcll(pv & am) - __popcll(mv & am);
 }
 
+// words of a 256-thread block's slots: per wavefront, narrow entries (4
+// bytes), wide entries (8 bytes) and two carry rows (8 bytes)
+__host__ __device__ __forceinline__ int64_t block_words(int32_t levels) {
+  return (int64_t)4 * ((int64_t)levels * 64 * 64 * 12 + 2 * 64 * 64 * 8) / 8;
+}
+
 __global__ __launch_bounds__(256) void k_genasm(Seqs S, Outs O, int32_t k, int32_t want_cigar, Work Wk,
                                                 uint64_t *store, int32_t levels) {
   const int lane = threadIdx.x & 63;
   // wavefront-uniform (kept in scalar registers, as the slot's resource must be)
   const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   Slot slot;
-  slot.rs = __builtin_amdgcn_make_buffer_rsrc(store + wave * (int64_t)levels * 64 * 64, 0, levels * 64 * 64 * 8,
-                                              BUF_FLAGS);
+  slot.rs = __builtin_amdgcn_make_buffer_rsrc(store + wave * (block_words(levels) / 4), 0,
+                                              (int32_t)(block_words(levels) / 4 * 8), BUF_FLAGS);
+  slot.wide_base = (uint32_t)levels * 64 * 64 * 4;
+  slot.carry_base = (uint32_t)levels * 64 * 64 * 12;
   const int64_t count = Wk.count ? (int64_t)(*(volatile const int32_t *)Wk.count) : Wk.n;
   // a wavefront the work can never reach leaves before touching the counter
   if (wave * 64 >= count) return;
@@ -206,8 +253,8 @@ __global__ __launch_bounds__(256) void k_genasm(Seqs S, Outs O, int32_t k, int32
     while (live && me > 0 && ne > 0) {
       const bool anchored = me <= GW && ne <= GW;
       const int32_t a = min(GW, me), b = min(GW, ne);
-      uint64_t pm[4];
-      pattern_masks(pat, pnw, me - a, a, pm);
+      uint64_t pm[4], plo, phi;
+      pattern_masks(pat, pnw, me - a, a, pm, plo, phi);
       const uint64_t tlo = dev::window32(txt, tnw, ne - b), thi = dev::window32(txt, tnw, ne - b + 32);
       int32_t lw = max(a, b);
       if (k >= 0) lw = min(lw, k - used);
@@ -226,22 +273,31 @@ __global__ __launch_bounds__(256) void k_genasm(Seqs S, Outs O, int32_t k, int32
       }
       // ---- status vectors of the levels the traceback reads, 0..dist-1,
       // LB levels per sweep over the text ----
+      // the traceback of a window other than the final one reads positions
+      // j >= b - GC only; a wavefront with a window of distance > 14 keeps
+      // whole vectors
+      const int32_t jmin = anchored ? 1 : max(1, b - GC);
+      const int32_t delta = a - b;
+      const bool wide = __any(dist > NARROW_MAX);
       for (int32_t d0 = 0; d0 < dist; d0 += LB) {
         uint64_t v[LB];  // R_{d0+q}[j-1]; bits at and above a are never read
 #pragma unroll
         for (int q = 0; q < LB; ++q) v[q] = anchored ? low_bits(d0 + q) : ~0ull;
         uint64_t pp = d0 > 0 ? (anchored ? low_bits(d0 - 1) : ~0ull) : 0ull;  // R_{d0-1}[j-1]
-        // R_{d0-1}[j], read (only when d0 > 0) JB positions ahead of use
+        // R_{d0-1}[j] from the previous sweep's carry row, read (only when
+        // d0 > 0) JB positions ahead of use
+        const int32_t par = (d0 / LB) & 1;
         uint64_t nxt[JB];
 #pragma unroll
-        for (int u = 0; u < JB; ++u) nxt[u] = slot.ld((d0 > 0 && u < b) ? slot_off(d0 - 1, u + 1, lane) : OFF_NONE);
+        for (int u = 0; u < JB; ++u)
+          nxt[u] = slot.ld64((d0 > 0 && u < b) ? slot.carry_off(par ^ 1, u + 1, lane) : OFF_NONE);
         for (int32_t j0 = 1; j0 <= b; j0 += JB) {
           uint64_t cur[JB];
 #pragma unroll
           for (int u = 0; u < JB; ++u) {
             cur[u] = nxt[u];
             const int32_t jn = j0 + JB + u;  // next chunk's position
-            nxt[u] = slot.ld((d0 > 0 && jn <= b) ? slot_off(d0 - 1, jn, lane) : OFF_NONE);
+            nxt[u] = slot.ld64((d0 > 0 && jn <= b) ? slot.carry_off(par ^ 1, jn, lane) : OFF_NONE);
           }
           // positions past b (the last chunk of a short window) compute
           // values nobody reads and store nothing
@@ -250,6 +306,7 @@ __global__ __launch_bounds__(256) void k_genasm(Seqs S, Outs O, int32_t k, int32
             const int32_t j = j0 + u;
             const uint64_t pmc = pick(pm, base_at(tlo, thi, j));
             uint64_t old_lo = pp, new_lo = cur[u];  // the level below at j - 1 and at j
+            const bool keep = j <= b && j >= jmin;
 #pragma unroll
             for (int q = 0; q < LB; ++q) {
               const int32_t d = d0 + q;
@@ -263,17 +320,29 @@ __global__ __launch_bounds__(256) void k_genasm(Seqs S, Outs O, int32_t k, int32
               old_lo = v[q];
               new_lo = nv;
               v[q] = nv;
-              slot.st(nv, (d < dist && j <= b) ? slot_off(d, j, lane) : OFF_NONE);
+              const bool st = keep && d < dist;
+              if (wide)
+                slot.st64(nv, st ? slot.wide_off(d, j, lane) : OFF_NONE);
+              else
+                slot.st32(slice32(nv, j + delta - 16), st ? slot.narrow_off(d, j, lane) : OFF_NONE);
             }
+            // the top level, for the next sweep of a lane that needs one
+            slot.st64(v[LB - 1], (j <= b && d0 + LB < dist) ? slot.carry_off(par, j, lane) : OFF_NONE);
             pp = cur[u];
           }
         }
       }
       // ---- traceback over the stored levels ----
       int32_t i = a, j = b, d = dist;
-      auto R = [&](int32_t dd, int32_t jj) -> uint64_t {  // R_dd[jj]
+      // R_dd[jj] as stored, shifted so that bit p of R_dd[jj] is bit p of the
+      // result for every bit the traceback reads
+      auto R = [&](int32_t dd, int32_t jj) -> uint64_t {
         if (jj == 0) return anchored ? low_bits(dd) : ~0ull;
-        return slot.ld(slot_off(dd, jj, lane));
+        if (wide) return slot.ld64(slot.wide_off(dd, jj, lane));
+        const int32_t lo = jj + delta - 16;
+        const uint64_t w = slot.ld32(slot.narrow_off(dd, jj, lane));
+        if (lo >= 64 || lo <= -32) return 0ull;  // no bit the walk reads
+        return lo >= 0 ? (w << lo) : (w >> (-lo));
       };
       // [D(ii - 1, jj) <= dd] from v = R_dd[jj] (ii >= 1)
       auto up = [&](uint64_t v, int32_t dd, int32_t jj, int32_t ii) -> bool {
@@ -305,22 +374,32 @@ __global__ __launch_bounds__(256) void k_genasm(Seqs S, Outs O, int32_t k, int32
             done = true;
             break;
           }
-          uint32_t op;
           if (i == 0) {
-            op = OP_D;
-          } else if (j == 0) {
-            op = OP_I;
-          } else if (prev != OP_I && prev != OP_D && ((pick(pm, base_at(tlo, thi, j)) >> (i - 1)) & 1ull)) {
-            // The walk only visits cells whose distance equals its budget d
-            // (it starts at the window's distance and every op keeps to an
-            // optimal continuation).  Adjacent cells of an edit-distance
-            // table differ by at most one and D(i-1, j-1) <= D(i, j), so
-            // where the bases match D(i-1, j-1) = d: '=' is available.
-            op = OP_EQ;
-          } else {
-            break;
+            apply(OP_D);
+            continue;
           }
-          apply(op);
+          if (j == 0) {
+            apply(OP_I);
+            continue;
+          }
+          if (prev == OP_I || prev == OP_D) break;
+          // The walk only visits cells whose distance equals its budget d
+          // (it starts at the window's distance and every op keeps to an
+          // optimal continuation).  Adjacent cells of an edit-distance table
+          // differ by at most one and D(i-1, j-1) <= D(i, j), so where the
+          // bases match D(i-1, j-1) = d and '=' is available: a run of
+          // matching bases along the diagonal is taken at once, up to where
+          // the window stops (or its first row or column).
+          const uint64_t x = tail32(plo, phi, i) ^ tail32(tlo, thi, j);
+          int32_t r = x ? (__clzll(x) >> 1) : 32;
+          int32_t lim = min(i, j);
+          if (!anchored) lim = min(lim, min(GC - (a - i), GC - (b - j)));
+          r = min(r, lim);
+          if (r == 0) break;
+          i -= r;
+          j -= r;
+          put(OP_EQ, (uint32_t)r, (int64_t)(me - a + i) + (ne - b + j) + 2);
+          prev = OP_EQ;
         }
         if (done) break;
         const uint64_t ri = d > 0 ? R(d - 1, j) : 0ull;      // [D(., j) <= d - 1]
@@ -364,7 +443,7 @@ int32_t genasm_levels(int32_t max_score) {
   return (top + 1 + LB - 1) / LB * LB;
 }
 
-int64_t genasm_block_words(int32_t levels) { return (int64_t)4 * levels * 64 * 64; }
+int64_t genasm_block_words(int32_t levels) { return block_words(levels); }
 
 hipError_t launch_genasm(const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk, uint64_t *store,
                          int32_t levels, int32_t nblocks, hipStream_t s) {
