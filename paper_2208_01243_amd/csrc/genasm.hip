@@ -279,6 +279,10 @@ __global__ __launch_bounds__(256) void k_genasm(Seqs S, Outs O, int32_t k, int32
       const int32_t jmin = anchored ? 1 : max(1, b - GC);
       const int32_t delta = a - b;
       const bool wide = __any(dist > NARROW_MAX);
+      // wavefront-uniform: the first position any lane stores (1, or GC
+      // positions before the end of a full window when every lane's window
+      // is one), so that earlier positions issue no store at all
+      const int32_t jlo = __any(jmin < GW - GC) ? 1 : GW - GC;
       for (int32_t d0 = 0; d0 < dist; d0 += LB) {
         uint64_t v[LB];  // R_{d0+q}[j-1]; bits at and above a are never read
 #pragma unroll
@@ -287,6 +291,12 @@ __global__ __launch_bounds__(256) void k_genasm(Seqs S, Outs O, int32_t k, int32
         // R_{d0-1}[j] from the previous sweep's carry row, read (only when
         // d0 > 0) JB positions ahead of use
         const int32_t par = (d0 / LB) & 1;
+        // wavefront-uniform: which of this sweep's levels some lane keeps,
+        // and whether some lane needs a further sweep
+        bool need[LB];
+#pragma unroll
+        for (int q = 0; q < LB; ++q) need[q] = __any(d0 + q < dist);
+        const bool carry = __any(d0 + LB < dist);
         uint64_t nxt[JB];
 #pragma unroll
         for (int u = 0; u < JB; ++u)
@@ -320,14 +330,16 @@ __global__ __launch_bounds__(256) void k_genasm(Seqs S, Outs O, int32_t k, int32
               old_lo = v[q];
               new_lo = nv;
               v[q] = nv;
-              const bool st = keep && d < dist;
-              if (wide)
-                slot.st64(nv, st ? slot.wide_off(d, j, lane) : OFF_NONE);
-              else
-                slot.st32(slice32(nv, j + delta - 16), st ? slot.narrow_off(d, j, lane) : OFF_NONE);
+              if (need[q] && j >= jlo) {
+                const bool st = keep && d < dist;
+                if (wide)
+                  slot.st64(nv, st ? slot.wide_off(d, j, lane) : OFF_NONE);
+                else
+                  slot.st32(slice32(nv, j + delta - 16), st ? slot.narrow_off(d, j, lane) : OFF_NONE);
+              }
             }
             // the top level, for the next sweep of a lane that needs one
-            slot.st64(v[LB - 1], (j <= b && d0 + LB < dist) ? slot.carry_off(par, j, lane) : OFF_NONE);
+            if (carry) slot.st64(v[LB - 1], (j <= b && d0 + LB < dist) ? slot.carry_off(par, j, lane) : OFF_NONE);
             pp = cur[u];
           }
         }
