@@ -52,7 +52,7 @@ namespace {
 
 constexpr int32_t GW = 64;       // window bases
 constexpr int32_t GC = GW - 24;  // bases a window other than the final one commits
-constexpr int32_t LB = 4;        // edit levels built per sweep over a window's text
+constexpr int32_t LB = 6;        // edit levels built per sweep over a window's text
 constexpr int32_t JB = 8;        // text positions whose lower-level vectors are read ahead
 constexpr uint32_t OP_NONE = 4;
 
