@@ -60,9 +60,11 @@ PEAK_HBM_GBS = 8000.0
 # kernel source they were taken on (first 16 hex of its SHA-256)
 MEASURED_TRAFFIC = {("swg150", "k_band16<32>"): ("32a97daf6917c56a", 3.0790e9),
                     ("wfa_mixed", "k_wfa_lds"): ("0c615b4af52df5a5", 2.535e12),
-                    ("wfa250", "k_wfa_score16"): ("16a875715b12058b", 4.297e9)}
+                    ("wfa250", "k_wfa_score16"): ("16a875715b12058b", 4.297e9),
+                    ("genasm150", "k_genasm"): ("01ff405ac50a6d6c", 5.05e9)}
 KERNEL_SOURCE = {"k_band16<32>": "dp_band16.hip", "k_band<32>": "dp_band.hip",
-                 "k_wfa_score16": "wfa.hip", "k_wfa_score": "wfa.hip", "k_wfa_lds": "wfa_lds.hip"}
+                 "k_wfa_score16": "wfa.hip", "k_wfa_score": "wfa.hip", "k_wfa_lds": "wfa_lds.hip",
+                 "k_genasm": "genasm.hip"}
 
 WORKLOAD_TEXT = {
     "swg150": "Gotoh 4/6/2 global, 1,000,000 pairs x 150 bp, 4% error (1/3 sub, ins, del), "
@@ -214,6 +216,7 @@ def roofline(run, phases, stats, steps):
         ms, launches = phases["genasm"]
         ms /= max(1, launches)
         u = genasm_units(run.name) if run.n == w["total"] else None
+        meas = MEASURED_TRAFFIC.get((run.name, "k_genasm"))
         out = {"kernel": "k_genasm", "avg_launch_ms": round(ms, 4), "bound": "alu", "achieved": None,
                "peak": round(PEAK_INT32_TOPS, 1), "unit": "Tops/s (int32)", "frac": None, "traffic": None,
                "ops_per_unit": {"status-vector update": GENASM_OPS_PER_UPDATE,
@@ -231,6 +234,8 @@ def roofline(run, phases, stats, steps):
             top = hbm if hbm["frac"] > alu["frac"] else alu
             out.update(top)
             out["bound"] = "hbm" if top is hbm else "alu"
+            if meas and meas[0] == src_hash("k_genasm"):
+                out["traffic"] = meas[1]
             out.update({"alu": alu, "hbm": hbm,
                         "units_per_launch": {"updates": u["updates"], "tb_steps": u["tb_steps"],
                                              "windows": u["windows"], "bases": u["bases"]},
