@@ -341,7 +341,12 @@ aim_status aim_timing_reset(aim_context *ctx);
  *     wfa_wide counts the pairs that outgrew them all (HBM-ring pass);
  *   prefilter_rejected: pairs rejected by the pre-alignment filter before
  *     any aligner ran (see aim_prefilter);
- *   wfa_adaptive_dropped: diagonals the WFA-adaptive reduction removed. */
+ *   wfa_adaptive_dropped: diagonals the WFA-adaptive reduction removed;
+ *   wfa_long_pairs: accepted WFA pairs whose full store passes the largest
+ *     class, walked by the memory-bounded long pass (checkpoints of the
+ *     wavefront ring and a window of recomputed origin codes);
+ *   wfa_long_failed: of those, pairs left CIGAR_OVERFLOW (a score or one
+ *     score's codes past that pass's caps, or no room for its slots). */
 typedef struct {
   int64_t n_pairs;
   int32_t band_escalated, band_escalated2;
@@ -353,6 +358,7 @@ typedef struct {
   int32_t wfa_class_window[4];
   int32_t prefilter_rejected;
   int64_t wfa_adaptive_dropped;
+  int32_t wfa_long_pairs, wfa_long_failed;
 } aim_call_stats;
 aim_status aim_last_call_stats(aim_context *ctx, aim_call_stats *out);
 

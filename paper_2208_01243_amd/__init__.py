@@ -77,7 +77,8 @@ class CallStats(ctypes.Structure):
     _fields_ = [("n_pairs", i64), ("band_escalated", i32), ("band_escalated2", i32), ("wfa_wide", i32),
                 ("wfa_walk_failed", i32), ("wfa_walk_skipped", i32), ("full_store", i32 * 4),
                 ("cigar_reruns", i32), ("wfa_window", i32), ("wfa_class_pairs", i32 * 4),
-                ("wfa_class_window", i32 * 4), ("prefilter_rejected", i32), ("wfa_adaptive_dropped", i64)]
+                ("wfa_class_window", i32 * 4), ("prefilter_rejected", i32), ("wfa_adaptive_dropped", i64),
+                ("wfa_long_pairs", i32), ("wfa_long_failed", i32)]
 
 
 class AimError(RuntimeError):

@@ -219,7 +219,40 @@ struct WfaLaunch {
   // for codes that were kept and read back intact) or because their codes
   // were not kept (walk_skip: more scores than the code slot holds)
   int32_t *walk_fail, *walk_skip;
+  // accepted pairs whose full store passes the largest class: appended here
+  // for the memory-bounded pass (nullptr: they get CIGAR_OVERFLOW)
+  int32_t *long_list, *long_count;
 };
+
+// The memory-bounded pass for long pairs (a CIGAR for pairs whose origin codes
+// and full store fit no slot), one workgroup per pair with a slot of
+// slot_words int32 words: the score pass again from s = 0 to the pair's known
+// score, keeping its ring of the last R wavefronts every K scores as a
+// checkpoint (at most ck_cap, K = ceil((score + 1) / ck_cap)) and each score's
+// width; then the walk from the end cell back, recomputing from the
+// checkpoint below the walk's score the origin codes of as many scores as
+// code_cap bytes (and wt_cap table entries) hold, walking them, and again
+// until the start.  Memory per pair: ck_cap rings, one code window and a
+// width per score, instead of every score's codes.
+struct WfaLong {
+  int32_t R;
+  int32_t wcap;       // widest wavefront (2 max_len + 1 bounds every pair)
+  int32_t seq_words;  // LDS staging per sequence (0: read in place)
+  int32_t ck_cap;     // checkpoints per pair
+  int32_t sw_cap;     // scores (width table); a pair with a higher score gets CIGAR_OVERFLOW
+  int32_t wt_cap;     // scores one recompute keeps the codes of
+  int32_t tok_cap;    // walk tokens
+  int64_t code_cap;   // bytes of origin codes per recompute (a multiple of 16)
+  int64_t slot_words;
+  int32_t *slots;
+  int32_t *failed;    // pairs left CIGAR_OVERFLOW (a score or a code row past the caps)
+};
+int64_t wfa_long_slot_words(const WfaLong &L, bool i16);
+constexpr int32_t WGMAX_THREADS = 256;  // workgroup of the long pass
+// nslots workgroups of `threads`; i16: 16-bit ring entries (max_len <=
+// WFA16_MAX_LEN).  Wk.direct: re-run, runs straight into the CIGAR output.
+hipError_t launch_wfa_long(const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk, const WfaLong &L,
+                           int32_t nslots, int32_t threads, bool i16, hipStream_t s);
 
 // One LDS-window class of wide pairs (k_wfa_lds): the last R scores of M and
 // the last e + 1 of I and D are LDS rows of packed 16-bit offsets indexed by
@@ -253,6 +286,7 @@ struct WfaLds {
   // compute another alignment).
   int32_t ad_min, ad_max;
   unsigned long long *ad_dropped;
+  int32_t *long_list, *long_count;  // as in WfaLaunch
 };
 int64_t wfa_ring_words(int32_t W, int32_t MG, int32_t R, int32_t e);
 size_t wfa_lds_bytes(int32_t W, int32_t MG, int32_t R, int32_t e, int32_t seq_words, bool gring);

@@ -118,7 +118,7 @@ struct Scratch {
   Buf order, hist;
   Buf flags, pflag, tflag, pat2, txt2, pat2off, txt2off, nruns, slot, tb32, tb64, full, list2,
       list3, counters, scan_tmp, spill, total, wring, warena1, warena2, warena3, wneed, wlists, pool, pooloff,
-      wbits, wwalk, wlds, wgring, flist, genasm;
+      wbits, wwalk, wlds, wgring, flist, genasm, wlong;
 };
 
 struct aim_graph {
@@ -263,7 +263,7 @@ struct DeviceGuard {
 enum Counter {
   C_T1 = 0, C_T2, C_T3, C_L2, C_L3, C_SPILL, C_SPILL_W,
   C_W1, C_W1G, C_RL, C_FAIL, C_N0, C_N1, C_N2, C_N3, C_P0, C_P1, C_P2, C_P3, C_TB, C_DTB,
-  C_M0, C_M1, C_M2, C_M3, C_WF, C_WS, C_FL, C_FR,
+  C_M0, C_M1, C_M2, C_M3, C_WF, C_WS, C_FL, C_FR, C_LL, C_LW, C_LF,
   C_CL = 32,  // WFA window classes 1..4: list lengths, then their work counters (C_CL + 4)
   C_N = 48
 };
@@ -432,6 +432,32 @@ aim_status run_genasm(aim_context *c, const aim::Seqs &S, const aim::Outs &O, co
   return AIM_OK;
 }
 
+// The memory-bounded long pass of a WFA call (CIGARs wanted): up to 8
+// workgroups, each with a slot of 16 ring checkpoints, a width per score, a
+// code window of 1/64 of the budget (1 to 16 MiB) and the walk tokens,
+// within 1/16 of the budget; none (nslots 0) when one slot does not fit.
+aim_status wfa_long_plan(aim_context *c, int32_t L, const aim::Scoring &P, const aim::WfaPlan &pl, bool i16,
+                         aim::WfaLong &LG, int32_t &nslots) {
+  LG = aim::WfaLong{};
+  nslots = 0;
+  LG.R = pl.R;
+  LG.wcap = 2 * L + 1;
+  LG.seq_words = pl.seq_words;
+  LG.ck_cap = 16;
+  LG.sw_cap = (int32_t)std::min<int64_t>(1 << 20, (int64_t)std::max(P.x, P.o + P.e) * (2 * (int64_t)L + 1) + 2);
+  LG.wt_cap = std::min(LG.sw_cap, 1 << 16);
+  LG.tok_cap = 2 * (2 * L + 1) + 8;
+  LG.code_cap = std::max<int64_t>(1 << 20, std::min<int64_t>(16 << 20, c->limit() / 64)) / 16 * 16;
+  LG.slot_words = aim::wfa_long_slot_words(LG, i16);
+  const int64_t fit = c->limit() / 16 / (LG.slot_words * 4);
+  if (fit < 1) return AIM_OK;
+  nslots = (int32_t)std::min<int64_t>(8, fit);
+  aim_status st = ensure(c, c->sc->wlong, (size_t)LG.slot_words * 4 * nslots);
+  if (st) return st;
+  LG.slots = as<int32_t>(c->sc->wlong);
+  return AIM_OK;
+}
+
 aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const aim::Scoring &Pin,
                    int64_t n, int32_t L, bool plain, int32_t *cnt, const int32_t *order,
                    const int32_t *order_count, const Tune &tu, hipStream_t s) {
@@ -442,7 +468,7 @@ aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const
   if ((st = ensure(c, c->sc->wneed, (size_t)n * 8))) return st;
   // lists: [0] the HBM-ring pass, [1-4] full-store classes, [5] unused,
   // [6-9] LDS-window classes, [10] predicted extents
-  if ((st = ensure(c, c->sc->wlists, (size_t)n * 4 * 11))) return st;
+  if ((st = ensure(c, c->sc->wlists, (size_t)n * 4 * 12))) return st;
   int32_t *lists = as<int32_t>(c->sc->wlists);
   aim::WfaLaunch WL{};
   WL.R = pl.R;
@@ -458,6 +484,18 @@ aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const
   WL.need = as<int64_t>(c->sc->wneed);
   WL.walk_fail = cnt + C_WF;
   WL.walk_skip = cnt + C_WS;
+  // long pairs: the memory-bounded pass, when its slots fit the budget
+  aim::WfaLong LG{};
+  int32_t long_slots = 0;
+  const bool long_i16 = L <= aim::WFA16_MAX_LEN;
+  if (P.want_cigar && !plain) {
+    if ((st = wfa_long_plan(c, L, P, pl, long_i16, LG, long_slots))) return st;
+    if (long_slots > 0) {
+      WL.long_list = lists + (int64_t)n * 11;
+      WL.long_count = cnt + C_LL;
+      LG.failed = cnt + C_LF;
+    }
+  }
   const int32_t slots = (int32_t)std::min<int64_t>(n, (int64_t)c->cus * 8);
   // one wavefront per pair with 16-bit offsets over a window of 64 C diagonals
   int32_t C16 = (int32_t)std::min<int64_t>(4, std::max<int64_t>(1, (pl.wcap + 63) / 64));
@@ -585,6 +623,8 @@ aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const
         D.need_max[q] = WL.need_max[q];
       }
       D.need = WL.need;
+      D.long_list = WL.long_list;
+      D.long_count = WL.long_count;
       D.walk_fail = WL.walk_fail;
       D.walk_skip = WL.walk_skip;
       code_bytes = std::max(code_bytes, (size_t)D.code_slot * cls[k].nslots);
@@ -664,6 +704,11 @@ aim_status run_wfa(aim_context *c, const aim::Seqs &S, const aim::Outs &O, const
         n, (int64_t)c->cus * std::max(1, std::min(20, 160 / std::max(1, tu.wfa_trace_kb))));
     HIP_TRY(aim::launch_wfa_trace(S, O, P, W, T, hbm, k == 0 ? lds_slots : pl.arena_slots[k],
                                   plain ? 64 : pl.threads[k], w16, s));
+  }
+  if (long_slots > 0) {
+    aim::Work W{WL.long_list, cnt + C_LL, n, cnt + C_LW, nullptr, nullptr, 0};
+    Phase ph(c, s, "wfa_long");
+    HIP_TRY(aim::launch_wfa_long(S, O, P, W, LG, long_slots, aim::WGMAX_THREADS, long_i16, s));
   }
   return AIM_OK;
 }
@@ -760,7 +805,7 @@ void aim_destroy(aim_context *c) {
                 &c->own.nruns, &c->own.slot, &c->own.tb32, &c->own.tb64, &c->own.full, &c->own.list2, &c->own.list3,
                 &c->own.counters, &c->own.scan_tmp, &c->own.spill, &c->own.total, &c->own.wring, &c->own.warena1,
                 &c->own.warena2, &c->own.warena3, &c->own.wneed, &c->own.wlists, &c->own.pool, &c->own.pooloff, &c->own.wbits, &c->own.wwalk, &c->own.wlds, &c->own.wgring, &c->own.flist,
-                &c->own.genasm};
+                &c->own.genasm, &c->own.wlong};
   for (Buf *b : all)
     if (b->p) (void)(b->pooled ? hipFreeAsync(b->p, nullptr) : hipFree(b->p));
   (void)hipDeviceSynchronize();
@@ -1093,6 +1138,16 @@ static aim_status align_batch(aim_context *c, const aim_batch *B, int32_t alg, a
     WL.full_in_lds = 0;
     WL.slot_words = pl.need_cap[3];
     WL.need = as<int64_t>(c->sc->wneed);
+    // the memory-bounded pass re-runs any pair, whatever its full store
+    aim::WfaLong LG{};
+    int32_t long_slots = 0;
+    if (!plain && (st = wfa_long_plan(c, L, PW, pl, L <= aim::WFA16_MAX_LEN, LG, long_slots))) return st;
+    if (long_slots > 0) {
+      LG.failed = cnt + C_LF;
+      Phase ph(c, s, "wfa_rerun");
+      HIP_TRY(aim::launch_wfa_long(S, O, PW, WS, LG, long_slots, aim::WGMAX_THREADS, L <= aim::WFA16_MAX_LEN, s));
+      return AIM_OK;
+    }
     if ((st = ensure(c, c->sc->warena3, (size_t)pl.pool_words[3] * 4))) return st;
     const int32_t rslots = (int32_t)std::max<int64_t>(1, pl.pool_words[3] / pl.need_cap[3]);
     Phase ph(c, s, "wfa_rerun");
@@ -1147,6 +1202,8 @@ aim_status aim_last_call_stats(aim_context *c, aim_call_stats *out) {
   unsigned long long dropped = 0;
   HIP_TRY(hipMemcpy(&dropped, c->last_cnt + C_N, sizeof dropped, hipMemcpyDeviceToHost));
   out->wfa_adaptive_dropped = (int64_t)dropped;
+  out->wfa_long_pairs = v[C_LL];
+  out->wfa_long_failed = v[C_LF];
   return AIM_OK;
 }
 

@@ -334,7 +334,7 @@ void k_wfa_score(Seqs S, Outs O, Scoring P, Work Wk, WfaLaunch L, int32_t *hbm) 
           int c = 0;
           while (c < 3 && need > L.need_cap[c]) ++c;
           if (need > L.need_cap[3]) {
-            O.status[p] = ST_OVERFLOW;  // full store larger than any arena class
+            to_long_pass(O, p, L.long_list, L.long_count);  // full store larger than any arena class
           } else {
             const int32_t k = atomicAdd(L.need_count[c], 1);
             L.need_list[c][k] = (int32_t)p;
@@ -588,7 +588,7 @@ __global__ __launch_bounds__(64) void k_wfa_score16(Seqs S, Outs O, Scoring P, W
           int cl = 0;
           while (cl < 3 && need > L.need_cap[cl]) ++cl;
           if (need > L.need_cap[3]) {
-            O.status[p] = ST_OVERFLOW;
+            to_long_pass(O, p, L.long_list, L.long_count);
           } else {
             const int32_t k = atomicAdd(L.need_count[cl], 1);
             L.need_list[cl][k] = (int32_t)p;
@@ -768,7 +768,278 @@ __global__ __launch_bounds__(WGMAX) void k_wfa_trace(Seqs S, Outs O, Scoring P, 
   }
 }
 
+
+// ------------------------------------- long pairs: checkpoints and recompute
+// See WfaLong.  Slot layout (int32 words): the ring (R slots of slot_w), the
+// checkpoints (ck_cap of R slots of slot_w plus R table entries), the width
+// of every score, the code table of one recompute (4 words per score), its
+// codes (code_cap bytes), the walk tokens.
+template <class E>
+__global__ __launch_bounds__(WGMAX) void k_wfa_long(Seqs S, Outs O, Scoring P, Work Wk, WfaLong L) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int32_t sh_pair, sh_res, sh_cs, sh_k, sh_comp, sh_nt, sh_wlo, sh_whi;
+  const int lane = threadIdx.x;
+  const int nthr = blockDim.x;
+  uint64_t *sP = (uint64_t *)smem;
+  uint64_t *sT = sP + L.seq_words;
+  int32_t *tab_ring = (int32_t *)(sT + L.seq_words);  // R entries
+  const int32_t x = P.x, oe = P.o + P.e, e = P.e, R = L.R;
+  const int32_t slot_w = wf_words<E>(3 * L.wcap);
+  const int64_t ckw = (int64_t)R * slot_w + (int64_t)R * ENTRY;  // words per checkpoint
+  int32_t *ring = L.slots + (int64_t)blockIdx.x * L.slot_words;
+  int32_t *ck = ring + (int64_t)R * slot_w;
+  int32_t *wid = ck + (int64_t)L.ck_cap * ckw;
+  int32_t *wtab = wid + L.sw_cap;
+  uint8_t *codes = reinterpret_cast<uint8_t *>(wtab + 4 * (int64_t)L.wt_cap);
+  uint32_t *tok = reinterpret_cast<uint32_t *>(codes + L.code_cap);
+  const int64_t count = Wk.count ? (int64_t)(*(volatile const int32_t *)Wk.count) : Wk.n;
+  // a workgroup the work can never reach leaves before touching the counter
+  if ((int64_t)blockIdx.x >= count) return;
+  auto slot_of = [&](int32_t s2) { return s2 % R; };
+  // live words of ring slot q (per its table entry)
+  auto live = [&](const int32_t *tb, int32_t q) -> int32_t {
+    return (tb[q * ENTRY + 3] & 7) ? wf_words<E>(3 * (tb[q * ENTRY + 1] - tb[q * ENTRY + 0] + 1)) : 0;
+  };
+  for (;;) {
+    __syncthreads();
+    if (lane == 0) sh_pair = atomicAdd(Wk.counter, 1);
+    __syncthreads();
+    const int64_t li = sh_pair;
+    if (li >= count) break;
+    const int64_t p = Wk.idx ? (int64_t)Wk.idx[li] : li;
+    const int32_t m = S.pat_len[p], n = S.txt_len[p];
+    const int32_t sfin = O.score[p] / P.unit;
+    const int64_t pnw = (m + 31) >> 5, tnw = (n + 31) >> 5;
+    const uint64_t *gP = S.pat + S.pat_off[p], *gT = S.txt + S.txt_off[p];
+    const bool staged = pnw <= L.seq_words && tnw <= L.seq_words;
+    if (staged) {
+      stage_seq(sP, gP, pnw);
+      stage_seq(sT, gT, tnw);
+    }
+    // no score of a slot exists before the pass fills it
+    for (int32_t q = lane; q < R; q += nthr) {
+      tab_ring[q * ENTRY + 0] = 0;
+      tab_ring[q * ENTRY + 1] = -1;
+      tab_ring[q * ENTRY + 2] = q * slot_w;
+      tab_ring[q * ENTRY + 3] = 0;
+    }
+    const int32_t K = max(1, (sfin + L.ck_cap) / L.ck_cap);  // checkpoints at 0, K, 2K, ... (<= ck_cap)
+    bool ok = sfin >= 0 && sfin < L.sw_cap;
+    __syncthreads();
+    // one score of the pass: into its ring slot, its table entry, and (when
+    // codes_from <= s) its origin codes at *cbase with its code-table entry
+    auto step = [&](const auto &q, int32_t s, int32_t codes_from, int64_t &cbase) -> bool {
+      const int sl = slot_of(s);
+      int32_t lo = 0, hi = -1;
+      int present;
+      bool overflow = false, fits = true;
+      const int64_t c0 = cbase;
+      if (s == 0) {
+        if (lane == 0) reinterpret_cast<E *>(ring + sl * slot_w)[0] = wf_put<E>(q.ext(m, n, 0, 0));
+        present = 1;
+        lo = hi = 0;
+      } else {
+        const bool keep = s >= codes_from;
+        int32_t cbytes = 0;
+        present = wf_step<E>(s, x, oe, e, m, n, tab_ring, ring, slot_of, ring, sl * slot_w, L.wcap, lo, hi, q,
+                             overflow, keep ? codes + cbase : nullptr, L.code_cap - cbase, &cbytes);
+        if (keep) {
+          if (cbytes < 0) fits = false;
+          else cbase += cbytes;
+        }
+      }
+      __syncthreads();
+      if (lane == 0) {
+        tab_ring[sl * ENTRY + 0] = lo;
+        tab_ring[sl * ENTRY + 1] = hi;
+        tab_ring[sl * ENTRY + 2] = sl * slot_w;
+        tab_ring[sl * ENTRY + 3] = present;
+        if (s >= codes_from && s > 0) {
+          int32_t *t = wtab + 4 * (s - codes_from);
+          t[0] = lo;
+          t[1] = present ? hi : lo - 1;
+          t[2] = (int32_t)c0;
+        }
+      }
+      __syncthreads();
+      return !overflow && fits;
+    };
+    // checkpoint c <-> the ring and its table (live words only)
+    auto save = [&](int32_t c) {
+      int32_t *dst = ck + (int64_t)c * ckw;
+      for (int32_t q = 0; q < R; ++q) {
+        const int32_t w = live(tab_ring, q);
+        for (int32_t t = lane; t < w; t += nthr) dst[(int64_t)q * slot_w + t] = ring[(int64_t)q * slot_w + t];
+      }
+      for (int32_t t = lane; t < R * ENTRY; t += nthr) dst[(int64_t)R * slot_w + t] = tab_ring[t];
+      __syncthreads();
+    };
+    auto restore = [&](int32_t c) {
+      const int32_t *src = ck + (int64_t)c * ckw;
+      // the agent-scope acquire drops L1 lines of these addresses that an
+      // earlier recompute or pair may have left
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      for (int32_t t = lane; t < R * ENTRY; t += nthr) tab_ring[t] = src[(int64_t)R * slot_w + t];
+      __syncthreads();
+      for (int32_t q = 0; q < R; ++q) {
+        const int32_t w = live(tab_ring, q);
+        for (int32_t t = lane; t < w; t += nthr) ring[(int64_t)q * slot_w + t] = src[(int64_t)q * slot_w + t];
+      }
+      __syncthreads();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    };
+    auto run = [&](const auto &q) {
+      // ---- the score pass: widths and checkpoints ----
+      int64_t none = 0;
+      for (int32_t s = 0; ok && s <= sfin; ++s) {
+        if (!step(q, s, INT32_MAX, none)) ok = false;
+        if (lane == 0) {
+          const int32_t sl = slot_of(s);
+          wid[s] = (tab_ring[sl * ENTRY + 3] & 7) ? tab_ring[sl * ENTRY + 1] - tab_ring[sl * ENTRY + 0] + 1 : 0;
+        }
+        if (s % K == 0) save(s / K);
+      }
+      __syncthreads();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      // ---- the walk, a window of recomputed codes at a time ----
+      if (lane == 0) {
+        sh_cs = sfin;
+        sh_k = n - m;
+        sh_comp = 0;
+        sh_nt = 0;
+        sh_wlo = 1;
+        sh_whi = 0;  // no codes yet
+        sh_res = ok ? 0 : -1;
+      }
+      __syncthreads();
+      while (sh_res == 0) {
+        if (lane < 64) {
+          // the token walk of walk_codes, paused when it needs a score
+          // outside the window (run by the first wavefront, lane 0 writes)
+          int32_t cs = sh_cs, k = sh_k, comp = sh_comp, nt = sh_nt, code = -1, res = 0;
+          const int32_t wlo = sh_wlo, whi = sh_whi;
+          auto code_at = [&](int32_t c2, int32_t k2) -> int32_t {
+            const int32_t *t = wtab + 4 * (c2 - wlo);
+            const int32_t lo = t[0], hi = t[1], cb = t[2];
+            if (k2 < lo || k2 > hi) return -1;
+            const uint32_t b = codes[cb + ((k2 - lo) >> 1)];
+            return (int32_t)(((k2 - lo) & 1) ? (b >> 4) : (b & 15u));
+          };
+          for (;;) {
+            if (nt + 2 > L.tok_cap || cs < 0) { res = -1; break; }
+            if (comp == 0) {
+              if (cs == 0) {
+                if (lane == 0) tok[nt] = TOK_M;
+                ++nt;
+                res = k == 0 ? 1 : -1;
+                break;
+              }
+              if (cs < wlo || cs > whi) break;  // pause: codes of cs needed
+              if (lane == 0) tok[nt] = TOK_M;
+              ++nt;
+              code = __builtin_amdgcn_readfirstlane(code_at(cs, k));
+              if (code < 0) { res = -1; break; }
+              const int32_t src = code & 3;
+              if (src == 0) {
+                if (lane == 0) tok[nt] = OP_X;
+                ++nt;
+                cs -= x;
+                code = -1;
+              } else {
+                comp = src;  // I or D of the same cell
+              }
+            } else {
+              if (code < 0) {
+                if (cs < wlo || cs > whi) break;
+                code = __builtin_amdgcn_readfirstlane(code_at(cs, k));
+                if (code < 0) { res = -1; break; }
+              }
+              const bool open = (code >> (comp + 1)) & 1;
+              if (lane == 0) tok[nt] = comp == 1 ? OP_I : OP_D;
+              ++nt;
+              k += comp == 1 ? 1 : -1;
+              if (open) { cs -= oe; comp = 0; } else { cs -= e; }
+              code = -1;
+            }
+          }
+          if (lane == 0) {
+            sh_cs = cs;
+            sh_k = k;
+            sh_comp = comp;
+            sh_nt = nt;
+            sh_res = res;
+            if (res == 0) {
+              // the next window: the checkpoint below cs, then as many of the
+              // scores up to cs as the code area and table hold
+              const int32_t cK = (cs - 1) / K * K;
+              int32_t lo2 = cs;
+              int64_t bytes = (wid[cs] + 1) / 2;
+              if (bytes > L.code_cap) {
+                sh_res = -1;
+              } else {
+                while (lo2 - 1 > cK && cs - lo2 + 2 <= L.wt_cap && bytes + (wid[lo2 - 1] + 1) / 2 <= L.code_cap) {
+                  --lo2;
+                  bytes += (wid[lo2] + 1) / 2;
+                }
+                sh_wlo = lo2;
+                sh_whi = cs;
+              }
+            }
+          }
+        }
+        __syncthreads();
+        if (sh_res != 0) break;
+        // recompute from the checkpoint below the window, keeping its codes
+        const int32_t wlo = sh_wlo, whi = sh_whi, c = (wlo - 1) / K;
+        restore(c);
+        int64_t cbase = 0;
+        bool fine = true;
+        for (int32_t s = c * K + 1; s <= whi; ++s) fine = step(q, s, wlo, cbase) && fine;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (!fine && lane == 0) sh_res = -1;
+        __syncthreads();
+      }
+      // ---- forward replay and the runs ----
+      if (lane < 64 && sh_res == 1) {
+        auto ext = [&](int32_t k2, int32_t f) { return q.ext(m, n, k2, f); };
+        const int32_t total = Wk.direct ? O.nruns[p] : 0;
+        uint32_t *dst = Wk.direct ? (O.cigar + O.cigar_off[p]) : nullptr;
+        const bool good = replay_tokens(O, p, ext, m, n, tok, sh_nt, dst, total);
+        if (!good && lane == 0) sh_res = -1;
+      }
+      __syncthreads();
+    };
+    if (staged)
+      run(SeqStaged{reinterpret_cast<const uint32_t *>(sP), reinterpret_cast<const uint32_t *>(sT)});
+    else
+      run(SeqInPlace{gP, gT, pnw, tnw});
+    if (lane == 0 && sh_res != 1) {
+      O.status[p] = ST_OVERFLOW;
+      if (!Wk.direct) O.nruns[p] = 0;
+      if (L.failed) atomicAdd(L.failed, 1);
+    }
+  }
+}
+
 }  // namespace
+
+int64_t wfa_long_slot_words(const WfaLong &L, bool i16) {
+  const int64_t slot_w = i16 ? (3 * (int64_t)L.wcap + 1) / 2 : 3 * (int64_t)L.wcap;
+  const int64_t ckw = (int64_t)L.R * slot_w + (int64_t)L.R * ENTRY;
+  return ((int64_t)L.R * slot_w + L.ck_cap * ckw + L.sw_cap + 4 * (int64_t)L.wt_cap + L.code_cap / 4 +
+          L.tok_cap + 63) / 64 * 64;
+}
+
+hipError_t launch_wfa_long(const Seqs &S, const Outs &O, const Scoring &P, const Work &Wk, const WfaLong &L,
+                           int32_t nslots, int32_t threads, bool i16, hipStream_t s) {
+  if (nslots <= 0) return hipSuccess;
+  const size_t lds = 2 * (size_t)L.seq_words * 8 + (size_t)L.R * ENTRY * 4;
+  if (i16)
+    hipLaunchKernelGGL((k_wfa_long<int16_t>), dim3(nslots), dim3(threads), lds, s, S, O, P, Wk, L);
+  else
+    hipLaunchKernelGGL((k_wfa_long<int32_t>), dim3(nslots), dim3(threads), lds, s, S, O, P, Wk, L);
+  return hipGetLastError();
+}
 
 WfaPlan wfa_plan(int32_t max_len, const Scoring &P, int64_t budget_bytes, int32_t cus, bool plain,
                  int32_t ring_kb, int32_t trace_kb, int32_t long_threads, bool strict) {

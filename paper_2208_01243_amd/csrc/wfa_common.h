@@ -130,6 +130,67 @@ __device__ __forceinline__ uint8_t code_pair(int32_t code) {
   return (uint8_t)(code | (up << 4));
 }
 
+// The second half of a walk: from the nt tokens (last first) in `tok`,
+// written by lane 0 of the calling wavefront, replay the alignment forward
+// from (0, 0), extending every M visit as far as the bases match, and write
+// the runs (to the pair's slot and pool, or to dst as walk_codes does).
+// Returns false if the tokens do not end at (m, n).
+template <class Ext>
+__device__ bool replay_tokens(const Outs &O, int64_t p, Ext ext, int32_t m, int32_t n, uint32_t *tok, int32_t nt,
+                              uint32_t *dst, int32_t total) {
+  const int lane = threadIdx.x & 63;
+  __threadfence_block();  // lane 0's tokens visible to the wavefront
+  // forward replay: the '=' run of each M visit
+  int32_t i = 0, j = 0;
+  for (int32_t t = nt - 1; t >= 0; --t) {
+    const uint32_t tk = __builtin_amdgcn_readfirstlane(tok[t]);
+    if (tk == TOK_M) {
+      const int32_t len = __builtin_amdgcn_readfirstlane(ext(j - i, j)) - j;
+      if (lane == 0) tok[t] = TOK_M | ((uint32_t)len << 4);
+      i += len;
+      j += len;
+    } else if (tk == OP_X) {
+      ++i; ++j;
+    } else if (tk == OP_I) {
+      ++i;
+    } else {
+      ++j;
+    }
+  }
+  if (i != m || j != n) return false;  // cannot happen for a reached end cell
+  __threadfence_block();
+  if (lane == 0) {
+    RunSink sink;
+    if (!dst) sink.begin(O, p);
+    auto put = [&](int32_t nr, uint32_t run, int64_t more) {
+      if (!dst) sink.put(nr, run, more);
+      else if (nr < total) dst[total - 1 - nr] = run;
+    };
+    uint32_t cur_op = 0xffu, cur_len = 0;
+    int32_t nr = 0;
+    for (int32_t t = 0; t < nt; ++t) {
+      const uint32_t tk = tok[t];
+      const uint32_t op = (tk & 15u) == TOK_M ? (uint32_t)OP_EQ : (tk & 15u);
+      const uint32_t len = (tk & 15u) == TOK_M ? (tk >> 4) : 1u;
+      if (len == 0) continue;
+      if (op == cur_op) {
+        cur_len += len;
+      } else {
+        if (cur_len) put(nr++, (cur_len << 4) | cur_op, nt - t + 1);
+        cur_op = op;
+        cur_len = len;
+      }
+    }
+    if (cur_len) put(nr++, (cur_len << 4) | cur_op, 1);
+    if (!dst) {
+      sink.finish();
+      O.nruns[p] = nr;
+    }
+  }
+  return true;
+}
+
+
 // Run by one whole wavefront on uniform values; its lane 0 writes.
 // code_at(s, k) is evaluated per lane and gives the code of a kept cell, or
 // -1; ext(k, f) extends offset f on diagonal k.  Returns false (nothing
@@ -230,55 +291,18 @@ __device__ bool walk_codes(const Outs &O, int64_t p, CodeAt code_at, Ext ext, in
     }
   }
   if (!ok) return false;
-  __threadfence_block();  // lane 0's tokens visible to the wavefront
-  // forward replay: the '=' run of each M visit
-  int32_t i = 0, j = 0;
-  for (int32_t t = nt - 1; t >= 0; --t) {
-    const uint32_t tk = __builtin_amdgcn_readfirstlane(tok[t]);
-    if (tk == TOK_M) {
-      const int32_t len = __builtin_amdgcn_readfirstlane(ext(j - i, j)) - j;
-      if (lane == 0) tok[t] = TOK_M | ((uint32_t)len << 4);
-      i += len;
-      j += len;
-    } else if (tk == OP_X) {
-      ++i; ++j;
-    } else if (tk == OP_I) {
-      ++i;
-    } else {
-      ++j;
-    }
+  return replay_tokens(O, p, ext, m, n, tok, nt, dst, total);
+}
+
+// An accepted pair whose full store passes the largest class: to the
+// memory-bounded long pass when one runs, else no CIGAR.  One thread.
+__device__ __forceinline__ void to_long_pass(const Outs &O, int64_t p, int32_t *list, int32_t *count) {
+  if (list) {
+    const int32_t k = atomicAdd(count, 1);
+    list[k] = (int32_t)p;
+  } else {
+    O.status[p] = ST_OVERFLOW;
   }
-  if (i != m || j != n) return false;  // cannot happen for a reached end cell
-  __threadfence_block();
-  if (lane == 0) {
-    RunSink sink;
-    if (!dst) sink.begin(O, p);
-    auto put = [&](int32_t nr, uint32_t run, int64_t more) {
-      if (!dst) sink.put(nr, run, more);
-      else if (nr < total) dst[total - 1 - nr] = run;
-    };
-    uint32_t cur_op = 0xffu, cur_len = 0;
-    int32_t nr = 0;
-    for (int32_t t = 0; t < nt; ++t) {
-      const uint32_t tk = tok[t];
-      const uint32_t op = (tk & 15u) == TOK_M ? (uint32_t)OP_EQ : (tk & 15u);
-      const uint32_t len = (tk & 15u) == TOK_M ? (tk >> 4) : 1u;
-      if (len == 0) continue;
-      if (op == cur_op) {
-        cur_len += len;
-      } else {
-        if (cur_len) put(nr++, (cur_len << 4) | cur_op, nt - t + 1);
-        cur_op = op;
-        cur_len = len;
-      }
-    }
-    if (cur_len) put(nr++, (cur_len << 4) | cur_op, 1);
-    if (!dst) {
-      sink.finish();
-      O.nruns[p] = nr;
-    }
-  }
-  return true;
 }
 
 __device__ __forceinline__ void stage_seq(uint64_t *lds, const uint64_t *g, int64_t nw) {

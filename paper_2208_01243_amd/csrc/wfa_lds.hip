@@ -602,7 +602,7 @@ __global__ __launch_bounds__(T) void k_wfa_lds(Seqs S, Outs O, Scoring P, Work W
           int c = 0;
           while (c < 3 && need > L.need_cap[c]) ++c;
           if (need > L.need_cap[3]) {
-            O.status[p] = ST_OVERFLOW;  // full store larger than any arena class
+            to_long_pass(O, p, L.long_list, L.long_count);  // full store larger than any arena class
           } else {
             const int32_t k = atomicAdd(L.need_count[c], 1);
             L.need_list[c][k] = (int32_t)p;
