@@ -73,9 +73,12 @@ typedef enum { AIM_ENC_ASCII = 0, AIM_ENC_CODE = 1, AIM_ENC_2BIT = 2 } aim_encod
 #define AIM_PAIR_ALIGNED 0
 #define AIM_PAIR_REJECTED 1       /* optimum > max_score: score -1, empty CIGAR */
 #define AIM_PAIR_CIGAR_OVERFLOW 2 /* score valid, no CIGAR: it did not fit cigar_cap, or
-                                     (WFA, scores in the tens of thousands) the
-                                     wavefronts its walk needs outgrow the largest
-                                     store the scratch budget allows, or (WFA-
+                                     (WFA) its full store passes the largest class
+                                     and the memory-bounded long pass cannot take
+                                     it either (scratch too small for one of its
+                                     slots, a score past 2^20, or one score's
+                                     origin codes past its code window; see
+                                     aim_call_stats.wfa_long_failed), or (WFA-
                                      adaptive) its origin codes outgrew the slot */
 #define AIM_PAIR_INVALID 3        /* non-ACGT base or length beyond max_len */
 
