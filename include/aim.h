@@ -418,8 +418,11 @@ aim_status aim_tune_load(aim_context *ctx, const char *path);
  * repeated batches of the same shape.  Runs the call once eagerly first (so
  * scratch is sized and `out` is valid), then captures it on `stream` (must
  * not be NULL).  The graph keeps the batch and result pointers: replays
- * re-align whatever those buffers hold.  A replay is refused if the context's
- * scratch was reallocated since capture. */
+ * re-align whatever those buffers hold.  A replay is refused
+ * (AIM_ERR_INVALID_ARG) if the context's scratch was reallocated since
+ * capture, or if the context was destroyed; aim_graph_destroy may be called
+ * before or after aim_destroy of its context.  Not thread-safe with other
+ * calls on the same context. */
 typedef struct aim_graph aim_graph;
 aim_status aim_graph_capture(aim_context *ctx, const aim_batch *pairs, int32_t alg,
                              aim_penalties pen, int32_t max_score, aim_results *out, void *stream,

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <set>
 #include <sstream>
 #include <mutex>
 #include <string>
@@ -122,7 +123,8 @@ struct Scratch {
 };
 
 struct aim_graph {
-  aim_context *c = nullptr;
+  aim_context *c = nullptr;  // nullptr once the context is destroyed
+  int32_t device = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int64_t generation = 0;
@@ -136,6 +138,7 @@ struct aim_context {
   PhaseTimer timer;
   std::map<std::pair<int32_t, int32_t>, Tune> tunes;  // (alg, length bucket) -> tune
   std::map<std::pair<int32_t, int32_t>, ClassTune> class_tunes;  // (alg, class length bucket)
+  std::set<aim_graph *> graphs;  // captured graphs still alive (detached when the context goes)
   const Tune *force = nullptr;  // set while the autotuner tries a candidate
   bool capturing = false;       // inside a hipGraph capture: no timing events
   // second stream (default priority) for the escalation tiers, which run
@@ -800,6 +803,8 @@ aim_status aim_create(aim_context **ctx, int32_t device, const aim_options *opt)
 void aim_destroy(aim_context *c) {
   if (!c) return;
   DeviceGuard g(c->device);
+  for (aim_graph *gr : c->graphs) gr->c = nullptr;  // their launches now fail; destroy still frees them
+  c->graphs.clear();
   (void)hipDeviceSynchronize();
   Buf *all[] = {&c->own.order, &c->own.hist, &c->own.flags, &c->own.pflag, &c->own.tflag, &c->own.pat2, &c->own.txt2, &c->own.pat2off, &c->own.txt2off,
                 &c->own.nruns, &c->own.slot, &c->own.tb32, &c->own.tb64, &c->own.full, &c->own.list2, &c->own.list3,
@@ -1596,6 +1601,8 @@ aim_status aim_graph_capture(aim_context *c, const aim_batch *B, int32_t alg, ai
   }
   auto *gr = new aim_graph();
   gr->c = c;
+  gr->device = c->device;
+  c->graphs.insert(gr);
   gr->graph = graph;
   gr->exec = exec;
   gr->generation = gen;
@@ -1606,6 +1613,7 @@ aim_status aim_graph_capture(aim_context *c, const aim_batch *B, int32_t alg, ai
 aim_status aim_graph_launch(aim_graph *gr, void *stream) {
   g_err.clear();
   if (!gr) return fail(AIM_ERR_INVALID_ARG, "NULL graph");
+  if (!gr->c) return fail(AIM_ERR_INVALID_ARG, "the graph's context was destroyed");
   if (gr->c->generation != gr->generation)
     return fail(AIM_ERR_INVALID_ARG, "the context's scratch was reallocated since capture; capture again");
   aim_context *c = gr->c;
@@ -1624,7 +1632,8 @@ aim_status aim_graph_launch(aim_graph *gr, void *stream) {
 
 void aim_graph_destroy(aim_graph *gr) {
   if (!gr) return;
-  DeviceGuard g(gr->c->device);
+  if (gr->c) gr->c->graphs.erase(gr);
+  DeviceGuard g(gr->device);
   if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
   if (gr->graph) (void)hipGraphDestroy(gr->graph);
   delete gr;

@@ -305,3 +305,22 @@ def test_autotune_wfa_mixed_per_bucket(tmp_path):
     for i in rng.choice(b.n, 30, replace=False):
         st, sc, runs, _ = oracle.wfa_pair(b.pattern(i), b.text(i), w["pen"])
         assert (want[1][i], want[0][i]) == (st, sc) and want[2][want[3][i]:want[3][i + 1]].tolist() == runs, i
+
+
+def test_graph_outlives_its_context():
+    # a graph destroyed after its context (as Python may do) frees its HIP
+    # objects without touching the context, and a launch of it is refused;
+    # the next context works
+    w = synth.WORKLOADS["swg150"]
+    b = synth.workload("swg150", n=500)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        ctx = aim.Context(0)
+        g, dev, outs, max_len, enc = _capture(ctx, b, w, stream)
+        ctx.close()
+        with pytest.raises(aim.AimError):
+            g.launch(stream)
+        g.close()
+    with aim.Context(0) as c2:
+        got = run(c2, b, w["alg"], w["pen"], w["max_score"], enc=w["enc"])
+        assert not compare(got, oracle.align_batch(b, w["alg"], w["pen"], w["max_score"]))

@@ -2,8 +2,9 @@
 (oracle.genasm_batch, windows of 64 bases overlapping by 24): scores,
 statuses and CIGARs element by element, on tiny pairs exhaustively, mixed
 lengths with window edges, thresholds from 0 up, unrelated and lopsided
-pairs, score-only calls, ASCII input, long pairs, and the in-place re-run of
-pairs whose runs outgrow their slot and the pool.
+pairs, score-only calls, ASCII input, long pairs, the in-place re-run of
+pairs whose runs outgrow their slot and the pool, graph replays and the
+autotuner.
 """
 import itertools
 
@@ -122,3 +123,59 @@ def test_invalid_and_empty(ctx):
     b = synth.from_lists(pats, txts)
     check(ctx, b, -1)
     check(ctx, b, 3)
+
+
+def _outputs(b):
+    n = b.n
+    cap = int((b.pat_len.astype(np.int64) + b.txt_len + 1).sum()) + 1
+    return (torch.empty(n, dtype=torch.int32, device="cuda"), torch.empty(n, dtype=torch.int8, device="cuda"),
+            torch.empty(cap, dtype=torch.int32, device="cuda"), torch.empty(n + 1, dtype=torch.int64, device="cuda"))
+
+
+def _host(outs):
+    s, st, cg, off = outs
+    torch.cuda.synchronize()
+    return s.cpu().numpy(), st.cpu().numpy(), cg.cpu().numpy().view(np.uint32), off.cpu().numpy()
+
+
+def test_graph_replays():
+    from gpu_util import to_device
+    w = synth.WORKLOADS["genasm150"]
+    b = synth.workload("genasm150", n=4000)
+    L = int(max(b.pat_len.max(), b.txt_len.max()))  # reads with insertions pass 150 bases
+    want = oracle.genasm_batch(b, w["max_score"])
+    stream = torch.cuda.Stream()
+    with aim.Context(0) as ctx, torch.cuda.stream(stream):
+        dev, enc = to_device(b, w["enc"])
+        outs = _outputs(b)
+        g = ctx.graph_capture(*dev, enc=enc, max_len=L, alg="genasm", pen=w["pen"], max_score=w["max_score"],
+                              score=outs[0], status=outs[1], cigar=outs[2], cigar_off=outs[3], stream=stream)
+        for rep in range(3):
+            for t in outs:
+                t.zero_()  # eager work between replays
+            stream.synchronize()
+            g.launch(stream)
+            got = _host(outs)
+            bad = compare(got, want)
+            assert not bad, (rep, describe(b, bad[0], got, want))
+
+
+def test_autotune_is_exact_and_cached(tmp_path):
+    from gpu_util import to_device
+    w = synth.WORKLOADS["genasm150"]
+    b = synth.workload("genasm150", n=5000)
+    L = int(max(b.pat_len.max(), b.txt_len.max()))
+    dev, enc = to_device(b, w["enc"])
+    outs = _outputs(b)
+    want = oracle.genasm_batch(b, w["max_score"])
+    with aim.Context(0) as ctx:
+        params, ms = ctx.autotune(*dev, enc=enc, max_len=L, alg="genasm", pen=w["pen"], max_score=w["max_score"],
+                                  score=outs[0], status=outs[1], cigar=outs[2], cigar_off=outs[3], reps=1)
+        assert ms > 0 and ctx.tune_get("genasm", L) == params
+        assert not compare(_host(outs), want)
+        path = str(tmp_path / "tune.txt")
+        ctx.tune_save(path)
+    with aim.Context(0) as ctx2:
+        ctx2.tune_load(path)
+        assert ctx2.tune_get("genasm", L) == params
+        assert not compare(run(ctx2, b, "genasm", EDIT, w["max_score"]), want)
