@@ -36,14 +36,15 @@
 // table).  Then only the levels the traceback can read (0 .. distance - 1)
 // are built: a sweep over the window's text builds LB consecutive levels at
 // once, each level's vector at j - 1 in a register, reading only the level
-// below the block (stored by the previous sweep) once per text position.
-// The vectors of those levels are stored for the traceback in the
-// wavefront's slot, entry (d, j) of lane l at word (d * 64 + j - 1) * 64 + l, so a
-// wavefront's loads and stores at one text position are one contiguous
-// 512-byte group.  The traceback compares bases on '=' steps and reads
-// stored vectors only around edits, in rounds in which every lane of the
-// wavefront that needs them reads them together.  Work comes 64 pairs at a
-// time from an atomic counter.
+// below the block (the previous sweep's carry row) once per text position.
+// Those levels are stored for the traceback in the wavefront's slot (see
+// Slot below), as 32-bit slices around the window's end diagonal unless a
+// window of the wavefront has a distance above 14, and only at positions the
+// traceback can reach; a wavefront's accesses at one text position are one
+// contiguous group.  The traceback compares bases on '=' steps (a run of
+// matches at once) and reads stored vectors only around edits, in rounds in
+// which every lane of the wavefront that needs them reads them together.
+// Work comes 64 pairs at a time from an atomic counter.
 #include "aim_internal.h"
 #include "dev_util.h"
 
