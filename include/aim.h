@@ -401,7 +401,10 @@ aim_status aim_autotune(aim_context *ctx, const aim_batch *pairs, int32_t alg, a
  * c + 1 keeps its recent wavefronts in a global buffer rather than LDS, [12]
  * the one-wavefront window in units of 64 diagonals (0: from the batch; at
  * most 4).  A class tune kept for a class's length bucket (aim_autotune)
- * overrides [8..11] for that class. */
+ * overrides [8..11] for that class.  Without a kept tune, the built-in
+ * defaults apply (aim_tune_get returns them): those above, except for WFA
+ * batches with max_len >= 4096, where [10] is 256 and [12] is 1 (the
+ * autotuner's choice for long mixed reads on MI355X). */
 aim_status aim_tune_get(aim_context *ctx, int32_t alg, int32_t max_len, int32_t *params);
 aim_status aim_tune_set(aim_context *ctx, int32_t alg, int32_t max_len, const int32_t *params);
 /* The kept tunes: for entry i < min(cap, *count), kind[i] 0 (batch tune) or
