@@ -274,6 +274,9 @@ enum Counter {
 // Smallest batch for which the packed band tier's traceback is walked by a
 // separate kernel beside the escalation tiers by default.
 constexpr int64_t SPLIT_MIN_PAIRS = 65536;
+// Below this many pairs the first tier is, by default, the 32-bit band (one
+// pair per lane) rather than the packed band (two pairs per lane).
+constexpr int64_t SMALL_BATCH_PAIRS = 16384;
 
 // WFA requires a bounded ring of past wavefronts: max(x, o + e) <= this.
 constexpr int32_t WFA_MAX_STEP = 1024;
@@ -328,18 +331,21 @@ int32_t len_bucket_host(int32_t L) {
   return b;
 }
 
-// Built-in defaults where no tune is kept.  For WFA batches of reads of
-// 4,096 bases or more, the autotuner's choice on MI355X for long mixed reads
-// (500,000 pairs of 100-10,000 bases at 0.5-10 % error: 489 ms per call
-// against 518 ms): a one-wavefront window of 64 diagonals (pairs that are
-// going to be wide leave it early, rather than after filling a wider window)
-// and 256-thread workgroups for the widest window class.
+// Built-in defaults where no tune is kept, from the autotuner on MI355X:
+// - WFA, reads of 4,096 bases or more (500,000 pairs of 100-10,000 bases at
+//   0.5-10 % error: 489 ms per call against 518 ms): a one-wavefront window
+//   of 64 diagonals (pairs that are going to be wide leave it early, rather
+//   than after filling a wider window) and 256-thread workgroups for the
+//   widest window class;
+// - GenASM: no length sort below 512 bases (1,000,000 x 150 bp: 2.17 ms
+//   against 2.28 ms; fixed-length reads gain nothing from it).
 Tune default_tune(int32_t alg, int32_t L) {
   Tune t;
   if (alg == AIM_WFA_AFFINE && L >= 4096) {
     t.wfa_c16 = 1;
     t.wfa_cls_threads[2] = 256;
   }
+  if (alg == AIM_GENASM) t.sort = L >= 512 ? 1 : 0;
   return t;
 }
 
@@ -1046,7 +1052,10 @@ static aim_status align_batch(aim_context *c, const aim_batch *B, int32_t alg, a
     const int32_t w0 = tu.band_w0 == 64 ? 64 : 32;
     // 32 diagonals in packed 16-bit arithmetic (two pairs per lane) when the
     // value bound allows, else 32-bit
-    const bool b16 = w0 == 32 && tu.band16 && aim::band16_fits(L, P, affine);
+    // (auto: not for batches too small to fill the GPU, which the one pair
+    // per lane of the 32-bit band spreads over twice the wavefronts)
+    const bool b16 = w0 == 32 && tu.band16 && !(tu.band16 == 3 && n < SMALL_BATCH_PAIRS) &&
+                     aim::band16_fits(L, P, affine);
     Buf &tbA = w0 == 32 ? c->sc->tb32 : c->sc->tb64;
     const int64_t swA = aim::band_tb_slot_words(b16 ? 64 : w0, affine, rows_cap);
     const int64_t chunksA = b16 ? (n + 127) / 128 : chunks;
