@@ -394,7 +394,8 @@ aim_status aim_autotune(aim_context *ctx, const aim_batch *pairs, int32_t alg, a
  * [6] packed 16-bit band cells when the value bound allows (0 off; 1 on, each
  * wavefront walking its own pairs' tracebacks; 2 on, the tracebacks walked by
  * a second kernel beside the escalation tiers; 3, the default: 2 for batches
- * of at least 65536 pairs, 1 from 16384, else 0), [7] WFA pairs wider than the
+ * of at least 65536 pairs, else 1, or 0 for fewer than 16384 pairs of reads
+ * of at most 128 bases), [7] WFA pairs wider than the
  * one-wavefront window go through LDS-window classes (1, the default) or
  * straight to the HBM-ring pass (0), [8..10] workgroup size (64, 128, 256 or
  * 512) of the three window classes (narrowest first), [11] bit c set: class
@@ -405,8 +406,9 @@ aim_status aim_autotune(aim_context *ctx, const aim_batch *pairs, int32_t alg, a
  * defaults apply (aim_tune_get returns them): those above, except [10] 256
  * and [12] 1 for WFA batches with max_len >= 4096, and [2] 0 for GenASM
  * below 512 bases (the autotuner's choices on MI355X);
- * and with [6] at 3, batches of fewer than 16,384 pairs use the 32-bit band
- * (one pair per lane, twice the wavefronts of the packed band). */
+ * and with [6] at 3, batches of fewer than 16,384 pairs of reads of at most
+ * 128 bases use the 32-bit band (one pair per lane, twice the wavefronts of
+ * the packed band). */
 aim_status aim_tune_get(aim_context *ctx, int32_t alg, int32_t max_len, int32_t *params);
 aim_status aim_tune_set(aim_context *ctx, int32_t alg, int32_t max_len, const int32_t *params);
 /* The kept tunes: for entry i < min(cap, *count), kind[i] 0 (batch tune) or
