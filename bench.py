@@ -61,7 +61,7 @@ PEAK_HBM_GBS = 8000.0
 MEASURED_TRAFFIC = {("swg150", "k_band16<32>"): ("32a97daf6917c56a", 3.0790e9),
                     ("wfa_mixed", "k_wfa_lds"): ("b017a606648c8edf", 2.210e12),
                     ("wfa250", "k_wfa_score16"): ("5bad4690d30beb16", 4.288e9),
-                    ("genasm150", "k_genasm"): ("b376741d59f1d343", 5.05e9)}
+                    ("genasm150", "k_genasm"): ("b376741d59f1d343", 5.15e9)}
 KERNEL_SOURCE = {"k_band16<32>": "dp_band16.hip", "k_band<32>": "dp_band.hip",
                  "k_wfa_score16": "wfa.hip", "k_wfa_score": "wfa.hip", "k_wfa_lds": "wfa_lds.hip",
                  "k_genasm": "genasm.hip"}
