@@ -58,7 +58,7 @@ PEAK_HBM_GBS = 8000.0
 # HBM bytes per launch of a kernel from two rocprofv3 --pmc passes (FETCH_SIZE
 # and WRITE_SIZE scaled by a copy-kernel calibration), valid only for the
 # kernel source they were taken on (first 16 hex of its SHA-256)
-MEASURED_TRAFFIC = {("swg150", "k_band16<32>"): ("32a97daf6917c56a", 3.0790e9),
+MEASURED_TRAFFIC = {("swg150", "k_band16<32>"): ("10b6889942966735", 3.0799e9),
                     ("wfa_mixed", "k_wfa_lds"): ("b017a606648c8edf", 2.210e12),
                     ("wfa250", "k_wfa_score16"): ("5bad4690d30beb16", 4.288e9),
                     ("genasm150", "k_genasm"): ("b376741d59f1d343", 5.15e9)}

@@ -53,10 +53,6 @@ __device__ __forceinline__ uint32_t push_signs(uint32_t acc, s16x2 d_lo, s16x2 d
   const uint32_t sg = __builtin_amdgcn_perm(U(d_hi), U(d_lo), 0x07050301u);
   return (sg & 0x80808080u) | ((acc >> 1) & 0x7f7f7f7fu);
 }
-// bit of plane q, pair h, band cell b in the words of one row (w[g*NP/2+pp])
-__device__ __forceinline__ uint32_t tb_bit(uint32_t w, int q, int h, int b) {
-  return (w >> (((q & 1) * 2 + h) * 8 + (b & 7))) & 1u;
-}
 
 // Traceback of one pair (half h of its lane's packed words) over rows of
 // bits staged in LDS, row r of a block at lds + r * 2 * planes * 64 words.
@@ -94,34 +90,67 @@ struct Walker16 {
     }
     cur_len += len;
   }
-  // Steps while the path stays in rows lo+1 .. (the rows staged).  Pattern
-  // bases lo .. lo+31 are in pw0/pw1 (words pq0, pq0+1); text bases from
-  // lo+kmin on in tw0..tw2 (words tq0 ..).
-  __device__ void walk(const uint32_t *lds, int lane, int h, int32_t lo, uint64_t pw0, uint64_t pw1,
-                       uint64_t tw0, uint64_t tw1, uint64_t tw2, int64_t pq0, int64_t tq0) {
-    while (i > lo && j > 0) {
-      const uint32_t *rw = lds + ((i - lo - 1) * NP * 2 + ((b >> 3) & 3) * (NP / 2)) * 64 + lane;
-      const uint32_t w01 = rw[0];
-      const uint32_t bd = tb_bit(w01, 0, h, b), b1 = tb_bit(w01, 1, h, b);
-      uint32_t b2 = 0, b3 = 0;
-      if (AFF) {
-        const uint32_t w23 = rw[64];
-        b2 = tb_bit(w23, 2, h, b);
-        b3 = tb_bit(w23, 3, h, b);
-      }
-      const int32_t g = (st == 0 && !bd) ? (b1 ? 2 : 1) : st;  // 0 diag, 1 I, 2 D
-      const uint64_t pw = (((i - 1) >> 5) == pq0) ? pw0 : pw1;
-      const int64_t tq = (int64_t)(j - 1) >> 5;
-      const uint64_t tw = tq == tq0 ? tw0 : (tq == tq0 + 1 ? tw1 : tw2);
-      const uint32_t ca = (uint32_t)(pw >> (2 * ((i - 1) & 31))) & 3u;
-      const uint32_t cb = (uint32_t)(tw >> (2 * ((j - 1) & 31))) & 3u;
-      const uint32_t op = g == 0 ? (ca == cb ? OP_EQ : OP_X) : (g == 1 ? OP_I : OP_D);
-      put(op, 1);
-      st = AFF ? (g == 1 ? (b2 ? 1 : 0) : (g == 2 ? (b3 ? 2 : 0) : 0)) : 0;
+  // 32 text bases from the one at ts + 32 tq0 on, ts = max(j - 1 - 32 tq0 -
+  // 31, 0): with j - 1 >= 32 tq0 the window holds base j - 1 and the 31
+  // below it, which the walk reaches before it needs another.
+  __device__ void text_window(uint64_t tw0, uint64_t tw1, uint64_t tw2, int64_t tq0, uint64_t &win,
+                              int32_t &base) {
+    const int32_t ts = max((int32_t)((int64_t)(j - 1) - 32 * tq0) - 31, 0);  // 0 .. 38
+    const uint64_t a = ts < 32 ? tw0 : tw1, c = ts < 32 ? tw1 : tw2;
+    const uint32_t s2 = 2 * (ts & 31);
+    win = s2 ? (a >> s2) | (c << (64 - s2)) : a;
+    base = (int32_t)(32 * tq0) + ts;
+  }
+  // Steps while the path stays in rows lo+1 .. (the rows staged, at most 8).
+  // Pattern bases lo .. lo+31 are in pw0/pw1 (words pq0, pq0+1); text bases
+  // from lo+kmin on in tw0..tw2 (words tq0 ..).  Every step reads one cell's
+  // bits (two words for four planes) and takes one op, with selects; the
+  // bases it compares come from a 16-base pattern window of the block and a
+  // 32-base text window below the walk's column.
+  // Only the cell groups (8 band cells each) set in gmask are staged: a walk
+  // that reaches another stops there and returns true.
+  __device__ bool walk(const uint32_t *lds, int lane, int h, int32_t lo, uint64_t pw0, uint64_t pw1,
+                       uint64_t tw0, uint64_t tw1, uint64_t tw2, int64_t pq0, int64_t tq0, uint32_t gmask) {
+    if (i <= lo || j <= 0) return false;
+    const uint32_t po = (uint32_t)(lo - 32 * pq0);  // 0 .. 31
+    const uint32_t p0 = (uint32_t)pw0, p1 = (uint32_t)(pw0 >> 32), p2 = (uint32_t)pw1;
+    // pattern base lo + r at bits 2r
+    const uint32_t pwin = __builtin_amdgcn_alignbit(po < 16 ? p1 : p2, po < 16 ? p0 : p1, 2 * (po & 15));
+    uint64_t twin;
+    int32_t tbase;
+    text_window(tw0, tw1, tw2, tq0, twin, tbase);
+    do {
+      if (!((gmask >> ((b >> 3) & 3)) & 1u)) return true;
+      const int32_t r = i - lo - 1;
+      const uint32_t *rw = lds + (r * NP * 2 + ((b >> 3) & 3) * (NP / 2)) * 64 + lane;
+      uint32_t w01 = rw[0], w23 = AFF ? rw[64] : 0u;
+      if (j - 1 < tbase) text_window(tw0, tw1, tw2, tq0, twin, tbase);
+      uint32_t eq = (pwin >> (2 * r)) ^ (uint32_t)(twin >> (2 * (j - 1 - tbase)));
+      // every lane computes every candidate: the empty asm statements keep the
+      // compiler from turning the selects below into branches
+      asm volatile("" : "+v"(w01), "+v"(w23), "+v"(eq));
+      // plane q of pair h, band cell b: bit ((q & 1) * 2 + h) * 8 + (b & 7)
+      // of the word of planes (q & ~1, q | 1)
+      const uint32_t sh = (uint32_t)h * 8 + (b & 7);
+      const uint32_t bd = (w01 >> sh) & 1u, b1 = (w01 >> (sh + 16)) & 1u;
+      const int32_t g = st ? st : (int32_t)((bd ^ 1u) * (1u + b1));  // 0 diag, 1 I, 2 D
+      // OP_EQ, OP_X on the diagonal; OP_I = 2 and OP_D = 3 are g + 1
+      static_assert(OP_EQ == 0 && OP_X == 1 && OP_I == 2 && OP_D == 3, "op codes");
+      const uint32_t op = g ? (uint32_t)g + 1u : (uint32_t)((eq & 3u) != 0);
+      // runs: a new op closes the current run (kept if the slot has room)
+      const bool close = op != cur_op && cur_len;
+      if (close && nr < cap) slot[nr] = (cur_len << 4) | cur_op;
+      nr += close ? 1 : 0;
+      cur_len = op != cur_op ? 1u : cur_len + 1;
+      cur_op = op;
+      // a gap continues while its extension plane says so: plane 2 (bit sh)
+      // for I, plane 3 (bit sh + 16) for D
+      st = AFF ? g * (int32_t)((w23 >> (sh + 8 * (g & 2))) & 1u) : 0;
       i -= g != 2;
       j -= g != 1;
       b += g == 1 ? 1 : (g == 2 ? -1 : 0);
-    }
+    } while (i > lo && j > 0);
+    return false;
   }
   __device__ void finish(const Outs &O, int64_t p) {
     if (i > 0) put(OP_I, (uint32_t)i);
@@ -377,7 +406,7 @@ __global__ __launch_bounds__(64, 3) void k_band16(Seqs Sq, Outs O, Scoring P, Wo
         for (int h = 0; h < 2; ++h)
           if (accept[h])
             wk[h].walk(reinterpret_cast<const uint32_t *>(fused_stage), lane, h, lo, w[h][0], w[h][1],
-                       w[h][2], w[h][3], w[h][4], pq0[h], tq0[h]);
+                       w[h][2], w[h][3], w[h][4], pq0[h], tq0[h], 0xfu);
       }
 #pragma unroll
       for (int h = 0; h < 2; ++h)
@@ -394,6 +423,9 @@ __global__ __launch_bounds__(64, 3) void k_band16(Seqs Sq, Outs O, Scoring P, Wo
 // can touch are loaded into registers beside them.  A lane's row index only
 // decreases, so each row is read from HBM once.
 constexpr int TB_ROWS = 8;
+// cells a lane's diagonal may move, over the block it is on and the next,
+// with the next block's rows still staged (further moves re-stage the block)
+constexpr int TB_TRACK = 3;
 
 template <bool AFF>
 __global__ __launch_bounds__(128) void k_band16_tb(Seqs Sq, Outs O, Work Wk, const uint32_t *tb_all,
@@ -402,6 +434,7 @@ __global__ __launch_bounds__(128) void k_band16_tb(Seqs Sq, Outs O, Work Wk, con
   constexpr int ROW = NP * 2 * 64;  // words per row
   __shared__ u32x4 stage[TB_ROWS * ROW / 4];
   __shared__ int32_t s_chunk, s_top;
+  __shared__ uint32_t s_gm[2], s_miss[2];
   const uint32_t *lds = reinterpret_cast<const uint32_t *>(stage);
   const int tid = threadIdx.x, lane = tid & 63, h = tid >> 6;
   const int64_t count = Wk.count ? (int64_t)(*(volatile const int32_t *)Wk.count) : Wk.n;
@@ -442,17 +475,24 @@ __global__ __launch_bounds__(128) void k_band16_tb(Seqs Sq, Outs O, Work Wk, con
     Walker16<AFF> wk;
     if (act) wk.begin(O, p, m, n, kmin);
     // rows lo+1 .. hi of the block below `hi` go through registers: the
-    // next block's loads are in flight while the lanes walk this one
+    // next block's loads are in flight while the lanes walk this one.  Of a
+    // row only the cell groups near the lanes' diagonals are fetched: the
+    // 16-byte piece at stage position tid + 128 k belongs to group qg (the
+    // same for every k, 128 being a multiple of the pieces per row).
     constexpr int PRE = TB_ROWS * ROW / 4 / 128;
+    constexpr int QR = ROW / 4;
+    const int qg = ((tid % QR) * 4) / QR;
     u32x4 pre[PRE];
-#define AIM_TB_FETCH(BHI)                                                              \
+#define AIM_TB_FETCH(BHI, GM)                                                          \
   do {                                                                                 \
     const int32_t bhi_ = (BHI), blo_ = max(bhi_ - TB_ROWS, 0);                         \
-    const int nq_ = (bhi_ - blo_) * (ROW / 4);                                         \
+    const int nq_ = (bhi_ - blo_) * QR;                                                \
     const u32x4 *g_ = reinterpret_cast<const u32x4 *>(src + (int64_t)(blo_ + 1) * ROW); \
-    _Pragma("unroll") for (int k = 0; k < PRE; ++k) pre[k] = g_[min(tid + 128 * k, nq_ - 1)]; \
+    if (((GM) >> qg) & 1u)                                                             \
+      _Pragma("unroll") for (int k = 0; k < PRE; ++k) pre[k] = g_[min(tid + 128 * k, nq_ - 1)]; \
   } while (0)
-    if (top > 0) AIM_TB_FETCH(top);
+    uint32_t gcur = 0xfu;  // groups of the block being walked
+    if (top > 0) AIM_TB_FETCH(top, gcur);
     // sequence words of the current block, reloaded only when the block's
     // first word moves (every fourth block or so)
     int64_t pq0 = INT64_MIN, tq0 = INT64_MIN;
@@ -460,11 +500,11 @@ __global__ __launch_bounds__(128) void k_band16_tb(Seqs Sq, Outs O, Work Wk, con
 #pragma unroll 1
     for (int32_t hi = top; hi > 0; hi -= TB_ROWS) {
       const int32_t lo = max(hi - TB_ROWS, 0);  // rows lo+1 .. hi
-      // the whole stage is written; entries past nq (copies of the block's
-      // last quad) belong to no staged row and are never read
-#pragma unroll
-      for (int k = 0; k < PRE; ++k) stage[tid + 128 * k] = pre[k];
-      // pattern bases lo .. hi-1; text bases lo+kmin .. hi-1+kmin+W-1
+      // pattern bases lo .. hi-1; text bases lo+kmin .. hi-1+kmin+W-1.  They
+      // are loaded before the stage is written, whose wait for this block's
+      // rows then covers them too: loaded after it, their wait would come
+      // after the next block's loads are issued and wait for those as well
+      // (the wait counter is in order), so the walk could not overlap them.
       const int64_t pq = lo >> 5, tq = ((int64_t)lo + kmin) >> 5;
       if (pq != pq0) {
         pq0 = pq;
@@ -477,12 +517,41 @@ __global__ __launch_bounds__(128) void k_band16_tb(Seqs Sq, Outs O, Work Wk, con
         tw1 = dev::ld_word(txt, tnw, tq + 1);
         tw2 = dev::ld_word(txt, tnw, tq + 2);
       }
+      // the groups fetched are written; entries past nq (copies of the
+      // block's last piece) belong to no staged row and are never read
+      if ((gcur >> qg) & 1u) {
+#pragma unroll
+        for (int k = 0; k < PRE; ++k) stage[tid + 128 * k] = pre[k];
+      }
+      // groups for the next block: within TB_TRACK cells of the diagonals
+      // of the lanes still walking, as they stand before this block
+      const bool live = act && wk.i > 0 && wk.j > 0;
+      const int32_t bmin = -dev::wave_max(live ? -max(wk.b - TB_TRACK, 0) : -W);
+      const int32_t bmax = dev::wave_max(live ? min(wk.b + TB_TRACK, W - 1) : -1);
+      if (lane == 0)
+        s_gm[h] = bmax < 0 ? 0u : ((2u << (bmax >> 3)) - 1u) & ~((1u << (bmin >> 3)) - 1u);
       __syncthreads();
-      // the next block; after the last one, a one-row dummy that keeps the
-      // loads unconditional
-      AIM_TB_FETCH(lo > 0 ? lo : 1);
-      if (act) wk.walk(lds, lane, h, lo, pw0, pw1, tw0, tw1, tw2, pq0, tq0);
+      const uint32_t gnext = s_gm[0] | s_gm[1];
+      // the next block; after the last one, a one-row dummy
+      AIM_TB_FETCH(lo > 0 ? lo : 1, gnext);
+      const bool miss = act && wk.walk(lds, lane, h, lo, pw0, pw1, tw0, tw1, tw2, pq0, tq0, gcur);
+      const bool wmiss = __ballot(miss) != 0;
+      if (lane == 0) s_miss[h] = wmiss;
       __syncthreads();
+      if (s_miss[0] | s_miss[1]) {
+        // a path left the groups staged: stage the rest of the block, one
+        // piece at a time (rare), and walk on
+        const u32x4 *g = reinterpret_cast<const u32x4 *>(src + (int64_t)(lo + 1) * ROW);
+        const int nq = (hi - lo) * QR;
+        if (!((gcur >> qg) & 1u)) {
+#pragma unroll 1
+          for (int k = 0; k < PRE; ++k) stage[tid + 128 * k] = g[min(tid + 128 * k, nq - 1)];
+        }
+        __syncthreads();
+        if (act) wk.walk(lds, lane, h, lo, pw0, pw1, tw0, tw1, tw2, pq0, tq0, 0xfu);
+        __syncthreads();
+      }
+      gcur = gnext;
     }
     if (act) wk.finish(O, p);
     __syncthreads();
