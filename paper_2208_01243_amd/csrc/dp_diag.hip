@@ -349,23 +349,32 @@ __global__ __launch_bounds__(64) void k_diag_tb(Seqs S, Outs O, Work Wk, const u
       }
       cur_len += len;
     };
-#pragma unroll 1
-    for (int32_t beta = btop; beta >= 0; --beta) {
-      __syncthreads();  // the previous block is no longer read
+    // block beta's bits go through registers: the next block's loads are in
+    // flight while the lanes walk this one (only active pairs' pieces)
+    constexpr int PRE = QUADS / 64;
+    u32x4 pre[PRE];
+    auto fetch = [&](int32_t beta) {
 #pragma unroll
-      for (int k = lane; k < QUADS; k += 64) {
-        const int pi = k / (NS * LPP / 4), stream = (k / (LPP / 4)) % NS, quad = k % (LPP / 4);
+      for (int k = 0; k < PRE; ++k) {
+        const int q = lane + 64 * k;
+        const int pi = q / (NS * LPP / 4), stream = (q / (LPP / 4)) % NS, quad = q % (LPP / 4);
         if ((actmask >> pi) & 1ull) {
           const int64_t lj = (int64_t)t * TBP + pi;
           const uint32_t *src = tb_all + (lj / G) * chunk_words + ((int64_t)beta * NS + stream) * 64 +
                                 (lj % G) * LPP + quad * 4;
-          stage[k] = *reinterpret_cast<const u32x4 *>(src);
+          pre[k] = *reinterpret_cast<const u32x4 *>(src);
         }
       }
+    };
+    if (btop >= 0) fetch(btop);
+#pragma unroll 1
+    for (int32_t beta = btop; beta >= 0; --beta) {
       // In block beta, i + j lies in [64 beta, 64 beta + 63] and j - i in
       // [kmin, kmin + 63], so base i-1 lies in 32 beta - (kmin + 65) / 2 ..
       // +64 and base j-1 in 32 beta + kmin / 2 - 1 .. +63; four words from
-      // one below the first cover either range.
+      // one below the first cover either range.  They are loaded before the
+      // stage is written, so that the wait for the block's bits covers them
+      // and no wait in the walk holds it for the next block's loads.
       const int64_t pq0 = ((int64_t)32 * beta - (kmin + 65) / 2 - 1) >> 5;
       const int64_t tq0 = ((int64_t)32 * beta + kmin / 2 - 2) >> 5;
       uint64_t pw[4], tw[4];
@@ -374,7 +383,18 @@ __global__ __launch_bounds__(64) void k_diag_tb(Seqs S, Outs O, Work Wk, const u
         pw[q] = dev::ld_word(pat, pnw, pq0 + q);
         tw[q] = dev::ld_word(txt, tnw, tq0 + q);
       }
+      // wait for them here (with the block's bits, loaded before them)
+      asm volatile("" ::"v"(pw[0]), "v"(pw[1]), "v"(pw[2]), "v"(pw[3]), "v"(tw[0]), "v"(tw[1]), "v"(tw[2]),
+                   "v"(tw[3]));
+      __syncthreads();  // the previous block is no longer read
+#pragma unroll
+      for (int k = 0; k < PRE; ++k)
+        if ((actmask >> ((lane + 64 * k) / (NS * LPP / 4))) & 1ull) stage[lane + 64 * k] = pre[k];
       __syncthreads();
+      if (beta > 0) fetch(beta - 1);
+      // keeps the compiler from sinking those loads below the walk (it emits
+      // nothing and waits for nothing)
+      asm volatile("" ::: "memory");
       while (act && i > 0 && j > 0) {
         const int32_t bb = j - i - kmin, ll = (bb >> 1) & (LPP - 1), s = bb & 1;
         const int32_t tau = (i + j - s) >> 1;
