@@ -135,52 +135,70 @@ __device__ __forceinline__ uint8_t code_pair(int32_t code) {
 // from (0, 0), extending every M visit as far as the bases match, and write
 // the runs (to the pair's slot and pool, or to dst as walk_codes does).
 // Returns false if the tokens do not end at (m, n).
+//
+// The tokens are taken 64 at a time, one per lane, into a register, and each
+// is read from there with a lane read: the walk over them is serial, and a
+// load per token would put one memory round trip on its path per token.  The
+// replay keeps the run lengths it finds in the same register and stores the
+// 64 tokens back together; the run-length pass reads them the same way.
 template <class Ext>
 __device__ bool replay_tokens(const Outs &O, int64_t p, Ext ext, int32_t m, int32_t n, uint32_t *tok, int32_t nt,
                               uint32_t *dst, int32_t total) {
   const int lane = threadIdx.x & 63;
   __threadfence_block();  // lane 0's tokens visible to the wavefront
-  // forward replay: the '=' run of each M visit
+  // forward replay: the '=' run of each M visit; lane l holds token t0 - l
   int32_t i = 0, j = 0;
-  for (int32_t t = nt - 1; t >= 0; --t) {
-    const uint32_t tk = __builtin_amdgcn_readfirstlane(tok[t]);
-    if (tk == TOK_M) {
-      const int32_t len = __builtin_amdgcn_readfirstlane(ext(j - i, j)) - j;
-      if (lane == 0) tok[t] = TOK_M | ((uint32_t)len << 4);
-      i += len;
-      j += len;
-    } else if (tk == OP_X) {
-      ++i; ++j;
-    } else if (tk == OP_I) {
-      ++i;
-    } else {
-      ++j;
+  for (int32_t t0 = nt - 1; t0 >= 0; t0 -= 64) {
+    const int32_t cnt = min(t0 + 1, 64);
+    uint32_t v = lane < cnt ? tok[t0 - lane] : 0u;
+    for (int32_t c = 0; c < cnt; ++c) {
+      const uint32_t tk = __builtin_amdgcn_readlane(v, c);
+      if (tk == TOK_M) {
+        const int32_t len = __builtin_amdgcn_readfirstlane(ext(j - i, j)) - j;
+        if (lane == c) v = TOK_M | ((uint32_t)len << 4);
+        i += len;
+        j += len;
+      } else if (tk == OP_X) {
+        ++i; ++j;
+      } else if (tk == OP_I) {
+        ++i;
+      } else {
+        ++j;
+      }
     }
+    if (lane < cnt) tok[t0 - lane] = v;
   }
   if (i != m || j != n) return false;  // cannot happen for a reached end cell
   __threadfence_block();
-  if (lane == 0) {
-    RunSink sink;
-    if (!dst) sink.begin(O, p);
-    auto put = [&](int32_t nr, uint32_t run, int64_t more) {
-      if (!dst) sink.put(nr, run, more);
-      else if (nr < total) dst[total - 1 - nr] = run;
-    };
-    uint32_t cur_op = 0xffu, cur_len = 0;
-    int32_t nr = 0;
-    for (int32_t t = 0; t < nt; ++t) {
-      const uint32_t tk = tok[t];
-      const uint32_t op = (tk & 15u) == TOK_M ? (uint32_t)OP_EQ : (tk & 15u);
-      const uint32_t len = (tk & 15u) == TOK_M ? (tk >> 4) : 1u;
-      if (len == 0) continue;
-      if (op == cur_op) {
-        cur_len += len;
-      } else {
-        if (cur_len) put(nr++, (cur_len << 4) | cur_op, nt - t + 1);
-        cur_op = op;
-        cur_len = len;
+  RunSink sink;
+  if (lane == 0 && !dst) sink.begin(O, p);
+  auto put = [&](int32_t nr, uint32_t run, int64_t more) {
+    if (!dst) sink.put(nr, run, more);
+    else if (nr < total) dst[total - 1 - nr] = run;
+  };
+  // lane 0 merges the tokens into runs; lane l holds token t0 + l
+  uint32_t cur_op = 0xffu, cur_len = 0;
+  int32_t nr = 0;
+  for (int32_t t0 = 0; t0 < nt; t0 += 64) {
+    const int32_t cnt = min(nt - t0, 64);
+    const uint32_t v = lane < cnt ? tok[t0 + lane] : 0u;
+    if (lane == 0) {
+      for (int32_t c = 0; c < cnt; ++c) {
+        const uint32_t tk = __builtin_amdgcn_readlane(v, c);
+        const uint32_t op = (tk & 15u) == TOK_M ? (uint32_t)OP_EQ : (tk & 15u);
+        const uint32_t len = (tk & 15u) == TOK_M ? (tk >> 4) : 1u;
+        if (len == 0) continue;
+        if (op == cur_op) {
+          cur_len += len;
+        } else {
+          if (cur_len) put(nr++, (cur_len << 4) | cur_op, nt - (t0 + c) + 1);
+          cur_op = op;
+          cur_len = len;
+        }
       }
     }
+  }
+  if (lane == 0) {
     if (cur_len) put(nr++, (cur_len << 4) | cur_op, 1);
     if (!dst) {
       sink.finish();
