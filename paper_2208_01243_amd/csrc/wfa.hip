@@ -303,7 +303,7 @@ void k_wfa_score(Seqs S, Outs O, Scoring P, Work Wk, WfaLaunch L, int32_t *hbm) 
           const uint32_t b = wcodes[cb + ((k - lo) >> 1)];
           return (int32_t)(((k - lo) & 1) ? (b >> 4) : (b & 15u));
         };
-        auto ext = [&](int32_t k, int32_t f) { return q.ext(m, n, k, f); };
+        auto ext = [&](int32_t k, int32_t f) { return q.ext_wave(m, n, k, f); };
         walked = walk_codes<true>(O, p, code_at, ext, x, oe, e, m, n, s, wtok, L.walk_tok);
         if (!walked && threadIdx.x == 0 && L.walk_fail) atomicAdd(L.walk_fail, 1);
       }
@@ -547,7 +547,7 @@ __global__ __launch_bounds__(64) void k_wfa_score16(Seqs S, Outs O, Scoring P, W
         const uint32_t b = bslot[(int64_t)cs * BR + (idx >> 1)];
         return (int32_t)((idx & 1) ? (b >> 4) : (b & 15u));
       };
-      auto ext = [&](int32_t k, int32_t f) { return extend_lds(P32, m, T32, n, k, f); };
+      auto ext = [&](int32_t k, int32_t f) { return extend_wave(P32, m, T32, n, k, f); };
       walked = walk_codes<false>(O, p, code_at, ext, x, oe, e, m, n, s, reinterpret_cast<uint32_t *>(rM),
                           (R + 2 * RE) * WS / 2);
       if (!walked && lane == 0 && L.walk_fail) atomicAdd(L.walk_fail, 1);
@@ -1001,7 +1001,7 @@ __global__ __launch_bounds__(WGMAX) void k_wfa_long(Seqs S, Outs O, Scoring P, W
       }
       // ---- forward replay and the runs ----
       if (lane < 64 && sh_res == 1) {
-        auto ext = [&](int32_t k2, int32_t f) { return q.ext(m, n, k2, f); };
+        auto ext = [&](int32_t k2, int32_t f) { return q.ext_wave(m, n, k2, f); };
         const int32_t total = Wk.direct ? O.nruns[p] : 0;
         uint32_t *dst = Wk.direct ? (O.cigar + O.cigar_off[p]) : nullptr;
         const bool good = replay_tokens(O, p, ext, m, n, tok, sh_nt, dst, total);

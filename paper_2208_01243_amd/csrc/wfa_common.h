@@ -48,11 +48,15 @@ struct SeqInPlace {
   int64_t pnw, tnw;
   __device__ __forceinline__ int32_t ext(int32_t m, int32_t n, int32_t k, int32_t f) const;
   __device__ __forceinline__ int32_t ext_all(int32_t m, int32_t n, int32_t k, int32_t f) const;
+  // by the whole wavefront, for the replay of a walk (same arguments in every lane)
+  __device__ __forceinline__ int32_t ext_wave(int32_t m, int32_t n, int32_t k, int32_t f) const;
 };
 struct SeqStaged {
   const uint32_t *P32, *T32;
   __device__ __forceinline__ int32_t ext(int32_t m, int32_t n, int32_t k, int32_t f) const;
   __device__ __forceinline__ int32_t ext_all(int32_t m, int32_t n, int32_t k, int32_t f) const;
+  // by the whole wavefront, for the replay of a walk (same arguments in every lane)
+  __device__ __forceinline__ int32_t ext_wave(int32_t m, int32_t n, int32_t k, int32_t f) const;
 };
 
 // Table entries are the same for every lane: read them as scalars, so that the
@@ -83,11 +87,50 @@ __device__ __forceinline__ int32_t extend_lds(const uint32_t *P32, int32_t m, co
   return j;
 }
 
+// extend_lds by a whole wavefront, for the serial walk's replay: lane l
+// compares the 16 bases that start 16 l bases along the diagonal, so one
+// round of LDS reads covers 1,024 bases; the first lane whose bases stop
+// matching, or that reaches an end, gives the run.  Every lane of the
+// wavefront calls it with the same arguments and gets the same result.  A
+// lane reads only where its first base lies before both ends: the words
+// extend_lds itself would read.
+__device__ __forceinline__ int32_t extend_wave(const uint32_t *P32, int32_t m, const uint32_t *T32, int32_t n,
+                                               int32_t k, int32_t f) {
+  const int32_t off = 16 * (int32_t)(threadIdx.x & 63);
+  int32_t i = f - k, j = f;
+  for (;;) {
+    const int32_t lim = min(m - i, n - j);
+    if (lim <= 0) return j;
+    const int32_t left = lim - off;  // bases this lane may compare
+    int32_t run = 0;
+    if (left > 0) {
+      const int32_t a = i + off, b = j + off;
+      const uint32_t d = __builtin_amdgcn_alignbit(P32[(a >> 4) + 1], P32[a >> 4], (uint32_t)(a & 15) * 2) ^
+                         __builtin_amdgcn_alignbit(T32[(b >> 4) + 1], T32[b >> 4], (uint32_t)(b & 15) * 2);
+      run = min(d ? (int32_t)(__builtin_ctz(d) >> 1) : 16, left);
+    }
+    const uint64_t stop = __ballot(run < 16);
+    if (stop) {
+      const int32_t first = (int32_t)__builtin_ctzll(stop);
+      return j + 16 * first + __builtin_amdgcn_readlane(run, first);
+    }
+    i += 1024;
+    j += 1024;
+  }
+}
+
 __device__ __forceinline__ int32_t SeqInPlace::ext(int32_t m, int32_t n, int32_t k, int32_t f) const {
   return extend(P, pnw, m, T, tnw, n, k, f);
 }
 __device__ __forceinline__ int32_t SeqStaged::ext(int32_t m, int32_t n, int32_t k, int32_t f) const {
   return extend_lds(P32, m, T32, n, k, f);
+}
+// in place (HBM): the serial extend, as ext
+__device__ __forceinline__ int32_t SeqInPlace::ext_wave(int32_t m, int32_t n, int32_t k, int32_t f) const {
+  return extend(P, pnw, m, T, tnw, n, k, f);
+}
+__device__ __forceinline__ int32_t SeqStaged::ext_wave(int32_t m, int32_t n, int32_t k, int32_t f) const {
+  return extend_wave(P32, m, T32, n, k, f);
 }
 __device__ __forceinline__ int32_t SeqInPlace::ext_all(int32_t m, int32_t n, int32_t k, int32_t f) const {
   return f >= 0 ? extend(P, pnw, m, T, tnw, n, k, f) : f;

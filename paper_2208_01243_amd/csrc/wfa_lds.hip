@@ -573,7 +573,7 @@ __global__ __launch_bounds__(T) void k_wfa_lds(Seqs S, Outs O, Scoring P, Work W
           const uint32_t b = cbytes[ctab[3 * cs + 2] + ((k - klo) >> 1)];
           return (int32_t)(((k - klo) & 1) ? (b >> 4) : (b & 15u));
         };
-        auto ext = [&](int32_t k, int32_t f) { return extend_lds(P32, m, T32, n, k, f); };
+        auto ext = [&](int32_t k, int32_t f) { return extend_wave(P32, m, T32, n, k, f); };
         // a re-run of a pair whose runs outgrew its slot and the pool writes
         // them straight into its CIGAR range
         uint32_t *dst = (ADAPT && Wk.direct) ? O.cigar + O.cigar_off[p] : nullptr;
