@@ -57,14 +57,18 @@ GENASM_OPS_PER_UPDATE, GENASM_OPS_PER_STEP, GENASM_BYTES_PER_UPDATE, GENASM_BYTE
 PEAK_HBM_GBS = 8000.0
 # HBM bytes per launch of a kernel from two rocprofv3 --pmc passes (FETCH_SIZE
 # and WRITE_SIZE scaled by a copy-kernel calibration), valid only for the
-# kernel source they were taken on (first 16 hex of its SHA-256)
-MEASURED_TRAFFIC = {("swg150", "k_band16<32>"): ("10b6889942966735", 3.0799e9),
-                    ("wfa_mixed", "k_wfa_lds"): ("b017a606648c8edf", 2.210e12),
-                    ("wfa250", "k_wfa_score16"): ("5bad4690d30beb16", 4.288e9),
-                    ("genasm150", "k_genasm"): ("b376741d59f1d343", 5.15e9)}
-KERNEL_SOURCE = {"k_band16<32>": "dp_band16.hip", "k_band<32>": "dp_band.hip",
-                 "k_wfa_score16": "wfa.hip", "k_wfa_score": "wfa.hip", "k_wfa_lds": "wfa_lds.hip",
-                 "k_genasm": "genasm.hip"}
+# kernel source they were taken on (first 16 hex of the SHA-256 of its source
+# file and the headers it includes)
+MEASURED_TRAFFIC = {("swg150", "k_band16<32>"): ("493d99bad8e4c2d4", 3.0799e9),
+                    ("wfa_mixed", "k_wfa_lds"): ("40348926033b3dc9", 2.2745e12),
+                    ("wfa250", "k_wfa_score16"): ("04f13bb9e7d35d4f", 4.335e9),
+                    ("genasm150", "k_genasm"): ("4e069b03afdd5683", 5.15e9)}
+KERNEL_SOURCE = {"k_band16<32>": ("dp_band16.hip", "aim_internal.h", "dev_util.h"),
+                 "k_band<32>": ("dp_band.hip", "aim_internal.h"),
+                 "k_wfa_score16": ("wfa.hip", "aim_internal.h", "wfa_common.h"),
+                 "k_wfa_score": ("wfa.hip", "aim_internal.h", "wfa_common.h"),
+                 "k_wfa_lds": ("wfa_lds.hip", "aim_internal.h", "wfa_common.h"),
+                 "k_genasm": ("genasm.hip", "aim_internal.h", "dev_util.h")}
 
 WORKLOAD_TEXT = {
     "swg150": "Gotoh 4/6/2 global, 1,000,000 pairs x 150 bp, 4% error (1/3 sub, ins, del), "
@@ -91,8 +95,11 @@ def log(*a):
 
 
 def src_hash(kernel):
-    src = open(os.path.join(ROOT, "paper_2208_01243_amd", "csrc", KERNEL_SOURCE[kernel]), "rb").read()
-    return hashlib.sha256(src).hexdigest()[:16]
+    """The kernel's source file and the headers it includes, hashed together."""
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCE[kernel]:
+        h.update(open(os.path.join(ROOT, "paper_2208_01243_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def genasm_units(name):
