@@ -208,3 +208,71 @@ def test_large_ring_penalties(ctx, smax, pen):
     # full-store walk run.  (0, 40, 10, 30) has the common divisor 10 and runs
     # as (4, 1, 3) in the one-wavefront pass.
     check(ctx, _mixed(45, 300, 0, 400, [0.0, 0.02, 0.1, 1.0]), pen, smax)
+
+
+def _long_run_pairs(seed):
+    """Pairs whose alignments hold match runs longer than 1,024 bases (the
+    replay extends a run one wavefront round per 1,024 bases): identical pairs
+    around multiples of 16 and 1,024 bases, one mismatch on either side of those
+    boundaries, and dense-edit blocks (10 %) between identical runs of
+    1,024-2,100 bases, wide enough to leave the one-wavefront window."""
+    rng = np.random.default_rng(seed)
+
+    def rand(n):
+        return "".join(rng.choice(list("ACGT"), n))
+
+    def dense(s, rate):
+        out = []
+        for c in s:
+            r = rng.random()
+            if r < rate / 3:
+                out.append("ACGT"[("ACGT".index(c) + 1 + int(rng.integers(3))) % 4])
+            elif r < 2 * rate / 3:
+                out.append(c + "ACGT"[int(rng.integers(4))])
+            elif r >= rate:
+                out.append(c)
+        return "".join(out)
+
+    pats, txts = [], []
+    for L in (1023, 1024, 1025, 1040, 2048, 3001):
+        t = rand(L)
+        pats.append(t)
+        txts.append(t)
+    for pos in (16, 1023, 1024, 1025, 2047, 3999):
+        t = rand(4000)
+        p = t[:pos] + "ACGT"[("ACGT".index(t[pos]) + 1) % 4] + t[pos + 1:]
+        pats.append(p)
+        txts.append(t)
+    for run_len in (1024, 1025, 1500, 2100):
+        blocks_t, blocks_p = [], []
+        for _ in range(3):
+            a = rand(700)
+            blocks_t.append(a)
+            blocks_p.append(dense(a, 0.10))
+            r = rand(run_len)
+            blocks_t.append(r)
+            blocks_p.append(r)
+        pats.append("".join(blocks_p))
+        txts.append("".join(blocks_t))
+    return synth.from_lists(pats, txts)
+
+
+def test_long_match_runs(ctx):
+    b = _long_run_pairs(2024)
+    s, st, cg, off = run(ctx, b, "wfa", AFF)
+    stats = ctx.last_call_stats()
+    # the dense-block pairs leave the one-wavefront window: their walks run in
+    # the window classes, the others' in the one-wavefront pass
+    assert sum(stats["wfa_class_pairs"]) >= 1, stats
+    assert stats["wfa_walk_failed"] == 0, stats
+    for i in range(b.n):
+        ws, wsc, wr, _ = oracle.wfa_pair(b.pattern(i), b.text(i), AFF)
+        assert (st[i], s[i]) == (ws, wsc), i
+        assert cg[off[i]:off[i + 1]].tolist() == wr, i
+    # the same pairs through WFA-adaptive (the class kernel's walk with the
+    # reduction step) against the adaptive oracle
+    ctx.wfa_adaptive_params(10, 50)
+    got = run(ctx, b, "wfa_adaptive", AFF)
+    want = oracle.wfa_batch(b, AFF, -1, adaptive=(10, 50))
+    bad = compare(got, want)
+    assert not bad, "%d mismatches, first: %s" % (len(bad), describe(b, bad[0], got, want))
