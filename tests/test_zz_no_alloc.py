@@ -50,7 +50,21 @@ CASES = [
      lambda: _mixed(11, 1500, 100, 3000), lambda: _mixed(12, 300, 100, 1500)),
     ("swg_100_2000", "swg", (0, 4, 6, 2), -1, "code",
      lambda: _mixed(13, 800, 100, 2000), lambda: _mixed(14, 200, 100, 800)),
+    ("wfa_adaptive_150", "wfa_adaptive", (0, 4, 6, 2), -1, "2bit",
+     lambda: synth.workload("wfa_adaptive_150", n=20000),
+     lambda: synth.workload("wfa_adaptive_150", start=20000, n=3000)),
+    ("genasm150", "genasm", (0, 1, 0, 1), 15, "2bit",
+     lambda: synth.workload("genasm150", n=20000), lambda: synth.workload("genasm150", start=20000, n=3000)),
 ]
+ADAPTIVE = (10, 50)  # the reduction rule of the WFA-adaptive cases
+
+
+def _oracle(sub, alg, pen, smax):
+    if alg == "genasm":
+        return oracle.genasm_batch(sub, smax)
+    if alg == "wfa_adaptive":
+        return oracle.wfa_batch(sub, pen, smax, adaptive=ADAPTIVE)
+    return oracle.align_batch(sub, alg, pen, smax)
 
 
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
@@ -60,9 +74,11 @@ def test_static_entry_matches_align_batch(case):
     assert b2.n < b1.n
     print("static entry point: %s, %d then %d pairs" % (label, b1.n, b2.n), flush=True)
     with aim.Context(0) as ctx:
+        ctx.wfa_adaptive_params(*ADAPTIVE)
         want1 = run(ctx, b1, alg, pen, smax, enc=enc)
         want2 = run(ctx, b2, alg, pen, smax, enc=enc)
     with aim.Context(0, static_scratch=True) as sctx:
+        sctx.wfa_adaptive_params(*ADAPTIVE)
         got1 = _run_static(sctx, b1, alg, pen, smax, enc)
         got2 = _run_static(sctx, b2, alg, pen, smax, enc)
     for b, got, want in ((b1, got1, want1), (b2, got2, want2)):
@@ -72,7 +88,7 @@ def test_static_entry_matches_align_batch(case):
     # and both against the oracle on a sample of the second batch
     idx = np.arange(0, b2.n, max(1, b2.n // 200))
     sub = b2.subset(idx)
-    ws, wst, wc, wo = oracle.align_batch(sub, alg, pen, smax)
+    ws, wst, wc, wo = _oracle(sub, alg, pen, smax)
     s, st, cg, off = got2
     for t, i in enumerate(idx):
         assert (s[i], st[i]) == (ws[t], wst[t]), (label, i)
