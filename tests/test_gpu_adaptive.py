@@ -111,3 +111,36 @@ def test_limits(ctx):
     with pytest.raises(aim.AimError):
         ctx.wfa_adaptive_params(0, 5)
     ctx.wfa_adaptive_params(10, 50)
+
+
+@pytest.mark.parametrize("name,n", [("wfa_adaptive_150", 4000), ("wfa_adaptive_1k", 800)])
+def test_graph_replays(name, n):
+    # the adaptive pass and its in-place re-run captured once; every replay,
+    # with eager work between them, gives the adaptive oracle's results
+    from gpu_util import to_device
+    w = synth.WORKLOADS[name]
+    b = synth.workload(name, n=n)
+    L = int(max(b.pat_len.max(), b.txt_len.max()))
+    want = oracle.wfa_batch(b, w["pen"], w["max_score"], adaptive=w["adaptive"])
+    cap = int((b.pat_len.astype(np.int64) + b.txt_len + 1).sum()) + 1
+    stream = torch.cuda.Stream()
+    print("adaptive graph replays: %s, %d pairs" % (name, n), flush=True)
+    with aim.Context(0) as c, torch.cuda.stream(stream):
+        c.wfa_adaptive_params(*w["adaptive"])
+        dev, enc = to_device(b, w["enc"])
+        outs = (torch.empty(b.n, dtype=torch.int32, device="cuda"), torch.empty(b.n, dtype=torch.int8, device="cuda"),
+                torch.empty(cap, dtype=torch.int32, device="cuda"),
+                torch.empty(b.n + 1, dtype=torch.int64, device="cuda"))
+        g = c.graph_capture(*dev, enc=enc, max_len=L, alg="wfa_adaptive", pen=w["pen"], max_score=w["max_score"],
+                            score=outs[0], status=outs[1], cigar=outs[2], cigar_off=outs[3], stream=stream)
+        for rep in range(3):
+            for t in outs:
+                t.zero_()  # eager work between replays
+            stream.synchronize()
+            g.launch(stream)
+            stream.synchronize()
+            s, st, cg, off = outs
+            got = (s.cpu().numpy(), st.cpu().numpy(), cg.cpu().numpy().view(np.uint32), off.cpu().numpy())
+            bad = compare(got, want)
+            assert not bad, (rep, describe(b, bad[0], got, want))
+        g.close()
