@@ -109,3 +109,35 @@ def test_full_wfa_mixed():
         res = list(ex.map(one, idx_l))
     for i, r in zip(idx_l, res):
         assert (st[i], s[i]) == (r[0], r[1]) and cg[off[i]:off[i + 1]].tolist() == r[2], i
+
+
+@pytest.mark.parametrize("name,sample", [("wfa_adaptive_150", 3000), ("wfa_adaptive_1k", 600),
+                                         ("wfa_adaptive_10k", 60), ("genasm150", 3000), ("genasm1k", 600)])
+def test_full_heuristic_workload(name, sample):
+    # WFA-adaptive and GenASM at full size, in the call bench.py times: every
+    # pair by the vectorised invariants (a heuristic's alignment is still a
+    # valid alignment whose cost is its score), a seeded sample bit for bit
+    # against the algorithm's own oracle
+    w = synth.WORKLOADS[name]
+    b = synth.workload(name)
+    print("full workload %s: %d pairs" % (name, b.n), flush=True)
+    with aim.Context(0) as ctx:
+        if w["alg"] == "wfa_adaptive":
+            ctx.wfa_adaptive_params(*w["adaptive"])
+        s, st, cg, off = run(ctx, b, w["alg"], w["pen"], w["max_score"], enc=w["enc"])
+        stats = ctx.last_call_stats()
+    assert stats["wfa_walk_failed"] == 0, stats
+    assert (st != aim.PAIR_INVALID).all() and (st != aim.PAIR_CIGAR_OVERFLOW).all()
+    if w["alg"] == "wfa_adaptive":
+        assert (st == aim.PAIR_ALIGNED).all() and stats["wfa_adaptive_dropped"] > 0, stats
+    vector_invariants(b, s, st, cg, off, w["pen"])
+    rng = np.random.default_rng(7)
+    idx = np.sort(rng.choice(b.n, size=min(sample, b.n), replace=False))
+    sub = b.subset(idx)
+    if w["alg"] == "genasm":
+        ws, wst, wc, wo = oracle.genasm_batch(sub, w["max_score"])
+    else:
+        ws, wst, wc, wo = oracle.wfa_batch(sub, w["pen"], w["max_score"], adaptive=w["adaptive"])
+    for t, i in enumerate(idx):
+        assert (s[i], st[i]) == (ws[t], wst[t]), (name, i)
+        assert np.array_equal(cg[off[i]:off[i + 1]], wc[wo[t]:wo[t + 1]]), (name, i)
