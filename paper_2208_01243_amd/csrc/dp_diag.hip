@@ -302,7 +302,12 @@ __global__ __launch_bounds__(64) void k_diag_tb(Seqs S, Outs O, Work Wk, const u
   constexpr int NP = AFF ? 4 : 2;
   constexpr int NS = 2 * NP;
   constexpr int QUADS = TBP * NS * LPP / 4;  // 16-byte pieces of one staged block
-  __shared__ u32x4 stage[QUADS];
+  // Each pair's pieces are followed by one quad of padding: a pair's block is
+  // NS * LPP words, a multiple of the 32 LDS banks, so without it the pairs'
+  // lanes reading the same word of their blocks all hit one bank; with it
+  // consecutive pairs are 4 banks apart (at most two lanes share a bank).
+  constexpr int PQ = NS * LPP / 4 + 1;  // quads per staged pair, padding included
+  __shared__ u32x4 stage[TBP * PQ];
   const uint32_t *lds = reinterpret_cast<const uint32_t *>(stage);
   const int lane = threadIdx.x;
   const int64_t count = Wk.count ? (int64_t)(*(volatile const int32_t *)Wk.count) : Wk.n;
@@ -389,7 +394,10 @@ __global__ __launch_bounds__(64) void k_diag_tb(Seqs S, Outs O, Work Wk, const u
       __syncthreads();  // the previous block is no longer read
 #pragma unroll
       for (int k = 0; k < PRE; ++k)
-        if ((actmask >> ((lane + 64 * k) / (NS * LPP / 4))) & 1ull) stage[lane + 64 * k] = pre[k];
+        if ((actmask >> ((lane + 64 * k) / (NS * LPP / 4))) & 1ull) {
+          const int q = lane + 64 * k;
+          stage[(q / (NS * LPP / 4)) * PQ + q % (NS * LPP / 4)] = pre[k];
+        }
       __syncthreads();
       if (beta > 0) fetch(beta - 1);
       // keeps the compiler from sinking those loads below the walk (it emits
@@ -399,7 +407,7 @@ __global__ __launch_bounds__(64) void k_diag_tb(Seqs S, Outs O, Work Wk, const u
         const int32_t bb = j - i - kmin, ll = (bb >> 1) & (LPP - 1), s = bb & 1;
         const int32_t tau = (i + j - s) >> 1;
         if (tau < 32 * beta) break;
-        const uint32_t *w = lds + (lane * NS + s * NP) * LPP + ll;
+        const uint32_t *w = lds + lane * (PQ * 4) + s * NP * LPP + ll;
         const int sh = 31 - (tau & 31);
         const uint32_t bd = (w[0] >> sh) & 1u, b1 = (w[LPP] >> sh) & 1u;
         uint32_t b2 = 0, b3 = 0;
