@@ -509,8 +509,9 @@ def main():
     if args.serve_seconds > 0:
         # The serving replay runs in a process of its own, as a server does:
         # in this one, after the batch workloads, its latencies came out
-        # ~40 % higher with the same schedule kept as closely (the cause lies
-        # in what those workloads leave in the process, not in the replay).
+        # ~40 % higher with the same schedule kept as closely -- and so they do
+        # after allocating and freeing 100 GiB through torch alone, so it is
+        # the state the device memory is left in, not the library.
         import subprocess
         cmd = [sys.executable, os.path.abspath(__file__), "--serve-only", "--serve-seconds",
                str(args.serve_seconds), "--serve-streams", str(args.serve_streams)]
